@@ -1,0 +1,156 @@
+"""CPU oracle for LocalContraction -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library never loads it and it never loads the GPU library.
+
+``lc_oracle.c`` holds the plain, step-by-step algorithm (Section 3, paragraph
+"LocalContraction"; closed neighbourhoods from Section 2; the contraction step from the
+proof of the lemma in Section 3; isolated nodes are final as in Section 6).  This module
+only compiles it and marshals arrays.
+
+Parity status of its functions (what pins each one; the tests hold the pins):
+  * ``priority``     -- pinned to the published definitions of SplitMix64 and MurmurHash3's
+                        finaliser (known output values) and to an independent numpy version.
+  * ``run`` parents  -- pinned by brute force from the definition (closed two-hop reachability
+                        then argmin) on every labelled graph with up to 7 vertices, by all
+                        orderings of small graphs, and by hand-worked fixtures.
+  * ``run`` labels   -- pinned as a partition to scipy's connected_components and to a
+                        textbook union-find; raw label values under the hash are pinned only
+                        by the frozen priority specification (the paper fixes no values).
+  * ``run`` stats    -- pinned by recount from the brute force on small graphs and by the
+                        paper's invariants (component count preserved, path lower bound).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lc_oracle.c")
+_LIB = os.path.join(_HERE, "liblcoracle.so")
+_lib = None
+
+NOT_A_NODE = 0xFFFFFFFF
+
+
+class RoundStats(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("pad_", ctypes.c_int32), ("n_active", ctypes.c_int64),
+                ("m_in", ctypes.c_int64), ("m_survive", ctypes.c_int64), ("m_out", ctypes.c_int64),
+                ("n_finalised", ctypes.c_int64)]
+
+    def as_tuple(self):
+        return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.lco_sm64.restype = ctypes.c_uint64
+        lib.lco_sm64.argtypes = [ctypes.c_uint64]
+        lib.lco_fmix32.restype = ctypes.c_uint32
+        lib.lco_fmix32.argtypes = [ctypes.c_uint32]
+        lib.lco_priority.restype = ctypes.c_uint32
+        lib.lco_priority.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32]
+        lib.lco_run.restype = ctypes.c_int32
+        lib.lco_run.argtypes = [ctypes.c_int64, ctypes.c_int64, u32p, u32p, ctypes.c_uint64, u32p, ctypes.c_int32,
+                                ctypes.c_int32, u32p, ctypes.POINTER(RoundStats), ctypes.c_int32, u32p,
+                                ctypes.c_int32]
+        lib.lco_run_batch.restype = ctypes.c_int32
+        lib.lco_run_batch.argtypes = [ctypes.c_int64, i64p, i64p, u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p,
+                                      ctypes.POINTER(ctypes.c_int32), u32p, ctypes.c_int32]
+        _lib = lib
+    return _lib
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct)) if a is not None else None
+
+
+def sm64(x: int) -> int:
+    return int(_load().lco_sm64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def fmix32(x: int) -> int:
+    return int(_load().lco_fmix32(x & 0xFFFFFFFF))
+
+
+def priority(seed: int, rnd: int, name: int) -> int:
+    return int(_load().lco_priority(seed & 0xFFFFFFFFFFFFFFFF, rnd, name & 0xFFFFFFFF))
+
+
+@dataclass
+class Result:
+    labels: np.ndarray                 # uint32 [n0]
+    rounds: int
+    stats: list = field(default_factory=list)   # tuples (round, n_active, m_in, m_survive, m_out, n_finalised)
+    parents: np.ndarray | None = None  # uint32 [min(rounds, cap), n0], NOT_A_NODE off V_r
+
+
+def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0,
+        record_parents: bool = False, parents_cap: int = 64, stats_cap: int = 256) -> Result:
+    """Run the oracle.  `explicit_prio` is an optional [rows, n] table of priorities (phase r
+    uses row min(r, rows-1))."""
+    lib = _load()
+    src = _u32(src)
+    dst = _u32(dst)
+    m = int(src.shape[0])
+    labels = np.empty(max(n, 1), dtype=np.uint32)
+    stats = (RoundStats * stats_cap)()
+    par = np.empty((parents_cap, max(n, 1)), dtype=np.uint32) if record_parents else None
+    ep = None
+    rows = 0
+    if explicit_prio is not None:
+        ep = np.ascontiguousarray(np.atleast_2d(explicit_prio), dtype=np.uint32)
+        assert ep.shape[1] == n
+        rows = ep.shape[0]
+    r = lib.lco_run(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
+                    _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats, stats_cap,
+                    _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0)
+    if r < 0:
+        raise ValueError("oracle rejected the input (ids out of range or out of memory)")
+    res = Result(labels[:n], int(r), [stats[i].as_tuple() for i in range(min(r, stats_cap))])
+    if record_parents:
+        res.parents = par[:min(r, parents_cap), :n]
+    return res
+
+
+def run_batch(voff, eoff, src, dst, seeds, record_parents: bool = False, parents_cap: int = 8):
+    """Run every graph of a packed arena independently.  Returns (labels, rounds, parents)."""
+    lib = _load()
+    voff = np.ascontiguousarray(voff, dtype=np.int64)
+    eoff = np.ascontiguousarray(eoff, dtype=np.int64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    src = _u32(src)
+    dst = _u32(dst)
+    G = int(voff.shape[0] - 1)
+    labels = np.empty(max(int(voff[-1]), 1), dtype=np.uint32)
+    rounds = np.empty(max(G, 1), dtype=np.int32)
+    par = np.empty(max(int(voff[-1]) * parents_cap, 1), dtype=np.uint32) if record_parents else None
+    st = lib.lco_run_batch(G, _ptr(voff, ctypes.c_int64), _ptr(eoff, ctypes.c_int64), _ptr(src, ctypes.c_uint32),
+                           _ptr(dst, ctypes.c_uint32), _ptr(seeds, ctypes.c_uint64), _ptr(labels, ctypes.c_uint32),
+                           _ptr(rounds, ctypes.c_int32), _ptr(par, ctypes.c_uint32),
+                           parents_cap if record_parents else 0)
+    if st != 0:
+        raise ValueError("oracle rejected a graph of the batch")
+    return labels[:int(voff[-1])], rounds[:G], par

@@ -1,0 +1,313 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix (no GPU needed).
+
+Each test checks the oracle against something other than itself: published hash values,
+the definition by brute force, hand-worked fixtures, textbook/library component routines,
+or an invariant or bound stated in the paper.
+"""
+import glob
+import math
+import os
+from itertools import permutations
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from lcref import (all_graph_adjacency, brute_all, canon, graph_records, scipy_components, simple_edges,
+                   spec_priority, spec_priority_inverse, two_hop_parents, union_find)
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---------------------------------------------------------------------------------------
+# priority specification
+# ---------------------------------------------------------------------------------------
+
+def test_hash_published_values():
+    # SplitMix64 (Steele, Lea, Flood 2014): the first outputs of the generator seeded with 0.
+    assert oracle.sm64(0) == 0xE220A8397B1DCDAF
+    # MurmurHash3_x86_32 of the empty input reduces to fmix32(seed): seed 1 -> 0x514E28B7,
+    # seed 0xFFFFFFFF -> 0x81F16F39 (published verification values).
+    assert oracle.fmix32(1) == 0x514E28B7
+    assert oracle.fmix32(0xFFFFFFFF) == 0x81F16F39
+    assert oracle.fmix32(0) == 0
+
+
+def test_priority_matches_independent_spec():
+    rng = np.random.default_rng(1)
+    names = rng.integers(0, 1 << 32, size=200, dtype=np.uint64).astype(np.uint32)
+    for seed in (0, 1, 0xC0FFEE00, (1 << 64) - 1):
+        for r in (0, 1, 7, 31):
+            want = spec_priority(seed, r, names)
+            got = np.array([oracle.priority(seed, r, int(x)) for x in names], np.uint32)
+            np.testing.assert_array_equal(got, want)
+
+
+def test_priority_is_a_bijection():
+    # Structure: xor with a constant, xor-shift-right and multiplication by an odd constant
+    # are each invertible on 32-bit words, so their composition is a bijection.  Checked
+    # here by an explicit inverse on 2^24 inputs and exact distinctness on a 2^24 block.
+    for seed, r in ((0, 0), (12345, 3)):
+        x = np.arange(1 << 24, dtype=np.uint32) * np.uint32(251) + np.uint32(seed & 0xFFFF)
+        p = spec_priority(seed, r, x)
+        np.testing.assert_array_equal(spec_priority_inverse(seed, r, p), x)
+        assert np.unique(p).shape[0] == x.shape[0]
+
+
+# ---------------------------------------------------------------------------------------
+# brute force from the definition on every labelled graph with up to 7 vertices
+# ---------------------------------------------------------------------------------------
+
+def _oracle_all(adj, seed):
+    src, dst, eoff = graph_records(adj)
+    G, n = adj.shape
+    voff = np.arange(G + 1, dtype=np.int64) * n
+    seeds = np.full(G, seed, np.uint64)
+    cap = 8
+    labels, rounds, par = oracle.run_batch(voff, eoff, src, dst, seeds, record_parents=True, parents_cap=cap)
+    return labels.reshape(G, n), rounds, par.reshape(G, cap, n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7])
+def test_oracle_equals_bruteforce_all_graphs(n):
+    adj = all_graph_adjacency(n)
+    for seed in (0, 0xC0FFEE00, 977):
+        lab_o, rounds_o, par_o = _oracle_all(adj, seed)
+        lab_b, rounds_b, par_b, _ = brute_all(adj, lambda r: spec_priority(seed, r, np.arange(n)), max_rounds=8)
+        np.testing.assert_array_equal(rounds_o, rounds_b)
+        np.testing.assert_array_equal(lab_o, lab_b.astype(np.uint32))
+        for r in range(int(rounds_b.max(initial=0))):
+            want = np.where(par_b[r] == 255, np.uint32(oracle.NOT_A_NODE), par_b[r].astype(np.uint32))
+            live = rounds_b > r
+            np.testing.assert_array_equal(par_o[live, r, :], want[live])
+
+
+def test_oracle_stats_equal_bruteforce():
+    n = 6
+    adj = all_graph_adjacency(n)
+    rng = np.random.default_rng(5)
+    pick = rng.choice(adj.shape[0], size=400, replace=False)
+    seed = 31337
+    _, rounds_b, _, stats_b = brute_all(adj[pick], lambda r: spec_priority(seed, r, np.arange(n)), max_rounds=8)
+    src, dst, eoff = graph_records(adj[pick])
+    for j in range(pick.shape[0]):
+        a, b = eoff[j], eoff[j + 1]
+        res = oracle.run(n, src[a:b], dst[a:b], seed)
+        assert res.rounds == rounds_b[j]
+        for r, st in enumerate(res.stats):
+            assert st[0] == r
+            assert list(st[1:]) == list(stats_b[r, j])
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_oracle_all_orderings(n):
+    """Every graph on n vertices under every ordering of its vertices (explicit priorities)."""
+    adj = all_graph_adjacency(n)
+    src, dst, eoff = graph_records(adj)
+    G = adj.shape[0]
+    for perm in permutations(range(n)):
+        prio = np.array(perm, np.int64)
+        lab_b, rounds_b, par_b, stats_b = brute_all(adj, lambda r: prio, max_rounds=8)
+        for g in range(G):
+            a, b = eoff[g], eoff[g + 1]
+            res = oracle.run(n, src[a:b], dst[a:b], explicit_prio=prio.astype(np.uint32), record_parents=True)
+            assert res.rounds == rounds_b[g]
+            np.testing.assert_array_equal(res.labels, lab_b[g].astype(np.uint32))
+            for r in range(res.rounds):
+                want = np.where(par_b[r, g] == 255, np.uint32(oracle.NOT_A_NODE), par_b[r, g].astype(np.uint32))
+                np.testing.assert_array_equal(res.parents[r], want)
+
+
+# ---------------------------------------------------------------------------------------
+# hand-worked fixtures
+# ---------------------------------------------------------------------------------------
+
+def load_fixture(path):
+    fx = {"parents": {}, "stats": {}}
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            key, *vals = line.split()
+            if key == "n":
+                fx["n"] = int(vals[0])
+            elif key == "edges":
+                fx["edges"] = [tuple(int(t) for t in v.split("-")) for v in vals]
+            elif key == "prio":
+                fx["prio"] = [int(v) for v in vals]
+            elif key.startswith("parents"):
+                fx["parents"][int(key[7:])] = [None if v == "-" else int(v) for v in vals]
+            elif key == "labels":
+                fx["labels"] = [int(v) for v in vals]
+            elif key == "rounds":
+                fx["rounds"] = int(vals[0])
+            elif key.startswith("stats"):
+                fx["stats"][int(key[5:])] = [int(v) for v in vals]
+    return fx
+
+
+FIXTURES = sorted(glob.glob(os.path.join(GOLDEN, "*.txt")))
+
+
+@pytest.mark.parametrize("path", FIXTURES, ids=[os.path.basename(p) for p in FIXTURES])
+def test_oracle_hand_worked(path):
+    fx = load_fixture(path)
+    src = [a for a, _ in fx["edges"]]
+    dst = [b for _, b in fx["edges"]]
+    res = oracle.run(fx["n"], src, dst, explicit_prio=np.array(fx["prio"], np.uint32), record_parents=True)
+    assert res.rounds == fx["rounds"]
+    assert res.labels.tolist() == fx["labels"]
+    for r, want in fx["parents"].items():
+        got = [None if v == oracle.NOT_A_NODE else int(v) for v in res.parents[r]]
+        assert got == want, (r, got, want)
+    for r, want in fx["stats"].items():
+        assert list(res.stats[r][1:]) == want
+
+
+# ---------------------------------------------------------------------------------------
+# closed forms and special cases
+# ---------------------------------------------------------------------------------------
+
+def test_edgeless_graph():
+    res = oracle.run(10, [3, 7], [3, 7], seed=4)   # loops only
+    assert res.rounds == 0
+    assert res.labels.tolist() == list(range(10))
+    res = oracle.run(0, [], [], seed=4)
+    assert res.rounds == 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 13, 64, 101])
+def test_path_identity_order_closed_form(k):
+    """Under rho(name) = name a path 0-1-...-(k-1) loses two nodes per phase: the two-hop
+    minimum of vertex i is max(0, i-2), so the classes are {0,1,2},{3},{4},... and the next
+    graph is again an increasing path; hence ceil((k-1)/2) phases."""
+    src = list(range(k - 1))
+    dst = list(range(1, k))
+    res = oracle.run(k, src, dst, explicit_prio=np.arange(k, dtype=np.uint32), record_parents=True)
+    assert res.rounds == math.ceil((k - 1) / 2)
+    if k >= 2:
+        assert res.parents[0].tolist() == [max(0, i - 2) for i in range(k)]
+    assert res.labels.tolist() == [0] * k
+
+
+@pytest.mark.parametrize("shape", ["star", "clique"])
+def test_diameter_two_one_phase(shape):
+    n = 40
+    if shape == "star":
+        src, dst = [7] * (n - 1), [v for v in range(n) if v != 7]
+    else:
+        src, dst = zip(*[(a, b) for a in range(n) for b in range(a + 1, n)])
+    for seed in range(5):
+        res = oracle.run(n, src, dst, seed=seed)
+        assert res.rounds == 1
+        assert len(set(res.labels.tolist())) == 1
+
+
+def test_path_lower_bound():
+    """A phase merges only vertices at distance <= 4, so a path shrinks at most 5 times per
+    phase and needs at least ceil(log_5 L) phases (Section 7, first theorem)."""
+    for L in (26, 126, 1000, 3125):
+        src, dst = np.arange(L - 1), np.arange(1, L)
+        for seed in range(4):
+            res = oracle.run(L, src, dst, seed=seed)
+            assert res.rounds >= math.ceil(math.log(L, 5) - 1e-9)
+            assert res.stats[0][1] == L
+            for before, after in zip(res.stats, res.stats[1:]):
+                assert after[1] * 5 >= before[1]       # a path never shrinks by more than 5x
+
+
+def test_disjoint_union_is_union_of_results():
+    """Components never interact (priorities are only compared within a component), so a
+    graph made of two copies run with the same priority per name gives each copy's result."""
+    g = graphgen.workload_small(seed=99)
+    n = 2000
+    keep = (g.src < n) & (g.dst < n)
+    s, d = g.src[keep], g.dst[keep]
+    prio = spec_priority(5, 0, np.arange(2 * n))
+    both = oracle.run(2 * n, np.concatenate([s, s + n]), np.concatenate([d, d + n]), explicit_prio=prio)
+    a = oracle.run(n, s, d, explicit_prio=prio[:n])
+    b = oracle.run(n, s + 0, d + 0, explicit_prio=prio[n:])
+    np.testing.assert_array_equal(both.labels[:n], a.labels)
+    np.testing.assert_array_equal(both.labels[n:], b.labels + n)
+
+
+# ---------------------------------------------------------------------------------------
+# partition against textbook and library routines, and per-phase invariants
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["gnm", "rmat", "paths", "sparse"])
+def test_partition_matches_union_find_and_scipy(kind):
+    if kind == "gnm":
+        g = graphgen.workload_small()
+    elif kind == "rmat":
+        g = graphgen.Graph(1 << 14, *graphgen.rmat(7, 14, 8 << 14))
+    elif kind == "paths":
+        g = graphgen.er_with_paths(11, 1 << 12, 1 << 12, 50, 200)
+    else:
+        g = graphgen.Graph(1 << 15, *graphgen.gnm(3, 1 << 15, 1 << 14))   # below the threshold
+    res = oracle.run(g.n, g.src, g.dst, seed=42)
+    want = canon(union_find(g.n, g.src, g.dst))
+    np.testing.assert_array_equal(canon(res.labels), want)
+    np.testing.assert_array_equal(canon(scipy_components(g.n, g.src, g.dst)), want)
+    # labels are vertices of the vertex's own component
+    np.testing.assert_array_equal(want[res.labels.astype(np.int64)], want)
+
+
+def test_per_phase_definition_and_invariants():
+    """Replays the phases independently: each recorded parent must be the argmin of the
+    priority over the closed two-hop ball (sparse (A+I)^2), rho(p(x)) <= rho(x) (proof of the
+    O(log n) lemma, Section 4), and components are preserved."""
+    g = graphgen.er_with_paths(21, 1 << 12, 3 << 11, 20, 100)
+    seed = 77
+    res = oracle.run(g.n, g.src, g.dst, seed=seed, record_parents=True)
+    lo, hi = simple_edges(g.src, g.dst)
+    n_comp0 = np.unique(canon(scipy_components(g.n, g.src, g.dst))[np.unique(np.concatenate([lo, hi]))]).shape[0]
+    finalised = 0
+    for r in range(res.rounds):
+        prio = spec_priority(seed, r, np.arange(g.n))
+        nodes, want = two_hop_parents(g.n, lo, hi, prio)
+        par = res.parents[r]
+        np.testing.assert_array_equal(par[nodes].astype(np.int64), want[nodes])
+        assert np.all(prio[par[nodes]] <= prio[nodes])
+        assert np.count_nonzero(par != oracle.NOT_A_NODE) == nodes.shape[0] == res.stats[r][1]
+        # next graph
+        plo, phi = par[lo].astype(np.int64), par[hi].astype(np.int64)
+        lo, hi = simple_edges(plo, phi)
+        assert res.stats[r][4] == lo.shape[0]
+        finalised += res.stats[r][5]
+        if lo.shape[0]:
+            nxt = np.unique(np.concatenate([lo, hi]))
+            comp = canon(scipy_components(g.n, lo, hi))[nxt]
+            n_now = np.unique(comp).shape[0]
+        else:
+            n_now = 0
+        assert n_now + finalised == n_comp0
+    assert lo.shape[0] == 0
+
+
+def test_expected_labels_at_most_three_quarters():
+    """E[#labels] <= 3n/4 for graphs without isolated vertices (Section 4, O(log n) lemma)."""
+    n = 600
+    src, dst = np.arange(0, n, 2), np.arange(1, n, 2)       # a perfect matching
+    ps, pd = np.arange(n - 1), np.arange(1, n)              # a path
+    for s, d in ((src, dst), (ps, pd)):
+        counts = []
+        for seed in range(100):
+            res = oracle.run(n, s, d, seed=seed, max_rounds=1, record_parents=True)
+            counts.append(np.unique(res.parents[0]).shape[0])
+        assert np.mean(counts) <= 0.75 * n
+
+
+def test_max_rounds_stops_early():
+    g = graphgen.er_with_paths(3, 0, 0, 4, 300)
+    full = oracle.run(g.n, g.src, g.dst, seed=9)
+    part = oracle.run(g.n, g.src, g.dst, seed=9, max_rounds=2)
+    assert full.rounds > 2 and part.rounds == 2
+    assert full.stats[:2] == part.stats
+
+
+def test_rejects_out_of_range_ids():
+    with pytest.raises(ValueError):
+        oracle.run(3, [0, 5], [1, 2])
