@@ -1,0 +1,184 @@
+/*
+ * cc.h -- LocalContraction connected components on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * Method: Lacki, Mirrokni, Wlodarczyk, "Connected Components at Scale via
+ * Local Contractions" (arXiv 1807.10727), Section 3, paragraph
+ * "LocalContraction".  Each phase ("round" below) draws a random ordering rho
+ * of the current nodes, gives every node v the vertex of smallest priority in
+ * its closed two-hop neighbourhood N(N(v)) (N(v) contains v, Section 2) as its
+ * parent, merges nodes with equal parents, and keeps one copy of every edge
+ * between different parents (the contraction step, proof of the lemma in
+ * Section 3).  The run ends when no edge is left (Section 3); nodes left
+ * without edges are final (Section 6 drops isolated nodes after each phase).
+ *
+ * Specification shared with any independent implementation:
+ *   - a merged node is named by the original vertex id of its parent;
+ *   - the priority of node name x in round r (r = 0 on the input graph) is
+ *       fmix32(fmix32(x ^ k0) ^ k1),   (k1 << 32 | k0) = sm64(seed ^ sm64(r)),
+ *     where sm64 is SplitMix64's output function (Steele, Lea, Flood 2014:
+ *     z = x + 0x9E3779B97F4A7C15, then the two xor-shift-multiply steps and a
+ *     final xor-shift) and fmix32 is MurmurHash3's 32-bit finaliser; priorities
+ *     are compared as unsigned 32-bit integers.  Both steps are bijections, so
+ *     no two nodes tie.
+ *   - records are undirected pairs; loops and repeated records are allowed in
+ *     the input and never change a closed neighbourhood.
+ *   - the label of an original vertex is the name of the final node it ended
+ *     in (an original vertex id of its component), or, with CC_CANONICAL, the
+ *     smallest original id of its component.
+ *
+ * Memory: every pointer argument named d_* is device memory.  The library
+ * never allocates device memory: the caller sizes a workspace with
+ * cc_workspace_size() and hands it over with cc_set_workspace().  Input edge
+ * buffers are borrowed (read only) until cc_destroy(); the caller must keep
+ * them alive and unchanged.  All device work is enqueued on the stream given
+ * in cc_options; calls that return statistics synchronise that stream.
+ *
+ * Errors: every entry point returns a cc_status.  No C++ exception crosses
+ * this interface.  cc_last_error() describes the most recent failure of a
+ * context (including the HIP error string when one is involved).
+ *
+ * Threading: a context is used by one thread at a time; distinct contexts
+ * are independent.
+ */
+#ifndef CC_H_
+#define CC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cc_status;
+enum {
+    CC_OK = 0,        /* success */
+    CC_DONE = 1,      /* cc_contract_round: no edge was left, nothing was done */
+    CC_E_ARG = -1,    /* invalid argument (null pointer, size, layout, alignment) */
+    CC_E_INPUT = -2,  /* an edge record names a vertex outside [0, n_vertices) */
+    CC_E_NOMEM = -3,  /* workspace missing or smaller than cc_workspace_size() */
+    CC_E_HIP = -4,    /* a HIP runtime call failed (see cc_last_error) */
+    CC_E_STATE = -5,  /* call not valid in the context's current state */
+    CC_E_BUDGET = -6  /* a request does not fit the serving memory budget */
+};
+
+/* Edge record layouts.  Vertex ids must lie in [0, n_vertices), n_vertices <= 2^31 - 1. */
+typedef enum {
+    CC_EDGES_SOA_I32 = 0,    /* src: int32[n_edges], dst: int32[n_edges] */
+    CC_EDGES_SOA_I64 = 1,    /* src: int64[n_edges], dst: int64[n_edges] */
+    CC_EDGES_PACKED_U64 = 2  /* src: uint64[n_edges], record = (a << 32) | b; dst unused (NULL) */
+} cc_edge_layout;
+
+typedef struct {
+    int64_t n_vertices;  /* vertex ids are 0 .. n_vertices-1 */
+    int64_t n_edges;     /* number of records (int64: may exceed 2^31) */
+    int32_t layout;      /* cc_edge_layout */
+    int32_t reserved;    /* must be 0 */
+    const void *src;     /* d_: see cc_edge_layout */
+    const void *dst;     /* d_: see cc_edge_layout */
+} cc_graph_desc;
+
+/* cc_options.flags */
+enum {
+    CC_CANONICAL = 1u << 0,  /* cc_labels writes the smallest original id of each component */
+    CC_PROFILE = 1u << 1     /* time every kernel with HIP events (see cc_kernel_times) */
+};
+
+typedef struct {
+    uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
+    int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
+    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE */
+    void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
+} cc_options;
+
+/* Statistics of one round (all counts exact). */
+typedef struct {
+    int32_t round;        /* r, from 0 */
+    int32_t reserved;
+    int64_t n_active;     /* nodes with at least one loop-free edge in this round */
+    int64_t m_in;         /* records read: the raw input count in round 0, |E_r| after */
+    int64_t m_survive;    /* records whose two endpoints get different parents (repeats counted) */
+    int64_t m_out;        /* distinct loop-free edges of the next graph, |E_{r+1}| */
+    int64_t n_finalised;  /* distinct parents of this round that keep no edge */
+} cc_round_stats;
+
+typedef struct cc_ctx cc_ctx;
+
+/*
+ * Create a context for one graph.  Validates the descriptor (layout, sizes,
+ * 16-byte alignment is NOT required).  Records are read only from round 0 on;
+ * an out-of-range id is detected on the device and reported as CC_E_INPUT by
+ * the first round (such records are skipped, never dereferenced).
+ * *out receives the context (NULL on failure).
+ */
+cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx **out);
+
+/* Bytes of device workspace this context needs (depends on n_vertices and n_edges only). */
+cc_status cc_workspace_size(const cc_ctx *ctx, size_t *bytes);
+
+/*
+ * Hand over the device workspace (caller-owned, >= cc_workspace_size bytes,
+ * 256-byte aligned).  Must precede the first round; resets the solve.
+ */
+cc_status cc_set_workspace(cc_ctx *ctx, void *d_workspace, size_t bytes);
+
+/*
+ * Restart the solve on the same borrowed input with a new seed (the
+ * workspace is kept).  Used to repeat solves without re-creating contexts.
+ */
+cc_status cc_reset(cc_ctx *ctx, uint64_t seed);
+
+/*
+ * Run one round (Section 3, one phase of LocalContraction) and synchronise
+ * the stream.  Returns CC_DONE without work once no edge is left.  `out`
+ * (nullable, host) receives the round's statistics.
+ */
+cc_status cc_contract_round(cc_ctx *ctx, cc_round_stats *out);
+
+/*
+ * Run rounds until no edge is left (or opts.max_rounds rounds ran), then
+ * compose the per-round maps into final labels on the device.  *rounds
+ * (nullable, host) receives the number of rounds of this solve so far.
+ */
+cc_status cc_run(cc_ctx *ctx, int32_t *rounds);
+
+/*
+ * Write the label of every original vertex into d_labels (int32[n_vertices]
+ * for CC_EDGES_SOA_I32 and CC_EDGES_PACKED_U64, int64[n_vertices] for
+ * CC_EDGES_SOA_I64).  Asynchronous on the context's stream.  Valid after
+ * cc_run, or after cc_contract_round returned CC_DONE; CC_E_STATE otherwise.
+ */
+cc_status cc_labels(cc_ctx *ctx, void *d_labels);
+
+/*
+ * Parents of the most recent round (test and inspection aid, not on the
+ * measured path): d_parents (int32[n_vertices]) receives, for every name x
+ * that was a node of that round, the name of its parent, and -1 for every
+ * other name.  *n_nodes (nullable, host) receives the node count.  Synchronises.
+ */
+cc_status cc_round_parents(cc_ctx *ctx, int32_t *d_parents, int64_t *n_nodes);
+
+/* Statistics of round r of the current solve (host copy kept by the library). */
+cc_status cc_get_round_stats(const cc_ctx *ctx, int32_t r, cc_round_stats *out);
+
+/*
+ * Kernel timing (CC_PROFILE): per kernel family, the summed event time in ms
+ * and the number of launches since the last cc_set_workspace/cc_reset.
+ * Families are listed by cc_kernel_family_name(i) for i < cc_kernel_family_count().
+ */
+int32_t cc_kernel_family_count(void);
+const char *cc_kernel_family_name(int32_t i);
+cc_status cc_kernel_times(const cc_ctx *ctx, double *ms, int64_t *launches, int32_t cap);
+
+cc_status cc_destroy(cc_ctx *ctx);
+const char *cc_last_error(const cc_ctx *ctx);
+
+/* Library version string and the offload target it was built for. */
+const char *cc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H_ */

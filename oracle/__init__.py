@@ -75,6 +75,8 @@ def _load():
         lib.lco_run_batch.restype = ctypes.c_int32
         lib.lco_run_batch.argtypes = [ctypes.c_int64, i64p, i64p, u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p,
                                       ctypes.POINTER(ctypes.c_int32), u32p, ctypes.c_int32]
+        lib.lco_components_min_id.restype = ctypes.c_int32
+        lib.lco_components_min_id.argtypes = [ctypes.c_int64, ctypes.c_int64, u32p, u32p, u32p]
         _lib = lib
     return _lib
 
@@ -154,3 +156,14 @@ def run_batch(voff, eoff, src, dst, seeds, record_parents: bool = False, parents
     if st != 0:
         raise ValueError("oracle rejected a graph of the batch")
     return labels[:int(voff[-1])], rounds[:G], par
+
+
+def components_min_id(n: int, src, dst) -> np.ndarray:
+    """Smallest vertex id of each vertex's connected component (textbook union-find)."""
+    src = _u32(src)
+    dst = _u32(dst)
+    out = np.empty(max(n, 1), dtype=np.uint32)
+    if _load().lco_components_min_id(n, int(src.shape[0]), _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32),
+                                     _ptr(out, ctypes.c_uint32)) != 0:
+        raise ValueError("ids out of range or out of memory")
+    return out[:n]

@@ -265,3 +265,47 @@ int32_t lco_run_batch(int64_t n_graphs, const int64_t *voff, const int64_t *eoff
     }
     return status;
 }
+
+/*
+ * Textbook union-find (union by size, path halving) over the records: writes
+ * for every vertex the smallest vertex id of its connected component.  Used to
+ * check the partition of large runs, where the phase-by-phase oracle is slow.
+ */
+int32_t lco_components_min_id(int64_t n, int64_t m, const uint32_t *src, const uint32_t *dst, uint32_t *out) {
+    uint32_t *parent = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *size = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    if (!parent || !size) {
+        free(parent);
+        free(size);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        parent[v] = (uint32_t)v;
+        size[v] = 1;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        if ((int64_t)src[i] >= n || (int64_t)dst[i] >= n) {
+            free(parent);
+            free(size);
+            return -1;
+        }
+        uint32_t a = src[i], b = dst[i];
+        while (parent[a] != a) { parent[a] = parent[parent[a]]; a = parent[a]; }
+        while (parent[b] != b) { parent[b] = parent[parent[b]]; b = parent[b]; }
+        if (a == b) continue;
+        if (size[a] < size[b]) { uint32_t t = a; a = b; b = t; }
+        parent[b] = a;
+        size[a] += size[b];
+    }
+    /* smallest id per root: vertices are visited in increasing order */
+    for (int64_t v = 0; v < n; ++v) out[v] = 0xFFFFFFFFu;
+    for (int64_t v = 0; v < n; ++v) {
+        uint32_t r = (uint32_t)v;
+        while (parent[r] != r) r = parent[r];
+        if (out[r] == 0xFFFFFFFFu) out[r] = (uint32_t)v;
+        out[v] = out[r];
+    }
+    free(parent);
+    free(size);
+    return 0;
+}

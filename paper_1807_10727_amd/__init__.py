@@ -1,0 +1,121 @@
+"""LocalContraction connected components on one AMD Instinct MI355X (gfx950).
+
+The work runs in the HIP library ``libcc.so`` (C ABI in ``include/cc.h``); this package
+only marshals arguments.  PyTorch provides device memory (the caller's edge tensors, the
+workspace, the label tensor) and the stream.
+
+    from paper_1807_10727_amd import Solver
+    s = Solver(n, src, dst, seed=1)        # src/dst: int32 or int64 CUDA tensors
+    rounds = s.run()
+    labels = s.labels()                    # int32 (or int64) CUDA tensor [n]
+"""
+from __future__ import annotations
+
+from . import _cc
+from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
+                  CC_PROFILE, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
+                  cc_kernel_family_names, cc_kernel_times, cc_labels, cc_last_error, cc_reset, cc_round_parents,
+                  cc_run, cc_set_workspace, cc_version, cc_workspace_size)
+
+__all__ = ["Solver", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One graph's solve behind the C ABI.  The edge tensors are borrowed (kept referenced)
+    until close(); the workspace is a torch uint8 tensor on the same device."""
+
+    def __init__(self, n: int, src, dst=None, seed: int = 0, max_rounds: int = 0, flags: int = 0,
+                 stream=None, layout: int | None = None):
+        torch = _torch()
+        if not src.is_cuda:
+            raise ValueError("edge tensors must be device tensors")
+        if layout is None:
+            if dst is None:
+                layout = CC_EDGES_PACKED_U64
+            elif src.dtype == torch.int32:
+                layout = CC_EDGES_SOA_I32
+            elif src.dtype == torch.int64:
+                layout = CC_EDGES_SOA_I64
+            else:
+                raise ValueError("unsupported edge dtype %s" % src.dtype)
+        if dst is not None and (dst.dtype != src.dtype or dst.shape != src.shape):
+            raise ValueError("src and dst must have the same dtype and shape")
+        if not src.is_contiguous() or (dst is not None and not dst.is_contiguous()):
+            raise ValueError("edge tensors must be contiguous")
+        self.n = int(n)
+        self.m = int(src.shape[0])
+        self.layout = layout
+        self.device = src.device
+        self._src, self._dst = src, dst
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = cc_create(self.n, self.m, layout, src.data_ptr(), dst.data_ptr() if dst is not None else 0,
+                             seed=seed, max_rounds=max_rounds, flags=flags, stream=self.stream.cuda_stream)
+        self.ws_bytes = cc_workspace_size(self.ctx)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        cc_set_workspace(self.ctx, self.ws.data_ptr(), self.ws_bytes)
+
+    @property
+    def label_dtype(self):
+        torch = _torch()
+        return torch.int64 if self.layout == CC_EDGES_SOA_I64 else torch.int32
+
+    def run(self) -> int:
+        return cc_run(self.ctx)
+
+    def contract_round(self):
+        return cc_contract_round(self.ctx)
+
+    def labels(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n, dtype=self.label_dtype, device=self.device)
+        cc_labels(self.ctx, out.data_ptr() if self.n else 1)
+        return out
+
+    def parents(self):
+        """Parents of the last round, by name (-1 for names that were not nodes)."""
+        torch = _torch()
+        out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        k = cc_round_parents(self.ctx, out.data_ptr())
+        return out[:self.n], k
+
+    def stats(self, rounds: int):
+        return [cc_get_round_stats(self.ctx, r) for r in range(rounds)]
+
+    def reset(self, seed: int) -> None:
+        cc_reset(self.ctx, seed)
+
+    def kernel_times(self):
+        return cc_kernel_times(self.ctx)
+
+    def close(self) -> None:
+        if self.ctx:
+            cc_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(n: int, src, dst=None, seed: int = 0, flags: int = 0, max_rounds: int = 0):
+    """Full solve: returns (labels tensor, rounds, per-round stats)."""
+    with Solver(n, src, dst, seed=seed, flags=flags, max_rounds=max_rounds) as s:
+        rounds = s.run()
+        lab = s.labels()
+        st = s.stats(rounds)
+        _torch().cuda.current_stream(s.device).synchronize()
+        return lab, rounds, st

@@ -1,0 +1,166 @@
+"""ctypes binding of libcc.so (include/cc.h): argument marshalling only.
+
+Every step of a solve runs in the HIP library; this module passes pointers and sizes.
+Importing it fails loudly when libcc.so has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcc.so is not built (run __graft_entry__.build() or "
+                      "python paper_1807_10727_amd/build.py); there is no fallback path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CC_OK, CC_DONE = 0, 1
+CC_E_ARG, CC_E_INPUT, CC_E_NOMEM, CC_E_HIP, CC_E_STATE, CC_E_BUDGET = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "CC_OK", 1: "CC_DONE", -1: "CC_E_ARG", -2: "CC_E_INPUT", -3: "CC_E_NOMEM", -4: "CC_E_HIP",
+                -5: "CC_E_STATE", -6: "CC_E_BUDGET"}
+
+CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_EDGES_PACKED_U64 = 0, 1, 2
+CC_CANONICAL = 1 << 0
+CC_PROFILE = 1 << 1
+
+
+class cc_graph_desc(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("n_edges", ctypes.c_int64), ("layout", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p)]
+
+
+class cc_options(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("max_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p)]
+
+
+class cc_round_stats(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_active", ctypes.c_int64),
+                ("m_in", ctypes.c_int64), ("m_survive", ctypes.c_int64), ("m_out", ctypes.c_int64),
+                ("n_finalised", ctypes.c_int64)]
+
+    def as_tuple(self):
+        return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
+
+
+_ctx_p = ctypes.c_void_p
+_sig = {
+    "cc_create": (ctypes.c_int32, [ctypes.POINTER(cc_graph_desc), ctypes.POINTER(cc_options),
+                                   ctypes.POINTER(_ctx_p)]),
+    "cc_workspace_size": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cc_set_workspace": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "cc_reset": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
+    "cc_contract_round": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_round_stats)]),
+    "cc_run": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cc_labels": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p]),
+    "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "cc_get_round_stats": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.POINTER(cc_round_stats)]),
+    "cc_kernel_family_count": (ctypes.c_int32, []),
+    "cc_kernel_family_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "cc_kernel_times": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int32]),
+    "cc_destroy": (ctypes.c_int32, [_ctx_p]),
+    "cc_last_error": (ctypes.c_char_p, [_ctx_p]),
+    "cc_version": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class CCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def _check(ctx, status: int) -> int:
+    if status < 0:
+        msg = _lib.cc_last_error(ctx) if ctx else b""
+        raise CCError(status, (msg or b"").decode())
+    return status
+
+
+# ---- same names as the C ABI -----------------------------------------------------------
+
+def cc_create(n_vertices: int, n_edges: int, layout: int, src_ptr: int, dst_ptr: int, seed: int = 0,
+              max_rounds: int = 0, flags: int = 0, stream: int = 0):
+    g = cc_graph_desc(n_vertices, n_edges, layout, 0, src_ptr or None, dst_ptr or None)
+    o = cc_options(seed & 0xFFFFFFFFFFFFFFFF, max_rounds, flags, stream or None)
+    ctx = _ctx_p()
+    _check(None, _lib.cc_create(ctypes.byref(g), ctypes.byref(o), ctypes.byref(ctx)))
+    return ctx
+
+
+def cc_workspace_size(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check(ctx, _lib.cc_workspace_size(ctx, ctypes.byref(n)))
+    return int(n.value)
+
+
+def cc_set_workspace(ctx, ptr: int, nbytes: int) -> None:
+    _check(ctx, _lib.cc_set_workspace(ctx, ptr, nbytes))
+
+
+def cc_reset(ctx, seed: int) -> None:
+    _check(ctx, _lib.cc_reset(ctx, seed & 0xFFFFFFFFFFFFFFFF))
+
+
+def cc_contract_round(ctx):
+    """Returns (status, stats tuple or None); status is CC_OK or CC_DONE."""
+    s = cc_round_stats()
+    st = _check(ctx, _lib.cc_contract_round(ctx, ctypes.byref(s)))
+    return st, (s.as_tuple() if st == CC_OK else None)
+
+
+def cc_run(ctx) -> int:
+    r = ctypes.c_int32()
+    _check(ctx, _lib.cc_run(ctx, ctypes.byref(r)))
+    return int(r.value)
+
+
+def cc_labels(ctx, ptr: int) -> None:
+    _check(ctx, _lib.cc_labels(ctx, ptr))
+
+
+def cc_round_parents(ctx, ptr: int) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, _lib.cc_round_parents(ctx, ptr, ctypes.byref(n)))
+    return int(n.value)
+
+
+def cc_get_round_stats(ctx, r: int):
+    s = cc_round_stats()
+    _check(ctx, _lib.cc_get_round_stats(ctx, r, ctypes.byref(s)))
+    return s.as_tuple()
+
+
+def cc_kernel_family_names():
+    return [_lib.cc_kernel_family_name(i).decode() for i in range(_lib.cc_kernel_family_count())]
+
+
+def cc_kernel_times(ctx):
+    k = _lib.cc_kernel_family_count()
+    ms = (ctypes.c_double * k)()
+    ln = (ctypes.c_int64 * k)()
+    _check(ctx, _lib.cc_kernel_times(ctx, ms, ln, k))
+    return {name: (ms[i], ln[i]) for i, name in enumerate(cc_kernel_family_names())}
+
+
+def cc_destroy(ctx) -> None:
+    if ctx:
+        _lib.cc_destroy(ctx)
+
+
+def cc_last_error(ctx) -> str:
+    return (_lib.cc_last_error(ctx) or b"").decode()
+
+
+def cc_version() -> str:
+    return _lib.cc_version().decode()

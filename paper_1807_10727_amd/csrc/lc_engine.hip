@@ -1,0 +1,451 @@
+// Round engine and C ABI (include/cc.h) of the plain single-graph solve.
+//
+// Host side of one LocalContraction round: enqueue the round's kernels on the caller's
+// stream, read the device round state back once, keep the per-round statistics.  The
+// library never allocates device memory; all arrays live in the caller's workspace.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cc.h"
+#include "lc_engine.hpp"
+
+namespace lc {
+
+const char *const kFamilyNames[kFamilies] = {"round_begin", "min1",   "min2",      "parent",   "relabel",
+                                             "sort_hist",   "sort_scan", "sort_scatter", "unique", "node_scan",
+                                             "nodes",       "map",    "rename",    "round_end", "compose",
+                                             "flatten"};
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
+    const size_t n = (size_t)std::max<int64_t>(n0, 1);
+    const size_t m = (size_t)std::max<int64_t>(m0, 2);
+    const size_t tiles = (size_t)ceil_div((int64_t)m, kSortTile);
+    const size_t parts = std::max<size_t>((size_t)ceil_div((int64_t)n, kScanTile),
+                                          (size_t)ceil_div((int64_t)(kRadix * tiles), kScanTile)) + 16;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return p;
+    };
+    Work t{};
+    t.st = (RoundState *)take(sizeof(RoundState));
+    t.m1 = (uint32_t *)take(4 * n);
+    t.lv = (uint32_t *)take(4 * n);
+    t.par = (uint32_t *)take(4 * n);
+    t.has_edge = (uint8_t *)take(n + 16);
+    t.is_label = (uint8_t *)take(n + 16);
+    t.newidx = (uint32_t *)take(4 * n);
+    t.names[0] = (uint32_t *)take(4 * n);
+    t.names[1] = (uint32_t *)take(4 * n);
+    t.idx_of = (uint32_t *)take(4 * n);
+    t.map0 = (uint32_t *)take(4 * n);
+    t.maps = (uint32_t *)take(4 * n);
+    if (batch) {
+        t.gids[0] = (uint32_t *)take(4 * n);
+        t.gids[1] = (uint32_t *)take(4 * n);
+        t.gid0 = (uint32_t *)take(4 * n);
+    }
+    t.keys[0] = (uint64_t *)take(8 * m);
+    t.keys[1] = (uint64_t *)take(8 * m);
+    t.counts = (uint32_t *)take(4 * kRadix * tiles);
+    t.tile_cnt = (uint32_t *)take(4 * tiles + 64);
+    t.partials = (uint32_t *)take(4 * parts);
+    t.n0 = n0;
+    t.m0 = m0;
+    if (w) *w = t;
+    return off;
+}
+
+int Engine::grid_for(int64_t units) const {
+    int64_t g = ceil_div(std::max<int64_t>(units, 1), kThreads);
+    return (int)std::min<int64_t>(g, grid_cap);
+}
+
+int Engine::grid_tiles(int64_t keys) const {
+    int64_t g = ceil_div(std::max<int64_t>(keys, 1), kSortTile);
+    return (int)std::min<int64_t>(g, grid_cap);
+}
+
+bool Engine::hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    err = buf;
+    failed_status = CC_E_HIP;
+    return false;
+}
+
+void Engine::ev_begin(int family) {
+    if (!profile) return;
+    if (ev_used + 2 > (int)events.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            events.push_back(e);
+        }
+    }
+    (void)hipEventRecord(events[ev_used], stream);
+    pending.push_back({family, ev_used});
+    ev_used += 2;
+}
+
+void Engine::ev_end() {
+    if (!profile || pending.empty()) return;
+    (void)hipEventRecord(events[pending.back().second + 1], stream);
+}
+
+void Engine::ev_collect() {
+    if (!profile) return;
+    for (auto &p : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, events[p.second], events[p.second + 1]) == hipSuccess) {
+            fam_ms[p.first] += ms;
+            fam_launches[p.first] += 1;
+        }
+    }
+    pending.clear();
+    ev_used = 0;
+}
+
+#define RUN(fam, expr)                                  \
+    do {                                                \
+        ev_begin(fam);                                  \
+        hipError_t e_ = (expr);                         \
+        ev_end();                                       \
+        if (!hip_ok(e_, kFamilyNames[fam])) return false; \
+    } while (0)
+
+bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc) {
+    const bool first = r == 0;
+    const EdgeIn *src = first ? &in : nullptr;
+    const int gn = grid_for(N);
+    const int gm = grid_for(ceil_div(M, first ? 4 : 2));
+    const int gt = grid_tiles(M);
+    const int gscan_n = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), kScanTile), grid_cap);
+    const int nbits = 2 * ceil_log2_host(std::max<int64_t>(N, 2));
+    const int passes = npasses(nbits);
+    const int64_t scan_entries = (int64_t)kRadix * ceil_div(std::max<int64_t>(M, 1), kSortTile);
+    const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
+
+    RUN(kRoundBegin, launch_round_begin(w, gn, stream));
+    RUN(kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
+    RUN(kMin2, launch_min2(w, src, gm, stream));
+    RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
+    RUN(kRelabel, launch_relabel(w, src, gm, stream));
+    for (int p = 0; p < passes; ++p) {
+        RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
+        RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 1));
+        RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
+        RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
+        RUN(kSortScatter, launch_sort_pass(w, p, gt, stream, 4));
+    }
+    RUN(kUnique, launch_unique(w, gt, stream, 0));
+    RUN(kUnique, launch_unique(w, 1, stream, 1));
+    RUN(kUnique, launch_unique(w, gt, stream, 2));
+    RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, gscan_n, stream, 0));
+    RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, 1, stream, 1));
+    RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, gscan_n, stream, 2));
+    RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
+    RUN(kMap, launch_map(w, r, gn, stream));
+    RUN(kRename, launch_rename(w, gm, stream));
+    RUN(kRoundEnd, launch_round_end(w, r, stream));
+    return true;
+}
+
+bool Engine::flatten() {
+    RUN(kFlatten, launch_flatten(w, grid_for(w.n0), stream));
+    host_levels = 0;
+    host_map_used = 0;
+    return true;
+}
+
+bool Engine::read_state() {
+    if (!hip_ok(hipMemcpyAsync(h_st, w.st, sizeof(RoundState), hipMemcpyDeviceToHost, stream), "state readback"))
+        return false;
+    if (!hip_ok(hipStreamSynchronize(stream), "stream synchronize")) return false;
+    ev_collect();
+    return true;
+}
+
+bool Engine::write_initial_state(int64_t n_cur, int64_t m_cur) {
+    memset(h_st, 0, sizeof(RoundState));
+    h_st->n_cur = (u64c)n_cur;
+    h_st->m_cur = (u64c)m_cur;
+    h_st->map_cap = (u64c)std::max<int64_t>(w.n0, 1);
+    if (!hip_ok(hipMemcpyAsync(w.st, h_st, sizeof(RoundState), hipMemcpyHostToDevice, stream), "state upload"))
+        return false;
+    return hip_ok(hipStreamSynchronize(stream), "stream synchronize");
+}
+
+int ceil_log2_host(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+struct cc_ctx : public lc::Engine {
+    cc_graph_desc g{};
+    cc_options o{};
+    std::vector<cc_round_stats> stats;
+    int32_t rounds = 0;       // rounds of this solve that had nodes
+    int32_t next_round = 0;   // index of the next round to enqueue
+    bool ran_first = false;   // round 0's kernels ran (map0 is valid)
+    bool labels_ready = false;
+    int64_t n_cur = 0, m_cur = 0;
+};
+
+namespace {
+
+// an error that ends the current solve (later calls return it until cc_reset)
+cc_status fail(cc_ctx *c, cc_status s, const char *msg) {
+    if (c) {
+        c->err = msg;
+        c->failed_status = s;
+    }
+    return s;
+}
+
+// a rejected call: the context is unchanged
+cc_status reject(cc_ctx *c, cc_status s, const char *msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+cc_status hip_status(cc_ctx *c) { return c->failed_status ? c->failed_status : CC_E_HIP; }
+
+cc_status reset_solve(cc_ctx *c, uint64_t seed) {
+    c->o.seed = seed;
+    c->stats.clear();
+    c->rounds = 0;
+    c->next_round = 0;
+    c->ran_first = false;
+    c->labels_ready = false;
+    c->done = c->g.n_edges == 0;
+    c->host_levels = 0;
+    c->host_map_used = 0;
+    c->n_cur = c->g.n_vertices;
+    c->m_cur = c->g.n_edges;
+    c->failed_status = 0;
+    c->err.clear();
+    for (int i = 0; i < kFamilies; ++i) {
+        c->fam_ms[i] = 0.0;
+        c->fam_launches[i] = 0;
+    }
+    if (!c->write_initial_state(c->n_cur, c->m_cur)) return hip_status(c);
+    return CC_OK;
+}
+
+// one round; returns CC_OK, CC_DONE or an error
+cc_status round_once(cc_ctx *c, cc_round_stats *out) {
+    if (c->failed_status) return c->failed_status;
+    if (!c->ws) return reject(c, CC_E_NOMEM, "no workspace: call cc_set_workspace first");
+    if (c->done) return CC_DONE;
+    const int r = c->next_round;
+    const int64_t N = r == 0 ? c->g.n_vertices : c->n_cur;
+    const int64_t M = r == 0 ? c->g.n_edges : c->m_cur;
+    if (r > 0 && (c->host_levels >= kMaxLevels || c->host_map_used + N > std::max<int64_t>(c->g.n_vertices, 1))) {
+        if (!c->flatten()) return hip_status(c);
+    }
+    PrioCtx pc{};
+    pc.key = round_key(c->o.seed, r);
+    if (!c->enqueue_round(r, N, M, pc)) return hip_status(c);
+    if (!c->read_state()) return hip_status(c);
+    const RoundState &st = *c->h_st;
+    if (st.err & 1u) return fail(c, CC_E_INPUT, "an edge record names a vertex outside [0, n_vertices)");
+    if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
+    if (r == 0) c->ran_first = true;
+    if (r > 0) {
+        c->host_levels += 1;
+        c->host_map_used += N;
+    }
+    c->next_round = r + 1;
+    c->n_cur = (int64_t)st.n_cur;
+    c->m_cur = (int64_t)st.m_cur;
+    c->done = st.m_cur == 0;
+    if (r == 0 && st.n_active == 0) {   // no loop-free record: zero rounds, labels are the ids
+        return CC_DONE;
+    }
+    cc_round_stats s{};
+    s.round = r;
+    s.n_active = (int64_t)st.n_active;
+    s.m_in = M;
+    s.m_survive = (int64_t)st.s_count;
+    s.m_out = (int64_t)st.m_next;
+    s.n_finalised = (int64_t)st.n_final;
+    c->stats.push_back(s);
+    c->rounds = r + 1;
+    if (out) *out = s;
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx **out) {
+    if (!out) return CC_E_ARG;
+    *out = nullptr;
+    if (!graph || !opts) return CC_E_ARG;
+    const cc_graph_desc &g = *graph;
+    if (g.n_vertices < 0 || g.n_vertices > 0x7FFFFFFFLL || g.n_edges < 0 || g.n_edges > 0xFFFFFFFELL) return CC_E_ARG;
+    if (g.layout < CC_EDGES_SOA_I32 || g.layout > CC_EDGES_PACKED_U64 || g.reserved != 0) return CC_E_ARG;
+    if (g.n_edges > 0 && (!g.src || (g.layout != CC_EDGES_PACKED_U64 && !g.dst))) return CC_E_ARG;
+    if (opts->max_rounds < 0) return CC_E_ARG;
+    cc_ctx *c = new (std::nothrow) cc_ctx();
+    if (!c) return CC_E_NOMEM;
+    c->g = g;
+    c->o = *opts;
+    c->stream = (hipStream_t)opts->stream;
+    c->profile = (opts->flags & CC_PROFILE) != 0;
+    c->batch = false;
+    c->in.s = g.src;
+    c->in.d = g.dst;
+    c->in.m = g.n_edges;
+    c->in.n = (uint32_t)g.n_vertices;
+    c->in.layout = g.layout == CC_EDGES_SOA_I32 ? kSoa32 : g.layout == CC_EDGES_SOA_I64 ? kSoa64 : kPacked;
+    const bool aligned = ((uintptr_t)g.src % 16 == 0) && (g.layout == CC_EDGES_PACKED_U64 || (uintptr_t)g.dst % 16 == 0);
+    c->in.vec = aligned ? 1 : 0;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    c->grid_cap = std::max(cus, 1) * 8;
+    if (hipHostMalloc((void **)&c->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+        // no usable device yet: a pageable mirror still works for every later copy
+        (void)hipGetLastError();
+        c->h_st = (RoundState *)calloc(1, sizeof(RoundState));
+        c->h_st_pageable = true;
+        if (!c->h_st) {
+            delete c;
+            return CC_E_NOMEM;
+        }
+    }
+    c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, nullptr, nullptr);
+    *out = c;
+    return CC_OK;
+}
+
+cc_status cc_workspace_size(const cc_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return CC_E_ARG;
+    *bytes = c->ws_need;
+    return CC_OK;
+}
+
+cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
+    if (!c || !d_ws) return CC_E_ARG;
+    if (bytes < c->ws_need) return reject(c, CC_E_NOMEM, "workspace smaller than cc_workspace_size()");
+    if ((uintptr_t)d_ws % 256 != 0) return reject(c, CC_E_ARG, "workspace must be 256-byte aligned");
+    c->ws = d_ws;
+    c->ws_bytes = bytes;
+    plan_workspace(c->g.n_vertices, c->g.n_edges, false, (char *)d_ws, &c->w);
+    return reset_solve(c, c->o.seed);
+}
+
+cc_status cc_reset(cc_ctx *c, uint64_t seed) {
+    if (!c) return CC_E_ARG;
+    if (!c->ws) return reject(c, CC_E_NOMEM, "no workspace: call cc_set_workspace first");
+    return reset_solve(c, seed);
+}
+
+cc_status cc_contract_round(cc_ctx *c, cc_round_stats *out) {
+    if (!c) return CC_E_ARG;
+    cc_status s = round_once(c, out);
+    if (s == CC_DONE) c->labels_ready = true;
+    return s;
+}
+
+cc_status cc_run(cc_ctx *c, int32_t *rounds) {
+    if (!c) return CC_E_ARG;
+    for (;;) {
+        if (c->o.max_rounds > 0 && c->next_round >= c->o.max_rounds) break;
+        cc_status s = round_once(c, nullptr);
+        if (s == CC_DONE) break;
+        if (s != CC_OK) return s;
+    }
+    if (c->failed_status) return c->failed_status;
+    c->labels_ready = true;
+    if (rounds) *rounds = c->rounds;
+    return CC_OK;
+}
+
+cc_status cc_labels(cc_ctx *c, void *d_labels) {
+    if (!c || !d_labels) return CC_E_ARG;
+    if (c->failed_status) return c->failed_status;
+    if (!c->labels_ready) return reject(c, CC_E_STATE, "labels requested before cc_run or CC_DONE");
+    if (c->g.n_vertices == 0) return CC_OK;
+    const bool out64 = c->g.layout == CC_EDGES_SOA_I64;
+    const int grid = c->grid_for(c->g.n_vertices);
+    c->ev_begin(kCompose);
+    hipError_t e = launch_compose(c->w, !c->ran_first, c->next_round, d_labels, out64, false, nullptr, grid, c->stream);
+    c->ev_end();
+    if (!c->hip_ok(e, "compose")) return CC_E_HIP;
+    if (c->o.flags & CC_CANONICAL) {
+        e = launch_canonical(c->w, d_labels, out64, false, nullptr, grid, c->stream);
+        if (!c->hip_ok(e, "canonical labels")) return CC_E_HIP;
+    }
+    return CC_OK;
+}
+
+cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {
+    if (!c || !d_parents) return CC_E_ARG;
+    if (c->failed_status) return c->failed_status;
+    if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
+    const int last = c->next_round - 1;
+    hipError_t e = launch_dump_parents(c->w, d_parents, last, c->grid_for(c->g.n_vertices), c->stream);
+    if (!c->hip_ok(e, "dump parents")) return CC_E_HIP;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
+    if (n_nodes) *n_nodes = last < (int)c->stats.size() ? c->stats[last].n_active : 0;
+    return CC_OK;
+}
+
+cc_status cc_get_round_stats(const cc_ctx *c, int32_t r, cc_round_stats *out) {
+    if (!c || !out || r < 0 || r >= (int32_t)c->stats.size()) return CC_E_ARG;
+    *out = c->stats[r];
+    return CC_OK;
+}
+
+int32_t cc_kernel_family_count(void) { return kFamilies; }
+
+const char *cc_kernel_family_name(int32_t i) { return (i >= 0 && i < kFamilies) ? kFamilyNames[i] : nullptr; }
+
+cc_status cc_kernel_times(const cc_ctx *c, double *ms, int64_t *launches, int32_t cap) {
+    if (!c) return CC_E_ARG;
+    for (int i = 0; i < kFamilies && i < cap; ++i) {
+        if (ms) ms[i] = c->fam_ms[i];
+        if (launches) launches[i] = c->fam_launches[i];
+    }
+    return CC_OK;
+}
+
+cc_status cc_destroy(cc_ctx *c) {
+    if (!c) return CC_E_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto e : c->events) (void)hipEventDestroy(e);
+    if (c->h_st) {
+        if (c->h_st_pageable)
+            free(c->h_st);
+        else
+            (void)hipHostFree(c->h_st);
+    }
+    delete c;
+    return CC_OK;
+}
+
+const char *cc_last_error(const cc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+const char *cc_version(void) { return "lc-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

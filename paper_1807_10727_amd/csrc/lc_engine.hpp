@@ -1,0 +1,60 @@
+// Host round engine shared by the plain solve and the batched solve.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+enum Family {
+    kRoundBegin = 0, kMin1, kMin2, kParent, kRelabel, kSortHist, kSortScan, kSortScatter, kUnique, kNodeScan,
+    kNodes, kMap, kRename, kRoundEnd, kCompose, kFlatten, kFamilies
+};
+extern const char *const kFamilyNames[kFamilies];
+
+// Lays the workspace out from `base` (or only sizes it when base is null).
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w);
+int ceil_log2_host(int64_t n);
+
+struct Engine {
+    hipStream_t stream = nullptr;
+    Work w{};
+    EdgeIn in{};
+    bool batch = false;
+    bool profile = false;
+    bool done = false;
+    int grid_cap = 2048;
+    void *ws = nullptr;
+    size_t ws_bytes = 0, ws_need = 0;
+    RoundState *h_st = nullptr;   // pinned host mirror of the device round state
+    bool h_st_pageable = false;
+    int host_levels = 0;          // per-round maps currently kept in the arena
+    int64_t host_map_used = 0;
+    std::string err;
+    int failed_status = 0;
+
+    // kernel timing (CC_PROFILE)
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, int>> pending;
+    int ev_used = 0;
+    double fam_ms[kFamilies] = {};
+    int64_t fam_launches[kFamilies] = {};
+
+    int grid_for(int64_t units) const;
+    int grid_tiles(int64_t keys) const;
+    bool hip_ok(hipError_t e, const char *what);
+    void ev_begin(int family);
+    void ev_end();
+    void ev_collect();
+    bool enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc);
+    bool flatten();
+    bool read_state();
+    bool write_initial_state(int64_t n_cur, int64_t m_cur);
+};
+
+}  // namespace lc

@@ -1,0 +1,133 @@
+// Internal interface between the round engine (host) and the kernels (device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lc_device.hpp"
+
+namespace lc {
+
+typedef unsigned long long u64c;  // type of 64-bit device atomics
+
+constexpr int kMaxLevels = 64;    // per-round maps kept before they are folded into map0
+
+// Device-resident state of the current round.  Every kernel reads its element counts
+// from here, so a sequence of rounds can be enqueued (or captured in a graph) without
+// host round trips; the eager driver reads it back once per round.
+struct RoundState {
+    u64c n_cur;        // N_r: nodes of this round (round 0: the whole id space n0)
+    u64c m_cur;        // M_r: records of this round
+    u64c n_active;     // nodes with a loop-free edge
+    u64c s_count;      // records surviving relabelling (repeats counted)
+    u64c m_next;       // distinct edges of the next graph
+    u64c n_next;       // nodes of the next graph
+    u64c n_final;      // parents of this round that keep no edge
+    u64c n_prev;       // N of the round that just ended
+    u64c aux_n;        // element count handed from one kernel to the next (scans)
+    u64c map_off;      // next free entry of the map arena
+    u64c map_cap;      // entries of the map arena
+    uint32_t err;      // bit 0: input id out of range; bit 1: map arena overflow
+    int32_t round;     // r
+    int32_t nbits;     // key bits of this round's sort: 2 * ceil(log2 N_r)
+    int32_t e_sel;     // key buffer that holds E_r (rounds >= 1)
+    int32_t done;      // no edge left
+    int32_t levels;    // per-round maps in the arena
+    u64c level_off[kMaxLevels];
+};
+
+enum Layout { kSoa32 = 0, kSoa64 = 1, kPacked = 2 };
+
+// Input edge records (round 0 only).
+struct EdgeIn {
+    const void *s;
+    const void *d;
+    int64_t m;      // records
+    uint32_t n;     // valid ids are [0, n)
+    int32_t layout;
+    int32_t vec;    // 1: both arrays 16-byte aligned, vector loads allowed
+};
+
+// Priority context.  Plain graph: one round key.  Batch of independent graphs packed in
+// one id space: graph g owns ids voff[g] .. voff[g+1]-1 and hashes its local ids with its
+// own per-round key keys[g].
+struct PrioCtx {
+    RoundKey key;
+    const RoundKey *keys;   // [G] (batch)
+    const uint32_t *voff;   // [G+1] (batch)
+};
+
+// Workspace arrays of one solve (device pointers).
+struct Work {
+    RoundState *st;
+    uint32_t *m1;        // [n0] one-hop minima
+    uint32_t *lv;        // [n0] two-hop minima
+    uint32_t *par;       // [n0] parent of each node (compact index of this round)
+    uint8_t *has_edge;   // [n0] node of this round is a node of the next graph
+    uint8_t *is_label;   // [n0] node of this round is somebody's parent
+    uint32_t *newidx;    // [n0] exclusive scan of has_edge
+    uint32_t *names[2];  // [n0] node names, rounds >= 1 (round r uses names[r & 1])
+    uint32_t *gids[2];   // [n0] batch: graph of each node, rounds >= 1
+    uint32_t *gid0;      // [n0] batch: graph of each vertex (round 0)
+    uint32_t *idx_of;    // [n0] compact index of a name in the current round
+    uint32_t *map0;      // [n0] vertex -> node of the first kept level (or kFinal | name)
+    uint32_t *maps;      // [n0] arena of the per-round maps of rounds >= 1
+    uint64_t *keys[2];   // [m0] edge / sort key ping-pong buffers
+    uint32_t *counts;    // [kRadix * sort tiles] digit counts of one sort pass
+    uint32_t *partials;  // scan partial sums
+    uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
+    int64_t n0, m0;
+};
+
+constexpr int kThreads = 256;                      // workgroup size of the streaming kernels
+constexpr int kSortItems = 16;                     // keys per thread in a sort tile
+constexpr int kSortTile = kThreads * kSortItems;   // 4096 keys per sort tile
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kThreads * kScanItems;   // elements per block of the generic scan
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxPasses = 8;                      // 64-bit keys
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Which key buffer each step uses, from the device state (identical on host and device).
+__host__ __device__ inline int npasses(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }
+__host__ __device__ inline int sort_src(int round, int e_sel) { return round == 0 ? 0 : 1 - e_sel; }
+__host__ __device__ inline int sorted_sel(int round, int e_sel, int nbits) {
+    return sort_src(round, e_sel) ^ (npasses(nbits) & 1);
+}
+
+// ---- launchers (lc_kernels.hip, lc_sort.hip) ------------------------------------------
+// `grid` arguments are workgroup counts chosen by the host (grid-stride loops cover the
+// rest); every kernel reads its true element count from RoundState.
+
+hipError_t launch_round_begin(const Work &w, int grid, hipStream_t s);
+hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool batch, int round, int grid,
+                       hipStream_t s);
+hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
+hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s);
+hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
+hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
+                          int grid, hipStream_t s, int stage);
+hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
+                           hipStream_t s, int stage);
+hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);
+hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
+hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
+hipError_t launch_rename(const Work &w, int grid, hipStream_t s);
+hipError_t launch_round_end(const Work &w, int round, hipStream_t s);
+hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,
+                          const uint32_t *voff, int grid, hipStream_t s);
+hipError_t launch_flatten(const Work &w, int grid, hipStream_t s);
+hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch, const uint32_t *voff, int grid,
+                            hipStream_t s);
+hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int grid, hipStream_t s);
+hipError_t launch_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, int round, hipStream_t s);
+hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s);
+
+// Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
+// Sort stages: 0 = digit counts, 1..3 = scan of the counts, 4 = scatter.
+// Unique stages: 0 = heads per tile, 1 = scan (one workgroup), 2 = write + mark.
+
+}  // namespace lc

@@ -1,0 +1,660 @@
+// Round kernels of LocalContraction on gfx950.
+//
+// One round (one phase of the method, Section 3 "LocalContraction"):
+//   round_begin  reset counters, m1 = lv = +inf, flags = 0 over the N_r nodes
+//   min1         m1[x] = min over the closed neighbourhood N(x) of rho   (Section 2: x in N(x))
+//   min2         lv[x] = min over N(x) of m1 = min over N(N(x)) of rho
+//   parent       parent of x = the node whose priority is lv[x] (inverse of the bijection)
+//   relabel      every record (a, b) -> (p(a), p(b)); loops dropped; survivors compacted
+//   sort/unique  duplicates dropped (lc_sort.hip)
+//   nodes/map    next node set, names, per-round map of the label composition
+//   rename       edges of the next graph in its compact index space
+//   round_end    advance the device state
+// Merged nodes are named by the original id of their parent vertex, and the per-round
+// maps are composed at the end into the label of every original vertex.
+//
+// Both min passes fold the node's own priority into each update (min(rho(a), rho(b)) is
+// sent to both endpoints), so the +inf fill replaces an initialisation pass; ids without a
+// loop-free record keep +inf and are their own parent.  Each update first reads the
+// current value and only issues the atomic when it can lower it: values only decrease, so
+// a stale read can only cause a redundant atomic, never a missed one.
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------------------
+// edge readers: each thread handles a chunk of kV consecutive records.  Records that are
+// out of range or past the end come back as a loop (a == b), which every kernel skips.
+// ---------------------------------------------------------------------------------------
+
+template <int V>
+struct ReadSoa32 {
+    static constexpr int kV = V;
+    const int32_t *s, *d;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadSoa32(const EdgeIn &e)
+        : s((const int32_t *)e.s), d((const int32_t *)e.d), m(e.m), n(e.n) {}
+    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
+    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        int32_t sa[V], sb[V];
+        if (V == 4 && base + 4 <= m) {
+            int4 x = *(const int4 *)(s + base);
+            int4 y = *(const int4 *)(d + base);
+            sa[0] = x.x; sa[1 % V] = x.y; sa[2 % V] = x.z; sa[3 % V] = x.w;
+            sb[0] = y.x; sb[1 % V] = y.y; sb[2 % V] = y.z; sb[3 % V] = y.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                sa[j] = base + j < m ? s[base + j] : 0;
+                sb[j] = base + j < m ? d[base + j] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            bool ok = (uint32_t)sa[j] < n && (uint32_t)sb[j] < n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? (uint32_t)sa[j] : 0u;
+            b[j] = ok ? (uint32_t)sb[j] : 0u;
+        }
+    }
+};
+
+template <int V>
+struct ReadSoa64 {
+    static constexpr int kV = V;
+    const int64_t *s, *d;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadSoa64(const EdgeIn &e)
+        : s((const int64_t *)e.s), d((const int64_t *)e.d), m(e.m), n(e.n) {}
+    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
+    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        int64_t sa[V], sb[V];
+        if (V == 2 && base + 2 <= m) {
+            longlong2 x = *(const longlong2 *)(s + base);
+            longlong2 y = *(const longlong2 *)(d + base);
+            sa[0] = x.x; sa[1 % V] = x.y;
+            sb[0] = y.x; sb[1 % V] = y.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                sa[j] = base + j < m ? s[base + j] : 0;
+                sb[j] = base + j < m ? d[base + j] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            bool ok = (uint64_t)sa[j] < (uint64_t)n && (uint64_t)sb[j] < (uint64_t)n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? (uint32_t)sa[j] : 0u;
+            b[j] = ok ? (uint32_t)sb[j] : 0u;
+        }
+    }
+};
+
+template <int V>
+struct ReadPacked {
+    static constexpr int kV = V;
+    const uint64_t *k;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadPacked(const EdgeIn &e) : k((const uint64_t *)e.s), m(e.m), n(e.n) {}
+    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
+    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        uint64_t r[V];
+        if (V == 2 && base + 2 <= m) {
+            ulonglong2 x = *(const ulonglong2 *)(k + base);
+            r[0] = x.x; r[1 % V] = x.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) r[j] = base + j < m ? k[base + j] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            uint32_t x = (uint32_t)(r[j] >> 32), y = (uint32_t)r[j];
+            bool ok = x < n && y < n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? x : 0u;
+            b[j] = ok ? y : 0u;
+        }
+    }
+};
+
+// Edges of rounds >= 1: (a << 32 | b) in the round's compact index space, in the key
+// buffer named by the device state; the count comes from the device state too.
+struct ReadInternal {
+    static constexpr int kV = 2;
+    uint64_t *k0, *k1;
+    __host__ explicit ReadInternal(const Work &w) : k0(w.keys[0]), k1(w.keys[1]) {}
+    __device__ int64_t chunks(const RoundState *st) const { return (int64_t)((st->m_cur + 1) / 2); }
+    __device__ void read(const RoundState *st, int64_t c, uint32_t *a, uint32_t *b, bool &) const {
+        const uint64_t *k = st->e_sel ? k1 : k0;
+        const int64_t m = (int64_t)st->m_cur;
+        const int64_t base = c * 2;
+        uint64_t r0, r1;
+        if (base + 2 <= m) {
+            ulonglong2 x = *(const ulonglong2 *)(k + base);
+            r0 = x.x;
+            r1 = x.y;
+        } else {
+            r0 = k[base];
+            r1 = 0ull;
+        }
+        a[0] = (uint32_t)(r0 >> 32); b[0] = (uint32_t)r0;
+        a[1] = (uint32_t)(r1 >> 32); b[1] = (uint32_t)r1;
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// priorities of nodes
+// ---------------------------------------------------------------------------------------
+
+template <bool kFirst, bool kBatch>
+__device__ inline uint32_t node_prio(const PrioCtx &pc, const Work &w, const uint32_t *names, const uint32_t *gids,
+                                     uint32_t i) {
+    const uint32_t name = kFirst ? i : names[i];
+    if (!kBatch) return prio(pc.key, name);
+    const uint32_t g = kFirst ? w.gid0[i] : gids[i];
+    return prio(pc.keys[g], name - pc.voff[g]);
+}
+
+__device__ inline int ceil_log2(uint64_t n) { return n <= 1 ? 0 : 64 - __clzll((long long)(n - 1)); }
+
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_active = 0;
+        st->s_count = 0;
+        st->m_next = 0;
+        st->n_next = 0;
+        st->n_final = 0;
+        st->nbits = 2 * ceil_log2(n < 2 ? 2 : (uint64_t)n);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        w.m1[i] = kInf;
+        w.lv[i] = kInf;
+        w.has_edge[i] = 0;
+        w.is_label[i] = 0;
+    }
+}
+
+template <class R, bool kFirst, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, const uint32_t *names,
+                                                   const uint32_t *gids) {
+    constexpr int V = R::kV;
+    const int64_t nch = rd.chunks(w.st);
+    bool bad = false;
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
+        uint32_t a[V], b[V], v[V], ca[V], cb[V];
+        rd.read(w.st, c, a, b, bad);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (a[j] != b[j]) {
+                uint32_t pa = node_prio<kFirst, kBatch>(pc, w, names, gids, a[j]);
+                uint32_t pb = node_prio<kFirst, kBatch>(pc, w, names, gids, b[j]);
+                v[j] = min(pa, pb);
+                ca[j] = w.m1[a[j]];
+                cb[j] = w.m1[b[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (a[j] != b[j]) {
+                if (ca[j] > v[j]) atomicMin(&w.m1[a[j]], v[j]);
+                if (cb[j] > v[j]) atomicMin(&w.m1[b[j]], v[j]);
+            }
+        }
+    }
+    if (bad) atomicOr(&w.st->err, 1u);
+}
+
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
+    constexpr int V = R::kV;
+    const int64_t nch = rd.chunks(w.st);
+    bool bad = false;
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
+        uint32_t a[V], b[V], v[V], ca[V], cb[V];
+        rd.read(w.st, c, a, b, bad);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (a[j] != b[j]) {
+                v[j] = min(w.m1[a[j]], w.m1[b[j]]);
+                ca[j] = w.lv[a[j]];
+                cb[j] = w.lv[b[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (a[j] != b[j]) {
+                if (ca[j] > v[j]) atomicMin(&w.lv[a[j]], v[j]);
+                if (cb[j] > v[j]) atomicMin(&w.lv[b[j]], v[j]);
+            }
+        }
+    }
+}
+
+template <bool kFirst, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const uint32_t *gids) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    uint32_t active = 0;
+    bool broken = false;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t l = w.lv[i];
+        if (l == kInf) {  // no loop-free record touches this id (round 0 only)
+            w.par[i] = (uint32_t)i;
+            continue;
+        }
+        uint32_t name;
+        if (!kBatch) {
+            name = prio_inv(pc.key, l);
+        } else {
+            const uint32_t g = kFirst ? w.gid0[i] : gids[i];
+            name = prio_inv(pc.keys[g], l) + pc.voff[g];
+        }
+        uint32_t p;
+        if (kFirst) {
+            p = name;
+        } else {
+            p = (int64_t)name < w.n0 ? w.idx_of[name] : 0xFFFFFFFFu;
+        }
+        if ((int64_t)p >= n) {  // cannot happen for a consistent state; never index out of range
+            broken = true;
+            p = (uint32_t)i;
+        }
+        w.par[i] = p;
+        w.is_label[p] = 1;
+        ++active;
+    }
+    active = wave_sum(active);
+    if (lane_id() == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
+    constexpr int V = R::kV;
+    RoundState *st = w.st;
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    __shared__ u64c base_sh;
+    const int64_t nch = rd.chunks(st);
+    uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
+    const int nb = st->nbits / 2;
+    bool bad = false;
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
+        uint64_t key[V];
+        bool keep[V];
+        uint32_t cnt = 0;
+        if (c < nch) {
+            uint32_t a[V], b[V], pa[V], pb[V];
+            rd.read(st, c, a, b, bad);
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                pa[j] = a[j] != b[j] ? w.par[a[j]] : 0u;
+                pb[j] = a[j] != b[j] ? w.par[b[j]] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                keep[j] = pa[j] != pb[j];
+                uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
+                key[j] = ((uint64_t)lo << nb) | hi;
+                cnt += keep[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) keep[j] = false;
+        }
+        uint32_t total;
+        uint32_t pre = block_excl_scan<kThreads>(cnt, lds, &total);
+        if (threadIdx.x == 0) base_sh = total ? atomicAdd(&st->s_count, (u64c)total) : 0ull;
+        __syncthreads();
+        const u64c base = base_sh;
+        uint32_t off = pre;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (keep[j]) out[base + off++] = key[j];
+        }
+        __syncthreads();
+    }
+    (void)bad;
+}
+
+template <bool kFirst, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_nodes(Work w, const uint32_t *names_cur, uint32_t *names_next,
+                                                    const uint32_t *gids_cur, uint32_t *gids_next) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    uint32_t fin = 0;
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+        if (w.has_edge[j]) {
+            const uint32_t k = w.newidx[j];
+            const uint32_t nm = kFirst ? (uint32_t)j : names_cur[j];
+            names_next[k] = nm;
+            w.idx_of[nm] = k;
+            if (kBatch) gids_next[k] = kFirst ? w.gid0[j] : gids_cur[j];
+        } else if (w.is_label[j]) {
+            ++fin;
+        }
+    }
+    fin = wave_sum(fin);
+    if (lane_id() == 0 && fin) atomicAdd(&st->n_final, (u64c)fin);
+}
+
+template <bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_cur) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    uint32_t *out;
+    if (kFirst) {
+        out = w.map0;
+    } else {
+        if (st->map_off + (u64c)n > st->map_cap || st->levels >= kMaxLevels) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 2u);
+            return;
+        }
+        out = w.maps + st->map_off;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t p = w.par[i];
+        out[i] = w.has_edge[p] ? w.newidx[p] : (kFinal | (kFirst ? p : names_cur[p]));
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rename(Work w) {
+    RoundState *st = w.st;
+    const int64_t m = (int64_t)st->m_next;
+    const int t = sorted_sel(st->round, st->e_sel, st->nbits);
+    const uint64_t *in = w.keys[1 - t];
+    uint64_t *out = w.keys[t];
+    const int nb = st->nbits / 2;
+    const uint64_t mask = (1ull << nb) - 1ull;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads) {
+        const uint64_t k = in[i];
+        const uint32_t lo = (uint32_t)(k >> nb), hi = (uint32_t)(k & mask);
+        out[i] = ((uint64_t)w.newidx[lo] << 32) | w.newidx[hi];
+    }
+}
+
+template <bool kFirst>
+__global__ void k_round_end(Work w) {
+    RoundState *st = w.st;
+    st->n_prev = st->n_cur;
+    if (!kFirst && !(st->err & 2u)) {
+        st->level_off[st->levels] = st->map_off;
+        st->levels += 1;
+        st->map_off += st->n_cur;
+    }
+    st->e_sel = sorted_sel(st->round, st->e_sel, st->nbits);
+    st->n_cur = st->n_next;
+    st->m_cur = st->m_next;
+    st->round += 1;
+    st->done = st->m_next == 0 ? 1 : 0;
+}
+
+// label of every original vertex: chase its map0 entry through the kept levels
+template <bool kOut64, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_compose(Work w, int identity, const uint32_t *names_cur,
+                                                      void *labels, const uint32_t *voff) {
+    const RoundState *st = w.st;
+    const int levels = st->levels;
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
+        uint32_t name;
+        if (identity) {
+            name = (uint32_t)v;
+        } else {
+            uint32_t x = w.map0[v];
+            for (int l = 0; l < levels && !(x & kFinal); ++l) x = w.maps[st->level_off[l] + x];
+            name = (x & kFinal) ? (x & ~kFinal) : (names_cur ? names_cur[x] : x);
+        }
+        const uint32_t lab = kBatch ? name - voff[w.gid0[v]] : name;
+        if (kOut64)
+            ((int64_t *)labels)[v] = (int64_t)lab;
+        else
+            ((int32_t *)labels)[v] = (int32_t)lab;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_flatten(Work w) {
+    const RoundState *st = w.st;
+    const int levels = st->levels;
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
+        uint32_t x = w.map0[v];
+        for (int l = 0; l < levels && !(x & kFinal); ++l) x = w.maps[st->level_off[l] + x];
+        w.map0[v] = x;
+    }
+}
+
+__global__ void k_flatten_reset(Work w) {
+    w.st->levels = 0;
+    w.st->map_off = 0;
+}
+
+template <bool kOut64, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_canon_min(Work w, const void *labels, const uint32_t *voff) {
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
+        uint32_t lab = kOut64 ? (uint32_t)((const int64_t *)labels)[v] : (uint32_t)((const int32_t *)labels)[v];
+        const uint32_t base = kBatch ? voff[w.gid0[v]] : 0u;
+        atomicMin(&w.m1[lab + base], (uint32_t)v);
+    }
+}
+
+template <bool kOut64, bool kBatch>
+__global__ __launch_bounds__(kThreads) void k_canon_apply(Work w, void *labels, const uint32_t *voff) {
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
+        uint32_t lab = kOut64 ? (uint32_t)((const int64_t *)labels)[v] : (uint32_t)((const int32_t *)labels)[v];
+        const uint32_t base = kBatch ? voff[w.gid0[v]] : 0u;
+        const uint32_t c = w.m1[lab + base] - base;
+        if (kOut64)
+            ((int64_t *)labels)[v] = (int64_t)c;
+        else
+            ((int32_t *)labels)[v] = (int32_t)c;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = v;
+}
+
+// parents of the round that just ended, by name (inspection aid)
+__global__ __launch_bounds__(kThreads) void k_dump_parents(Work w, int first, const uint32_t *names_prev,
+                                                           int32_t *out) {
+    const int64_t n = (int64_t)w.st->n_prev;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        if (first && w.lv[i] == kInf) continue;
+        const uint32_t p = w.par[i];
+        const uint32_t x = first ? (uint32_t)i : names_prev[i];
+        out[x] = (int32_t)(first ? p : names_prev[p]);
+    }
+}
+
+__global__ void k_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t g, int32_t round) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g; i += gridDim.x * blockDim.x)
+        keys[i] = round_key(seeds[i], round);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t g) {
+    for (int32_t j = blockIdx.x; j < g; j += gridDim.x)
+        for (uint32_t v = voff[j] + threadIdx.x; v < voff[j + 1]; v += kThreads) gid0[v] = (uint32_t)j;
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+
+#define LC_LAUNCH(kern, grid, ...)                                            \
+    do {                                                                      \
+        hipLaunchKernelGGL((kern), dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__); \
+        return hipGetLastError();                                             \
+    } while (0)
+
+hipError_t launch_round_begin(const Work &w, int grid, hipStream_t s) { LC_LAUNCH(k_round_begin, grid, w); }
+
+template <bool kBatch>
+static hipError_t min1_in(const Work &w, const EdgeIn &e, const PrioCtx &p, int grid, hipStream_t s) {
+    const uint32_t *nul = nullptr;
+    switch (e.layout) {
+        case kSoa32:
+            if (e.vec) LC_LAUNCH((k_min1<ReadSoa32<4>, true, kBatch>), grid, ReadSoa32<4>(e), w, p, nul, nul);
+            LC_LAUNCH((k_min1<ReadSoa32<1>, true, kBatch>), grid, ReadSoa32<1>(e), w, p, nul, nul);
+        case kSoa64:
+            if (e.vec) LC_LAUNCH((k_min1<ReadSoa64<2>, true, kBatch>), grid, ReadSoa64<2>(e), w, p, nul, nul);
+            LC_LAUNCH((k_min1<ReadSoa64<1>, true, kBatch>), grid, ReadSoa64<1>(e), w, p, nul, nul);
+        default:
+            if (e.vec) LC_LAUNCH((k_min1<ReadPacked<2>, true, kBatch>), grid, ReadPacked<2>(e), w, p, nul, nul);
+            LC_LAUNCH((k_min1<ReadPacked<1>, true, kBatch>), grid, ReadPacked<1>(e), w, p, nul, nul);
+    }
+}
+
+hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool batch, int round, int grid,
+                       hipStream_t s) {
+    if (in) return batch ? min1_in<true>(w, *in, p, grid, s) : min1_in<false>(w, *in, p, grid, s);
+    const uint32_t *names = w.names[round & 1];
+    const uint32_t *gids = w.gids[round & 1];
+    if (batch) LC_LAUNCH((k_min1<ReadInternal, false, true>), grid, ReadInternal(w), w, p, names, gids);
+    LC_LAUNCH((k_min1<ReadInternal, false, false>), grid, ReadInternal(w), w, p, names, gids);
+}
+
+hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s) {
+    if (!in) LC_LAUNCH(k_min2<ReadInternal>, grid, ReadInternal(w), w);
+    const EdgeIn &e = *in;
+    switch (e.layout) {
+        case kSoa32:
+            if (e.vec) LC_LAUNCH(k_min2<ReadSoa32<4>>, grid, ReadSoa32<4>(e), w);
+            LC_LAUNCH(k_min2<ReadSoa32<1>>, grid, ReadSoa32<1>(e), w);
+        case kSoa64:
+            if (e.vec) LC_LAUNCH(k_min2<ReadSoa64<2>>, grid, ReadSoa64<2>(e), w);
+            LC_LAUNCH(k_min2<ReadSoa64<1>>, grid, ReadSoa64<1>(e), w);
+        default:
+            if (e.vec) LC_LAUNCH(k_min2<ReadPacked<2>>, grid, ReadPacked<2>(e), w);
+            LC_LAUNCH(k_min2<ReadPacked<1>>, grid, ReadPacked<1>(e), w);
+    }
+}
+
+hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s) {
+    const uint32_t *gids = w.gids[round & 1];
+    if (round == 0) {
+        if (batch) LC_LAUNCH((k_parent<true, true>), grid, w, p, gids);
+        LC_LAUNCH((k_parent<true, false>), grid, w, p, gids);
+    }
+    if (batch) LC_LAUNCH((k_parent<false, true>), grid, w, p, gids);
+    LC_LAUNCH((k_parent<false, false>), grid, w, p, gids);
+}
+
+hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s) {
+    if (!in) LC_LAUNCH(k_relabel<ReadInternal>, grid, ReadInternal(w), w);
+    const EdgeIn &e = *in;
+    switch (e.layout) {
+        case kSoa32:
+            if (e.vec) LC_LAUNCH(k_relabel<ReadSoa32<4>>, grid, ReadSoa32<4>(e), w);
+            LC_LAUNCH(k_relabel<ReadSoa32<1>>, grid, ReadSoa32<1>(e), w);
+        case kSoa64:
+            if (e.vec) LC_LAUNCH(k_relabel<ReadSoa64<2>>, grid, ReadSoa64<2>(e), w);
+            LC_LAUNCH(k_relabel<ReadSoa64<1>>, grid, ReadSoa64<1>(e), w);
+        default:
+            if (e.vec) LC_LAUNCH(k_relabel<ReadPacked<2>>, grid, ReadPacked<2>(e), w);
+            LC_LAUNCH(k_relabel<ReadPacked<1>>, grid, ReadPacked<1>(e), w);
+    }
+}
+
+hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s) {
+    const uint32_t *nc = w.names[round & 1];
+    uint32_t *nn = w.names[(round + 1) & 1];
+    const uint32_t *gc = w.gids[round & 1];
+    uint32_t *gn = w.gids[(round + 1) & 1];
+    if (round == 0) {
+        if (batch) LC_LAUNCH((k_nodes<true, true>), grid, w, nc, nn, gc, gn);
+        LC_LAUNCH((k_nodes<true, false>), grid, w, nc, nn, gc, gn);
+    }
+    if (batch) LC_LAUNCH((k_nodes<false, true>), grid, w, nc, nn, gc, gn);
+    LC_LAUNCH((k_nodes<false, false>), grid, w, nc, nn, gc, gn);
+}
+
+hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s) {
+    if (round == 0) LC_LAUNCH(k_map<true>, grid, w, (const uint32_t *)nullptr);
+    LC_LAUNCH(k_map<false>, grid, w, (const uint32_t *)w.names[round & 1]);
+}
+
+hipError_t launch_rename(const Work &w, int grid, hipStream_t s) { LC_LAUNCH(k_rename, grid, w); }
+
+hipError_t launch_round_end(const Work &w, int round, hipStream_t s) {
+    if (round == 0) {
+        hipLaunchKernelGGL(k_round_end<true>, dim3(1), dim3(1), 0, s, w);
+    } else {
+        hipLaunchKernelGGL(k_round_end<false>, dim3(1), dim3(1), 0, s, w);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,
+                          const uint32_t *voff, int grid, hipStream_t s) {
+    const uint32_t *names_cur = cur_round == 0 ? nullptr : w.names[cur_round & 1];
+    const int id = identity ? 1 : 0;
+    if (out64) {
+        if (batch) LC_LAUNCH((k_compose<true, true>), grid, w, id, names_cur, labels, voff);
+        LC_LAUNCH((k_compose<true, false>), grid, w, id, names_cur, labels, voff);
+    }
+    if (batch) LC_LAUNCH((k_compose<false, true>), grid, w, id, names_cur, labels, voff);
+    LC_LAUNCH((k_compose<false, false>), grid, w, id, names_cur, labels, voff);
+}
+
+hipError_t launch_flatten(const Work &w, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_flatten, dim3(grid), dim3(kThreads), 0, s, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_flatten_reset, dim3(1), dim3(1), 0, s, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch, const uint32_t *voff, int grid,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, w.m1, kInf, w.n0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (out64) {
+        if (batch) {
+            hipLaunchKernelGGL((k_canon_min<true, true>), dim3(grid), dim3(kThreads), 0, s, w, labels, voff);
+            LC_LAUNCH((k_canon_apply<true, true>), grid, w, labels, voff);
+        }
+        hipLaunchKernelGGL((k_canon_min<true, false>), dim3(grid), dim3(kThreads), 0, s, w, labels, voff);
+        LC_LAUNCH((k_canon_apply<true, false>), grid, w, labels, voff);
+    }
+    if (batch) {
+        hipLaunchKernelGGL((k_canon_min<false, true>), dim3(grid), dim3(kThreads), 0, s, w, labels, voff);
+        LC_LAUNCH((k_canon_apply<false, true>), grid, w, labels, voff);
+    }
+    hipLaunchKernelGGL((k_canon_min<false, false>), dim3(grid), dim3(kThreads), 0, s, w, labels, voff);
+    LC_LAUNCH((k_canon_apply<false, false>), grid, w, labels, voff);
+}
+
+hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, (uint32_t *)out, 0xFFFFFFFFu, w.n0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LC_LAUNCH(k_dump_parents, grid, w, last_round == 0 ? 1 : 0, (const uint32_t *)w.names[last_round & 1], out);
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, int grid, hipStream_t s) {
+    LC_LAUNCH(k_fill_u32, grid, p, v, n);
+}
+
+hipError_t launch_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, int round, hipStream_t s) {
+    int grid = (int)ceil_div(n_graphs, kThreads);
+    if (grid < 1) grid = 1;
+    LC_LAUNCH(k_batch_keys, grid, keys, seeds, n_graphs, round);
+}
+
+hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s) {
+    LC_LAUNCH(k_fill_gid, grid, gid0, voff, n_graphs);
+}
+
+}  // namespace lc

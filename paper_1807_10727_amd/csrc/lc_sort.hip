@@ -1,0 +1,374 @@
+// Scans, LSD radix sort and unique for the duplicate-dropping step of a round (the
+// contraction step keeps one copy of each edge between two different parents; proof of
+// the contraction-step lemma, Section 3).
+//
+// Sort: least-significant-digit radix sort of the round's survivor keys
+// (lo << b | hi, b = ceil(log2 N_r)), 8-bit digits, only as many passes as the key has
+// bits.  Each pass: per-tile digit counts (wave-aggregated LDS atomics), an exclusive scan
+// of the digit-major count table, then a scatter in which each 4096-key tile is ranked
+// stably in LDS (wave ballots find lanes with equal digits; per-wave digit counters give
+// the order across iterations and waves), staged in LDS in sorted order and written out
+// as contiguous runs per digit.
+// Unique: a head flag per sorted key, per-tile counts, one-workgroup scan, ordered write.
+// The unique write also marks both endpoints of every kept edge as nodes of the next graph.
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------------------
+// generic exclusive scan of uint8 or uint32 values into uint32 (count on the device)
+// ---------------------------------------------------------------------------------------
+
+template <typename T>
+__device__ inline void load16(const T *in, int64_t base, int64_t n, uint32_t (&v)[16]) {
+    if (base + 16 <= n) {
+        if (sizeof(T) == 1) {
+            uint4 x = *(const uint4 *)(in + base);
+            uint32_t wds[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 x = *(const uint4 *)(in + base + 4 * q);
+                v[4 * q + 0] = x.x;
+                v[4 * q + 1] = x.y;
+                v[4 * q + 2] = x.z;
+                v[4 * q + 3] = x.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = base + j < n ? (uint32_t)in[base + j] : 0u;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T *in, const u64c *n_ptr, uint32_t *partials) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t nblk = ceil_div(n, kScanTile);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t v[16];
+        load16(in, blk * kScanTile + threadIdx.x * 16, n, v);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sum += v[j];
+        uint32_t total;
+        block_excl_scan<kThreads>(sum, lds, &total);
+        if (threadIdx.x == 0) partials[blk] = total;
+    }
+}
+
+// One workgroup scans `cnt` values in place (cnt = *n_ptr, or ceil(*n_ptr / per_entry)).
+__global__ __launch_bounds__(kThreads) void k_scan_single(uint32_t *data, const u64c *n_ptr, int per_entry,
+                                                          u64c *total_out) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t cnt = per_entry ? ceil_div(n, per_entry) : n;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < cnt; base += kScanTile) {
+        uint32_t v[16];
+        const int64_t my = base + threadIdx.x * 16;
+        load16(data, my, cnt, v);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sum += v[j];
+        uint32_t total;
+        uint32_t run = carry + block_excl_scan<kThreads>(sum, lds, &total);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (my + j < cnt) data[my + j] = run;
+            run += v[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_down(const T *in, uint32_t *out, const u64c *n_ptr,
+                                                        const uint32_t *partials) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t nblk = ceil_div(n, kScanTile);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t v[16];
+        const int64_t my = blk * kScanTile + threadIdx.x * 16;
+        load16(in, my, n, v);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sum += v[j];
+        uint32_t total;
+        uint32_t run = partials[blk] + block_excl_scan<kThreads>(sum, lds, &total);
+        uint32_t o[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            o[j] = run;
+            run += v[j];
+        }
+        if (my + 16 <= n) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *(uint4 *)(out + my + 4 * q) = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (my + j < n) out[my + j] = o[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// radix sort passes
+// ---------------------------------------------------------------------------------------
+
+__device__ inline bool is_leader(uint64_t peers) { return (int)(__ffsll((long long)peers) - 1) == lane_id(); }
+
+__global__ __launch_bounds__(kThreads) void k_sort_hist(Work w, int pass) {
+    RoundState *st = w.st;
+    const int passes = npasses(st->nbits);
+    const int64_t S = (int64_t)st->s_count;
+    const int64_t ntiles = ceil_div(S, kSortTile);
+    if (pass >= passes) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = 0;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)kRadix * (u64c)ntiles;
+    const uint64_t *in = w.keys[sort_src(st->round, st->e_sel) ^ (pass & 1)];
+    const int shift = pass * kRadixBits;
+    __shared__ uint32_t hist[kRadix];
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+#pragma unroll 4
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kThreads + threadIdx.x;
+            const bool valid = idx < S;
+            const uint32_t d = valid ? (uint32_t)(in[idx] >> shift) & (kRadix - 1) : 0u;
+            const uint64_t peers = match_bits<kRadixBits>(d, ballot(valid));
+            if (valid && is_leader(peers)) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
+        }
+        __syncthreads();
+        w.counts[(int64_t)threadIdx.x * ntiles + tile] = hist[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
+    RoundState *st = w.st;
+    const int passes = npasses(st->nbits);
+    if (pass >= passes) return;
+    const int64_t S = (int64_t)st->s_count;
+    const int64_t ntiles = ceil_div(S, kSortTile);
+    const int src = sort_src(st->round, st->e_sel) ^ (pass & 1);
+    const uint64_t *in = w.keys[src];
+    uint64_t *out = w.keys[src ^ 1];
+    const int shift = pass * kRadixBits;
+
+    constexpr int kWaves = kThreads / kWave;
+    __shared__ uint32_t wcnt[kWaves][kRadix];
+    __shared__ uint64_t skeys[kSortTile];
+    __shared__ uint32_t dstart[kRadix];
+    __shared__ uint32_t gofs[kRadix];
+    __shared__ uint32_t lds[kWaves + 1];
+
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+
+        uint64_t k[kSortItems];
+        uint32_t rk[kSortItems];
+        const int64_t wbase = tile * kSortTile + (int64_t)wave * (kSortItems * kWave);
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = wbase + j * kWave + lane;
+            k[j] = idx < S ? in[idx] : ~0ull;   // padding sorts last within its tile
+        }
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
+            const uint64_t peers = match_bits<kRadixBits>(d, ~0ull);
+            const uint32_t cur = wcnt[wave][d];
+            rk[j] = cur + (uint32_t)__popcll(peers & lt);
+            __builtin_amdgcn_wave_barrier();
+            if (is_leader(peers)) wcnt[wave][d] = cur + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+
+        {   // per digit: prefix over waves, start within the tile, global offset
+            const int d = threadIdx.x;
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                const uint32_t c = wcnt[q][d];
+                wcnt[q][d] = run;
+                run += c;
+            }
+            uint32_t total;
+            dstart[d] = block_excl_scan<kThreads>(run, lds, &total);
+            gofs[d] = w.counts[(int64_t)d * ntiles + tile];
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
+            skeys[dstart[d] + wcnt[wave][d] + rk[j]] = k[j];
+        }
+        __syncthreads();
+
+        const int64_t valid = S - tile * kSortTile < kSortTile ? S - tile * kSortTile : kSortTile;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int pos = j * kThreads + threadIdx.x;
+            if (pos < valid) {
+                const uint64_t kk = skeys[pos];
+                const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+                out[gofs[d] + (uint32_t)pos - dstart[d]] = kk;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// unique
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_unique_count(Work w) {
+    RoundState *st = w.st;
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t S = (int64_t)st->s_count;
+    const int64_t ntiles = ceil_div(S, kSortTile);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;
+    const uint64_t *in = w.keys[sorted_sel(st->round, st->e_sel, st->nbits)];
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint32_t cnt = 0;
+#pragma unroll 4
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kThreads + threadIdx.x;
+            if (idx < S) cnt += (idx == 0 || in[idx] != in[idx - 1]) ? 1u : 0u;
+        }
+        uint32_t total;
+        block_excl_scan<kThreads>(cnt, lds, &total);
+        if (threadIdx.x == 0) w.tile_cnt[tile] = total;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_unique_write(Work w) {
+    RoundState *st = w.st;
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t S = (int64_t)st->s_count;
+    const int64_t ntiles = ceil_div(S, kSortTile);
+    const int t = sorted_sel(st->round, st->e_sel, st->nbits);
+    const uint64_t *in = w.keys[t];
+    uint64_t *out = w.keys[1 - t];
+    const int nb = st->nbits / 2;
+    const uint64_t mask = (1ull << nb) - 1ull;
+    const uint64_t n_cur = st->n_cur;
+    bool broken = false;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t my = tile * kSortTile + (int64_t)threadIdx.x * kSortItems;
+        uint64_t k[kSortItems];
+        if (my + kSortItems <= S) {
+#pragma unroll
+            for (int q = 0; q < kSortItems / 2; ++q) {
+                ulonglong2 x = *(const ulonglong2 *)(in + my + 2 * q);
+                k[2 * q] = x.x;
+                k[2 * q + 1] = x.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) k[j] = my + j < S ? in[my + j] : 0ull;
+        }
+        const uint64_t prev = (my > 0 && my < S) ? in[my - 1] : ~0ull;
+        uint32_t cnt = 0;
+        uint32_t heads = 0;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const bool h = my + j < S && (my + j == 0 || k[j] != (j ? k[j - 1] : prev));
+            heads |= (h ? 1u : 0u) << j;
+            cnt += h;
+        }
+        uint32_t total;
+        uint32_t off = w.tile_cnt[tile] + block_excl_scan<kThreads>(cnt, lds, &total);
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (heads >> j & 1u) {
+                out[off++] = k[j];
+                const uint64_t lo = k[j] >> nb, hi = k[j] & mask;
+                if (lo < n_cur && hi < n_cur) {
+                    w.has_edge[lo] = 1;
+                    w.has_edge[hi] = 1;
+                } else {
+                    broken = true;
+                }
+            }
+        }
+    }
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+
+hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total, int grid,
+                          hipStream_t s, int stage) {
+    if (stage == 0)
+        hipLaunchKernelGGL(k_scan_reduce<uint8_t>, dim3(grid), dim3(kThreads), 0, s, in, n, partials);
+    else if (stage == 1)
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, partials, n, kScanTile, total);
+    else
+        hipLaunchKernelGGL(k_scan_down<uint8_t>, dim3(grid), dim3(kThreads), 0, s, in, out, n,
+                           (const uint32_t *)partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid, hipStream_t s,
+                           int stage) {
+    if (stage == 0)
+        hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3(grid), dim3(kThreads), 0, s, (const uint32_t *)data, n,
+                           partials);
+    else if (stage == 1)
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, partials, n, kScanTile, total);
+    else
+        hipLaunchKernelGGL(k_scan_down<uint32_t>, dim3(grid), dim3(kThreads), 0, s, (const uint32_t *)data, data, n,
+                           (const uint32_t *)partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage) {
+    switch (stage) {
+        case 0:
+            hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kThreads), 0, s, w, pass);
+            return hipGetLastError();
+        case 1:
+        case 2:
+        case 3:
+            return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 1);
+        default:
+            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kThreads), 0, s, w, pass);
+            return hipGetLastError();
+    }
+}
+
+hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage) {
+    if (stage == 0)
+        hipLaunchKernelGGL(k_unique_count, dim3(grid), dim3(kThreads), 0, s, w);
+    else if (stage == 1)
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.tile_cnt, &w.st->aux_n, 0,
+                           &w.st->m_next);
+    else
+        hipLaunchKernelGGL(k_unique_write, dim3(grid), dim3(kThreads), 0, s, w);
+    return hipGetLastError();
+}
+
+}  // namespace lc

@@ -1,0 +1,119 @@
+"""The C ABI library without a GPU: it loads, exports what include/cc.h declares, validates
+arguments, sizes workspaces, and stays independent of the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cc.h")
+PKG = os.path.join(ROOT, "paper_1807_10727_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(cc_[a-z0-9_]+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("cc_create", "cc_workspace_size", "cc_set_workspace", "cc_contract_round", "cc_run",
+                 "cc_labels", "cc_round_parents", "cc_destroy", "cc_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1807_10727_amd import _cc
+    lib = ctypes.CDLL(_cc.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    nm = subprocess.run(["nm", "-D", "--defined-only", _cc.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = set(re.findall(r"\bT (cc_[a-z0-9_]+)", nm))
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_names_match_the_abi():
+    import paper_1807_10727_amd._cc as b
+    for n in declared_functions():
+        if n in ("cc_kernel_family_count", "cc_kernel_family_name"):
+            continue
+        assert hasattr(b, n), n
+
+
+def test_product_never_touches_the_oracle():
+    # the library links no oracle symbol and no package source imports the oracle
+    from paper_1807_10727_amd import _cc
+    nm = subprocess.run(["nm", "-D", _cc.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    assert "lco_" not in nm
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+                assert "lc_oracle" not in src, f
+
+
+def test_create_validates_arguments():
+    from paper_1807_10727_amd import _cc
+    bad = [
+        dict(n_vertices=-1, n_edges=1, layout=0),
+        dict(n_vertices=1 << 31, n_edges=1, layout=0),
+        dict(n_vertices=10, n_edges=-1, layout=0),
+        dict(n_vertices=10, n_edges=1 << 32, layout=0),
+        dict(n_vertices=10, n_edges=1, layout=3),
+    ]
+    for kw in bad:
+        with pytest.raises(_cc.CCError) as e:
+            _cc.cc_create(kw["n_vertices"], kw["n_edges"], kw["layout"], 0x1000, 0x2000)
+        assert e.value.status == _cc.CC_E_ARG
+    with pytest.raises(_cc.CCError):
+        _cc.cc_create(10, 5, _cc.CC_EDGES_SOA_I32, 0x1000, 0)     # dst missing
+    with pytest.raises(_cc.CCError):
+        _cc.cc_create(10, 5, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, max_rounds=-2)
+    ctx = _cc.cc_create(10, 5, _cc.CC_EDGES_PACKED_U64, 0x1000, 0)   # packed: dst unused
+    _cc.cc_destroy(ctx)
+    ctx = _cc.cc_create(10, 0, _cc.CC_EDGES_SOA_I32, 0, 0)           # no records: no pointers needed
+    _cc.cc_destroy(ctx)
+
+
+def test_workspace_size_and_state_errors():
+    from paper_1807_10727_amd import _cc
+    sizes = {}
+    for n, m in ((1, 0), (1000, 5000), (1 << 20, 1 << 22)):
+        ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000)
+        sizes[(n, m)] = _cc.cc_workspace_size(ctx)
+        if n == 1000:
+            with pytest.raises(_cc.CCError) as e:
+                _cc.cc_set_workspace(ctx, 0x100000, 16)
+            assert e.value.status == _cc.CC_E_NOMEM
+            with pytest.raises(_cc.CCError) as e:
+                _cc.cc_set_workspace(ctx, 0x100001, 1 << 30)
+            assert e.value.status == _cc.CC_E_ARG
+            with pytest.raises(_cc.CCError) as e:
+                _cc.cc_contract_round(ctx)
+            assert e.value.status == _cc.CC_E_NOMEM
+        _cc.cc_destroy(ctx)
+    big = sizes[(1 << 20, 1 << 22)]
+    # state arrays (about 38 bytes per id) and two key buffers of 8 bytes per record dominate
+    assert 16 * (1 << 22) + 36 * (1 << 20) < big < 18 * (1 << 22) + 80 * (1 << 20)
+    assert sizes[(1, 0)] < sizes[(1000, 5000)] < big
+
+
+def test_labels_before_run_is_a_state_error():
+    from paper_1807_10727_amd import _cc
+    ctx = _cc.cc_create(10, 5, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000)
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_labels(ctx, 0x3000)
+    assert e.value.status == _cc.CC_E_STATE
+    _cc.cc_destroy(ctx)
+
+
+def test_kernel_families_listed():
+    from paper_1807_10727_amd import _cc
+    names = _cc.cc_kernel_family_names()
+    for want in ("min1", "min2", "parent", "relabel", "sort_scatter", "unique", "compose"):
+        assert want in names

@@ -1,0 +1,210 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact on integers: per-round parents by name, per-round statistics, round count and
+final labels, on seeded synthetic graphs that span several sort tiles with ragged tails,
+all input layouts, and the degenerate cases of the method.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from lcref import all_graph_adjacency, graph_records
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1807_10727_amd as lc
+    return lc
+
+
+DEV = "cuda:0"
+
+
+def to_device(g, layout="soa32", offset=0):
+    """Edge tensors of graph `g` in the given layout; `offset` > 0 misaligns the pointers."""
+    if layout == "soa32":
+        s = torch.from_numpy(np.concatenate([np.zeros(offset, np.uint32), g.src]).view(np.int32)).to(DEV)
+        d = torch.from_numpy(np.concatenate([np.zeros(offset, np.uint32), g.dst]).view(np.int32)).to(DEV)
+        return s[offset:], d[offset:], None
+    if layout == "soa64":
+        s = torch.from_numpy(np.concatenate([np.zeros(offset, np.int64), g.src.astype(np.int64)])).to(DEV)
+        d = torch.from_numpy(np.concatenate([np.zeros(offset, np.int64), g.dst.astype(np.int64)])).to(DEV)
+        return s[offset:], d[offset:], None
+    k = graphgen.pack(g.src, g.dst).view(np.int64)
+    k = torch.from_numpy(np.concatenate([np.zeros(offset, np.int64), k])).to(DEV)
+    return k[offset:], None, 2
+
+
+def gpu_solve(lc, g, seed, layout="soa32", per_round=True, flags=0, max_rounds=0, offset=0):
+    s_t, d_t, lay = to_device(g, layout, offset)
+    out = {"parents": [], "stats": []}
+    with lc.Solver(g.n, s_t, d_t, seed=seed, flags=flags, max_rounds=max_rounds, layout=lay) as s:
+        if per_round:
+            while max_rounds == 0 or len(out["stats"]) < max_rounds:
+                st, stats = s.contract_round()
+                if st == lc.CC_DONE:
+                    break
+                out["stats"].append(stats)
+                par, k = s.parents()
+                out["parents"].append(par.cpu().numpy().view(np.uint32).copy())
+                assert k == stats[1]
+            # finish via cc_run (no rounds left, or stops at max_rounds)
+            out["rounds"] = s.run()
+        else:
+            out["rounds"] = s.run()
+            out["stats"] = s.stats(out["rounds"])
+        lab = s.labels()
+        torch.cuda.synchronize()
+        out["labels"] = lab.cpu().numpy()
+    return out
+
+
+def check(lc, g, seed, **kw):
+    max_rounds = kw.get("max_rounds", 0)
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, record_parents=True, max_rounds=max_rounds)
+    got = gpu_solve(lc, g, seed, **kw)
+    assert got["rounds"] == want.rounds
+    assert [tuple(x) for x in got["stats"]] == [tuple(x) for x in want.stats]
+    if kw.get("per_round", True):
+        assert len(got["parents"]) == want.rounds
+        for r in range(want.rounds):
+            np.testing.assert_array_equal(got["parents"][r], want.parents[r], err_msg="round %d" % r)
+    lab = got["labels"]
+    np.testing.assert_array_equal(lab.astype(np.int64), want.labels.astype(np.int64))
+    return want
+
+
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,m,seed", [(100, 300, 1), (1000, 4097, 2), (5000, 20001, 3), (3000, 2000, 4),
+                                      (20000, 61441, 5)])
+def test_gnm_parity(lc, n, m, seed):
+    g = graphgen.Graph(n, *graphgen.gnm(seed * 7919, n, m))
+    check(lc, g, seed)
+
+
+def test_small_workload_parity(lc):
+    """G(n, m) with n = 65,536 and m = 262,144, every round and the labels bit-exact."""
+    g = graphgen.workload_small()
+    w = check(lc, g, seed=0xC0FFEE00)
+    assert w.rounds >= 2
+
+
+@pytest.mark.parametrize("scale,ef", [(10, 8), (13, 16)])
+def test_rmat_parity(lc, scale, ef):
+    g = graphgen.Graph(1 << scale, *graphgen.rmat(scale * 31, scale, ef << scale))
+    check(lc, g, seed=scale)
+
+
+def test_paths_parity_many_rounds(lc):
+    g = graphgen.er_with_paths(17, 1 << 11, 1 << 12, 30, 700)
+    w = check(lc, g, seed=99)
+    assert w.rounds >= 5
+
+
+@pytest.mark.parametrize("layout", ["soa32", "soa64", "packed"])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_layouts_and_alignment(lc, layout, offset):
+    g = graphgen.Graph(3001, *graphgen.gnm(44, 3001, 9003))
+    check(lc, g, seed=5, layout=layout, offset=offset, per_round=False)
+
+
+def test_union_of_all_graphs_on_five_vertices(lc):
+    adj = all_graph_adjacency(5)
+    src, dst, eoff = graph_records(adj)
+    G = adj.shape[0]
+    gid = np.repeat(np.arange(G), np.diff(eoff))
+    g = graphgen.Graph(5 * G, (src + 5 * gid).astype(np.uint32), (dst + 5 * gid).astype(np.uint32))
+    check(lc, g, seed=12345)
+
+
+@pytest.mark.parametrize("case", ["empty", "no_edges", "loops_only", "single_edge", "duplicates", "isolated",
+                                  "one_vertex"])
+def test_degenerate_cases(lc, case):
+    if case == "empty":
+        g = graphgen.Graph(0, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    elif case == "no_edges":
+        g = graphgen.Graph(17, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    elif case == "loops_only":
+        g = graphgen.Graph(9, np.array([3, 3, 8], np.uint32), np.array([3, 3, 8], np.uint32))
+    elif case == "single_edge":
+        g = graphgen.Graph(2, np.array([1], np.uint32), np.array([0], np.uint32))
+    elif case == "duplicates":
+        g = graphgen.Graph(6, np.array([0, 1, 1, 0, 2, 4, 5, 4], np.uint32), np.array([1, 0, 0, 1, 2, 5, 4, 5], np.uint32))
+    elif case == "isolated":
+        g = graphgen.Graph(1000, np.array([10, 500], np.uint32), np.array([999, 10], np.uint32))
+    else:
+        g = graphgen.Graph(1, np.zeros(3, np.uint32), np.zeros(3, np.uint32))
+    check(lc, g, seed=3)
+
+
+def test_max_rounds_partial_labels(lc):
+    g = graphgen.er_with_paths(5, 0, 0, 20, 400)
+    for k in (1, 2, 3):
+        check(lc, g, seed=8, max_rounds=k)
+
+
+def test_canonical_labels(lc):
+    g = graphgen.workload_small(seed=77)
+    s_t, d_t, _ = to_device(g)
+    lab, rounds, _ = lc.solve(g.n, s_t, d_t, seed=4, flags=lc.CC_CANONICAL)
+    np.testing.assert_array_equal(lab.cpu().numpy().astype(np.uint32), oracle.components_min_id(g.n, g.src, g.dst))
+
+
+def test_invalid_ids_rejected(lc):
+    g = graphgen.Graph(100, np.array([1, 2, 100], np.uint32), np.array([2, 3, 4], np.uint32))
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=1) as s:
+        with pytest.raises(lc.CCError) as e:
+            s.run()
+        assert e.value.status == -2
+    neg = torch.tensor([-1, 2], dtype=torch.int32, device=DEV)
+    ok = torch.tensor([2, 3], dtype=torch.int32, device=DEV)
+    with lc.Solver(10, neg, ok, seed=1) as s:
+        with pytest.raises(lc.CCError):
+            s.run()
+
+
+def test_reset_repeat_and_reseed(lc):
+    g = graphgen.Graph(4000, *graphgen.gnm(2, 4000, 12000))
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=1) as s:
+        s.run()
+        a = s.labels().cpu().numpy().copy()
+        s.reset(1)
+        s.run()
+        b = s.labels().cpu().numpy().copy()
+        s.reset(2)
+        r2 = s.run()
+        c = s.labels().cpu().numpy().copy()
+    np.testing.assert_array_equal(a, b)
+    want = oracle.run(g.n, g.src, g.dst, seed=2)
+    assert r2 == want.rounds
+    np.testing.assert_array_equal(c.astype(np.uint32), want.labels)
+
+
+def test_edge_order_does_not_matter(lc):
+    g = graphgen.Graph(5000, *graphgen.gnm(9, 5000, 15000))
+    perm = np.random.default_rng(0).permutation(g.m)
+    h = graphgen.Graph(g.n, g.dst[perm].copy(), g.src[perm].copy())
+    a = gpu_solve(lc, g, 3, per_round=False)
+    b = gpu_solve(lc, h, 3, per_round=False)
+    np.testing.assert_array_equal(a["labels"], b["labels"])
+    assert a["stats"] == b["stats"]
+
+
+def test_profile_times_kernels(lc):
+    g = graphgen.workload_small()
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE) as s:
+        r = s.run()
+        t = s.kernel_times()
+    assert t["min1"][1] == r + (0 if r else 1) or t["min1"][1] >= r
+    assert t["min1"][0] > 0 and t["sort_scatter"][0] > 0
