@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Throughput of LocalContraction connected components on one MI355X.
+
+A step is one full solve -- every round until no edge is left, then the label of every
+vertex -- of the G(n, m) graph with n = 2^24, m = 2^27 (int32 ids, endpoints uniform,
+duplicates and self-loops kept) plus 10,000 disjoint random paths of 1,000 vertices,
+with the edge list already resident in HBM.  Each step draws fresh priorities (seed
+base + step index).  The value is input edges per second.
+
+Printed (stdout, one JSON line): the metric, the roofline of the dominant kernel family
+(algorithmic bytes per launch over its HIP-event launch time, against 8 TB/s), and the
+CPU oracle timed on a bounded sample of the same mix.  Diagnostics go to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ceil_log2(n):
+    b = 0
+    while (1 << b) < n:
+        b += 1
+    return b
+
+
+def family_bytes(stats, n0):
+    """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
+
+    Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
+    M' = distinct edges out, P = radix passes.  Random-access amplification (cache-line
+    reads for 4-byte gathers and atomics, extra sort passes) is implementation overhead
+    and deliberately not counted."""
+    fam = {}
+
+    def add(k, v):
+        fam[k] = fam.get(k, 0) + v
+
+    for (r, n_active, m_in, s, m_out, _fin) in stats:
+        N = n0 if r == 0 else n_active
+        M = m_in
+        P = (2 * ceil_log2(max(N, 2)) + 7) // 8
+        add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
+        add("min1", 8 * M + 4 * N)                 # records in, m1 out once
+        add("min2", 8 * M + 8 * N)                 # records in, m1 in once, lv out once
+        add("parent", 8 * N)                       # lv in, parent out
+        add("relabel", 8 * M + 4 * N + 8 * s)      # records in, parents in once, survivor keys out
+        add("sort_hist", 8 * s * P)                # keys in per pass
+        add("sort_scatter", 16 * s * P)            # keys in and out per pass
+        add("unique", 16 * s + 8 * m_out)          # sorted keys read twice, unique keys out
+        add("node_scan", 6 * N)                    # flags in (twice), index out
+        add("nodes", 9 * N)
+        add("map", 9 * N)
+        add("rename", 16 * m_out + 4 * N)
+    add("compose", 8 * n0)
+    return fam
+
+
+def job_alg_bytes(stats, n0):
+    """The job's algorithmic bytes: three streaming reads of the records, the survivors
+    written and read once, the unique edges written, 24 bytes of node state per node and
+    round, and the labels."""
+    b = 4 * n0
+    for (r, n_active, m_in, s, m_out, _fin) in stats:
+        N = n0 if r == 0 else n_active
+        b += 24 * m_in + 16 * s + 8 * m_out + 24 * N
+    return b
+
+
+def cpu_baseline(shrink):
+    import graphgen
+    import oracle
+    g = graphgen.workload_er_paths(shrink=shrink)
+    t0 = time.perf_counter()
+    res = oracle.run(g.n, g.src, g.dst, seed=graphgen.CONFIG_SEED_BASE)
+    dt = time.perf_counter() - t0
+    return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "same G(n,m)+paths mix scaled by 1/%d: n=%d, m=%d records, %d rounds, %.1f s single-threaded"
+                      % (shrink, g.n, g.m, res.rounds, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="er_paths", choices=["er_paths", "small", "rmat26", "rmat24"])
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-shrink", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1807_10727_amd as lc
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    if args.workload == "er_paths":
+        g = graphgen.workload_er_paths()
+        wname = "G(n=2^24, m=2^27) + 10,000 paths x 1,000 vertices, int32 ids"
+    elif args.workload == "small":
+        g = graphgen.workload_small()
+        wname = "G(n=65,536, m=262,144), int32 ids"
+    else:
+        scale = 26 if args.workload == "rmat26" else 24
+        g = graphgen.workload_rmat(scale=scale)
+        wname = "R-MAT scale %d, edge factor 16, (0.57,0.19,0.19,0.05) +-10%%, permuted ids" % scale
+    log("generated %s: n=%d m=%d in %.1fs" % (wname, g.n, g.m, time.perf_counter() - t0))
+
+    if args.workload.startswith("rmat"):
+        keys = graphgen.pack(g.src, g.dst).view(np.int64)
+        src = torch.from_numpy(keys).to(dev)
+        dst = None
+        layout = lc.CC_EDGES_PACKED_U64
+    else:
+        src = torch.from_numpy(g.src.view(np.int32)).to(dev)
+        dst = torch.from_numpy(g.dst.view(np.int32)).to(dev)
+        layout = lc.CC_EDGES_SOA_I32
+    del g.src, g.dst
+    n0, m0 = g.n, int(src.shape[0])
+    torch.cuda.synchronize()
+
+    flags = 0 if args.no_profile else lc.CC_PROFILE
+    stream = torch.cuda.current_stream(dev)
+    base_seed = graphgen.CONFIG_SEED_BASE + 1
+    labels = torch.empty(n0, dtype=torch.int32, device=dev)
+    solver = lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout)
+    log("workspace %.2f GiB" % (solver.ws_bytes / 2**30))
+
+    def step(i):
+        solver.reset(base_seed + i)
+        r = solver.run()
+        solver.labels(labels)
+        return r
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    torch.cuda.synchronize()
+    solver.reset(base_seed)            # clears the per-kernel timers too
+    all_stats = []
+    rounds = []
+    fam_ms = {}
+    fam_n = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step(i)
+        rounds.append(r)
+        all_stats.append(solver.stats(r))
+        for k, (ms, n) in solver.kernel_times().items():   # per solve (reset clears them)
+            fam_ms[k] = fam_ms.get(k, 0.0) + ms
+            fam_n[k] = fam_n.get(k, 0) + n
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = m0 * args.steps / dt
+    log("rounds per step: %s" % rounds)
+    for st in all_stats[0]:
+        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st)
+
+    # algorithmic bytes per family over the timed steps
+    fam_bytes = {}
+    for st in all_stats:
+        for k, v in family_bytes(st, n0).items():
+            fam_bytes[k] = fam_bytes.get(k, 0) + v
+    job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
+
+    roofline = None
+    if not args.no_profile and fam_ms:
+        log("kernel family       ms/step  launches/step  GB/s(alg)")
+        for k in sorted(fam_ms, key=lambda x: -fam_ms[x]):
+            if fam_n[k] == 0:
+                continue
+            gbs = fam_bytes.get(k, 0) / (fam_ms[k] * 1e-3) / 1e9 if fam_ms[k] > 0 else 0.0
+            log("  %-16s %8.3f %10.1f %10.1f" % (k, fam_ms[k] / args.steps, fam_n[k] / args.steps, gbs))
+        dom = max((k for k in fam_ms if k in fam_bytes), key=lambda k: fam_ms[k])
+        avg_launch_s = fam_ms[dom] * 1e-3 / fam_n[dom]
+        bytes_per_launch = fam_bytes[dom] / fam_n[dom]
+        achieved = bytes_per_launch / avg_launch_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+        kernel_ms = sum(fam_ms.values()) / args.steps
+        log("sum of kernel time per step %.3f ms of %.3f ms wall" % (kernel_ms, ms_per_step))
+
+    job_gbs = job_bytes / dt / 1e9
+    log("job algorithmic bytes per step %.2f GB -> %.1f GB/s (%.1f%% of 8 TB/s)"
+        % (job_bytes / args.steps / 1e9, job_gbs, 100 * job_gbs / HBM_PEAK_GBS))
+
+    cpu = None
+    if not args.no_cpu:
+        try:
+            cpu = cpu_baseline(args.cpu_shrink if args.workload == "er_paths" else 8)
+        except Exception as e:  # the GPU figure stands on its own
+            log("cpu baseline failed: %r" % (e,))
+
+    out = {
+        "metric": "input edges/sec to full CC labels (1 GPU)",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": wname, "n_vertices": n0, "n_records": m0, "rounds": rounds[0],
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

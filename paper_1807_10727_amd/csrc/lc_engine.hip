@@ -29,7 +29,8 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
     const size_t n = (size_t)std::max<int64_t>(n0, 1);
     const size_t m = (size_t)std::max<int64_t>(m0, 2);
-    const size_t tiles = (size_t)ceil_div((int64_t)m, kSortTile);
+    const size_t tiles = (size_t)ceil_div((int64_t)m, kSortTile) + 2;
+    const size_t slabs = (size_t)ceil_div((int64_t)m, kSlab) + 1;
     const size_t parts = std::max<size_t>((size_t)ceil_div((int64_t)n, kScanTile),
                                           (size_t)ceil_div((int64_t)(kRadix * tiles), kScanTile)) + 16;
     size_t off = 0;
@@ -40,8 +41,7 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
     };
     Work t{};
     t.st = (RoundState *)take(sizeof(RoundState));
-    t.m1 = (uint32_t *)take(4 * n);
-    t.lv = (uint32_t *)take(4 * n);
+    t.ml = (uint32_t *)take(8 * n);
     t.par = (uint32_t *)take(4 * n);
     t.has_edge = (uint8_t *)take(n + 16);
     t.is_label = (uint8_t *)take(n + 16);
@@ -60,6 +60,7 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
     t.keys[1] = (uint64_t *)take(8 * m);
     t.counts = (uint32_t *)take(4 * kRadix * tiles);
     t.tile_cnt = (uint32_t *)take(4 * tiles + 64);
+    t.slab_cnt = (uint32_t *)take(4 * slabs + 64);
     t.partials = (uint32_t *)take(4 * parts);
     t.n0 = n0;
     t.m0 = m0;
@@ -135,14 +136,15 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc) {
     const int gscan_n = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), kScanTile), grid_cap);
     const int nbits = 2 * ceil_log2_host(std::max<int64_t>(N, 2));
     const int passes = npasses(nbits);
-    const int64_t scan_entries = (int64_t)kRadix * ceil_div(std::max<int64_t>(M, 1), kSortTile);
+    const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(M, 1), kSortTile) + 2);
+    const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 
     RUN(kRoundBegin, launch_round_begin(w, gn, stream));
     RUN(kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
     RUN(kMin2, launch_min2(w, src, gm, stream));
     RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
-    RUN(kRelabel, launch_relabel(w, src, gm, stream));
+    RUN(kRelabel, launch_relabel(w, src, gslab, stream));
     for (int p = 0; p < passes; ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
         RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 1));

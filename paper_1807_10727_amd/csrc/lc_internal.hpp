@@ -14,26 +14,32 @@ constexpr int kMaxLevels = 64;    // per-round maps kept before they are folded 
 
 // Device-resident state of the current round.  Every kernel reads its element counts
 // from here, so a sequence of rounds can be enqueued (or captured in a graph) without
-// host round trips; the eager driver reads it back once per round.
+// host round trips; the eager driver reads it back once per round.  Fields that kernels
+// update with atomics sit on cache lines of their own, away from the fields every
+// thread reads.
 struct RoundState {
+    // written only between rounds (single-thread kernels) or by one thread of a kernel
     u64c n_cur;        // N_r: nodes of this round (round 0: the whole id space n0)
     u64c m_cur;        // M_r: records of this round
-    u64c n_active;     // nodes with a loop-free edge
-    u64c s_count;      // records surviving relabelling (repeats counted)
-    u64c m_next;       // distinct edges of the next graph
-    u64c n_next;       // nodes of the next graph
-    u64c n_final;      // parents of this round that keep no edge
     u64c n_prev;       // N of the round that just ended
     u64c aux_n;        // element count handed from one kernel to the next (scans)
     u64c map_off;      // next free entry of the map arena
     u64c map_cap;      // entries of the map arena
-    uint32_t err;      // bit 0: input id out of range; bit 1: map arena overflow
+    u64c n_slabs;      // relabel output slabs of this round
     int32_t round;     // r
     int32_t nbits;     // key bits of this round's sort: 2 * ceil(log2 N_r)
     int32_t e_sel;     // key buffer that holds E_r (rounds >= 1)
     int32_t done;      // no edge left
     int32_t levels;    // per-round maps in the arena
-    u64c level_off[kMaxLevels];
+    int32_t pad0_;
+    alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
+    alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
+    alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
+    alignas(128) uint32_t err;    // bit 0: input id out of range; bit 1: map arena overflow;
+                                  // bit 2: internal consistency (atomics)
+    alignas(128) u64c m_next;     // distinct edges of the next graph (one workgroup)
+    u64c n_next;                  // nodes of the next graph (one workgroup)
+    alignas(128) u64c level_off[kMaxLevels];
 };
 
 enum Layout { kSoa32 = 0, kSoa64 = 1, kPacked = 2 };
@@ -60,8 +66,7 @@ struct PrioCtx {
 // Workspace arrays of one solve (device pointers).
 struct Work {
     RoundState *st;
-    uint32_t *m1;        // [n0] one-hop minima
-    uint32_t *lv;        // [n0] two-hop minima
+    uint32_t *ml;        // [2 n0] node word: ml[2x] one-hop minimum, ml[2x+1] two-hop minimum
     uint32_t *par;       // [n0] parent of each node (compact index of this round)
     uint8_t *has_edge;   // [n0] node of this round is a node of the next graph
     uint8_t *is_label;   // [n0] node of this round is somebody's parent
@@ -76,6 +81,7 @@ struct Work {
     uint32_t *counts;    // [kRadix * sort tiles] digit counts of one sort pass
     uint32_t *partials;  // scan partial sums
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
+    uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
     int64_t n0, m0;
 };
 
@@ -87,6 +93,7 @@ constexpr int kScanTile = kThreads * kScanItems;   // elements per block of the 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
+constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

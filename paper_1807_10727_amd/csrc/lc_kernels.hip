@@ -36,8 +36,10 @@ struct ReadSoa32 {
     uint32_t n;
     __host__ explicit ReadSoa32(const EdgeIn &e)
         : s((const int32_t *)e.s), d((const int32_t *)e.d), m(e.m), n(e.n) {}
-    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
-    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
         const int64_t base = c * V;
         int32_t sa[V], sb[V];
         if (V == 4 && base + 4 <= m) {
@@ -70,8 +72,10 @@ struct ReadSoa64 {
     uint32_t n;
     __host__ explicit ReadSoa64(const EdgeIn &e)
         : s((const int64_t *)e.s), d((const int64_t *)e.d), m(e.m), n(e.n) {}
-    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
-    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
         const int64_t base = c * V;
         int64_t sa[V], sb[V];
         if (V == 2 && base + 2 <= m) {
@@ -103,8 +107,10 @@ struct ReadPacked {
     int64_t m;
     uint32_t n;
     __host__ explicit ReadPacked(const EdgeIn &e) : k((const uint64_t *)e.s), m(e.m), n(e.n) {}
-    __device__ int64_t chunks(const RoundState *) const { return (m + V - 1) / V; }
-    __device__ void read(const RoundState *, int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
         const int64_t base = c * V;
         uint64_t r[V];
         if (V == 2 && base + 2 <= m) {
@@ -130,11 +136,16 @@ struct ReadPacked {
 struct ReadInternal {
     static constexpr int kV = 2;
     uint64_t *k0, *k1;
-    __host__ explicit ReadInternal(const Work &w) : k0(w.keys[0]), k1(w.keys[1]) {}
-    __device__ int64_t chunks(const RoundState *st) const { return (int64_t)((st->m_cur + 1) / 2); }
-    __device__ void read(const RoundState *st, int64_t c, uint32_t *a, uint32_t *b, bool &) const {
-        const uint64_t *k = st->e_sel ? k1 : k0;
-        const int64_t m = (int64_t)st->m_cur;
+    const uint64_t *k;
+    int64_t m;
+    __host__ explicit ReadInternal(const Work &w) : k0(w.keys[0]), k1(w.keys[1]), k(nullptr), m(0) {}
+    __device__ void init(const RoundState *st) {
+        k = st->e_sel ? k1 : k0;
+        m = (int64_t)st->m_cur;
+    }
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + 1) / 2; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &) const {
         const int64_t base = c * 2;
         uint64_t r0, r1;
         if (base + 2 <= m) {
@@ -173,14 +184,14 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->n_active = 0;
         st->s_count = 0;
+        st->n_slabs = 0;
         st->m_next = 0;
         st->n_next = 0;
         st->n_final = 0;
         st->nbits = 2 * ceil_log2(n < 2 ? 2 : (uint64_t)n);
     }
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        w.m1[i] = kInf;
-        w.lv[i] = kInf;
+        ((uint64_t *)w.ml)[i] = ~0ull;
         w.has_edge[i] = 0;
         w.is_label[i] = 0;
     }
@@ -190,26 +201,28 @@ template <class R, bool kFirst, bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, const uint32_t *names,
                                                    const uint32_t *gids) {
     constexpr int V = R::kV;
-    const int64_t nch = rd.chunks(w.st);
+    rd.init(w.st);
+    const int64_t nch = rd.chunks();
+    uint32_t *m1 = w.ml;   // one-hop minimum of node x at m1[2x]
     bool bad = false;
     for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
         uint32_t a[V], b[V], v[V], ca[V], cb[V];
-        rd.read(w.st, c, a, b, bad);
+        rd.read(c, a, b, bad);
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             if (a[j] != b[j]) {
                 uint32_t pa = node_prio<kFirst, kBatch>(pc, w, names, gids, a[j]);
                 uint32_t pb = node_prio<kFirst, kBatch>(pc, w, names, gids, b[j]);
                 v[j] = min(pa, pb);
-                ca[j] = w.m1[a[j]];
-                cb[j] = w.m1[b[j]];
+                ca[j] = m1[2 * (size_t)a[j]];
+                cb[j] = m1[2 * (size_t)b[j]];
             }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             if (a[j] != b[j]) {
-                if (ca[j] > v[j]) atomicMin(&w.m1[a[j]], v[j]);
-                if (cb[j] > v[j]) atomicMin(&w.m1[b[j]], v[j]);
+                if (ca[j] > v[j]) atomicMin(&m1[2 * (size_t)a[j]], v[j]);
+                if (cb[j] > v[j]) atomicMin(&m1[2 * (size_t)b[j]], v[j]);
             }
         }
     }
@@ -219,24 +232,28 @@ __global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, con
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
     constexpr int V = R::kV;
-    const int64_t nch = rd.chunks(w.st);
+    rd.init(w.st);
+    const int64_t nch = rd.chunks();
+    const uint64_t *word = (const uint64_t *)w.ml;   // low half: one-hop min, high half: two-hop min
+    uint32_t *ml = w.ml;
     bool bad = false;
     for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
-        uint32_t a[V], b[V], v[V], ca[V], cb[V];
-        rd.read(w.st, c, a, b, bad);
+        uint32_t a[V], b[V];
+        uint64_t wa[V], wb[V];
+        rd.read(c, a, b, bad);
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             if (a[j] != b[j]) {
-                v[j] = min(w.m1[a[j]], w.m1[b[j]]);
-                ca[j] = w.lv[a[j]];
-                cb[j] = w.lv[b[j]];
+                wa[j] = word[a[j]];
+                wb[j] = word[b[j]];
             }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             if (a[j] != b[j]) {
-                if (ca[j] > v[j]) atomicMin(&w.lv[a[j]], v[j]);
-                if (cb[j] > v[j]) atomicMin(&w.lv[b[j]], v[j]);
+                const uint32_t v = min((uint32_t)wa[j], (uint32_t)wb[j]);
+                if ((uint32_t)(wa[j] >> 32) > v) atomicMin(&ml[2 * (size_t)a[j] + 1], v);
+                if ((uint32_t)(wb[j] >> 32) > v) atomicMin(&ml[2 * (size_t)b[j] + 1], v);
             }
         }
     }
@@ -249,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
     uint32_t active = 0;
     bool broken = false;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t l = w.lv[i];
+        const uint32_t l = w.ml[2 * i + 1];
         if (l == kInf) {  // no loop-free record touches this id (round 0 only)
             w.par[i] = (uint32_t)i;
             continue;
@@ -280,53 +297,64 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
     if (broken) atomicOr(&st->err, 4u);
 }
 
+// Relabel every record through the parents and keep the loop-free ones as sort keys
+// (lo << b | hi).  Each workgroup owns a slab of kSlab consecutive records and writes its
+// survivors, in order, to the start of the same slab of the output: no global counter is
+// involved.  slab_cnt holds the survivors per slab; the first radix pass reads the slabs.
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     constexpr int V = R::kV;
+    constexpr int64_t kChunksPerSlab = kSlab / V;
     RoundState *st = w.st;
     __shared__ uint32_t lds[kThreads / kWave + 1];
-    __shared__ u64c base_sh;
-    const int64_t nch = rd.chunks(st);
+    rd.init(st);
+    const int64_t nch = rd.chunks();
+    const int64_t nslabs = ceil_div(rd.records(), kSlab);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_slabs = (u64c)nslabs;
     uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
     const int nb = st->nbits / 2;
     bool bad = false;
-    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
-        const int64_t c = cb + threadIdx.x;
-        uint64_t key[V];
-        bool keep[V];
-        uint32_t cnt = 0;
-        if (c < nch) {
-            uint32_t a[V], b[V], pa[V], pb[V];
-            rd.read(st, c, a, b, bad);
+    for (int64_t slab = blockIdx.x; slab < nslabs; slab += gridDim.x) {
+        const int64_t c_end = min(nch, (slab + 1) * kChunksPerSlab);
+        uint64_t *dst = out + slab * kSlab;
+        uint32_t cursor = 0;
+        for (int64_t cb = slab * kChunksPerSlab; cb < c_end; cb += kThreads) {
+            const int64_t c = cb + threadIdx.x;
+            uint64_t key[V];
+            bool keep[V];
+            uint32_t cnt = 0;
+            if (c < c_end) {
+                uint32_t a[V], b[V], pa[V], pb[V];
+                rd.read(c, a, b, bad);
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    pa[j] = a[j] != b[j] ? w.par[a[j]] : 0u;
+                    pb[j] = a[j] != b[j] ? w.par[b[j]] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    keep[j] = pa[j] != pb[j];
+                    const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
+                    key[j] = ((uint64_t)lo << nb) | hi;
+                    cnt += keep[j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) keep[j] = false;
+            }
+            uint32_t total;
+            uint32_t off = cursor + block_excl_scan<kThreads>(cnt, lds, &total);
 #pragma unroll
             for (int j = 0; j < V; ++j) {
-                pa[j] = a[j] != b[j] ? w.par[a[j]] : 0u;
-                pb[j] = a[j] != b[j] ? w.par[b[j]] : 0u;
+                if (keep[j]) dst[off++] = key[j];
             }
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                keep[j] = pa[j] != pb[j];
-                uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
-                key[j] = ((uint64_t)lo << nb) | hi;
-                cnt += keep[j];
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) keep[j] = false;
+            cursor += total;
         }
-        uint32_t total;
-        uint32_t pre = block_excl_scan<kThreads>(cnt, lds, &total);
-        if (threadIdx.x == 0) base_sh = total ? atomicAdd(&st->s_count, (u64c)total) : 0ull;
-        __syncthreads();
-        const u64c base = base_sh;
-        uint32_t off = pre;
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            if (keep[j]) out[base + off++] = key[j];
+        if (threadIdx.x == 0) {
+            w.slab_cnt[slab] = cursor;
+            if (cursor) atomicAdd(&st->s_count, (u64c)cursor);
         }
-        __syncthreads();
     }
-    (void)bad;
 }
 
 template <bool kFirst, bool kBatch>
@@ -444,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void k_canon_min(Work w, const void *labe
     for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
         uint32_t lab = kOut64 ? (uint32_t)((const int64_t *)labels)[v] : (uint32_t)((const int32_t *)labels)[v];
         const uint32_t base = kBatch ? voff[w.gid0[v]] : 0u;
-        atomicMin(&w.m1[lab + base], (uint32_t)v);
+        atomicMin(&w.newidx[lab + base], (uint32_t)v);
     }
 }
 
@@ -453,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void k_canon_apply(Work w, void *labels, 
     for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
         uint32_t lab = kOut64 ? (uint32_t)((const int64_t *)labels)[v] : (uint32_t)((const int32_t *)labels)[v];
         const uint32_t base = kBatch ? voff[w.gid0[v]] : 0u;
-        const uint32_t c = w.m1[lab + base] - base;
+        const uint32_t c = w.newidx[lab + base] - base;
         if (kOut64)
             ((int64_t *)labels)[v] = (int64_t)c;
         else
@@ -470,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_dump_parents(Work w, int first, co
                                                            int32_t *out) {
     const int64_t n = (int64_t)w.st->n_prev;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        if (first && w.lv[i] == kInf) continue;
+        if (first && w.ml[2 * i + 1] == kInf) continue;
         const uint32_t p = w.par[i];
         const uint32_t x = first ? (uint32_t)i : names_prev[i];
         out[x] = (int32_t)(first ? p : names_prev[p]);
@@ -617,7 +645,7 @@ hipError_t launch_flatten(const Work &w, int grid, hipStream_t s) {
 
 hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch, const uint32_t *voff, int grid,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, w.m1, kInf, w.n0);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, w.newidx, kInf, w.n0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (out64) {

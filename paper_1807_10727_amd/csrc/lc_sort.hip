@@ -124,34 +124,60 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T *in, uint32_t *o
 // radix sort passes
 // ---------------------------------------------------------------------------------------
 
+// Tiles of one pass.  Pass 0 reads the relabel output in place: tile t is the (t % 2)-th
+// half of slab t / 2, filled from its start with that slab's survivors.  Later passes read
+// a compact array of S keys.  In both cases the keys of tile t are the first valid(t)
+// positions of [t * kSortTile, (t + 1) * kSortTile).
+struct Tiles {
+    int64_t ntiles;
+    int64_t S;
+    const uint32_t *slab_cnt;
+    bool slab;
+    __device__ int valid(int64_t t) const {
+        constexpr int kPer = kSlab / kSortTile;
+        const int64_t c = slab ? (int64_t)slab_cnt[t / kPer] - (t % kPer) * kSortTile : S - t * kSortTile;
+        return c <= 0 ? 0 : (c >= kSortTile ? kSortTile : (int)c);
+    }
+};
+
+__device__ inline Tiles tiles_of(const Work &w, int pass) {
+    const RoundState *st = w.st;
+    Tiles t;
+    t.S = (int64_t)st->s_count;
+    t.slab = pass == 0;
+    t.slab_cnt = w.slab_cnt;
+    t.ntiles = t.slab ? (int64_t)st->n_slabs * (kSlab / kSortTile) : ceil_div(t.S, kSortTile);
+    return t;
+}
+
 __device__ inline bool is_leader(uint64_t peers) { return (int)(__ffsll((long long)peers) - 1) == lane_id(); }
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(Work w, int pass) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
-    const int64_t S = (int64_t)st->s_count;
-    const int64_t ntiles = ceil_div(S, kSortTile);
     if (pass >= passes) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = 0;
         return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)kRadix * (u64c)ntiles;
+    const Tiles tl = tiles_of(w, pass);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)kRadix * (u64c)tl.ntiles;
     const uint64_t *in = w.keys[sort_src(st->round, st->e_sel) ^ (pass & 1)];
     const int shift = pass * kRadixBits;
     __shared__ uint32_t hist[kRadix];
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
+        const int tv = tl.valid(tile);
         hist[threadIdx.x] = 0;
         __syncthreads();
 #pragma unroll 4
         for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = tile * kSortTile + j * kThreads + threadIdx.x;
-            const bool valid = idx < S;
-            const uint32_t d = valid ? (uint32_t)(in[idx] >> shift) & (kRadix - 1) : 0u;
+            const int it = j * kThreads + threadIdx.x;
+            const bool valid = it < tv;
+            const uint32_t d = valid ? (uint32_t)(in[tile * kSortTile + it] >> shift) & (kRadix - 1) : 0u;
             const uint64_t peers = match_bits<kRadixBits>(d, ballot(valid));
             if (valid && is_leader(peers)) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
         }
         __syncthreads();
-        w.counts[(int64_t)threadIdx.x * ntiles + tile] = hist[threadIdx.x];
+        w.counts[(int64_t)threadIdx.x * tl.ntiles + tile] = hist[threadIdx.x];
         __syncthreads();
     }
 }
@@ -160,8 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
     if (pass >= passes) return;
-    const int64_t S = (int64_t)st->s_count;
-    const int64_t ntiles = ceil_div(S, kSortTile);
+    const Tiles tl = tiles_of(w, pass);
+    const int64_t ntiles = tl.ntiles;
     const int src = sort_src(st->round, st->e_sel) ^ (pass & 1);
     const uint64_t *in = w.keys[src];
     uint64_t *out = w.keys[src ^ 1];
@@ -179,16 +205,17 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
     const uint64_t lt = lanemask_lt();
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tv = tl.valid(tile);
         for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
 
         uint64_t k[kSortItems];
         uint32_t rk[kSortItems];
-        const int64_t wbase = tile * kSortTile + (int64_t)wave * (kSortItems * kWave);
+        const int wbase = wave * (kSortItems * kWave);
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = wbase + j * kWave + lane;
-            k[j] = idx < S ? in[idx] : ~0ull;   // padding sorts last within its tile
+            const int it = wbase + j * kWave + lane;
+            k[j] = it < tv ? in[tile * kSortTile + it] : ~0ull;   // padding sorts last within its tile
         }
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
@@ -224,11 +251,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
         }
         __syncthreads();
 
-        const int64_t valid = S - tile * kSortTile < kSortTile ? S - tile * kSortTile : kSortTile;
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const int pos = j * kThreads + threadIdx.x;
-            if (pos < valid) {
+            if (pos < tv) {
                 const uint64_t kk = skeys[pos];
                 const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
                 out[gofs[d] + (uint32_t)pos - dstart[d]] = kk;
