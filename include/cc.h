@@ -174,6 +174,45 @@ cc_status cc_kernel_times(const cc_ctx *ctx, double *ms, int64_t *launches, int3
 cc_status cc_destroy(cc_ctx *ctx);
 const char *cc_last_error(const cc_ctx *ctx);
 
+/* ------------------------------------------------------------------------------------
+ * Batched solve of many independent graphs (one launch sequence, captured in a hipGraph).
+ *
+ * Graph g has vertices 0 .. n_g-1 (n_g = h_vtx_off[g+1] - h_vtx_off[g]) and the records
+ * d_src[i], d_dst[i] (int32 local ids) for i in [h_edge_off[g], h_edge_off[g+1]).  Its
+ * priorities come from h_seeds[g] exactly as in a solo solve with that seed, and components
+ * of different graphs never interact (Section 3: only priorities inside a component are
+ * compared), so every graph's labels equal its solo cc_run + cc_labels.  Offsets and seeds
+ * are copied at creation; device arrays are borrowed until cc_batch_destroy.
+ * ------------------------------------------------------------------------------------ */
+typedef struct cc_batch cc_batch;
+
+/* Tuning knobs (picked by the autotuner; every setting gives identical labels). */
+typedef struct {
+    int32_t blocks_per_cu;        /* workgroups per CU of the grid-stride kernels (1..64) */
+    int32_t small_variant;        /* LDS solver limits: 0 none, 1 (512 vertices, 4096 records),
+                                     2 (1024, 8192), 3 (2048, 16384) */
+    int32_t small_threads;        /* workgroup size of the LDS solver: 256 or 512 */
+    int32_t small_blocks_per_cu;  /* persistent LDS workgroups per CU (1..16) */
+    int32_t rounds_per_graph;     /* union rounds captured in the graph (1..64); more run eagerly */
+    int32_t use_graph;            /* 1: capture once and replay; 0: eager launches */
+} cc_batch_config;
+
+cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
+                          const uint64_t *h_seeds, const void *d_src, const void *d_dst, const cc_options *opts,
+                          cc_batch **out);
+cc_status cc_batch_workspace_size(const cc_batch *batch, size_t *bytes);
+cc_status cc_batch_set_workspace(cc_batch *batch, void *d_workspace, size_t bytes);
+cc_status cc_batch_set_config(cc_batch *batch, const cc_batch_config *config);
+cc_status cc_batch_get_config(const cc_batch *batch, cc_batch_config *config);
+/* Solve every graph: d_labels int32[h_vtx_off[G]] receives local labels (slot h_vtx_off[g] + v
+ * for vertex v of graph g); h_rounds (nullable, host int32[G]) the rounds of each graph.
+ * Synchronises the stream. */
+cc_status cc_batch_run(cc_batch *batch, int32_t *d_labels, int32_t *h_rounds);
+/* How the current configuration split the batch: graphs on the LDS solver, union records. */
+cc_status cc_batch_split(const cc_batch *batch, int32_t *n_small, int64_t *union_records);
+cc_status cc_batch_destroy(cc_batch *batch);
+const char *cc_batch_last_error(const cc_batch *batch);
+
 /* Library version string and the offload target it was built for. */
 const char *cc_version(void);
 

@@ -12,12 +12,14 @@ workspace, the label tensor) and the stream.
 from __future__ import annotations
 
 from . import _cc
+from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_batch_run, cc_batch_set_config,
+                  cc_batch_set_workspace, cc_batch_split, cc_batch_workspace_size)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_PROFILE, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
                   cc_kernel_family_names, cc_kernel_times, cc_labels, cc_last_error, cc_reset, cc_round_parents,
                   cc_run, cc_set_workspace, cc_version, cc_workspace_size)
 
-__all__ = ["Solver", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
+__all__ = ["Solver", "Batch", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
 
 
 def _torch():
@@ -119,3 +121,64 @@ def solve(n: int, src, dst=None, seed: int = 0, flags: int = 0, max_rounds: int 
         st = s.stats(rounds)
         _torch().cuda.current_stream(s.device).synchronize()
         return lab, rounds, st
+
+
+class Batch:
+    """Many independent graphs solved together (cc_batch_*).  Graph g has vertices
+    0 .. n_g-1 and records src[i], dst[i] (int32 local ids, device tensors) for i in
+    [edge_off[g], edge_off[g+1]); seeds[g] is its priority seed.  Labels come back as one
+    int32 tensor with graph g's labels at [vtx_off[g], vtx_off[g+1])."""
+
+    def __init__(self, vtx_off, edge_off, seeds, src, dst, stream=None, **config):
+        torch = _torch()
+        import numpy as np
+        self.voff = np.ascontiguousarray(vtx_off, dtype=np.int64)
+        self.eoff = np.ascontiguousarray(edge_off, dtype=np.int64)
+        self.G = int(self.voff.shape[0] - 1)
+        self.n_total = int(self.voff[-1])
+        self.device = src.device
+        if src.dtype != torch.int32 or dst.dtype != torch.int32:
+            raise ValueError("batched records are int32 local ids")
+        self._src, self._dst = src, dst
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.b = cc_batch_create(self.voff, self.eoff, seeds, src.data_ptr(), dst.data_ptr(),
+                                 stream=self.stream.cuda_stream)
+        self.ws_bytes = cc_batch_workspace_size(self.b)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        cc_batch_set_workspace(self.b, self.ws.data_ptr(), self.ws_bytes)
+        if config:
+            cc_batch_set_config(self.b, **config)
+        self.labels_buf = torch.empty(max(self.n_total, 1), dtype=torch.int32, device=self.device)
+
+    def configure(self, **config):
+        cc_batch_set_config(self.b, **config)
+
+    @property
+    def config(self):
+        return cc_batch_get_config(self.b)
+
+    def split(self):
+        return cc_batch_split(self.b)
+
+    def run(self, with_rounds: bool = True):
+        import numpy as np
+        rounds = np.zeros(max(self.G, 1), dtype=np.int32) if with_rounds else None
+        cc_batch_run(self.b, self.labels_buf.data_ptr(), rounds)
+        return self.labels_buf[:self.n_total], (rounds[:self.G] if with_rounds else None)
+
+    def close(self):
+        if self.b:
+            cc_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

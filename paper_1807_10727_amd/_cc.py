@@ -46,6 +46,15 @@ class cc_round_stats(ctypes.Structure):
         return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
 
 
+class cc_batch_config(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("small_variant", ctypes.c_int32),
+                ("small_threads", ctypes.c_int32), ("small_blocks_per_cu", ctypes.c_int32),
+                ("rounds_per_graph", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _ctx_p = ctypes.c_void_p
 _sig = {
     "cc_create": (ctypes.c_int32, [ctypes.POINTER(cc_graph_desc), ctypes.POINTER(cc_options),
@@ -65,6 +74,17 @@ _sig = {
     "cc_destroy": (ctypes.c_int32, [_ctx_p]),
     "cc_last_error": (ctypes.c_char_p, [_ctx_p]),
     "cc_version": (ctypes.c_char_p, []),
+    "cc_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(cc_options), ctypes.POINTER(_ctx_p)]),
+    "cc_batch_workspace_size": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cc_batch_set_workspace": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "cc_batch_set_config": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_batch_config)]),
+    "cc_batch_get_config": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_batch_config)]),
+    "cc_batch_run": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cc_batch_split": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
+    "cc_batch_destroy": (ctypes.c_int32, [_ctx_p]),
+    "cc_batch_last_error": (ctypes.c_char_p, [_ctx_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -164,3 +184,73 @@ def cc_last_error(ctx) -> str:
 
 def cc_version() -> str:
     return _lib.cc_version().decode()
+
+
+# ---- batched solve ---------------------------------------------------------------------
+
+def _bcheck(b, status: int) -> int:
+    if status < 0:
+        msg = _lib.cc_batch_last_error(b) if b else b""
+        raise CCError(status, (msg or b"").decode())
+    return status
+
+
+def cc_batch_create(vtx_off, edge_off, seeds, src_ptr: int, dst_ptr: int, flags: int = 0, stream: int = 0):
+    import numpy as np
+    voff = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    eoff = np.ascontiguousarray(edge_off, dtype=np.int64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    G = int(voff.shape[0] - 1)
+    o = cc_options(0, 0, flags, stream or None)
+    b = _ctx_p()
+    _bcheck(None, _lib.cc_batch_create(G, voff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       eoff.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), src_ptr or None,
+                                       dst_ptr or None, ctypes.byref(o), ctypes.byref(b)))
+    return b
+
+
+def cc_batch_workspace_size(b) -> int:
+    n = ctypes.c_size_t()
+    _bcheck(b, _lib.cc_batch_workspace_size(b, ctypes.byref(n)))
+    return int(n.value)
+
+
+def cc_batch_set_workspace(b, ptr: int, nbytes: int) -> None:
+    _bcheck(b, _lib.cc_batch_set_workspace(b, ptr, nbytes))
+
+
+def cc_batch_set_config(b, **kw) -> None:
+    c = cc_batch_config()
+    _bcheck(b, _lib.cc_batch_get_config(b, ctypes.byref(c)))
+    for k, v in kw.items():
+        setattr(c, k, int(v))
+    _bcheck(b, _lib.cc_batch_set_config(b, ctypes.byref(c)))
+
+
+def cc_batch_get_config(b) -> dict:
+    c = cc_batch_config()
+    _bcheck(b, _lib.cc_batch_get_config(b, ctypes.byref(c)))
+    return c.as_dict()
+
+
+def cc_batch_run(b, labels_ptr: int, rounds=None) -> None:
+    """rounds: optional host int32 numpy array [G] receiving per-graph round counts."""
+    rp = rounds.ctypes.data_as(ctypes.c_void_p) if rounds is not None else None
+    _bcheck(b, _lib.cc_batch_run(b, labels_ptr or None, rp))
+
+
+def cc_batch_split(b):
+    ns = ctypes.c_int32()
+    um = ctypes.c_int64()
+    _bcheck(b, _lib.cc_batch_split(b, ctypes.byref(ns), ctypes.byref(um)))
+    return int(ns.value), int(um.value)
+
+
+def cc_batch_destroy(b) -> None:
+    if b:
+        _lib.cc_batch_destroy(b)
+
+
+def cc_batch_last_error(b) -> str:
+    return (_lib.cc_batch_last_error(b) or b"").decode()

@@ -127,7 +127,7 @@ void Engine::ev_collect() {
         if (!hip_ok(e_, kFamilyNames[fam])) return false; \
     } while (0)
 
-bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc) {
+bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int passes_bound) {
     const bool first = r == 0;
     const EdgeIn *src = first ? &in : nullptr;
     const int gn = grid_for(N);
@@ -135,12 +135,13 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc) {
     const int gt = grid_tiles(M);
     const int gscan_n = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), kScanTile), grid_cap);
     const int nbits = 2 * ceil_log2_host(std::max<int64_t>(N, 2));
-    const int passes = npasses(nbits);
+    const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
     const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(M, 1), kSortTile) + 2);
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 
     RUN(kRoundBegin, launch_round_begin(w, gn, stream));
+    if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
     RUN(kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
     RUN(kMin2, launch_min2(w, src, gm, stream));
     RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));

@@ -33,6 +33,11 @@ struct Engine {
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state
     bool h_st_pageable = false;
+    // batch of independent graphs (union path)
+    RoundKey *d_keys = nullptr;         // [G] per-graph round keys (device)
+    const uint64_t *d_seeds = nullptr;  // [G] per-graph seeds (device)
+    const uint32_t *d_voff = nullptr;   // [G+1] first union id of each graph (device)
+    int32_t n_graphs = 0;
     int host_levels = 0;          // per-round maps currently kept in the arena
     int64_t host_map_used = 0;
     std::string err;
@@ -51,7 +56,10 @@ struct Engine {
     void ev_begin(int family);
     void ev_end();
     void ev_collect();
-    bool enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc);
+    // Enqueue round r (only r == 0 and the parity of r matter to the launch sequence).
+    // N and M bound the round's nodes and records (exact in eager mode); passes bounds the
+    // radix passes (computed from N when negative).
+    bool enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int passes = -1);
     bool flatten();
     bool read_state();
     bool write_initial_state(int64_t n_cur, int64_t m_cur);

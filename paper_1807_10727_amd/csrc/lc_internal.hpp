@@ -82,6 +82,7 @@ struct Work {
     uint32_t *partials;  // scan partial sums
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
+    int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
     int64_t n0, m0;
 };
 
@@ -130,7 +131,7 @@ hipError_t launch_flatten(const Work &w, int grid, hipStream_t s);
 hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch, const uint32_t *voff, int grid,
                             hipStream_t s);
 hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int grid, hipStream_t s);
-hipError_t launch_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, int round, hipStream_t s);
+hipError_t launch_batch_keys(const Work &w, RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, hipStream_t s);
 hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.

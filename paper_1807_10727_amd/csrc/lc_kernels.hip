@@ -290,6 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
         }
         w.par[i] = p;
         w.is_label[p] = 1;
+        if (kBatch) w.g_rounds[kFirst ? w.gid0[i] : gids[i]] = st->round + 1;
         ++active;
     }
     active = wave_sum(active);
@@ -386,6 +387,7 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
     if (kFirst) {
         out = w.map0;
     } else {
+        if (n == 0) return;
         if (st->map_off + (u64c)n > st->map_cap || st->levels >= kMaxLevels) {
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 2u);
             return;
@@ -417,7 +419,7 @@ template <bool kFirst>
 __global__ void k_round_end(Work w) {
     RoundState *st = w.st;
     st->n_prev = st->n_cur;
-    if (!kFirst && !(st->err & 2u)) {
+    if (!kFirst && st->n_cur > 0 && !(st->err & 2u)) {
         st->level_off[st->levels] = st->map_off;
         st->levels += 1;
         st->map_off += st->n_cur;
@@ -505,7 +507,10 @@ __global__ __launch_bounds__(kThreads) void k_dump_parents(Work w, int first, co
     }
 }
 
-__global__ void k_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t g, int32_t round) {
+// per-graph round keys of the current round (the round index is read on the device, so
+// the launch can be replayed from a captured graph)
+__global__ void k_batch_keys(Work w, RoundKey *keys, const uint64_t *seeds, int32_t g) {
+    const int32_t round = w.st->round;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g; i += gridDim.x * blockDim.x)
         keys[i] = round_key(seeds[i], round);
 }
@@ -675,10 +680,10 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, int grid, hipStre
     LC_LAUNCH(k_fill_u32, grid, p, v, n);
 }
 
-hipError_t launch_batch_keys(RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, int round, hipStream_t s) {
+hipError_t launch_batch_keys(const Work &w, RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, hipStream_t s) {
     int grid = (int)ceil_div(n_graphs, kThreads);
     if (grid < 1) grid = 1;
-    LC_LAUNCH(k_batch_keys, grid, keys, seeds, n_graphs, round);
+    LC_LAUNCH(k_batch_keys, grid, w, keys, seeds, n_graphs);
 }
 
 hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s) {
