@@ -90,6 +90,79 @@ def cpu_baseline(shrink):
                       % (shrink, g.n, g.m, res.rounds, dt)}
 
 
+def bench_batch(args, log_prefix="batch"):
+    """4,096 independent graphs (half G(n,m) with average degree U[1.5,16], half R-MAT with
+    edge factor 8, vertex counts log-uniform in [2^8, 2^18]) solved as one batch, against
+    the same graphs solved one after another with the plain API on the same GPU."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1807_10727_amd as lc
+    from paper_1807_10727_amd import autotune
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    b = graphgen.batch_mix(count=args.batch_graphs, log2_max=args.batch_log2_max)
+    log("%s: generated %d graphs, n=%d, m=%d in %.1fs" % (log_prefix, b.count, int(b.voff[-1]), int(b.eoff[-1]),
+                                                          time.perf_counter() - t0))
+    src = torch.from_numpy(b.src.view(np.int32)).to(dev)
+    dst = torch.from_numpy(b.dst.view(np.int32)).to(dev)
+    bt = lc.Batch(b.voff, b.eoff, b.seeds, src, dst)
+    t0 = time.perf_counter()
+    cfg, _, tried = autotune.tune(bt, repeats=1, cache=args.tune_cache, log=log if args.verbose_tune else None)
+    log("%s: autotune picked %s (%d candidates timed, %.1fs)" % (log_prefix, cfg, tried, time.perf_counter() - t0))
+    n_small, union_m = bt.split()
+    lab, rounds = bt.run()                      # warm (captures the graph if needed)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.batch_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.run(with_rounds=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_batch = sorted(ts)[len(ts) // 2]
+    batch_labels = bt.labels_buf[:bt.n_total].clone()
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+
+    # sequential plain solves: one context per graph on its own (aligned) copy of its records
+    seq_labels = torch.empty(max(int(b.voff[-1]), 1), dtype=torch.int32, device=dev)
+    solvers = []
+    for j in range(b.count):
+        a, e = int(b.eoff[j]), int(b.eoff[j + 1])
+        sj = src[a:e].clone() if e > a else torch.zeros(1, dtype=torch.int32, device=dev)[:0]
+        dj = dst[a:e].clone() if e > a else torch.zeros(1, dtype=torch.int32, device=dev)[:0]
+        solvers.append(lc.Solver(int(b.n[j]), sj, dj, seed=int(b.seeds[j])))
+    for j in range(min(64, b.count)):
+        solvers[j].run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, sv in enumerate(solvers):
+        sv.reset(int(b.seeds[j]))
+        sv.run()
+        if sv.n:
+            sv.labels(seq_labels[int(b.voff[j]):int(b.voff[j + 1])])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for sv in solvers:
+        sv.close()
+    same = bool(torch.equal(seq_labels[:int(b.voff[-1])], batch_labels))
+    log("%s: batch %.1f ms, sequential %.1f ms, labels identical: %s" % (log_prefix, t_batch * 1e3, t_seq * 1e3, same))
+    if not same:
+        raise RuntimeError("batched labels differ from the sequential solves")
+    del solvers, seq_labels, batch_labels, src, dst
+    torch.cuda.empty_cache()
+    return {"graphs": b.count, "records": int(b.eoff[-1]), "vertices": int(b.voff[-1]),
+            "graphs_per_s": b.count / t_batch, "ms": t_batch * 1e3,
+            "sequential_graphs_per_s": b.count / t_seq, "sequential_ms": t_seq * 1e3,
+            "speedup_vs_sequential": t_seq / t_batch, "labels_identical_to_sequential": same,
+            "lds_path_graphs": n_small, "union_records": union_m, "max_rounds": int(rounds.max()),
+            "config": cfg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +172,13 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-shrink", type=int, default=8)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode leg")
+    ap.add_argument("--batch-only", action="store_true", help="run only the batched-mode leg")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--batch-log2-max", type=int, default=18)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: none, tune every run)")
+    ap.add_argument("--verbose-tune", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -111,6 +191,10 @@ def main():
 
     import graphgen
     import paper_1807_10727_amd as lc
+
+    if args.batch_only:
+        print(json.dumps({"batched": bench_batch(args)}), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -206,6 +290,17 @@ def main():
     log("job algorithmic bytes per step %.2f GB -> %.1f GB/s (%.1f%% of 8 TB/s)"
         % (job_bytes / args.steps / 1e9, job_gbs, 100 * job_gbs / HBM_PEAK_GBS))
 
+    solver.close()
+    del solver, src, dst, labels
+    torch.cuda.empty_cache()
+    batched = None
+    if not args.no_batch:
+        try:
+            batched = bench_batch(args)
+        except Exception as e:  # the main figure stands on its own
+            log("batched leg failed: %r" % (e,))
+            batched = {"error": repr(e)}
+
     cpu = None
     if not args.no_cpu:
         try:
@@ -231,9 +326,9 @@ def main():
         "roofline": roofline,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":

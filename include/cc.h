@@ -213,6 +213,71 @@ cc_status cc_batch_split(const cc_batch *batch, int32_t *n_small, int64_t *union
 cc_status cc_batch_destroy(cc_batch *batch);
 const char *cc_batch_last_error(const cc_batch *batch);
 
+/* ------------------------------------------------------------------------------------
+ * Serving: continuous batching of requests on one GPU.
+ *
+ * A scheduler thread admits requests while a slot and device memory are free and keeps
+ * their state on the device; requests that arrive while others run are admitted as
+ * slots and memory free up, and their work overlaps on the device.  Waiting small
+ * requests (CC_EDGES_SOA_I32 within the LDS limits of small_variant) are fused into one
+ * launch of the LDS solver; every other request gets a slot stream and a workspace from
+ * the arena and advances one round (Section 3, one phase) per scheduler step.  A request's
+ * labels equal its solo solve with the same seed, whatever else is in flight.
+ *
+ * The arena is caller-owned device memory of budget_bytes (256-byte aligned); request
+ * workspaces are carved from it and returned when the request completes, so the budget
+ * caps the device memory in use.  A request whose own workspace exceeds the whole budget
+ * is refused (CC_E_BUDGET); one that only waits for memory is deferred, never failed.
+ * A request's edge arrays and label array are caller-owned device memory that must stay
+ * valid until the request completes.  All entry points are thread-safe.
+ * ------------------------------------------------------------------------------------ */
+typedef struct cc_server cc_server;
+
+typedef struct {
+    int32_t n_slots;               /* large requests in flight at once (1..64), one stream each */
+    int32_t small_variant;         /* LDS limits for small requests as in cc_batch_config; 0 = none */
+    int32_t small_threads;         /* 256 or 512 */
+    int32_t small_blocks_per_cu;   /* 1..16 */
+    int32_t max_small_per_launch;  /* small requests fused into one launch (1..65536) */
+    int32_t small_launches;        /* small launches in flight at once (1..8) */
+} cc_server_config;
+
+typedef struct {
+    uint64_t id;
+    cc_status status;      /* CC_OK; CC_E_INPUT for an id out of range; CC_E_STATE if cancelled */
+    int32_t rounds;
+    int32_t small_path;    /* 1 if solved by the fused LDS launch */
+    int32_t reserved;
+    double t_submit;       /* seconds on the server clock (cc_server_info().now) */
+    double t_admit;
+    double t_done;         /* labels written */
+} cc_request_result;
+
+typedef struct {
+    double now;            /* server clock, seconds since creation */
+    int64_t pending;       /* submitted, not admitted */
+    int64_t active;        /* admitted, not completed */
+    int64_t bytes_in_use;  /* arena bytes held by admitted requests */
+    int64_t peak_bytes;
+    int64_t small_launches;
+} cc_server_info_t;
+
+cc_status cc_server_create(void *d_arena, size_t budget_bytes, const cc_server_config *config, cc_server **out);
+/* Queue one graph (described as for cc_create) with its priority seed; labels (int32, or
+ * int64 for CC_EDGES_SOA_I64) go to d_labels.  *req_id identifies the request. */
+cc_status cc_server_submit(cc_server *server, const cc_graph_desc *graph, uint64_t seed, void *d_labels,
+                           uint64_t *req_id);
+/* Completed requests (non-blocking): up to cap results into out, count in *n. */
+cc_status cc_server_poll(cc_server *server, cc_request_result *out, int32_t cap, int32_t *n);
+/* Like cc_server_poll, but waits up to timeout_s seconds for at least one completion. */
+cc_status cc_server_wait(cc_server *server, cc_request_result *out, int32_t cap, int32_t *n, double timeout_s);
+/* Cancel a request that has not completed (it completes with CC_E_STATE). */
+cc_status cc_server_cancel(cc_server *server, uint64_t req_id);
+cc_status cc_server_info(cc_server *server, cc_server_info_t *info);
+/* Finishes every admitted request, cancels the waiting ones, stops the scheduler. */
+cc_status cc_server_destroy(cc_server *server);
+const char *cc_server_last_error(const cc_server *server);
+
 /* Library version string and the offload target it was built for. */
 const char *cc_version(void);
 

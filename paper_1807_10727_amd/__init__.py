@@ -14,12 +14,14 @@ from __future__ import annotations
 from . import _cc
 from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_batch_run, cc_batch_set_config,
                   cc_batch_set_workspace, cc_batch_split, cc_batch_workspace_size)
+from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
+                  cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_PROFILE, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
                   cc_kernel_family_names, cc_kernel_times, cc_labels, cc_last_error, cc_reset, cc_round_parents,
                   cc_run, cc_set_workspace, cc_version, cc_workspace_size)
 
-__all__ = ["Solver", "Batch", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
+__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
 
 
 def _torch():
@@ -170,6 +172,77 @@ class Batch:
         if self.b:
             cc_batch_destroy(self.b)
             self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over the C ABI (cc_server_*).  The arena is a torch uint8
+    tensor of `budget` bytes; submitted tensors are kept referenced until their request
+    completes."""
+
+    def __init__(self, budget: int, device="cuda:0", **config):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.arena = torch.empty(budget, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        self.srv = cc_server_create(self.arena.data_ptr(), budget, **config)
+        self._held = {}
+
+    def submit(self, n: int, src, dst, seed: int, labels=None, layout: int | None = None):
+        """Returns (request id, labels tensor).  src/dst: int32 (or int64) device tensors."""
+        torch = _torch()
+        if layout is None:
+            layout = CC_EDGES_SOA_I32 if src.dtype == torch.int32 else CC_EDGES_SOA_I64
+        if labels is None:
+            labels = torch.empty(max(n, 1), dtype=torch.int64 if layout == CC_EDGES_SOA_I64 else torch.int32,
+                                 device=self.device)
+        rid = cc_server_submit(self.srv, n, int(src.shape[0]), layout, src.data_ptr(),
+                               dst.data_ptr() if dst is not None else 0, seed, labels.data_ptr())
+        self._held[rid] = (src, dst, labels)
+        return rid, labels[:n]
+
+    def _release(self, results):
+        for r in results:
+            self._held.pop(r["id"], None)
+        return results
+
+    def poll(self):
+        return self._release(cc_server_poll(self.srv))
+
+    def wait(self, timeout_s: float = 1.0):
+        return self._release(cc_server_wait(self.srv, timeout_s))
+
+    def drain(self, timeout_s: float = 600.0):
+        """Wait for every submitted request; returns their results."""
+        import time
+        out = []
+        t_end = time.time() + timeout_s
+        while self._held and time.time() < t_end:
+            out += self.wait(0.5)
+        return out
+
+    def cancel(self, rid: int):
+        cc_server_cancel(self.srv, rid)
+
+    def info(self):
+        return cc_server_info(self.srv)
+
+    def close(self):
+        if self.srv:
+            cc_server_destroy(self.srv)
+            self.srv = None
+            self._held.clear()
 
     def __enter__(self):
         return self

@@ -55,6 +55,29 @@ class cc_batch_config(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class cc_server_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("small_variant", ctypes.c_int32), ("small_threads", ctypes.c_int32),
+                ("small_blocks_per_cu", ctypes.c_int32), ("max_small_per_launch", ctypes.c_int32),
+                ("small_launches", ctypes.c_int32)]
+
+
+class cc_request_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("small_path", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class cc_server_info_t(ctypes.Structure):
+    _fields_ = [("now", ctypes.c_double), ("pending", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("small_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _ctx_p = ctypes.c_void_p
 _sig = {
     "cc_create": (ctypes.c_int32, [ctypes.POINTER(cc_graph_desc), ctypes.POINTER(cc_options),
@@ -85,6 +108,18 @@ _sig = {
     "cc_batch_split": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]),
     "cc_batch_destroy": (ctypes.c_int32, [_ctx_p]),
     "cc_batch_last_error": (ctypes.c_char_p, [_ctx_p]),
+    "cc_server_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(cc_server_config),
+                                          ctypes.POINTER(_ctx_p)]),
+    "cc_server_submit": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_graph_desc), ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "cc_server_poll": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_request_result), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "cc_server_wait": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_request_result), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_double]),
+    "cc_server_cancel": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
+    "cc_server_info": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_server_info_t)]),
+    "cc_server_destroy": (ctypes.c_int32, [_ctx_p]),
+    "cc_server_last_error": (ctypes.c_char_p, [_ctx_p]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -254,3 +289,63 @@ def cc_batch_destroy(b) -> None:
 
 def cc_batch_last_error(b) -> str:
     return (_lib.cc_batch_last_error(b) or b"").decode()
+
+
+# ---- serving ---------------------------------------------------------------------------
+
+def _scheck(srv, status: int) -> int:
+    if status < 0:
+        msg = _lib.cc_server_last_error(srv) if srv else b""
+        raise CCError(status, (msg or b"").decode())
+    return status
+
+
+def cc_server_create(arena_ptr: int, budget: int, n_slots: int = 4, small_variant: int = 1, small_threads: int = 256,
+                     small_blocks_per_cu: int = 2, max_small_per_launch: int = 1024, small_launches: int = 2):
+    c = cc_server_config(n_slots, small_variant, small_threads, small_blocks_per_cu, max_small_per_launch,
+                         small_launches)
+    srv = _ctx_p()
+    _scheck(None, _lib.cc_server_create(arena_ptr, budget, ctypes.byref(c), ctypes.byref(srv)))
+    return srv
+
+
+def cc_server_submit(srv, n_vertices: int, n_edges: int, layout: int, src_ptr: int, dst_ptr: int, seed: int,
+                     labels_ptr: int) -> int:
+    g = cc_graph_desc(n_vertices, n_edges, layout, 0, src_ptr or None, dst_ptr or None)
+    rid = ctypes.c_uint64()
+    _scheck(srv, _lib.cc_server_submit(srv, ctypes.byref(g), seed & 0xFFFFFFFFFFFFFFFF, labels_ptr or None,
+                                       ctypes.byref(rid)))
+    return int(rid.value)
+
+
+def cc_server_poll(srv, cap: int = 256):
+    out = (cc_request_result * cap)()
+    n = ctypes.c_int32()
+    _scheck(srv, _lib.cc_server_poll(srv, out, cap, ctypes.byref(n)))
+    return [out[i].as_dict() for i in range(n.value)]
+
+
+def cc_server_wait(srv, timeout_s: float = 1.0, cap: int = 256):
+    out = (cc_request_result * cap)()
+    n = ctypes.c_int32()
+    _scheck(srv, _lib.cc_server_wait(srv, out, cap, ctypes.byref(n), timeout_s))
+    return [out[i].as_dict() for i in range(n.value)]
+
+
+def cc_server_cancel(srv, rid: int) -> None:
+    _scheck(srv, _lib.cc_server_cancel(srv, rid))
+
+
+def cc_server_info(srv) -> dict:
+    i = cc_server_info_t()
+    _scheck(srv, _lib.cc_server_info(srv, ctypes.byref(i)))
+    return i.as_dict()
+
+
+def cc_server_destroy(srv) -> None:
+    if srv:
+        _lib.cc_server_destroy(srv)
+
+
+def cc_server_last_error(srv) -> str:
+    return (_lib.cc_server_last_error(srv) or b"").decode()

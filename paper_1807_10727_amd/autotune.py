@@ -1,0 +1,109 @@
+"""Autotuner for the batched solve.
+
+The knobs of ``cc_batch_config`` (grid size of the streaming kernels, the LDS solver's
+size limits, workgroup size and persistence) change only speed: every candidate must give
+bit-identical labels, and the tuner checks that.  Candidates are timed on the batch
+itself (or on a caller-chosen sample of the same mix), coordinate by coordinate, and the
+winner is cached as JSON under a key made of the device (architecture, CU count) and the
+batch's size class (log2 of its graph and record counts).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+import time
+
+DEFAULT_CACHE = os.environ.get("LC_TUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "lc_mi355x", "tune.json"))
+
+SEARCH_SPACE = {
+    "small_variant": [0, 1, 2, 3],
+    "small_threads": [256, 512],
+    "small_blocks_per_cu": [1, 2, 4],
+    "blocks_per_cu": [4, 8, 16],
+}
+
+
+def device_key():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "gpu").split(":")[0]
+    return "%s:%dcu" % (arch, p.multi_processor_count)
+
+
+def size_class(batch) -> str:
+    m = int(batch.eoff[-1])
+    return "G2^%d:M2^%d" % (max(0, round(math.log2(max(batch.G, 1)))), max(0, round(math.log2(max(m, 1)))))
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_run(batch, repeats):
+    import torch
+    best = float("inf")
+    digest = None
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab, _ = batch.run(with_rounds=False)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+        if digest is None:
+            digest = hashlib.sha1(lab.cpu().numpy().tobytes()).hexdigest()
+    return best, digest
+
+
+def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, space=None):
+    """Pick the fastest configuration for `batch` (a paper_1807_10727_amd.Batch), apply it
+    and return (config dict, seconds of the best run, number of candidates timed)."""
+    key = "%s|%s" % (device_key(), size_class(batch))
+    if cache:
+        hit = _load(cache).get(key)
+        if hit:
+            batch.configure(**hit["config"])
+            return hit["config"], hit["seconds"], 0
+    space = space or SEARCH_SPACE
+    cfg = dict(batch.config)
+    cfg["use_graph"] = 1
+    batch.configure(**cfg)
+    best_t, ref = _time_run(batch, repeats)
+    tried = 1
+    for knob, values in space.items():
+        for v in values:
+            if v == cfg[knob]:
+                continue
+            cand = dict(cfg, **{knob: v})
+            try:
+                batch.configure(**cand)
+            except Exception:          # e.g. an LDS variant larger than the device allows
+                continue
+            t, digest = _time_run(batch, repeats)
+            tried += 1
+            if digest != ref:
+                raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+            if log:
+                log("  tune %-22s %s -> %.2f ms" % (knob, v, t * 1e3))
+            if t < best_t:
+                best_t, cfg = t, cand
+        batch.configure(**cfg)
+    if cache:
+        data = _load(cache)
+        data[key] = {"config": cfg, "seconds": best_t}
+        _store(cache, data)
+    return cfg, best_t, tried

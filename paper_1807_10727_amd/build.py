@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcc.so")
-SOURCES = ["lc_kernels.hip", "lc_sort.hip", "lc_engine.hip", "lc_batch.hip"]
+SOURCES = ["lc_kernels.hip", "lc_sort.hip", "lc_engine.hip", "lc_batch.hip", "lc_serve.hip"]
 ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950")
 
 
@@ -17,7 +17,7 @@ def command(out: str = LIB):
     return (["hipcc", "--offload-arch=%s" % ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
              # no packed fp32 instructions in any kernel
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-Wno-unused-command-line-argument",
+             "-Wno-unused-command-line-argument", "-pthread",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out]
             + [os.path.join(CSRC, s) for s in SOURCES])
 

@@ -120,12 +120,6 @@ __global__ __launch_bounds__(kThreads) void k_compose_batch(Work w, const uint32
 
 // ---- small-graph variants ----------------------------------------------------------------
 
-struct SmallVariant {
-    int nmax, mmax;
-};
-static const SmallVariant kSmallVariants[] = {{0, 0}, {512, 4096}, {1024, 8192}, {2048, 16384}};
-static const int kNumSmallVariants = 4;
-
 template <int kNT, int kNMax, int kMMax>
 static hipError_t prepare_small_t() {
     return hipFuncSetAttribute((const void *)k_small<kNT, kNMax, kMMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -139,7 +133,7 @@ static hipError_t launch_small_t(const SmallArgs &a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-static size_t small_bytes(int variant, int threads) {
+size_t small_bytes(int variant, int threads) {
     switch (variant) {
         case 1: return threads == 512 ? SmallLds<512, 512, 4096>::kBytes : SmallLds<256, 512, 4096>::kBytes;
         case 2: return threads == 512 ? SmallLds<512, 1024, 8192>::kBytes : SmallLds<256, 1024, 8192>::kBytes;
@@ -149,7 +143,7 @@ static size_t small_bytes(int variant, int threads) {
 }
 
 // allow the variant's dynamic LDS size (done outside any capture)
-static hipError_t prepare_small(int variant, int threads) {
+hipError_t prepare_small(int variant, int threads) {
     switch (variant) {
         case 1: return threads == 512 ? prepare_small_t<512, 512, 4096>() : prepare_small_t<256, 512, 4096>();
         case 2: return threads == 512 ? prepare_small_t<512, 1024, 8192>() : prepare_small_t<256, 1024, 8192>();
@@ -158,7 +152,7 @@ static hipError_t prepare_small(int variant, int threads) {
     }
 }
 
-static hipError_t launch_small(int variant, int threads, const SmallArgs &a, int grid, hipStream_t s) {
+hipError_t launch_small(int variant, int threads, const SmallArgs &a, int grid, hipStream_t s) {
     switch (variant) {
         case 1: return threads == 512 ? launch_small_t<512, 512, 4096>(a, grid, s) : launch_small_t<256, 512, 4096>(a, grid, s);
         case 2: return threads == 512 ? launch_small_t<512, 1024, 8192>(a, grid, s) : launch_small_t<256, 1024, 8192>(a, grid, s);
@@ -184,7 +178,10 @@ struct cc_batch : public lc::Engine {
     int64_t *d_voff64 = nullptr, *d_eoff64 = nullptr, *d_ubase = nullptr;
     uint32_t *d_voff32 = nullptr, *d_queue = nullptr;
     uint64_t *d_seeds_w = nullptr;
-    int32_t *d_small = nullptr, *d_big = nullptr, *d_rounds = nullptr;
+    int32_t *d_big = nullptr, *d_rounds = nullptr;
+    SmallDesc *d_desc = nullptr;
+    std::vector<SmallDesc> h_desc;
+    int32_t *desc_labels = nullptr;   // labels pointer the uploaded descriptors point into
     uint8_t *d_skip = nullptr;
     // host plan of the current configuration
     std::vector<int32_t> small_list, big_list;
@@ -205,7 +202,7 @@ namespace {
 
 size_t batch_extra_bytes(int32_t G) {
     const size_t g = (size_t)G + 1;
-    return 256 * 12 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 3 + g + 64;
+    return 256 * 12 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 2 + sizeof(SmallDesc) * g + g + 64;
 }
 
 char *carve(char *&p, size_t bytes) {
@@ -258,10 +255,7 @@ cc_status plan(cc_batch *b) {
         !batch_hip(b, prepare_small(b->cfg.small_variant, b->cfg.small_threads), "small-graph LDS size"))
         return CC_E_HIP;
     hipStream_t s = b->stream;
-    if (!b->small_list.empty() &&
-        !batch_hip(b, hipMemcpyAsync(b->d_small, b->small_list.data(), 4 * b->small_list.size(),
-                                     hipMemcpyHostToDevice, s), "upload small list"))
-        return CC_E_HIP;
+    b->desc_labels = nullptr;   // descriptors are written against the labels of the next run
     if (!b->big_list.empty() &&
         !batch_hip(b, hipMemcpyAsync(b->d_big, b->big_list.data(), 4 * b->big_list.size(), hipMemcpyHostToDevice, s),
                    "upload union list"))
@@ -304,19 +298,37 @@ bool enqueue_epilogue(cc_batch *b, int32_t *labels, int cur_round) {
     return true;
 }
 
+// descriptors of the LDS-path graphs, pointing into `labels` (uploaded when it changes)
+bool upload_desc(cc_batch *b, int32_t *labels) {
+    if (b->small_list.empty() || b->desc_labels == labels) return true;
+    b->h_desc.resize(b->small_list.size());
+    for (size_t k = 0; k < b->small_list.size(); ++k) {
+        const int32_t g = b->small_list[k];
+        SmallDesc &d = b->h_desc[k];
+        d.src = b->d_src + b->h_eoff[g];
+        d.dst = b->d_dst + b->h_eoff[g];
+        d.m = b->h_eoff[g + 1] - b->h_eoff[g];
+        d.n = (int32_t)(b->h_voff[g + 1] - b->h_voff[g]);
+        d.status = 0;
+        d.seed = b->h_seeds[g];
+        d.labels = labels + b->h_voff[g];
+        d.rounds = b->d_rounds + g;
+    }
+    if (!batch_hip(b, hipMemcpyAsync(b->d_desc, b->h_desc.data(), sizeof(SmallDesc) * b->h_desc.size(),
+                                     hipMemcpyHostToDevice, b->stream), "upload descriptors") ||
+        !batch_hip(b, hipStreamSynchronize(b->stream), "stream synchronize"))
+        return false;
+    b->desc_labels = labels;
+    return true;
+}
+
 bool enqueue_small(cc_batch *b, int32_t *labels) {
+    (void)labels;
     if (b->small_list.empty()) return true;
     SmallArgs a;
-    a.src = b->d_src;
-    a.dst = b->d_dst;
-    a.voff = b->d_voff64;
-    a.eoff = b->d_eoff64;
-    a.seeds = b->d_seeds_w;
-    a.list = b->d_small;
+    a.desc = b->d_desc;
     a.count = (int32_t)b->small_list.size();
     a.queue = b->d_queue;
-    a.labels = labels;
-    a.rounds = b->d_rounds;
     a.err = &b->w.st->err;
     const int grid = (int)std::min<int64_t>((int64_t)b->cus * std::max(1, b->cfg.small_blocks_per_cu), a.count);
     return batch_hip(b, launch_small(b->cfg.small_variant, b->cfg.small_threads, a, std::max(grid, 1), b->stream),
@@ -454,7 +466,7 @@ cc_status cc_batch_set_workspace(cc_batch *b, void *d_ws, size_t bytes) {
     b->d_voff32 = (uint32_t *)carve(p, 4 * g);
     b->d_seeds_w = (uint64_t *)carve(p, 8 * g);
     b->d_keys = (RoundKey *)carve(p, sizeof(RoundKey) * g);
-    b->d_small = (int32_t *)carve(p, 4 * g);
+    b->d_desc = (SmallDesc *)carve(p, sizeof(SmallDesc) * g);
     b->d_big = (int32_t *)carve(p, 4 * g);
     b->d_rounds = (int32_t *)carve(p, 4 * g);
     b->d_skip = (uint8_t *)carve(p, g);
@@ -516,6 +528,7 @@ cc_status cc_batch_run(cc_batch *b, int32_t *d_labels, int32_t *h_rounds) {
         b->fam_ms[i] = 0.0;
         b->fam_launches[i] = 0;
     }
+    if (!upload_desc(b, d_labels)) return CC_E_HIP;
     int cur_round = 0;
     if (b->cfg.use_graph) {
         if (!b->exec || b->graph_labels != d_labels) {

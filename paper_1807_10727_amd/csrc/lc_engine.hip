@@ -186,9 +186,9 @@ bool Engine::write_initial_state(int64_t n_cur, int64_t m_cur) {
     h_st->n_cur = (u64c)n_cur;
     h_st->m_cur = (u64c)m_cur;
     h_st->map_cap = (u64c)std::max<int64_t>(w.n0, 1);
-    if (!hip_ok(hipMemcpyAsync(w.st, h_st, sizeof(RoundState), hipMemcpyHostToDevice, stream), "state upload"))
-        return false;
-    return hip_ok(hipStreamSynchronize(stream), "stream synchronize");
+    // ordered before every later kernel on the stream; the host buffer is next written by
+    // the state readback of round 0, which the stream also orders after this copy
+    return hip_ok(hipMemcpyAsync(w.st, h_st, sizeof(RoundState), hipMemcpyHostToDevice, stream), "state upload");
 }
 
 int ceil_log2_host(int64_t n) {
@@ -201,18 +201,7 @@ int ceil_log2_host(int64_t n) {
 
 using namespace lc;
 
-struct cc_ctx : public lc::Engine {
-    cc_graph_desc g{};
-    cc_options o{};
-    std::vector<cc_round_stats> stats;
-    int32_t rounds = 0;       // rounds of this solve that had nodes
-    int32_t next_round = 0;   // index of the next round to enqueue
-    bool ran_first = false;   // round 0's kernels ran (map0 is valid)
-    bool labels_ready = false;
-    int64_t n_cur = 0, m_cur = 0;
-};
-
-namespace {
+namespace lc {
 
 // an error that ends the current solve (later calls return it until cc_reset)
 cc_status fail(cc_ctx *c, cc_status s, const char *msg) {
@@ -230,6 +219,10 @@ cc_status reject(cc_ctx *c, cc_status s, const char *msg) {
 }
 
 cc_status hip_status(cc_ctx *c) { return c->failed_status ? c->failed_status : CC_E_HIP; }
+
+}  // namespace lc
+
+namespace {
 
 cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     c->o.seed = seed;
@@ -253,8 +246,14 @@ cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     return CC_OK;
 }
 
-// one round; returns CC_OK, CC_DONE or an error
-cc_status round_once(cc_ctx *c, cc_round_stats *out) {
+}  // namespace
+
+namespace lc {
+
+// Enqueue round `next_round` and the asynchronous readback of the device state (no wait).
+// *launched is 0 when nothing was enqueued (solve finished, or an error was returned).
+cc_status ctx_round_enqueue(cc_ctx *c, int *launched) {
+    *launched = 0;
     if (c->failed_status) return c->failed_status;
     if (!c->ws) return reject(c, CC_E_NOMEM, "no workspace: call cc_set_workspace first");
     if (c->done) return CC_DONE;
@@ -267,8 +266,21 @@ cc_status round_once(cc_ctx *c, cc_round_stats *out) {
     PrioCtx pc{};
     pc.key = round_key(c->o.seed, r);
     if (!c->enqueue_round(r, N, M, pc)) return hip_status(c);
-    if (!c->read_state()) return hip_status(c);
+    if (!c->hip_ok(hipMemcpyAsync(c->h_st, c->w.st, sizeof(RoundState), hipMemcpyDeviceToHost, c->stream),
+                   "state readback"))
+        return hip_status(c);
+    c->pending_N = N;
+    c->pending_M = M;
+    *launched = 1;
+    return CC_OK;
+}
+
+// Consume the state of the round enqueued last (its readback must have completed).
+cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out) {
+    c->ev_collect();
     const RoundState &st = *c->h_st;
+    const int r = c->next_round;
+    const int64_t N = c->pending_N, M = c->pending_M;
     if (st.err & 1u) return fail(c, CC_E_INPUT, "an edge record names a vertex outside [0, n_vertices)");
     if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
     if (r == 0) c->ran_first = true;
@@ -294,6 +306,34 @@ cc_status round_once(cc_ctx *c, cc_round_stats *out) {
     c->rounds = r + 1;
     if (out) *out = s;
     return CC_OK;
+}
+
+cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels) {
+    if (c->g.n_vertices == 0) return CC_OK;
+    const bool out64 = c->g.layout == CC_EDGES_SOA_I64;
+    const int grid = c->grid_for(c->g.n_vertices);
+    c->ev_begin(kCompose);
+    hipError_t e = launch_compose(c->w, !c->ran_first, c->next_round, d_labels, out64, false, nullptr, grid, c->stream);
+    c->ev_end();
+    if (!c->hip_ok(e, "compose")) return CC_E_HIP;
+    if (c->o.flags & CC_CANONICAL) {
+        e = launch_canonical(c->w, d_labels, out64, false, nullptr, grid, c->stream);
+        if (!c->hip_ok(e, "canonical labels")) return CC_E_HIP;
+    }
+    return CC_OK;
+}
+
+}  // namespace lc
+
+namespace {
+
+// one round, synchronously; returns CC_OK, CC_DONE or an error
+cc_status round_once(cc_ctx *c, cc_round_stats *out) {
+    int launched = 0;
+    cc_status s = ctx_round_enqueue(c, &launched);
+    if (!launched) return s;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return hip_status(c);
+    return ctx_round_complete(c, out);
 }
 
 }  // namespace
@@ -388,18 +428,7 @@ cc_status cc_labels(cc_ctx *c, void *d_labels) {
     if (!c || !d_labels) return CC_E_ARG;
     if (c->failed_status) return c->failed_status;
     if (!c->labels_ready) return reject(c, CC_E_STATE, "labels requested before cc_run or CC_DONE");
-    if (c->g.n_vertices == 0) return CC_OK;
-    const bool out64 = c->g.layout == CC_EDGES_SOA_I64;
-    const int grid = c->grid_for(c->g.n_vertices);
-    c->ev_begin(kCompose);
-    hipError_t e = launch_compose(c->w, !c->ran_first, c->next_round, d_labels, out64, false, nullptr, grid, c->stream);
-    c->ev_end();
-    if (!c->hip_ok(e, "compose")) return CC_E_HIP;
-    if (c->o.flags & CC_CANONICAL) {
-        e = launch_canonical(c->w, d_labels, out64, false, nullptr, grid, c->stream);
-        if (!c->hip_ok(e, "canonical labels")) return CC_E_HIP;
-    }
-    return CC_OK;
+    return ctx_labels_enqueue(c, d_labels);
 }
 
 cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {

@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "cc.h"
 #include "lc_internal.hpp"
 
 namespace lc {
@@ -65,4 +66,27 @@ struct Engine {
     bool write_initial_state(int64_t n_cur, int64_t m_cur);
 };
 
+}  // namespace lc
+
+// A single-graph solve behind the C ABI (cc_ctx of include/cc.h).
+struct cc_ctx : public lc::Engine {
+    cc_graph_desc g{};
+    cc_options o{};
+    std::vector<cc_round_stats> stats;
+    int32_t rounds = 0;       // rounds of this solve that had nodes
+    int32_t next_round = 0;   // index of the next round to enqueue
+    bool ran_first = false;   // round 0's kernels ran (map0 is valid)
+    bool labels_ready = false;
+    int64_t n_cur = 0, m_cur = 0;
+    int64_t pending_N = 0, pending_M = 0;   // bounds of the round in flight
+};
+
+namespace lc {
+cc_status fail(cc_ctx *c, cc_status s, const char *msg);
+cc_status reject(cc_ctx *c, cc_status s, const char *msg);
+cc_status hip_status(cc_ctx *c);
+// asynchronous round interface (used by the serving scheduler)
+cc_status ctx_round_enqueue(cc_ctx *c, int *launched);
+cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out);
+cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels);
 }  // namespace lc

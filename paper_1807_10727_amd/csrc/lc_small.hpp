@@ -20,21 +20,37 @@
 
 namespace lc {
 
-struct SmallArgs {
-    const int32_t *src;      // local ids, per-graph record ranges [eoff[g], eoff[g+1])
+// One graph for the LDS solver: records src[i], dst[i] (int32 local ids, i < m), n vertices.
+struct SmallDesc {
+    const int32_t *src;
     const int32_t *dst;
-    const int64_t *voff;     // [G+1] first label slot of each graph
-    const int64_t *eoff;     // [G+1]
-    const uint64_t *seeds;   // [G]
-    const int32_t *list;     // graph ids handled here
+    int64_t m;
+    int32_t n;
+    int32_t status;          // written: 0 ok, 1 an id out of range
+    uint64_t seed;
+    int32_t *labels;         // [n] local labels (written)
+    int32_t *rounds;         // rounds of the graph (written; may be null)
+};
+
+struct SmallArgs {
+    SmallDesc *desc;         // [count]
     int32_t count;
-    uint32_t *queue;         // next list slot (zeroed before the launch)
-    int32_t *labels;         // [sum n] local labels
-    int32_t *rounds;         // [G]
-    uint32_t *err;           // bit 0: an id out of range
+    uint32_t *queue;         // next descriptor (zeroed before the launch)
+    uint32_t *err;           // bit 0 set when any graph had an id out of range
 };
 
 constexpr uint16_t kSmallFinal = 0x8000u;
+
+// Variants of the solver (index 1..3): at most nmax vertices and mmax records per graph.
+struct SmallVariant {
+    int nmax, mmax;
+};
+constexpr SmallVariant kSmallVariants[] = {{0, 0}, {512, 4096}, {1024, 8192}, {2048, 16384}};
+constexpr int kNumSmallVariants = 4;
+
+size_t small_bytes(int variant, int threads);                 // LDS bytes of a variant
+hipError_t prepare_small(int variant, int threads);           // allow its LDS size (outside captures)
+hipError_t launch_small(int variant, int threads, const SmallArgs &a, int grid, hipStream_t s);
 
 template <int kNT, int kNMax, int kMMax>
 struct SmallLds {
@@ -75,18 +91,19 @@ __global__ __launch_bounds__(kNT) void k_small(SmallArgs a) {
         const uint32_t slot = sh_slot;
         __syncthreads();
         if (slot >= (uint32_t)a.count) break;
-        const int32_t g = a.list[slot];
-        const int n = (int)(a.voff[g + 1] - a.voff[g]);
-        const int64_t e0 = a.eoff[g];
-        const int m = (int)(a.eoff[g + 1] - e0);
-        const uint64_t seed = a.seeds[g];
+        SmallDesc *dsc = a.desc + slot;
+        const int n = dsc->n;
+        const int m = (int)dsc->m;
+        const uint64_t seed = dsc->seed;
+        const int32_t *gsrc = dsc->src;
+        const int32_t *gdst = dsc->dst;
 
         // load: loop-free records as (min << 16 | max); everything else ~0u
         if (tid == 0) sh_bad = 0;
         for (int i = tid; i < kMMax; i += kNT) {
             uint32_t v = ~0u;
             if (i < m) {
-                const int32_t x = a.src[e0 + i], y = a.dst[e0 + i];
+                const int32_t x = gsrc[i], y = gdst[i];
                 if ((uint32_t)x < (uint32_t)n && (uint32_t)y < (uint32_t)n) {
                     if (x != y) v = ((uint32_t)min(x, y) << 16) | (uint32_t)max(x, y);
                 } else {
@@ -100,7 +117,10 @@ __global__ __launch_bounds__(kNT) void k_small(SmallArgs a) {
             lab[v] = (uint16_t)v;
         }
         __syncthreads();
-        if (sh_bad && tid == 0) atomicOr(a.err, 1u);
+        if (tid == 0) {
+            dsc->status = sh_bad ? 1 : 0;
+            if (sh_bad) atomicOr(a.err, 1u);
+        }
 
         int N = n;          // nodes of this round (round 0: every id)
         int M = m;          // record slots of this round
@@ -260,12 +280,12 @@ __global__ __launch_bounds__(kNT) void k_small(SmallArgs a) {
             ++r;
             __syncthreads();
         }
-        int32_t *out = a.labels + a.voff[g];
+        int32_t *out = dsc->labels;
         for (int v = tid; v < n; v += kNT) {
             const uint16_t x = lab[v];
             out[v] = (x & kSmallFinal) ? (int32_t)(x & 0x7FFF) : (int32_t)names[x];
         }
-        if (tid == 0) a.rounds[g] = r;
+        if (tid == 0 && dsc->rounds) *dsc->rounds = r;
         __syncthreads();
     }
 }
