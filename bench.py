@@ -163,6 +163,108 @@ def bench_batch(args, log_prefix="batch"):
             "config": cfg}
 
 
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+def bench_serve(args):
+    """Poisson arrivals of requests with vertex counts log-uniform in [2^10, 2^24] (half
+    G(n,m) with average degree U[4,16], half R-MAT with edge factor 16), inputs resident in
+    HBM, served by the continuous-batching server under an HBM budget, against the same
+    trace served FIFO by sequential plain solves (their measured service times)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1807_10727_amd as lc
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    trace = graphgen.request_trace(graphgen.CONFIG_SEED_BASE + 4, args.serve_requests, rate=1.0,
+                                   log2_min=10, log2_max=args.serve_log2_max)
+    reqs = []
+    for r in trace:
+        g = r.graph()
+        reqs.append((r, g.n, torch.from_numpy(g.src.view(np.int32)).to(dev),
+                     torch.from_numpy(g.dst.view(np.int32)).to(dev)))
+        del g
+    total_m = sum(int(x[2].shape[0]) for x in reqs)
+    torch.cuda.synchronize()
+    log("serve: %d requests, %d records, generated and uploaded in %.1fs" % (len(reqs), total_m, time.perf_counter() - t0))
+
+    # sequential plain solves, back to back: service times and reference labels
+    ref = []
+    service = []
+    for (r, n, s, d) in reqs[:min(4, len(reqs))]:          # warm the kernels
+        lc.solve(n, s, d, seed=r.seed)
+    for (r, n, s, d) in reqs:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lab, _, _ = lc.solve(n, s, d, seed=r.seed)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t1)
+        ref.append(lab)
+    cap = len(reqs) / sum(service)
+    log("serve: sequential capacity %.1f requests/s (service p50 %.2f ms, max %.2f ms)"
+        % (cap, 1e3 * _pct(service, 50), 1e3 * max(service)))
+
+    def fifo(arrivals):
+        fin, lat = 0.0, []
+        for a, sv in zip(arrivals, service):
+            fin = max(fin, a) + sv
+            lat.append(fin - a)
+        return lat, fin - arrivals[0]
+
+    base_arr = [r.arrival for (r, _, _, _) in reqs]
+    loads = []
+    identical = True
+    srv = lc.Server(args.serve_budget_gib << 30, n_slots=args.serve_slots, small_variant=1,
+                    max_small_per_launch=256)
+    try:
+        for rho in args.serve_loads:
+            lam = rho * cap
+            arr = [a / lam for a in base_arr]
+            seq_lat, seq_span = fifo(arr)
+            labs = {}
+            t_start = srv.info()["now"]
+            for i, (r, n, s, d) in enumerate(reqs):
+                while srv.info()["now"] - t_start < arr[i] - arr[0]:
+                    time.sleep(0.0002)
+                rid, lab = srv.submit(n, s, d, r.seed)
+                labs[rid] = (i, lab)
+            res = srv.drain()
+            if len(res) != len(reqs) or any(x["status"] != 0 for x in res):
+                raise RuntimeError("serving run lost or failed requests")
+            lat = [x["t_done"] - x["t_submit"] for x in res]
+            span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+            for x in res:
+                i, lab = labs[x["id"]]
+                identical &= bool(torch.equal(lab, ref[i]))
+            loads.append({"load": rho, "lambda_req_per_s": lam,
+                          "p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99),
+                          "graphs_per_s": len(res) / span,
+                          "sequential_p50_ms": 1e3 * _pct(seq_lat, 50), "sequential_p99_ms": 1e3 * _pct(seq_lat, 99),
+                          "sequential_graphs_per_s": len(res) / seq_span,
+                          "small_path": sum(1 for x in res if x["small_path"])})
+            log("serve: load %.1f  p50 %.2f ms  p99 %.2f ms  %.1f graphs/s | sequential p50 %.2f ms  p99 %.2f ms  %.1f graphs/s"
+                % (rho, loads[-1]["p50_ms"], loads[-1]["p99_ms"], loads[-1]["graphs_per_s"],
+                   loads[-1]["sequential_p50_ms"], loads[-1]["sequential_p99_ms"], loads[-1]["sequential_graphs_per_s"]))
+        peak = srv.info()["peak_bytes"]
+    finally:
+        srv.close()
+    del reqs, ref
+    torch.cuda.empty_cache()
+    if not identical:
+        raise RuntimeError("served labels differ from the solo solves")
+    return {"requests": len(base_arr), "records": total_m, "budget_gib": args.serve_budget_gib,
+            "slots": args.serve_slots, "sequential_capacity_req_per_s": cap, "loads": loads,
+            "labels_identical_to_solo": identical, "peak_arena_gib": peak / 2**30}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +281,13 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: none, tune every run)")
     ap.add_argument("--verbose-tune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-log2-max", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=int, default=128)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.2])
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -194,6 +303,9 @@ def main():
 
     if args.batch_only:
         print(json.dumps({"batched": bench_batch(args)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": bench_serve(args)}), flush=True)
         return
 
     dev = torch.device("cuda:0")
@@ -301,6 +413,14 @@ def main():
             log("batched leg failed: %r" % (e,))
             batched = {"error": repr(e)}
 
+    serving = None
+    if not args.no_serve:
+        try:
+            serving = bench_serve(args)
+        except Exception as e:  # the main figure stands on its own
+            log("serving leg failed: %r" % (e,))
+            serving = {"error": repr(e)}
+
     cpu = None
     if not args.no_cpu:
         try:
@@ -327,6 +447,7 @@ def main():
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
