@@ -134,7 +134,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
     const int gscan_n = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), kScanTile), grid_cap);
-    const int nbits = 2 * ceil_log2_host(std::max<int64_t>(N, 2));
+    // key bits: 2 kb plus at most kb - 17 block bits (blocks are >= 2^17 indices wide)
+    const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
+    const int nbits = std::min(64, 2 * kb + std::max(0, kb - 17));
     const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
     const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(M, 1), kSortTile) + 2);
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
@@ -145,6 +147,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     RUN(kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
     RUN(kMin2, launch_min2(w, src, gm, stream));
     RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
+    RUN(kParent, launch_plan_blocks(w, gn, stream));
     RUN(kRelabel, launch_relabel(w, src, gslab, stream));
     for (int p = 0; p < passes; ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));

@@ -31,10 +31,13 @@ struct RoundState {
     int32_t e_sel;     // key buffer that holds E_r (rounds >= 1)
     int32_t done;      // no edge left
     int32_t levels;    // per-round maps in the arena
+    int32_t kb;        // bits per endpoint in this round's sort keys: ceil(log2 N_r)
+    int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (63: one block)
     int32_t pad0_;
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
     alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
+    alignas(128) u64c n_labels;   // distinct parents of this round (atomics)
     alignas(128) uint32_t err;    // bit 0: input id out of range; bit 1: map arena overflow;
                                   // bit 2: internal consistency (atomics)
     alignas(128) u64c m_next;     // distinct edges of the next graph (one workgroup)
@@ -95,6 +98,11 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
+// Sort keys are (block(hi) << 2kb) | (lo << kb) | hi, so the next round reads its edges
+// grouped by the block of their larger endpoint.  A block spans about kBlockNodes next-round
+// nodes: their 8-byte node words (2 MiB) stay resident in one XCD's 4 MiB L2 while the
+// round streams that block's edges, and lo is swept in increasing order within the block.
+constexpr int64_t kBlockNodes = 1 << 18;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -115,6 +123,7 @@ hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool b
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
 hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
+hipError_t launch_plan_blocks(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
                           int grid, hipStream_t s, int stage);

@@ -31,6 +31,7 @@ namespace lc {
 template <int V>
 struct ReadSoa32 {
     static constexpr int kV = V;
+    static constexpr bool kSorted = false;
     const int32_t *s, *d;
     int64_t m;
     uint32_t n;
@@ -67,6 +68,7 @@ struct ReadSoa32 {
 template <int V>
 struct ReadSoa64 {
     static constexpr int kV = V;
+    static constexpr bool kSorted = false;
     const int64_t *s, *d;
     int64_t m;
     uint32_t n;
@@ -103,6 +105,7 @@ struct ReadSoa64 {
 template <int V>
 struct ReadPacked {
     static constexpr int kV = V;
+    static constexpr bool kSorted = false;
     const uint64_t *k;
     int64_t m;
     uint32_t n;
@@ -135,6 +138,7 @@ struct ReadPacked {
 // buffer named by the device state; the count comes from the device state too.
 struct ReadInternal {
     static constexpr int kV = 2;
+    static constexpr bool kSorted = true;   // records ordered by (block of b, a, b): lanes share a
     uint64_t *k0, *k1;
     const uint64_t *k;
     int64_t m;
@@ -176,6 +180,22 @@ __device__ inline uint32_t node_prio(const PrioCtx &pc, const Work &w, const uin
 
 __device__ inline int ceil_log2(uint64_t n) { return n <= 1 ? 0 : 64 - __clzll((long long)(n - 1)); }
 
+// Lanes of a wave reading sorted records hold runs of equal first endpoints.  Combine the
+// values of lanes with equal keys (a min over same-key lanes is a valid update for that key)
+// so that only the last lane of each run touches memory.
+__device__ inline uint32_t run_min(uint32_t key, uint32_t val, bool &last) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t ov = __shfl_up(val, d, kWave);
+        const uint32_t ok = __shfl_up(key, d, kWave);
+        if (lane >= d && ok == key) val = min(val, ov);
+    }
+    const uint32_t nk = __shfl_down(key, 1, kWave);
+    last = lane == kWave - 1 || nk != key;
+    return val;
+}
+
 // ---------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
@@ -188,7 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
         st->m_next = 0;
         st->n_next = 0;
         st->n_final = 0;
-        st->nbits = 2 * ceil_log2(n < 2 ? 2 : (uint64_t)n);
+        st->n_labels = 0;
+        st->kb = ceil_log2(n < 2 ? 2 : (uint64_t)n);
+        st->hb_shift = 63;
+        st->nbits = 2 * st->kb;
     }
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         ((uint64_t *)w.ml)[i] = ~0ull;
@@ -205,24 +228,48 @@ __global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, con
     const int64_t nch = rd.chunks();
     uint32_t *m1 = w.ml;   // one-hop minimum of node x at m1[2x]
     bool bad = false;
-    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
-        uint32_t a[V], b[V], v[V], ca[V], cb[V];
-        rd.read(c, a, b, bad);
+    // grid-stride with a loop bound that is uniform per wave, so the wave shuffles of the
+    // sorted variant always see every lane
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
+        uint32_t a[V], b[V], v[V], ca[V], cb_[V];
+        bool ok[V];
+        if (c < nch) {
+            rd.read(c, a, b, bad);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+        }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            if (a[j] != b[j]) {
+            ok[j] = a[j] != b[j];
+            v[j] = kInf;
+            if (ok[j]) {
                 uint32_t pa = node_prio<kFirst, kBatch>(pc, w, names, gids, a[j]);
                 uint32_t pb = node_prio<kFirst, kBatch>(pc, w, names, gids, b[j]);
                 v[j] = min(pa, pb);
-                ca[j] = m1[2 * (size_t)a[j]];
-                cb[j] = m1[2 * (size_t)b[j]];
+            }
+        }
+        bool la[V];
+        uint32_t va[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            if (R::kSorted) {
+                va[j] = run_min(ok[j] ? a[j] : 0xFFFFFFFFu, v[j], la[j]);
+            } else {
+                va[j] = v[j];
+                la[j] = true;
+            }
+            if (ok[j]) {
+                if (la[j]) ca[j] = m1[2 * (size_t)a[j]];
+                cb_[j] = m1[2 * (size_t)b[j]];
             }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            if (a[j] != b[j]) {
-                if (ca[j] > v[j]) atomicMin(&m1[2 * (size_t)a[j]], v[j]);
-                if (cb[j] > v[j]) atomicMin(&m1[2 * (size_t)b[j]], v[j]);
+            if (ok[j]) {
+                if (la[j] && ca[j] > va[j]) atomicMin(&m1[2 * (size_t)a[j]], va[j]);
+                if (cb_[j] > v[j]) atomicMin(&m1[2 * (size_t)b[j]], v[j]);
             }
         }
     }
@@ -237,22 +284,32 @@ __global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
     const uint64_t *word = (const uint64_t *)w.ml;   // low half: one-hop min, high half: two-hop min
     uint32_t *ml = w.ml;
     bool bad = false;
-    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
         uint32_t a[V], b[V];
         uint64_t wa[V], wb[V];
-        rd.read(c, a, b, bad);
+        bool ok[V];
+        if (c < nch) {
+            rd.read(c, a, b, bad);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+        }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            if (a[j] != b[j]) {
+            ok[j] = a[j] != b[j];
+            if (ok[j]) {
                 wa[j] = word[a[j]];
                 wb[j] = word[b[j]];
             }
         }
 #pragma unroll
         for (int j = 0; j < V; ++j) {
-            if (a[j] != b[j]) {
-                const uint32_t v = min((uint32_t)wa[j], (uint32_t)wb[j]);
-                if ((uint32_t)(wa[j] >> 32) > v) atomicMin(&ml[2 * (size_t)a[j] + 1], v);
+            const uint32_t v = ok[j] ? min((uint32_t)wa[j], (uint32_t)wb[j]) : kInf;
+            bool la = true;
+            const uint32_t va = R::kSorted ? run_min(ok[j] ? a[j] : 0xFFFFFFFFu, v, la) : v;
+            if (ok[j]) {
+                if (la && (uint32_t)(wa[j] >> 32) > va) atomicMin(&ml[2 * (size_t)a[j] + 1], va);
                 if ((uint32_t)(wb[j] >> 32) > v) atomicMin(&ml[2 * (size_t)b[j] + 1], v);
             }
         }
@@ -313,7 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     const int64_t nslabs = ceil_div(rd.records(), kSlab);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->n_slabs = (u64c)nslabs;
     uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
-    const int nb = st->nbits / 2;
+    const int kb = st->kb;
+    const int hbs = st->hb_shift;
     bool bad = false;
     for (int64_t slab = blockIdx.x; slab < nslabs; slab += gridDim.x) {
         const int64_t c_end = min(nch, (slab + 1) * kChunksPerSlab);
@@ -336,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
                 for (int j = 0; j < V; ++j) {
                     keep[j] = pa[j] != pb[j];
                     const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
-                    key[j] = ((uint64_t)lo << nb) | hi;
+                    key[j] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
                     cnt += keep[j];
                 }
             } else {
@@ -356,6 +414,41 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
             if (cursor) atomicAdd(&st->s_count, (u64c)cursor);
         }
     }
+}
+
+// distinct parents of the round (the flags set by k_parent)
+__global__ __launch_bounds__(kThreads) void k_count_labels(Work w) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    uint32_t c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        c += w.is_label[i];
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(&st->n_labels, (u64c)c);
+}
+
+// Block width for the next round's edge order: about kBlockNodes parents per block,
+// assuming parents spread evenly over this round's indices; its bits join the sort key.
+__global__ void k_plan_blocks(Work w) {
+    RoundState *st = w.st;
+    const uint64_t N = st->n_cur, L = st->n_labels;
+    const int kb = st->kb;
+    int shift = 63, hb_bits = 0;
+    if (L > 0 && N > 0) {
+        uint64_t width = (uint64_t)kBlockNodes * N / L;
+        if (width < 1) width = 1;
+        shift = 63 - __clzll((long long)width);              // floor(log2(width))
+        const uint64_t blocks = (N + (1ull << shift) - 1) >> shift;
+        hb_bits = blocks <= 1 ? 0 : ceil_log2(blocks);
+        const int cap = 64 - 2 * kb;
+        if (hb_bits > cap) {
+            hb_bits = cap > 0 ? cap : 0;
+            shift = hb_bits > 0 ? kb - hb_bits : 63;
+        }
+        if (hb_bits == 0) shift = 63;
+    }
+    st->hb_shift = shift;
+    st->nbits = 2 * kb + hb_bits;
 }
 
 template <bool kFirst, bool kBatch>
@@ -406,11 +499,11 @@ __global__ __launch_bounds__(kThreads) void k_rename(Work w) {
     const int t = sorted_sel(st->round, st->e_sel, st->nbits);
     const uint64_t *in = w.keys[1 - t];
     uint64_t *out = w.keys[t];
-    const int nb = st->nbits / 2;
-    const uint64_t mask = (1ull << nb) - 1ull;
+    const int kb = st->kb;
+    const uint64_t mask = (1ull << kb) - 1ull;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads) {
         const uint64_t k = in[i];
-        const uint32_t lo = (uint32_t)(k >> nb), hi = (uint32_t)(k & mask);
+        const uint32_t lo = (uint32_t)((k >> kb) & mask), hi = (uint32_t)(k & mask);
         out[i] = ((uint64_t)w.newidx[lo] << 32) | w.newidx[hi];
     }
 }
@@ -597,6 +690,14 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
             if (e.vec) LC_LAUNCH(k_relabel<ReadPacked<2>>, grid, ReadPacked<2>(e), w);
             LC_LAUNCH(k_relabel<ReadPacked<1>>, grid, ReadPacked<1>(e), w);
     }
+}
+
+hipError_t launch_plan_blocks(const Work &w, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_labels, dim3(grid), dim3(kThreads), 0, s, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_blocks, dim3(1), dim3(1), 0, s, w);
+    return hipGetLastError();
 }
 
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s) {

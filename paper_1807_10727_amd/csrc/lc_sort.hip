@@ -173,8 +173,15 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(Work w, int pass) {
             const int it = j * kThreads + threadIdx.x;
             const bool valid = it < tv;
             const uint32_t d = valid ? (uint32_t)(in[tile * kSortTile + it] >> shift) & (kRadix - 1) : 0u;
-            const uint64_t peers = match_bits<kRadixBits>(d, ballot(valid));
-            if (valid && is_leader(peers)) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
+            const uint64_t act = ballot(valid);
+            if (!act) continue;
+            const int first = __ffsll((long long)act) - 1;
+            const uint32_t d0 = __shfl(d, first, kWave);
+            if (ballot(valid && d == d0) == act) {
+                if (lane_id() == first) atomicAdd(&hist[d0], (uint32_t)__popcll(act));
+            } else if (valid) {
+                atomicAdd(&hist[d], 1u);
+            }
         }
         __syncthreads();
         w.counts[(int64_t)threadIdx.x * tl.ntiles + tile] = hist[threadIdx.x];
@@ -296,8 +303,8 @@ __global__ __launch_bounds__(kThreads) void k_unique_write(Work w) {
     const int t = sorted_sel(st->round, st->e_sel, st->nbits);
     const uint64_t *in = w.keys[t];
     uint64_t *out = w.keys[1 - t];
-    const int nb = st->nbits / 2;
-    const uint64_t mask = (1ull << nb) - 1ull;
+    const int kb = st->kb;
+    const uint64_t mask = (1ull << kb) - 1ull;
     const uint64_t n_cur = st->n_cur;
     bool broken = false;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_unique_write(Work w) {
         for (int j = 0; j < kSortItems; ++j) {
             if (heads >> j & 1u) {
                 out[off++] = k[j];
-                const uint64_t lo = k[j] >> nb, hi = k[j] & mask;
+                const uint64_t lo = (k[j] >> kb) & mask, hi = k[j] & mask;
                 if (lo < n_cur && hi < n_cur) {
                     w.has_edge[lo] = 1;
                     w.has_edge[hi] = 1;
