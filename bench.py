@@ -22,6 +22,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+# kernel symbol (as rocprofv3 prints it) of each timed family of the int32 input path
+FAMILY_SYMBOL = {
+    "min1_round0": "lc::k_min1<lc::ReadSoa32<4>, true, false>",
+    "min2_round0": "lc::k_min2<lc::ReadSoa32<4> >",
+    "relabel_round0": "lc::k_relabel<lc::ReadSoa32<4> >",
+    "min1": "lc::k_min1<lc::ReadInternal, false, false>",
+    "min2": "lc::k_min2<lc::ReadInternal>",
+    "relabel": "lc::k_relabel<lc::ReadInternal>",
+    "sort_hist": "lc::k_sort_hist",
+    "sort_scatter": "lc::k_sort_scatter",
+    "compose": "lc::k_compose<false, false>",
+}
 
 
 def log(*a):
@@ -51,11 +64,13 @@ def family_bytes(stats, n0):
         N = n0 if r == 0 else n_active
         M = m_in
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8
+        sfx = "_round0" if r == 0 else ""
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
-        add("min1", 8 * M + 4 * N)                 # records in, m1 out once
-        add("min2", 8 * M + 8 * N)                 # records in, m1 in once, lv out once
+        add("min1" + sfx, 8 * M + 4 * N)           # records in, m1 out once
+        add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
         add("parent", 8 * N)                       # lv in, parent out
-        add("relabel", 8 * M + 4 * N + 8 * s)      # records in, parents in once, survivor keys out
+        add("plan_blocks", N)                      # parent flags in
+        add("relabel" + sfx, 8 * M + 4 * N + 8 * s)   # records in, parents in once, survivor keys out
         add("sort_hist", 8 * s * P)                # keys in per pass
         add("sort_scatter", 16 * s * P)            # keys in and out per pass
         add("unique", 16 * s + 8 * m_out)          # sorted keys read twice, unique keys out
@@ -335,6 +350,13 @@ def main():
     n0, m0 = g.n, int(src.shape[0])
     torch.cuda.synchronize()
 
+    # calibration copy for the HBM traffic counters: one plain 1 GiB device-to-device copy
+    cal_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cal_b = torch.empty_like(cal_a)
+    cal_b.copy_(cal_a)
+    torch.cuda.synchronize()
+    del cal_a, cal_b
+
     flags = 0 if args.no_profile else lc.CC_PROFILE
     stream = torch.cuda.current_stream(dev)
     base_seed = graphgen.CONFIG_SEED_BASE + 1
@@ -392,8 +414,13 @@ def main():
         avg_launch_s = fam_ms[dom] * 1e-3 / fam_n[dom]
         bytes_per_launch = fam_bytes[dom] / fam_n[dom]
         achieved = bytes_per_launch / avg_launch_s / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        traffic = None
+        if dom in FAMILY_SYMBOL and args.workload == "er_paths":
+            from paper_1807_10727_amd import profiling
+            traffic = profiling.load_traffic(TRAFFIC_FILE, FAMILY_SYMBOL[dom])
+        roofline = {"bound": "hbm", "kernel": dom, "symbol": FAMILY_SYMBOL.get(dom), "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else int(traffic),
                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_s * 1e6, 2)}
         kernel_ms = sum(fam_ms.values()) / args.steps
         log("sum of kernel time per step %.3f ms of %.3f ms wall" % (kernel_ms, ms_per_step))

@@ -13,8 +13,8 @@
 namespace lc {
 
 enum Family {
-    kRoundBegin = 0, kMin1, kMin2, kParent, kRelabel, kSortHist, kSortScan, kSortScatter, kUnique, kNodeScan,
-    kNodes, kMap, kRename, kRoundEnd, kCompose, kFlatten, kFamilies
+    kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kPlanBlocks, kRelabelIn, kRelabel, kSortHist,
+    kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRename, kRoundEnd, kCompose, kFlatten, kFamilies
 };
 extern const char *const kFamilyNames[kFamilies];
 
