@@ -34,6 +34,13 @@ FAMILY_SYMBOL = {
     "sort_hist": "lc::k_sort_hist",
     "sort_scatter": "lc::k_sort_scatter",
     "compose": "lc::k_compose<false, false>",
+    "part_a_hist": "lc::k_part_a_hist<lc::ReadSoa32<4> >",
+    "part_a_scatter": "lc::k_part_a_scatter<lc::ReadSoa32<4> >",
+    "part_b_hist": "lc::k_part_b_hist",
+    "part_b_scatter": "lc::k_part_b_scatter",
+    "min1_tiled": "lc::k_tiled_min<1>",
+    "min2_tiled": "lc::k_tiled_min<2>",
+    "relabel_tiled": "lc::k_tiled_relabel",
 }
 
 
@@ -48,13 +55,14 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0):
+def family_bytes(stats, n0, tiled=False, loops=0):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
     M' = distinct edges out, P = radix passes.  Random-access amplification (cache-line
     reads for 4-byte gathers and atomics, extra sort passes) is implementation overhead
-    and deliberately not counted."""
+    and deliberately not counted.  With the tiled round 0, T = 2 (M - loops) directed
+    records are written once, re-read by the row pass and read by each row kernel."""
     fam = {}
 
     def add(k, v):
@@ -66,11 +74,21 @@ def family_bytes(stats, n0):
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8
         sfx = "_round0" if r == 0 else ""
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
-        add("min1" + sfx, 8 * M + 4 * N)           # records in, m1 out once
-        add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
-        add("parent", 8 * N)                       # lv in, parent out
         add("plan_blocks", N)                      # parent flags in
-        add("relabel" + sfx, 8 * M + 4 * N + 8 * s)   # records in, parents in once, survivor keys out
+        if r == 0 and tiled:
+            T = 2 * (M - loops)
+            add("part_a_hist", 8 * M)              # records in
+            add("part_a_scatter", 8 * M + 8 * T)   # records in, directed records out
+            add("part_b_hist", 8 * T)
+            add("part_b_scatter", 16 * T)
+            add("min1_tiled", 8 * T + 4 * N)       # directed records in, m1 out
+            add("min2_tiled", 8 * T + 8 * N)       # directed records in, m1 in once, parent out
+            add("relabel_tiled", 8 * T + 4 * N + 8 * s)   # directed records, parents once, survivors
+        else:
+            add("min1" + sfx, 8 * M + 4 * N)           # records in, m1 out once
+            add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
+            add("parent", 8 * N)                       # lv in, parent out
+            add("relabel" + sfx, 8 * M + 4 * N + 8 * s)   # records in, parents in once, survivor keys out
         add("sort_hist", 8 * s * P)                # keys in per pass
         add("sort_scatter", 16 * s * P)            # keys in and out per pass
         add("unique", 16 * s + 8 * m_out)          # sorted keys read twice, unique keys out
@@ -287,6 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="er_paths", choices=["er_paths", "small", "rmat26", "rmat24"])
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--round0", default="auto", choices=["auto", "direct", "tiled"],
+                    help="how round 0 reads the input records (auto: the library's choice by size)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-shrink", type=int, default=8)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode leg")
@@ -306,8 +326,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the sharding "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -346,6 +366,7 @@ def main():
         src = torch.from_numpy(g.src.view(np.int32)).to(dev)
         dst = torch.from_numpy(g.dst.view(np.int32)).to(dev)
         layout = lc.CC_EDGES_SOA_I32
+    loops = int(np.count_nonzero(g.src == g.dst))
     del g.src, g.dst
     n0, m0 = g.n, int(src.shape[0])
     torch.cuda.synchronize()
@@ -358,6 +379,7 @@ def main():
     del cal_a, cal_b
 
     flags = 0 if args.no_profile else lc.CC_PROFILE
+    flags |= {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED}[args.round0]
     stream = torch.cuda.current_stream(dev)
     base_seed = graphgen.CONFIG_SEED_BASE + 1
     labels = torch.empty(n0, dtype=torch.int32, device=dev)
@@ -398,7 +420,7 @@ def main():
     # algorithmic bytes per family over the timed steps
     fam_bytes = {}
     for st in all_stats:
-        for k, v in family_bytes(st, n0).items():
+        for k, v in family_bytes(st, n0, tiled=fam_n.get("min1_tiled", 0) > 0, loops=loops).items():
             fam_bytes[k] = fam_bytes.get(k, 0) + v
     job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
 
@@ -469,7 +491,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": wname, "n_vertices": n0, "n_records": m0, "rounds": rounds[0],
-                   "parallelism": "single GPU"},
+                   "round0": args.round0, "parallelism": "single GPU"},
         "roofline": roofline,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,

@@ -79,16 +79,27 @@ typedef struct {
     const void *dst;     /* d_: see cc_edge_layout */
 } cc_graph_desc;
 
-/* cc_options.flags */
+/* cc_options.flags
+ *
+ * Round 0 reads the caller's records in one of two ways, with identical results.  Direct:
+ * the min and relabel passes read the input records as they are.  Tiled: the input is first
+ * partitioned into directed records grouped by blocks of their endpoints, so that those
+ * passes touch node values that stay on chip; the key buffers then hold twice the records
+ * (cc_workspace_size grows by 16 bytes per record) and n_vertices must be at most 2^26.
+ * Without either flag, a solve runs tiled when n_vertices and n_edges are both at least
+ * 2^20 and n_vertices is at most 2^26.  Setting both flags, or CC_ROUND0_TILED with more
+ * than 2^26 vertices, makes cc_create return CC_E_ARG. */
 enum {
-    CC_CANONICAL = 1u << 0,  /* cc_labels writes the smallest original id of each component */
-    CC_PROFILE = 1u << 1     /* time every kernel with HIP events (see cc_kernel_times) */
+    CC_CANONICAL = 1u << 0,     /* cc_labels writes the smallest original id of each component */
+    CC_PROFILE = 1u << 1,       /* time every kernel with HIP events (see cc_kernel_times) */
+    CC_ROUND0_DIRECT = 1u << 2, /* round 0 reads the input records directly */
+    CC_ROUND0_TILED = 1u << 3   /* round 0 over the tiled record layout */
 };
 
 typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
     int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
-    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE */
+    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED */
     void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
 } cc_options;
 

@@ -17,11 +17,12 @@ from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_bat
 from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
-                  CC_PROFILE, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
+                  CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
                   cc_kernel_family_names, cc_kernel_times, cc_labels, cc_last_error, cc_reset, cc_round_parents,
                   cc_run, cc_set_workspace, cc_version, cc_workspace_size)
 
-__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "cc_version"]
+__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "CC_ROUND0_DIRECT",
+           "CC_ROUND0_TILED", "cc_version"]
 
 
 def _torch():

@@ -25,6 +25,8 @@ STATUS_NAMES = {0: "CC_OK", 1: "CC_DONE", -1: "CC_E_ARG", -2: "CC_E_INPUT", -3: 
 CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_EDGES_PACKED_U64 = 0, 1, 2
 CC_CANONICAL = 1 << 0
 CC_PROFILE = 1 << 1
+CC_ROUND0_DIRECT = 1 << 2
+CC_ROUND0_TILED = 1 << 3
 
 
 class cc_graph_desc(ctypes.Structure):

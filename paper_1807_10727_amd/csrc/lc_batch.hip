@@ -444,7 +444,7 @@ cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int6
             return CC_E_NOMEM;
         }
     }
-    b->ws_need = plan_workspace(n0, m0, true, nullptr, nullptr) + batch_extra_bytes(n_graphs);
+    b->ws_need = plan_workspace(n0, m0, true, false, nullptr, nullptr) + batch_extra_bytes(n_graphs);
     *out = b;
     return CC_OK;
 }
@@ -461,7 +461,7 @@ cc_status cc_batch_set_workspace(cc_batch *b, void *d_ws, size_t bytes) {
     if ((uintptr_t)d_ws % 256 != 0) return bfail(b, CC_E_ARG, "workspace must be 256-byte aligned");
     const int64_t n0 = b->h_voff[b->G];
     const int64_t m0 = b->h_eoff[b->G];
-    size_t off = plan_workspace(n0, m0, true, (char *)d_ws, &b->w);
+    size_t off = plan_workspace(n0, m0, true, false, (char *)d_ws, &b->w);
     char *p = (char *)d_ws + off;
     const size_t g = (size_t)b->G + 1;
     b->d_voff64 = (int64_t *)carve(p, 8 * g);

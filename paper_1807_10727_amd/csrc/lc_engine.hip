@@ -24,17 +24,34 @@ namespace lc {
 const char *const kFamilyNames[kFamilies] = {
     "round_begin", "min1_round0", "min1",      "min2_round0", "min2",      "parent",    "plan_blocks",
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
-    "nodes",       "map",         "rename",    "round_end",   "compose",   "flatten"};
+    "nodes",       "map",         "rename",    "round_end",   "compose",   "flatten",
+    "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
+    "relabel_tiled"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
+bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags) {
+    if (flags & CC_ROUND0_DIRECT) return false;
+    if (!tiled_fits(n0)) return false;
+    if (flags & CC_ROUND0_TILED) return true;
+    return n0 >= kTiledMinVertices && m0 >= kTiledMinVertices;
+}
+
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w) {
     const size_t n = (size_t)std::max<int64_t>(n0, 1);
     const size_t m = (size_t)std::max<int64_t>(m0, 2);
-    const size_t tiles = (size_t)ceil_div((int64_t)m, kSortTile) + 2;
-    const size_t slabs = (size_t)ceil_div((int64_t)m, kSlab) + 1;
+    // records a key buffer holds: the tiled round 0 keeps two directed records per input
+    const size_t mk = tiled ? 2 * m : m;
+    const size_t tiles = (size_t)ceil_div((int64_t)mk, kSortTile) + 2;
+    const size_t slabs = (size_t)ceil_div((int64_t)mk, kSlab) + 1;
+    size_t count_entries = kRadix * tiles;
+    if (tiled) {
+        const TPlan tp = tiled_plan(n0, m0);
+        count_entries = std::max(count_entries, (size_t)256 * (size_t)tp.tiles_a);
+        count_entries = std::max(count_entries, (size_t)tp.rows * (size_t)tp.tiles_b);
+    }
     const size_t parts = std::max<size_t>((size_t)ceil_div((int64_t)n, kScanTile),
-                                          (size_t)ceil_div((int64_t)(kRadix * tiles), kScanTile)) + 16;
+                                          (size_t)ceil_div((int64_t)count_entries, kScanTile)) + 16;
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
@@ -58,9 +75,9 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w) {
         t.gids[1] = (uint32_t *)take(4 * n);
         t.gid0 = (uint32_t *)take(4 * n);
     }
-    t.keys[0] = (uint64_t *)take(8 * m);
-    t.keys[1] = (uint64_t *)take(8 * m);
-    t.counts = (uint32_t *)take(4 * kRadix * tiles);
+    t.keys[0] = (uint64_t *)take(8 * mk);
+    t.keys[1] = (uint64_t *)take(8 * mk);
+    t.counts = (uint32_t *)take(4 * count_entries);
     t.tile_cnt = (uint32_t *)take(4 * tiles + 64);
     t.slab_cnt = (uint32_t *)take(4 * slabs + 64);
     t.partials = (uint32_t *)take(4 * parts);
@@ -140,17 +157,39 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = std::min(64, 2 * kb + std::max(0, kb - 17));
     const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
-    const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(M, 1), kSortTile) + 2);
+    // the tiled round 0 hands the first radix pass up to twice as many slab tiles
+    const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(first && tiled ? 2 * M : M, 1), kSortTile) + 2);
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 
     RUN(kRoundBegin, launch_round_begin(w, gn, stream));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
-    RUN(first ? kMin1In : kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
-    RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
-    RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
-    RUN(kPlanBlocks, launch_plan_blocks(w, gn, stream));
-    RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
+    if (first && tiled) {
+        const int ga = (int)std::min<int64_t>(tp.tiles_a, grid_cap);
+        const int gb = (int)std::min<int64_t>(tp.tiles_b, grid_cap);
+        const int gsa = (int)std::min<int64_t>(ceil_div(256 * tp.tiles_a, kScanTile), grid_cap);
+        const int gsb = (int)std::min<int64_t>(ceil_div((int64_t)tp.rows * tp.tiles_b, kScanTile), grid_cap);
+        RUN(kPartAHist, launch_tiled_partition(w, in, tp, ga, stream, 0));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 1));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 2));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 3));
+        RUN(kPartAScatter, launch_tiled_partition(w, in, tp, ga, stream, 4));
+        RUN(kPartBHist, launch_tiled_partition(w, in, tp, gb, stream, 5));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 6));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 7));
+        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 8));
+        RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
+        RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream));
+        RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
+        RUN(kPlanBlocks, launch_plan_blocks(w, gn, stream));
+        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
+    } else {
+        RUN(first ? kMin1In : kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
+        RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
+        RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
+        RUN(kPlanBlocks, launch_plan_blocks(w, gn, stream));
+        RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
+    }
     for (int p = 0; p < passes; ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
         RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 1));
@@ -354,6 +393,8 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if (g.layout < CC_EDGES_SOA_I32 || g.layout > CC_EDGES_PACKED_U64 || g.reserved != 0) return CC_E_ARG;
     if (g.n_edges > 0 && (!g.src || (g.layout != CC_EDGES_PACKED_U64 && !g.dst))) return CC_E_ARG;
     if (opts->max_rounds < 0) return CC_E_ARG;
+    if ((opts->flags & CC_ROUND0_DIRECT) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
+    if ((opts->flags & CC_ROUND0_TILED) && g.n_vertices > 0 && !tiled_fits(g.n_vertices)) return CC_E_ARG;
     cc_ctx *c = new (std::nothrow) cc_ctx();
     if (!c) return CC_E_NOMEM;
     c->g = g;
@@ -381,7 +422,9 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
             return CC_E_NOMEM;
         }
     }
-    c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, nullptr, nullptr);
+    c->tiled = choose_tiled(g.n_vertices, g.n_edges, opts->flags);
+    c->tp = tiled_plan(g.n_vertices, g.n_edges);
+    c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, c->tiled, nullptr, nullptr);
     *out = c;
     return CC_OK;
 }
@@ -398,7 +441,7 @@ cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
     if ((uintptr_t)d_ws % 256 != 0) return reject(c, CC_E_ARG, "workspace must be 256-byte aligned");
     c->ws = d_ws;
     c->ws_bytes = bytes;
-    plan_workspace(c->g.n_vertices, c->g.n_edges, false, (char *)d_ws, &c->w);
+    plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)d_ws, &c->w);
     return reset_solve(c, c->o.seed);
 }
 

@@ -14,12 +14,17 @@ namespace lc {
 
 enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kPlanBlocks, kRelabelIn, kRelabel, kSortHist,
-    kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRename, kRoundEnd, kCompose, kFlatten, kFamilies
+    kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRename, kRoundEnd, kCompose, kFlatten,
+    kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
+    kFamilies
 };
 extern const char *const kFamilyNames[kFamilies];
 
-// Lays the workspace out from `base` (or only sizes it when base is null).
-size_t plan_workspace(int64_t n0, int64_t m0, bool batch, char *base, Work *w);
+// Lays the workspace out from `base` (or only sizes it when base is null).  `tiled`: round 0
+// runs over the tiled record layout, whose two key buffers hold twice the input records.
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w);
+// Whether a plain solve of this size with these cc_options flags runs round 0 tiled.
+bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags);
 int ceil_log2_host(int64_t n);
 
 struct Engine {
@@ -27,6 +32,8 @@ struct Engine {
     Work w{};
     EdgeIn in{};
     bool batch = false;
+    bool tiled = false;           // round 0 over the tiled record layout
+    TPlan tp{};
     bool profile = false;
     bool done = false;
     int grid_cap = 2048;

@@ -34,6 +34,7 @@ struct RoundState {
     int32_t kb;        // bits per endpoint in this round's sort keys: ceil(log2 N_r)
     int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (63: one block)
     int32_t pad0_;
+    u64c t_count;      // round 0, tiled layout: directed records (twice the loop-free inputs)
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
     alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
@@ -113,7 +114,46 @@ __host__ __device__ inline int sorted_sel(int round, int e_sel, int nbits) {
     return sort_src(round, e_sel) ^ (npasses(nbits) & 1);
 }
 
-// ---- launchers (lc_kernels.hip, lc_sort.hip) ------------------------------------------
+// Round 0 over the tiled record layout (lc_tiled.hip).  The input is partitioned once into
+// directed records (x << 32 | y), two per loop-free input record, grouped by the row block
+// x >> xs and, within a row, by the column block y >> ys.  One workgroup owns a row: the
+// row's node values live in LDS, and the rows that run at the same time sweep the column
+// blocks in the same order, so the values gathered at y stay resident in L2.
+struct TPlan {
+    int32_t xs, ys;      // row / column block shifts
+    int32_t rows, cols;  // row blocks (<= kTRowsMax), column blocks (<= 256)
+    int64_t tiles_a;     // partition pass A: tiles of kTaIn input records
+    int64_t tiles_b;     // partition pass B: upper bound of its kTbTile-record tiles
+};
+constexpr int kTxShiftMax = 15;            // 2^15 four-byte node values: 128 KiB of LDS
+constexpr int kTRowsMax = 2048;            // row digit of at most 11 bits
+constexpr int kTaIn = 2048;                // input records per pass-A tile
+constexpr int kTbThreads = 512;
+constexpr int kTbTile = 16 * kTbThreads;   // directed records per pass-B tile
+constexpr int kTRowThreads = 1024;         // workgroup of the per-row kernels
+constexpr int64_t kTiledMinVertices = 1 << 20;   // default: tiled round 0 from 2^20 ids and records
+
+__host__ __device__ inline int ceil_log2_i64(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << b) < n) ++b;
+    return b;
+}
+
+inline TPlan tiled_plan(int64_t n, int64_t m) {
+    TPlan p{};
+    const int lg = ceil_log2_i64(n < 2 ? 2 : n);
+    p.xs = lg - 8 < 0 ? 0 : (lg - 8 > kTxShiftMax ? kTxShiftMax : lg - 8);
+    p.ys = lg - 8 < 0 ? 0 : lg - 8;
+    p.rows = (int32_t)ceil_div(n < 1 ? 1 : n, (int64_t)1 << p.xs);
+    p.cols = (int32_t)ceil_div(n < 1 ? 1 : n, (int64_t)1 << p.ys);
+    p.tiles_a = ceil_div(m < 1 ? 1 : m, kTaIn);
+    p.tiles_b = ceil_div(2 * (m < 1 ? 1 : m), kTbTile);
+    return p;
+}
+
+inline bool tiled_fits(int64_t n) { return n >= 1 && tiled_plan(n, 1).rows <= kTRowsMax; }
+
+// ---- launchers (lc_kernels.hip, lc_sort.hip, lc_tiled.hip) ------------------------------------------
 // `grid` arguments are workgroup counts chosen by the host (grid-stride loops cover the
 // rest); every kernel reads its true element count from RoundState.
 
@@ -142,6 +182,13 @@ hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch,
 hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int grid, hipStream_t s);
 hipError_t launch_batch_keys(const Work &w, RoundKey *keys, const uint64_t *seeds, int32_t n_graphs, hipStream_t s);
 hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s);
+// Tiled round 0.  Partition stages: 0 = pass-A counts, 1..3 = their scan (total ->
+// t_count), 4 = pass-A scatter, 5 = pass-B counts, 6..8 = their scan, 9 = pass-B scatter.
+hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &tp, int grid, hipStream_t s,
+                                  int stage);
+hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s);
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s);
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
 // Sort stages: 0 = digit counts, 1..3 = scan of the counts, 4 = scatter.

@@ -1,0 +1,152 @@
+// Edge-record readers shared by the round kernels: each yields the records of a chunk as
+// endpoint pairs, turning out-of-range and padding records into loops that every kernel
+// skips.
+#pragma once
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------------------
+// edge readers: each thread handles a chunk of kV consecutive records.  Records that are
+// out of range or past the end come back as a loop (a == b), which every kernel skips.
+// ---------------------------------------------------------------------------------------
+
+template <int V>
+struct ReadSoa32 {
+    static constexpr int kV = V;
+    static constexpr bool kSorted = false;
+    const int32_t *s, *d;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadSoa32(const EdgeIn &e)
+        : s((const int32_t *)e.s), d((const int32_t *)e.d), m(e.m), n(e.n) {}
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        int32_t sa[V], sb[V];
+        if (V == 4 && base + 4 <= m) {
+            int4 x = *(const int4 *)(s + base);
+            int4 y = *(const int4 *)(d + base);
+            sa[0] = x.x; sa[1 % V] = x.y; sa[2 % V] = x.z; sa[3 % V] = x.w;
+            sb[0] = y.x; sb[1 % V] = y.y; sb[2 % V] = y.z; sb[3 % V] = y.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                sa[j] = base + j < m ? s[base + j] : 0;
+                sb[j] = base + j < m ? d[base + j] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            bool ok = (uint32_t)sa[j] < n && (uint32_t)sb[j] < n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? (uint32_t)sa[j] : 0u;
+            b[j] = ok ? (uint32_t)sb[j] : 0u;
+        }
+    }
+};
+
+template <int V>
+struct ReadSoa64 {
+    static constexpr int kV = V;
+    static constexpr bool kSorted = false;
+    const int64_t *s, *d;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadSoa64(const EdgeIn &e)
+        : s((const int64_t *)e.s), d((const int64_t *)e.d), m(e.m), n(e.n) {}
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        int64_t sa[V], sb[V];
+        if (V == 2 && base + 2 <= m) {
+            longlong2 x = *(const longlong2 *)(s + base);
+            longlong2 y = *(const longlong2 *)(d + base);
+            sa[0] = x.x; sa[1 % V] = x.y;
+            sb[0] = y.x; sb[1 % V] = y.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                sa[j] = base + j < m ? s[base + j] : 0;
+                sb[j] = base + j < m ? d[base + j] : 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            bool ok = (uint64_t)sa[j] < (uint64_t)n && (uint64_t)sb[j] < (uint64_t)n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? (uint32_t)sa[j] : 0u;
+            b[j] = ok ? (uint32_t)sb[j] : 0u;
+        }
+    }
+};
+
+template <int V>
+struct ReadPacked {
+    static constexpr int kV = V;
+    static constexpr bool kSorted = false;
+    const uint64_t *k;
+    int64_t m;
+    uint32_t n;
+    __host__ explicit ReadPacked(const EdgeIn &e) : k((const uint64_t *)e.s), m(e.m), n(e.n) {}
+    __device__ void init(const RoundState *) {}
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + V - 1) / V; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &bad) const {
+        const int64_t base = c * V;
+        uint64_t r[V];
+        if (V == 2 && base + 2 <= m) {
+            ulonglong2 x = *(const ulonglong2 *)(k + base);
+            r[0] = x.x; r[1 % V] = x.y;
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) r[j] = base + j < m ? k[base + j] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            uint32_t x = (uint32_t)(r[j] >> 32), y = (uint32_t)r[j];
+            bool ok = x < n && y < n;
+            bad |= (base + j < m) && !ok;
+            a[j] = ok ? x : 0u;
+            b[j] = ok ? y : 0u;
+        }
+    }
+};
+
+// Edges of rounds >= 1: (a << 32 | b) in the round's compact index space, in the key
+// buffer named by the device state; the count comes from the device state too.
+struct ReadInternal {
+    static constexpr int kV = 2;
+    static constexpr bool kSorted = true;   // records ordered by (block of b, a, b): lanes share a
+    uint64_t *k0, *k1;
+    const uint64_t *k;
+    int64_t m;
+    __host__ explicit ReadInternal(const Work &w) : k0(w.keys[0]), k1(w.keys[1]), k(nullptr), m(0) {}
+    __device__ void init(const RoundState *st) {
+        k = st->e_sel ? k1 : k0;
+        m = (int64_t)st->m_cur;
+    }
+    __device__ int64_t records() const { return m; }
+    __device__ int64_t chunks() const { return (m + 1) / 2; }
+    __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &) const {
+        const int64_t base = c * 2;
+        uint64_t r0, r1;
+        if (base + 2 <= m) {
+            ulonglong2 x = *(const ulonglong2 *)(k + base);
+            r0 = x.x;
+            r1 = x.y;
+        } else {
+            r0 = k[base];
+            r1 = 0ull;
+        }
+        a[0] = (uint32_t)(r0 >> 32); b[0] = (uint32_t)r0;
+        a[1] = (uint32_t)(r1 >> 32); b[1] = (uint32_t)r1;
+    }
+};
+
+}  // namespace lc

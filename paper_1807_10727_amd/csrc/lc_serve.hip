@@ -480,7 +480,9 @@ cc_status cc_server_submit(cc_server *s, const cc_graph_desc *g, uint64_t seed, 
     r->seed = seed;
     r->labels = d_labels;
     r->small = small_ok(s, *g);
-    r->footprint = r->small ? 0 : plan_workspace(g->n_vertices, g->n_edges, false, nullptr, nullptr);
+    r->footprint = r->small ? 0
+                            : plan_workspace(g->n_vertices, g->n_edges, false,
+                                             choose_tiled(g->n_vertices, g->n_edges, 0), nullptr, nullptr);
     if (r->footprint > s->budget) {
         delete r;
         std::lock_guard<std::mutex> lk(s->mu);

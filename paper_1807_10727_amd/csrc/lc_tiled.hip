@@ -1,0 +1,480 @@
+// Round 0 of LocalContraction over a tiled layout of the input records.
+//
+// The first round reads the raw input, whose endpoints are uniformly scattered over the
+// whole id space: every per-record access to a node value misses L2 and costs a full
+// cache line.  This file first partitions the input, once, into directed records
+// (x << 32 | y), two per loop-free input record, grouped by the row block x >> xs and,
+// inside a row, by the column block y >> ys (two counting passes: pass A by column into
+// one key buffer, pass B by row into the other; the order inside a tile is free).  Then:
+//
+//   min1     one workgroup per row: LDS minimum of rho(y) over the row's records, folded
+//            with rho(x); no global atomics (Section 2: x is in its own neighbourhood)
+//   min2     the same with the gathered one-hop minimum m1[y], folded with m1[x], and the
+//            parent written directly (the node whose priority is the two-hop minimum)
+//   relabel  every record with x < y becomes (p(x), p(y)); loops are dropped; survivors go
+//            to fixed output slabs, as the first radix pass expects
+//
+// Rows that run at the same time sweep the column blocks in the same order, so the values
+// gathered at y come from one or two column blocks per XCD, resident in its L2.
+
+#include "lc_internal.hpp"
+#include "lc_readers.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------------------
+// partition pass A: input records -> directed records ordered by column block
+// ---------------------------------------------------------------------------------------
+
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_part_a_hist(R rd, Work w, TPlan tp) {
+    constexpr int V = R::kV;
+    constexpr int kIter = kTaIn / (V * kThreads);
+    static_assert(kIter * V * kThreads == kTaIn, "pass-A tile must be whole reader chunks");
+    static_assert(kThreads == 256, "one column digit per thread");
+    RoundState *st = w.st;
+    __shared__ uint32_t hist[256];
+    rd.init(st);
+    const int64_t nt = tp.tiles_a;
+    const int64_t nch = rd.chunks();
+    const int ys = tp.ys;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)256 * (u64c)nt;
+    bool bad = false;
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        hist[threadIdx.x] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int64_t c = tile * (kTaIn / V) + (int64_t)it * kThreads + threadIdx.x;
+            if (c < nch) {
+                uint32_t a[V], b[V];
+                rd.read(c, a, b, bad);
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    if (a[j] != b[j]) {
+                        atomicAdd(&hist[b[j] >> ys], 1u);
+                        atomicAdd(&hist[a[j] >> ys], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        w.counts[(int64_t)threadIdx.x * nt + tile] = hist[threadIdx.x];
+        __syncthreads();
+    }
+    if (bad) atomicOr(&st->err, 1u);
+}
+
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_part_a_scatter(R rd, Work w, TPlan tp) {
+    constexpr int V = R::kV;
+    constexpr int kIter = kTaIn / (V * kThreads);
+    constexpr int kItems = 2 * V * kIter;   // directed records per thread
+    RoundState *st = w.st;
+    __shared__ uint32_t cnt[256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t gofs[256];
+    __shared__ uint64_t skeys[2 * kTaIn];
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    rd.init(st);
+    const int64_t nt = tp.tiles_a;
+    const int64_t nch = rd.chunks();
+    const int ys = tp.ys;
+    uint64_t *out = w.keys[0];
+    bool bad = false;
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        cnt[threadIdx.x] = 0;
+        __syncthreads();
+        uint64_t k[kItems];
+        uint32_t rk[kItems];
+#pragma unroll
+        for (int it = 0; it < kIter; ++it) {
+            const int64_t c = tile * (kTaIn / V) + (int64_t)it * kThreads + threadIdx.x;
+            uint32_t a[V], b[V];
+            if (c < nch) {
+                rd.read(c, a, b, bad);
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int q = 2 * (it * V + j);
+                const bool valid = a[j] != b[j];
+                k[q] = ((uint64_t)a[j] << 32) | b[j];
+                k[q + 1] = ((uint64_t)b[j] << 32) | a[j];
+                rk[q] = valid ? atomicAdd(&cnt[b[j] >> ys], 1u) : ~0u;
+                rk[q + 1] = valid ? atomicAdd(&cnt[a[j] >> ys], 1u) : ~0u;
+            }
+        }
+        __syncthreads();
+        uint32_t total;
+        {
+            const uint32_t c0 = cnt[threadIdx.x];
+            dstart[threadIdx.x] = block_excl_scan<kThreads>(c0, lds, &total);
+            gofs[threadIdx.x] = w.counts[(int64_t)threadIdx.x * nt + tile];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) {
+            if (rk[q] != ~0u) skeys[dstart[(uint32_t)k[q] >> ys] + rk[q]] = k[q];
+        }
+        __syncthreads();
+        for (uint32_t pos = threadIdx.x; pos < total; pos += kThreads) {
+            const uint64_t kk = skeys[pos];
+            const uint32_t d = (uint32_t)kk >> ys;
+            out[gofs[d] + pos - dstart[d]] = kk;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// partition pass B: directed records -> ordered by row block, column order kept per tile
+// ---------------------------------------------------------------------------------------
+
+__device__ inline int64_t tiles_b_of(const RoundState *st) { return ceil_div((int64_t)st->t_count, kTbTile); }
+
+// Load the two records at even position p of a key array that holds an even number of
+// records (so p + 1 is in range whenever p is).
+__device__ inline void load_pair(const uint64_t *k, int64_t p, int64_t T, uint64_t &r0, uint64_t &r1, bool &v0,
+                                 bool &v1) {
+    v0 = p < T;
+    v1 = p + 1 < T;
+    if (v1) {
+        const ulonglong2 x = *(const ulonglong2 *)(k + p);
+        r0 = x.x;
+        r1 = x.y;
+    } else {
+        r0 = v0 ? k[p] : 0ull;
+        r1 = 0ull;
+    }
+}
+
+__global__ __launch_bounds__(kTbThreads) void k_part_b_hist(Work w, TPlan tp) {
+    RoundState *st = w.st;
+    __shared__ uint32_t hist[kTRowsMax];
+    const int64_t T = (int64_t)st->t_count;
+    const int64_t nt = tiles_b_of(st);
+    const int64_t nslabs = ceil_div(T, kSlab);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->aux_n = (u64c)tp.rows * (u64c)nt;
+        st->n_slabs = (u64c)nslabs;
+    }
+    // the tiled relabel reserves space in its output slabs with atomics: clear them here
+    for (int64_t i = (int64_t)blockIdx.x * kTbThreads + threadIdx.x; i < nslabs; i += (int64_t)gridDim.x * kTbThreads)
+        w.slab_cnt[i] = 0;
+    const uint64_t *in = w.keys[0];
+    const int xs = tp.xs;
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < tp.rows; i += kTbThreads) hist[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kTbTile / (2 * kTbThreads); ++j) {
+            const int64_t p = tile * kTbTile + 2 * ((int64_t)j * kTbThreads + threadIdx.x);
+            uint64_t r0, r1;
+            bool v0, v1;
+            load_pair(in, p, T, r0, r1, v0, v1);
+            if (v0) atomicAdd(&hist[(uint32_t)(r0 >> 32) >> xs], 1u);
+            if (v1) atomicAdd(&hist[(uint32_t)(r1 >> 32) >> xs], 1u);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < tp.rows; i += kTbThreads) w.counts[(int64_t)i * nt + tile] = hist[i];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp) {
+    constexpr int kPairs = kTbTile / (2 * kTbThreads);
+    constexpr int kPerThread = kTRowsMax / kTbThreads;   // row digits scanned by each thread
+    static_assert(kPerThread * kTbThreads == kTRowsMax, "row digits per thread");
+    RoundState *st = w.st;
+    __shared__ uint32_t cnt[kTRowsMax];
+    __shared__ uint32_t dstart[kTRowsMax];
+    __shared__ uint32_t gofs[kTRowsMax];
+    __shared__ uint64_t skeys[kTbTile];
+    __shared__ uint32_t lds[kTbThreads / kWave + 1];
+    const int64_t T = (int64_t)st->t_count;
+    const int64_t nt = tiles_b_of(st);
+    const uint64_t *in = w.keys[0];
+    uint64_t *out = w.keys[1];
+    const int xs = tp.xs;
+    const int rows = tp.rows;
+    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < rows; i += kTbThreads) cnt[i] = 0;
+        __syncthreads();
+        uint64_t k[2 * kPairs];
+        uint32_t rk[2 * kPairs];
+#pragma unroll
+        for (int j = 0; j < kPairs; ++j) {
+            const int64_t p = tile * kTbTile + 2 * ((int64_t)j * kTbThreads + threadIdx.x);
+            bool v0, v1;
+            load_pair(in, p, T, k[2 * j], k[2 * j + 1], v0, v1);
+            rk[2 * j] = v0 ? atomicAdd(&cnt[(uint32_t)(k[2 * j] >> 32) >> xs], 1u) : ~0u;
+            rk[2 * j + 1] = v1 ? atomicAdd(&cnt[(uint32_t)(k[2 * j + 1] >> 32) >> xs], 1u) : ~0u;
+        }
+        __syncthreads();
+        uint32_t total;
+        {
+            uint32_t c[kPerThread];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int i = kPerThread * threadIdx.x + q;
+                c[q] = i < rows ? cnt[i] : 0u;
+                sum += c[q];
+            }
+            uint32_t run = block_excl_scan<kTbThreads>(sum, lds, &total);
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int i = kPerThread * threadIdx.x + q;
+                if (i < rows) {
+                    dstart[i] = run;
+                    gofs[i] = w.counts[(int64_t)i * nt + tile];
+                }
+                run += c[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2 * kPairs; ++q) {
+            if (rk[q] != ~0u) skeys[dstart[(uint32_t)(k[q] >> 32) >> xs] + rk[q]] = k[q];
+        }
+        __syncthreads();
+        for (uint32_t pos = threadIdx.x; pos < total; pos += kTbThreads) {
+            const uint64_t kk = skeys[pos];
+            const uint32_t d = (uint32_t)(kk >> 32) >> xs;
+            out[gofs[d] + pos - dstart[d]] = kk;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// per-row kernels
+// ---------------------------------------------------------------------------------------
+
+// Records [start, end) of row X in the tiled array; the scanned pass-B count table holds
+// the first position of each row in the column of tile 0.
+__device__ inline void row_range(const Work &w, const TPlan &tp, int X, int64_t nt, int64_t T, int64_t &start,
+                                 int64_t &end) {
+    if (nt == 0) {
+        start = end = 0;
+        return;
+    }
+    start = w.counts[(int64_t)X * nt];
+    end = X + 1 < tp.rows ? (int64_t)w.counts[(int64_t)(X + 1) * nt] : T;
+}
+
+// kStep 1: m1[x] = min(rho(x), min over the row's records (x, y) of rho(y)), or +inf for an
+// id without a loop-free record.  kStep 2: two-hop minimum min(m1[x], min m1[y]) and the
+// parent it names (the inverse of the priority bijection); an id without records is its
+// own parent.
+template <int kStep>
+__global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp) {
+    constexpr int kUnroll = 4;
+    __shared__ uint32_t acc[1 << kTxShiftMax];
+    RoundState *st = w.st;
+    const int64_t T = (int64_t)st->t_count;
+    const int64_t nt = tiles_b_of(st);
+    const int64_t n = (int64_t)st->n_cur;
+    const uint64_t *rec = w.keys[1];
+    uint32_t *m1 = w.ml;
+    uint32_t active = 0;
+    bool broken = false;
+    for (int X = blockIdx.x; X < tp.rows; X += gridDim.x) {
+        const int64_t base = (int64_t)X << tp.xs;
+        const int cnt = (int)min((int64_t)1 << tp.xs, n - base);
+        for (int i = threadIdx.x; i < cnt; i += kTRowThreads) acc[i] = kInf;
+        __syncthreads();
+        int64_t start, end;
+        row_range(w, tp, X, nt, T, start, end);
+        const int64_t p0 = start & ~(int64_t)1;
+        for (int64_t pb = p0 + 2 * (int64_t)threadIdx.x; pb < end; pb += 2 * kUnroll * kTRowThreads) {
+            uint64_t r[2 * kUnroll];
+            bool v[2 * kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t p = pb + 2 * (int64_t)u * kTRowThreads;
+                load_pair(rec, p, end, r[2 * u], r[2 * u + 1], v[2 * u], v[2 * u + 1]);
+                v[2 * u] = v[2 * u] && p >= start;
+            }
+            uint32_t val[2 * kUnroll];
+#pragma unroll
+            for (int q = 0; q < 2 * kUnroll; ++q) {
+                const uint32_t y = (uint32_t)r[q];
+                if (kStep == 1)
+                    val[q] = prio(pc.key, y);
+                else
+                    val[q] = v[q] ? m1[y] : kInf;
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * kUnroll; ++q) {
+                const int64_t xi = (int64_t)(uint32_t)(r[q] >> 32) - base;
+                if (v[q]) {
+                    if (xi >= 0 && xi < cnt)
+                        atomicMin(&acc[xi], val[q]);
+                    else
+                        broken = true;
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kTRowThreads) {
+            const uint32_t a = acc[i];
+            const uint32_t x = (uint32_t)(base + i);
+            if (kStep == 1) {
+                m1[x] = a == kInf ? kInf : min(a, prio(pc.key, x));
+            } else if (a == kInf) {
+                w.par[x] = x;
+            } else {
+                uint32_t p = prio_inv(pc.key, min(a, m1[x]));
+                if ((int64_t)p >= n) {   // cannot happen for a consistent state
+                    broken = true;
+                    p = x;
+                }
+                w.par[x] = p;
+                w.is_label[p] = 1;
+                ++active;
+            }
+        }
+        __syncthreads();
+    }
+    if (kStep == 2) {
+        active = wave_sum(active);
+        if (lane_id() == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+    }
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+// Relabel the row's records with x < y (each input record once) through the parents.
+// Every aligned chunk of 2 kTRowThreads records lies inside one output slab of kSlab
+// records; a row reserves its survivors' space in that slab with one atomic, so the slab
+// (shared by at most the two rows that meet inside it) is filled from its start.
+__global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp) {
+    constexpr int kChunk = 2 * kTRowThreads;
+    static_assert(kSlab % kChunk == 0, "chunks must not straddle slabs");
+    RoundState *st = w.st;
+    __shared__ uint32_t lds[kTRowThreads / kWave + 1];
+    __shared__ uint32_t sbase;
+    const int64_t T = (int64_t)st->t_count;
+    const int64_t nt = tiles_b_of(st);
+    const uint64_t *rec = w.keys[1];
+    uint64_t *out = w.keys[0];
+    const int kb = st->kb;
+    const int hbs = st->hb_shift;
+    uint32_t kept = 0;
+    for (int X = blockIdx.x; X < tp.rows; X += gridDim.x) {
+        int64_t start, end;
+        row_range(w, tp, X, nt, T, start, end);
+        for (int64_t cb = start & ~(int64_t)(kChunk - 1); cb < end; cb += kChunk) {
+            const int64_t p = cb + 2 * (int64_t)threadIdx.x;
+            uint64_t r[2];
+            bool v[2];
+            load_pair(rec, p, end, r[0], r[1], v[0], v[1]);
+            v[0] = v[0] && p >= start;
+            v[1] = v[1] && p + 1 >= start;
+            uint64_t key[2];
+            bool keep[2];
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t x = (uint32_t)(r[j] >> 32), y = (uint32_t)r[j];
+                keep[j] = v[j] && x < y;
+                uint32_t pa = 0, pb = 0;
+                if (keep[j]) {
+                    pa = w.par[x];
+                    pb = w.par[y];
+                }
+                keep[j] = keep[j] && pa != pb;
+                const uint32_t lo = min(pa, pb), hi = max(pa, pb);
+                key[j] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
+                c += keep[j];
+            }
+            uint32_t total;
+            const uint32_t off = block_excl_scan<kTRowThreads>(c, lds, &total);
+            if (total == 0) continue;
+            const int64_t slab = cb / kSlab;
+            if (threadIdx.x == 0) sbase = atomicAdd(&w.slab_cnt[slab], total);
+            __syncthreads();
+            uint64_t *dst = out + slab * kSlab + sbase + off;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (keep[j]) *dst++ = key[j];
+            }
+            kept += total;
+        }
+    }
+    if (threadIdx.x == 0 && kept) atomicAdd(&st->s_count, (u64c)kept);
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+
+template <class R>
+static hipError_t part_a(const R &rd, const Work &w, const TPlan &tp, int grid, hipStream_t s, bool scatter) {
+    if (scatter)
+        hipLaunchKernelGGL(k_part_a_scatter<R>, dim3(grid), dim3(kThreads), 0, s, rd, w, tp);
+    else
+        hipLaunchKernelGGL(k_part_a_hist<R>, dim3(grid), dim3(kThreads), 0, s, rd, w, tp);
+    return hipGetLastError();
+}
+
+static hipError_t part_a_layout(const EdgeIn &e, const Work &w, const TPlan &tp, int grid, hipStream_t s,
+                                bool scatter) {
+    switch (e.layout) {
+        case kSoa32:
+            if (e.vec) return part_a(ReadSoa32<4>(e), w, tp, grid, s, scatter);
+            return part_a(ReadSoa32<1>(e), w, tp, grid, s, scatter);
+        case kSoa64:
+            if (e.vec) return part_a(ReadSoa64<2>(e), w, tp, grid, s, scatter);
+            return part_a(ReadSoa64<1>(e), w, tp, grid, s, scatter);
+        default:
+            if (e.vec) return part_a(ReadPacked<2>(e), w, tp, grid, s, scatter);
+            return part_a(ReadPacked<1>(e), w, tp, grid, s, scatter);
+    }
+}
+
+hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &tp, int grid, hipStream_t s,
+                                  int stage) {
+    switch (stage) {
+        case 0:
+            return part_a_layout(in, w, tp, grid, s, false);
+        case 1:
+        case 2:
+        case 3:
+            return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, &w.st->t_count, grid, s, stage - 1);
+        case 4:
+            return part_a_layout(in, w, tp, grid, s, true);
+        case 5:
+            hipLaunchKernelGGL(k_part_b_hist, dim3(grid), dim3(kTbThreads), 0, s, w, tp);
+            return hipGetLastError();
+        case 6:
+        case 7:
+        case 8:
+            return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 6);
+        case 9:
+            hipLaunchKernelGGL(k_part_b_scatter, dim3(grid), dim3(kTbThreads), 0, s, w, tp);
+            return hipGetLastError();
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s) {
+    hipLaunchKernelGGL(k_tiled_min<1>, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s) {
+    hipLaunchKernelGGL(k_tiled_min<2>, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s) {
+    hipLaunchKernelGGL(k_tiled_relabel, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, tp);
+    return hipGetLastError();
+}
+
+}  // namespace lc

@@ -84,7 +84,7 @@ def test_workspace_size_and_state_errors():
     from paper_1807_10727_amd import _cc
     sizes = {}
     for n, m in ((1, 0), (1000, 5000), (1 << 20, 1 << 22)):
-        ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000)
+        ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_ROUND0_DIRECT)
         sizes[(n, m)] = _cc.cc_workspace_size(ctx)
         if n == 1000:
             with pytest.raises(_cc.CCError) as e:
@@ -103,6 +103,38 @@ def test_workspace_size_and_state_errors():
     assert sizes[(1, 0)] < sizes[(1000, 5000)] < big
 
 
+def test_round0_layout_flags():
+    """The tiled round 0 doubles the key buffers (16 more bytes per record) and is chosen by
+    default from 2^20 ids and records up to 2^26 ids; contradictory or impossible requests
+    are argument errors."""
+    from paper_1807_10727_amd import _cc
+    n, m = 1 << 20, 1 << 22
+
+    def size(n, m, flags):
+        ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=flags)
+        try:
+            return _cc.cc_workspace_size(ctx)
+        finally:
+            _cc.cc_destroy(ctx)
+
+    direct = size(n, m, _cc.CC_ROUND0_DIRECT)
+    tiled = size(n, m, _cc.CC_ROUND0_TILED)
+    assert 16 * m <= tiled - direct < 16 * m + (m // 2) * 4 + (1 << 20)
+    assert size(n, m, 0) == tiled
+    assert size(n - 1, m, 0) == size(n - 1, m, _cc.CC_ROUND0_DIRECT)      # below 2^20 ids
+    assert size(1 << 27, m, 0) == size(1 << 27, m, _cc.CC_ROUND0_DIRECT)  # above 2^26 ids
+    assert size(1000, 5000, _cc.CC_ROUND0_TILED) > size(1000, 5000, 0)
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000,
+                      flags=_cc.CC_ROUND0_TILED | _cc.CC_ROUND0_DIRECT)
+    assert e.value.status == _cc.CC_E_ARG
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_create((1 << 26) + 1, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_ROUND0_TILED)
+    assert e.value.status == _cc.CC_E_ARG
+    ctx = _cc.cc_create(1 << 26, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_ROUND0_TILED)
+    _cc.cc_destroy(ctx)
+
+
 def test_labels_before_run_is_a_state_error():
     from paper_1807_10727_amd import _cc
     ctx = _cc.cc_create(10, 5, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000)
@@ -115,5 +147,6 @@ def test_labels_before_run_is_a_state_error():
 def test_kernel_families_listed():
     from paper_1807_10727_amd import _cc
     names = _cc.cc_kernel_family_names()
-    for want in ("min1", "min2", "parent", "relabel", "sort_scatter", "unique", "compose"):
+    for want in ("min1", "min2", "parent", "relabel", "sort_scatter", "unique", "compose", "part_a_hist",
+                 "part_b_scatter", "min1_tiled", "min2_tiled", "relabel_tiled"):
         assert want in names

@@ -25,6 +25,8 @@ def lc():
 
 
 DEV = "cuda:0"
+# round 0 reads the input directly, or through the tiled layout (flag values of include/cc.h)
+MODES = {"direct": 1 << 2, "tiled": 1 << 3}
 
 
 def to_device(g, layout="soa32", offset=0):
@@ -83,10 +85,19 @@ def check(lc, g, seed, **kw):
 
 # ---------------------------------------------------------------------------------------
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("n,m,seed", [(100, 300, 1), (1000, 4097, 2), (5000, 20001, 3), (3000, 2000, 4),
                                       (20000, 61441, 5)])
-def test_gnm_parity(lc, n, m, seed):
+def test_gnm_parity(lc, n, m, seed, mode):
     g = graphgen.Graph(n, *graphgen.gnm(seed * 7919, n, m))
+    check(lc, g, seed, flags=MODES[mode])
+
+
+@pytest.mark.parametrize("n,m,seed", [((1 << 20) + 3, (1 << 22) + 1, 6), ((1 << 22) + 7777, 1 << 23, 7)])
+def test_tiled_full_blocks_parity(lc, n, m, seed):
+    """Sizes where the tiled round 0 is the default: 256 row blocks of 2^12 ids, then
+    row blocks of 2^15 ids (the whole LDS) with 2^15-id column blocks, ragged last blocks."""
+    g = graphgen.Graph(n, *graphgen.gnm(seed * 104729, n, m))
     check(lc, g, seed)
 
 
@@ -97,37 +108,42 @@ def test_small_workload_parity(lc):
     assert w.rounds >= 2
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("scale,ef", [(10, 8), (13, 16)])
-def test_rmat_parity(lc, scale, ef):
+def test_rmat_parity(lc, scale, ef, mode):
     g = graphgen.Graph(1 << scale, *graphgen.rmat(scale * 31, scale, ef << scale))
-    check(lc, g, seed=scale)
+    check(lc, g, seed=scale, flags=MODES[mode])
 
 
-def test_paths_parity_many_rounds(lc):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_paths_parity_many_rounds(lc, mode):
     g = graphgen.er_with_paths(17, 1 << 11, 1 << 12, 30, 700)
-    w = check(lc, g, seed=99)
+    w = check(lc, g, seed=99, flags=MODES[mode])
     assert w.rounds >= 5
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("layout", ["soa32", "soa64", "packed"])
 @pytest.mark.parametrize("offset", [0, 1])
-def test_layouts_and_alignment(lc, layout, offset):
+def test_layouts_and_alignment(lc, layout, offset, mode):
     g = graphgen.Graph(3001, *graphgen.gnm(44, 3001, 9003))
-    check(lc, g, seed=5, layout=layout, offset=offset, per_round=False)
+    check(lc, g, seed=5, layout=layout, offset=offset, per_round=False, flags=MODES[mode])
 
 
-def test_union_of_all_graphs_on_five_vertices(lc):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_union_of_all_graphs_on_five_vertices(lc, mode):
     adj = all_graph_adjacency(5)
     src, dst, eoff = graph_records(adj)
     G = adj.shape[0]
     gid = np.repeat(np.arange(G), np.diff(eoff))
     g = graphgen.Graph(5 * G, (src + 5 * gid).astype(np.uint32), (dst + 5 * gid).astype(np.uint32))
-    check(lc, g, seed=12345)
+    check(lc, g, seed=12345, flags=MODES[mode])
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("case", ["empty", "no_edges", "loops_only", "single_edge", "duplicates", "isolated",
                                   "one_vertex"])
-def test_degenerate_cases(lc, case):
+def test_degenerate_cases(lc, case, mode):
     if case == "empty":
         g = graphgen.Graph(0, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
     elif case == "no_edges":
@@ -142,13 +158,14 @@ def test_degenerate_cases(lc, case):
         g = graphgen.Graph(1000, np.array([10, 500], np.uint32), np.array([999, 10], np.uint32))
     else:
         g = graphgen.Graph(1, np.zeros(3, np.uint32), np.zeros(3, np.uint32))
-    check(lc, g, seed=3)
+    check(lc, g, seed=3, flags=MODES[mode])
 
 
-def test_max_rounds_partial_labels(lc):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_max_rounds_partial_labels(lc, mode):
     g = graphgen.er_with_paths(5, 0, 0, 20, 400)
     for k in (1, 2, 3):
-        check(lc, g, seed=8, max_rounds=k)
+        check(lc, g, seed=8, max_rounds=k, flags=MODES[mode])
 
 
 def test_canonical_labels(lc):
@@ -158,16 +175,17 @@ def test_canonical_labels(lc):
     np.testing.assert_array_equal(lab.cpu().numpy().astype(np.uint32), oracle.components_min_id(g.n, g.src, g.dst))
 
 
-def test_invalid_ids_rejected(lc):
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_invalid_ids_rejected(lc, mode):
     g = graphgen.Graph(100, np.array([1, 2, 100], np.uint32), np.array([2, 3, 4], np.uint32))
     s_t, d_t, _ = to_device(g)
-    with lc.Solver(g.n, s_t, d_t, seed=1) as s:
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=MODES[mode]) as s:
         with pytest.raises(lc.CCError) as e:
             s.run()
         assert e.value.status == -2
     neg = torch.tensor([-1, 2], dtype=torch.int32, device=DEV)
     ok = torch.tensor([2, 3], dtype=torch.int32, device=DEV)
-    with lc.Solver(10, neg, ok, seed=1) as s:
+    with lc.Solver(10, neg, ok, seed=1, flags=MODES[mode]) as s:
         with pytest.raises(lc.CCError):
             s.run()
 
@@ -206,5 +224,11 @@ def test_profile_times_kernels(lc):
     with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE) as s:
         r = s.run()
         t = s.kernel_times()
-    assert t["min1_round0"][1] == 1 and t["min1"][1] == r - 1
+    assert t["min1_round0"][1] == 1 and t["min1"][1] == r - 1 and t["min1_tiled"][1] == 0
     assert t["min1_round0"][0] > 0 and t["sort_scatter"][0] > 0
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE | lc.CC_ROUND0_TILED) as s:
+        r2 = s.run()
+        t = s.kernel_times()
+    assert r2 == r
+    assert t["min1_round0"][1] == 0 and t["min1_tiled"][1] == 1 and t["relabel_tiled"][1] == 1
+    assert t["part_a_hist"][1] == 1 and t["part_b_scatter"][1] == 1 and t["min1"][1] == r - 1
