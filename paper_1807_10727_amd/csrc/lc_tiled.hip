@@ -20,6 +20,17 @@
 #include "lc_internal.hpp"
 #include "lc_readers.hpp"
 
+// Record pairs each thread keeps in flight in the gathering row kernels.  A row sweeps
+// the whole column id space once, so the ids its workgroup gathers in one step span
+// (pairs * 2 * 1024 / row records) of that space: few enough pairs keep the span of the
+// rows running together on an XCD inside its L2.
+#ifndef LC_TMIN2_PAIRS
+#define LC_TMIN2_PAIRS 4
+#endif
+#ifndef LC_TRELABEL_PAIRS
+#define LC_TRELABEL_PAIRS 2
+#endif
+
 namespace lc {
 
 // ---------------------------------------------------------------------------------------
@@ -184,16 +195,18 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_hist(Work w, TPlan tp) {
     }
 }
 
+// LDS: digit counts (scanned in place into tile starts), global offsets and the staged tile:
+// 80 KiB, so that two workgroups share a CU.  The scan's scratch words borrow the staging
+// area, which is idle while the counts are scanned.
 __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp) {
     constexpr int kPairs = kTbTile / (2 * kTbThreads);
     constexpr int kPerThread = kTRowsMax / kTbThreads;   // row digits scanned by each thread
     static_assert(kPerThread * kTbThreads == kTRowsMax, "row digits per thread");
     RoundState *st = w.st;
-    __shared__ uint32_t cnt[kTRowsMax];
     __shared__ uint32_t dstart[kTRowsMax];
     __shared__ uint32_t gofs[kTRowsMax];
     __shared__ uint64_t skeys[kTbTile];
-    __shared__ uint32_t lds[kTbThreads / kWave + 1];
+    uint32_t *lds = (uint32_t *)skeys;
     const int64_t T = (int64_t)st->t_count;
     const int64_t nt = tiles_b_of(st);
     const uint64_t *in = w.keys[0];
@@ -201,7 +214,7 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp)
     const int xs = tp.xs;
     const int rows = tp.rows;
     for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
-        for (int i = threadIdx.x; i < rows; i += kTbThreads) cnt[i] = 0;
+        for (int i = threadIdx.x; i < rows; i += kTbThreads) dstart[i] = 0;
         __syncthreads();
         uint64_t k[2 * kPairs];
         uint32_t rk[2 * kPairs];
@@ -210,8 +223,8 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp)
             const int64_t p = tile * kTbTile + 2 * ((int64_t)j * kTbThreads + threadIdx.x);
             bool v0, v1;
             load_pair(in, p, T, k[2 * j], k[2 * j + 1], v0, v1);
-            rk[2 * j] = v0 ? atomicAdd(&cnt[(uint32_t)(k[2 * j] >> 32) >> xs], 1u) : ~0u;
-            rk[2 * j + 1] = v1 ? atomicAdd(&cnt[(uint32_t)(k[2 * j + 1] >> 32) >> xs], 1u) : ~0u;
+            rk[2 * j] = v0 ? atomicAdd(&dstart[(uint32_t)(k[2 * j] >> 32) >> xs], 1u) : ~0u;
+            rk[2 * j + 1] = v1 ? atomicAdd(&dstart[(uint32_t)(k[2 * j + 1] >> 32) >> xs], 1u) : ~0u;
         }
         __syncthreads();
         uint32_t total;
@@ -221,7 +234,7 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp)
 #pragma unroll
             for (int q = 0; q < kPerThread; ++q) {
                 const int i = kPerThread * threadIdx.x + q;
-                c[q] = i < rows ? cnt[i] : 0u;
+                c[q] = i < rows ? dstart[i] : 0u;
                 sum += c[q];
             }
             uint32_t run = block_excl_scan<kTbThreads>(sum, lds, &total);
@@ -272,7 +285,7 @@ __device__ inline void row_range(const Work &w, const TPlan &tp, int X, int64_t 
 // own parent.
 template <int kStep>
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp) {
-    constexpr int kUnroll = 4;
+    constexpr int kUnroll = kStep == 1 ? 4 : LC_TMIN2_PAIRS;   // record pairs in flight per thread
     __shared__ uint32_t acc[1 << kTxShiftMax];
     RoundState *st = w.st;
     const int64_t T = (int64_t)st->t_count;
@@ -347,49 +360,70 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
     if (broken) atomicOr(&st->err, 4u);
 }
 
-// Relabel the row's records with x < y (each input record once) through the parents.
-// Every aligned chunk of 2 kTRowThreads records lies inside one output slab of kSlab
-// records; a row reserves its survivors' space in that slab with one atomic, so the slab
-// (shared by at most the two rows that meet inside it) is filled from its start.
+// Relabel the row's records with x < y (each input record once) through the parents.  The
+// row's parents are staged in LDS; the parents at y are gathered from the column block that
+// the concurrent rows share in L2.  The row is walked in chunks aligned to the output slabs
+// of kSlab records; a row reserves its survivors' space in a slab with one atomic, so the
+// slab (shared by at most the two rows that meet inside it) is filled from its start.
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp) {
-    constexpr int kChunk = 2 * kTRowThreads;
-    static_assert(kSlab % kChunk == 0, "chunks must not straddle slabs");
+    constexpr int kPairs = LC_TRELABEL_PAIRS;   // record pairs per thread and chunk
+    constexpr int kChunk = 2 * kPairs * kTRowThreads;
+    static_assert(kSlab % kChunk == 0, "a chunk lies inside one slab");
     RoundState *st = w.st;
+    __shared__ uint32_t lpar[1 << kTxShiftMax];
     __shared__ uint32_t lds[kTRowThreads / kWave + 1];
     __shared__ uint32_t sbase;
     const int64_t T = (int64_t)st->t_count;
     const int64_t nt = tiles_b_of(st);
+    const int64_t n = (int64_t)st->n_cur;
     const uint64_t *rec = w.keys[1];
     uint64_t *out = w.keys[0];
     const int kb = st->kb;
     const int hbs = st->hb_shift;
     uint32_t kept = 0;
+    bool broken = false;
     for (int X = blockIdx.x; X < tp.rows; X += gridDim.x) {
+        const int64_t base = (int64_t)X << tp.xs;
+        const int cnt = (int)min((int64_t)1 << tp.xs, n - base);
+        for (int i = threadIdx.x; i < cnt; i += kTRowThreads) lpar[i] = w.par[base + i];
+        __syncthreads();
         int64_t start, end;
         row_range(w, tp, X, nt, T, start, end);
         for (int64_t cb = start & ~(int64_t)(kChunk - 1); cb < end; cb += kChunk) {
-            const int64_t p = cb + 2 * (int64_t)threadIdx.x;
-            uint64_t r[2];
-            bool v[2];
-            load_pair(rec, p, end, r[0], r[1], v[0], v[1]);
-            v[0] = v[0] && p >= start;
-            v[1] = v[1] && p + 1 >= start;
-            uint64_t key[2];
-            bool keep[2];
+            uint64_t r[2 * kPairs];
+            bool v[2 * kPairs];
+#pragma unroll
+            for (int u = 0; u < kPairs; ++u) {
+                const int64_t p = cb + 2 * ((int64_t)u * kTRowThreads + threadIdx.x);
+                load_pair(rec, p, end, r[2 * u], r[2 * u + 1], v[2 * u], v[2 * u + 1]);
+                v[2 * u] = v[2 * u] && p >= start;
+                v[2 * u + 1] = v[2 * u + 1] && p + 1 >= start;
+            }
+            uint32_t pb[2 * kPairs];
+#pragma unroll
+            for (int q = 0; q < 2 * kPairs; ++q) {
+                const uint32_t x = (uint32_t)(r[q] >> 32), y = (uint32_t)r[q];
+                v[q] = v[q] && x < y;
+                pb[q] = v[q] ? w.par[y] : 0u;
+            }
+            uint64_t key[2 * kPairs];
             uint32_t c = 0;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint32_t x = (uint32_t)(r[j] >> 32), y = (uint32_t)r[j];
-                keep[j] = v[j] && x < y;
-                uint32_t pa = 0, pb = 0;
-                if (keep[j]) {
-                    pa = w.par[x];
-                    pb = w.par[y];
+            for (int q = 0; q < 2 * kPairs; ++q) {
+                const int64_t xi = (int64_t)(uint32_t)(r[q] >> 32) - base;
+                uint32_t pa = 0;
+                if (v[q]) {
+                    if (xi >= 0 && xi < cnt) {
+                        pa = lpar[xi];
+                    } else {
+                        broken = true;
+                        v[q] = false;
+                    }
                 }
-                keep[j] = keep[j] && pa != pb;
-                const uint32_t lo = min(pa, pb), hi = max(pa, pb);
-                key[j] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
-                c += keep[j];
+                v[q] = v[q] && pa != pb[q];
+                const uint32_t lo = min(pa, pb[q]), hi = max(pa, pb[q]);
+                key[q] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
+                c += v[q];
             }
             uint32_t total;
             const uint32_t off = block_excl_scan<kTRowThreads>(c, lds, &total);
@@ -399,13 +433,15 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
             __syncthreads();
             uint64_t *dst = out + slab * kSlab + sbase + off;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                if (keep[j]) *dst++ = key[j];
+            for (int q = 0; q < 2 * kPairs; ++q) {
+                if (v[q]) *dst++ = key[q];
             }
             kept += total;
         }
+        __syncthreads();   // lpar is rewritten for the next row
     }
     if (threadIdx.x == 0 && kept) atomicAdd(&st->s_count, (u64c)kept);
+    if (broken) atomicOr(&st->err, 4u);
 }
 
 // ---------------------------------------------------------------------------------------
