@@ -91,8 +91,12 @@ struct Work {
 };
 
 constexpr int kThreads = 256;                      // workgroup size of the streaming kernels
-constexpr int kSortItems = 16;                     // keys per thread in a sort tile
-constexpr int kSortTile = kThreads * kSortItems;   // 4096 keys per sort tile
+#ifndef LC_SORT_THREADS
+#define LC_SORT_THREADS 256
+#endif
+constexpr int kSortThreads = LC_SORT_THREADS;          // workgroup of the sort and unique kernels
+constexpr int kSortItems = 16;                         // keys per thread in a sort tile
+constexpr int kSortTile = kSortThreads * kSortItems;   // keys per sort tile
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;   // elements per block of the generic scan
 constexpr int kRadixBits = 8;

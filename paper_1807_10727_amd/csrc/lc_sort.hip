@@ -152,7 +152,7 @@ __device__ inline Tiles tiles_of(const Work &w, int pass) {
 
 __device__ inline bool is_leader(uint64_t peers) { return (int)(__ffsll((long long)peers) - 1) == lane_id(); }
 
-__global__ __launch_bounds__(kThreads) void k_sort_hist(Work w, int pass) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
     if (pass >= passes) {
@@ -166,30 +166,52 @@ __global__ __launch_bounds__(kThreads) void k_sort_hist(Work w, int pass) {
     __shared__ uint32_t hist[kRadix];
     for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
-        hist[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[i] = 0;
+        // every load of the tile in flight at once: pairs of keys, 16-byte aligned
+        uint32_t d[kSortItems];
+        bool valid[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems / 2; ++j) {
+            const int it = 2 * (j * kSortThreads + threadIdx.x);
+            uint64_t k0 = 0, k1 = 0;
+            if (it + 1 < tv) {
+                const ulonglong2 x = *(const ulonglong2 *)(in + tile * kSortTile + it);
+                k0 = x.x;
+                k1 = x.y;
+            } else if (it < tv) {
+                k0 = in[tile * kSortTile + it];
+            }
+            valid[2 * j] = it < tv;
+            valid[2 * j + 1] = it + 1 < tv;
+            d[2 * j] = (uint32_t)(k0 >> shift) & (kRadix - 1);
+            d[2 * j + 1] = (uint32_t)(k1 >> shift) & (kRadix - 1);
+        }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
-            const int it = j * kThreads + threadIdx.x;
-            const bool valid = it < tv;
-            const uint32_t d = valid ? (uint32_t)(in[tile * kSortTile + it] >> shift) & (kRadix - 1) : 0u;
-            const uint64_t act = ballot(valid);
+            const uint64_t act = ballot(valid[j]);
             if (!act) continue;
             const int first = __ffsll((long long)act) - 1;
-            const uint32_t d0 = __shfl(d, first, kWave);
-            if (ballot(valid && d == d0) == act) {
+            const uint32_t d0 = __shfl(d[j], first, kWave);
+            if (ballot(valid[j] && d[j] == d0) == act) {
                 if (lane_id() == first) atomicAdd(&hist[d0], (uint32_t)__popcll(act));
-            } else if (valid) {
-                atomicAdd(&hist[d], 1u);
+            } else if (valid[j]) {
+                atomicAdd(&hist[d[j]], 1u);
             }
         }
         __syncthreads();
-        w.counts[(int64_t)threadIdx.x * tl.ntiles + tile] = hist[threadIdx.x];
+        for (int i = threadIdx.x; i < kRadix; i += kSortThreads) w.counts[(int64_t)i * tl.ntiles + tile] = hist[i];
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
+// Waves per SIMD the scatter is compiled for: 3 trades a few spilled words for a third more
+// waves in flight than the unconstrained register count allows (measured faster).
+#ifndef LC_SCATTER_WAVES
+#define LC_SCATTER_WAVES 3
+#endif
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LC_SCATTER_WAVES)))
+void k_sort_scatter(Work w, int pass) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
     if (pass >= passes) return;
@@ -200,7 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
     uint64_t *out = w.keys[src ^ 1];
     const int shift = pass * kRadixBits;
 
-    constexpr int kWaves = kThreads / kWave;
+    constexpr int kWaves = kSortThreads / kWave;
     __shared__ uint32_t wcnt[kWaves][kRadix];
     __shared__ uint64_t skeys[kSortTile];
     __shared__ uint32_t dstart[kRadix];
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
-        for (int i = threadIdx.x; i < kWaves * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0;
+        for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
 
         uint64_t k[kSortItems];
@@ -239,15 +261,20 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
         {   // per digit: prefix over waves, start within the tile, global offset
             const int d = threadIdx.x;
             uint32_t run = 0;
+            if (d < kRadix) {
 #pragma unroll
-            for (int q = 0; q < kWaves; ++q) {
-                const uint32_t c = wcnt[q][d];
-                wcnt[q][d] = run;
-                run += c;
+                for (int q = 0; q < kWaves; ++q) {
+                    const uint32_t c = wcnt[q][d];
+                    wcnt[q][d] = run;
+                    run += c;
+                }
             }
             uint32_t total;
-            dstart[d] = block_excl_scan<kThreads>(run, lds, &total);
-            gofs[d] = w.counts[(int64_t)d * ntiles + tile];
+            const uint32_t ds = block_excl_scan<kSortThreads>(run, lds, &total);
+            if (d < kRadix) {
+                dstart[d] = ds;
+                gofs[d] = w.counts[(int64_t)d * ntiles + tile];
+            }
         }
         __syncthreads();
 
@@ -260,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
 
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
-            const int pos = j * kThreads + threadIdx.x;
+            const int pos = j * kSortThreads + threadIdx.x;
             if (pos < tv) {
                 const uint64_t kk = skeys[pos];
                 const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
@@ -275,9 +302,9 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(Work w, int pass) {
 // unique
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_unique_count(Work w) {
+__global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     RoundState *st = w.st;
-    __shared__ uint32_t lds[kThreads / kWave + 1];
+    __shared__ uint32_t lds[kSortThreads / kWave + 1];
     const int64_t S = (int64_t)st->s_count;
     const int64_t ntiles = ceil_div(S, kSortTile);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;
@@ -286,18 +313,18 @@ __global__ __launch_bounds__(kThreads) void k_unique_count(Work w) {
         uint32_t cnt = 0;
 #pragma unroll 4
         for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = tile * kSortTile + j * kThreads + threadIdx.x;
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
             if (idx < S) cnt += (idx == 0 || in[idx] != in[idx - 1]) ? 1u : 0u;
         }
         uint32_t total;
-        block_excl_scan<kThreads>(cnt, lds, &total);
+        block_excl_scan<kSortThreads>(cnt, lds, &total);
         if (threadIdx.x == 0) w.tile_cnt[tile] = total;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_unique_write(Work w) {
+__global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     RoundState *st = w.st;
-    __shared__ uint32_t lds[kThreads / kWave + 1];
+    __shared__ uint32_t lds[kSortThreads / kWave + 1];
     const int64_t S = (int64_t)st->s_count;
     const int64_t ntiles = ceil_div(S, kSortTile);
     const int t = sorted_sel(st->round, st->e_sel, st->nbits);
@@ -331,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void k_unique_write(Work w) {
             cnt += h;
         }
         uint32_t total;
-        uint32_t off = w.tile_cnt[tile] + block_excl_scan<kThreads>(cnt, lds, &total);
+        uint32_t off = w.tile_cnt[tile] + block_excl_scan<kSortThreads>(cnt, lds, &total);
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             if (heads >> j & 1u) {
@@ -381,26 +408,26 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage) {
     switch (stage) {
         case 0:
-            hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kThreads), 0, s, w, pass);
+            hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
             return hipGetLastError();
         case 1:
         case 2:
         case 3:
             return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 1);
         default:
-            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kThreads), 0, s, w, pass);
+            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
             return hipGetLastError();
     }
 }
 
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage) {
     if (stage == 0)
-        hipLaunchKernelGGL(k_unique_count, dim3(grid), dim3(kThreads), 0, s, w);
+        hipLaunchKernelGGL(k_unique_count, dim3(grid), dim3(kSortThreads), 0, s, w);
     else if (stage == 1)
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.tile_cnt, &w.st->aux_n, 0,
                            &w.st->m_next);
     else
-        hipLaunchKernelGGL(k_unique_write, dim3(grid), dim3(kThreads), 0, s, w);
+        hipLaunchKernelGGL(k_unique_write, dim3(grid), dim3(kSortThreads), 0, s, w);
     return hipGetLastError();
 }
 

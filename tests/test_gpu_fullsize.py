@@ -1,0 +1,191 @@
+"""Full-size checks, in the launch configuration bench.py times (default flags: the tiled
+round 0 where the size allows it, the caller's stream, per-kernel timing on).
+
+At these sizes the oracle cannot replay every round, so each test checks what it can
+compute one by one or what holds at any size:
+  * round-0 parents of sampled vertices, straight from the definition (the vertex of least
+    priority in the closed two-hop neighbourhood, Section 3), in 64-bit (priority, id) keys
+    computed with the test-side priority restatement that test_oracle pins to the oracle;
+  * round-0 statistics that have a closed form (active nodes, records read);
+  * the final labels against textbook union-find: every label is an id of its vertex's
+    component and there are exactly as many distinct labels as components;
+  * the tiled and the direct round 0 give identical statistics and labels.
+The batched and serving workloads are checked graph by graph on a seeded sample against the
+oracle (labels and round counts, bit for bit)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from lcref import spec_priority
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+BENCH_SEED = graphgen.CONFIG_SEED_BASE + 1     # the seed of bench.py's first timed step
+
+
+@pytest.fixture(scope="module")
+def lc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1807_10727_amd as lc
+    return lc
+
+
+def sampled_round0_parents(src, dst, seed, sample):
+    """Round-0 parent of each sampled vertex by the definition; -1 without a loop-free record."""
+    keep = src != dst
+    a, b = src[keep], dst[keep]
+
+    def key(x):
+        x = np.asarray(x, dtype=np.uint32)
+        return (spec_priority(seed, 0, x).astype(np.uint64) << np.uint64(32)) | x.astype(np.uint64)
+
+    S = np.unique(np.asarray(sample, dtype=np.uint32))
+    ma, mb = np.isin(a, S), np.isin(b, S)
+    pv = np.concatenate([a[ma], b[mb]])          # (sampled vertex, neighbour) pairs
+    pu = np.concatenate([b[ma], a[mb]])
+    U = np.unique(np.concatenate([S, pu]))
+    # one-hop minimum over the closed neighbourhood of every u in U
+    m1 = key(U)
+    has = np.zeros(U.size, dtype=bool)
+    for x, y in ((a, b), (b, a)):
+        sel = np.isin(x, U)
+        idx = np.searchsorted(U, x[sel])
+        np.minimum.at(m1, idx, key(y[sel]))
+        has[idx] = True
+    # two-hop minimum of the sampled vertices
+    si = np.searchsorted(U, S)
+    lv = m1[si].copy()
+    np.minimum.at(lv, np.searchsorted(S, pv), m1[np.searchsorted(U, pu)])
+    par = (lv & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    par[~has[si]] = -1
+    return S, par
+
+
+def check_partition(labels, comp_min):
+    labels = labels.astype(np.int64)
+    assert labels.min() >= 0 and labels.max() < comp_min.size
+    np.testing.assert_array_equal(comp_min[labels], comp_min)        # label lies in the component
+    assert np.unique(labels).size == np.unique(comp_min).size        # one label per component
+
+
+def solve_full(lc, n, src_t, dst_t, layout, flags, seed):
+    out = {}
+    stream = torch.cuda.current_stream()
+    with lc.Solver(n, src_t, dst_t, seed=seed, flags=flags | lc.CC_PROFILE, stream=stream, layout=layout) as s:
+        st, stats0 = s.contract_round()
+        assert st == lc.CC_OK
+        par, k = s.parents()
+        out["par0"] = par.cpu().numpy().astype(np.int64)
+        rounds = s.run()
+        out["stats"] = s.stats(rounds)
+        out["labels"] = s.labels().cpu().numpy()
+        out["times"] = s.kernel_times()
+    return out
+
+
+def run_full_graph(lc, g, layout, seed, sample_size):
+    n = g.n
+    if layout == "packed":
+        keys = graphgen.pack(g.src, g.dst).view(np.int64)
+        src_t, dst_t, lay = torch.from_numpy(keys).to(DEV), None, lc.CC_EDGES_PACKED_U64
+        del keys
+    else:
+        src_t = torch.from_numpy(g.src.view(np.int32)).to(DEV)
+        dst_t = torch.from_numpy(g.dst.view(np.int32)).to(DEV)
+        lay = lc.CC_EDGES_SOA_I32
+    torch.cuda.synchronize()
+    tiled = solve_full(lc, n, src_t, dst_t, lay, 0, seed)
+    assert tiled["times"]["min1_tiled"][1] == 1          # the default chose the tiled round 0
+    direct = solve_full(lc, n, src_t, dst_t, lay, lc.CC_ROUND0_DIRECT, seed)
+    assert direct["times"]["min1_round0"][1] == 1
+    del src_t, dst_t
+    torch.cuda.empty_cache()
+    assert tiled["stats"] == direct["stats"]
+    np.testing.assert_array_equal(tiled["labels"], direct["labels"])
+    np.testing.assert_array_equal(tiled["par0"], direct["par0"])
+
+    # round 0 statistics with a closed form
+    keep = g.src != g.dst
+    active = np.unique(np.concatenate([g.src[keep], g.dst[keep]])).size
+    r0 = tiled["stats"][0]
+    assert r0[0] == 0 and r0[1] == active and r0[2] == g.m
+
+    # sampled round-0 parents from the definition
+    rng = np.random.default_rng(seed & 0xFFFF)
+    sample = rng.choice(n, size=sample_size, replace=False)
+    S, want = sampled_round0_parents(g.src, g.dst, seed, sample)
+    np.testing.assert_array_equal(tiled["par0"][S], want)
+
+    # labels against union-find
+    check_partition(tiled["labels"], oracle.components_min_id(n, g.src, g.dst).astype(np.int64))
+    return tiled
+
+
+@pytest.mark.timeout(900)
+def test_er_paths_full_size(lc):
+    """G(2^24, 2^27) + 10,000 paths of 1,000 vertices (26,777,216 ids, 144,207,728 records)."""
+    g = graphgen.workload_er_paths()
+    out = run_full_graph(lc, g, "soa32", BENCH_SEED, 2000)
+    assert len(out["stats"]) >= 5           # a 1,000-vertex path needs >= log5(1000) phases (Section 7)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_rmat26_full_size(lc):
+    """R-MAT scale 26, edge factor 16 (1,073,741,824 packed records, 2^26 ids)."""
+    g = graphgen.workload_rmat()
+    run_full_graph(lc, g, "packed", graphgen.CONFIG_SEED_BASE + 2, 500)
+
+
+@pytest.mark.timeout(900)
+def test_batch_4096_sampled(lc):
+    """The 4,096-graph batch of the batched benchmark, default configuration: 96 graphs
+    drawn at random are each checked against the oracle's labels and round count."""
+    b = graphgen.batch_mix()
+    src = torch.from_numpy(b.src.view(np.int32)).to(DEV)
+    dst = torch.from_numpy(b.dst.view(np.int32)).to(DEV)
+    with lc.Batch(b.voff, b.eoff, b.seeds, src, dst) as bt:
+        lab, rounds = bt.run()
+        lab = lab.cpu().numpy()
+    pick = np.random.default_rng(7).choice(b.count, size=96, replace=False)
+    for j in pick:
+        g = b.graph(int(j))
+        want = oracle.run(g.n, g.src, g.dst, seed=int(b.seeds[j]))
+        a = int(b.voff[j])
+        np.testing.assert_array_equal(lab[a:a + g.n].astype(np.uint32), want.labels, err_msg="graph %d" % j)
+        assert rounds[j] == want.rounds, "graph %d" % j
+
+
+@pytest.mark.timeout(900)
+def test_serving_trace_sampled(lc):
+    """The first 24 requests of the serving benchmark's trace (log-uniform sizes up to
+    2^24 vertices), submitted at once: each result equals its solo solve, and the oracle's
+    labels for requests of at most 2^20 vertices."""
+    trace = graphgen.request_trace(graphgen.CONFIG_SEED_BASE + 4, 24, rate=1.0)
+    graphs = [r.graph() for r in trace]
+    dev = [(torch.from_numpy(g.src.view(np.int32)).to(DEV), torch.from_numpy(g.dst.view(np.int32)).to(DEV))
+           for g in graphs]
+    torch.cuda.synchronize()
+    with lc.Server(96 << 30, n_slots=8, small_variant=1, max_small_per_launch=256) as srv:
+        labs = {}
+        for i, (g, r) in enumerate(zip(graphs, trace)):
+            rid, lab = srv.submit(g.n, dev[i][0], dev[i][1], r.seed)
+            labs[rid] = (i, lab)
+        results = srv.drain()
+    assert len(results) == len(trace)
+    for res in results:
+        assert res["status"] == 0
+        i, lab = labs[res["id"]]
+        g, r = graphs[i], trace[i]
+        got = lab.cpu().numpy()
+        solo, rounds, _ = lc.solve(g.n, dev[i][0], dev[i][1], seed=r.seed)
+        np.testing.assert_array_equal(got, solo.cpu().numpy(), err_msg="request %d" % i)
+        assert res["rounds"] == rounds
+        if g.n <= (1 << 20):
+            want = oracle.run(g.n, g.src, g.dst, seed=r.seed)
+            np.testing.assert_array_equal(got.astype(np.uint32), want.labels, err_msg="request %d" % i)
+            assert res["rounds"] == want.rounds

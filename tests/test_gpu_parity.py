@@ -232,3 +232,44 @@ def test_profile_times_kernels(lc):
     assert r2 == r
     assert t["min1_round0"][1] == 0 and t["min1_tiled"][1] == 1 and t["relabel_tiled"][1] == 1
     assert t["part_a_hist"][1] == 1 and t["part_b_scatter"][1] == 1 and t["min1"][1] == r - 1
+
+
+# --- heavy repeats and a hub ------------------------------------------------------------
+
+def dup_path(nv, reps, seed):
+    """A path on nv ids whose every edge is repeated reps times, in shuffled order."""
+    a = np.repeat(np.arange(nv - 1, dtype=np.uint32), reps)
+    perm = np.random.default_rng(seed).permutation(a.size)
+    return graphgen.Graph(nv, a[perm].copy(), (a[perm] + 1).astype(np.uint32))
+
+
+def sun(k, seed):
+    """A centre joined to k paths of six edges; the centre and the first two vertices of
+    every path take the low ids, so after round 0 the merged centre is the smaller
+    endpoint of most edges of the next graph (a hub with about k distinct neighbours)."""
+    c = 0
+    a = 1 + np.arange(k, dtype=np.uint32)
+    b = 1 + k + np.arange(k, dtype=np.uint32)
+    rest = [1 + 2 * k + j * k + np.arange(k, dtype=np.uint32) for j in range(4)]
+    chain = [np.full(k, c, np.uint32), a, b] + rest
+    src = np.concatenate(chain[:-1])
+    dst = np.concatenate(chain[1:])
+    perm = np.random.default_rng(seed).permutation(src.size)
+    return graphgen.Graph(1 + 6 * k, src[perm].copy(), dst[perm].copy())
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+@pytest.mark.parametrize("case", ["dup_path_12", "dup_path_300", "sun_40000"])
+def test_heavy_repeats_and_hub(lc, case, mode):
+    """Survivors with 9,000 repeats of every key (12 and 300 ids), and a hub whose edges to
+    ~40,000 distinct neighbours all share their smaller endpoint: the duplicate drop keeps
+    exactly one copy; bit-exact with the oracle."""
+    seed = 21
+    if case == "dup_path_12":
+        g = dup_path(12, 9000, 1)
+    elif case == "dup_path_300":
+        g = dup_path(300, 9000, 2)
+    else:
+        g = sun(40000, 3)
+    w = check(lc, g, seed, flags=MODES[mode])
+    assert w.stats[0][3] > 2 * w.stats[0][4] or case == "sun_40000"   # many repeats dropped
