@@ -346,9 +346,14 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
         }
         out = w.maps + st->map_off;
     }
+    // newidx is the exclusive scan of has_edge, so p keeps an edge exactly when the next
+    // entry is larger: both come from one cache line (n_next stands in past the end)
+    const uint32_t last = (uint32_t)st->n_next;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const uint32_t p = w.par[i];
-        out[i] = w.has_edge[p] ? w.newidx[p] : (kFinal | (kFirst ? p : names_cur[p]));
+        const uint32_t a = w.newidx[p];
+        const uint32_t b = (int64_t)p + 1 < n ? w.newidx[p + 1] : last;
+        out[i] = b != a ? a : (kFinal | (kFirst ? p : names_cur[p]));
     }
 }
 

@@ -11,8 +11,8 @@
 //            with rho(x); no global atomics (Section 2: x is in its own neighbourhood)
 //   min2     the same with the gathered one-hop minimum m1[y], folded with m1[x], and the
 //            parent written directly (the node whose priority is the two-hop minimum)
-//   relabel  every record with x < y becomes (p(x), p(y)); loops are dropped; survivors go
-//            to fixed output slabs, as the first radix pass expects
+//   relabel  one direction of every record becomes (p(x), p(y)); loops are dropped;
+//            survivors go to fixed output slabs, as the first radix pass expects
 //
 // Rows that run at the same time sweep the column blocks in the same order, so the values
 // gathered at y come from one or two column blocks per XCD, resident in its L2.
@@ -360,9 +360,11 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
     if (broken) atomicOr(&st->err, 4u);
 }
 
-// Relabel the row's records with x < y (each input record once) through the parents.  The
-// row's parents are staged in LDS; the parents at y are gathered from the column block that
-// the concurrent rows share in L2.  The row is walked in chunks aligned to the output slabs
+// Relabel one direction of each record through the parents: (x, y) is taken when
+// (x < y) differs from the parity of x + y, which takes exactly one of (x, y) and (y, x) and
+// about half of every row's records, so all rows advance through the columns at the same
+// pace.  The row's parents are staged in LDS; the parents at y are gathered from the column
+// block that the concurrent rows share in L2.  The row is walked in chunks aligned to the output slabs
 // of kSlab records; a row reserves its survivors' space in a slab with one atomic, so the
 // slab (shared by at most the two rows that meet inside it) is filled from its start.
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp) {
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
 #pragma unroll
             for (int q = 0; q < 2 * kPairs; ++q) {
                 const uint32_t x = (uint32_t)(r[q] >> 32), y = (uint32_t)r[q];
-                v[q] = v[q] && x < y;
+                v[q] = v[q] && ((x < y) != (((x ^ y) & 1u) != 0u));
                 pb[q] = v[q] ? w.par[y] : 0u;
             }
             uint64_t key[2 * kPairs];
