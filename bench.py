@@ -91,11 +91,10 @@ def family_bytes(stats, n0, tiled=False, loops=0):
             add("relabel" + sfx, 8 * M + 4 * N + 8 * s)   # records in, parents in once, survivor keys out
         add("sort_hist", 8 * s * P)                # keys in per pass
         add("sort_scatter", 16 * s * P)            # keys in and out per pass
-        add("unique", 16 * s + 8 * m_out)          # sorted keys read twice, unique keys out
+        add("unique", 16 * s + 8 * m_out + 4 * N)  # sorted keys read twice, renamed unique keys out
         add("node_scan", 6 * N)                    # flags in (twice), index out
         add("nodes", 9 * N)
         add("map", 9 * N)
-        add("rename", 16 * m_out + 4 * N)
     add("compose", 8 * n0)
     return fam
 

@@ -24,7 +24,7 @@ namespace lc {
 const char *const kFamilyNames[kFamilies] = {
     "round_begin", "min1_round0", "min1",      "min2_round0", "min2",      "parent",    "plan_blocks",
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
-    "nodes",       "map",         "rename",    "round_end",   "compose",   "flatten",
+    "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
     "relabel_tiled"};
 
@@ -199,13 +199,12 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kUnique, launch_unique(w, gt, stream, 0));
     RUN(kUnique, launch_unique(w, 1, stream, 1));
-    RUN(kUnique, launch_unique(w, gt, stream, 2));
     RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, gscan_n, stream, 0));
     RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, 1, stream, 1));
     RUN(kNodeScan, launch_scan_u8(w.has_edge, w.newidx, w.partials, &w.st->n_cur, &w.st->n_next, gscan_n, stream, 2));
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
-    RUN(kRename, launch_rename(w, gm, stream));
+    RUN(kUnique, launch_unique(w, gt, stream, 2));
     RUN(kRoundEnd, launch_round_end(w, r, stream));
     return true;
 }

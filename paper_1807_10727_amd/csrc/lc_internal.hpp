@@ -81,7 +81,7 @@ struct Work {
     uint32_t *idx_of;    // [n0] compact index of a name in the current round
     uint32_t *map0;      // [n0] vertex -> node of the first kept level (or kFinal | name)
     uint32_t *maps;      // [n0] arena of the per-round maps of rounds >= 1
-    uint64_t *keys[2];   // [m0] edge / sort key ping-pong buffers
+    uint64_t *keys[2];   // [m0] edge / sort key ping-pong buffers (E_r is keys[e_sel])
     uint32_t *counts;    // [kRadix * sort tiles] digit counts of one sort pass
     uint32_t *partials;  // scan partial sums
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
@@ -176,7 +176,6 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
-hipError_t launch_rename(const Work &w, int grid, hipStream_t s);
 hipError_t launch_round_end(const Work &w, int round, hipStream_t s);
 hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,
                           const uint32_t *voff, int grid, hipStream_t s);
@@ -196,6 +195,7 @@ hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
 // Sort stages: 0 = digit counts, 1..3 = scan of the counts, 4 = scatter.
-// Unique stages: 0 = heads per tile, 1 = scan (one workgroup), 2 = write + mark.
+// Unique stages: 0 = heads per tile + next-node marks, 1 = scan (one workgroup), 2 = ordered
+// write of the heads renamed into the next round's indices (after the node scan and map).
 
 }  // namespace lc

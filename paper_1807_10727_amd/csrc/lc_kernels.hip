@@ -7,8 +7,8 @@
 //   parent       parent of x = the node whose priority is lv[x] (inverse of the bijection)
 //   relabel      every record (a, b) -> (p(a), p(b)); loops dropped; survivors compacted
 //   sort/unique  duplicates dropped (lc_sort.hip)
-//   nodes/map    next node set, names, per-round map of the label composition
-//   rename       edges of the next graph in its compact index space
+//   nodes/map    next node set, names, per-round map of the label composition; then the
+//                unique write emits the next graph's edges in its compact index space
 //   round_end    advance the device state
 // Merged nodes are named by the original id of their parent vertex, and the per-round
 // maps are composed at the end into the label of every original vertex.
@@ -357,21 +357,6 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_rename(Work w) {
-    RoundState *st = w.st;
-    const int64_t m = (int64_t)st->m_next;
-    const int t = sorted_sel(st->round, st->e_sel, st->nbits);
-    const uint64_t *in = w.keys[1 - t];
-    uint64_t *out = w.keys[t];
-    const int kb = st->kb;
-    const uint64_t mask = (1ull << kb) - 1ull;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads) {
-        const uint64_t k = in[i];
-        const uint32_t lo = (uint32_t)((k >> kb) & mask), hi = (uint32_t)(k & mask);
-        out[i] = ((uint64_t)w.newidx[lo] << 32) | w.newidx[hi];
-    }
-}
-
 template <bool kFirst>
 __global__ void k_round_end(Work w) {
     RoundState *st = w.st;
@@ -381,7 +366,7 @@ __global__ void k_round_end(Work w) {
         st->levels += 1;
         st->map_off += st->n_cur;
     }
-    st->e_sel = sorted_sel(st->round, st->e_sel, st->nbits);
+    st->e_sel = 1 - sorted_sel(st->round, st->e_sel, st->nbits);   // the unique write's output
     st->n_cur = st->n_next;
     st->m_cur = st->m_next;
     st->round += 1;
@@ -583,8 +568,6 @@ hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s) {
     if (round == 0) LC_LAUNCH(k_map<true>, grid, w, (const uint32_t *)nullptr);
     LC_LAUNCH(k_map<false>, grid, w, (const uint32_t *)w.names[round & 1]);
 }
-
-hipError_t launch_rename(const Work &w, int grid, hipStream_t s) { LC_LAUNCH(k_rename, grid, w); }
 
 hipError_t launch_round_end(const Work &w, int round, hipStream_t s) {
     if (round == 0) {

@@ -9,8 +9,9 @@
 // stably in LDS (wave ballots find lanes with equal digits; per-wave digit counters give
 // the order across iterations and waves), staged in LDS in sorted order and written out
 // as contiguous runs per digit.
-// Unique: a head flag per sorted key, per-tile counts, one-workgroup scan, ordered write.
-// The unique write also marks both endpoints of every kept edge as nodes of the next graph.
+// Unique: a head flag per sorted key, per-tile counts (which also mark both endpoints of
+// every kept edge as nodes of the next graph), one-workgroup scan; after the next graph's
+// index is known, an ordered write of the heads renamed into it.
 
 #include "lc_internal.hpp"
 
@@ -302,6 +303,8 @@ void k_sort_scatter(Work w, int pass) {
 // unique
 // ---------------------------------------------------------------------------------------
 
+// Heads (first key of every run of equal sorted keys) per tile, and the next graph's node
+// marks: both endpoints of every kept edge (the endpoints of all survivors, the same set).
 __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     RoundState *st = w.st;
     __shared__ uint32_t lds[kSortThreads / kWave + 1];
@@ -309,61 +312,20 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     const int64_t ntiles = ceil_div(S, kSortTile);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;
     const uint64_t *in = w.keys[sorted_sel(st->round, st->e_sel, st->nbits)];
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        uint32_t cnt = 0;
-#pragma unroll 4
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
-            if (idx < S) cnt += (idx == 0 || in[idx] != in[idx - 1]) ? 1u : 0u;
-        }
-        uint32_t total;
-        block_excl_scan<kSortThreads>(cnt, lds, &total);
-        if (threadIdx.x == 0) w.tile_cnt[tile] = total;
-    }
-}
-
-__global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
-    RoundState *st = w.st;
-    __shared__ uint32_t lds[kSortThreads / kWave + 1];
-    const int64_t S = (int64_t)st->s_count;
-    const int64_t ntiles = ceil_div(S, kSortTile);
-    const int t = sorted_sel(st->round, st->e_sel, st->nbits);
-    const uint64_t *in = w.keys[t];
-    uint64_t *out = w.keys[1 - t];
     const int kb = st->kb;
     const uint64_t mask = (1ull << kb) - 1ull;
     const uint64_t n_cur = st->n_cur;
     bool broken = false;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t my = tile * kSortTile + (int64_t)threadIdx.x * kSortItems;
-        uint64_t k[kSortItems];
-        if (my + kSortItems <= S) {
-#pragma unroll
-            for (int q = 0; q < kSortItems / 2; ++q) {
-                ulonglong2 x = *(const ulonglong2 *)(in + my + 2 * q);
-                k[2 * q] = x.x;
-                k[2 * q + 1] = x.y;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kSortItems; ++j) k[j] = my + j < S ? in[my + j] : 0ull;
-        }
-        const uint64_t prev = (my > 0 && my < S) ? in[my - 1] : ~0ull;
         uint32_t cnt = 0;
-        uint32_t heads = 0;
 #pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const bool h = my + j < S && (my + j == 0 || k[j] != (j ? k[j - 1] : prev));
-            heads |= (h ? 1u : 0u) << j;
-            cnt += h;
-        }
-        uint32_t total;
-        uint32_t off = w.tile_cnt[tile] + block_excl_scan<kSortThreads>(cnt, lds, &total);
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            if (heads >> j & 1u) {
-                out[off++] = k[j];
-                const uint64_t lo = (k[j] >> kb) & mask, hi = k[j] & mask;
+        for (int j = 0; j < kSortItems; ++j) {   // consecutive lanes take consecutive keys
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
+            const uint64_t k = idx < S ? in[idx] : 0ull;
+            const uint64_t prev = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
+            if (idx < S && (idx == 0 || k != prev)) {
+                ++cnt;
+                const uint64_t lo = (k >> kb) & mask, hi = k & mask;
                 if (lo < n_cur && hi < n_cur) {
                     w.has_edge[lo] = 1;
                     w.has_edge[hi] = 1;
@@ -372,8 +334,71 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
                 }
             }
         }
+        uint32_t total;
+        block_excl_scan<kSortThreads>(cnt, lds, &total);
+        if (threadIdx.x == 0) w.tile_cnt[tile] = total;
     }
     if (broken) atomicOr(&st->err, 4u);
+}
+
+// The next graph's edge list: the heads, in sorted order, renamed into the next round's
+// compact index space (newidx), written to the other key buffer.  Row j of a tile is the
+// kSortThreads consecutive keys [j * kSortThreads, (j + 1) * kSortThreads): a wave ballot
+// per row and a prefix over (row, wave) give each head its place, so consecutive lanes read,
+// gather and write consecutive keys.
+__global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
+    constexpr int kWaves = kSortThreads / kWave;
+    RoundState *st = w.st;
+    __shared__ uint32_t rowcnt[kSortItems * kWaves];
+    const int64_t S = (int64_t)st->s_count;
+    const int64_t ntiles = ceil_div(S, kSortTile);
+    const int t = sorted_sel(st->round, st->e_sel, st->nbits);
+    const uint64_t *in = w.keys[t];
+    uint64_t *out = w.keys[1 - t];
+    const int kb = st->kb;
+    const uint64_t mask = (1ull << kb) - 1ull;
+    const uint64_t n_cur = st->n_cur;
+    const int wave = threadIdx.x / kWave;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t k[kSortItems];
+        bool h[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
+            k[j] = idx < S ? in[idx] : 0ull;
+            const uint64_t prev = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
+            h[j] = idx < S && (idx == 0 || k[j] != prev);
+        }
+        uint64_t bal[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            bal[j] = ballot(h[j]);
+            if (lane_id() == 0) rowcnt[j * kWaves + wave] = (uint32_t)__popcll(bal[j]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {   // exclusive prefix over (row, wave) in key order
+            uint32_t run = w.tile_cnt[tile];
+            for (int i = 0; i < kSortItems * kWaves; ++i) {
+                const uint32_t c = rowcnt[i];
+                rowcnt[i] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (h[j]) {
+                const uint32_t off = rowcnt[j * kWaves + wave] + (uint32_t)__popcll(bal[j] & lt);
+                const uint64_t lo = (k[j] >> kb) & mask, hi = k[j] & mask;
+                // ids were checked by the count pass (a failed check flags the round)
+                const uint32_t a = lo < n_cur ? w.newidx[lo] : 0u;
+                const uint32_t b = hi < n_cur ? w.newidx[hi] : 0u;
+                out[off] = ((uint64_t)a << 32) | b;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------------------
