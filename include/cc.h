@@ -182,6 +182,14 @@ int32_t cc_kernel_family_count(void);
 const char *cc_kernel_family_name(int32_t i);
 cc_status cc_kernel_times(const cc_ctx *ctx, double *ms, int64_t *launches, int32_t cap);
 
+/*
+ * Restrict CC_PROFILE's events to some families: bit i of family_mask enables family i
+ * (default: all).  Each timed launch costs two event records on the stream, so timing one
+ * family keeps the stream almost as fast as an untimed run.  Applies to launches enqueued
+ * after the call; CC_E_ARG for a null context.
+ */
+cc_status cc_set_profile_mask(cc_ctx *ctx, uint64_t family_mask);
+
 cc_status cc_destroy(cc_ctx *ctx);
 const char *cc_last_error(const cc_ctx *ctx);
 

@@ -19,6 +19,7 @@ from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_serv
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CCError, cc_contract_round, cc_create, cc_destroy, cc_get_round_stats,
                   cc_kernel_family_names, cc_kernel_times, cc_labels, cc_last_error, cc_reset, cc_round_parents,
+                  cc_set_profile_mask,
                   cc_run, cc_set_workspace, cc_version, cc_workspace_size)
 
 __all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_PROFILE", "CC_ROUND0_DIRECT",
@@ -97,6 +98,10 @@ class Solver:
 
     def kernel_times(self):
         return cc_kernel_times(self.ctx)
+
+    def profile_families(self, names=None) -> None:
+        """Time only these kernel families under CC_PROFILE (None: all)."""
+        cc_set_profile_mask(self.ctx, names)
 
     def close(self) -> None:
         if self.ctx:

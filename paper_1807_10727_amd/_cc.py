@@ -93,6 +93,7 @@ _sig = {
     "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "cc_get_round_stats": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.POINTER(cc_round_stats)]),
     "cc_kernel_family_count": (ctypes.c_int32, []),
+    "cc_set_profile_mask": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
     "cc_kernel_family_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "cc_kernel_times": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int32]),
@@ -200,6 +201,18 @@ def cc_get_round_stats(ctx, r: int):
 
 def cc_kernel_family_names():
     return [_lib.cc_kernel_family_name(i).decode() for i in range(_lib.cc_kernel_family_count())]
+
+
+def cc_set_profile_mask(ctx, names) -> None:
+    """Time only the named kernel families under CC_PROFILE (None: all)."""
+    if names is None:
+        mask = (1 << 64) - 1
+    else:
+        fams = cc_kernel_family_names()
+        mask = 0
+        for n in names:
+            mask |= 1 << fams.index(n)
+    _check(ctx, _lib.cc_set_profile_mask(ctx, mask))
 
 
 def cc_kernel_times(ctx):

@@ -106,22 +106,23 @@ bool Engine::hip_ok(hipError_t e, const char *what) {
     return false;
 }
 
-void Engine::ev_begin(int family) {
-    if (!profile) return;
+bool Engine::ev_begin(int family) {
+    if (!profile || !((prof_mask >> family) & 1ull)) return false;
     if (ev_used + 2 > (int)events.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return;
+            if (hipEventCreate(&e) != hipSuccess) return false;
             events.push_back(e);
         }
     }
     (void)hipEventRecord(events[ev_used], stream);
     pending.push_back({family, ev_used});
     ev_used += 2;
+    return true;
 }
 
-void Engine::ev_end() {
-    if (!profile || pending.empty()) return;
+void Engine::ev_end(bool open) {
+    if (!open || pending.empty()) return;
     (void)hipEventRecord(events[pending.back().second + 1], stream);
 }
 
@@ -140,9 +141,9 @@ void Engine::ev_collect() {
 
 #define RUN(fam, expr)                                  \
     do {                                                \
-        ev_begin(fam);                                  \
+        const bool ev_ = ev_begin(fam);                 \
         hipError_t e_ = (expr);                         \
-        ev_end();                                       \
+        ev_end(ev_);                                    \
         if (!hip_ok(e_, kFamilyNames[fam])) return false; \
     } while (0)
 
@@ -355,9 +356,9 @@ cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels) {
     if (c->g.n_vertices == 0) return CC_OK;
     const bool out64 = c->g.layout == CC_EDGES_SOA_I64;
     const int grid = c->grid_for(c->g.n_vertices);
-    c->ev_begin(kCompose);
+    const bool ev = c->ev_begin(kCompose);
     hipError_t e = launch_compose(c->w, !c->ran_first, c->next_round, d_labels, out64, false, nullptr, grid, c->stream);
-    c->ev_end();
+    c->ev_end(ev);
     if (!c->hip_ok(e, "compose")) return CC_E_HIP;
     if (c->o.flags & CC_CANONICAL) {
         e = launch_canonical(c->w, d_labels, out64, false, nullptr, grid, c->stream);
@@ -499,6 +500,12 @@ cc_status cc_get_round_stats(const cc_ctx *c, int32_t r, cc_round_stats *out) {
 int32_t cc_kernel_family_count(void) { return kFamilies; }
 
 const char *cc_kernel_family_name(int32_t i) { return (i >= 0 && i < kFamilies) ? kFamilyNames[i] : nullptr; }
+
+cc_status cc_set_profile_mask(cc_ctx *c, uint64_t family_mask) {
+    if (!c) return CC_E_ARG;
+    c->prof_mask = family_mask;
+    return CC_OK;
+}
 
 cc_status cc_kernel_times(const cc_ctx *c, double *ms, int64_t *launches, int32_t cap) {
     if (!c) return CC_E_ARG;

@@ -35,6 +35,7 @@ struct Engine {
     bool tiled = false;           // round 0 over the tiled record layout
     TPlan tp{};
     bool profile = false;
+    uint64_t prof_mask = ~0ull;   // families timed under CC_PROFILE (bit i: family i)
     bool done = false;
     int grid_cap = 2048;
     void *ws = nullptr;
@@ -61,8 +62,8 @@ struct Engine {
     int grid_for(int64_t units) const;
     int grid_tiles(int64_t keys) const;
     bool hip_ok(hipError_t e, const char *what);
-    void ev_begin(int family);
-    void ev_end();
+    bool ev_begin(int family);   // true when an event pair was opened for this launch
+    void ev_end(bool open);
     void ev_collect();
     // Enqueue round r (only r == 0 and the parity of r matter to the launch sequence).
     // N and M bound the round's nodes and records (exact in eager mode); passes bounds the

@@ -232,6 +232,12 @@ def test_profile_times_kernels(lc):
     assert r2 == r
     assert t["min1_round0"][1] == 0 and t["min1_tiled"][1] == 1 and t["relabel_tiled"][1] == 1
     assert t["part_a_hist"][1] == 1 and t["part_b_scatter"][1] == 1 and t["min1"][1] == r - 1
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE) as s:
+        s.profile_families(["sort_scatter"])
+        s.run()
+        t = s.kernel_times()
+    assert t["sort_scatter"][1] > 0 and t["sort_scatter"][0] > 0
+    assert all(n == 0 for k, (_, n) in t.items() if k != "sort_scatter")
 
 
 # --- heavy repeats and a hub ------------------------------------------------------------
