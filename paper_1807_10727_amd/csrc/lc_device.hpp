@@ -110,6 +110,23 @@ __device__ inline T wave_sum(T x) {
     return x;
 }
 
+// Sum over a block of kThreads (multiple of 64), valid in thread 0.  `lds` holds
+// kThreads/64 entries.  Every thread of the block must call it.
+template <int kThreads, typename T>
+__device__ inline T block_sum(T x, T *lds) {
+    constexpr int kWaves = kThreads / kWave;
+    x = wave_sum(x);
+    if (lane_id() == 0) lds[threadIdx.x / kWave] = x;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kWaves; ++i) r += lds[i];
+    }
+    __syncthreads();
+    return r;
+}
+
 // Exclusive scan over a block of kThreads (multiple of 64).  Returns this thread's
 // exclusive prefix; *total receives the block sum.  `lds` holds kThreads/64 + 1 entries.
 template <int kThreads, typename T>

@@ -209,8 +209,9 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
         if (kBatch) w.g_rounds[kFirst ? w.gid0[i] : gids[i]] = st->round + 1;
         ++active;
     }
-    active = wave_sum(active);
-    if (lane_id() == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+    __shared__ uint32_t red[kThreads / kWave];
+    active = block_sum<kThreads>(active, red);   // one atomic per workgroup
+    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
     if (broken) atomicOr(&st->err, 4u);
 }
 
@@ -282,8 +283,9 @@ __global__ __launch_bounds__(kThreads) void k_count_labels(Work w) {
     uint32_t c = 0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
         c += w.is_label[i];
-    c = wave_sum(c);
-    if (lane_id() == 0 && c) atomicAdd(&st->n_labels, (u64c)c);
+    __shared__ uint32_t red[kThreads / kWave];
+    c = block_sum<kThreads>(c, red);
+    if (threadIdx.x == 0 && c) atomicAdd(&st->n_labels, (u64c)c);
 }
 
 // Block width for the next round's edge order: about kBlockNodes parents per block,
@@ -327,8 +329,9 @@ __global__ __launch_bounds__(kThreads) void k_nodes(Work w, const uint32_t *name
             ++fin;
         }
     }
-    fin = wave_sum(fin);
-    if (lane_id() == 0 && fin) atomicAdd(&st->n_final, (u64c)fin);
+    __shared__ uint32_t red[kThreads / kWave];
+    fin = block_sum<kThreads>(fin, red);
+    if (threadIdx.x == 0 && fin) atomicAdd(&st->n_final, (u64c)fin);
 }
 
 template <bool kFirst>

@@ -354,8 +354,9 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
         __syncthreads();
     }
     if (kStep == 2) {
-        active = wave_sum(active);
-        if (lane_id() == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+        __shared__ uint32_t red[kTRowThreads / kWave];
+        active = block_sum<kTRowThreads>(active, red);
+        if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
     }
     if (broken) atomicOr(&st->err, 4u);
 }
