@@ -88,7 +88,7 @@ __global__ void k_state_init(RoundState *st, int64_t n0, int64_t m0, int64_t map
         st->round = 0;
         st->nbits = 0;
         st->kb = 0;
-        st->hb_shift = 63;
+        st->hb_shift = 0;
         st->e_sel = 0;
         st->done = m0 == 0 ? 1 : 0;
         st->levels = 0;
@@ -343,7 +343,7 @@ bool enqueue_union_round(cc_batch *b, int r) {
     pc.keys = b->d_keys;
     pc.voff = b->d_voff32;
     const int kb = ceil_log2_host(std::max<int64_t>(b->w.n0, 2));
-    const int passes = npasses(std::min(64, 2 * kb + std::max(0, kb - 17)));
+    const int passes = npasses(2 * kb);
     return b->enqueue_round(r, b->w.n0, std::max<int64_t>(b->union_m, 1), pc, passes);
 }
 

@@ -154,9 +154,8 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
     const int gscan_n = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), kScanTile), grid_cap);
-    // key bits: 2 kb plus at most kb - 17 block bits (blocks are >= 2^17 indices wide)
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
-    const int nbits = std::min(64, 2 * kb + std::max(0, kb - 17));
+    const int nbits = 2 * kb;   // edge_key
     const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
     // the tiled round 0 hands the first radix pass up to twice as many slab tiles
     const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(first && tiled ? 2 * M : M, 1), kSortTile) + 2);

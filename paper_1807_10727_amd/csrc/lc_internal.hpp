@@ -32,7 +32,7 @@ struct RoundState {
     int32_t done;      // no edge left
     int32_t levels;    // per-round maps in the arena
     int32_t kb;        // bits per endpoint in this round's sort keys: ceil(log2 N_r)
-    int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (63: one block)
+    int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (kb: one block)
     int32_t pad0_;
     u64c t_count;      // round 0, tiled layout: directed records (twice the loop-free inputs)
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
@@ -103,13 +103,29 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
-// Sort keys are (block(hi) << 2kb) | (lo << kb) | hi, so the next round reads its edges
-// grouped by the block of their larger endpoint.  A block spans about kBlockNodes next-round
-// nodes: their 8-byte node words (2 MiB) stay resident in one XCD's 4 MiB L2 while the
-// round streams that block's edges, and lo is swept in increasing order within the block.
-constexpr int64_t kBlockNodes = 1 << 18;
+// Sort keys (edge_key) order edges by the block of hi, then lo, then hi, so the next round
+// reads its edges grouped by the block of their larger endpoint.  A block spans about
+// kBlockNodes next-round nodes, and lo is swept in increasing order within the block.  Wider
+// blocks mean fewer sweeps over lo (better for the min passes), narrower ones keep hi's node
+// state in L2 (better for the next-node marks); 2^19 measured best on the bench graph.
+#ifndef LC_BLOCK_NODES_LOG2
+#define LC_BLOCK_NODES_LOG2 19
+#endif
+constexpr int64_t kBlockNodes = 1 << LC_BLOCK_NODES_LOG2;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Sort key of an edge lo < hi between indices of a round with b = ceil(log2 N) bits per
+// index: hi's block (hi >> s), then lo, then hi's s bits below the block.  The block number
+// is hi's top b - s bits, so the key has 2 b bits whatever the block width; s = b when the
+// round has a single block.
+__host__ __device__ inline uint64_t edge_key(uint32_t lo, uint32_t hi, int kb, int s) {
+    return ((uint64_t)(hi >> s) << (kb + s)) | ((uint64_t)lo << s) | (uint64_t)(hi & ((1u << s) - 1u));
+}
+__host__ __device__ inline void edge_key_split(uint64_t k, int kb, int s, uint64_t &lo, uint64_t &hi) {
+    lo = (k >> s) & ((1ull << kb) - 1ull);
+    hi = ((k >> (kb + s)) << s) | (k & ((1ull << s) - 1ull));
+}
 
 // Which key buffer each step uses, from the device state (identical on host and device).
 __host__ __device__ inline int npasses(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
         st->n_final = 0;
         st->n_labels = 0;
         st->kb = ceil_log2(n < 2 ? 2 : (uint64_t)n);
-        st->hb_shift = 63;
+        st->hb_shift = st->kb;
         st->nbits = 2 * st->kb;
     }
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
                 for (int j = 0; j < V; ++j) {
                     keep[j] = pa[j] != pb[j];
                     const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
-                    key[j] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
+                    key[j] = edge_key(lo, hi, kb, hbs);
                     cnt += keep[j];
                 }
             } else {
@@ -289,27 +289,20 @@ __global__ __launch_bounds__(kThreads) void k_count_labels(Work w) {
 }
 
 // Block width for the next round's edge order: about kBlockNodes parents per block,
-// assuming parents spread evenly over this round's indices; its bits join the sort key.
+// assuming parents spread evenly over this round's indices (the key keeps 2 kb bits).
 __global__ void k_plan_blocks(Work w) {
     RoundState *st = w.st;
     const uint64_t N = st->n_cur, L = st->n_labels;
     const int kb = st->kb;
-    int shift = 63, hb_bits = 0;
+    int shift = kb;
     if (L > 0 && N > 0) {
         uint64_t width = (uint64_t)kBlockNodes * N / L;
         if (width < 1) width = 1;
         shift = 63 - __clzll((long long)width);              // floor(log2(width))
-        const uint64_t blocks = (N + (1ull << shift) - 1) >> shift;
-        hb_bits = blocks <= 1 ? 0 : ceil_log2(blocks);
-        const int cap = 64 - 2 * kb;
-        if (hb_bits > cap) {
-            hb_bits = cap > 0 ? cap : 0;
-            shift = hb_bits > 0 ? kb - hb_bits : 63;
-        }
-        if (hb_bits == 0) shift = 63;
+        if (shift > kb) shift = kb;
     }
     st->hb_shift = shift;
-    st->nbits = 2 * kb + hb_bits;
+    st->nbits = 2 * kb;
 }
 
 template <bool kFirst, bool kBatch>

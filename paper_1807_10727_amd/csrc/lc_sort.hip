@@ -236,25 +236,32 @@ void k_sort_scatter(Work w, int pass) {
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
+        // this tile's global digit offsets: loaded now, used after the ranking
+        const uint32_t my_gofs = threadIdx.x < kRadix ? w.counts[(int64_t)threadIdx.x * ntiles + tile] : 0u;
         for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
 
+        // Slab tiles of the first pass are often partly or wholly empty: positions past tv
+        // are neither ranked nor staged, and rows of the tile with no valid key are skipped.
         uint64_t k[kSortItems];
         uint32_t rk[kSortItems];
         const int wbase = wave * (kSortItems * kWave);
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const int it = wbase + j * kWave + lane;
-            k[j] = it < tv ? in[tile * kSortTile + it] : ~0ull;   // padding sorts last within its tile
+            k[j] = it < tv ? in[tile * kSortTile + it] : ~0ull;
         }
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
+            if (wbase + j * kWave >= tv) break;   // uniform over the wave
+            const bool valid = wbase + j * kWave + lane < tv;
             const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
-            const uint64_t peers = match_bits<kRadixBits>(d, ~0ull);
-            const uint32_t cur = wcnt[wave][d];
+            const uint64_t peers = match_bits<kRadixBits>(d, ballot(valid));
+            uint32_t cur = 0;
+            if (valid) cur = wcnt[wave][d];
             rk[j] = cur + (uint32_t)__popcll(peers & lt);
             __builtin_amdgcn_wave_barrier();
-            if (is_leader(peers)) wcnt[wave][d] = cur + (uint32_t)__popcll(peers);
+            if (valid && is_leader(peers)) wcnt[wave][d] = cur + (uint32_t)__popcll(peers);
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
@@ -274,15 +281,17 @@ void k_sort_scatter(Work w, int pass) {
             const uint32_t ds = block_excl_scan<kSortThreads>(run, lds, &total);
             if (d < kRadix) {
                 dstart[d] = ds;
-                gofs[d] = w.counts[(int64_t)d * ntiles + tile];
+                gofs[d] = my_gofs;
             }
         }
         __syncthreads();
 
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
-            const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
-            skeys[dstart[d] + wcnt[wave][d] + rk[j]] = k[j];
+            if (wbase + j * kWave + lane < tv) {
+                const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
+                skeys[dstart[d] + wcnt[wave][d] + rk[j]] = k[j];
+            }
         }
         __syncthreads();
 
@@ -313,7 +322,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;
     const uint64_t *in = w.keys[sorted_sel(st->round, st->e_sel, st->nbits)];
     const int kb = st->kb;
-    const uint64_t mask = (1ull << kb) - 1ull;
+    const int hbs = st->hb_shift;
     const uint64_t n_cur = st->n_cur;
     bool broken = false;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -325,7 +334,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
             const uint64_t prev = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
             if (idx < S && (idx == 0 || k != prev)) {
                 ++cnt;
-                const uint64_t lo = (k >> kb) & mask, hi = k & mask;
+                uint64_t lo, hi;
+                edge_key_split(k, kb, hbs, lo, hi);
                 if (lo < n_cur && hi < n_cur) {
                     w.has_edge[lo] = 1;
                     w.has_edge[hi] = 1;
@@ -356,7 +366,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     const uint64_t *in = w.keys[t];
     uint64_t *out = w.keys[1 - t];
     const int kb = st->kb;
-    const uint64_t mask = (1ull << kb) - 1ull;
+    const int hbs = st->hb_shift;
     const uint64_t n_cur = st->n_cur;
     const int wave = threadIdx.x / kWave;
     const uint64_t lt = lanemask_lt();
@@ -390,7 +400,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
         for (int j = 0; j < kSortItems; ++j) {
             if (h[j]) {
                 const uint32_t off = rowcnt[j * kWaves + wave] + (uint32_t)__popcll(bal[j] & lt);
-                const uint64_t lo = (k[j] >> kb) & mask, hi = k[j] & mask;
+                uint64_t lo, hi;
+                edge_key_split(k[j], kb, hbs, lo, hi);
                 // ids were checked by the count pass (a failed check flags the round)
                 const uint32_t a = lo < n_cur ? w.newidx[lo] : 0u;
                 const uint32_t b = hi < n_cur ? w.newidx[hi] : 0u;

@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
                 }
                 v[q] = v[q] && pa != pb[q];
                 const uint32_t lo = min(pa, pb[q]), hi = max(pa, pb[q]);
-                key[q] = (((uint64_t)hi >> hbs) << (2 * kb)) | ((uint64_t)lo << kb) | hi;
+                key[q] = edge_key(lo, hi, kb, hbs);
                 c += v[q];
             }
             uint32_t total;
