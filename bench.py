@@ -55,7 +55,7 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0, tiled=False, loops=0):
+def family_bytes(stats, n0, tiled=False, loops=0, in_graph=None):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
@@ -65,14 +65,21 @@ def family_bytes(stats, n0, tiled=False, loops=0):
     records are written once, re-read by the row pass and read by each row kernel."""
     fam = {}
 
-    def add(k, v):
+    def add_family(k, v):
         fam[k] = fam.get(k, 0) + v
+
+    def add_tail(_k, v):
+        fam["tail_graph"] = fam.get("tail_graph", 0) + v
 
     for (r, n_active, m_in, s, m_out, _fin) in stats:
         N = n0 if r == 0 else n_active
         M = m_in
-        P = (2 * ceil_log2(max(N, 2)) + 7) // 8
+        P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
         sfx = "_round0" if r == 0 else ""
+        if in_graph is not None and in_graph[r]:   # timed as one captured tail
+            add = add_tail
+        else:
+            add = add_family
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
         add("plan_blocks", N)                      # parent flags in
         if r == 0 and tiled:
@@ -95,7 +102,7 @@ def family_bytes(stats, n0, tiled=False, loops=0):
         add("node_scan", 6 * N)                    # flags in (twice), index out
         add("nodes", 9 * N)
         add("map", 9 * N)
-    add("compose", 8 * n0)
+    fam["compose"] = fam.get("compose", 0) + 8 * n0
     return fam
 
 
@@ -396,10 +403,11 @@ def main():
             acc_ms[k] = acc_ms.get(k, 0.0) + ms
             acc_n[k] = acc_n.get(k, 0) + n
 
-    def fam_bytes_of(stats_list, launches):
+    def fam_bytes_of(stats_list, launches, graph_flags):
         out = {}
-        for st in stats_list:
-            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops).items():
+        for st, gf in zip(stats_list, graph_flags):
+            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
+                                     in_graph=gf).items():
                 out[k] = out.get(k, 0) + v
         return out
 
@@ -414,21 +422,23 @@ def main():
     # Warm-up steps time every kernel family; the dominant one (largest kernel time) is then
     # the only family timed during the measured steps, so that the events of the others do
     # not slow the stream down.
-    warm_ms, warm_n, warm_stats = {}, {}, []
+    warm_ms, warm_n, warm_stats, warm_graph = {}, {}, [], []
     for i in range(args.warmup):
         r = step(1000 + i)
         warm_stats.append(solver.stats(r))
+        warm_graph.append(solver.rounds_in_graph(r))
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom = None
     if not args.no_profile and warm_ms:
-        warm_bytes = fam_bytes_of(warm_stats, warm_n)
+        warm_bytes = fam_bytes_of(warm_stats, warm_n, warm_graph)
         log_families("warm-up", warm_ms, warm_n, warm_bytes, args.warmup)
         log("warm-up: sum of kernel time per step %.3f ms" % (sum(warm_ms.values()) / args.warmup))
         dom = max((k for k in warm_ms if k in warm_bytes and warm_n[k] > 0), key=lambda k: warm_ms[k])
         solver.profile_families([dom])
     solver.reset(base_seed)            # clears the per-kernel timers too
     all_stats = []
+    all_graph = []
     rounds = []
     fam_ms = {}
     fam_n = {}
@@ -438,6 +448,7 @@ def main():
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
+        all_graph.append(solver.rounds_in_graph(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -448,7 +459,7 @@ def main():
         log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st)
 
     # algorithmic bytes per family over the timed steps
-    fam_bytes = fam_bytes_of(all_stats, fam_n if dom is None else warm_n)
+    fam_bytes = fam_bytes_of(all_stats, fam_n if dom is None else warm_n, all_graph)
     job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
 
     roofline = None

@@ -93,20 +93,29 @@ enum {
     CC_CANONICAL = 1u << 0,     /* cc_labels writes the smallest original id of each component */
     CC_PROFILE = 1u << 1,       /* time every kernel with HIP events (see cc_kernel_times) */
     CC_ROUND0_DIRECT = 1u << 2, /* round 0 reads the input records directly */
-    CC_ROUND0_TILED = 1u << 3   /* round 0 over the tiled record layout */
+    CC_ROUND0_TILED = 1u << 3,  /* round 0 over the tiled record layout */
+    CC_EAGER = 1u << 4          /* cc_run enqueues every round on its own (no captured tail) */
 };
+
+/* cc_run and captured tails.  Once the remaining graph of a solve has at most 2^22
+ * records, cc_run replays a hipGraph of up to 8 rounds (captured on first use, kept per
+ * context and reused while the rounded-up sizes match) instead of enqueuing each round and
+ * reading its state back: small rounds are otherwise bound by launch overhead.  Results are
+ * identical; rounds run this way have in_graph = 1 in their statistics, their kernels are
+ * timed together as the family "tail_graph", and cc_round_parents is not available for
+ * them.  CC_EAGER turns this off (cc_contract_round never uses it). */
 
 typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
     int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
-    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED */
+    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED | CC_EAGER */
     void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
 } cc_options;
 
 /* Statistics of one round (all counts exact). */
 typedef struct {
     int32_t round;        /* r, from 0 */
-    int32_t reserved;
+    int32_t in_graph;     /* 1 when the round ran inside a captured tail (see cc_run) */
     int64_t n_active;     /* nodes with at least one loop-free edge in this round */
     int64_t m_in;         /* records read: the raw input count in round 0, |E_r| after */
     int64_t m_survive;    /* records whose two endpoints get different parents (repeats counted) */

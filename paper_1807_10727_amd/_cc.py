@@ -27,6 +27,7 @@ CC_CANONICAL = 1 << 0
 CC_PROFILE = 1 << 1
 CC_ROUND0_DIRECT = 1 << 2
 CC_ROUND0_TILED = 1 << 3
+CC_EAGER = 1 << 4
 
 
 class cc_graph_desc(ctypes.Structure):
@@ -40,7 +41,7 @@ class cc_options(ctypes.Structure):
 
 
 class cc_round_stats(ctypes.Structure):
-    _fields_ = [("round", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_active", ctypes.c_int64),
+    _fields_ = [("round", ctypes.c_int32), ("in_graph", ctypes.c_int32), ("n_active", ctypes.c_int64),
                 ("m_in", ctypes.c_int64), ("m_survive", ctypes.c_int64), ("m_out", ctypes.c_int64),
                 ("n_finalised", ctypes.c_int64)]
 
@@ -193,10 +194,10 @@ def cc_round_parents(ctx, ptr: int) -> int:
     return int(n.value)
 
 
-def cc_get_round_stats(ctx, r: int):
+def cc_get_round_stats(ctx, r: int, with_graph_flag: bool = False):
     s = cc_round_stats()
     _check(ctx, _lib.cc_get_round_stats(ctx, r, ctypes.byref(s)))
-    return s.as_tuple()
+    return s.as_tuple() + ((s.in_graph,) if with_graph_flag else ())
 
 
 def cc_kernel_family_names():

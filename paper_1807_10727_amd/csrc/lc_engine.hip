@@ -26,7 +26,7 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled"};
+    "relabel_tiled", "tail_graph"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -224,10 +224,11 @@ bool Engine::read_state() {
     return true;
 }
 
-bool Engine::write_initial_state(int64_t n_cur, int64_t m_cur) {
+bool Engine::write_initial_state(int64_t n_cur, int64_t m_cur, uint64_t seed) {
     memset(h_st, 0, sizeof(RoundState));
     h_st->n_cur = (u64c)n_cur;
     h_st->m_cur = (u64c)m_cur;
+    h_st->seed = seed;
     h_st->map_cap = (u64c)std::max<int64_t>(w.n0, 1);
     // ordered before every later kernel on the stream; the host buffer is next written by
     // the state readback of round 0, which the stream also orders after this copy
@@ -279,13 +280,14 @@ cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     c->host_map_used = 0;
     c->n_cur = c->g.n_vertices;
     c->m_cur = c->g.n_edges;
+    c->last_graph_round = -1;
     c->failed_status = 0;
     c->err.clear();
     for (int i = 0; i < kFamilies; ++i) {
         c->fam_ms[i] = 0.0;
         c->fam_launches[i] = 0;
     }
-    if (!c->write_initial_state(c->n_cur, c->m_cur)) return hip_status(c);
+    if (!c->write_initial_state(c->n_cur, c->m_cur, seed)) return hip_status(c);
     return CC_OK;
 }
 
@@ -369,6 +371,118 @@ cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels) {
 }  // namespace lc
 
 namespace {
+
+cc_status round_once(cc_ctx *c, cc_round_stats *out);
+
+constexpr int kTailRounds = 8;                 // rounds per captured tail
+constexpr int64_t kTailMaxRecords = 1 << 22;   // remaining graph small enough for a tail
+
+int64_t pow2_ceil(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+constexpr size_t kTailCache = 6;               // captured tails kept per context
+
+void drop_tails(cc_ctx *c) {
+    for (auto &t : c->tails) (void)hipGraphExecDestroy(t.exec);
+    c->tails.clear();
+}
+
+bool tail_wanted(const cc_ctx *c) {
+    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->next_round >= 1 && !c->done && c->m_cur > 0 &&
+           c->m_cur <= kTailMaxRecords;
+}
+
+// Capture kTailRounds rounds sized for (Nb, Mb) on a private stream.  The kernels read
+// every count and the round's priority key from the device state, so the graph serves any
+// solve whose remaining sizes round up to the same bounds and whose next round has the
+// same parity (names and gids alternate between two buffers).
+hipGraphExec_t capture_tail(cc_ctx *c, int64_t Nb, int64_t Mb) {
+    if (!c->cap_stream && !c->hip_ok(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "capture stream"))
+        return nullptr;
+    hipStream_t user = c->stream;
+    const bool prof = c->profile;
+    c->stream = c->cap_stream;
+    c->profile = false;   // no events inside a captured graph
+    bool ok = c->hip_ok(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    PrioCtx pc{};
+    for (int i = 0; ok && i < kTailRounds; ++i) ok = c->enqueue_round(c->next_round + i, Nb, Mb, pc);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    c->profile = prof;
+    hipGraphExec_t exec = nullptr;
+    if (ok) ok = c->hip_ok(e, "end capture");
+    if (ok) ok = c->hip_ok(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "graph instantiate");
+    if (g) (void)hipGraphDestroy(g);
+    return ok ? exec : nullptr;
+}
+
+hipGraphExec_t tail_for(cc_ctx *c, int64_t Nb, int64_t Mb) {
+    const int parity = c->next_round & 1;
+    for (auto &t : c->tails) {
+        if (t.N == Nb && t.M == Mb && t.parity == parity && t.ws == c->ws) {
+            t.used = ++c->tail_clock;
+            return t.exec;
+        }
+    }
+    hipGraphExec_t exec = capture_tail(c, Nb, Mb);
+    if (!exec) return nullptr;
+    if (c->tails.size() >= kTailCache) {   // replace the least recently used
+        size_t victim = 0;
+        for (size_t i = 1; i < c->tails.size(); ++i)
+            if (c->tails[i].used < c->tails[victim].used) victim = i;
+        (void)hipGraphExecDestroy(c->tails[victim].exec);
+        c->tails.erase(c->tails.begin() + (long)victim);
+    }
+    c->tails.push_back({exec, Nb, Mb, parity, c->ws, ++c->tail_clock});
+    return exec;
+}
+
+// Up to kTailRounds rounds from one captured graph and one readback.
+cc_status run_tail(cc_ctx *c) {
+    const int64_t Nb = pow2_ceil(std::max<int64_t>(c->n_cur, 2));
+    const int64_t Mb = pow2_ceil(std::max<int64_t>(c->m_cur, 2));
+    const int64_t cap = std::max<int64_t>(c->g.n_vertices, 1);
+    auto room = [&]() {
+        return std::min<int64_t>((cap - c->host_map_used) / Nb, (int64_t)(kMaxLevels - c->host_levels));
+    };
+    if (room() < kTailRounds && !c->flatten()) return hip_status(c);
+    if (room() < kTailRounds || c->next_round + kTailRounds > kStatRounds) return round_once(c, nullptr);
+    hipGraphExec_t exec = tail_for(c, Nb, Mb);
+    if (!exec) return hip_status(c);
+    const bool ev = c->ev_begin(kTailGraph);
+    const hipError_t e = hipGraphLaunch(exec, c->stream);
+    c->ev_end(ev);
+    if (!c->hip_ok(e, "graph launch")) return hip_status(c);
+    if (!c->read_state()) return hip_status(c);
+    const RoundState &st = *c->h_st;
+    if (st.err & 1u) return fail(c, CC_E_INPUT, "an edge record names a vertex outside [0, n_vertices)");
+    if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
+    const int end = st.rounds_active;
+    for (int r = c->next_round; r < end; ++r) {
+        cc_round_stats s{};
+        s.round = r;
+        s.in_graph = 1;
+        s.n_active = (int64_t)st.rstats[r][1];
+        s.m_in = (int64_t)st.rstats[r][2];
+        s.m_survive = (int64_t)st.rstats[r][3];
+        s.m_out = (int64_t)st.rstats[r][4];
+        s.n_finalised = (int64_t)st.rstats[r][5];
+        c->stats.push_back(s);
+    }
+    c->rounds = end;
+    c->next_round = end;
+    c->last_graph_round = end - 1;
+    c->host_levels = st.levels;
+    c->host_map_used = (int64_t)st.map_off;
+    c->n_cur = (int64_t)st.n_cur;
+    c->m_cur = (int64_t)st.m_cur;
+    c->done = st.m_cur == 0;
+    return c->done ? CC_DONE : CC_OK;
+}
 
 // one round, synchronously; returns CC_OK, CC_DONE or an error
 cc_status round_once(cc_ctx *c, cc_round_stats *out) {
@@ -461,7 +575,7 @@ cc_status cc_run(cc_ctx *c, int32_t *rounds) {
     if (!c) return CC_E_ARG;
     for (;;) {
         if (c->o.max_rounds > 0 && c->next_round >= c->o.max_rounds) break;
-        cc_status s = round_once(c, nullptr);
+        cc_status s = tail_wanted(c) ? run_tail(c) : round_once(c, nullptr);
         if (s == CC_DONE) break;
         if (s != CC_OK) return s;
     }
@@ -483,6 +597,8 @@ cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {
     if (c->failed_status) return c->failed_status;
     if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
     const int last = c->next_round - 1;
+    if (last == c->last_graph_round)
+        return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
     hipError_t e = launch_dump_parents(c->w, d_parents, last, c->grid_for(c->g.n_vertices), c->stream);
     if (!c->hip_ok(e, "dump parents")) return CC_E_HIP;
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
@@ -519,6 +635,8 @@ cc_status cc_destroy(cc_ctx *c) {
     if (!c) return CC_E_ARG;
     (void)hipStreamSynchronize(c->stream);
     for (auto e : c->events) (void)hipEventDestroy(e);
+    drop_tails(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_st) {
         if (c->h_st_pageable)
             free(c->h_st);

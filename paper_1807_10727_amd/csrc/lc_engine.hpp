@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kPlanBlocks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kFamilies
+    kTailGraph, kFamilies
 };
 extern const char *const kFamilyNames[kFamilies];
 
@@ -71,7 +71,7 @@ struct Engine {
     bool enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int passes = -1);
     bool flatten();
     bool read_state();
-    bool write_initial_state(int64_t n_cur, int64_t m_cur);
+    bool write_initial_state(int64_t n_cur, int64_t m_cur, uint64_t seed = 0);
 };
 
 }  // namespace lc
@@ -87,6 +87,18 @@ struct cc_ctx : public lc::Engine {
     bool labels_ready = false;
     int64_t n_cur = 0, m_cur = 0;
     int64_t pending_N = 0, pending_M = 0;   // bounds of the round in flight
+    int32_t last_graph_round = -1;          // last round run inside a captured tail
+    // captured tails of rounds (cc_run), replayed while the rounded-up sizes match
+    struct Tail {
+        hipGraphExec_t exec;
+        int64_t N, M;
+        int parity;
+        void *ws;
+        uint64_t used;   // last use, for replacement
+    };
+    hipStream_t cap_stream = nullptr;
+    std::vector<Tail> tails;
+    uint64_t tail_clock = 0;
 };
 
 namespace lc {

@@ -11,6 +11,7 @@ namespace lc {
 typedef unsigned long long u64c;  // type of 64-bit device atomics
 
 constexpr int kMaxLevels = 64;    // per-round maps kept before they are folded into map0
+constexpr int kStatRounds = 128;  // rounds whose statistics the device keeps (plain solve)
 
 // Device-resident state of the current round.  Every kernel reads its element counts
 // from here, so a sequence of rounds can be enqueued (or captured in a graph) without
@@ -35,6 +36,10 @@ struct RoundState {
     int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (kb: one block)
     int32_t pad0_;
     u64c t_count;      // round 0, tiled layout: directed records (twice the loop-free inputs)
+    uint64_t seed;     // priority seed of a plain solve
+    RoundKey key;      // this round's priority key, round_key(seed, round) (plain solve)
+    int32_t rounds_active;   // rounds so far that read at least one record
+    int32_t pad1_;
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
     alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
@@ -44,6 +49,9 @@ struct RoundState {
     alignas(128) u64c m_next;     // distinct edges of the next graph (one workgroup)
     u64c n_next;                  // nodes of the next graph (one workgroup)
     alignas(128) u64c level_off[kMaxLevels];
+    // statistics of every round that read records (round, n_active, m_in, survivors, m_out,
+    // n_final), so that rounds enqueued back to back need a single readback
+    u64c rstats[kStatRounds][6];
 };
 
 enum Layout { kSoa32 = 0, kSoa64 = 1, kPacked = 2 };

@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
         st->kb = ceil_log2(n < 2 ? 2 : (uint64_t)n);
         st->hb_shift = st->kb;
         st->nbits = 2 * st->kb;
+        st->key = round_key(st->seed, st->round);
     }
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         ((uint64_t *)w.ml)[i] = ~0ull;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, con
                                                    const uint32_t *gids) {
     constexpr int V = R::kV;
     rd.init(w.st);
+    if (!kBatch) pc.key = w.st->key;
     const int64_t nch = rd.chunks();
     uint32_t *m1 = w.ml;   // one-hop minimum of node x at m1[2x]
     bool bad = false;
@@ -178,6 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
 template <bool kFirst, bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const uint32_t *gids) {
     RoundState *st = w.st;
+    if (!kBatch) pc.key = st->key;
     const int64_t n = (int64_t)st->n_cur;
     uint32_t active = 0;
     bool broken = false;
@@ -356,6 +359,19 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
 template <bool kFirst>
 __global__ void k_round_end(Work w) {
     RoundState *st = w.st;
+    if (st->m_cur > 0) {
+        const int r = st->round;
+        if (r < kStatRounds) {
+            u64c *s = st->rstats[r];
+            s[0] = (u64c)r;
+            s[1] = st->n_active;
+            s[2] = st->m_cur;
+            s[3] = st->s_count;
+            s[4] = st->m_next;
+            s[5] = st->n_final;
+        }
+        st->rounds_active = r + 1;
+    }
     st->n_prev = st->n_cur;
     if (!kFirst && st->n_cur > 0 && !(st->err & 2u)) {
         st->level_off[st->levels] = st->map_off;

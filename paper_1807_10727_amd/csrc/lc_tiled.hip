@@ -288,6 +288,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
     constexpr int kUnroll = kStep == 1 ? 4 : LC_TMIN2_PAIRS;   // record pairs in flight per thread
     __shared__ uint32_t acc[1 << kTxShiftMax];
     RoundState *st = w.st;
+    pc.key = st->key;
     const int64_t T = (int64_t)st->t_count;
     const int64_t nt = tiles_b_of(st);
     const int64_t n = (int64_t)st->n_cur;

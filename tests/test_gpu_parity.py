@@ -221,12 +221,12 @@ def test_edge_order_does_not_matter(lc):
 def test_profile_times_kernels(lc):
     g = graphgen.workload_small()
     s_t, d_t, _ = to_device(g)
-    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE) as s:
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE | lc.CC_EAGER) as s:
         r = s.run()
         t = s.kernel_times()
     assert t["min1_round0"][1] == 1 and t["min1"][1] == r - 1 and t["min1_tiled"][1] == 0
     assert t["min1_round0"][0] > 0 and t["sort_scatter"][0] > 0
-    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE | lc.CC_ROUND0_TILED) as s:
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_PROFILE | lc.CC_ROUND0_TILED | lc.CC_EAGER) as s:
         r2 = s.run()
         t = s.kernel_times()
     assert r2 == r
@@ -279,3 +279,29 @@ def test_heavy_repeats_and_hub(lc, case, mode):
         g = sun(40000, 3)
     w = check(lc, g, seed, flags=MODES[mode])
     assert w.stats[0][3] > 2 * w.stats[0][4] or case == "sun_40000"   # many repeats dropped
+
+
+def test_captured_tail_matches_eager_and_oracle(lc):
+    """cc_run replays a captured graph of rounds once the remaining graph is small: the same
+    statistics and labels as eager rounds and as the oracle, for consecutive solves with
+    different seeds on one context (the graph is reused), and for a graph of many rounds."""
+    g = graphgen.er_with_paths(17, 1 << 11, 1 << 12, 30, 700)
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=1) as tail, lc.Solver(g.n, s_t, d_t, seed=1, flags=lc.CC_EAGER) as eager:
+        for seed in (11, 12, 13, 11):
+            tail.reset(seed)
+            eager.reset(seed)
+            rt, re_ = tail.run(), eager.run()
+            want = oracle.run(g.n, g.src, g.dst, seed=seed)
+            assert rt == re_ == want.rounds
+            assert [tuple(x) for x in tail.stats(rt)] == [tuple(x) for x in want.stats]
+            assert tail.stats(rt) == eager.stats(re_)
+            flags = tail.rounds_in_graph(rt)
+            assert not flags[0] and any(flags) and not any(eager.rounds_in_graph(re_))
+            lt, le = tail.labels(), eager.labels()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(lt.cpu().numpy(), le.cpu().numpy())
+            np.testing.assert_array_equal(lt.cpu().numpy().astype(np.uint32), want.labels)
+        with pytest.raises(lc.CCError) as e:
+            tail.parents()
+        assert e.value.status == -5     # CC_E_STATE: the last round ran inside the graph
