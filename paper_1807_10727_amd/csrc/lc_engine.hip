@@ -44,7 +44,7 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     const size_t mk = tiled ? 2 * m : m;
     const size_t tiles = (size_t)ceil_div((int64_t)mk, kSortTile) + 2;
     const size_t slabs = (size_t)ceil_div((int64_t)mk, kSlab) + 1;
-    size_t count_entries = kRadix * tiles;
+    size_t count_entries = (size_t)kRadixMax * tiles;
     if (tiled) {
         const TPlan tp = tiled_plan(n0, m0);
         count_entries = std::max(count_entries, (size_t)256 * (size_t)tp.tiles_a);
@@ -158,7 +158,8 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int nbits = 2 * kb;   // edge_key
     const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
     // the tiled round 0 hands the first radix pass up to twice as many slab tiles
-    const int64_t scan_entries = (int64_t)kRadix * (ceil_div(std::max<int64_t>(first && tiled ? 2 * M : M, 1), kSortTile) + 2);
+    const int64_t scan_entries =
+        (int64_t)kRadixMax * (ceil_div(std::max<int64_t>(first && tiled ? 2 * M : M, 1), kSortTile) + 2);
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 

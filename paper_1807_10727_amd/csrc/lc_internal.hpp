@@ -90,7 +90,7 @@ struct Work {
     uint32_t *map0;      // [n0] vertex -> node of the first kept level (or kFinal | name)
     uint32_t *maps;      // [n0] arena of the per-round maps of rounds >= 1
     uint64_t *keys[2];   // [m0] edge / sort key ping-pong buffers (E_r is keys[e_sel])
-    uint32_t *counts;    // [kRadix * sort tiles] digit counts of one sort pass
+    uint32_t *counts;    // [kRadixMax * sort tiles] digit counts of one sort pass
     uint32_t *partials;  // scan partial sums
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
@@ -109,6 +109,14 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kThreads * kScanItems;   // elements per block of the generic scan
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+// Widest sort digit: a pass may take up to kRadixMaxBits bits when that saves a pass (see
+// npasses and pass_digit).  9-bit digits measured slower than the pass they save (twice the
+// bins halve the runs each tile writes), so the default keeps 8.
+#ifndef LC_SORT_MAX_BITS
+#define LC_SORT_MAX_BITS 8
+#endif
+constexpr int kRadixMaxBits = LC_SORT_MAX_BITS;
+constexpr int kRadixMax = 1 << kRadixMaxBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 // Sort keys (edge_key) order edges by the block of hi, then lo, then hi, so the next round
@@ -136,7 +144,21 @@ __host__ __device__ inline void edge_key_split(uint64_t k, int kb, int s, uint64
 }
 
 // Which key buffer each step uses, from the device state (identical on host and device).
-__host__ __device__ inline int npasses(int nbits) { return (nbits + kRadixBits - 1) / kRadixBits; }
+// Radix passes for nbits-bit keys: 8-bit digits, or up to kRadixMaxBits-bit digits when
+// that takes fewer passes.  pass_digit spreads the bits evenly, earlier passes taking the
+// spare bit.
+__host__ __device__ inline int npasses(int nbits) {
+    if (nbits <= 0) return 0;
+    const int p8 = (nbits + kRadixBits - 1) / kRadixBits;
+    const int pw = (nbits + kRadixMaxBits - 1) / kRadixMaxBits;
+    return pw < p8 ? pw : p8;
+}
+__host__ __device__ inline void pass_digit(int nbits, int pass, int &shift, int &width) {
+    const int P = npasses(nbits);
+    const int base = nbits / P, extra = nbits % P;
+    width = base + (pass < extra ? 1 : 0);
+    shift = pass * base + (pass < extra ? pass : extra);
+}
 __host__ __device__ inline int sort_src(int round, int e_sel) { return round == 0 ? 0 : 1 - e_sel; }
 __host__ __device__ inline int sorted_sel(int round, int e_sel, int nbits) {
     return sort_src(round, e_sel) ^ (npasses(nbits) & 1);

@@ -160,14 +160,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = 0;
         return;
     }
+    int shift, width;
+    pass_digit(st->nbits, pass, shift, width);
+    const int nbins = 1 << width;
+    const uint32_t dmask = (uint32_t)nbins - 1u;
     const Tiles tl = tiles_of(w, pass);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)kRadix * (u64c)tl.ntiles;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)nbins * (u64c)tl.ntiles;
     const uint64_t *in = w.keys[sort_src(st->round, st->e_sel) ^ (pass & 1)];
-    const int shift = pass * kRadixBits;
-    __shared__ uint32_t hist[kRadix];
+    __shared__ uint32_t hist[kRadixMax];
     for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
-        for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[i] = 0;
+        for (int i = threadIdx.x; i < nbins; i += kSortThreads) hist[i] = 0;
         // every load of the tile in flight at once: pairs of keys, 16-byte aligned
         uint32_t d[kSortItems];
         bool valid[kSortItems];
@@ -184,8 +187,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
             }
             valid[2 * j] = it < tv;
             valid[2 * j + 1] = it + 1 < tv;
-            d[2 * j] = (uint32_t)(k0 >> shift) & (kRadix - 1);
-            d[2 * j + 1] = (uint32_t)(k1 >> shift) & (kRadix - 1);
+            d[2 * j] = (uint32_t)(k0 >> shift) & dmask;
+            d[2 * j + 1] = (uint32_t)(k1 >> shift) & dmask;
         }
         __syncthreads();
 #pragma unroll
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < kRadix; i += kSortThreads) w.counts[(int64_t)i * tl.ntiles + tile] = hist[i];
+        for (int i = threadIdx.x; i < nbins; i += kSortThreads) w.counts[(int64_t)i * tl.ntiles + tile] = hist[i];
         __syncthreads();
     }
 }
@@ -216,29 +219,40 @@ void k_sort_scatter(Work w, int pass) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
     if (pass >= passes) return;
+    int shift, width;
+    pass_digit(st->nbits, pass, shift, width);
+    const int nbins = 1 << width;
+    const uint32_t dmask = (uint32_t)nbins - 1u;
     const Tiles tl = tiles_of(w, pass);
     const int64_t ntiles = tl.ntiles;
     const int src = sort_src(st->round, st->e_sel) ^ (pass & 1);
     const uint64_t *in = w.keys[src];
     uint64_t *out = w.keys[src ^ 1];
-    const int shift = pass * kRadixBits;
 
     constexpr int kWaves = kSortThreads / kWave;
-    __shared__ uint32_t wcnt[kWaves][kRadix];
+    constexpr int kPer = (kRadixMax + kSortThreads - 1) / kSortThreads;   // digits per thread at most
+    __shared__ uint32_t wcnt[kWaves][kRadixMax];
     __shared__ uint64_t skeys[kSortTile];
-    __shared__ uint32_t dstart[kRadix];
-    __shared__ uint32_t gofs[kRadix];
+    __shared__ uint32_t dstart[kRadixMax];
+    __shared__ uint32_t gofs[kRadixMax];
     __shared__ uint32_t lds[kWaves + 1];
 
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     const uint64_t lt = lanemask_lt();
+    // thread t owns digits [t * per, (t + 1) * per) of this pass
+    const int per = nbins > kSortThreads ? nbins / kSortThreads : 1;
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
         // this tile's global digit offsets: loaded now, used after the ranking
-        const uint32_t my_gofs = threadIdx.x < kRadix ? w.counts[(int64_t)threadIdx.x * ntiles + tile] : 0u;
-        for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+        uint32_t my_gofs[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int d = threadIdx.x * per + q;
+            my_gofs[q] = (q < per && d < nbins) ? w.counts[(int64_t)d * ntiles + tile] : 0u;
+        }
+        for (int i = threadIdx.x; i < kWaves * kRadixMax; i += kSortThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
 
         // Slab tiles of the first pass are often partly or wholly empty: positions past tv
@@ -255,8 +269,8 @@ void k_sort_scatter(Work w, int pass) {
         for (int j = 0; j < kSortItems; ++j) {
             if (wbase + j * kWave >= tv) break;   // uniform over the wave
             const bool valid = wbase + j * kWave + lane < tv;
-            const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
-            const uint64_t peers = match_bits<kRadixBits>(d, ballot(valid));
+            const uint32_t d = (uint32_t)(k[j] >> shift) & dmask;
+            const uint64_t peers = match_bits<kRadixMaxBits>(d, ballot(valid));
             uint32_t cur = 0;
             if (valid) cur = wcnt[wave][d];
             rk[j] = cur + (uint32_t)__popcll(peers & lt);
@@ -267,21 +281,33 @@ void k_sort_scatter(Work w, int pass) {
         __syncthreads();
 
         {   // per digit: prefix over waves, start within the tile, global offset
-            const int d = threadIdx.x;
-            uint32_t run = 0;
-            if (d < kRadix) {
+            uint32_t tot[kPer];
+            uint32_t sum = 0;
 #pragma unroll
-                for (int q = 0; q < kWaves; ++q) {
-                    const uint32_t c = wcnt[q][d];
-                    wcnt[q][d] = run;
-                    run += c;
+            for (int q = 0; q < kPer; ++q) {
+                const int d = threadIdx.x * per + q;
+                uint32_t run = 0;
+                if (q < per && d < nbins) {
+#pragma unroll
+                    for (int v = 0; v < kWaves; ++v) {
+                        const uint32_t c = wcnt[v][d];
+                        wcnt[v][d] = run;
+                        run += c;
+                    }
                 }
+                tot[q] = run;
+                sum += run;
             }
             uint32_t total;
-            const uint32_t ds = block_excl_scan<kSortThreads>(run, lds, &total);
-            if (d < kRadix) {
-                dstart[d] = ds;
-                gofs[d] = my_gofs;
+            uint32_t ds = block_excl_scan<kSortThreads>(sum, lds, &total);
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int d = threadIdx.x * per + q;
+                if (q < per && d < nbins) {
+                    dstart[d] = ds;
+                    gofs[d] = my_gofs[q];
+                }
+                ds += tot[q];
             }
         }
         __syncthreads();
@@ -289,7 +315,7 @@ void k_sort_scatter(Work w, int pass) {
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             if (wbase + j * kWave + lane < tv) {
-                const uint32_t d = (uint32_t)(k[j] >> shift) & (kRadix - 1);
+                const uint32_t d = (uint32_t)(k[j] >> shift) & dmask;
                 skeys[dstart[d] + wcnt[wave][d] + rk[j]] = k[j];
             }
         }
@@ -300,7 +326,7 @@ void k_sort_scatter(Work w, int pass) {
             const int pos = j * kSortThreads + threadIdx.x;
             if (pos < tv) {
                 const uint64_t kk = skeys[pos];
-                const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+                const uint32_t d = (uint32_t)(kk >> shift) & dmask;
                 out[gofs[d] + (uint32_t)pos - dstart[d]] = kk;
             }
         }
