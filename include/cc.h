@@ -97,10 +97,11 @@ enum {
     CC_EAGER = 1u << 4          /* cc_run enqueues every round on its own (no captured tail) */
 };
 
-/* cc_run and captured tails.  Once the remaining graph of a solve has at most 2^22
- * records, cc_run replays a hipGraph of up to 8 rounds (captured on first use, kept per
- * context and reused while the rounded-up sizes match) instead of enqueuing each round and
- * reading its state back: small rounds are otherwise bound by launch overhead.  Results are
+/* cc_run and captured tails.  On a context that has already finished a solve, once the
+ * remaining graph has at most 2^22 records, cc_run replays a hipGraph of up to 8 rounds
+ * (captured on first use, kept per context and reused while the rounded-up sizes match)
+ * instead of enqueuing each round and reading its state back: small rounds are otherwise
+ * bound by launch overhead.  Results are
  * identical; rounds run this way have in_graph = 1 in their statistics, their kernels are
  * timed together as the family "tail_graph", and cc_round_parents is not available for
  * them.  CC_EAGER turns this off (cc_contract_round never uses it). */

@@ -391,9 +391,11 @@ void drop_tails(cc_ctx *c) {
     c->tails.clear();
 }
 
+// A capture costs far more than a few small rounds: a context captures only once it has
+// finished an earlier solve, i.e. when it is being reused.
 bool tail_wanted(const cc_ctx *c) {
-    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->next_round >= 1 && !c->done && c->m_cur > 0 &&
-           c->m_cur <= kTailMaxRecords;
+    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->solves_done > 0 && c->next_round >= 1 &&
+           !c->done && c->m_cur > 0 && c->m_cur <= kTailMaxRecords;
 }
 
 // Capture kTailRounds rounds sized for (Nb, Mb) on a private stream.  The kernels read
@@ -582,6 +584,7 @@ cc_status cc_run(cc_ctx *c, int32_t *rounds) {
     }
     if (c->failed_status) return c->failed_status;
     c->labels_ready = true;
+    c->solves_done += 1;
     if (rounds) *rounds = c->rounds;
     return CC_OK;
 }

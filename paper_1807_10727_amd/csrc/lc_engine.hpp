@@ -88,6 +88,7 @@ struct cc_ctx : public lc::Engine {
     int64_t n_cur = 0, m_cur = 0;
     int64_t pending_N = 0, pending_M = 0;   // bounds of the round in flight
     int32_t last_graph_round = -1;          // last round run inside a captured tail
+    int64_t solves_done = 0;                // solves that cc_run finished on this context
     // captured tails of rounds (cc_run), replayed while the rounded-up sizes match
     struct Tail {
         hipGraphExec_t exec;
