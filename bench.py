@@ -55,7 +55,7 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0, tiled=False, loops=0, in_graph=None):
+def family_bytes(stats, n0, tiled=False, loops=0):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
@@ -65,21 +65,14 @@ def family_bytes(stats, n0, tiled=False, loops=0, in_graph=None):
     records are written once, re-read by the row pass and read by each row kernel."""
     fam = {}
 
-    def add_family(k, v):
+    def add(k, v):
         fam[k] = fam.get(k, 0) + v
-
-    def add_tail(_k, v):
-        fam["tail_graph"] = fam.get("tail_graph", 0) + v
 
     for (r, n_active, m_in, s, m_out, _fin) in stats:
         N = n0 if r == 0 else n_active
         M = m_in
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
         sfx = "_round0" if r == 0 else ""
-        if in_graph is not None and in_graph[r]:   # timed as one captured tail
-            add = add_tail
-        else:
-            add = add_family
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
         add("plan_blocks", N)                      # parent flags in
         if r == 0 and tiled:
@@ -311,6 +304,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="er_paths", choices=["er_paths", "small", "rmat26", "rmat24"])
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--eager", action="store_true",
+                    help="run every round eagerly even without per-kernel timing (as the timed run does)")
     ap.add_argument("--round0", default="auto", choices=["auto", "direct", "tiled"],
                     help="how round 0 reads the input records (auto: the library's choice by size)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -384,7 +379,12 @@ def main():
     torch.cuda.synchronize()
     del cal_a, cal_b
 
-    flags = 0 if args.no_profile else lc.CC_PROFILE
+    # With per-kernel timing every round runs eagerly (CC_EAGER), so that each launch of the
+    # timed kernel carries its HIP events on the stream; --no-profile lets later rounds
+    # replay captured tails.
+    flags = 0 if args.no_profile else (lc.CC_PROFILE | lc.CC_EAGER)
+    if args.eager:
+        flags |= lc.CC_EAGER
     flags |= {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED}[args.round0]
     stream = torch.cuda.current_stream(dev)
     base_seed = graphgen.CONFIG_SEED_BASE + 1
@@ -403,11 +403,10 @@ def main():
             acc_ms[k] = acc_ms.get(k, 0.0) + ms
             acc_n[k] = acc_n.get(k, 0) + n
 
-    def fam_bytes_of(stats_list, launches, graph_flags):
+    def fam_bytes_of(stats_list, launches):
         out = {}
-        for st, gf in zip(stats_list, graph_flags):
-            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
-                                     in_graph=gf).items():
+        for st in stats_list:
+            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops).items():
                 out[k] = out.get(k, 0) + v
         return out
 
@@ -421,24 +420,26 @@ def main():
 
     # Warm-up steps time every kernel family; the dominant one (largest kernel time) is then
     # the only family timed during the measured steps, so that the events of the others do
-    # not slow the stream down.
-    warm_ms, warm_n, warm_stats, warm_graph = {}, {}, [], []
-    for i in range(args.warmup):
+    # not slow the stream down.  One more warm-up step runs with that setting (it captures
+    # the tails of rounds the measured steps replay).
+    warm_ms, warm_n, warm_stats = {}, {}, []
+    for i in range(max(args.warmup - 1, 0) if not args.no_profile else args.warmup):
         r = step(1000 + i)
         warm_stats.append(solver.stats(r))
-        warm_graph.append(solver.rounds_in_graph(r))
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom = None
     if not args.no_profile and warm_ms:
-        warm_bytes = fam_bytes_of(warm_stats, warm_n, warm_graph)
-        log_families("warm-up", warm_ms, warm_n, warm_bytes, args.warmup)
-        log("warm-up: sum of kernel time per step %.3f ms" % (sum(warm_ms.values()) / args.warmup))
+        warm_bytes = fam_bytes_of(warm_stats, warm_n)
+        steps_w = len(warm_stats)
+        log_families("warm-up", warm_ms, warm_n, warm_bytes, steps_w)
+        log("warm-up: sum of kernel time per step %.3f ms" % (sum(warm_ms.values()) / steps_w))
         dom = max((k for k in warm_ms if k in warm_bytes and warm_n[k] > 0), key=lambda k: warm_ms[k])
         solver.profile_families([dom])
+        step(2000)
+        torch.cuda.synchronize()
     solver.reset(base_seed)            # clears the per-kernel timers too
     all_stats = []
-    all_graph = []
     rounds = []
     fam_ms = {}
     fam_n = {}
@@ -448,7 +449,6 @@ def main():
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
-        all_graph.append(solver.rounds_in_graph(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -459,7 +459,7 @@ def main():
         log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st)
 
     # algorithmic bytes per family over the timed steps
-    fam_bytes = fam_bytes_of(all_stats, fam_n if dom is None else warm_n, all_graph)
+    fam_bytes = fam_bytes_of(all_stats, fam_n if dom is None else warm_n)
     job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
 
     roofline = None

@@ -25,11 +25,16 @@ COPY_SYMBOL = "__amd_rocclr_copyBuffer"
 
 
 def source_hash() -> str:
+    """Hash of the sources that hold device code (host-only files do not change what a
+    kernel moves)."""
     h = hashlib.sha1()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
         with open(p, "rb") as f:
-            h.update(os.path.basename(p).encode())
-            h.update(f.read())
+            text = f.read()
+        if b"__global__" not in text and b"__device__" not in text:
+            continue
+        h.update(os.path.basename(p).encode())
+        h.update(text)
     return h.hexdigest()
 
 
