@@ -28,7 +28,7 @@ FAMILY_SYMBOL = {
     "min1_round0": "lc::k_min1<lc::ReadSoa32<4>, true, false>",
     "min2_round0": "lc::k_min2<lc::ReadSoa32<4> >",
     "relabel_round0": "lc::k_relabel<lc::ReadSoa32<4> >",
-    "min1": "lc::k_min1<lc::ReadInternal, false, false>",
+    "min1": "lc::k_min1_seeded",
     "min2": "lc::k_min2<lc::ReadInternal>",
     "relabel": "lc::k_relabel<lc::ReadInternal>",
     "sort_hist": "lc::k_sort_hist",
@@ -55,11 +55,12 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0, tiled=False, loops=0):
+def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
-    M' = distinct edges out, P = radix passes.  Random-access amplification (cache-line
+    K = keys the relabel wrote and the sort processed (S less the repeats the relabel
+    workgroups dropped; S when not given), M' = distinct edges out, P = radix passes.  Random-access amplification (cache-line
     reads for 4-byte gathers and atomics, extra sort passes) is implementation overhead
     and deliberately not counted.  With the tiled round 0, T = 2 (M - loops) directed
     records are written once, re-read by the row pass and read by each row kernel."""
@@ -68,9 +69,10 @@ def family_bytes(stats, n0, tiled=False, loops=0):
     def add(k, v):
         fam[k] = fam.get(k, 0) + v
 
-    for (r, n_active, m_in, s, m_out, _fin) in stats:
+    for i, (r, n_active, m_in, s, m_out, _fin) in enumerate(stats):
         N = n0 if r == 0 else n_active
         M = m_in
+        K = sorted_keys[i] if sorted_keys is not None else s
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
         sfx = "_round0" if r == 0 else ""
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
@@ -83,15 +85,15 @@ def family_bytes(stats, n0, tiled=False, loops=0):
             add("part_b_scatter", 16 * T)
             add("min1_tiled", 8 * T + 4 * N)       # directed records in, m1 out
             add("min2_tiled", 8 * T + 8 * N)       # directed records in, m1 in once, parent out
-            add("relabel_tiled", 8 * T + 4 * N + 8 * s)   # directed records, parents once, survivors
+            add("relabel_tiled", 8 * T + 4 * N + 8 * K)   # directed records, parents once, keys out
         else:
             add("min1" + sfx, 8 * M + 4 * N)           # records in, m1 out once
             add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
             add("parent", 8 * N)                       # lv in, parent out
-            add("relabel" + sfx, 8 * M + 4 * N + 8 * s)   # records in, parents in once, survivor keys out
-        add("sort_hist", 8 * s * P)                # keys in per pass
-        add("sort_scatter", 16 * s * P)            # keys in and out per pass
-        add("unique", 16 * s + 8 * m_out + 4 * N)  # sorted keys read twice, renamed unique keys out
+            add("relabel" + sfx, 8 * M + 4 * N + 8 * K)   # records in, parents in once, keys out
+        add("sort_hist", 8 * K * P)                # keys in per pass
+        add("sort_scatter", 16 * K * P)            # keys in and out per pass
+        add("unique", 16 * K + 8 * m_out + 4 * N)  # sorted keys read twice, renamed unique keys out
         add("node_scan", 6 * N)                    # flags in (twice), index out
         add("nodes", 9 * N)
         add("map", 9 * N)
@@ -102,7 +104,8 @@ def family_bytes(stats, n0, tiled=False, loops=0):
 def job_alg_bytes(stats, n0):
     """The job's algorithmic bytes: three streaming reads of the records, the survivors
     written and read once, the unique edges written, 24 bytes of node state per node and
-    round, and the labels."""
+    round, and the labels.  Survivors as the method defines them (m_survive), whatever
+    share of them the implementation drops before writing."""
     b = 4 * n0
     for (r, n_active, m_in, s, m_out, _fin) in stats:
         N = n0 if r == 0 else n_active
@@ -403,10 +406,11 @@ def main():
             acc_ms[k] = acc_ms.get(k, 0.0) + ms
             acc_n[k] = acc_n.get(k, 0) + n
 
-    def fam_bytes_of(stats_list, launches):
+    def fam_bytes_of(stats_list, keys_list, launches):
         out = {}
-        for st in stats_list:
-            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops).items():
+        for st, ks in zip(stats_list, keys_list):
+            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
+                                     sorted_keys=ks).items():
                 out[k] = out.get(k, 0) + v
         return out
 
@@ -422,15 +426,16 @@ def main():
     # the only family timed during the measured steps, so that the events of the others do
     # not slow the stream down.  One more warm-up step runs with that setting (it captures
     # the tails of rounds the measured steps replay).
-    warm_ms, warm_n, warm_stats = {}, {}, []
+    warm_ms, warm_n, warm_stats, warm_keys = {}, {}, [], []
     for i in range(max(args.warmup - 1, 0) if not args.no_profile else args.warmup):
         r = step(1000 + i)
         warm_stats.append(solver.stats(r))
+        warm_keys.append(solver.sorted_keys(r))
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom = None
     if not args.no_profile and warm_ms:
-        warm_bytes = fam_bytes_of(warm_stats, warm_n)
+        warm_bytes = fam_bytes_of(warm_stats, warm_keys, warm_n)
         steps_w = len(warm_stats)
         log_families("warm-up", warm_ms, warm_n, warm_bytes, steps_w)
         log("warm-up: sum of kernel time per step %.3f ms" % (sum(warm_ms.values()) / steps_w))
@@ -440,6 +445,7 @@ def main():
         torch.cuda.synchronize()
     solver.reset(base_seed)            # clears the per-kernel timers too
     all_stats = []
+    all_keys = []
     rounds = []
     fam_ms = {}
     fam_n = {}
@@ -449,17 +455,18 @@ def main():
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
+        all_keys.append(solver.sorted_keys(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
     value = m0 * args.steps / dt
     log("rounds per step: %s" % rounds)
-    for st in all_stats[0]:
-        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st)
+    for st, k in zip(all_stats[0], all_keys[0]):
+        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st + " sorted=%d" % k)
 
     # algorithmic bytes per family over the timed steps
-    fam_bytes = fam_bytes_of(all_stats, fam_n if dom is None else warm_n)
+    fam_bytes = fam_bytes_of(all_stats, all_keys, fam_n if dom is None else warm_n)
     job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
 
     roofline = None

@@ -94,6 +94,7 @@ __global__ void k_state_init(RoundState *st, int64_t n0, int64_t m0, int64_t map
         st->levels = 0;
         st->n_active = 0;
         st->s_count = 0;
+        st->s_keys = 0;
         st->n_final = 0;
         st->n_labels = 0;
         st->err = 0;

@@ -163,7 +163,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 
-    RUN(kRoundBegin, launch_round_begin(w, gn, stream));
+    RUN(kRoundBegin, launch_round_begin(w, !first && !batch, r, gn, stream));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
     if (first && tiled) {
         const int ga = (int)std::min<int64_t>(tp.tiles_a, grid_cap);
@@ -348,6 +348,7 @@ cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out) {
     s.m_survive = (int64_t)st.s_count;
     s.m_out = (int64_t)st.m_next;
     s.n_finalised = (int64_t)st.n_final;
+    s.m_sorted = (int64_t)st.s_keys;
     c->stats.push_back(s);
     c->rounds = r + 1;
     if (out) *out = s;
@@ -474,6 +475,7 @@ cc_status run_tail(cc_ctx *c) {
         s.m_survive = (int64_t)st.rstats[r][3];
         s.m_out = (int64_t)st.rstats[r][4];
         s.n_finalised = (int64_t)st.rstats[r][5];
+        s.m_sorted = (int64_t)st.rstats[r][6];
         c->stats.push_back(s);
     }
     c->rounds = end;

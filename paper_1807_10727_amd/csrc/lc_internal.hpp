@@ -42,6 +42,8 @@ struct RoundState {
     int32_t pad1_;
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
+    alignas(128) u64c s_keys;     // sort keys written by the relabel: the survivors less the
+                                  // repeats a workgroup recognised itself (atomics)
     alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
     alignas(128) u64c n_labels;   // distinct parents of this round (atomics)
     alignas(128) uint32_t err;    // bit 0: input id out of range; bit 1: map arena overflow;
@@ -50,8 +52,8 @@ struct RoundState {
     u64c n_next;                  // nodes of the next graph (one workgroup)
     alignas(128) u64c level_off[kMaxLevels];
     // statistics of every round that read records (round, n_active, m_in, survivors, m_out,
-    // n_final), so that rounds enqueued back to back need a single readback
-    u64c rstats[kStatRounds][6];
+    // n_final, sort keys), so that rounds enqueued back to back need a single readback
+    u64c rstats[kStatRounds][7];
 };
 
 enum Layout { kSoa32 = 0, kSoa64 = 1, kPacked = 2 };
@@ -119,6 +121,9 @@ constexpr int kRadixMaxBits = LC_SORT_MAX_BITS;
 constexpr int kRadixMax = 1 << kRadixMaxBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
+#ifndef LC_DEDUP_LOG2
+#define LC_DEDUP_LOG2 12   // slots of the relabel's workgroup key set (8 B each)
+#endif
 // Sort keys (edge_key) order edges by the block of hi, then lo, then hi, so the next round
 // reads its edges grouped by the block of their larger endpoint.  A block spans about
 // kBlockNodes next-round nodes, and lo is swept in increasing order within the block.  Wider
@@ -207,7 +212,8 @@ inline bool tiled_fits(int64_t n) { return n >= 1 && tiled_plan(n, 1).rows <= kT
 // `grid` arguments are workgroup counts chosen by the host (grid-stride loops cover the
 // rest); every kernel reads its true element count from RoundState.
 
-hipError_t launch_round_begin(const Work &w, int grid, hipStream_t s);
+// seeded: plain solve, rounds >= 1 (node words start at the own priority)
+hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s);
 hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool batch, int round, int grid,
                        hipStream_t s);
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);

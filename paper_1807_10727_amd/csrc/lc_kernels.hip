@@ -1,7 +1,7 @@
 // Round kernels of LocalContraction on gfx950.
 //
 // One round (one phase of the method, Section 3 "LocalContraction"):
-//   round_begin  reset counters, m1 = lv = +inf, flags = 0 over the N_r nodes
+//   round_begin  reset counters, m1 = lv = +inf (or rho), flags = 0 over the N_r nodes
 //   min1         m1[x] = min over the closed neighbourhood N(x) of rho   (Section 2: x in N(x))
 //   min2         lv[x] = min over N(x) of m1 = min over N(N(x)) of rho
 //   parent       parent of x = the node whose priority is lv[x] (inverse of the bijection)
@@ -13,9 +13,11 @@
 // Merged nodes are named by the original id of their parent vertex, and the per-round
 // maps are composed at the end into the label of every original vertex.
 //
-// Both min passes fold the node's own priority into each update (min(rho(a), rho(b)) is
-// sent to both endpoints), so the +inf fill replaces an initialisation pass; ids without a
-// loop-free record keep +inf and are their own parent.  Each update first reads the
+// In round 0 (and in batches) both min passes fold the node's own priority into each update
+// (min(rho(a), rho(b)) is sent to both endpoints), so the +inf fill replaces an
+// initialisation pass; ids without a loop-free record keep +inf and are their own parent.
+// From round 1 on every node has a record, and round_begin seeds the node words with the
+// own priority instead, so that the one-hop pass needs no name lookups.  Each update first reads the
 // current value and only issues the atomic when it can lower it: values only decrease, so
 // a stale read can only cause a redundant atomic, never a missed one.
 
@@ -57,12 +59,19 @@ __device__ inline uint32_t run_min(uint32_t key, uint32_t val, bool &last) {
 
 // ---------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
+// kSeeded (plain solve, rounds >= 1, where every node has a loop-free record): both halves of
+// the node word start at the node's own priority rather than +inf.  The one-hop minimum over
+// the closed neighbourhood then only needs the far endpoint's priority, which the same 8-byte
+// load that fetches the current minimum brings along; the two-hop accumulator may start at
+// rho(x) because it ends at most at m1[x] <= rho(x).
+template <bool kSeeded>
+__global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t *names) {
     RoundState *st = w.st;
     const int64_t n = (int64_t)st->n_cur;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->n_active = 0;
         st->s_count = 0;
+        st->s_keys = 0;
         st->n_slabs = 0;
         st->m_next = 0;
         st->n_next = 0;
@@ -73,11 +82,61 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w) {
         st->nbits = 2 * st->kb;
         st->key = round_key(st->seed, st->round);
     }
+    RoundKey key{};
+    if (kSeeded) key = round_key(st->seed, st->round);
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        ((uint64_t *)w.ml)[i] = ~0ull;
+        uint64_t v = ~0ull;
+        if (kSeeded) {
+            const uint64_t p = prio(key, names[i]);
+            v = (p << 32) | p;
+        }
+        ((uint64_t *)w.ml)[i] = v;
         w.has_edge[i] = 0;
         w.is_label[i] = 0;
     }
+}
+
+// One-hop minimum, plain solve, rounds >= 1 (node words seeded with the own priority): each
+// record sends rho(b) to a and rho(a) to b, read from the high halves of the two words.
+__global__ __launch_bounds__(kThreads) void k_min1_seeded(ReadInternal rd, Work w) {
+    constexpr int V = ReadInternal::kV;
+    rd.init(w.st);
+    const int64_t nch = rd.chunks();
+    const uint64_t *word = (const uint64_t *)w.ml;
+    uint32_t *m1 = w.ml;
+    bool bad = false;
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
+        uint32_t a[V], b[V];
+        uint64_t wa[V], wb[V];
+        bool ok[V];
+        if (c < nch) {
+            rd.read(c, a, b, bad);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            ok[j] = a[j] != b[j];
+            wa[j] = wb[j] = ~0ull;
+            if (ok[j]) {
+                wa[j] = word[a[j]];
+                wb[j] = word[b[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const uint32_t pa = (uint32_t)(wa[j] >> 32), pb = (uint32_t)(wb[j] >> 32);
+            bool la;
+            const uint32_t va = run_min(ok[j] ? a[j] : 0xFFFFFFFFu, pb, la);
+            if (ok[j]) {
+                if (la && (uint32_t)wa[j] > va) atomicMin(&m1[2 * (size_t)a[j]], va);
+                if ((uint32_t)wb[j] > pa) atomicMin(&m1[2 * (size_t)b[j]], pa);
+            }
+        }
+    }
+    if (bad) atomicOr(&w.st->err, 1u);
 }
 
 template <class R, bool kFirst, bool kBatch>
@@ -218,16 +277,48 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
     if (broken) atomicOr(&st->err, 4u);
 }
 
+// Workgroup-local set of sort keys already written (sorted records, i.e. rounds >= 1).
+constexpr int kDedupLog2 = LC_DEDUP_LOG2;
+constexpr int kDedupSlots = 1 << kDedupLog2;
+constexpr int kDedupProbes = 8;
+constexpr unsigned long long kNoKey = ~0ull;   // no sort key has all 64 bits set (lo < hi)
+
+// False when `key` is in the set already; true when it was added now, or when its probes
+// all met other keys (the key is then written again: later passes drop any repeat).
+__device__ inline bool set_insert(unsigned long long *set, uint64_t key) {
+    if (key == kNoKey) return true;
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kDedupLog2));
+    for (int p = 0; p < kDedupProbes; ++p) {
+        const unsigned long long old = atomicCAS(&set[h], kNoKey, (unsigned long long)key);
+        if (old == kNoKey) return true;
+        if (old == key) return false;
+        h = (h + 1) & (kDedupSlots - 1);
+    }
+    return true;
+}
+
 // Relabel every record through the parents and keep the loop-free ones as sort keys
-// (lo << b | hi).  Each workgroup owns a slab of kSlab consecutive records and writes its
-// survivors, in order, to the start of the same slab of the output: no global counter is
-// involved.  slab_cnt holds the survivors per slab; the first radix pass reads the slabs.
+// (edge_key of (min, max) of the two parents).  Each workgroup owns a slab of kSlab
+// consecutive records and writes its survivors, in order, to the start of the same slab of
+// the output: no global counter is involved.  slab_cnt holds the keys per slab; the first
+// radix pass reads the slabs.
+//
+// On sorted records (rounds >= 1) a workgroup also drops every key it has written before:
+// a dense region that contracts onto a few parents maps many records onto the same parent
+// pairs, and a hash set in LDS (kept for the whole launch) removes most of those repeats
+// before they reach the sort.  s_count still counts every survivor; s_keys counts the keys.
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     constexpr int V = R::kV;
+    constexpr bool kDedup = R::kSorted;
     constexpr int64_t kChunksPerSlab = kSlab / V;
     RoundState *st = w.st;
     __shared__ uint32_t lds[kThreads / kWave + 1];
+    __shared__ unsigned long long set[kDedup ? kDedupSlots : 1];
+    if (kDedup) {
+        for (int i = threadIdx.x; i < kDedupSlots; i += kThreads) set[i] = kNoKey;
+        __syncthreads();
+    }
     rd.init(st);
     const int64_t nch = rd.chunks();
     const int64_t nslabs = ceil_div(rd.records(), kSlab);
@@ -236,6 +327,8 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     const int kb = st->kb;
     const int hbs = st->hb_shift;
     bool bad = false;
+    uint32_t survived = 0;   // this thread's loop-free records
+    uint64_t written = 0;    // this workgroup's keys (thread 0)
     for (int64_t slab = blockIdx.x; slab < nslabs; slab += gridDim.x) {
         const int64_t c_end = min(nch, (slab + 1) * kChunksPerSlab);
         uint64_t *dst = out + slab * kSlab;
@@ -256,8 +349,10 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
 #pragma unroll
                 for (int j = 0; j < V; ++j) {
                     keep[j] = pa[j] != pb[j];
+                    survived += keep[j];
                     const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
                     key[j] = edge_key(lo, hi, kb, hbs);
+                    if (kDedup && keep[j]) keep[j] = set_insert(set, key[j]);
                     cnt += keep[j];
                 }
             } else {
@@ -272,10 +367,13 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
             }
             cursor += total;
         }
-        if (threadIdx.x == 0) {
-            w.slab_cnt[slab] = cursor;
-            if (cursor) atomicAdd(&st->s_count, (u64c)cursor);
-        }
+        if (threadIdx.x == 0) w.slab_cnt[slab] = cursor;
+        written += cursor;
+    }
+    survived = block_sum<kThreads>(survived, lds);
+    if (threadIdx.x == 0) {
+        if (survived) atomicAdd(&st->s_count, (u64c)survived);
+        if (written) atomicAdd(&st->s_keys, (u64c)written);
     }
 }
 
@@ -369,6 +467,7 @@ __global__ void k_round_end(Work w) {
             s[3] = st->s_count;
             s[4] = st->m_next;
             s[5] = st->n_final;
+            s[6] = st->s_keys;
         }
         st->rounds_active = r + 1;
     }
@@ -486,7 +585,11 @@ __global__ __launch_bounds__(kThreads) void k_fill_gid(uint32_t *gid0, const uin
         return hipGetLastError();                                             \
     } while (0)
 
-hipError_t launch_round_begin(const Work &w, int grid, hipStream_t s) { LC_LAUNCH(k_round_begin, grid, w); }
+hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s) {
+    const uint32_t *names = w.names[round & 1];
+    if (seeded) LC_LAUNCH(k_round_begin<true>, grid, w, names);
+    LC_LAUNCH(k_round_begin<false>, grid, w, names);
+}
 
 template <bool kBatch>
 static hipError_t min1_in(const Work &w, const EdgeIn &e, const PrioCtx &p, int grid, hipStream_t s) {
@@ -510,7 +613,7 @@ hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool b
     const uint32_t *names = w.names[round & 1];
     const uint32_t *gids = w.gids[round & 1];
     if (batch) LC_LAUNCH((k_min1<ReadInternal, false, true>), grid, ReadInternal(w), w, p, names, gids);
-    LC_LAUNCH((k_min1<ReadInternal, false, false>), grid, ReadInternal(w), w, p, names, gids);
+    LC_LAUNCH(k_min1_seeded, grid, ReadInternal(w), w);
 }
 
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s) {

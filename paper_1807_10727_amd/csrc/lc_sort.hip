@@ -144,7 +144,7 @@ struct Tiles {
 __device__ inline Tiles tiles_of(const Work &w, int pass) {
     const RoundState *st = w.st;
     Tiles t;
-    t.S = (int64_t)st->s_count;
+    t.S = (int64_t)st->s_keys;
     t.slab = pass == 0;
     t.slab_cnt = w.slab_cnt;
     t.ntiles = t.slab ? (int64_t)st->n_slabs * (kSlab / kSortTile) : ceil_div(t.S, kSortTile);
@@ -343,7 +343,7 @@ void k_sort_scatter(Work w, int pass) {
 __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     RoundState *st = w.st;
     __shared__ uint32_t lds[kSortThreads / kWave + 1];
-    const int64_t S = (int64_t)st->s_count;
+    const int64_t S = (int64_t)st->s_keys;
     const int64_t ntiles = ceil_div(S, kSortTile);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;
     const uint64_t *in = w.keys[sorted_sel(st->round, st->e_sel, st->nbits)];
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     constexpr int kWaves = kSortThreads / kWave;
     RoundState *st = w.st;
     __shared__ uint32_t rowcnt[kSortItems * kWaves];
-    const int64_t S = (int64_t)st->s_count;
+    const int64_t S = (int64_t)st->s_keys;
     const int64_t ntiles = ceil_div(S, kSortTile);
     const int t = sorted_sel(st->round, st->e_sel, st->nbits);
     const uint64_t *in = w.keys[t];

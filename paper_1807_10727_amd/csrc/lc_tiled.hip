@@ -444,7 +444,10 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
         }
         __syncthreads();   // lpar is rewritten for the next row
     }
-    if (threadIdx.x == 0 && kept) atomicAdd(&st->s_count, (u64c)kept);
+    if (threadIdx.x == 0 && kept) {
+        atomicAdd(&st->s_count, (u64c)kept);
+        atomicAdd(&st->s_keys, (u64c)kept);
+    }
     if (broken) atomicOr(&st->err, 4u);
 }
 

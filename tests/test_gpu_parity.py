@@ -281,6 +281,30 @@ def test_heavy_repeats_and_hub(lc, case, mode):
     assert w.stats[0][3] > 2 * w.stats[0][4] or case == "sun_40000"   # many repeats dropped
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
+@pytest.mark.parametrize("seed", [2, 5])
+def test_relabel_drops_workgroup_repeats(lc, mode, seed):
+    """G(2^15, 2^18), seeds whose round 1 maps 3,100-4,600 survivors onto five or fewer
+    parent pairs.  The relabel workgroups drop the repeats they recognise themselves before
+    the sort: the keys sorted lie between the distinct edges out and the survivors (all
+    survivors in round 0), far fewer than the survivors in round 1, and rounds, statistics
+    and labels stay bit-exact with the oracle."""
+    g = graphgen.Graph(1 << 15, *graphgen.gnm(31, 1 << 15, 1 << 18))
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=seed, flags=MODES[mode] | lc.CC_EAGER) as s:
+        r = s.run()
+        st = [tuple(x) for x in s.stats(r)]
+        ks = s.sorted_keys(r)
+        lab = s.labels().cpu().numpy()
+    want = oracle.run(g.n, g.src, g.dst, seed=seed)
+    assert r == want.rounds and st == [tuple(x) for x in want.stats]
+    np.testing.assert_array_equal(lab.astype(np.uint32), want.labels)
+    assert ks[0] == st[0][3]
+    for x, k in zip(st, ks):
+        assert x[4] <= k <= x[3]
+    assert st[1][3] > 1000 and ks[1] * 10 < st[1][3]
+
+
 def test_captured_tail_matches_eager_and_oracle(lc):
     """On a reused context cc_run replays a captured graph of rounds once the remaining graph
     is small: the same statistics and labels as eager rounds and as the oracle, for
