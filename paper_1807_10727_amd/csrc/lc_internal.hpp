@@ -82,9 +82,9 @@ struct Work {
     RoundState *st;
     uint32_t *ml;        // [2 n0] node word: ml[2x] one-hop minimum, ml[2x+1] two-hop minimum
     uint32_t *par;       // [n0] parent of each node (compact index of this round)
-    uint8_t *has_edge;   // [n0] node of this round is a node of the next graph
+    uint32_t *nmap;      // [2 ceil(n0 / 32)] next-graph node map (see nmap_rank)
     uint8_t *is_label;   // [n0] node of this round is somebody's parent
-    uint32_t *newidx;    // [n0] exclusive scan of has_edge
+    uint32_t *newidx;    // [n0] scratch of the canonical relabelling
     uint32_t *names[2];  // [n0] node names, rounds >= 1 (round r uses names[r & 1])
     uint32_t *gids[2];   // [n0] batch: graph of each node, rounds >= 1
     uint32_t *gid0;      // [n0] batch: graph of each vertex (round 0)
@@ -135,6 +135,24 @@ constexpr int kSlab = 2 * kSortTile;               // records per relabel workgr
 constexpr int64_t kBlockNodes = 1 << LC_BLOCK_NODES_LOG2;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Next-graph node map of a round.  Word pair i covers nodes 32 i .. 32 i + 31 of the round:
+// nmap[2 i] has a bit for each of them that keeps an edge, nmap[2 i + 1] counts the nodes
+// before 32 i that keep one.  A node's index in the next graph is then one 8-byte load and a
+// popcount away, and the map of N nodes takes N / 4 bytes, small enough to stay in cache
+// while the sorted edges sweep over it once per block of the key order.
+__device__ inline bool nmap_has(const uint32_t *nmap, uint64_t x) {
+    return (nmap[2 * (x >> 5)] >> (x & 31)) & 1u;
+}
+__device__ inline uint32_t nmap_rank(const uint32_t *nmap, uint64_t x) {
+    const uint2 e = *(const uint2 *)(nmap + 2 * (x >> 5));
+    return e.y + (uint32_t)__popc(e.x & ((1u << (x & 31)) - 1u));
+}
+__device__ inline void nmap_mark(uint32_t *nmap, uint64_t x) {
+    uint32_t *p = nmap + 2 * (x >> 5);
+    const uint32_t bit = 1u << (x & 31);
+    if (!(*p & bit)) atomicOr(p, bit);   // bits are only ever set: a stale read costs an atomic
+}
 
 // Sort key of an edge lo < hi between indices of a round with b = ceil(log2 N) bits per
 // index: hi's block (hi >> s), then lo, then hi's s bits below the block.  The block number
@@ -223,6 +241,8 @@ hipError_t launch_plan_blocks(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
                           int grid, hipStream_t s, int stage);
+// prefix counts of the next-graph node map; the total becomes n_next
+hipError_t launch_node_scan(const Work &w, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
                            hipStream_t s, int stage);
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);

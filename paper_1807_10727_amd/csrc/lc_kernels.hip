@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t
     }
     RoundKey key{};
     if (kSeeded) key = round_key(st->seed, st->round);
+    const int64_t nw = ceil_div(n, 32);
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         uint64_t v = ~0ull;
         if (kSeeded) {
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t
             v = (p << 32) | p;
         }
         ((uint64_t *)w.ml)[i] = v;
-        w.has_edge[i] = 0;
         w.is_label[i] = 0;
+        if (i < nw) ((uint64_t *)w.nmap)[i] = 0ull;
     }
 }
 
@@ -413,8 +414,8 @@ __global__ __launch_bounds__(kThreads) void k_nodes(Work w, const uint32_t *name
     const int64_t n = (int64_t)st->n_cur;
     uint32_t fin = 0;
     for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
-        if (w.has_edge[j]) {
-            const uint32_t k = w.newidx[j];
+        if (nmap_has(w.nmap, j)) {
+            const uint32_t k = nmap_rank(w.nmap, j);
             const uint32_t nm = kFirst ? (uint32_t)j : names_cur[j];
             names_next[k] = nm;
             w.idx_of[nm] = k;
@@ -443,14 +444,12 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
         }
         out = w.maps + st->map_off;
     }
-    // newidx is the exclusive scan of has_edge, so p keeps an edge exactly when the next
-    // entry is larger: both come from one cache line (n_next stands in past the end)
-    const uint32_t last = (uint32_t)st->n_next;
+    // the parent's bit and its index in the next graph come from one 8-byte word of the map
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const uint32_t p = w.par[i];
-        const uint32_t a = w.newidx[p];
-        const uint32_t b = (int64_t)p + 1 < n ? w.newidx[p + 1] : last;
-        out[i] = b != a ? a : (kFinal | (kFirst ? p : names_cur[p]));
+        const uint2 e = *(const uint2 *)(w.nmap + 2 * (p >> 5));
+        const uint32_t below = e.x & ((1u << (p & 31)) - 1u);
+        out[i] = ((e.x >> (p & 31)) & 1u) ? e.y + (uint32_t)__popc(below) : (kFinal | (kFirst ? p : names_cur[p]));
     }
 }
 

@@ -335,11 +335,59 @@ void k_sort_scatter(Work w, int pass) {
 }
 
 // ---------------------------------------------------------------------------------------
+// next-graph node map: prefix counts over the bit words
+// ---------------------------------------------------------------------------------------
+
+// Thread t of a block takes the 16 consecutive words [16 t, 16 t + 16) of the block's kScanTile.
+__device__ inline void nmap_load16(const uint32_t *nmap, int64_t base, int64_t nw, uint32_t (&c)[16]) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c[j] = base + j < nw ? (uint32_t)__popc(nmap[2 * (base + j)]) : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_nmap_reduce(Work w) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t nw = ceil_div((int64_t)w.st->n_cur, 32);
+    const int64_t nblk = ceil_div(nw, kScanTile);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t c[16];
+        nmap_load16(w.nmap, blk * kScanTile + threadIdx.x * 16, nw, c);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sum += c[j];
+        uint32_t total;
+        block_excl_scan<kThreads>(sum, lds, &total);
+        if (threadIdx.x == 0) w.partials[blk] = total;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_nmap_down(Work w) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t nw = ceil_div((int64_t)w.st->n_cur, 32);
+    const int64_t nblk = ceil_div(nw, kScanTile);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        uint32_t c[16];
+        const int64_t my = blk * kScanTile + threadIdx.x * 16;
+        nmap_load16(w.nmap, my, nw, c);
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sum += c[j];
+        uint32_t total;
+        uint32_t run = w.partials[blk] + block_excl_scan<kThreads>(sum, lds, &total);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (my + j < nw) w.nmap[2 * (my + j) + 1] = run;
+            run += c[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // unique
 // ---------------------------------------------------------------------------------------
 
 // Heads (first key of every run of equal sorted keys) per tile, and the next graph's node
 // marks: both endpoints of every kept edge (the endpoints of all survivors, the same set).
+// Keys with equal lo are adjacent, so lo is marked by the first key of its run only.
 __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     RoundState *st = w.st;
     __shared__ uint32_t lds[kSortThreads / kWave + 1];
@@ -360,11 +408,12 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
             const uint64_t prev = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
             if (idx < S && (idx == 0 || k != prev)) {
                 ++cnt;
-                uint64_t lo, hi;
+                uint64_t lo, hi, plo = ~0ull, phi;
                 edge_key_split(k, kb, hbs, lo, hi);
+                if (idx > 0) edge_key_split(prev, kb, hbs, plo, phi);
                 if (lo < n_cur && hi < n_cur) {
-                    w.has_edge[lo] = 1;
-                    w.has_edge[hi] = 1;
+                    if (plo != lo) nmap_mark(w.nmap, lo);
+                    nmap_mark(w.nmap, hi);
                 } else {
                     broken = true;
                 }
@@ -378,7 +427,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
 }
 
 // The next graph's edge list: the heads, in sorted order, renamed into the next round's
-// compact index space (newidx), written to the other key buffer.  Row j of a tile is the
+// compact index space (nmap_rank), written to the other key buffer.  Row j of a tile is the
 // kSortThreads consecutive keys [j * kSortThreads, (j + 1) * kSortThreads): a wave ballot
 // per row and a prefix over (row, wave) give each head its place, so consecutive lanes read,
 // gather and write consecutive keys.
@@ -429,8 +478,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
                 uint64_t lo, hi;
                 edge_key_split(k[j], kb, hbs, lo, hi);
                 // ids were checked by the count pass (a failed check flags the round)
-                const uint32_t a = lo < n_cur ? w.newidx[lo] : 0u;
-                const uint32_t b = hi < n_cur ? w.newidx[hi] : 0u;
+                const uint32_t a = lo < n_cur ? nmap_rank(w.nmap, lo) : 0u;
+                const uint32_t b = hi < n_cur ? nmap_rank(w.nmap, hi) : 0u;
                 out[off] = ((uint64_t)a << 32) | b;
             }
         }
@@ -480,6 +529,17 @@ hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, in
             hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
             return hipGetLastError();
     }
+}
+
+hipError_t launch_node_scan(const Work &w, int grid, hipStream_t s, int stage) {
+    if (stage == 0)
+        hipLaunchKernelGGL(k_nmap_reduce, dim3(grid), dim3(kThreads), 0, s, w);
+    else if (stage == 1)   // one partial per kScanTile words of 32 nodes
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, &w.st->n_cur, 32 * kScanTile,
+                           &w.st->n_next);
+    else
+        hipLaunchKernelGGL(k_nmap_down, dim3(grid), dim3(kThreads), 0, s, w);
+    return hipGetLastError();
 }
 
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage) {
