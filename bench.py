@@ -76,7 +76,7 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
         sfx = "_round0" if r == 0 else ""
         add("round_begin", 9 * N + N // 4)         # m1, lv (4 B), a flag byte and the node-map word per node
-        add("plan_blocks", N)                      # parent flags in
+        add("label_ranks", 8 * N + 3 * N // 8)     # parents in, their label ranks out, label map scanned
         if r == 0 and tiled:
             T = 2 * (M - loops)
             add("part_a_hist", 8 * M)              # records in

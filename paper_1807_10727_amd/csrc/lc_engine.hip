@@ -22,7 +22,7 @@ namespace lc {
 // Kernel families timed with CC_PROFILE.  The round-0 passes over the input records
 // ("_round0") are separate families, so each of them is exactly one kernel symbol.
 const char *const kFamilyNames[kFamilies] = {
-    "round_begin", "min1_round0", "min1",      "min2_round0", "min2",      "parent",    "plan_blocks",
+    "round_begin", "min1_round0", "min1",      "min2_round0", "min2",      "parent",    "label_ranks",
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
@@ -63,7 +63,9 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     t.ml = (uint32_t *)take(8 * n);
     t.par = (uint32_t *)take(4 * n);
     t.nmap = (uint32_t *)take(8 * (size_t)ceil_div((int64_t)n, 32) + 64);
-    t.is_label = (uint8_t *)take(n + 16);
+    t.is_label = (uint8_t *)take(n + 64);
+    t.lmap = (uint32_t *)take(8 * (size_t)ceil_div((int64_t)n, 32) + 64);
+    t.lab_at = (uint32_t *)take(4 * n);
     t.newidx = (uint32_t *)take(4 * n);
     t.names[0] = (uint32_t *)take(4 * n);
     t.names[1] = (uint32_t *)take(4 * n);
@@ -154,6 +156,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
     const int gscan_n = (int)std::min<int64_t>(ceil_div(ceil_div(std::max<int64_t>(N, 1), 32), kScanTile), grid_cap);
+    const int gscan_l = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), 32 * kThreads), grid_cap);
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = 2 * kb;   // edge_key
     const int passes = passes_bound >= 0 ? passes_bound : npasses(nbits);
@@ -182,13 +185,13 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
         RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream));
         RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
-        RUN(kPlanBlocks, launch_plan_blocks(w, gn, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
         RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
     } else {
         RUN(first ? kMin1In : kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
         RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
         RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
-        RUN(kPlanBlocks, launch_plan_blocks(w, gn, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     }
     for (int p = 0; p < passes; ++p) {
@@ -200,9 +203,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kUnique, launch_unique(w, gt, stream, 0));
     RUN(kUnique, launch_unique(w, 1, stream, 1));
-    RUN(kNodeScan, launch_node_scan(w, gscan_n, stream, 0));
-    RUN(kNodeScan, launch_node_scan(w, 1, stream, 1));
-    RUN(kNodeScan, launch_node_scan(w, gscan_n, stream, 2));
+    RUN(kNodeScan, launch_map_scan(w, false, gscan_n, stream, 0));
+    RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 1));
+    RUN(kNodeScan, launch_map_scan(w, false, gscan_n, stream, 2));
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
     RUN(kUnique, launch_unique(w, gt, stream, 2));

@@ -13,7 +13,7 @@
 namespace lc {
 
 enum Family {
-    kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kPlanBlocks, kRelabelIn, kRelabel, kSortHist,
+    kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
     kTailGraph, kFamilies

@@ -81,9 +81,14 @@ struct PrioCtx {
 struct Work {
     RoundState *st;
     uint32_t *ml;        // [2 n0] node word: ml[2x] one-hop minimum, ml[2x+1] two-hop minimum
-    uint32_t *par;       // [n0] parent of each node (compact index of this round)
+    uint32_t *par;       // [n0] parent of each node: its index in this round, then (after
+                         // the label scan) its rank among the labels, or kNoParent
     uint32_t *nmap;      // [2 ceil(n0 / 32)] next-graph node map (see nmap_rank)
-    uint8_t *is_label;   // [n0] node of this round is somebody's parent
+    uint8_t *is_label;   // [n0] node of this round is somebody's parent (byte stores: many
+                         // nodes name the same parent, which bit atomics would serialise)
+    uint32_t *lmap;      // [2 ceil(n0 / 32)] the same as bits (nmap format): a label's
+                         // rank among them is the index its edges use in the sort keys
+    uint32_t *lab_at;    // [n0] node of this round that is the label of each rank
     uint32_t *newidx;    // [n0] scratch of the canonical relabelling
     uint32_t *names[2];  // [n0] node names, rounds >= 1 (round r uses names[r & 1])
     uint32_t *gids[2];   // [n0] batch: graph of each node, rounds >= 1
@@ -135,6 +140,9 @@ constexpr int kSlab = 2 * kSortTile;               // records per relabel workgr
 constexpr int64_t kBlockNodes = 1 << LC_BLOCK_NODES_LOG2;
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// A round-0 id without a loop-free record has no parent and is nobody's parent (its rank).
+constexpr uint32_t kNoParent = 0xFFFFFFFFu;
 
 // Next-graph node map of a round.  Word pair i covers nodes 32 i .. 32 i + 31 of the round:
 // nmap[2 i] has a bit for each of them that keeps an edge, nmap[2 i + 1] counts the nodes
@@ -237,12 +245,14 @@ hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool b
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
 hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
-hipError_t launch_plan_blocks(const Work &w, int grid, hipStream_t s);
+// parents -> label ranks, the label of each rank, and the key width of the sort
+hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
                           int grid, hipStream_t s, int stage);
-// prefix counts of the next-graph node map; the total becomes n_next
-hipError_t launch_node_scan(const Work &w, int grid, hipStream_t s, int stage);
+// prefix counts of the label map (total -> n_labels) or of the next-graph node map over the
+// labels (total -> n_next)
+hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
                            hipStream_t s, int stage);
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);

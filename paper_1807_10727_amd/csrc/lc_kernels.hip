@@ -378,49 +378,47 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     }
 }
 
-// distinct parents of the round (the flags set by k_parent)
-__global__ __launch_bounds__(kThreads) void k_count_labels(Work w) {
-    RoundState *st = w.st;
-    const int64_t n = (int64_t)st->n_cur;
-    uint32_t c = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        c += w.is_label[i];
-    __shared__ uint32_t red[kThreads / kWave];
-    c = block_sum<kThreads>(c, red);
-    if (threadIdx.x == 0 && c) atomicAdd(&st->n_labels, (u64c)c);
+// Parents become ranks among the labels (the distinct parents, marked in lmap, whose scan
+// has just run): the relabelled edges then name their endpoints with ceil(log2 L) bits
+// instead of ceil(log2 N), and everything after the relabel works over the L labels.
+// lab_at inverts the ranking.
+__global__ __launch_bounds__(kThreads) void k_rank_parents(Work w) {
+    const int64_t n = (int64_t)w.st->n_cur;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t p = w.par[i];
+        w.par[i] = nmap_has(w.lmap, p) ? nmap_rank(w.lmap, p) : kNoParent;
+        if (nmap_has(w.lmap, i)) w.lab_at[nmap_rank(w.lmap, i)] = (uint32_t)i;
+    }
 }
 
-// Block width for the next round's edge order: about kBlockNodes parents per block,
-// assuming parents spread evenly over this round's indices (the key keeps 2 kb bits).
+// Key width of the round's sort (2 ceil(log2 L) bits) and the block width of the next
+// round's edge order: kBlockNodes labels, which become about as many next-round nodes.
 __global__ void k_plan_blocks(Work w) {
     RoundState *st = w.st;
-    const uint64_t N = st->n_cur, L = st->n_labels;
-    const int kb = st->kb;
-    int shift = kb;
-    if (L > 0 && N > 0) {
-        uint64_t width = (uint64_t)kBlockNodes * N / L;
-        if (width < 1) width = 1;
-        shift = 63 - __clzll((long long)width);              // floor(log2(width))
-        if (shift > kb) shift = kb;
-    }
-    st->hb_shift = shift;
+    const uint64_t L = st->n_labels;
+    const int kb = ceil_log2(L < 2 ? 2 : L);
+    st->kb = kb;
+    st->hb_shift = kb < LC_BLOCK_NODES_LOG2 ? kb : LC_BLOCK_NODES_LOG2;
     st->nbits = 2 * kb;
 }
 
+// The next graph's nodes: the labels that keep an edge, named and indexed; the others are
+// final (counted).
 template <bool kFirst, bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_nodes(Work w, const uint32_t *names_cur, uint32_t *names_next,
                                                     const uint32_t *gids_cur, uint32_t *gids_next) {
     RoundState *st = w.st;
-    const int64_t n = (int64_t)st->n_cur;
+    const int64_t L = (int64_t)st->n_labels;
     uint32_t fin = 0;
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < n; j += (int64_t)gridDim.x * kThreads) {
+    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < L; j += (int64_t)gridDim.x * kThreads) {
         if (nmap_has(w.nmap, j)) {
             const uint32_t k = nmap_rank(w.nmap, j);
-            const uint32_t nm = kFirst ? (uint32_t)j : names_cur[j];
+            const uint32_t x = w.lab_at[j];
+            const uint32_t nm = kFirst ? x : names_cur[x];
             names_next[k] = nm;
             w.idx_of[nm] = k;
-            if (kBatch) gids_next[k] = kFirst ? w.gid0[j] : gids_cur[j];
-        } else if (w.is_label[j]) {
+            if (kBatch) gids_next[k] = kFirst ? w.gid0[x] : gids_cur[x];
+        } else {
             ++fin;
         }
     }
@@ -444,12 +442,21 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
         }
         out = w.maps + st->map_off;
     }
-    // the parent's bit and its index in the next graph come from one 8-byte word of the map
+    // the parent's bit and its index in the next graph come from one 8-byte word of the map;
+    // a final parent is named through the label of its rank
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t p = w.par[i];
-        const uint2 e = *(const uint2 *)(w.nmap + 2 * (p >> 5));
-        const uint32_t below = e.x & ((1u << (p & 31)) - 1u);
-        out[i] = ((e.x >> (p & 31)) & 1u) ? e.y + (uint32_t)__popc(below) : (kFinal | (kFirst ? p : names_cur[p]));
+        const uint32_t q = w.par[i];
+        if (q == kNoParent) {   // round 0: an id without a loop-free record is final on its own
+            out[i] = kFinal | (uint32_t)i;
+            continue;
+        }
+        const uint2 e = *(const uint2 *)(w.nmap + 2 * (q >> 5));
+        if ((e.x >> (q & 31)) & 1u) {
+            out[i] = e.y + (uint32_t)__popc(e.x & ((1u << (q & 31)) - 1u));
+        } else {
+            const uint32_t x = w.lab_at[q];
+            out[i] = kFinal | (kFirst ? x : names_cur[x]);
+        }
     }
 }
 
@@ -547,15 +554,15 @@ __global__ __launch_bounds__(kThreads) void k_fill_u32(uint32_t *p, uint32_t v, 
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = v;
 }
 
-// parents of the round that just ended, by name (inspection aid).  In round 0 an id without
-// a loop-free record is its own parent and nobody else's (it is in no neighbourhood), and
-// it is reported as not being a node.
+// parents of the round that just ended, by name (inspection aid; par holds label ranks).
+// In round 0 an id without a loop-free record has no parent and is nobody's (it is in no
+// neighbourhood): it is reported as not being a node.
 __global__ __launch_bounds__(kThreads) void k_dump_parents(Work w, int first, const uint32_t *names_prev,
                                                            int32_t *out) {
     const int64_t n = (int64_t)w.st->n_prev;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        if (first && w.par[i] == (uint32_t)i && !w.is_label[i]) continue;
-        const uint32_t p = w.par[i];
+        if (w.par[i] == kNoParent) continue;
+        const uint32_t p = w.lab_at[w.par[i]];
         const uint32_t x = first ? (uint32_t)i : names_prev[i];
         out[x] = (int32_t)(first ? p : names_prev[p]);
     }
@@ -657,9 +664,13 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
     }
 }
 
-hipError_t launch_plan_blocks(const Work &w, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_labels, dim3(grid), dim3(kThreads), 0, s, w);
-    hipError_t e = hipGetLastError();
+hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
+        e = launch_map_scan(w, true, stage == 1 ? 1 : grid_scan, s, stage);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank_parents, dim3(grid), dim3(kThreads), 0, s, w);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_plan_blocks, dim3(1), dim3(1), 0, s, w);
     return hipGetLastError();

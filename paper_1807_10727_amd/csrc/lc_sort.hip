@@ -339,45 +339,94 @@ void k_sort_scatter(Work w, int pass) {
 // ---------------------------------------------------------------------------------------
 
 // Thread t of a block takes the 16 consecutive words [16 t, 16 t + 16) of the block's kScanTile.
-__device__ inline void nmap_load16(const uint32_t *nmap, int64_t base, int64_t nw, uint32_t (&c)[16]) {
+__device__ inline void map_load16(const uint32_t *map, int64_t base, int64_t nw, uint32_t (&c)[16]) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) c[j] = base + j < nw ? (uint32_t)__popc(nmap[2 * (base + j)]) : 0u;
+    for (int j = 0; j < 16; ++j) c[j] = base + j < nw ? (uint32_t)__popc(map[2 * (base + j)]) : 0u;
 }
 
-__global__ __launch_bounds__(kThreads) void k_nmap_reduce(Work w) {
+// map covers *n_ptr entries
+__global__ __launch_bounds__(kThreads) void k_map_reduce(const uint32_t *map, const u64c *n_ptr, uint32_t *partials) {
     __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t nw = ceil_div((int64_t)w.st->n_cur, 32);
+    const int64_t nw = ceil_div((int64_t)*n_ptr, 32);
     const int64_t nblk = ceil_div(nw, kScanTile);
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         uint32_t c[16];
-        nmap_load16(w.nmap, blk * kScanTile + threadIdx.x * 16, nw, c);
+        map_load16(map, blk * kScanTile + threadIdx.x * 16, nw, c);
         uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < 16; ++j) sum += c[j];
         uint32_t total;
         block_excl_scan<kThreads>(sum, lds, &total);
-        if (threadIdx.x == 0) w.partials[blk] = total;
+        if (threadIdx.x == 0) partials[blk] = total;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_nmap_down(Work w) {
+__global__ __launch_bounds__(kThreads) void k_map_down(uint32_t *map, const u64c *n_ptr, const uint32_t *partials) {
     __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t nw = ceil_div((int64_t)w.st->n_cur, 32);
+    const int64_t nw = ceil_div((int64_t)*n_ptr, 32);
     const int64_t nblk = ceil_div(nw, kScanTile);
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         uint32_t c[16];
         const int64_t my = blk * kScanTile + threadIdx.x * 16;
-        nmap_load16(w.nmap, my, nw, c);
+        map_load16(map, my, nw, c);
         uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < 16; ++j) sum += c[j];
         uint32_t total;
-        uint32_t run = w.partials[blk] + block_excl_scan<kThreads>(sum, lds, &total);
+        uint32_t run = partials[blk] + block_excl_scan<kThreads>(sum, lds, &total);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            if (my + j < nw) w.nmap[2 * (my + j) + 1] = run;
+            if (my + j < nw) map[2 * (my + j) + 1] = run;
             run += c[j];
         }
+    }
+}
+
+// Label map from the label bytes: thread t of a block turns the 32 bytes of word
+// blk * kThreads + t into bits; the block's counts are scanned like any other.
+__device__ inline uint32_t label_bits(const uint8_t *f, int64_t w, int64_t n) {
+    const int64_t base = w * 32;
+    uint32_t bits = 0;
+    if (base + 32 <= n) {
+        const uint4 a = *(const uint4 *)(f + base), b = *(const uint4 *)(f + base + 16);
+        const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bits |= (((v[q] >> (8 * k)) & 0xFFu) != 0u ? 1u : 0u) << (4 * q + k);
+    } else {
+        for (int k = 0; k < 32; ++k)
+            if (base + k < n && f[base + k]) bits |= 1u << k;
+    }
+    return bits;
+}
+
+__global__ __launch_bounds__(kThreads) void k_label_reduce(const uint8_t *f, const u64c *n_ptr, uint32_t *partials) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t nw = ceil_div(n, 32);
+    const int64_t nblk = ceil_div(nw, kThreads);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t wd = blk * kThreads + threadIdx.x;
+        const uint32_t c = wd < nw ? (uint32_t)__popc(label_bits(f, wd, n)) : 0u;
+        uint32_t total;
+        block_excl_scan<kThreads>(c, lds, &total);
+        if (threadIdx.x == 0) partials[blk] = total;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_label_down(const uint8_t *f, const u64c *n_ptr,
+                                                         const uint32_t *partials, uint32_t *lmap) {
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t nw = ceil_div(n, 32);
+    const int64_t nblk = ceil_div(nw, kThreads);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t wd = blk * kThreads + threadIdx.x;
+        const uint32_t bits = wd < nw ? label_bits(f, wd, n) : 0u;
+        uint32_t total;
+        const uint32_t before = partials[blk] + block_excl_scan<kThreads>((uint32_t)__popc(bits), lds, &total);
+        if (wd < nw) *(uint2 *)(lmap + 2 * wd) = make_uint2(bits, before);
     }
 }
 
@@ -397,7 +446,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     const uint64_t *in = w.keys[sorted_sel(st->round, st->e_sel, st->nbits)];
     const int kb = st->kb;
     const int hbs = st->hb_shift;
-    const uint64_t n_cur = st->n_cur;
+    const uint64_t n_lab = st->n_labels;   // key endpoints are label ranks
     bool broken = false;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         uint32_t cnt = 0;
@@ -411,7 +460,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
                 uint64_t lo, hi, plo = ~0ull, phi;
                 edge_key_split(k, kb, hbs, lo, hi);
                 if (idx > 0) edge_key_split(prev, kb, hbs, plo, phi);
-                if (lo < n_cur && hi < n_cur) {
+                if (lo < n_lab && hi < n_lab) {
                     if (plo != lo) nmap_mark(w.nmap, lo);
                     nmap_mark(w.nmap, hi);
                 } else {
@@ -442,7 +491,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     uint64_t *out = w.keys[1 - t];
     const int kb = st->kb;
     const int hbs = st->hb_shift;
-    const uint64_t n_cur = st->n_cur;
+    const uint64_t n_lab = st->n_labels;   // key endpoints are label ranks
     const int wave = threadIdx.x / kWave;
     const uint64_t lt = lanemask_lt();
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -478,8 +527,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
                 uint64_t lo, hi;
                 edge_key_split(k[j], kb, hbs, lo, hi);
                 // ids were checked by the count pass (a failed check flags the round)
-                const uint32_t a = lo < n_cur ? nmap_rank(w.nmap, lo) : 0u;
-                const uint32_t b = hi < n_cur ? nmap_rank(w.nmap, hi) : 0u;
+                const uint32_t a = lo < n_lab ? nmap_rank(w.nmap, lo) : 0u;
+                const uint32_t b = hi < n_lab ? nmap_rank(w.nmap, hi) : 0u;
                 out[off] = ((uint64_t)a << 32) | b;
             }
         }
@@ -531,14 +580,27 @@ hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, in
     }
 }
 
-hipError_t launch_node_scan(const Work &w, int grid, hipStream_t s, int stage) {
+hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage) {
+    if (labels) {   // label bytes of this round's nodes -> label map
+        const u64c *n = &w.st->n_cur;
+        if (stage == 0)
+            hipLaunchKernelGGL(k_label_reduce, dim3(grid), dim3(kThreads), 0, s, w.is_label, n, w.partials);
+        else if (stage == 1)   // one partial per kThreads words of 32 nodes
+            hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kThreads,
+                               &w.st->n_labels);
+        else
+            hipLaunchKernelGGL(k_label_down, dim3(grid), dim3(kThreads), 0, s, w.is_label, n,
+                               (const uint32_t *)w.partials, w.lmap);
+        return hipGetLastError();
+    }
+    // node map over the labels
+    const u64c *n = &w.st->n_labels;
     if (stage == 0)
-        hipLaunchKernelGGL(k_nmap_reduce, dim3(grid), dim3(kThreads), 0, s, w);
-    else if (stage == 1)   // one partial per kScanTile words of 32 nodes
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, &w.st->n_cur, 32 * kScanTile,
-                           &w.st->n_next);
+        hipLaunchKernelGGL(k_map_reduce, dim3(grid), dim3(kThreads), 0, s, w.nmap, n, w.partials);
+    else if (stage == 1)   // one partial per kScanTile words of 32 entries
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kScanTile, &w.st->n_next);
     else
-        hipLaunchKernelGGL(k_nmap_down, dim3(grid), dim3(kThreads), 0, s, w);
+        hipLaunchKernelGGL(k_map_down, dim3(grid), dim3(kThreads), 0, s, w.nmap, n, (const uint32_t *)w.partials);
     return hipGetLastError();
 }
 

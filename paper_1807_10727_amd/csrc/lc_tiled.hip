@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
             if (kStep == 1) {
                 m1[x] = a == kInf ? kInf : min(a, prio(pc.key, x));
             } else if (a == kInf) {
-                w.par[x] = x;
+                w.par[x] = x;   // no loop-free record: not a label, ranked as kNoParent
             } else {
                 uint32_t p = prio_inv(pc.key, min(a, m1[x]));
                 if ((int64_t)p >= n) {   // cannot happen for a consistent state
