@@ -75,7 +75,7 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
         K = sorted_keys[i] if sorted_keys is not None else s
         P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
         sfx = "_round0" if r == 0 else ""
-        add("round_begin", 9 * N + N // 4)         # m1, lv (4 B), a flag byte and the node-map word per node
+        add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
         add("label_ranks", 8 * N + 3 * N // 8)     # parents in, their label ranks out, label map scanned
         if r == 0 and tiled:
             T = 2 * (M - loops)
@@ -93,8 +93,8 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
             add("relabel" + sfx, 8 * M + 4 * N + 8 * K)   # records in, parents in once, keys out
         add("sort_hist", 8 * K * P)                # keys in per pass
         add("sort_scatter", 16 * K * P)            # keys in and out per pass
-        add("unique", 16 * K + 8 * m_out + N // 4)  # sorted keys read twice, renamed unique keys out, node map
-        add("node_scan", 3 * N // 8)               # node-map bits in (twice), prefix counts out
+        add("unique", 16 * K + 8 * m_out)          # sorted keys read twice, renamed unique keys out
+        add("node_scan", 2 * N)                    # flags of the labels (at most N) in twice, node map out
         add("nodes", 9 * N)
         add("map", 9 * N)
     fam["compose"] = fam.get("compose", 0) + 8 * n0

@@ -19,6 +19,16 @@ Parity status of its functions (what pins each one; the tests hold the pins):
                         by the frozen priority specification (the paper fixes no values).
   * ``run`` stats    -- pinned by recount from the brute force on small graphs and by the
                         paper's invariants (component count preserved, path lower bound).
+  * ``run(variant="tree")`` -- TreeContraction (Section 3): pinned by a brute force that walks
+                        v, f(v), f(f(v)), ... to the terminal 2-cycle (Lemma "cycle") on every
+                        labelled graph with up to 6 vertices, by the lemma's invariants (every
+                        merged class has at least two nodes, classes are connected, two
+                        nodes share a class iff their terminal cycles agree), and by partition.
+  * ``run(variant="one_hop")`` -- closed one-hop labels: pinned by the same brute force with
+                        one hop, and by partition.
+  * ``run(finish_edges=T)`` -- union-find finish (Section 6): pinned by the per-round results
+                        being those of the plain run up to the switch, and by labels equal to
+                        the smallest name of each remaining component (recomputed with scipy).
 """
 from __future__ import annotations
 
@@ -72,6 +82,9 @@ def _load():
         lib.lco_run.argtypes = [ctypes.c_int64, ctypes.c_int64, u32p, u32p, ctypes.c_uint64, u32p, ctypes.c_int32,
                                 ctypes.c_int32, u32p, ctypes.POINTER(RoundStats), ctypes.c_int32, u32p,
                                 ctypes.c_int32]
+        lib.lco_run_variant.restype = ctypes.c_int32
+        lib.lco_run_variant.argtypes = lib.lco_run.argtypes + [ctypes.c_int32, ctypes.c_int64,
+                                                               ctypes.POINTER(ctypes.c_int32)]
         lib.lco_run_batch.restype = ctypes.c_int32
         lib.lco_run_batch.argtypes = [ctypes.c_int64, i64p, i64p, u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p,
                                       ctypes.POINTER(ctypes.c_int32), u32p, ctypes.c_int32]
@@ -101,18 +114,25 @@ def priority(seed: int, rnd: int, name: int) -> int:
     return int(_load().lco_priority(seed & 0xFFFFFFFFFFFFFFFF, rnd, name & 0xFFFFFFFF))
 
 
+VARIANTS = {"local": 0, "tree": 1, "one_hop": 2}
+
+
 @dataclass
 class Result:
     labels: np.ndarray                 # uint32 [n0]
     rounds: int
     stats: list = field(default_factory=list)   # tuples (round, n_active, m_in, m_survive, m_out, n_finalised)
     parents: np.ndarray | None = None  # uint32 [min(rounds, cap), n0], NOT_A_NODE off V_r
+    finished: bool = False             # the union-find finish ran
 
 
 def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0,
-        record_parents: bool = False, parents_cap: int = 64, stats_cap: int = 256) -> Result:
+        record_parents: bool = False, parents_cap: int = 64, stats_cap: int = 256, variant: str = "local",
+        finish_edges: int = 0) -> Result:
     """Run the oracle.  `explicit_prio` is an optional [rows, n] table of priorities (phase r
-    uses row min(r, rows-1))."""
+    uses row min(r, rows-1)).  `variant`: "local" (LocalContraction), "tree"
+    (TreeContraction) or "one_hop"; `finish_edges` > 0 finishes with union-find once a phase
+    leaves at most that many edges."""
     lib = _load()
     src = _u32(src)
     dst = _u32(dst)
@@ -126,12 +146,15 @@ def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0
         ep = np.ascontiguousarray(np.atleast_2d(explicit_prio), dtype=np.uint32)
         assert ep.shape[1] == n
         rows = ep.shape[0]
-    r = lib.lco_run(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
-                    _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats, stats_cap,
-                    _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0)
+    fin = ctypes.c_int32(0)
+    r = lib.lco_run_variant(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
+                            _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats,
+                            stats_cap, _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0,
+                            VARIANTS[variant], int(finish_edges), ctypes.byref(fin))
     if r < 0:
         raise ValueError("oracle rejected the input (ids out of range or out of memory)")
-    res = Result(labels[:n], int(r), [stats[i].as_tuple() for i in range(min(r, stats_cap))])
+    res = Result(labels[:n], int(r), [stats[i].as_tuple() for i in range(min(r, stats_cap))],
+                 finished=bool(fin.value))
     if record_parents:
         res.parents = par[:min(r, parents_cap), :n]
     return res

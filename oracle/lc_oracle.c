@@ -23,6 +23,18 @@
  * after each phase).  The labels of the original vertices are the composition
  * of the per-phase maps.
  *
+ * Two other ways to choose the labels of step 2 share steps 1, 3 and 4:
+ *   - TreeContraction (Section 3, paragraph "TreeContraction"): every node v
+ *     points to f(v), the vertex of smallest priority in N(v) \ {v}; nodes in
+ *     the same weakly connected component of the graph of f are merged.  The
+ *     merged node is named by the component's vertex of smallest priority
+ *     (a reading: the paper names no representative);
+ *   - the one-hop label (Section 6, the Cracker-equivalent rule without its
+ *     edge rewiring): the vertex of smallest priority in the closed N(v).
+ * And an optional finish (Section 6): once a phase leaves at most
+ * `finish_edges` edges, the components of what is left are found by
+ * union-find, and each is named by its smallest name.
+ *
  * Readings of points the paper leaves open (all shared with the GPU library
  * by specification only, never by code):
  *   - a merged node is named by the original id of its label vertex;
@@ -94,8 +106,27 @@ static int64_t sort_unique(uint64_t *k, int64_t n) {
     return w;
 }
 
+#define LCO_LOCAL 0     /* LocalContraction */
+#define LCO_TREE 1      /* TreeContraction */
+#define LCO_ONE_HOP 2   /* one-hop label */
+
+/* union-find over names (path halving), for the TreeContraction components and the finish */
+static uint32_t uf_find(uint32_t *up, uint32_t x) {
+    while (up[x] != x) {
+        up[x] = up[up[x]];
+        x = up[x];
+    }
+    return x;
+}
+
+static void uf_union(uint32_t *up, uint32_t a, uint32_t b) {
+    a = uf_find(up, a);
+    b = uf_find(up, b);
+    if (a != b) up[a < b ? b : a] = a < b ? a : b;
+}
+
 /*
- * Run LocalContraction on n0 vertices and m0 records (src[i], dst[i]).
+ * Run LocalContraction (or a variant) on n0 vertices and m0 records (src[i], dst[i]).
  *
  *   explicit_prio  optional [prio_rows][n0] table; phase r uses row
  *                  min(r, prio_rows-1); values must be distinct on the nodes
@@ -106,12 +137,18 @@ static int64_t sort_unique(uint64_t *k, int64_t n) {
  *   parents        out [parents_cap][n0]: label vertex of every node of the
  *                  phase, 0xFFFFFFFF for names that are not nodes of it
  *                  (may be NULL).
+ *   variant        LCO_LOCAL, LCO_TREE or LCO_ONE_HOP.
+ *   finish_edges   0, or: before every phase after the first, if at most this
+ *                  many edges are left, finish with union-find instead.
+ *   finished       out (may be NULL): 1 when the finish ran.
  * Returns the number of phases run, or -1 on bad input / out of memory.
  */
-int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
-                const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
-                uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
-                int32_t parents_cap) {
+int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
+                        const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
+                        uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
+                        int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished) {
+    if (variant < LCO_LOCAL || variant > LCO_ONE_HOP) return -1;
+    if (finished) *finished = 0;
     if (n0 < 0 || m0 < 0 || n0 > 0xFFFFFFFFLL) return -1;
     for (int64_t i = 0; i < m0; ++i)
         if ((int64_t)src[i] >= n0 || (int64_t)dst[i] >= n0) return -1;
@@ -127,9 +164,10 @@ int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst
     uint32_t *m1_arg = (uint32_t *)malloc(sizeof(uint32_t) * nn);
     uint32_t *l_val = (uint32_t *)malloc(sizeof(uint32_t) * nn);
     uint32_t *l_arg = (uint32_t *)malloc(sizeof(uint32_t) * nn);
-    if (!E || !E2 || !in_v || !is_label || !in_next || !rho || !m1_val || !m1_arg || !l_val || !l_arg) {
+    uint32_t *up = (uint32_t *)malloc(sizeof(uint32_t) * nn);
+    if (!E || !E2 || !in_v || !is_label || !in_next || !rho || !m1_val || !m1_arg || !l_val || !l_arg || !up) {
         free(E); free(E2); free(in_v); free(is_label); free(in_next);
-        free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg);
+        free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg); free(up);
         return -1;
     }
 
@@ -143,6 +181,24 @@ int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst
 
     int32_t r = 0;
     while (mE > 0 && (max_rounds <= 0 || r < max_rounds)) {
+        if (finish_edges > 0 && r > 0 && mE <= finish_edges) {
+            /* Section 6: the small remaining graph's components by union-find; a
+               component is named by its smallest name */
+            for (int64_t x = 0; x < n0; ++x) up[x] = (uint32_t)x;
+            for (int64_t i = 0; i < mE; ++i) uf_union(up, (uint32_t)(E[i] >> 32), (uint32_t)E[i]);
+            memset(in_v, 0, nn);
+            for (int64_t i = 0; i < mE; ++i) {
+                in_v[E[i] >> 32] = 1;
+                in_v[(uint32_t)E[i]] = 1;
+            }
+            /* linking the larger root under the smaller keeps every root the smallest
+               name of its component */
+            for (int64_t v = 0; v < n0; ++v)
+                if (in_v[labels[v]]) labels[v] = uf_find(up, labels[v]);
+            if (finished) *finished = 1;
+            mE = 0;
+            break;
+        }
         /* V_r: endpoints of the current edges */
         memset(in_v, 0, nn);
         for (int64_t i = 0; i < mE; ++i) {
@@ -161,21 +217,52 @@ int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst
             }
         }
 
-        /* closed one-hop argmin: v itself, then every neighbour */
-        for (int64_t x = 0; x < n0; ++x)
-            if (in_v[x]) { m1_val[x] = rho[x]; m1_arg[x] = (uint32_t)x; }
-        for (int64_t i = 0; i < mE; ++i) {
-            uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
-            if (rho[b] < m1_val[a]) { m1_val[a] = rho[b]; m1_arg[a] = b; }
-            if (rho[a] < m1_val[b]) { m1_val[b] = rho[a]; m1_arg[b] = a; }
-        }
-        /* the same over the one-hop results: argmin of rho over N(N(v)) */
-        for (int64_t x = 0; x < n0; ++x)
-            if (in_v[x]) { l_val[x] = m1_val[x]; l_arg[x] = m1_arg[x]; }
-        for (int64_t i = 0; i < mE; ++i) {
-            uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
-            if (m1_val[b] < l_val[a]) { l_val[a] = m1_val[b]; l_arg[a] = m1_arg[b]; }
-            if (m1_val[a] < l_val[b]) { l_val[b] = m1_val[a]; l_arg[b] = m1_arg[a]; }
+        if (variant == LCO_TREE) {
+            /* f(v): argmin of rho over the neighbours other than v (every node of
+               the phase has one: the edges are loop-free) */
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) { m1_val[x] = 0xFFFFFFFFu; m1_arg[x] = (uint32_t)x; }
+            for (int64_t i = 0; i < mE; ++i) {
+                uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
+                if (m1_arg[a] == (uint32_t)a || rho[b] < m1_val[a]) { m1_val[a] = rho[b]; m1_arg[a] = b; }
+                if (m1_arg[b] == (uint32_t)b || rho[a] < m1_val[b]) { m1_val[b] = rho[a]; m1_arg[b] = a; }
+            }
+            /* weakly connected components of the graph v -> f(v) */
+            for (int64_t x = 0; x < n0; ++x) up[x] = (uint32_t)x;
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) uf_union(up, (uint32_t)x, m1_arg[x]);
+            /* each component's vertex of smallest priority names it */
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) l_val[x] = 0xFFFFFFFFu;
+            for (int64_t x = 0; x < n0; ++x) {
+                if (!in_v[x]) continue;
+                uint32_t c = uf_find(up, (uint32_t)x);
+                if (l_val[c] == 0xFFFFFFFFu || rho[x] < rho[l_arg[c]]) { l_val[c] = 0; l_arg[c] = (uint32_t)x; }
+            }
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) m1_val[x] = l_arg[uf_find(up, (uint32_t)x)];
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) l_arg[x] = m1_val[x];
+        } else {
+            /* closed one-hop argmin: v itself, then every neighbour */
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) { m1_val[x] = rho[x]; m1_arg[x] = (uint32_t)x; }
+            for (int64_t i = 0; i < mE; ++i) {
+                uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
+                if (rho[b] < m1_val[a]) { m1_val[a] = rho[b]; m1_arg[a] = b; }
+                if (rho[a] < m1_val[b]) { m1_val[b] = rho[a]; m1_arg[b] = a; }
+            }
+            /* LocalContraction: the same over the one-hop results, argmin of rho
+               over N(N(v)); the one-hop label stops here */
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) { l_val[x] = m1_val[x]; l_arg[x] = m1_arg[x]; }
+            if (variant == LCO_LOCAL) {
+                for (int64_t i = 0; i < mE; ++i) {
+                    uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
+                    if (m1_val[b] < l_val[a]) { l_val[a] = m1_val[b]; l_arg[a] = m1_arg[b]; }
+                    if (m1_val[a] < l_val[b]) { l_val[b] = m1_val[a]; l_arg[b] = m1_arg[a]; }
+                }
+            }
         }
         /* l_arg[x] is now the label vertex (parent) of node x */
 
@@ -240,8 +327,16 @@ int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst
     }
 
     free(E); free(E2); free(in_v); free(is_label); free(in_next);
-    free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg);
+    free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg); free(up);
     return r;
+}
+
+int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
+                const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
+                uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
+                int32_t parents_cap) {
+    return lco_run_variant(n0, m0, src, dst, seed, explicit_prio, prio_rows, max_rounds, labels, stats, stats_cap,
+                           parents, parents_cap, LCO_LOCAL, 0, NULL);
 }
 
 /*

@@ -62,6 +62,7 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     t.st = (RoundState *)take(sizeof(RoundState));
     t.ml = (uint32_t *)take(8 * n);
     t.par = (uint32_t *)take(4 * n);
+    t.has_edge = (uint8_t *)take(n + 64);
     t.nmap = (uint32_t *)take(8 * (size_t)ceil_div((int64_t)n, 32) + 64);
     t.is_label = (uint8_t *)take(n + 64);
     t.lmap = (uint32_t *)take(8 * (size_t)ceil_div((int64_t)n, 32) + 64);
@@ -155,7 +156,6 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gn = grid_for(N);
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
-    const int gscan_n = (int)std::min<int64_t>(ceil_div(ceil_div(std::max<int64_t>(N, 1), 32), kScanTile), grid_cap);
     const int gscan_l = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), 32 * kThreads), grid_cap);
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = 2 * kb;   // edge_key
@@ -203,9 +203,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kUnique, launch_unique(w, gt, stream, 0));
     RUN(kUnique, launch_unique(w, 1, stream, 1));
-    RUN(kNodeScan, launch_map_scan(w, false, gscan_n, stream, 0));
+    RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 0));
     RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 1));
-    RUN(kNodeScan, launch_map_scan(w, false, gscan_n, stream, 2));
+    RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 2));
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
     RUN(kUnique, launch_unique(w, gt, stream, 2));

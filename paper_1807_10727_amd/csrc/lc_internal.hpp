@@ -83,7 +83,8 @@ struct Work {
     uint32_t *ml;        // [2 n0] node word: ml[2x] one-hop minimum, ml[2x+1] two-hop minimum
     uint32_t *par;       // [n0] parent of each node: its index in this round, then (after
                          // the label scan) its rank among the labels, or kNoParent
-    uint32_t *nmap;      // [2 ceil(n0 / 32)] next-graph node map (see nmap_rank)
+    uint8_t *has_edge;   // [n0] label keeps an edge (byte stores by the unique count pass)
+    uint32_t *nmap;      // [2 ceil(n0 / 32)] the same as bits: next-graph node map (nmap_rank)
     uint8_t *is_label;   // [n0] node of this round is somebody's parent (byte stores: many
                          // nodes name the same parent, which bit atomics would serialise)
     uint32_t *lmap;      // [2 ceil(n0 / 32)] the same as bits (nmap format): a label's
@@ -144,22 +145,19 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 // A round-0 id without a loop-free record has no parent and is nobody's parent (its rank).
 constexpr uint32_t kNoParent = 0xFFFFFFFFu;
 
-// Next-graph node map of a round.  Word pair i covers nodes 32 i .. 32 i + 31 of the round:
-// nmap[2 i] has a bit for each of them that keeps an edge, nmap[2 i + 1] counts the nodes
-// before 32 i that keep one.  A node's index in the next graph is then one 8-byte load and a
-// popcount away, and the map of N nodes takes N / 4 bytes, small enough to stay in cache
-// while the sorted edges sweep over it once per block of the key order.
+// Bit maps with prefix counts (the label map over a round's nodes, the next-graph node map
+// over its labels).  Word pair i covers entries 32 i .. 32 i + 31: map[2 i] has a bit for each
+// entry that is set, map[2 i + 1] counts the set entries before 32 i.  An entry's rank among
+// the set ones is then one 8-byte load and a popcount away, and the map of N entries takes
+// N / 4 bytes, small enough to stay in cache while sorted edges sweep over it.  The maps are
+// built by a scan over byte flags: many threads set the same entry, which plain byte stores
+// absorb and bit atomics would serialise.
 __device__ inline bool nmap_has(const uint32_t *nmap, uint64_t x) {
     return (nmap[2 * (x >> 5)] >> (x & 31)) & 1u;
 }
 __device__ inline uint32_t nmap_rank(const uint32_t *nmap, uint64_t x) {
     const uint2 e = *(const uint2 *)(nmap + 2 * (x >> 5));
     return e.y + (uint32_t)__popc(e.x & ((1u << (x & 31)) - 1u));
-}
-__device__ inline void nmap_mark(uint32_t *nmap, uint64_t x) {
-    uint32_t *p = nmap + 2 * (x >> 5);
-    const uint32_t bit = 1u << (x & 31);
-    if (!(*p & bit)) atomicOr(p, bit);   // bits are only ever set: a stale read costs an atomic
 }
 
 // Sort key of an edge lo < hi between indices of a round with b = ceil(log2 N) bits per

@@ -84,7 +84,6 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t
     }
     RoundKey key{};
     if (kSeeded) key = round_key(st->seed, st->round);
-    const int64_t nw = ceil_div(n, 32);
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         uint64_t v = ~0ull;
         if (kSeeded) {
@@ -93,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t
         }
         ((uint64_t *)w.ml)[i] = v;
         w.is_label[i] = 0;
-        if (i < nw) ((uint64_t *)w.nmap)[i] = 0ull;
+        w.has_edge[i] = 0;
     }
 }
 

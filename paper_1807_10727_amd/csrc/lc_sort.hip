@@ -338,52 +338,8 @@ void k_sort_scatter(Work w, int pass) {
 // next-graph node map: prefix counts over the bit words
 // ---------------------------------------------------------------------------------------
 
-// Thread t of a block takes the 16 consecutive words [16 t, 16 t + 16) of the block's kScanTile.
-__device__ inline void map_load16(const uint32_t *map, int64_t base, int64_t nw, uint32_t (&c)[16]) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) c[j] = base + j < nw ? (uint32_t)__popc(map[2 * (base + j)]) : 0u;
-}
-
-// map covers *n_ptr entries
-__global__ __launch_bounds__(kThreads) void k_map_reduce(const uint32_t *map, const u64c *n_ptr, uint32_t *partials) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t nw = ceil_div((int64_t)*n_ptr, 32);
-    const int64_t nblk = ceil_div(nw, kScanTile);
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        uint32_t c[16];
-        map_load16(map, blk * kScanTile + threadIdx.x * 16, nw, c);
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) sum += c[j];
-        uint32_t total;
-        block_excl_scan<kThreads>(sum, lds, &total);
-        if (threadIdx.x == 0) partials[blk] = total;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_map_down(uint32_t *map, const u64c *n_ptr, const uint32_t *partials) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t nw = ceil_div((int64_t)*n_ptr, 32);
-    const int64_t nblk = ceil_div(nw, kScanTile);
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        uint32_t c[16];
-        const int64_t my = blk * kScanTile + threadIdx.x * 16;
-        map_load16(map, my, nw, c);
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) sum += c[j];
-        uint32_t total;
-        uint32_t run = partials[blk] + block_excl_scan<kThreads>(sum, lds, &total);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (my + j < nw) map[2 * (my + j) + 1] = run;
-            run += c[j];
-        }
-    }
-}
-
-// Label map from the label bytes: thread t of a block turns the 32 bytes of word
-// blk * kThreads + t into bits; the block's counts are scanned like any other.
+// Bit map from byte flags (label map, node map): thread t of a block turns the 32 flags of
+// word blk * kThreads + t into bits; the blocks' counts are scanned like any other.
 __device__ inline uint32_t label_bits(const uint8_t *f, int64_t w, int64_t n) {
     const int64_t base = w * 32;
     uint32_t bits = 0;
@@ -401,7 +357,7 @@ __device__ inline uint32_t label_bits(const uint8_t *f, int64_t w, int64_t n) {
     return bits;
 }
 
-__global__ __launch_bounds__(kThreads) void k_label_reduce(const uint8_t *f, const u64c *n_ptr, uint32_t *partials) {
+__global__ __launch_bounds__(kThreads) void k_flags_reduce(const uint8_t *f, const u64c *n_ptr, uint32_t *partials) {
     __shared__ uint32_t lds[kThreads / kWave + 1];
     const int64_t n = (int64_t)*n_ptr;
     const int64_t nw = ceil_div(n, 32);
@@ -415,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_label_reduce(const uint8_t *f, con
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_label_down(const uint8_t *f, const u64c *n_ptr,
+__global__ __launch_bounds__(kThreads) void k_flags_down(const uint8_t *f, const u64c *n_ptr,
                                                          const uint32_t *partials, uint32_t *lmap) {
     __shared__ uint32_t lds[kThreads / kWave + 1];
     const int64_t n = (int64_t)*n_ptr;
@@ -461,8 +417,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
                 edge_key_split(k, kb, hbs, lo, hi);
                 if (idx > 0) edge_key_split(prev, kb, hbs, plo, phi);
                 if (lo < n_lab && hi < n_lab) {
-                    if (plo != lo) nmap_mark(w.nmap, lo);
-                    nmap_mark(w.nmap, hi);
+                    if (plo != lo) w.has_edge[lo] = 1;
+                    w.has_edge[hi] = 1;
                 } else {
                     broken = true;
                 }
@@ -581,26 +537,17 @@ hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, in
 }
 
 hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage) {
-    if (labels) {   // label bytes of this round's nodes -> label map
-        const u64c *n = &w.st->n_cur;
-        if (stage == 0)
-            hipLaunchKernelGGL(k_label_reduce, dim3(grid), dim3(kThreads), 0, s, w.is_label, n, w.partials);
-        else if (stage == 1)   // one partial per kThreads words of 32 nodes
-            hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kThreads,
-                               &w.st->n_labels);
-        else
-            hipLaunchKernelGGL(k_label_down, dim3(grid), dim3(kThreads), 0, s, w.is_label, n,
-                               (const uint32_t *)w.partials, w.lmap);
-        return hipGetLastError();
-    }
-    // node map over the labels
-    const u64c *n = &w.st->n_labels;
+    // label map: flags of this round's nodes; node map: flags of the labels
+    const uint8_t *f = labels ? w.is_label : w.has_edge;
+    uint32_t *map = labels ? w.lmap : w.nmap;
+    const u64c *n = labels ? &w.st->n_cur : &w.st->n_labels;
+    u64c *total = labels ? &w.st->n_labels : &w.st->n_next;
     if (stage == 0)
-        hipLaunchKernelGGL(k_map_reduce, dim3(grid), dim3(kThreads), 0, s, w.nmap, n, w.partials);
-    else if (stage == 1)   // one partial per kScanTile words of 32 entries
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kScanTile, &w.st->n_next);
+        hipLaunchKernelGGL(k_flags_reduce, dim3(grid), dim3(kThreads), 0, s, f, n, w.partials);
+    else if (stage == 1)   // one partial per kThreads words of 32 flags
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kThreads, total);
     else
-        hipLaunchKernelGGL(k_map_down, dim3(grid), dim3(kThreads), 0, s, w.nmap, n, (const uint32_t *)w.partials);
+        hipLaunchKernelGGL(k_flags_down, dim3(grid), dim3(kThreads), 0, s, f, n, (const uint32_t *)w.partials, map);
     return hipGetLastError();
 }
 

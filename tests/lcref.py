@@ -122,9 +122,30 @@ def graph_records(adj: np.ndarray):
     return src, dst, eoff
 
 
-def brute_all(adj: np.ndarray, prio_of_round, max_rounds: int = 16):
-    """Run LocalContraction on a stack of graphs given by adjacency bitmasks over names
-    0..n-1.  prio_of_round(r) -> priorities [n] (or [G, n]) of the names in phase r.
+def _argmin_over(mask, prio, n):
+    """Per (graph, node): the name of smallest priority among the bits of mask [G, n]."""
+    G = mask.shape[0]
+    best = np.full((G, n), np.iinfo(np.int64).max, np.int64)
+    arg = np.zeros((G, n), np.uint8)
+    for y in range(n):
+        has_y = ((mask >> np.uint8(y)) & np.uint8(1)).astype(bool)
+        better = has_y & (prio[:, y:y + 1] < best)
+        best = np.where(better, prio[:, y:y + 1], best)
+        arg = np.where(better, np.uint8(y), arg)
+    return arg
+
+
+def brute_all(adj: np.ndarray, prio_of_round, max_rounds: int = 16, variant: str = "local"):
+    """Run LocalContraction (or a variant) on a stack of graphs given by adjacency bitmasks
+    over names 0..n-1.  prio_of_round(r) -> priorities [n] (or [G, n]) of the names in phase r.
+
+    Labels of a phase, from the definitions (Section 3):
+      local    argmin of rho over N(N(x)) (closed two-hop reachability);
+      one_hop  argmin of rho over the closed N(x);
+      tree     f(x) = argmin of rho over N(x) minus x; walk x, f(x), f(f(x)), ... n steps,
+               which ends inside the terminal 2-cycle {y, f(y)} (Lemma "cycle"); the label is
+               the member of the cycle with the smaller priority (two nodes share a class iff
+               they share the cycle, Lemma "wccs").
 
     Returns (labels [G, n], rounds [G], parents [max_rounds, G, n] with 255 for names that
     are not nodes of that phase, stats [max_rounds, G, 5])."""
@@ -146,17 +167,23 @@ def brute_all(adj: np.ndarray, prio_of_round, max_rounds: int = 16):
         if prio.ndim == 1:
             prio = np.broadcast_to(prio, (G, n))
         n1 = adj | bit[None, :]                       # closed neighbourhood N(x)
-        n2 = n1.copy()                                # N(N(x))
-        for y in range(n):
-            has_y = ((n1 >> np.uint8(y)) & np.uint8(1)).astype(bool)
-            n2 |= np.where(has_y, n1[:, y:y + 1], np.uint8(0))
-        best = np.full((G, n), np.iinfo(np.int64).max, np.int64)
-        arg = np.zeros((G, n), np.uint8)
-        for y in range(n):
-            has_y = ((n2 >> np.uint8(y)) & np.uint8(1)).astype(bool)
-            better = has_y & (prio[:, y:y + 1] < best)
-            best = np.where(better, prio[:, y:y + 1], best)
-            arg = np.where(better, np.uint8(y), arg)
+        if variant == "local":
+            n2 = n1.copy()                            # N(N(x))
+            for y in range(n):
+                has_y = ((n1 >> np.uint8(y)) & np.uint8(1)).astype(bool)
+                n2 |= np.where(has_y, n1[:, y:y + 1], np.uint8(0))
+            arg = _argmin_over(n2, prio, n)
+        elif variant == "one_hop":
+            arg = _argmin_over(n1, prio, n)
+        else:
+            f = _argmin_over(adj, prio, n).astype(np.int64)     # open neighbourhood
+            y = np.tile(np.arange(n, dtype=np.int64), (G, 1))
+            for _ in range(n):
+                y = np.take_along_axis(f, y, axis=1)
+            fy = np.take_along_axis(f, y, axis=1)
+            py = np.take_along_axis(prio, y, axis=1)
+            pfy = np.take_along_axis(prio, fy, axis=1)
+            arg = np.where(py < pfy, y, fy).astype(np.uint8)
         par = np.where(in_v, arg, np.uint8(255))
         parents[r] = par
         # next graph: the parents of the two endpoints of each edge, loops dropped

@@ -311,3 +311,93 @@ def test_max_rounds_stops_early():
 def test_rejects_out_of_range_ids():
     with pytest.raises(ValueError):
         oracle.run(3, [0, 5], [1, 2])
+
+
+# ---------------------------------------------------------------------------------------
+# TreeContraction, the one-hop label, the union-find finish
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", ["tree", "one_hop"])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_variant_equals_bruteforce(variant, n):
+    """Labels, parents, rounds and statistics of every graph on up to 5 vertices (a sample
+    of 600 on 6) under two seeds equal the brute force from the definition: for
+    TreeContraction the walk to the terminal 2-cycle of v -> f(v), an independent route to
+    the weakly connected components that the oracle forms by union-find."""
+    adj = all_graph_adjacency(n)
+    pick = np.arange(adj.shape[0])
+    if n == 6:
+        pick = np.random.default_rng(n).choice(adj.shape[0], size=600, replace=False)
+    adj = adj[pick]
+    src, dst, eoff = graph_records(adj)
+    for seed in (1, 0xBEEF):
+        lab_b, rounds_b, par_b, stats_b = brute_all(adj, lambda r: spec_priority(seed, r, np.arange(n)),
+                                                    max_rounds=12, variant=variant)
+        for g in range(adj.shape[0]):
+            a, b = eoff[g], eoff[g + 1]
+            res = oracle.run(n, src[a:b], dst[a:b], seed=seed, variant=variant, record_parents=True)
+            assert res.rounds == rounds_b[g]
+            np.testing.assert_array_equal(res.labels, lab_b[g].astype(np.uint32))
+            for r in range(res.rounds):
+                want = np.where(par_b[r, g] == 255, np.uint32(oracle.NOT_A_NODE), par_b[r, g].astype(np.uint32))
+                np.testing.assert_array_equal(res.parents[r], want)
+                assert list(res.stats[r][1:]) == list(stats_b[r, g])
+
+
+@pytest.mark.parametrize("variant", ["tree", "one_hop"])
+@pytest.mark.parametrize("kind", ["gnm", "rmat", "paths"])
+def test_variant_partition(variant, kind):
+    if kind == "gnm":
+        g = graphgen.workload_small()
+    elif kind == "rmat":
+        g = graphgen.Graph(1 << 13, *graphgen.rmat(7, 13, 8 << 13))
+    else:
+        g = graphgen.er_with_paths(11, 1 << 11, 1 << 11, 30, 150)
+    res = oracle.run(g.n, g.src, g.dst, seed=42, variant=variant)
+    want = canon(scipy_components(g.n, g.src, g.dst))
+    np.testing.assert_array_equal(canon(res.labels), want)
+    np.testing.assert_array_equal(want[res.labels.astype(np.int64)], want)
+
+
+def test_tree_classes_are_connected_and_never_single():
+    """TreeContraction merges along edges v -> f(v): every class of a phase has at least two
+    nodes (each node points to a neighbour), induces a connected subgraph, and contains its
+    label; so a phase at least halves the nodes and the contracted graph is a minor."""
+    g = graphgen.er_with_paths(5, 1 << 11, 3 << 10, 20, 60)
+    res = oracle.run(g.n, g.src, g.dst, seed=8, variant="tree", record_parents=True)
+    lo, hi = simple_edges(g.src, g.dst)
+    assert res.rounds >= 2
+    for r in range(res.rounds):
+        par = res.parents[r].astype(np.int64)
+        nodes = np.nonzero(res.parents[r] != oracle.NOT_A_NODE)[0]
+        cls, size = np.unique(par[nodes], return_counts=True)
+        assert size.min() >= 2
+        assert np.all(par[cls] == cls)                       # the label is in its own class
+        assert cls.shape[0] * 2 <= nodes.shape[0]
+        # connected inside each class: edges between members of one class join them all
+        same = par[lo] == par[hi]
+        comp = scipy_components(g.n, lo[same], hi[same])
+        for c in cls[:200]:
+            members = nodes[par[nodes] == c]
+            assert np.unique(comp[members]).shape[0] == 1
+        lo, hi = simple_edges(par[lo], par[hi])
+
+
+@pytest.mark.parametrize("finish", [1, 50, 2000, 10 ** 9])
+def test_finish_is_smallest_remaining_name(finish):
+    """Union-find finish (Section 6): the phases before the switch are those of the plain run;
+    after it every vertex is labelled with the smallest name its component still has, i.e.
+    the minimum, over the component's vertices, of their labels after those phases."""
+    g = graphgen.er_with_paths(13, 1 << 11, 1 << 12, 10, 120)
+    plain = oracle.run(g.n, g.src, g.dst, seed=4)
+    res = oracle.run(g.n, g.src, g.dst, seed=4, finish_edges=finish)
+    k = res.rounds
+    assert res.stats == plain.stats[:k]
+    assert res.finished == (k < plain.rounds)
+    if res.finished:
+        assert plain.stats[k - 1][4] <= finish < min([plain.stats[j][4] for j in range(k - 1)], default=2 ** 62)
+    part = oracle.run(g.n, g.src, g.dst, seed=4, max_rounds=k)
+    comp = canon(scipy_components(g.n, g.src, g.dst))
+    want = np.full(g.n, np.iinfo(np.int64).max, np.int64)
+    np.minimum.at(want, comp, part.labels.astype(np.int64))
+    np.testing.assert_array_equal(res.labels.astype(np.int64), want[comp])
