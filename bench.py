@@ -8,8 +8,10 @@ with the edge list already resident in HBM.  Each step draws fresh priorities (s
 base + step index).  The value is input edges per second.
 
 Printed (stdout, one JSON line): the metric, the roofline of the dominant kernel family
-(algorithmic bytes per launch over its HIP-event launch time, against 8 TB/s), and the
-CPU oracle timed on a bounded sample of the same mix.  Diagnostics go to stderr.
+(algorithmic bytes per launch over its HIP-event launch time, against 8 TB/s), the CPU
+oracle timed on a bounded sample of the same mix, the same workload under TreeContraction,
+the one-hop label and the union-find finish, the batched and the serving legs.
+Diagnostics go to stderr.
 """
 import argparse
 import json
@@ -111,6 +113,53 @@ def job_alg_bytes(stats, n0):
         N = n0 if r == 0 else n_active
         b += 24 * m_in + 16 * s + 8 * m_out + 24 * N
     return b
+
+
+def bench_variants(args, lc, n0, m0, src, dst, layout, stream, base_seed):
+    """The same workload, seeds and residency under the other label rules and with the
+    union-find finish (cc_run as a user calls it, no per-kernel events).  Each variant's
+    CC_CANONICAL labels are compared with LocalContraction's (same partition)."""
+    import torch
+
+    dev = src.device
+    out = {}
+
+    def canonical(flags, finish):
+        with lc.Solver(n0, src, dst, seed=base_seed, flags=flags | lc.CC_CANONICAL, stream=stream, layout=layout,
+                       finish_edges=finish) as s:
+            s.run()
+            lab = s.labels()
+            torch.cuda.synchronize()
+            return lab
+
+    want = canonical(0, 0)
+    for name, flags, finish in (("tree", lc.CC_TREE, 0), ("one_hop", lc.CC_ONE_HOP, 0),
+                                ("uf_finish", 0, args.finish_edges)):
+        with lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout,
+                       finish_edges=finish) as s:
+            labels = torch.empty(n0, dtype=torch.int32, device=dev)
+            s.reset(base_seed + 999)
+            s.run()                                  # warm-up
+            torch.cuda.synchronize()
+            rounds, finished = [], []
+            t0 = time.perf_counter()
+            for i in range(args.variant_steps):
+                s.reset(base_seed + i)
+                rounds.append(s.run())
+                finished.append(s.finished)
+                s.labels(labels)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        same = bool(torch.equal(canonical(flags, finish), want))
+        ent = {"ms_per_step": dt * 1e3 / args.variant_steps, "value": m0 * args.variant_steps / dt,
+               "unit": "edges/s", "rounds": rounds, "canonical_labels_identical": same}
+        if finish:
+            ent["finish_edges"] = finish
+            ent["finished"] = finished
+        out[name] = ent
+        log("variant %s: %.2f ms/step, rounds %s, canonical labels identical: %s"
+            % (name, ent["ms_per_step"], rounds, same))
+    return out
 
 
 def cpu_baseline(shrink):
@@ -327,6 +376,10 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=int, default=128)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.2])
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip TreeContraction, the one-hop label and the union-find finish")
+    ap.add_argument("--variant-steps", type=int, default=5)
+    ap.add_argument("--finish-edges", type=int, default=1 << 22)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -493,7 +546,16 @@ def main():
         % (job_bytes / args.steps / 1e9, job_gbs, 100 * job_gbs / HBM_PEAK_GBS))
 
     solver.close()
-    del solver, src, dst, labels
+    del solver, labels
+    torch.cuda.empty_cache()
+    variants = None
+    if not args.no_variants:
+        try:
+            variants = bench_variants(args, lc, n0, m0, src, dst, layout, stream, base_seed)
+        except Exception as e:  # the main figure stands on its own
+            log("variants leg failed: %r" % (e,))
+            variants = {"error": repr(e)}
+    del src, dst
     torch.cuda.empty_cache()
     batched = None
     if not args.no_batch:
@@ -536,6 +598,7 @@ def main():
         "roofline": roofline,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
+        "variants": variants,
         "batched": batched,
         "serving": serving,
     }

@@ -94,8 +94,21 @@ enum {
     CC_PROFILE = 1u << 1,       /* time every kernel with HIP events (see cc_kernel_times) */
     CC_ROUND0_DIRECT = 1u << 2, /* round 0 reads the input records directly */
     CC_ROUND0_TILED = 1u << 3,  /* round 0 over the tiled record layout */
-    CC_EAGER = 1u << 4          /* cc_run enqueues every round on its own (no captured tail) */
+    CC_EAGER = 1u << 4,         /* cc_run enqueues every round on its own (no captured tail) */
+    CC_TREE = 1u << 5,          /* TreeContraction phases (see below) */
+    CC_ONE_HOP = 1u << 6        /* one-hop labels (see below) */
 };
+
+/* Label rule of a phase.  Default: LocalContraction (Section 3), the vertex of smallest
+ * priority within distance two (closed neighbourhoods).  CC_TREE: TreeContraction (Section 3):
+ * every node points to its neighbour of smallest priority other than itself, and the nodes of
+ * each weakly connected component of those pointers are merged, under the name of the
+ * component's node of smallest priority (the smaller of the two nodes the pointers end in);
+ * each phase at least halves the nodes and merged nodes are always connected.  CC_ONE_HOP: the
+ * vertex of smallest priority in the closed neighbourhood (the rule of Section 6's Cracker
+ * comparison, without its edge rewiring); more phases than LocalContraction.  Both run
+ * round 0 directly: together, or either with CC_ROUND0_TILED, cc_create returns CC_E_ARG.
+ * Priorities, statistics, naming and the labels' meaning are as for LocalContraction. */
 
 /* cc_run and captured tails.  On a context that has already finished a solve, once the
  * remaining graph has at most 2^22 records, cc_run replays a hipGraph of up to 8 rounds
@@ -109,7 +122,8 @@ enum {
 typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
     int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
-    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED | CC_EAGER */
+    uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED | CC_EAGER |
+                            CC_TREE | CC_ONE_HOP */
     void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
 } cc_options;
 
@@ -182,6 +196,20 @@ cc_status cc_labels(cc_ctx *ctx, void *d_labels);
  * other name.  *n_nodes (nullable, host) receives the node count.  Synchronises.
  */
 cc_status cc_round_parents(cc_ctx *ctx, int32_t *d_parents, int64_t *n_nodes);
+
+/*
+ * Union-find finish (Section 6): from round 1 on, once the graph left by a round has at most
+ * max_edges edges (0, the default, turns this off), cc_run ends the solve by finding the
+ * components of that graph with a union-find on the device instead of running more rounds.
+ * Every remaining node then becomes final under the smallest name in its component, so the
+ * raw labels differ from a solve without the finish (CC_CANONICAL labels do not).  The rounds
+ * before the switch are unchanged; cc_run's round count and the statistics cover only them,
+ * and cc_round_parents returns CC_E_STATE afterwards.  cc_contract_round never finishes.
+ * Applies from the next cc_run; CC_E_ARG for a null context or a negative count.
+ * cc_get_finished reports (1/0) whether the current solve ended this way.
+ */
+cc_status cc_set_finish(cc_ctx *ctx, int64_t max_edges);
+cc_status cc_get_finished(const cc_ctx *ctx, int32_t *finished);
 
 /* Statistics of round r of the current solve (host copy kept by the library). */
 cc_status cc_get_round_stats(const cc_ctx *ctx, int32_t r, cc_round_stats *out);

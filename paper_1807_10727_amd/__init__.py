@@ -17,13 +17,13 @@ from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_bat
 from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
-                  CC_EAGER, CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CCError, cc_contract_round, cc_create,
-                  cc_destroy, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
-                  cc_labels, cc_last_error, cc_reset, cc_round_parents, cc_run, cc_set_profile_mask,
+                  CC_EAGER, CC_ONE_HOP, CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CC_TREE, CCError,
+                  cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
+                  cc_labels, cc_last_error, cc_reset, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
 
-__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_PROFILE", "CC_ROUND0_DIRECT",
-           "CC_ROUND0_TILED", "cc_version"]
+__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_ONE_HOP", "CC_PROFILE",
+           "CC_ROUND0_DIRECT", "CC_ROUND0_TILED", "CC_TREE", "cc_version"]
 
 
 def _torch():
@@ -36,7 +36,7 @@ class Solver:
     until close(); the workspace is a torch uint8 tensor on the same device."""
 
     def __init__(self, n: int, src, dst=None, seed: int = 0, max_rounds: int = 0, flags: int = 0,
-                 stream=None, layout: int | None = None):
+                 stream=None, layout: int | None = None, finish_edges: int = 0):
         torch = _torch()
         if not src.is_cuda:
             raise ValueError("edge tensors must be device tensors")
@@ -64,6 +64,17 @@ class Solver:
         self.ws_bytes = cc_workspace_size(self.ctx)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         cc_set_workspace(self.ctx, self.ws.data_ptr(), self.ws_bytes)
+        if finish_edges:
+            cc_set_finish(self.ctx, finish_edges)
+
+    def set_finish(self, max_edges: int) -> None:
+        """Union-find finish once a round leaves at most max_edges edges (0: off)."""
+        cc_set_finish(self.ctx, max_edges)
+
+    @property
+    def finished(self) -> bool:
+        """Whether the current solve ended with the union-find finish."""
+        return cc_get_finished(self.ctx)
 
     @property
     def label_dtype(self):
@@ -129,9 +140,9 @@ class Solver:
             pass
 
 
-def solve(n: int, src, dst=None, seed: int = 0, flags: int = 0, max_rounds: int = 0):
+def solve(n: int, src, dst=None, seed: int = 0, flags: int = 0, max_rounds: int = 0, finish_edges: int = 0):
     """Full solve: returns (labels tensor, rounds, per-round stats)."""
-    with Solver(n, src, dst, seed=seed, flags=flags, max_rounds=max_rounds) as s:
+    with Solver(n, src, dst, seed=seed, flags=flags, max_rounds=max_rounds, finish_edges=finish_edges) as s:
         rounds = s.run()
         lab = s.labels()
         st = s.stats(rounds)

@@ -28,6 +28,8 @@ CC_PROFILE = 1 << 1
 CC_ROUND0_DIRECT = 1 << 2
 CC_ROUND0_TILED = 1 << 3
 CC_EAGER = 1 << 4
+CC_TREE = 1 << 5
+CC_ONE_HOP = 1 << 6
 
 
 class cc_graph_desc(ctypes.Structure):
@@ -95,6 +97,8 @@ _sig = {
     "cc_get_round_stats": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.POINTER(cc_round_stats)]),
     "cc_kernel_family_count": (ctypes.c_int32, []),
     "cc_set_profile_mask": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
+    "cc_set_finish": (ctypes.c_int32, [_ctx_p, ctypes.c_int64]),
+    "cc_get_finished": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32)]),
     "cc_kernel_family_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "cc_kernel_times": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.c_int32]),
@@ -198,6 +202,16 @@ def cc_get_round_stats(ctx, r: int, with_graph_flag: bool = False):
     s = cc_round_stats()
     _check(ctx, _lib.cc_get_round_stats(ctx, r, ctypes.byref(s)))
     return s.as_tuple() + ((s.in_graph,) if with_graph_flag else ())
+
+
+def cc_set_finish(ctx, max_edges: int) -> None:
+    _check(ctx, _lib.cc_set_finish(ctx, int(max_edges)))
+
+
+def cc_get_finished(ctx) -> bool:
+    f = ctypes.c_int32()
+    _check(ctx, _lib.cc_get_finished(ctx, ctypes.byref(f)))
+    return bool(f.value)
 
 
 def cc_get_round_sorted(ctx, r: int) -> int:

@@ -153,4 +153,20 @@ __device__ inline T block_excl_scan(T x, T *lds, T *total) {
     return res;
 }
 
+// Lanes of a wave reading sorted records hold runs of equal first endpoints.  Combine the
+// values of lanes with equal keys (a min over same-key lanes is a valid update for that key)
+// so that only the last lane of each run touches memory.
+__device__ inline uint32_t run_min(uint32_t key, uint32_t val, bool &last) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t ov = __shfl_up(val, d, kWave);
+        const uint32_t ok = __shfl_up(key, d, kWave);
+        if (lane >= d && ok == key) val = min(val, ov);
+    }
+    const uint32_t nk = __shfl_down(key, 1, kWave);
+    last = lane == kWave - 1 || nk != key;
+    return val;
+}
+
 }  // namespace lc

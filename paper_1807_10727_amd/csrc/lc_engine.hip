@@ -26,12 +26,12 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph"};
+    "relabel_tiled", "tail_graph", "uf_finish"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags) {
-    if (flags & CC_ROUND0_DIRECT) return false;
+    if (flags & (CC_ROUND0_DIRECT | CC_TREE | CC_ONE_HOP)) return false;
     if (!tiled_fits(n0)) return false;
     if (flags & CC_ROUND0_TILED) return true;
     return n0 >= kTiledMinVertices && m0 >= kTiledMinVertices;
@@ -166,7 +166,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
 
-    RUN(kRoundBegin, launch_round_begin(w, !first && !batch, r, gn, stream));
+    RUN(kRoundBegin, launch_round_begin(w, !first && !batch && variant != kVarTree, r, gn, stream));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
     if (first && tiled) {
         const int ga = (int)std::min<int64_t>(tp.tiles_a, grid_cap);
@@ -187,10 +187,15 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
         RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
         RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
+    } else if (variant == kVarTree) {
+        RUN(first ? kMin1In : kMin1, launch_min1_open(w, src, pc, r, gm, stream));
+        RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
+        RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     } else {
         RUN(first ? kMin1In : kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
-        RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
-        RUN(kParent, launch_parent(w, pc, batch, r, gn, stream));
+        if (variant != kVarOneHop) RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
+        RUN(kParent, launch_parent(w, pc, batch, r, gn, stream, variant == kVarOneHop));
         RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     }
@@ -285,6 +290,7 @@ cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     c->n_cur = c->g.n_vertices;
     c->m_cur = c->g.n_edges;
     c->last_graph_round = -1;
+    c->finished = false;
     c->failed_status = 0;
     c->err.clear();
     for (int i = 0; i < kFamilies; ++i) {
@@ -398,7 +404,8 @@ void drop_tails(cc_ctx *c) {
 // A capture costs far more than a few small rounds: a context captures only once it has
 // finished an earlier solve, i.e. when it is being reused.
 bool tail_wanted(const cc_ctx *c) {
-    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->solves_done > 0 && c->next_round >= 1 &&
+    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->finish_edges == 0 && c->solves_done > 0 &&
+           c->next_round >= 1 &&
            !c->done && c->m_cur > 0 && c->m_cur <= kTailMaxRecords;
 }
 
@@ -501,6 +508,34 @@ cc_status round_once(cc_ctx *c, cc_round_stats *out) {
     return ctx_round_complete(c, out);
 }
 
+bool finish_wanted(const cc_ctx *c) {
+    return c->finish_edges > 0 && c->next_round >= 1 && !c->done && c->m_cur > 0 && c->m_cur <= c->finish_edges;
+}
+
+// The union-find finish of the current graph (Section 6); ends the solve.
+cc_status run_finish(cc_ctx *c) {
+    if (c->failed_status) return c->failed_status;
+    const int r = c->next_round;
+    const int64_t N = c->n_cur, M = c->m_cur;
+    if (c->host_levels >= kMaxLevels || c->host_map_used + N > std::max<int64_t>(c->g.n_vertices, 1)) {
+        if (!c->flatten()) return hip_status(c);
+    }
+    const bool ev = c->ev_begin(kUfFinish);
+    const hipError_t e = launch_uf_finish(c->w, r, c->grid_for(N), c->grid_for(ceil_div(M, 2)), c->stream);
+    c->ev_end(ev);
+    if (!c->hip_ok(e, "union-find finish")) return hip_status(c);
+    if (!c->read_state()) return hip_status(c);
+    const RoundState &st = *c->h_st;
+    if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
+    c->host_levels += 1;
+    c->host_map_used += N;
+    c->n_cur = 0;
+    c->m_cur = 0;
+    c->done = true;
+    c->finished = true;
+    return CC_DONE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -516,6 +551,8 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if (opts->max_rounds < 0) return CC_E_ARG;
     if ((opts->flags & CC_ROUND0_DIRECT) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     if ((opts->flags & CC_ROUND0_TILED) && g.n_vertices > 0 && !tiled_fits(g.n_vertices)) return CC_E_ARG;
+    if ((opts->flags & CC_TREE) && (opts->flags & CC_ONE_HOP)) return CC_E_ARG;
+    if ((opts->flags & (CC_TREE | CC_ONE_HOP)) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     cc_ctx *c = new (std::nothrow) cc_ctx();
     if (!c) return CC_E_NOMEM;
     c->g = g;
@@ -544,6 +581,7 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
         }
     }
     c->tiled = choose_tiled(g.n_vertices, g.n_edges, opts->flags);
+    c->variant = (opts->flags & CC_TREE) ? kVarTree : (opts->flags & CC_ONE_HOP) ? kVarOneHop : kVarLocal;
     c->tp = tiled_plan(g.n_vertices, g.n_edges);
     c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, c->tiled, nullptr, nullptr);
     *out = c;
@@ -583,7 +621,7 @@ cc_status cc_run(cc_ctx *c, int32_t *rounds) {
     if (!c) return CC_E_ARG;
     for (;;) {
         if (c->o.max_rounds > 0 && c->next_round >= c->o.max_rounds) break;
-        cc_status s = tail_wanted(c) ? run_tail(c) : round_once(c, nullptr);
+        cc_status s = finish_wanted(c) ? run_finish(c) : tail_wanted(c) ? run_tail(c) : round_once(c, nullptr);
         if (s == CC_DONE) break;
         if (s != CC_OK) return s;
     }
@@ -608,6 +646,7 @@ cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {
     const int last = c->next_round - 1;
     if (last == c->last_graph_round)
         return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
+    if (c->finished) return reject(c, CC_E_STATE, "the solve ended with the union-find finish");
     hipError_t e = launch_dump_parents(c->w, d_parents, last, c->grid_for(c->g.n_vertices), c->stream);
     if (!c->hip_ok(e, "dump parents")) return CC_E_HIP;
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
@@ -624,6 +663,18 @@ cc_status cc_get_round_stats(const cc_ctx *c, int32_t r, cc_round_stats *out) {
 int32_t cc_kernel_family_count(void) { return kFamilies; }
 
 const char *cc_kernel_family_name(int32_t i) { return (i >= 0 && i < kFamilies) ? kFamilyNames[i] : nullptr; }
+
+cc_status cc_set_finish(cc_ctx *c, int64_t max_edges) {
+    if (!c || max_edges < 0) return CC_E_ARG;
+    c->finish_edges = max_edges;
+    return CC_OK;
+}
+
+cc_status cc_get_finished(const cc_ctx *c, int32_t *finished) {
+    if (!c || !finished) return CC_E_ARG;
+    *finished = c->finished ? 1 : 0;
+    return CC_OK;
+}
 
 cc_status cc_set_profile_mask(cc_ctx *c, uint64_t family_mask) {
     if (!c) return CC_E_ARG;

@@ -16,8 +16,11 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kFamilies
+    kTailGraph, kUfFinish, kFamilies
 };
+
+// how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)
+enum Variant { kVarLocal = 0, kVarTree = 1, kVarOneHop = 2 };
 extern const char *const kFamilyNames[kFamilies];
 
 // Lays the workspace out from `base` (or only sizes it when base is null).  `tiled`: round 0
@@ -33,6 +36,7 @@ struct Engine {
     EdgeIn in{};
     bool batch = false;
     bool tiled = false;           // round 0 over the tiled record layout
+    int variant = kVarLocal;
     TPlan tp{};
     bool profile = false;
     uint64_t prof_mask = ~0ull;   // families timed under CC_PROFILE (bit i: family i)
@@ -89,6 +93,8 @@ struct cc_ctx : public lc::Engine {
     int64_t pending_N = 0, pending_M = 0;   // bounds of the round in flight
     int32_t last_graph_round = -1;          // last round run inside a captured tail
     int64_t solves_done = 0;                // solves that cc_run finished on this context
+    int64_t finish_edges = 0;               // union-find finish threshold (0: off)
+    bool finished = false;                  // this solve ended with the union-find finish
     // captured tails of rounds (cc_run), replayed while the rounded-up sizes match
     struct Tail {
         hipGraphExec_t exec;

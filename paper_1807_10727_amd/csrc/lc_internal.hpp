@@ -46,6 +46,8 @@ struct RoundState {
                                   // repeats a workgroup recognised itself (atomics)
     alignas(128) u64c n_final;    // parents of this round that keep no edge (atomics)
     alignas(128) u64c n_labels;   // distinct parents of this round (atomics)
+    alignas(128) uint32_t jflag[3];   // TreeContraction: pointer-jumping passes that changed a pointer
+    uint32_t jdone;                   // TreeContraction: a pass found every pointer on its cycle
     alignas(128) uint32_t err;    // bit 0: input id out of range; bit 1: map arena overflow;
                                   // bit 2: internal consistency (atomics)
     alignas(128) u64c m_next;     // distinct edges of the next graph (one workgroup)
@@ -241,7 +243,15 @@ hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, h
 hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool batch, int round, int grid,
                        hipStream_t s);
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
-hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s);
+// one_hop: the parent is the argmin of the one-hop minimum (the one-hop label variant)
+hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s,
+                         bool one_hop = false);
+// TreeContraction (lc_variants.hip): open one-hop minimum; then f, pointer jumping over at most
+// ceil(log2 n_bound) + 2 passes, and the labels
+hipError_t launch_min1_open(const Work &w, const EdgeIn *in, const PrioCtx &p, int round, int grid, hipStream_t s);
+hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s);
+// union-find finish of the graph of round `round` (lc_variants.hip)
+hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
 // parents -> label ranks, the label of each rank, and the key width of the sort
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);

@@ -41,21 +41,6 @@ __device__ inline uint32_t node_prio(const PrioCtx &pc, const Work &w, const uin
 
 __device__ inline int ceil_log2(uint64_t n) { return n <= 1 ? 0 : 64 - __clzll((long long)(n - 1)); }
 
-// Lanes of a wave reading sorted records hold runs of equal first endpoints.  Combine the
-// values of lanes with equal keys (a min over same-key lanes is a valid update for that key)
-// so that only the last lane of each run touches memory.
-__device__ inline uint32_t run_min(uint32_t key, uint32_t val, bool &last) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t ov = __shfl_up(val, d, kWave);
-        const uint32_t ok = __shfl_up(key, d, kWave);
-        if (lane >= d && ok == key) val = min(val, ov);
-    }
-    const uint32_t nk = __shfl_down(key, 1, kWave);
-    last = lane == kWave - 1 || nk != key;
-    return val;
-}
 
 // ---------------------------------------------------------------------------------------
 
@@ -236,15 +221,16 @@ __global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
     }
 }
 
+// word 1: the two-hop minimum (LocalContraction); word 0: the one-hop minimum (one-hop label)
 template <bool kFirst, bool kBatch>
-__global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const uint32_t *gids) {
+__global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const uint32_t *gids, int word) {
     RoundState *st = w.st;
     if (!kBatch) pc.key = st->key;
     const int64_t n = (int64_t)st->n_cur;
     uint32_t active = 0;
     bool broken = false;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t l = w.ml[2 * i + 1];
+        const uint32_t l = w.ml[2 * i + word];
         if (l == kInf) {  // no loop-free record touches this id (round 0 only)
             w.par[i] = (uint32_t)i;
             continue;
@@ -637,14 +623,16 @@ hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s)
     }
 }
 
-hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s) {
+hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round, int grid, hipStream_t s,
+                         bool one_hop) {
     const uint32_t *gids = w.gids[round & 1];
+    const int word = one_hop ? 0 : 1;
     if (round == 0) {
-        if (batch) LC_LAUNCH((k_parent<true, true>), grid, w, p, gids);
-        LC_LAUNCH((k_parent<true, false>), grid, w, p, gids);
+        if (batch) LC_LAUNCH((k_parent<true, true>), grid, w, p, gids, word);
+        LC_LAUNCH((k_parent<true, false>), grid, w, p, gids, word);
     }
-    if (batch) LC_LAUNCH((k_parent<false, true>), grid, w, p, gids);
-    LC_LAUNCH((k_parent<false, false>), grid, w, p, gids);
+    if (batch) LC_LAUNCH((k_parent<false, true>), grid, w, p, gids, word);
+    LC_LAUNCH((k_parent<false, false>), grid, w, p, gids, word);
 }
 
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s) {

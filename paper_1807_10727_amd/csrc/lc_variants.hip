@@ -1,0 +1,294 @@
+// Other ways to choose a phase's labels, and the union-find finish.
+//
+// TreeContraction (Section 3, paragraph "TreeContraction"): every node v points to f(v), the
+// node of smallest priority among its neighbours other than v; the nodes of one weakly
+// connected component of the graph of f are merged.  Following f from any node ends in a
+// 2-cycle {y, f(y)} (Lemma "cycle"), two nodes share a component exactly when they end in
+// the same cycle (Lemma "wccs"), and the component's node of smallest priority lies on
+// that cycle, so the merged node is named by the cycle's member of smaller priority.  The
+// cycle is reached by pointer jumping (proof of the TreeContraction round theorem): every
+// node keeps a pointer that starts at f(v) and is replaced by its target's pointer until it
+// lands on a cycle, which at least doubles the distance covered per pass.
+//
+// The one-hop label (the rule Section 6 gives for its Cracker comparison, without the edge
+// rewiring) reuses the LocalContraction kernels: the parent is read from the one-hop minimum.
+//
+// Union-find finish (Section 6): once a round leaves a small graph, its components are found
+// by a lock-free union-find over its edges (roots are linked larger index under smaller, so a
+// component's root is its smallest index, which is also its smallest name) and every node
+// becomes final under its root's name, as one more per-round map.
+
+#include "lc_internal.hpp"
+#include "lc_readers.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------------------
+// TreeContraction
+// ---------------------------------------------------------------------------------------
+
+template <bool kFirst>
+__device__ inline uint32_t tree_prio(const PrioCtx &pc, const uint32_t *names, uint32_t i) {
+    return prio(pc.key, kFirst ? i : names[i]);
+}
+
+// Open one-hop minimum: each loop-free record sends rho(b) to a and rho(a) to b (no self
+// term), into the low half of the node word, which round_begin filled with +inf.
+template <class R, bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_min1_open(R rd, Work w, PrioCtx pc, const uint32_t *names) {
+    constexpr int V = R::kV;
+    rd.init(w.st);
+    pc.key = w.st->key;
+    const int64_t nch = rd.chunks();
+    uint32_t *m1 = w.ml;
+    bool bad = false;
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
+        uint32_t a[V], b[V];
+        if (c < nch) {
+            rd.read(c, a, b, bad);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const bool ok = a[j] != b[j];
+            const uint32_t pa = ok ? tree_prio<kFirst>(pc, names, a[j]) : kInf;
+            const uint32_t pb = ok ? tree_prio<kFirst>(pc, names, b[j]) : kInf;
+            bool la = true;
+            const uint32_t va = R::kSorted ? run_min(ok ? a[j] : 0xFFFFFFFFu, pb, la) : pb;
+            if (ok) {
+                if (la && m1[2 * (size_t)a[j]] > va) atomicMin(&m1[2 * (size_t)a[j]], va);
+                if (m1[2 * (size_t)b[j]] > pa) atomicMin(&m1[2 * (size_t)b[j]], pa);
+            }
+        }
+    }
+    if (bad) atomicOr(&w.st->err, 1u);
+}
+
+// f(v) into the high half of the node word and as the starting jump pointer (par); a node
+// without a loop-free record (round 0 only) points to itself.  Resets the jump flags.
+template <bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
+    RoundState *st = w.st;
+    pc.key = st->key;
+    const int64_t n = (int64_t)st->n_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->jflag[0] = 0u;
+        st->jdone = 0u;
+    }
+    uint32_t active = 0;
+    bool broken = false;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t m = w.ml[2 * i];
+        uint32_t p = (uint32_t)i;
+        if (m != kInf) {
+            const uint32_t name = prio_inv(pc.key, m);
+            p = kFirst ? name : ((int64_t)name < w.n0 ? w.idx_of[name] : 0xFFFFFFFFu);
+            if ((int64_t)p >= n) {   // cannot happen for a consistent state
+                broken = true;
+                p = (uint32_t)i;
+            }
+            ++active;
+        }
+        w.ml[2 * i + 1] = p;
+        w.par[i] = p;
+    }
+    __shared__ uint32_t red[kThreads / kWave];
+    active = block_sum<kThreads>(active, red);
+    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+// One pointer-jumping pass: a pointer not yet on a 2-cycle takes its target's pointer.
+// Pass `it` reads whether pass it-1 changed anything (flag slot (it + 2) % 3), records its
+// own changes in slot it % 3 and clears slot (it + 1) % 3 for the next pass; once a pass
+// changes nothing, the next one sets jdone and every later pass returns at once.  Passes
+// never read a slot that the same pass writes, so every workgroup decides alike.
+__global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
+    RoundState *st = w.st;
+    if (st->jdone) return;
+    if (it > 0 && st->jflag[(it + 2) % 3] == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->jdone = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->jflag[(it + 1) % 3] = 0u;
+    const int64_t n = (int64_t)st->n_cur;
+    const uint32_t *ml = w.ml;
+    bool changed = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t j = w.par[x];
+        const uint32_t fj = ml[2 * (size_t)j + 1];
+        if (ml[2 * (size_t)fj + 1] != j) {
+            w.par[x] = w.par[j];
+            changed = true;
+        }
+    }
+    if (__any(changed) && lane_id() == 0) st->jflag[it % 3] = 1u;
+}
+
+// The label of each node: the member of smaller priority of the 2-cycle its pointer reached.
+template <bool kFirst>
+__global__ __launch_bounds__(kThreads) void k_tree_label(Work w, PrioCtx pc, const uint32_t *names) {
+    RoundState *st = w.st;
+    pc.key = st->key;
+    const int64_t n = (int64_t)st->n_cur;
+    const uint32_t *ml = w.ml;
+    bool broken = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        if (ml[2 * x + 1] == (uint32_t)x) {   // no neighbour: its own parent, nobody's label
+            w.par[x] = (uint32_t)x;
+            continue;
+        }
+        const uint32_t j = w.par[x];
+        const uint32_t fj = ml[2 * (size_t)j + 1];
+        if (ml[2 * (size_t)fj + 1] != j) broken = true;   // pointer jumping did not converge
+        const uint32_t lab = tree_prio<kFirst>(pc, names, j) < tree_prio<kFirst>(pc, names, fj) ? j : fj;
+        w.par[x] = lab;
+        w.is_label[lab] = 1;
+    }
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+hipError_t launch_min1_open(const Work &w, const EdgeIn *in, const PrioCtx &p, int round, int grid, hipStream_t s) {
+    const uint32_t *names = w.names[round & 1];
+    if (!in) {
+        hipLaunchKernelGGL((k_min1_open<ReadInternal, false>), dim3(grid), dim3(kThreads), 0, s, ReadInternal(w), w,
+                           p, names);
+        return hipGetLastError();
+    }
+    const EdgeIn &e = *in;
+    switch (e.layout) {
+        case kSoa32:
+            hipLaunchKernelGGL((k_min1_open<ReadSoa32<1>, true>), dim3(grid), dim3(kThreads), 0, s, ReadSoa32<1>(e),
+                               w, p, names);
+            break;
+        case kSoa64:
+            hipLaunchKernelGGL((k_min1_open<ReadSoa64<1>, true>), dim3(grid), dim3(kThreads), 0, s, ReadSoa64<1>(e),
+                               w, p, names);
+            break;
+        default:
+            hipLaunchKernelGGL((k_min1_open<ReadPacked<1>, true>), dim3(grid), dim3(kThreads), 0, s,
+                               ReadPacked<1>(e), w, p, names);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s) {
+    const uint32_t *names = w.names[round & 1];
+    if (round == 0)
+        hipLaunchKernelGGL(k_tree_f<true>, dim3(grid), dim3(kThreads), 0, s, w, p);
+    else
+        hipLaunchKernelGGL(k_tree_f<false>, dim3(grid), dim3(kThreads), 0, s, w, p);
+    hipError_t e = hipGetLastError();
+    // a pass at least doubles how far every unfinished pointer has moved along f, so
+    // ceil(log2 N) + 1 passes reach every cycle; one more observes that nothing changed
+    const int passes = ceil_log2_i64(n_bound < 2 ? 2 : n_bound) + 2;
+    for (int it = 0; it < passes && e == hipSuccess; ++it) {
+        hipLaunchKernelGGL(k_tree_jump, dim3(grid), dim3(kThreads), 0, s, w, it);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    if (round == 0)
+        hipLaunchKernelGGL(k_tree_label<true>, dim3(grid), dim3(kThreads), 0, s, w, p, names);
+    else
+        hipLaunchKernelGGL(k_tree_label<false>, dim3(grid), dim3(kThreads), 0, s, w, p, names);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// union-find finish
+// ---------------------------------------------------------------------------------------
+
+// Every pointer goes to a smaller index (links put the larger root under the smaller, and
+// halving only shortens paths), so a find always ends.
+__device__ inline uint32_t uf_find(uint32_t *up, uint32_t x) {
+    for (;;) {
+        const uint32_t p = up[x];
+        if (p == x) return x;
+        const uint32_t g = up[p];
+        if (g != p) up[x] = g;   // path halving: any ancestor is a valid pointer
+        x = g;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_uf_init(Work w) {
+    const int64_t n = (int64_t)w.st->n_cur;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        w.par[i] = (uint32_t)i;
+}
+
+// One union per edge.  A failed link means the other root was linked meanwhile: retry from
+// the roots of both ends (the number of links is bounded by the number of nodes).
+__global__ __launch_bounds__(kThreads) void k_uf_hook(ReadInternal rd, Work w) {
+    constexpr int V = ReadInternal::kV;
+    rd.init(w.st);
+    const int64_t nch = rd.chunks();
+    bool bad = false;
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
+        uint32_t a[V], b[V];
+        rd.read(c, a, b, bad);
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            uint32_t x = a[j], y = b[j];
+            while (x != y) {
+                x = uf_find(w.par, x);
+                y = uf_find(w.par, y);
+                if (x == y) break;
+                if (x > y) {
+                    const uint32_t t = x;
+                    x = y;
+                    y = t;
+                }
+                const uint32_t old = atomicCAS(&w.par[y], y, x);
+                if (old == y) break;
+                y = old;
+            }
+        }
+    }
+}
+
+// The finishing map: every node of the remaining graph is final under the name of its
+// component's root; appended to the per-round maps like a round's map.
+__global__ __launch_bounds__(kThreads) void k_uf_map(Work w, const uint32_t *names_cur) {
+    RoundState *st = w.st;
+    const int64_t n = (int64_t)st->n_cur;
+    if (n == 0) return;
+    if (st->map_off + (u64c)n > st->map_cap || st->levels >= kMaxLevels) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 2u);
+        return;
+    }
+    uint32_t *out = w.maps + st->map_off;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        out[i] = kFinal | names_cur[uf_find(w.par, (uint32_t)i)];
+}
+
+__global__ void k_uf_end(Work w) {
+    RoundState *st = w.st;
+    if (st->n_cur > 0 && !(st->err & 2u)) {
+        st->level_off[st->levels] = st->map_off;
+        st->levels += 1;
+        st->map_off += st->n_cur;
+    }
+    st->n_prev = st->n_cur;
+    st->n_cur = 0;
+    st->m_cur = 0;
+    st->done = 1;
+}
+
+hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s) {
+    hipLaunchKernelGGL(k_uf_init, dim3(grid_nodes), dim3(kThreads), 0, s, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_uf_hook, dim3(grid_edges), dim3(kThreads), 0, s, ReadInternal(w), w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_uf_map, dim3(grid_nodes), dim3(kThreads), 0, s, w, (const uint32_t *)w.names[round & 1]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_uf_end, dim3(1), dim3(1), 0, s, w);
+    return hipGetLastError();
+}
+
+}  // namespace lc

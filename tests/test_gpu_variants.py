@@ -1,0 +1,152 @@
+"""Parity of the other label rules and of the union-find finish (HIP path through the C ABI)
+with the CPU oracle.
+
+TreeContraction (CC_TREE) and the one-hop label (CC_ONE_HOP): per-round parents by name,
+per-round statistics, round counts and labels bit for bit.  The union-find finish
+(cc_set_finish): the rounds before the switch and the labels after it (every remaining
+component named by its smallest name) bit for bit.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1807_10727_amd as lc
+    return lc
+
+
+def dev(g):
+    return (torch.from_numpy(g.src.view(np.int32)).to(DEV), torch.from_numpy(g.dst.view(np.int32)).to(DEV))
+
+
+def dup_path(nv, reps, seed):
+    a = np.repeat(np.arange(nv - 1, dtype=np.uint32), reps)
+    perm = np.random.default_rng(seed).permutation(a.size)
+    return graphgen.Graph(nv, a[perm].copy(), (a[perm] + 1).astype(np.uint32))
+
+
+GRAPHS = {
+    "gnm_small": lambda: graphgen.Graph(1000, *graphgen.gnm(11, 1000, 4097)),
+    "gnm_mid": lambda: graphgen.Graph(20000, *graphgen.gnm(12, 20000, 61441)),
+    "sparse": lambda: graphgen.Graph(30000, *graphgen.gnm(13, 30000, 12000)),
+    "rmat": lambda: graphgen.Graph(1 << 14, *graphgen.rmat(14, 14, 8 << 14)),
+    "paths": lambda: graphgen.er_with_paths(15, 1 << 11, 1 << 12, 30, 300),
+    "dup_path": lambda: dup_path(300, 500, 16),
+    "workload_small": graphgen.workload_small,
+}
+
+VARIANT_FLAGS = {"tree": 1 << 5, "one_hop": 1 << 6}
+
+
+def per_round(lc, g, seed, flags):
+    s_t, d_t = dev(g)
+    out = {"parents": [], "stats": []}
+    with lc.Solver(g.n, s_t, d_t, seed=seed, flags=flags) as s:
+        while True:
+            st, stats = s.contract_round()
+            if st == lc.CC_DONE:
+                break
+            out["stats"].append(tuple(stats))
+            par, k = s.parents()
+            out["parents"].append(par.cpu().numpy().view(np.uint32).copy())
+            assert k == stats[1]
+        out["rounds"] = s.run()
+        out["labels"] = s.labels().cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANT_FLAGS))
+@pytest.mark.parametrize("name", sorted(GRAPHS))
+def test_variant_parity(lc, variant, name):
+    g = GRAPHS[name]()
+    seed = 0xA11CE + len(name)
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant, record_parents=True)
+    got = per_round(lc, g, seed, VARIANT_FLAGS[variant])
+    assert got["rounds"] == want.rounds
+    assert got["stats"] == [tuple(x) for x in want.stats]
+    for r in range(want.rounds):
+        np.testing.assert_array_equal(got["parents"][r], want.parents[r], err_msg="round %d" % r)
+    np.testing.assert_array_equal(got["labels"].astype(np.uint32), want.labels)
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANT_FLAGS))
+def test_variant_cc_run_and_reuse(lc, variant):
+    """cc_run (captured tails on a reused context) equals the oracle for several seeds."""
+    g = graphgen.er_with_paths(17, 1 << 11, 1 << 12, 30, 700)
+    s_t, d_t = dev(g)
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=VARIANT_FLAGS[variant]) as s:
+        for seed in (3, 4, 3):
+            s.reset(seed)
+            r = s.run()
+            want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant)
+            assert r == want.rounds
+            assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+            np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want.labels)
+
+
+def test_tree_halves_the_nodes(lc):
+    """Every TreeContraction class has at least two nodes: each round at least halves them."""
+    g = graphgen.workload_small()
+    _, rounds, st = lc.solve(g.n, *dev(g), seed=9, flags=VARIANT_FLAGS["tree"])
+    for r in range(1, rounds):
+        assert 2 * st[r][1] <= st[r - 1][1]
+
+
+def test_variant_flags_rejected_with_tiled(lc):
+    g = GRAPHS["gnm_small"]()
+    s_t, d_t = dev(g)
+    for flags in (VARIANT_FLAGS["tree"] | VARIANT_FLAGS["one_hop"], VARIANT_FLAGS["tree"] | lc.CC_ROUND0_TILED,
+                  VARIANT_FLAGS["one_hop"] | lc.CC_ROUND0_TILED):
+        with pytest.raises(lc.CCError) as e:
+            lc.Solver(g.n, s_t, d_t, flags=flags)
+        assert e.value.status == -1
+
+
+@pytest.mark.parametrize("variant", ["local", "tree"])
+@pytest.mark.parametrize("name,finish", [("paths", 3000), ("paths", 1), ("workload_small", 50000),
+                                         ("rmat", 10 ** 9), ("dup_path", 100)])
+def test_finish_parity(lc, name, finish, variant):
+    g = GRAPHS[name]()
+    seed = 77
+    flags = VARIANT_FLAGS.get(variant, 0)
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant, finish_edges=finish)
+    s_t, d_t = dev(g)
+    with lc.Solver(g.n, s_t, d_t, seed=seed, flags=flags | lc.CC_EAGER, finish_edges=finish) as s:
+        r = s.run()
+        assert r == want.rounds
+        assert s.finished == want.finished
+        assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want.labels)
+        if want.finished:
+            with pytest.raises(lc.CCError) as e:
+                s.parents()
+            assert e.value.status == -5
+        # the same context without the finish: the plain labels again
+        s.set_finish(0)
+        s.reset(seed)
+        r2 = s.run()
+        plain = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant)
+        assert r2 == plain.rounds and not s.finished
+        np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), plain.labels)
+
+
+def test_finish_canonical_labels_unchanged(lc):
+    """With CC_CANONICAL the finish changes nothing: the smallest id of every component."""
+    g = graphgen.er_with_paths(19, 1 << 12, 1 << 13, 40, 500)
+    s_t, d_t = dev(g)
+    want = oracle.components_min_id(g.n, g.src, g.dst)
+    for finish in (0, 1, 5000):
+        with lc.Solver(g.n, s_t, d_t, seed=5, flags=lc.CC_CANONICAL, finish_edges=finish) as s:
+            s.run()
+            np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want)
