@@ -153,6 +153,15 @@ __device__ inline T block_excl_scan(T x, T *lds, T *total) {
     return res;
 }
 
+// Workgroup b of a launch runs on XCD b % 8 (MI355X: 8 XCDs, each with its own L2).  Tile
+// loops number their workgroups so that consecutive logical ids share an XCD: neighbouring
+// tiles then read and write the same lines of per-tile tables (digit counts, offsets) from
+// one L2 instead of eight.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_rank(int64_t b, int64_t g) {
+    return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
+}
+
 // Lanes of a wave reading sorted records hold runs of equal first endpoints.  Combine the
 // values of lanes with equal keys (a min over same-key lanes is a valid update for that key)
 // so that only the last lane of each run touches memory.

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)nbins * (u64c)tl.ntiles;
     const uint64_t *in = w.keys[sort_src(st->round, st->e_sel) ^ (pass & 1)];
     __shared__ uint32_t hist[kRadixMax];
-    for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < tl.ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
         for (int i = threadIdx.x; i < nbins; i += kSortThreads) hist[i] = 0;
         // every load of the tile in flight at once: pairs of keys, 16-byte aligned
@@ -243,7 +243,7 @@ void k_sort_scatter(Work w, int pass) {
     // thread t owns digits [t * per, (t + 1) * per) of this pass
     const int per = nbins > kSortThreads ? nbins / kSortThreads : 1;
 
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
         // this tile's global digit offsets: loaded now, used after the ranking
         uint32_t my_gofs[kPer];
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     const int hbs = st->hb_shift;
     const uint64_t n_lab = st->n_labels;   // key endpoints are label ranks
     bool broken = false;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         uint32_t cnt = 0;
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {   // consecutive lanes take consecutive keys
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     const uint64_t n_lab = st->n_labels;   // key endpoints are label ranks
     const int wave = threadIdx.x / kWave;
     const uint64_t lt = lanemask_lt();
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         uint64_t k[kSortItems];
         bool h[kSortItems];
 #pragma unroll

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_part_a_hist(R rd, Work w, TPlan tp
     const int ys = tp.ys;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)256 * (u64c)nt;
     bool bad = false;
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
         hist[threadIdx.x] = 0;
         __syncthreads();
 #pragma unroll
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_part_a_scatter(R rd, Work w, TPlan
     const int ys = tp.ys;
     uint64_t *out = w.keys[0];
     bool bad = false;
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
         cnt[threadIdx.x] = 0;
         __syncthreads();
         uint64_t k[kItems];
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_hist(Work w, TPlan tp) {
         w.slab_cnt[i] = 0;
     const uint64_t *in = w.keys[0];
     const int xs = tp.xs;
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
         for (int i = threadIdx.x; i < tp.rows; i += kTbThreads) hist[i] = 0;
         __syncthreads();
 #pragma unroll
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp)
     uint64_t *out = w.keys[1];
     const int xs = tp.xs;
     const int rows = tp.rows;
-    for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
         for (int i = threadIdx.x; i < rows; i += kTbThreads) dstart[i] = 0;
         __syncthreads();
         uint64_t k[2 * kPairs];
