@@ -26,7 +26,7 @@ struct RoundState {
     u64c aux_n;        // element count handed from one kernel to the next (scans)
     u64c map_off;      // next free entry of the map arena
     u64c map_cap;      // entries of the map arena
-    u64c n_slabs;      // relabel output slabs of this round
+    u64c n_slabs;      // relabel output slabs of this round (slab layout)
     int32_t round;     // r
     int32_t nbits;     // key bits of this round's sort: 2 * ceil(log2 N_r)
     int32_t e_sel;     // key buffer that holds E_r (rounds >= 1)
@@ -34,7 +34,7 @@ struct RoundState {
     int32_t levels;    // per-round maps in the arena
     int32_t kb;        // bits per endpoint in this round's sort keys: ceil(log2 N_r)
     int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (kb: one block)
-    int32_t pad0_;
+    int32_t keys_dense;  // the relabel wrote its keys packed at [0, s_keys) (else: in slabs)
     u64c t_count;      // round 0, tiled layout: directed records (twice the loop-free inputs)
     uint64_t seed;     // priority seed of a plain solve
     RoundKey key;      // this round's priority key, round_key(seed, round) (plain solve)

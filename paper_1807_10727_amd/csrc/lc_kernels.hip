@@ -286,8 +286,9 @@ __device__ inline bool set_insert(unsigned long long *set, uint64_t key) {
 // Relabel every record through the parents and keep the loop-free ones as sort keys
 // (edge_key of (min, max) of the two parents).  Each workgroup owns a slab of kSlab
 // consecutive records and writes its survivors, in order, to the start of the same slab of
-// the output: no global counter is involved.  slab_cnt holds the keys per slab; the first
-// radix pass reads the slabs.
+// the output: no global counter is involved (one shared cursor, taken per chunk, measured
+// slower: the first chunks of every workgroup all write and contend on it).  slab_cnt holds
+// the keys per slab; the first radix pass reads the slabs.
 //
 // On sorted records (rounds >= 1) a workgroup also drops every key it has written before:
 // a dense region that contracts onto a few parents maps many records onto the same parent
@@ -308,7 +309,10 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     rd.init(st);
     const int64_t nch = rd.chunks();
     const int64_t nslabs = ceil_div(rd.records(), kSlab);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->n_slabs = (u64c)nslabs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->n_slabs = (u64c)nslabs;
+        st->keys_dense = 0;
+    }
     uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
     const int kb = st->kb;
     const int hbs = st->hb_shift;

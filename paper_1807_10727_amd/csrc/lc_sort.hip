@@ -125,10 +125,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T *in, uint32_t *o
 // radix sort passes
 // ---------------------------------------------------------------------------------------
 
-// Tiles of one pass.  Pass 0 reads the relabel output in place: tile t is the (t % 2)-th
-// half of slab t / 2, filled from its start with that slab's survivors.  Later passes read
-// a compact array of S keys.  In both cases the keys of tile t are the first valid(t)
-// positions of [t * kSortTile, (t + 1) * kSortTile).
+// Tiles of one pass.  Pass 0 reads the relabel output in place: either packed (the tiled
+// round 0), or in slabs, where tile t is the (t % 2)-th half of slab t / 2,
+// filled from its start with that slab's survivors.  Later passes read a compact array of S
+// keys.  In every case the keys of tile t are the first valid(t) positions of
+// [t * kSortTile, (t + 1) * kSortTile).
 struct Tiles {
     int64_t ntiles;
     int64_t S;
@@ -145,7 +146,7 @@ __device__ inline Tiles tiles_of(const Work &w, int pass) {
     const RoundState *st = w.st;
     Tiles t;
     t.S = (int64_t)st->s_keys;
-    t.slab = pass == 0;
+    t.slab = pass == 0 && !st->keys_dense;
     t.slab_cnt = w.slab_cnt;
     t.ntiles = t.slab ? (int64_t)st->n_slabs * (kSlab / kSortTile) : ceil_div(t.S, kSortTile);
     return t;

@@ -172,9 +172,6 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_hist(Work w, TPlan tp) {
         st->aux_n = (u64c)tp.rows * (u64c)nt;
         st->n_slabs = (u64c)nslabs;
     }
-    // the tiled relabel reserves space in its output slabs with atomics: clear them here
-    for (int64_t i = (int64_t)blockIdx.x * kTbThreads + threadIdx.x; i < nslabs; i += (int64_t)gridDim.x * kTbThreads)
-        w.slab_cnt[i] = 0;
     const uint64_t *in = w.keys[0];
     const int xs = tp.xs;
     for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
@@ -366,17 +363,18 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
 // (x < y) differs from the parity of x + y, which takes exactly one of (x, y) and (y, x) and
 // about half of every row's records, so all rows advance through the columns at the same
 // pace.  The row's parents are staged in LDS; the parents at y are gathered from the column
-// block that the concurrent rows share in L2.  The row is walked in chunks aligned to the output slabs
-// of kSlab records; a row reserves its survivors' space in a slab with one atomic, so the
-// slab (shared by at most the two rows that meet inside it) is filled from its start.
+// block that the concurrent rows share in L2.  The row is walked in chunks of kChunk
+// records; each chunk reserves its survivors' space at the end of the packed key array with
+// one atomic, so the first radix pass reads full tiles (only about half of the directed
+// records are taken, which would leave slabs aligned to the records half empty).
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp) {
     constexpr int kPairs = LC_TRELABEL_PAIRS;   // record pairs per thread and chunk
     constexpr int kChunk = 2 * kPairs * kTRowThreads;
-    static_assert(kSlab % kChunk == 0, "a chunk lies inside one slab");
     RoundState *st = w.st;
     __shared__ uint32_t lpar[1 << kTxShiftMax];
     __shared__ uint32_t lds[kTRowThreads / kWave + 1];
-    __shared__ uint32_t sbase;
+    __shared__ u64c sbase;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->keys_dense = 1;
     const int64_t T = (int64_t)st->t_count;
     const int64_t nt = tiles_b_of(st);
     const int64_t n = (int64_t)st->n_cur;
@@ -432,10 +430,9 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
             uint32_t total;
             const uint32_t off = block_excl_scan<kTRowThreads>(c, lds, &total);
             if (total == 0) continue;
-            const int64_t slab = cb / kSlab;
-            if (threadIdx.x == 0) sbase = atomicAdd(&w.slab_cnt[slab], total);
+            if (threadIdx.x == 0) sbase = atomicAdd(&st->s_keys, (u64c)total);
             __syncthreads();
-            uint64_t *dst = out + slab * kSlab + sbase + off;
+            uint64_t *dst = out + sbase + off;
 #pragma unroll
             for (int q = 0; q < 2 * kPairs; ++q) {
                 if (v[q]) *dst++ = key[q];
@@ -444,10 +441,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
         }
         __syncthreads();   // lpar is rewritten for the next row
     }
-    if (threadIdx.x == 0 && kept) {
-        atomicAdd(&st->s_count, (u64c)kept);
-        atomicAdd(&st->s_keys, (u64c)kept);
-    }
+    if (threadIdx.x == 0 && kept) atomicAdd(&st->s_count, (u64c)kept);
     if (broken) atomicOr(&st->err, 4u);
 }
 
