@@ -219,7 +219,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
 }
 
 bool Engine::flatten() {
-    RUN(kFlatten, launch_flatten(w, grid_for(w.n0), stream));
+    RUN(kFlatten, launch_flatten(w, host_levels, grid_for(w.n0), stream));
     host_levels = 0;
     host_map_used = 0;
     return true;
@@ -366,6 +366,8 @@ cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out) {
 
 cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels) {
     if (c->g.n_vertices == 0) return CC_OK;
+    // with several levels, fold them first: compose then takes one lookup per vertex
+    if (c->host_levels >= 2 && !c->flatten()) return hip_status(c);
     const bool out64 = c->g.layout == CC_EDGES_SOA_I64;
     const int grid = c->grid_for(c->g.n_vertices);
     const bool ev = c->ev_begin(kCompose);

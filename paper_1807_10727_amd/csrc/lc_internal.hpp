@@ -269,7 +269,8 @@ hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
 hipError_t launch_round_end(const Work &w, int round, hipStream_t s);
 hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,
                           const uint32_t *voff, int grid, hipStream_t s);
-hipError_t launch_flatten(const Work &w, int grid, hipStream_t s);
+// fold the host-known `levels` per-round maps into map0 and empty the arena
+hipError_t launch_flatten(const Work &w, int levels, int grid, hipStream_t s);
 hipError_t launch_canonical(const Work &w, void *labels, bool out64, bool batch, const uint32_t *voff, int grid,
                             hipStream_t s);
 hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int grid, hipStream_t s);

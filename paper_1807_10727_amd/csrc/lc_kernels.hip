@@ -502,13 +502,34 @@ __global__ __launch_bounds__(kThreads) void k_compose(Work w, int identity, cons
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_flatten(Work w) {
+// Folding the per-round maps, last level first: level l - 1 (the map of one round's nodes
+// into the next round's) is composed with level l, so that after every fold level 0 maps
+// straight to the last level's targets.  The levels shrink round by round, so the folds
+// cost far less than chasing every vertex through every level.
+__global__ __launch_bounds__(kThreads) void k_fold_level(Work w, int l) {
     const RoundState *st = w.st;
+    if (l <= 0 || l >= st->levels) return;
+    const int64_t a = (int64_t)st->level_off[l - 1], b = (int64_t)st->level_off[l];
+    for (int64_t i = a + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < b; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t x = w.maps[i];
+        if (!(x & kFinal)) w.maps[i] = w.maps[b + x];
+    }
+}
+
+// map0 through the folded level 0: every vertex then maps to a final name or to a node of
+// the current graph, and the arena is empty again.  `folded`: the levels the host folded
+// (a device with more would hold unfolded levels: flagged as an inconsistency).
+__global__ __launch_bounds__(kThreads) void k_flatten(Work w, int folded) {
+    RoundState *st = w.st;
     const int levels = st->levels;
+    if (levels > (folded > 1 ? folded : 1)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 4u);
+        return;
+    }
+    const int64_t off0 = (int64_t)st->level_off[0];
     for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
-        uint32_t x = w.map0[v];
-        for (int l = 0; l < levels && !(x & kFinal); ++l) x = w.maps[st->level_off[l] + x];
-        w.map0[v] = x;
+        const uint32_t x = w.map0[v];
+        if (levels > 0 && !(x & kFinal)) w.map0[v] = w.maps[off0 + x];
     }
 }
 
@@ -706,8 +727,13 @@ hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *lab
     LC_LAUNCH((k_compose<false, false>), grid, w, id, names_cur, labels, voff);
 }
 
-hipError_t launch_flatten(const Work &w, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_flatten, dim3(grid), dim3(kThreads), 0, s, w);
+hipError_t launch_flatten(const Work &w, int levels, int grid, hipStream_t s) {
+    for (int l = levels - 1; l >= 1; --l) {
+        hipLaunchKernelGGL(k_fold_level, dim3(grid), dim3(kThreads), 0, s, w, l);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_flatten, dim3(grid), dim3(kThreads), 0, s, w, levels);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_flatten_reset, dim3(1), dim3(1), 0, s, w);
