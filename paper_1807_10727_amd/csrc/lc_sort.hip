@@ -416,11 +416,18 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
     bool broken = false;
     for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         uint32_t cnt = 0;
+        // every load of the tile in flight before any key is looked at
+        uint64_t kk[kSortItems], pk[kSortItems];
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) {   // consecutive lanes take consecutive keys
             const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
-            const uint64_t k = idx < S ? in[idx] : 0ull;
-            const uint64_t prev = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
+            kk[j] = idx < S ? in[idx] : 0ull;
+            pk[j] = (idx > 0 && idx < S) ? in[idx - 1] : ~0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
+            const uint64_t k = kk[j], prev = pk[j];
             if (idx < S && (idx == 0 || k != prev)) {
                 ++cnt;
                 uint64_t lo, hi, plo = ~0ull, phi;
@@ -477,13 +484,10 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
             if (lane_id() == 0) rowcnt[j * kWaves + wave] = (uint32_t)__popcll(bal[j]);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {   // exclusive prefix over (row, wave) in key order
-            uint32_t run = w.tile_cnt[tile];
-            for (int i = 0; i < kSortItems * kWaves; ++i) {
-                const uint32_t c = rowcnt[i];
-                rowcnt[i] = run;
-                run += c;
-            }
+        static_assert(kSortItems * kWaves == kWave, "one (row, wave) count per lane of wave 0");
+        if (threadIdx.x < kWave) {   // exclusive prefix over (row, wave) in key order
+            const uint32_t c = rowcnt[threadIdx.x];
+            rowcnt[threadIdx.x] = (uint32_t)w.tile_cnt[tile] + wave_incl_scan(c) - c;
         }
         __syncthreads();
 #pragma unroll
