@@ -165,6 +165,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         (int64_t)kRadixMax * (ceil_div(std::max<int64_t>(first && tiled ? 2 * M : M, 1), kSortTile) + 2);
     const int gslab = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(M, 1), kSlab), grid_cap);
     const int gscan_c = (int)std::min<int64_t>(ceil_div(scan_entries, kScanTile), grid_cap);
+    // small rounds scan in one workgroup: one launch instead of three (launch-bound sizes)
+    const bool small_sort = scan_entries <= kSmallScanEntries;
+    const bool small_flags = N <= kSmallFlagNodes;
 
     RUN(kRoundBegin, launch_round_begin(w, !first && !batch && variant != kVarTree, r, gn, stream));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
@@ -185,32 +188,40 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
         RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream));
         RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
-        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
     } else if (variant == kVarTree) {
         RUN(first ? kMin1In : kMin1, launch_min1_open(w, src, pc, r, gm, stream));
         RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream));
-        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     } else {
         RUN(first ? kMin1In : kMin1, launch_min1(w, src, pc, batch, r, gm, stream));
         if (variant != kVarOneHop) RUN(first ? kMin2In : kMin2, launch_min2(w, src, gm, stream));
         RUN(kParent, launch_parent(w, pc, batch, r, gn, stream, variant == kVarOneHop));
-        RUN(kLabelRanks, launch_rank_parents(w, gn, gscan_l, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     }
     for (int p = 0; p < passes; ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
-        RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 1));
-        RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
-        RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
+        if (small_sort) {
+            RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 5));
+        } else {
+            RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 1));
+            RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
+            RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
+        }
         RUN(kSortScatter, launch_sort_pass(w, p, gt, stream, 4));
     }
     RUN(kUnique, launch_unique(w, gt, stream, 0));
     RUN(kUnique, launch_unique(w, 1, stream, 1));
-    RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 0));
-    RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 1));
-    RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 2));
+    if (small_flags) {
+        RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 3));
+    } else {
+        RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 0));
+        RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 1));
+        RUN(kNodeScan, launch_map_scan(w, false, gscan_l, stream, 2));
+    }
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
     RUN(kUnique, launch_unique(w, gt, stream, 2));

@@ -129,6 +129,8 @@ constexpr int kRadixMaxBits = LC_SORT_MAX_BITS;
 constexpr int kRadixMax = 1 << kRadixMaxBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
+constexpr int64_t kSmallScanEntries = 1 << 15;    // count tables scanned by one workgroup
+constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one workgroup
 #ifndef LC_DEDUP_LOG2
 #define LC_DEDUP_LOG2 12   // slots of the relabel's workgroup key set (8 B each)
 #endif
@@ -253,7 +255,8 @@ hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_
 // union-find finish of the graph of round `round` (lc_variants.hip)
 hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
-// parents -> label ranks, the label of each rank, and the key width of the sort
+// parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:
+// the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
@@ -285,7 +288,8 @@ hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, h
 hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
-// Sort stages: 0 = digit counts, 1..3 = scan of the counts, 4 = scatter.
+// Sort stages: 0 = digit counts, 1..3 = scan of the counts (or 5: the whole scan in one
+// workgroup), 4 = scatter.  Map scans: 0..2 as the generic scan, 3 = all in one workgroup.
 // Unique stages: 0 = heads per tile + next-node marks, 1 = scan (one workgroup), 2 = ordered
 // write of the heads renamed into the next round's indices (after the node scan and map).
 

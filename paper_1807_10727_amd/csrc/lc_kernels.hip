@@ -678,8 +678,12 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
 
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s) {
     hipError_t e = hipSuccess;
-    for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
-        e = launch_map_scan(w, true, stage == 1 ? 1 : grid_scan, s, stage);
+    if (grid_scan == 0) {   // one workgroup
+        e = launch_map_scan(w, true, 1, s, 3);
+    } else {
+        for (int stage = 0; stage < 3 && e == hipSuccess; ++stage)
+            e = launch_map_scan(w, true, stage == 1 ? 1 : grid_scan, s, stage);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_parents, dim3(grid), dim3(kThreads), 0, s, w);
     e = hipGetLastError();

@@ -124,8 +124,11 @@ struct ReadPacked {
 
 // Edges of rounds >= 1: (a << 32 | b) in the round's compact index space, in the key
 // buffer named by the device state; the count comes from the device state too.
+#ifndef LC_INTERNAL_V
+#define LC_INTERNAL_V 2
+#endif
 struct ReadInternal {
-    static constexpr int kV = 2;
+    static constexpr int kV = LC_INTERNAL_V;   // records per chunk (2 or 4)
     static constexpr bool kSorted = true;   // records ordered by (block of b, a, b): lanes share a
     uint64_t *k0, *k1;
     const uint64_t *k;
@@ -136,24 +139,30 @@ struct ReadInternal {
         m = (int64_t)st->m_cur;
     }
     __device__ int64_t records() const { return m; }
-    __device__ int64_t chunks() const { return (m + 1) / 2; }
+    __device__ int64_t chunks() const { return (m + kV - 1) / kV; }
     __device__ void read(int64_t c, uint32_t *a, uint32_t *b, bool &) const {
-        const int64_t base = c * 2;
-        uint64_t r0, r1;
-        if (base + 2 <= m) {
-            typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        const int64_t base = c * kV;
+        uint64_t r[kV];
+        if (base + kV <= m) {
             // records stream through once: load them non-temporally, so that the node state
             // the same pass gathers keeps its place in L2
-            const u64x2 x = LC_NT_INTERNAL ? __builtin_nontemporal_load((const u64x2 *)(k + base))
-                                           : *(const u64x2 *)(k + base);
-            r0 = x.x;
-            r1 = x.y;
+#pragma unroll
+            for (int h = 0; h < kV; h += 2) {
+                const u64x2 x = LC_NT_INTERNAL ? __builtin_nontemporal_load((const u64x2 *)(k + base + h))
+                                               : *(const u64x2 *)(k + base + h);
+                r[h] = x.x;
+                r[h + 1] = x.y;
+            }
         } else {
-            r0 = k[base];
-            r1 = 0ull;
+#pragma unroll
+            for (int h = 0; h < kV; ++h) r[h] = base + h < m ? k[base + h] : 0ull;
         }
-        a[0] = (uint32_t)(r0 >> 32); b[0] = (uint32_t)r0;
-        a[1] = (uint32_t)(r1 >> 32); b[1] = (uint32_t)r1;
+#pragma unroll
+        for (int h = 0; h < kV; ++h) {
+            a[h] = (uint32_t)(r[h] >> 32);
+            b[h] = (uint32_t)r[h];
+        }
     }
 };
 

@@ -396,6 +396,37 @@ __global__ __launch_bounds__(kThreads) void k_flags_down(const uint8_t *f, const
     }
 }
 
+// The same in one workgroup, for small rounds: every stage in a single launch (four words a
+// thread per step, a running carry across steps).
+__global__ __launch_bounds__(kThreads) void k_flags_single(const uint8_t *f, const u64c *n_ptr, uint32_t *map,
+                                                           u64c *total_out) {
+    constexpr int kW = 4;
+    __shared__ uint32_t lds[kThreads / kWave + 1];
+    const int64_t n = (int64_t)*n_ptr;
+    const int64_t nw = ceil_div(n, 32);
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nw; base += (int64_t)kThreads * kW) {
+        uint32_t bits[kW], c[kW], sum = 0;
+#pragma unroll
+        for (int q = 0; q < kW; ++q) {
+            const int64_t wd = base + (int64_t)threadIdx.x * kW + q;
+            bits[q] = wd < nw ? label_bits(f, wd, n) : 0u;
+            c[q] = (uint32_t)__popc(bits[q]);
+            sum += c[q];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_excl_scan<kThreads>(sum, lds, &total);
+#pragma unroll
+        for (int q = 0; q < kW; ++q) {
+            const int64_t wd = base + (int64_t)threadIdx.x * kW + q;
+            if (wd < nw) *(uint2 *)(map + 2 * wd) = make_uint2(bits[q], run);
+            run += c[q];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
 // ---------------------------------------------------------------------------------------
 // unique
 // ---------------------------------------------------------------------------------------
@@ -537,6 +568,10 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
 
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage) {
     switch (stage) {
+        case 5:   // the count table scanned by one workgroup (small rounds)
+            hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.counts, &w.st->aux_n, 0,
+                               (u64c *)nullptr);
+            return hipGetLastError();
         case 0:
             hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
             return hipGetLastError();
@@ -560,8 +595,10 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
         hipLaunchKernelGGL(k_flags_reduce, dim3(grid), dim3(kThreads), 0, s, f, n, w.partials);
     else if (stage == 1)   // one partial per kThreads words of 32 flags
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.partials, n, 32 * kThreads, total);
-    else
+    else if (stage == 2)
         hipLaunchKernelGGL(k_flags_down, dim3(grid), dim3(kThreads), 0, s, f, n, (const uint32_t *)w.partials, map);
+    else   // all of it in one workgroup (small rounds)
+        hipLaunchKernelGGL(k_flags_single, dim3(1), dim3(kThreads), 0, s, f, n, map, total);
     return hipGetLastError();
 }
 
