@@ -106,9 +106,9 @@ enum {
  * component's node of smallest priority (the smaller of the two nodes the pointers end in);
  * each phase at least halves the nodes and merged nodes are always connected.  CC_ONE_HOP: the
  * vertex of smallest priority in the closed neighbourhood (the rule of Section 6's Cracker
- * comparison, without its edge rewiring); more phases than LocalContraction.  Both run
- * round 0 directly: together, or either with CC_ROUND0_TILED, cc_create returns CC_E_ARG.
- * Priorities, statistics, naming and the labels' meaning are as for LocalContraction. */
+ * comparison, without its edge rewiring); more phases than LocalContraction.  Setting both
+ * makes cc_create return CC_E_ARG.  Either runs round 0 directly or tiled like the default
+ * rule.  Priorities, statistics, naming and the labels' meaning are as for LocalContraction. */
 
 /* cc_run and captured tails.  On a context that has already finished a solve, once the
  * remaining graph has at most 2^22 records, cc_run replays a hipGraph of up to 8 rounds

@@ -31,7 +31,7 @@ const char *const kFamilyNames[kFamilies] = {
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags) {
-    if (flags & (CC_ROUND0_DIRECT | CC_TREE | CC_ONE_HOP)) return false;
+    if (flags & CC_ROUND0_DIRECT) return false;
     if (!tiled_fits(n0)) return false;
     if (flags & CC_ROUND0_TILED) return true;
     return n0 >= kTiledMinVertices && m0 >= kTiledMinVertices;
@@ -186,8 +186,13 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 7));
         RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 8));
         RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
-        RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream));
-        RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
+        RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream, variant == kVarTree));
+        if (variant == kVarTree)
+            RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream, true));
+        else if (variant == kVarOneHop)
+            RUN(kParent, launch_tiled_parent1(w, pc, gn, stream));
+        else
+            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
     } else if (variant == kVarTree) {
@@ -565,7 +570,6 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if ((opts->flags & CC_ROUND0_DIRECT) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     if ((opts->flags & CC_ROUND0_TILED) && g.n_vertices > 0 && !tiled_fits(g.n_vertices)) return CC_E_ARG;
     if ((opts->flags & CC_TREE) && (opts->flags & CC_ONE_HOP)) return CC_E_ARG;
-    if ((opts->flags & (CC_TREE | CC_ONE_HOP)) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     cc_ctx *c = new (std::nothrow) cc_ctx();
     if (!c) return CC_E_NOMEM;
     c->g = g;

@@ -251,7 +251,9 @@ hipError_t launch_parent(const Work &w, const PrioCtx &p, bool batch, int round,
 // TreeContraction (lc_variants.hip): open one-hop minimum; then f, pointer jumping over at most
 // ceil(log2 n_bound) + 2 passes, and the labels
 hipError_t launch_min1_open(const Work &w, const EdgeIn *in, const PrioCtx &p, int round, int grid, hipStream_t s);
-hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s);
+// dense: after the tiled round 0's row pass (m1 dense, f kept in lab_at)
+hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s,
+                              bool dense = false);
 // union-find finish of the graph of round `round` (lc_variants.hip)
 hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
@@ -283,7 +285,10 @@ hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graph
 // t_count), 4 = pass-A scatter, 5 = pass-B counts, 6..8 = their scan, 9 = pass-B scatter.
 hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &tp, int grid, hipStream_t s,
                                   int stage);
-hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s);
+// open: TreeContraction's one-hop minimum without the node's own priority
+hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, bool open = false);
+// the one-hop label's parents from the row pass's one-hop minima
+hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipStream_t s);
 hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s);
 hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s);
 

@@ -288,10 +288,10 @@ __device__ inline void row_range(const Work &w, const TPlan &tp, int X, int64_t 
 }
 
 // kStep 1: m1[x] = min(rho(x), min over the row's records (x, y) of rho(y)), or +inf for an
-// id without a loop-free record.  kStep 2: two-hop minimum min(m1[x], min m1[y]) and the
-// parent it names (the inverse of the priority bijection); an id without records is its
-// own parent.
-template <int kStep>
+// id without a loop-free record; kOpen leaves rho(x) out (TreeContraction's open
+// neighbourhood).  kStep 2: two-hop minimum min(m1[x], min m1[y]) and the parent it names
+// (the inverse of the priority bijection); an id without records is its own parent.
+template <int kStep, bool kOpen = false>
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp) {
     constexpr int kUnroll = kStep == 1 ? 4 : LC_TMIN2_PAIRS;   // record pairs in flight per thread
     __shared__ uint32_t acc[1 << kTxShiftMax];
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
             const uint32_t a = acc[i];
             const uint32_t x = (uint32_t)(base + i);
             if (kStep == 1) {
-                m1[x] = a == kInf ? kInf : min(a, prio(pc.key, x));
+                m1[x] = (a == kInf || kOpen) ? a : min(a, prio(pc.key, x));
             } else if (a == kInf) {
                 w.par[x] = x;   // no loop-free record: not a label, ranked as kNoParent
             } else {
@@ -510,8 +510,39 @@ hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &
     }
 }
 
-hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s) {
-    hipLaunchKernelGGL(k_tiled_min<1>, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, bool open) {
+    if (open)
+        hipLaunchKernelGGL((k_tiled_min<1, true>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+    else
+        hipLaunchKernelGGL((k_tiled_min<1, false>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+    return hipGetLastError();
+}
+
+// The one-hop label over the tiled round 0: the parent named by the closed one-hop minimum
+// (one value per id, as the row pass left it).
+__global__ __launch_bounds__(kThreads) void k_tiled_parent1(Work w, PrioCtx pc) {
+    RoundState *st = w.st;
+    pc.key = st->key;
+    const int64_t n = (int64_t)st->n_cur;
+    uint32_t active = 0;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t a = w.ml[x];
+        if (a == kInf) {
+            w.par[x] = (uint32_t)x;
+            continue;
+        }
+        const uint32_t p = prio_inv(pc.key, a);
+        w.par[x] = p;
+        w.is_label[p] = 1;
+        ++active;
+    }
+    __shared__ uint32_t red[kThreads / kWave];
+    active = block_sum<kThreads>(active, red);
+    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+}
+
+hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_tiled_parent1, dim3(grid), dim3(kThreads), 0, s, w, p);
     return hipGetLastError();
 }
 

@@ -67,9 +67,17 @@ __global__ __launch_bounds__(kThreads) void k_min1_open(R rd, Work w, PrioCtx pc
     if (bad) atomicOr(&w.st->err, 1u);
 }
 
-// f(v) into the high half of the node word and as the starting jump pointer (par); a node
-// without a loop-free record (round 0 only) points to itself.  Resets the jump flags.
-template <bool kFirst>
+// Where the open one-hop minimum and f live: the node word (low half m1, high half f), or
+// after the tiled round 0's row pass, a dense m1 array with f kept in lab_at (free until the
+// labels are ranked).
+template <bool kDense>
+__device__ inline uint32_t tree_m1(const Work &w, int64_t i) { return kDense ? w.ml[i] : w.ml[2 * i]; }
+template <bool kDense>
+__device__ inline uint32_t *tree_f_ptr(const Work &w, int64_t i) { return kDense ? w.lab_at + i : w.ml + 2 * i + 1; }
+
+// f(v) (see tree_f_ptr) and the starting jump pointer (par); a node without a loop-free
+// record (round 0 only) points to itself.  Resets the jump flags.
+template <bool kFirst, bool kDense>
 __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
     RoundState *st = w.st;
     pc.key = st->key;
@@ -81,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
     uint32_t active = 0;
     bool broken = false;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t m = w.ml[2 * i];
+        const uint32_t m = tree_m1<kDense>(w, i);
         uint32_t p = (uint32_t)i;
         if (m != kInf) {
             const uint32_t name = prio_inv(pc.key, m);
@@ -92,7 +100,7 @@ __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
             }
             ++active;
         }
-        w.ml[2 * i + 1] = p;
+        *tree_f_ptr<kDense>(w, i) = p;
         w.par[i] = p;
     }
     __shared__ uint32_t red[kThreads / kWave];
@@ -106,6 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
 // own changes in slot it % 3 and clears slot (it + 1) % 3 for the next pass; once a pass
 // changes nothing, the next one sets jdone and every later pass returns at once.  Passes
 // never read a slot that the same pass writes, so every workgroup decides alike.
+template <bool kDense>
 __global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
     RoundState *st = w.st;
     if (st->jdone) return;
@@ -115,12 +124,11 @@ __global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st->jflag[(it + 1) % 3] = 0u;
     const int64_t n = (int64_t)st->n_cur;
-    const uint32_t *ml = w.ml;
     bool changed = false;
     for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
         const uint32_t j = w.par[x];
-        const uint32_t fj = ml[2 * (size_t)j + 1];
-        if (ml[2 * (size_t)fj + 1] != j) {
+        const uint32_t fj = *tree_f_ptr<kDense>(w, j);
+        if (*tree_f_ptr<kDense>(w, fj) != j) {
             w.par[x] = w.par[j];
             changed = true;
         }
@@ -129,21 +137,20 @@ __global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
 }
 
 // The label of each node: the member of smaller priority of the 2-cycle its pointer reached.
-template <bool kFirst>
+template <bool kFirst, bool kDense>
 __global__ __launch_bounds__(kThreads) void k_tree_label(Work w, PrioCtx pc, const uint32_t *names) {
     RoundState *st = w.st;
     pc.key = st->key;
     const int64_t n = (int64_t)st->n_cur;
-    const uint32_t *ml = w.ml;
     bool broken = false;
     for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
-        if (ml[2 * x + 1] == (uint32_t)x) {   // no neighbour: its own parent, nobody's label
+        if (*tree_f_ptr<kDense>(w, x) == (uint32_t)x) {   // no neighbour: its own parent, nobody's label
             w.par[x] = (uint32_t)x;
             continue;
         }
         const uint32_t j = w.par[x];
-        const uint32_t fj = ml[2 * (size_t)j + 1];
-        if (ml[2 * (size_t)fj + 1] != j) broken = true;   // pointer jumping did not converge
+        const uint32_t fj = *tree_f_ptr<kDense>(w, j);
+        if (*tree_f_ptr<kDense>(w, fj) != j) broken = true;   // pointer jumping did not converge
         const uint32_t lab = tree_prio<kFirst>(pc, names, j) < tree_prio<kFirst>(pc, names, fj) ? j : fj;
         w.par[x] = lab;
         w.is_label[lab] = 1;
@@ -175,26 +182,32 @@ hipError_t launch_min1_open(const Work &w, const EdgeIn *in, const PrioCtx &p, i
     return hipGetLastError();
 }
 
-hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s) {
+template <bool kDense>
+static hipError_t tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s) {
     const uint32_t *names = w.names[round & 1];
     if (round == 0)
-        hipLaunchKernelGGL(k_tree_f<true>, dim3(grid), dim3(kThreads), 0, s, w, p);
+        hipLaunchKernelGGL((k_tree_f<true, kDense>), dim3(grid), dim3(kThreads), 0, s, w, p);
     else
-        hipLaunchKernelGGL(k_tree_f<false>, dim3(grid), dim3(kThreads), 0, s, w, p);
+        hipLaunchKernelGGL((k_tree_f<false, kDense>), dim3(grid), dim3(kThreads), 0, s, w, p);
     hipError_t e = hipGetLastError();
     // a pass at least doubles how far every unfinished pointer has moved along f, so
     // ceil(log2 N) + 1 passes reach every cycle; one more observes that nothing changed
     const int passes = ceil_log2_i64(n_bound < 2 ? 2 : n_bound) + 2;
     for (int it = 0; it < passes && e == hipSuccess; ++it) {
-        hipLaunchKernelGGL(k_tree_jump, dim3(grid), dim3(kThreads), 0, s, w, it);
+        hipLaunchKernelGGL(k_tree_jump<kDense>, dim3(grid), dim3(kThreads), 0, s, w, it);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     if (round == 0)
-        hipLaunchKernelGGL(k_tree_label<true>, dim3(grid), dim3(kThreads), 0, s, w, p, names);
+        hipLaunchKernelGGL((k_tree_label<true, kDense>), dim3(grid), dim3(kThreads), 0, s, w, p, names);
     else
-        hipLaunchKernelGGL(k_tree_label<false>, dim3(grid), dim3(kThreads), 0, s, w, p, names);
+        hipLaunchKernelGGL((k_tree_label<false, kDense>), dim3(grid), dim3(kThreads), 0, s, w, p, names);
     return hipGetLastError();
+}
+
+hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s,
+                              bool dense) {
+    return dense ? tree_labels<true>(w, p, round, n_bound, grid, s) : tree_labels<false>(w, p, round, n_bound, grid, s);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -49,6 +49,9 @@ GRAPHS = {
 VARIANT_FLAGS = {"tree": 1 << 5, "one_hop": 1 << 6}
 
 
+MODES = {"direct": 1 << 2, "tiled": 1 << 3}
+
+
 def per_round(lc, g, seed, flags):
     s_t, d_t = dev(g)
     out = {"parents": [], "stats": []}
@@ -66,13 +69,14 @@ def per_round(lc, g, seed, flags):
     return out
 
 
+@pytest.mark.parametrize("mode", sorted(MODES))
 @pytest.mark.parametrize("variant", sorted(VARIANT_FLAGS))
 @pytest.mark.parametrize("name", sorted(GRAPHS))
-def test_variant_parity(lc, variant, name):
+def test_variant_parity(lc, variant, name, mode):
     g = GRAPHS[name]()
     seed = 0xA11CE + len(name)
     want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant, record_parents=True)
-    got = per_round(lc, g, seed, VARIANT_FLAGS[variant])
+    got = per_round(lc, g, seed, VARIANT_FLAGS[variant] | MODES[mode])
     assert got["rounds"] == want.rounds
     assert got["stats"] == [tuple(x) for x in want.stats]
     for r in range(want.rounds):
@@ -103,14 +107,26 @@ def test_tree_halves_the_nodes(lc):
         assert 2 * st[r][1] <= st[r - 1][1]
 
 
-def test_variant_flags_rejected_with_tiled(lc):
+def test_variant_flags_exclusive(lc):
     g = GRAPHS["gnm_small"]()
     s_t, d_t = dev(g)
-    for flags in (VARIANT_FLAGS["tree"] | VARIANT_FLAGS["one_hop"], VARIANT_FLAGS["tree"] | lc.CC_ROUND0_TILED,
-                  VARIANT_FLAGS["one_hop"] | lc.CC_ROUND0_TILED):
-        with pytest.raises(lc.CCError) as e:
-            lc.Solver(g.n, s_t, d_t, flags=flags)
-        assert e.value.status == -1
+    with pytest.raises(lc.CCError) as e:
+        lc.Solver(g.n, s_t, d_t, flags=VARIANT_FLAGS["tree"] | VARIANT_FLAGS["one_hop"])
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANT_FLAGS))
+def test_variant_tiled_default_sizes(lc, variant):
+    """G(2^20 + 3, 2^22 + 1): the default picks the tiled round 0 for the other rules too."""
+    g = graphgen.Graph((1 << 20) + 3, *graphgen.gnm(61, (1 << 20) + 3, (1 << 22) + 1))
+    s_t, d_t = dev(g)
+    want = oracle.run(g.n, g.src, g.dst, seed=8, variant=variant)
+    with lc.Solver(g.n, s_t, d_t, seed=8, flags=VARIANT_FLAGS[variant] | lc.CC_PROFILE) as s:
+        r = s.run()
+        assert s.kernel_times()["min1_tiled"][1] == 1
+        assert r == want.rounds
+        assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want.labels)
 
 
 @pytest.mark.parametrize("variant", ["local", "tree"])
