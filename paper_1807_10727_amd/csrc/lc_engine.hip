@@ -192,9 +192,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         else if (variant == kVarOneHop)
             RUN(kParent, launch_tiled_parent1(w, pc, gn, stream));
         else
-            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream));
+            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, grid_cap / 8));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
-        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream));
+        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, grid_cap / 8));
     } else if (variant == kVarTree) {
         RUN(first ? kMin1In : kMin1, launch_min1_open(w, src, pc, r, gm, stream));
         RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream));

@@ -289,8 +289,9 @@ hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &
 hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, bool open = false);
 // the one-hop label's parents from the row pass's one-hop minima
 hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipStream_t s);
-hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s);
-hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s);
+// gen: rows per launch (the CU count: one 1024-thread, 128 KiB-LDS workgroup each)
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen);
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
 // Sort stages: 0 = digit counts, 1..3 = scan of the counts (or 5: the whole scan in one

@@ -150,6 +150,9 @@ __device__ inline int64_t tiles_b_of(const RoundState *st) { return ceil_div((in
 // records (so p + 1 is in range whenever p is).
 // Directed records stream through each row kernel once: non-temporal loads keep them from
 // evicting the gathered column values from L2 (measured: the two-hop row pass ~7 % faster).
+#ifndef LC_ROW_GENERATIONS
+#define LC_ROW_GENERATIONS 1
+#endif
 #ifndef LC_NT_RECORDS
 #define LC_NT_RECORDS 1
 #endif
@@ -292,7 +295,7 @@ __device__ inline void row_range(const Work &w, const TPlan &tp, int X, int64_t 
 // neighbourhood).  kStep 2: two-hop minimum min(m1[x], min m1[y]) and the parent it names
 // (the inverse of the priority bijection); an id without records is its own parent.
 template <int kStep, bool kOpen = false>
-__global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp) {
+__global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp, int row0) {
     constexpr int kUnroll = kStep == 1 ? 4 : LC_TMIN2_PAIRS;   // record pairs in flight per thread
     __shared__ uint32_t acc[1 << kTxShiftMax];
     RoundState *st = w.st;
@@ -304,7 +307,9 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
     uint32_t *m1 = w.ml;
     uint32_t active = 0;
     bool broken = false;
-    for (int X = blockIdx.x; X < tp.rows; X += gridDim.x) {
+    // one workgroup per row of [row0, row0 + gridDim.x)
+    const int row_end = min(tp.rows, row0 + (int)gridDim.x);
+    for (int X = row0 + blockIdx.x; X < row_end; X += gridDim.x) {
         const int64_t base = (int64_t)X << tp.xs;
         const int cnt = (int)min((int64_t)1 << tp.xs, n - base);
         for (int i = threadIdx.x; i < cnt; i += kTRowThreads) acc[i] = kInf;
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
 // records; each chunk reserves its survivors' space at the end of the packed key array with
 // one atomic, so the first radix pass reads full tiles (only about half of the directed
 // records are taken, which would leave slabs aligned to the records half empty).
-__global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp) {
+__global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp, int row0) {
     constexpr int kPairs = LC_TRELABEL_PAIRS;   // record pairs per thread and chunk
     constexpr int kChunk = 2 * kPairs * kTRowThreads;
     RoundState *st = w.st;
@@ -395,7 +400,9 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
     const int hbs = st->hb_shift;
     uint32_t kept = 0;
     bool broken = false;
-    for (int X = blockIdx.x; X < tp.rows; X += gridDim.x) {
+    // one workgroup per row of [row0, row0 + gridDim.x)
+    const int row_end = min(tp.rows, row0 + (int)gridDim.x);
+    for (int X = row0 + blockIdx.x; X < row_end; X += gridDim.x) {
         const int64_t base = (int64_t)X << tp.xs;
         const int cnt = (int)min((int64_t)1 << tp.xs, n - base);
         for (int i = threadIdx.x; i < cnt; i += kTRowThreads) lpar[i] = w.par[base + i];
@@ -510,11 +517,25 @@ hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &
     }
 }
 
+// Row kernels run in generations of `gen` rows (one workgroup per CU, all of a generation
+// starting together), so that the rows in flight sweep the column blocks in step and share
+// the gathered column values in L2; a single launch of every row would start late rows at
+// column 0 while early ones are near the end.  gen <= 0: one launch.
+template <class Launch>
+static hipError_t by_generations(const TPlan &tp, int gen, Launch launch) {
+    if (gen <= 0 || !LC_ROW_GENERATIONS) return launch(0, tp.rows);
+    for (int r0 = 0; r0 < tp.rows; r0 += gen) {
+        const hipError_t e = launch(r0, std::min(gen, tp.rows - r0));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, bool open) {
     if (open)
-        hipLaunchKernelGGL((k_tiled_min<1, true>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+        hipLaunchKernelGGL((k_tiled_min<1, true>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp, 0);
     else
-        hipLaunchKernelGGL((k_tiled_min<1, false>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
+        hipLaunchKernelGGL((k_tiled_min<1, false>), dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp, 0);
     return hipGetLastError();
 }
 
@@ -546,14 +567,18 @@ hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s) {
-    hipLaunchKernelGGL(k_tiled_min<2>, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, p, tp);
-    return hipGetLastError();
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen) {
+    return by_generations(tp, gen, [&](int r0, int g) {
+        hipLaunchKernelGGL(k_tiled_min<2>, dim3(g), dim3(kTRowThreads), 0, s, w, p, tp, r0);
+        return hipGetLastError();
+    });
 }
 
-hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s) {
-    hipLaunchKernelGGL(k_tiled_relabel, dim3(tp.rows), dim3(kTRowThreads), 0, s, w, tp);
-    return hipGetLastError();
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen) {
+    return by_generations(tp, gen, [&](int r0, int g) {
+        hipLaunchKernelGGL(k_tiled_relabel, dim3(g), dim3(kTRowThreads), 0, s, w, tp, r0);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace lc
