@@ -156,6 +156,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gn = grid_for(N);
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
+    // the scatter keeps LC_SCATTER_WAVES waves per SIMD resident (four-wave workgroups): a grid
+    // of exactly that many workgroups runs in one go instead of a resident share and a tail
+    const int gt_scatter = LC_SCATTER_GRID ? std::min(gt, std::max(1, grid_cap / 8 * LC_SCATTER_WAVES)) : gt;
     const int gscan_l = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), 32 * kThreads), grid_cap);
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = 2 * kb;   // edge_key
@@ -216,7 +219,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
             RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
         }
-        RUN(kSortScatter, launch_sort_pass(w, p, gt, stream, 4));
+        RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4));
     }
     RUN(kUnique, launch_unique(w, gt, stream, 0));
     RUN(kUnique, launch_unique(w, 1, stream, 1));

@@ -131,6 +131,12 @@ constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 constexpr int64_t kSmallScanEntries = 1 << 15;    // count tables scanned by one workgroup
 constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one workgroup
+#ifndef LC_SCATTER_WAVES
+#define LC_SCATTER_WAVES 3   // waves per SIMD the radix scatter is compiled for
+#endif
+#ifndef LC_SCATTER_GRID
+#define LC_SCATTER_GRID 1
+#endif
 #ifndef LC_DEDUP_LOG2
 #define LC_DEDUP_LOG2 12   // slots of the relabel's workgroup key set (8 B each)
 #endif

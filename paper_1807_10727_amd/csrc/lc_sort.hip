@@ -218,11 +218,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
     }
 }
 
-// Waves per SIMD the scatter is compiled for: 3 trades a few spilled words for a third more
-// waves in flight than the unconstrained register count allows (measured faster).
-#ifndef LC_SCATTER_WAVES
-#define LC_SCATTER_WAVES 3
-#endif
+// Waves per SIMD the scatter is compiled for (LC_SCATTER_WAVES): 3 trades a few spilled
+// words for a third more waves in flight than the unconstrained register count allows
+// (measured faster).
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LC_SCATTER_WAVES)))
 void k_sort_scatter(Work w, int pass) {
     RoundState *st = w.st;
