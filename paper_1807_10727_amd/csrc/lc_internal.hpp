@@ -267,8 +267,6 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
-hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total,
-                          int grid, hipStream_t s, int stage);
 // prefix counts of the label map (total -> n_labels) or of the next-graph node map over the
 // labels (total -> n_next)
 hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage);

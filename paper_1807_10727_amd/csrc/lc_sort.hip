@@ -539,18 +539,6 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
 // launchers
 // ---------------------------------------------------------------------------------------
 
-hipError_t launch_scan_u8(const uint8_t *in, uint32_t *out, uint32_t *partials, const u64c *n, u64c *total, int grid,
-                          hipStream_t s, int stage) {
-    if (stage == 0)
-        hipLaunchKernelGGL(k_scan_reduce<uint8_t>, dim3(grid), dim3(kThreads), 0, s, in, n, partials);
-    else if (stage == 1)
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, partials, n, kScanTile, total);
-    else
-        hipLaunchKernelGGL(k_scan_down<uint8_t>, dim3(grid), dim3(kThreads), 0, s, in, out, n,
-                           (const uint32_t *)partials);
-    return hipGetLastError();
-}
-
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid, hipStream_t s,
                            int stage) {
     if (stage == 0)
