@@ -1,8 +1,8 @@
 """Full-size checks, in the launch configuration bench.py times (default flags: the tiled
 round 0 where the size allows it, the caller's stream, per-kernel timing on).
 
-At these sizes the oracle cannot replay every round, so each test checks what it can
-compute one by one or what holds at any size:
+Beside the full replays below, each test checks what can be computed one by one or what
+holds at any size (the only checks for R-MAT scale 26, too large to replay):
   * round-0 parents of sampled vertices, straight from the definition (the vertex of least
     priority in the closed two-hop neighbourhood, Section 3), in 64-bit (priority, id) keys
     computed with the test-side priority restatement that test_oracle pins to the oracle;
@@ -10,8 +10,16 @@ compute one by one or what holds at any size:
   * the final labels against textbook union-find: every label is an id of its vertex's
     component and there are exactly as many distinct labels as components;
   * the tiled and the direct round 0 give identical statistics and labels.
+The bench graph itself is small enough for the oracle to replay in full (about 1.5 to 2
+minutes a run on one core): its labels, round count and per-round statistics are compared
+bit for bit, for LocalContraction in the timed configuration and for the other label rules
+and the union-find finish as the bench's variant leg runs them.  The four oracle runs start
+in threads (the oracle's calls release the interpreter lock) when the module's first test
+starts, so they overlap the GPU work.
 The batched and serving workloads are checked graph by graph on a seeded sample against the
 oracle (labels and round counts, bit for bit)."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -32,6 +40,27 @@ def lc():
         pytest.skip("no GPU")
     import paper_1807_10727_amd as lc
     return lc
+
+
+# How bench.py runs each rule on the bench graph: (oracle variant, solver flags, finish edges).
+FULL_RUNS = {
+    "local": ("local", "timed", 0),          # CC_PROFILE | CC_EAGER, the timed steps' flags
+    "tree": ("tree", "tree", 0),
+    "one_hop": ("one_hop", "one_hop", 0),
+    "uf_finish": ("local", 0, 1 << 22),
+}
+
+
+@pytest.fixture(scope="module")
+def er_full():
+    """The bench graph and the oracle's runs of it, started in background threads."""
+    g = graphgen.workload_er_paths()
+    oracle.run(2, np.array([0], np.uint32), np.array([1], np.uint32))   # load the library once
+    pool = ThreadPoolExecutor(max_workers=len(FULL_RUNS))
+    futs = {k: pool.submit(oracle.run, g.n, g.src, g.dst, seed=BENCH_SEED, variant=v, finish_edges=f)
+            for k, (v, _, f) in FULL_RUNS.items()}
+    yield g, futs
+    pool.shutdown(wait=True)
 
 
 def sampled_round0_parents(src, dst, seed, sample):
@@ -126,11 +155,36 @@ def run_full_graph(lc, g, layout, seed, sample_size):
 
 
 @pytest.mark.timeout(900)
-def test_er_paths_full_size(lc):
+def test_er_paths_full_size(lc, er_full):
     """G(2^24, 2^27) + 10,000 paths of 1,000 vertices (26,777,216 ids, 144,207,728 records)."""
-    g = graphgen.workload_er_paths()
+    g, _ = er_full
     out = run_full_graph(lc, g, "soa32", BENCH_SEED, 2000)
     assert len(out["stats"]) >= 5           # a 1,000-vertex path needs >= log5(1000) phases (Section 7)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("rule", list(FULL_RUNS))
+def test_er_paths_full_size_vs_oracle(lc, er_full, rule):
+    """The bench graph at the bench's first seed, bit for bit against the oracle: labels,
+    round count, per-round statistics, and whether the union-find finish ran."""
+    g, futs = er_full
+    _, how, finish = FULL_RUNS[rule]
+    flags = {"timed": lc.CC_PROFILE | lc.CC_EAGER, "tree": lc.CC_TREE, "one_hop": lc.CC_ONE_HOP}.get(how, how)
+    src_t = torch.from_numpy(g.src.view(np.int32)).to(DEV)
+    dst_t = torch.from_numpy(g.dst.view(np.int32)).to(DEV)
+    with lc.Solver(g.n, src_t, dst_t, seed=BENCH_SEED, flags=flags, stream=torch.cuda.current_stream(),
+                   finish_edges=finish) as s:
+        rounds = s.run()
+        stats = s.stats(rounds)
+        finished = s.finished
+        labels = s.labels().cpu().numpy()
+    del src_t, dst_t
+    torch.cuda.empty_cache()
+    want = futs[rule].result()
+    assert rounds == want.rounds
+    assert finished == want.finished == (finish > 0)
+    assert [tuple(x) for x in stats] == [tuple(x) for x in want.stats]
+    np.testing.assert_array_equal(labels.astype(np.uint32), want.labels)
 
 
 @pytest.mark.slow
