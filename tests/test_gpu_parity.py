@@ -9,7 +9,7 @@ import pytest
 
 import graphgen
 import oracle
-from lcref import all_graph_adjacency, graph_records
+from lcref import all_graph_adjacency, brute_all, graph_records, spec_priority
 
 pytestmark = pytest.mark.gpu
 
@@ -335,3 +335,56 @@ def test_captured_tail_matches_eager_and_oracle(lc):
         with pytest.raises(lc.CCError) as e:
             tail.parents()
         assert e.value.status == -5     # CC_E_STATE: the last round ran inside the graph
+
+
+# --- the largest vertex ids ---------------------------------------------------------------
+
+@pytest.mark.parametrize("layout", ["soa32", "packed"])
+def test_largest_vertex_ids(lc, layout):
+    """n_vertices = 2^31 - 1, the most the boundary takes (include/cc.h), with edges among
+    eight ids at both ends of the range.  Their per-round parents and statistics, the round
+    count and their labels come from the brute force over their names (priorities depend on
+    names only, Section 3); every other id has no edge and keeps its own id (checked on the
+    device, in chunks)."""
+    n = (1 << 31) - 1
+    names = np.array([0, 1, n - 8, n - 5, n - 4, n - 3, n - 2, n - 1], np.uint32)
+    local = [(0, 7), (7, 6), (6, 4), (1, 2), (2, 3), (3, 1)]
+    adj = np.zeros((1, names.size), np.uint8)
+    for i, j in local:
+        adj[0, i] |= np.uint8(1 << j)
+        adj[0, j] |= np.uint8(1 << i)
+    seed = 0x5EED
+    lab_b, rounds_b, par_b, stats_b = brute_all(adj, lambda r: spec_priority(seed, r, names), max_rounds=8)
+    g = graphgen.Graph(n, names[[i for i, _ in local]], names[[j for _, j in local]])
+    s_t, d_t, lay = to_device(g, layout)
+    nm = torch.from_numpy(names.astype(np.int64)).to(DEV)
+    with lc.Solver(n, s_t, d_t, seed=seed, layout=lay) as s:
+        r = 0
+        while True:
+            st, stats = s.contract_round()
+            if st == lc.CC_DONE:
+                break
+            par, k = s.parents()
+            got = par[nm].cpu().numpy().astype(np.int64)
+            del par
+            pb = par_b[r, 0].astype(np.int64)
+            want = np.where(pb == 255, -1, names[np.minimum(pb, names.size - 1)].astype(np.int64))
+            np.testing.assert_array_equal(got, want, err_msg="round %d" % r)
+            assert tuple(stats[1:]) == tuple(int(x) for x in stats_b[r, 0])
+            assert k == stats[1]
+            r += 1
+        assert r == rounds_b[0]
+        assert s.run() == r
+        lab = s.labels()
+        np.testing.assert_array_equal(lab[nm].cpu().numpy().astype(np.int64), names[lab_b[0]].astype(np.int64))
+        moved = []
+        chunk = 1 << 28
+        for a in range(0, n, chunk):
+            b = min(n, a + chunk)
+            ids = torch.arange(a, b, device=DEV, dtype=lab.dtype)
+            moved += (torch.nonzero(lab[a:b] != ids).flatten() + a).cpu().tolist()
+            del ids
+        assert set(moved) <= set(int(x) for x in names)
+        del lab
+    del s_t, d_t
+    torch.cuda.empty_cache()
