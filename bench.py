@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+COPY_REPS = 5             # timed repetitions of the 1 GiB calibration copy
 # kernel symbol (as rocprofv3 prints it) of each timed family of the int32 input path
 FAMILY_SYMBOL = {
     "min1_round0": "lc::k_min1<lc::ReadSoa32<4>, true, false>",
@@ -57,15 +58,17 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
+def family_bytes(stats, n0, tiled=False, loops=0, sort_info=None):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
     K = keys the relabel wrote and the sort processed (S less the repeats the relabel
-    workgroups dropped; S when not given), M' = distinct edges out, P = radix passes.  Random-access amplification (cache-line
-    reads for 4-byte gathers and atomics, extra sort passes) is implementation overhead
-    and deliberately not counted.  With the tiled round 0, T = 2 (M - loops) directed
-    records are written once, re-read by the row pass and read by each row kernel."""
+    workgroups dropped), M' = distinct edges out, P = radix passes over the keys, as the
+    device reports them (cc_round_stats).
+    Random-access amplification (cache-line reads for 4-byte gathers and atomics) is
+    implementation overhead and deliberately not counted.  With the tiled round 0,
+    T = 2 (M - loops) directed records are written once, re-read by the row pass and read
+    by each row kernel."""
     fam = {}
 
     def add(k, v):
@@ -74,8 +77,7 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
     for i, (r, n_active, m_in, s, m_out, _fin) in enumerate(stats):
         N = n0 if r == 0 else n_active
         M = m_in
-        K = sorted_keys[i] if sorted_keys is not None else s
-        P = (2 * ceil_log2(max(N, 2)) + 7) // 8  # radix passes over the 2 ceil(log2 N)-bit keys
+        K, P = sort_info[i]
         sfx = "_round0" if r == 0 else ""
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
         add("label_ranks", 8 * N + 3 * N // 8)     # parents in, their label ranks out, label map scanned
@@ -433,6 +435,16 @@ def main():
     cal_b = torch.empty_like(cal_a)
     cal_b.copy_(cal_a)
     torch.cuda.synchronize()
+    # the same copy timed with events: the streaming bandwidth this GPU reaches (read + write),
+    # the second denominator beside the 8 TB/s peak
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(COPY_REPS):
+        cal_b.copy_(cal_a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 2.0 * cal_a.numel() * COPY_REPS / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+    log("plain 1 GiB device copy: %.1f GB/s (read + write)" % copy_gbs)
     del cal_a, cal_b
 
     # With per-kernel timing every round runs eagerly (CC_EAGER), so that each launch of the
@@ -463,7 +475,7 @@ def main():
         out = {}
         for st, ks in zip(stats_list, keys_list):
             for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
-                                     sorted_keys=ks).items():
+                                     sort_info=ks).items():
                 out[k] = out.get(k, 0) + v
         return out
 
@@ -483,7 +495,7 @@ def main():
     for i in range(max(args.warmup - 1, 0) if not args.no_profile else args.warmup):
         r = step(1000 + i)
         warm_stats.append(solver.stats(r))
-        warm_keys.append(solver.sorted_keys(r))
+        warm_keys.append(solver.sort_info(r))
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom = None
@@ -508,7 +520,7 @@ def main():
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
-        all_keys.append(solver.sorted_keys(r))
+        all_keys.append(solver.sort_info(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -516,7 +528,8 @@ def main():
     value = m0 * args.steps / dt
     log("rounds per step: %s" % rounds)
     for st, k in zip(all_stats[0], all_keys[0]):
-        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st + " sorted=%d" % k)
+        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st
+            + " sorted=%d radix passes=%d" % k)
 
     # algorithmic bytes per family over the timed steps
     fam_bytes = fam_bytes_of(all_stats, all_keys, fam_n if dom is None else warm_n)
@@ -537,7 +550,8 @@ def main():
         roofline = {"bound": "hbm", "kernel": dom, "symbol": FAMILY_SYMBOL.get(dom), "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else int(traffic),
-                    "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+                    "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                    "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
         log("timed steps: %s %.3f ms/step over %d launches/step, %.1f GB/s algorithmic"
             % (dom, fam_ms[dom] / args.steps, fam_n[dom] / args.steps, achieved))
 
@@ -597,6 +611,7 @@ def main():
                    "round0": args.round0, "parallelism": "single GPU"},
         "roofline": roofline,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
+        "job_alg_frac_of_copy": round(job_gbs / copy_gbs, 4),
         "cpu_baseline": cpu,
         "variants": variants,
         "batched": batched,
