@@ -58,13 +58,14 @@ def ceil_log2(n):
     return b
 
 
-def family_bytes(stats, n0, tiled=False, loops=0, sort_info=None):
+def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
     """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
 
     Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
     K = keys the relabel wrote and the sort processed (S less the repeats the relabel
-    workgroups dropped), M' = distinct edges out, P = radix passes over the keys, as the
-    device reports them (cc_round_stats).
+    workgroups dropped), M' = distinct edges out, P = radix passes over the keys: they carry
+    2 ceil(log2 L) bits in digits of at most 8 bits, L = the round's labels = the next round's
+    nodes plus the labels the round finalised.
     Random-access amplification (cache-line reads for 4-byte gathers and atomics) is
     implementation overhead and deliberately not counted.  With the tiled round 0,
     T = 2 (M - loops) directed records are written once, re-read by the row pass and read
@@ -74,10 +75,12 @@ def family_bytes(stats, n0, tiled=False, loops=0, sort_info=None):
     def add(k, v):
         fam[k] = fam.get(k, 0) + v
 
-    for i, (r, n_active, m_in, s, m_out, _fin) in enumerate(stats):
+    for i, (r, n_active, m_in, s, m_out, fin) in enumerate(stats):
         N = n0 if r == 0 else n_active
         M = m_in
-        K, P = sort_info[i]
+        K = sorted_keys[i]
+        L = fin + (stats[i + 1][1] if i + 1 < len(stats) else 0)
+        P = (2 * ceil_log2(max(L, 2)) + 7) // 8
         sfx = "_round0" if r == 0 else ""
         add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
         add("label_ranks", 8 * N + 3 * N // 8)     # parents in, their label ranks out, label map scanned
@@ -475,7 +478,7 @@ def main():
         out = {}
         for st, ks in zip(stats_list, keys_list):
             for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
-                                     sort_info=ks).items():
+                                     sorted_keys=ks).items():
                 out[k] = out.get(k, 0) + v
         return out
 
@@ -495,7 +498,7 @@ def main():
     for i in range(max(args.warmup - 1, 0) if not args.no_profile else args.warmup):
         r = step(1000 + i)
         warm_stats.append(solver.stats(r))
-        warm_keys.append(solver.sort_info(r))
+        warm_keys.append(solver.sorted_keys(r))
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom = None
@@ -520,7 +523,7 @@ def main():
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
-        all_keys.append(solver.sort_info(r))
+        all_keys.append(solver.sorted_keys(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -528,8 +531,7 @@ def main():
     value = m0 * args.steps / dt
     log("rounds per step: %s" % rounds)
     for st, k in zip(all_stats[0], all_keys[0]):
-        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st
-            + " sorted=%d radix passes=%d" % k)
+        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st + " sorted=%d" % k)
 
     # algorithmic bytes per family over the timed steps
     fam_bytes = fam_bytes_of(all_stats, all_keys, fam_n if dom is None else warm_n)

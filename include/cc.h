@@ -139,9 +139,6 @@ typedef struct {
     int64_t m_sorted;     /* keys this round's sort processed: m_survive less the repeats each
                              relabel workgroup recognised itself (launch-dependent, not a
                              property of the method; m_survive in round 0) */
-    int32_t sort_passes;  /* radix passes over this round's keys (2 ceil(log2 L) bits, L = the
-                             round's labels, digits of at most 8 bits) */
-    int32_t pad_;
 } cc_round_stats;
 
 typedef struct cc_ctx cc_ctx;

@@ -18,8 +18,7 @@ from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_serv
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_EAGER, CC_ONE_HOP, CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CC_TREE, CCError,
-                  cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sort, cc_get_round_sorted,
-                  cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
+                  cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
                   cc_labels, cc_last_error, cc_reset, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
 
@@ -108,11 +107,6 @@ class Solver:
     def sorted_keys(self, rounds: int):
         """For each round, the keys its sort processed (include/cc.h, cc_round_stats.m_sorted)."""
         return [cc_get_round_sorted(self.ctx, r) for r in range(rounds)]
-
-    def sort_info(self, rounds: int):
-        """For each round, (keys sorted, radix passes over them) (include/cc.h,
-        cc_round_stats.m_sorted, sort_passes)."""
-        return [cc_get_round_sort(self.ctx, r) for r in range(rounds)]
 
     def rounds_in_graph(self, rounds: int):
         """For each round, whether it ran inside a captured tail (include/cc.h, cc_run)."""

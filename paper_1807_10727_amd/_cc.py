@@ -45,8 +45,7 @@ class cc_options(ctypes.Structure):
 class cc_round_stats(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("in_graph", ctypes.c_int32), ("n_active", ctypes.c_int64),
                 ("m_in", ctypes.c_int64), ("m_survive", ctypes.c_int64), ("m_out", ctypes.c_int64),
-                ("n_finalised", ctypes.c_int64), ("m_sorted", ctypes.c_int64), ("sort_passes", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("n_finalised", ctypes.c_int64), ("m_sorted", ctypes.c_int64)]
 
     def as_tuple(self):
         return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
@@ -220,13 +219,6 @@ def cc_get_round_sorted(ctx, r: int) -> int:
     s = cc_round_stats()
     _check(ctx, _lib.cc_get_round_stats(ctx, r, ctypes.byref(s)))
     return int(s.m_sorted)
-
-
-def cc_get_round_sort(ctx, r: int):
-    """How round r sorted: (keys, radix passes) from cc_round_stats."""
-    s = cc_round_stats()
-    _check(ctx, _lib.cc_get_round_stats(ctx, r, ctypes.byref(s)))
-    return int(s.m_sorted), int(s.sort_passes)
 
 
 def cc_kernel_family_names():

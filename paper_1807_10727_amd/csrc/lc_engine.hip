@@ -377,7 +377,6 @@ cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out) {
     s.m_out = (int64_t)st.m_next;
     s.n_finalised = (int64_t)st.n_final;
     s.m_sorted = (int64_t)st.s_keys;
-    s.sort_passes = npasses(st.nbits);
     c->stats.push_back(s);
     c->rounds = r + 1;
     if (out) *out = s;
@@ -508,7 +507,6 @@ cc_status run_tail(cc_ctx *c) {
         s.m_out = (int64_t)st.rstats[r][4];
         s.n_finalised = (int64_t)st.rstats[r][5];
         s.m_sorted = (int64_t)st.rstats[r][6];
-        s.sort_passes = (int32_t)st.rstats[r][7];
         c->stats.push_back(s);
     }
     c->rounds = end;

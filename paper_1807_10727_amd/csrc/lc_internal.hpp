@@ -54,9 +54,8 @@ struct RoundState {
     u64c n_next;                  // nodes of the next graph (one workgroup)
     alignas(128) u64c level_off[kMaxLevels];
     // statistics of every round that read records (round, n_active, m_in, survivors, m_out,
-    // n_final, sort keys, radix passes), so that rounds enqueued back to back need a single
-    // readback
-    u64c rstats[kStatRounds][8];
+    // n_final, sort keys), so that rounds enqueued back to back need a single readback
+    u64c rstats[kStatRounds][7];
 };
 
 enum Layout { kSoa32 = 0, kSoa64 = 1, kPacked = 2 };

@@ -463,7 +463,6 @@ __global__ void k_round_end(Work w) {
             s[4] = st->m_next;
             s[5] = st->n_final;
             s[6] = st->s_keys;
-            s[7] = (u64c)npasses(st->nbits);
         }
         st->rounds_active = r + 1;
     }

@@ -1,0 +1,34 @@
+"""The byte model bench.py divides by kernel time (host logic, no GPU).
+
+The statistics below are one solve of the bench graph as the library reported them
+(cc_round_stats: round, n_active, m_in, m_survive, m_out, n_finalised; m_sorted), with the
+radix passes each round ran as the library counted them on the device.  bench.py must
+derive the same passes from the statistics alone: keys carry 2 ceil(log2 L) bits, L = the
+round's labels = the next round's nodes plus the labels finalised."""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import bench  # noqa: E402
+
+STATS = [(0, 26777215, 144207728, 129152105, 121755054, 0), (1, 3773340, 121755054, 57677051, 1106428, 0),
+         (2, 1114120, 1106428, 363522, 363514, 0), (3, 373515, 363514, 116857, 116857, 1),
+         (4, 126857, 116857, 34695, 34695, 0), (5, 44695, 34695, 6659, 6659, 4092),
+         (6, 12567, 6659, 22, 22, 5886), (7, 44, 22, 0, 0, 22)]
+SORTED = [129152105, 1473052, 363514, 116857, 34695, 6659, 22, 0]
+DEVICE_PASSES = [6, 6, 5, 5, 4, 4, 4, 2]
+
+
+def test_radix_passes_follow_the_labels():
+    fb = bench.family_bytes(STATS, 26777216, tiled=True, loops=0, sorted_keys=SORTED)
+    assert fb["sort_scatter"] == sum(16 * k * p for k, p in zip(SORTED, DEVICE_PASSES))
+    assert fb["sort_hist"] == sum(8 * k * p for k, p in zip(SORTED, DEVICE_PASSES))
+
+
+def test_round0_tiled_families():
+    fb = bench.family_bytes(STATS[:1] + STATS[1:2], 26777216, tiled=True, loops=0, sorted_keys=SORTED[:2])
+    T = 2 * STATS[0][2]
+    assert fb["part_b_scatter"] == 16 * T
+    assert fb["min2_tiled"] == 8 * T + 8 * 26777216
+    assert fb["unique"] == 16 * SORTED[0] + 8 * STATS[0][4] + 16 * SORTED[1] + 8 * STATS[1][4]

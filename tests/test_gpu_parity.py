@@ -388,24 +388,3 @@ def test_largest_vertex_ids(lc, layout):
         del lab
     del s_t, d_t
     torch.cuda.empty_cache()
-
-
-@pytest.mark.parametrize("mode", sorted(MODES))
-def test_sort_passes_follow_the_labels(lc, mode):
-    """cc_round_stats.sort_passes: the radix passes over 2 ceil(log2 L)-bit keys (8-bit digits
-    at most), L = the round's labels = the next round's nodes plus the labels finalised."""
-    g = graphgen.er_with_paths(23, 1 << 13, 1 << 15, 50, 400)
-    s_t, d_t, lay = to_device(g)
-    with lc.Solver(g.n, s_t, d_t, seed=4, flags=MODES[mode], layout=lay) as s:
-        r = s.run()
-        st = s.stats(r)
-        info = s.sort_info(r)
-        s.reset(4)                               # the same solve again, later rounds in captured tails
-        assert s.run() == r
-        assert s.sort_info(r) == info and any(s.rounds_in_graph(r))
-    assert r >= 3
-    for i in range(r):
-        labels = st[i][5] + (st[i + 1][1] if i + 1 < r else 0)
-        kb = max(int(labels) - 1, 1).bit_length()
-        assert info[i][1] == (2 * kb + 7) // 8, "round %d" % i
-        assert 0 <= info[i][0] <= st[i][3]      # keys sorted: at most the survivors
