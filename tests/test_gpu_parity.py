@@ -339,8 +339,9 @@ def test_captured_tail_matches_eager_and_oracle(lc):
 
 # --- the largest vertex ids ---------------------------------------------------------------
 
+@pytest.mark.parametrize("variant", ["local", "tree", "one_hop"])
 @pytest.mark.parametrize("layout", ["soa32", "packed"])
-def test_largest_vertex_ids(lc, layout):
+def test_largest_vertex_ids(lc, layout, variant):
     """n_vertices = 2^31 - 1, the most the boundary takes (include/cc.h), with edges among
     eight ids at both ends of the range.  Their per-round parents and statistics, the round
     count and their labels come from the brute force over their names (priorities depend on
@@ -354,11 +355,13 @@ def test_largest_vertex_ids(lc, layout):
         adj[0, i] |= np.uint8(1 << j)
         adj[0, j] |= np.uint8(1 << i)
     seed = 0x5EED
-    lab_b, rounds_b, par_b, stats_b = brute_all(adj, lambda r: spec_priority(seed, r, names), max_rounds=8)
+    lab_b, rounds_b, par_b, stats_b = brute_all(adj, lambda r: spec_priority(seed, r, names), max_rounds=8,
+                                                variant=variant)
     g = graphgen.Graph(n, names[[i for i, _ in local]], names[[j for _, j in local]])
     s_t, d_t, lay = to_device(g, layout)
     nm = torch.from_numpy(names.astype(np.int64)).to(DEV)
-    with lc.Solver(n, s_t, d_t, seed=seed, layout=lay) as s:
+    flags = {"local": 0, "tree": lc.CC_TREE, "one_hop": lc.CC_ONE_HOP}[variant]
+    with lc.Solver(n, s_t, d_t, seed=seed, layout=lay, flags=flags) as s:
         r = 0
         while True:
             st, stats = s.contract_round()
