@@ -109,11 +109,17 @@ __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
     if (broken) atomicOr(&st->err, 4u);
 }
 
-// One pointer-jumping pass: a pointer not yet on a 2-cycle takes its target's pointer.
-// Pass `it` reads whether pass it-1 changed anything (flag slot (it + 2) % 3), records its
-// own changes in slot it % 3 and clears slot (it + 1) % 3 for the next pass; once a pass
-// changes nothing, the next one sets jdone and every later pass returns at once.  Passes
-// never read a slot that the same pass writes, so every workgroup decides alike.
+// A pointer found on its 2-cycle is final: the top bit of par marks it (node indices are
+// below 2^31), so later passes stream over it without gathering.
+constexpr uint32_t kOnCycle = 0x80000000u;
+
+// One pointer-jumping pass: a pointer not yet on a 2-cycle takes its target's pointer; one
+// found on its cycle is marked final.  Pass `it` reads whether pass it-1 moved a pointer
+// (flag slot (it + 2) % 3), records its own moves in slot it % 3 and clears slot
+// (it + 1) % 3 for the next pass; once a pass moves nothing, every pointer is on its cycle,
+// the next pass sets jdone and every later pass returns at once.  Passes never read a slot
+// that the same pass writes, so every workgroup decides alike.  Pointers read while another
+// thread updates them are valid either way (the old or the new position on the same path).
 template <bool kDense>
 __global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
     RoundState *st = w.st;
@@ -126,11 +132,14 @@ __global__ __launch_bounds__(kThreads) void k_tree_jump(Work w, int it) {
     const int64_t n = (int64_t)st->n_cur;
     bool changed = false;
     for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
-        const uint32_t j = w.par[x];
-        const uint32_t fj = *tree_f_ptr<kDense>(w, j);
-        if (*tree_f_ptr<kDense>(w, fj) != j) {
-            w.par[x] = w.par[j];
+        const uint32_t pj = w.par[x];
+        if (pj & kOnCycle) continue;
+        const uint32_t fj = *tree_f_ptr<kDense>(w, pj);
+        if (*tree_f_ptr<kDense>(w, fj) != pj) {
+            w.par[x] = w.par[pj] & ~kOnCycle;
             changed = true;
+        } else {
+            w.par[x] = pj | kOnCycle;
         }
     }
     if (__any(changed) && lane_id() == 0) st->jflag[it % 3] = 1u;
@@ -148,9 +157,12 @@ __global__ __launch_bounds__(kThreads) void k_tree_label(Work w, PrioCtx pc, con
             w.par[x] = (uint32_t)x;
             continue;
         }
-        const uint32_t j = w.par[x];
+        const uint32_t pj = w.par[x];
+        const uint32_t j = pj & ~kOnCycle;
         const uint32_t fj = *tree_f_ptr<kDense>(w, j);
-        if (*tree_f_ptr<kDense>(w, fj) != j) broken = true;   // pointer jumping did not converge
+        // a pointer without the mark was never found on its cycle: check it (the passes
+        // should have converged)
+        if (!(pj & kOnCycle) && *tree_f_ptr<kDense>(w, fj) != j) broken = true;
         const uint32_t lab = tree_prio<kFirst>(pc, names, j) < tree_prio<kFirst>(pc, names, fj) ? j : fj;
         w.par[x] = lab;
         w.is_label[lab] = 1;
