@@ -87,6 +87,24 @@ def test_batch_of_all_graphs_on_five_vertices(lc):
             check_batch(lc, b, lab, rounds)
 
 
+def test_batch_of_all_graphs_on_seven_vertices(lc):
+    """Every labelled graph on 7 vertices (2^21 graphs, 22 M records) as one batch, on the
+    union path and on the LDS path, each with its own seed: labels and round counts equal
+    the oracle's graph by graph (the oracle itself equals the brute force on these graphs)."""
+    adj = all_graph_adjacency(7)
+    src, dst, eoff = graph_records(adj)
+    G = adj.shape[0]
+    voff = np.arange(G + 1, dtype=np.int64) * 7
+    seeds = np.array([graphgen.sm64(91 ^ g) for g in range(G)], dtype=np.uint64)
+    b = graphgen.Batch(np.full(G, 7), np.diff(eoff), voff, eoff, seeds, src, dst)
+    s, d = dev_arrays(b)
+    for variant in (0, 1):
+        with lc.Batch(voff, eoff, seeds, s, d, small_variant=variant) as bt:
+            assert bt.split()[0] == (G if variant else 0)
+            lab, rounds = bt.run()
+            check_batch(lc, b, lab, rounds)
+
+
 def test_batch_degenerate_members(lc):
     specs = [("gnm", 0, 0, 1), ("gnm", 7, 0, 2), ("gnm", 1, 3, 3), ("gnm", 3000, 9000, 4), ("gnm", 2, 1, 5),
              ("rmat", 1 << 12, 8 << 12, 6)]
