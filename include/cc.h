@@ -198,6 +198,18 @@ cc_status cc_labels(cc_ctx *ctx, void *d_labels);
 cc_status cc_round_parents(cc_ctx *ctx, int32_t *d_parents, int64_t *n_nodes);
 
 /*
+ * Edges of the graph the most recent round left (test and inspection aid, not on the
+ * measured path): the distinct loop-free edges between that round's parents (the
+ * contraction step, proof of the lemma in Section 3), each once, written to d_edges
+ * (uint64[cap]) as (a << 32) | b with a < b the two endpoints' names, in no particular
+ * order.  *n_edges (host) receives their number; d_edges NULL asks for the number only, and
+ * a d_edges of fewer than that many entries gets nothing (CC_E_ARG).  Synchronises when it
+ * writes.  CC_E_STATE like cc_round_parents (no round yet, a round inside a captured tail,
+ * the union-find finish).
+ */
+cc_status cc_round_edges(cc_ctx *ctx, uint64_t *d_edges, int64_t cap, int64_t *n_edges);
+
+/*
  * Union-find finish (Section 6): from round 1 on, once the graph left by a round has at most
  * max_edges edges (0, the default, turns this off), cc_run ends the solve by finding the
  * components of that graph with a union-find on the device instead of running more rounds.

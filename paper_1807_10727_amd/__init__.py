@@ -19,7 +19,7 @@ from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_serv
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_EAGER, CC_ONE_HOP, CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CC_TREE, CCError,
                   cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
-                  cc_labels, cc_last_error, cc_reset, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
+                  cc_labels, cc_last_error, cc_reset, cc_round_edges, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
 
 __all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_ONE_HOP", "CC_PROFILE",
@@ -100,6 +100,15 @@ class Solver:
         out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
         k = cc_round_parents(self.ctx, out.data_ptr())
         return out[:self.n], k
+
+    def edges(self):
+        """Edges of the graph the last round left, by name: an int64 tensor of
+        (a << 32) | b with a < b, one entry per distinct edge, in no particular order."""
+        torch = _torch()
+        m = cc_round_edges(self.ctx, 0, 0)            # the count only
+        out = torch.empty(max(m, 1), dtype=torch.int64, device=self.device)
+        k = cc_round_edges(self.ctx, out.data_ptr(), out.numel())
+        return out[:k]
 
     def stats(self, rounds: int):
         return [cc_get_round_stats(self.ctx, r) for r in range(rounds)]

@@ -94,6 +94,7 @@ _sig = {
     "cc_run": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32)]),
     "cc_labels": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p]),
     "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "cc_round_edges": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "cc_get_round_stats": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.POINTER(cc_round_stats)]),
     "cc_kernel_family_count": (ctypes.c_int32, []),
     "cc_set_profile_mask": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
@@ -195,6 +196,14 @@ def cc_labels(ctx, ptr: int) -> None:
 def cc_round_parents(ctx, ptr: int) -> int:
     n = ctypes.c_int64()
     _check(ctx, _lib.cc_round_parents(ctx, ptr, ctypes.byref(n)))
+    return int(n.value)
+
+
+def cc_round_edges(ctx, ptr: int, cap: int) -> int:
+    """Edges of the graph the last round left, by name, into the device buffer at ptr
+    (uint64[cap]); returns their number (include/cc.h)."""
+    n = ctypes.c_int64()
+    _check(ctx, _lib.cc_round_edges(ctx, ptr, int(cap), ctypes.byref(n)))
     return int(n.value)
 
 

@@ -674,6 +674,23 @@ cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {
     return CC_OK;
 }
 
+cc_status cc_round_edges(cc_ctx *c, uint64_t *d_edges, int64_t cap, int64_t *n_edges) {
+    if (!c || !n_edges) return CC_E_ARG;
+    if (c->failed_status) return c->failed_status;
+    if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
+    if (c->next_round - 1 == c->last_graph_round)
+        return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
+    if (c->finished) return reject(c, CC_E_STATE, "the solve ended with the union-find finish");
+    const int64_t m = c->m_cur;   // records of the graph the last round left (its readback)
+    *n_edges = m;
+    if (m == 0 || !d_edges) return CC_OK;   // no edge left, or the count only
+    if (cap < m) return reject(c, CC_E_ARG, "edge buffer smaller than the edge count");
+    hipError_t e = launch_dump_edges(c->w, d_edges, c->next_round, c->grid_for(m), c->stream);
+    if (!c->hip_ok(e, "dump edges")) return CC_E_HIP;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
+    return CC_OK;
+}
+
 cc_status cc_get_round_stats(const cc_ctx *c, int32_t r, cc_round_stats *out) {
     if (!c || !out || r < 0 || r >= (int32_t)c->stats.size()) return CC_E_ARG;
     *out = c->stats[r];

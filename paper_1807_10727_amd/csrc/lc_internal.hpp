@@ -276,6 +276,8 @@ hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
 hipError_t launch_round_end(const Work &w, int round, hipStream_t s);
+// the current graph's edges by name (the graph round `next_round` reads)
+hipError_t launch_dump_edges(const Work &w, uint64_t *out, int next_round, int grid, hipStream_t s);
 hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,
                           const uint32_t *voff, int grid, hipStream_t s);
 // fold the host-known `levels` per-round maps into map0 and empty the arena

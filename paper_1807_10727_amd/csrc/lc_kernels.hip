@@ -578,6 +578,19 @@ __global__ __launch_bounds__(kThreads) void k_dump_parents(Work w, int first, co
     }
 }
 
+// The edges of the next graph by name (cc_round_edges): each record (a, b) of node indices
+// becomes (smaller name << 32) | larger name.
+__global__ __launch_bounds__(kThreads) void k_dump_edges(Work w, const uint32_t *names, uint64_t *out) {
+    const RoundState *st = w.st;
+    const int64_t m = (int64_t)st->m_cur;
+    const uint64_t *rec = w.keys[st->e_sel];
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < m; i += (int64_t)gridDim.x * kThreads) {
+        const uint64_t r = rec[i];
+        const uint32_t a = names[(uint32_t)(r >> 32)], b = names[(uint32_t)r];
+        out[i] = ((uint64_t)min(a, b) << 32) | max(a, b);
+    }
+}
+
 // per-graph round keys of the current round (the round index is read on the device, so
 // the launch can be replayed from a captured graph)
 __global__ void k_batch_keys(Work w, RoundKey *keys, const uint64_t *seeds, int32_t g) {
@@ -770,6 +783,10 @@ hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     LC_LAUNCH(k_dump_parents, grid, w, last_round == 0 ? 1 : 0, (const uint32_t *)w.names[last_round & 1], out);
+}
+
+hipError_t launch_dump_edges(const Work &w, uint64_t *out, int next_round, int grid, hipStream_t s) {
+    LC_LAUNCH(k_dump_edges, grid, w, (const uint32_t *)w.names[next_round & 1], out);
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, int grid, hipStream_t s) {

@@ -297,3 +297,24 @@ def scipy_components(n: int, src, dst) -> np.ndarray:
                       shape=(n, n)).tocsr()
     _, lab = connected_components(A, directed=True, connection="weak")
     return lab
+
+
+def contract_edges(a, b, parent_of):
+    """The contraction step (proof of the lemma in Section 3) applied to edges (a[i], b[i])
+    by name: the distinct loop-free pairs (parent(a), parent(b)), as sorted uint64 keys
+    (smaller name << 32) | larger name.  Loops among (a, b) are dropped first."""
+    a = np.asarray(a, dtype=np.uint64)
+    b = np.asarray(b, dtype=np.uint64)
+    keep = a != b
+    pa = np.asarray(parent_of, dtype=np.uint64)[a[keep].astype(np.int64)]
+    pb = np.asarray(parent_of, dtype=np.uint64)[b[keep].astype(np.int64)]
+    keep = pa != pb
+    lo = np.minimum(pa[keep], pb[keep])
+    hi = np.maximum(pa[keep], pb[keep])
+    return np.unique((lo << np.uint64(32)) | hi)
+
+
+def split_keys(k):
+    """(a, b) name arrays of uint64 keys (a << 32) | b."""
+    k = np.asarray(k, dtype=np.uint64)
+    return (k >> np.uint64(32)).astype(np.uint32), (k & np.uint64(0xFFFFFFFF)).astype(np.uint32)

@@ -9,7 +9,7 @@ import pytest
 
 import graphgen
 import oracle
-from lcref import all_graph_adjacency, brute_all, graph_records, spec_priority
+from lcref import all_graph_adjacency, brute_all, contract_edges, graph_records, spec_priority, split_keys
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,7 @@ def gpu_solve(lc, g, seed, layout="soa32", per_round=True, flags=0, max_rounds=0
                 par, k = s.parents()
                 out["parents"].append(par.cpu().numpy().view(np.uint32).copy())
                 assert k == stats[1]
+                out.setdefault("edges", []).append(np.sort(s.edges().cpu().numpy().view(np.uint64)))
             # finish via cc_run (no rounds left, or stops at max_rounds)
             out["rounds"] = s.run()
         else:
@@ -78,6 +79,14 @@ def check(lc, g, seed, **kw):
         assert len(got["parents"]) == want.rounds
         for r in range(want.rounds):
             np.testing.assert_array_equal(got["parents"][r], want.parents[r], err_msg="round %d" % r)
+        # the graph each round left: the contraction of the previous one through the oracle's
+        # parents (the input records for round 0)
+        a, b = g.src, g.dst
+        for r in range(len(got.get("edges", []))):
+            want_e = contract_edges(a, b, want.parents[r])
+            np.testing.assert_array_equal(got["edges"][r], want_e, err_msg="edges after round %d" % r)
+            assert want_e.size == want.stats[r][4]
+            a, b = split_keys(want_e)
     lab = got["labels"]
     np.testing.assert_array_equal(lab.astype(np.int64), want.labels.astype(np.int64))
     return want

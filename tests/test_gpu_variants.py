@@ -11,6 +11,7 @@ import pytest
 
 import graphgen
 import oracle
+from lcref import contract_edges, split_keys
 
 pytestmark = pytest.mark.gpu
 
@@ -64,6 +65,7 @@ def per_round(lc, g, seed, flags):
             par, k = s.parents()
             out["parents"].append(par.cpu().numpy().view(np.uint32).copy())
             assert k == stats[1]
+            out.setdefault("edges", []).append(np.sort(s.edges().cpu().numpy().view(np.uint64)))
         out["rounds"] = s.run()
         out["labels"] = s.labels().cpu().numpy()
     return out
@@ -82,6 +84,11 @@ def test_variant_parity(lc, variant, name, mode):
     for r in range(want.rounds):
         np.testing.assert_array_equal(got["parents"][r], want.parents[r], err_msg="round %d" % r)
     np.testing.assert_array_equal(got["labels"].astype(np.uint32), want.labels)
+    a, b = g.src, g.dst          # each round's graph: the contraction through the oracle's parents
+    for r in range(want.rounds):
+        want_e = contract_edges(a, b, want.parents[r])
+        np.testing.assert_array_equal(got["edges"][r], want_e, err_msg="edges after round %d" % r)
+        a, b = split_keys(want_e)
 
 
 @pytest.mark.parametrize("variant", sorted(VARIANT_FLAGS))

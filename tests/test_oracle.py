@@ -401,3 +401,23 @@ def test_finish_is_smallest_remaining_name(finish):
     want = np.full(g.n, np.iinfo(np.int64).max, np.int64)
     np.minimum.at(want, comp, part.labels.astype(np.int64))
     np.testing.assert_array_equal(res.labels.astype(np.int64), want[comp])
+
+
+@pytest.mark.parametrize("variant", ["local", "tree", "one_hop"])
+def test_edge_counts_follow_the_contraction(variant):
+    """Each round's distinct edges out (m_out) and the next round's records (m_in) equal the
+    size of the previous edge set contracted through the oracle's own parents: the distinct
+    loop-free parent pairs (proof of the contraction-step lemma, Section 3)."""
+    from lcref import contract_edges, split_keys
+    for g, seed in ((graphgen.Graph(3000, *graphgen.gnm(31, 3000, 9001)), 4),
+                    (graphgen.er_with_paths(32, 1 << 10, 1 << 11, 20, 50), 5),
+                    (graphgen.Graph(1 << 12, *graphgen.rmat(33, 12, 8 << 12)), 6)):
+        want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant, record_parents=True)
+        a, b = g.src, g.dst
+        for r in range(want.rounds):
+            e = contract_edges(a, b, want.parents[r])
+            assert e.size == want.stats[r][4]
+            if r + 1 < want.rounds:
+                assert want.stats[r + 1][2] == e.size
+            a, b = split_keys(e)
+        assert a.size == 0
