@@ -141,3 +141,17 @@ def test_batch_rejects_bad_ids(lc):
             with pytest.raises(lc.CCError) as e:
                 bt.run()
             assert e.value.status == -2
+
+
+def test_autotune_candidates_agree(lc):
+    """Every candidate the autotuner times gives bit-identical labels (it raises otherwise),
+    and the configuration it picks matches the oracle graph by graph."""
+    from paper_1807_10727_amd import autotune
+    b = make_batch(300, 0xA070, log2_min=4, log2_max=12)
+    s, d = dev_arrays(b)
+    with lc.Batch(b.voff, b.eoff, b.seeds, s, d) as bt:
+        cfg, _, tried = autotune.tune(bt, repeats=1, cache=None)
+        assert tried > 1
+        assert bt.config == cfg or all(bt.config[k] == v for k, v in cfg.items())
+        lab, rounds = bt.run()
+        check_batch(lc, b, lab, rounds)
