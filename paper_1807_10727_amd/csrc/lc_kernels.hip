@@ -432,11 +432,17 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
         out = w.maps + st->map_off;
     }
     // the parent's bit and its index in the next graph come from one 8-byte word of the map;
-    // a final parent is named through the label of its rank
+    // a final parent is named through the label of its rank.  When every label keeps an edge,
+    // a parent's index in the next graph is its rank.
+    const bool same = st->n_next == st->n_labels;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         const uint32_t q = w.par[i];
         if (q == kNoParent) {   // round 0: an id without a loop-free record is final on its own
             out[i] = kFinal | (uint32_t)i;
+            continue;
+        }
+        if (same) {
+            out[i] = q;
             continue;
         }
         const uint2 e = *(const uint2 *)(w.nmap + 2 * (q >> 5));

@@ -494,6 +494,9 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
     const int kb = st->kb;
     const int hbs = st->hb_shift;
     const uint64_t n_lab = st->n_labels;   // key endpoints are label ranks
+    // every label keeps an edge (none is final this round): the next round's index of label
+    // q is q itself, and the renaming lookups are skipped
+    const bool same = st->n_next == n_lab;
     const int wave = threadIdx.x / kWave;
     const uint64_t lt = lanemask_lt();
     for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
@@ -526,8 +529,8 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
                 uint64_t lo, hi;
                 edge_key_split(k[j], kb, hbs, lo, hi);
                 // ids were checked by the count pass (a failed check flags the round)
-                const uint32_t a = lo < n_lab ? nmap_rank(w.nmap, lo) : 0u;
-                const uint32_t b = hi < n_lab ? nmap_rank(w.nmap, hi) : 0u;
+                const uint32_t a = lo < n_lab ? (same ? (uint32_t)lo : nmap_rank(w.nmap, lo)) : 0u;
+                const uint32_t b = hi < n_lab ? (same ? (uint32_t)hi : nmap_rank(w.nmap, hi)) : 0u;
                 out[off] = ((uint64_t)a << 32) | b;
             }
         }
