@@ -110,6 +110,15 @@ def test_tiled_full_blocks_parity(lc, n, m, seed):
     check(lc, g, seed)
 
 
+def test_tiled_largest_id_space(lc):
+    """The largest id space the tiled round 0 takes (2^26 ids: 2048 row blocks of 2^15 ids,
+    the most the row digit holds), sparse records over all of it, against the oracle round
+    by round."""
+    n = 1 << 26
+    g = graphgen.Graph(n, *graphgen.gnm(0x7171, n, 1 << 21))
+    check(lc, g, 13, flags=MODES["tiled"])
+
+
 def test_small_workload_parity(lc):
     """G(n, m) with n = 65,536 and m = 262,144, every round and the labels bit-exact."""
     g = graphgen.workload_small()
