@@ -353,6 +353,10 @@ def test_captured_tail_matches_eager_and_oracle(lc):
         with pytest.raises(lc.CCError) as e:
             tail.parents()
         assert e.value.status == -5     # CC_E_STATE: the last round ran inside the graph
+        with pytest.raises(lc.CCError) as e:
+            tail.edges()
+        assert e.value.status == -5
+        assert eager.edges().numel() == 0   # an eager solve that ran to the end left no edge
 
 
 # --- the largest vertex ids ---------------------------------------------------------------

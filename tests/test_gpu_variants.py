@@ -152,9 +152,10 @@ def test_finish_parity(lc, name, finish, variant):
         assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
         np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want.labels)
         if want.finished:
-            with pytest.raises(lc.CCError) as e:
-                s.parents()
-            assert e.value.status == -5
+            for query in (s.parents, s.edges):
+                with pytest.raises(lc.CCError) as e:
+                    query()
+                assert e.value.status == -5
         # the same context without the finish: the plain labels again
         s.set_finish(0)
         s.reset(seed)
