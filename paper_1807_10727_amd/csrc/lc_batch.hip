@@ -90,6 +90,7 @@ __global__ void k_state_init(RoundState *st, int64_t n0, int64_t m0, int64_t map
         st->kb = 0;
         st->hb_shift = 0;
         st->e_sel = 0;
+        st->hash_slots = 0;   // read by every round end
         st->done = m0 == 0 ? 1 : 0;
         st->levels = 0;
         st->n_active = 0;

@@ -26,7 +26,7 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph", "uf_finish"};
+    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -81,6 +81,7 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     t.keys[0] = (uint64_t *)take(8 * mk);
     t.keys[1] = (uint64_t *)take(8 * mk);
     t.counts = (uint32_t *)take(4 * count_entries);
+    t.kcap = (int64_t)mk;
     t.tile_cnt = (uint32_t *)take(4 * tiles + 64);
     t.slab_cnt = (uint32_t *)take(4 * slabs + 64);
     t.partials = (uint32_t *)take(4 * parts);
@@ -210,7 +211,16 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     }
-    for (int p = 0; p < passes; ++p) {
+    // rounds >= 1 small enough for the key set drop repeats by hashing, the rest by sorting
+    const bool hashed = LC_HASH_DEDUP && !first && M <= kHashMaxRecords && 2 * M + 1 <= w.kcap;
+    const int ghash = grid_tiles(2 * M + 1);
+    if (hashed) {
+        RUN(kHashDedup, launch_hash_dedup(w, 1, stream, 0));
+        RUN(kHashDedup, launch_hash_dedup(w, grid_for(2 * M + 1), stream, 1));
+        RUN(kHashDedup, launch_hash_dedup(w, gt, stream, 2));
+        RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 3));
+    }
+    for (int p = 0; p < (hashed ? 0 : passes); ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
         if (small_sort) {
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 5));
@@ -221,8 +231,8 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         }
         RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4));
     }
-    RUN(kUnique, launch_unique(w, gt, stream, 0));
-    RUN(kUnique, launch_unique(w, 1, stream, 1));
+    if (!hashed) RUN(kUnique, launch_unique(w, gt, stream, 0));
+    RUN(hashed ? kHashDedup : kUnique, launch_unique(w, 1, stream, 1));   // tile counts scanned
     if (small_flags) {
         RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 3));
     } else {
@@ -232,8 +242,11 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
-    RUN(kUnique, launch_unique(w, gt, stream, 2));
-    RUN(kRoundEnd, launch_round_end(w, r, stream));
+    if (hashed)
+        RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 4));
+    else
+        RUN(kUnique, launch_unique(w, gt, stream, 2));
+    RUN(kRoundEnd, launch_round_end(w, r, hashed, stream));
     return true;
 }
 

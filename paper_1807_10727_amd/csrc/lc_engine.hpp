@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kUfFinish, kFamilies
+    kTailGraph, kUfFinish, kHashDedup, kFamilies
 };
 
 // how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)

@@ -39,7 +39,7 @@ struct RoundState {
     uint64_t seed;     // priority seed of a plain solve
     RoundKey key;      // this round's priority key, round_key(seed, round) (plain solve)
     int32_t rounds_active;   // rounds so far that read at least one record
-    int32_t pad1_;
+    int32_t hash_slots;      // slots of the hashed duplicate drop (rounds that use it)
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
     alignas(128) u64c s_keys;     // sort keys written by the relabel: the survivors less the
@@ -102,6 +102,7 @@ struct Work {
     uint64_t *keys[2];   // [m0] edge / sort key ping-pong buffers (E_r is keys[e_sel])
     uint32_t *counts;    // [kRadixMax * sort tiles] digit counts of one sort pass
     uint32_t *partials;  // scan partial sums
+    int64_t kcap;        // records each key buffer holds
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
     int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
@@ -131,6 +132,14 @@ constexpr int kMaxPasses = 8;                      // 64-bit keys
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 constexpr int64_t kSmallScanEntries = 1 << 15;    // count tables scanned by one workgroup
 constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one workgroup
+// Rounds >= 1 with at most kHashMaxRecords records (and a key buffer of at least 2 M + 1
+// records) drop repeated edges through an open-addressing key set of 2 K + 1 slots instead of
+// the radix passes, whose launches dominate such rounds.  The set lives in the round's own
+// edge buffer, which the relabel has consumed.
+#ifndef LC_HASH_DEDUP
+#define LC_HASH_DEDUP 1
+#endif
+constexpr int64_t kHashMaxRecords = 1 << 22;   // as large as a captured tail's record bound
 #ifndef LC_SCATTER_WAVES
 #define LC_SCATTER_WAVES 3   // waves per SIMD the radix scatter is compiled for
 #endif
@@ -273,9 +282,14 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
                            hipStream_t s, int stage);
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);
+// duplicate drop by hashing: stage 0 table size (one thread), 1 clear, 2 insert the relabel's
+// keys, 3 count the kept keys per table tile and mark the next graph's nodes, 4 write them
+// renamed into the relabel's buffer (after the tile counts and the node map are scanned)
+hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage);
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
-hipError_t launch_round_end(const Work &w, int round, hipStream_t s);
+// hashed: the round dropped repeats by hashing (its edges are in the relabel's buffer)
+hipError_t launch_round_end(const Work &w, int round, bool hashed, hipStream_t s);
 // the current graph's edges by name (the graph round `next_round` reads)
 hipError_t launch_dump_edges(const Work &w, uint64_t *out, int next_round, int grid, hipStream_t s);
 hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
 }
 
 template <bool kFirst>
-__global__ void k_round_end(Work w) {
+__global__ void k_round_end(Work w, int hashed) {
     RoundState *st = w.st;
     if (st->m_cur > 0) {
         const int r = st->round;
@@ -478,7 +478,8 @@ __global__ void k_round_end(Work w) {
         st->levels += 1;
         st->map_off += st->n_cur;
     }
-    st->e_sel = 1 - sorted_sel(st->round, st->e_sel, st->nbits);   // the unique write's output
+    // the unique write's output (the hashed drop writes into the relabel's buffer)
+    st->e_sel = hashed ? sort_src(st->round, st->e_sel) : 1 - sorted_sel(st->round, st->e_sel, st->nbits);
     st->n_cur = st->n_next;
     st->m_cur = st->m_next;
     st->round += 1;
@@ -729,11 +730,11 @@ hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s) {
     LC_LAUNCH(k_map<false>, grid, w, (const uint32_t *)w.names[round & 1]);
 }
 
-hipError_t launch_round_end(const Work &w, int round, hipStream_t s) {
+hipError_t launch_round_end(const Work &w, int round, bool hashed, hipStream_t s) {
     if (round == 0) {
-        hipLaunchKernelGGL(k_round_end<true>, dim3(1), dim3(1), 0, s, w);
+        hipLaunchKernelGGL(k_round_end<true>, dim3(1), dim3(1), 0, s, w, (int)hashed);
     } else {
-        hipLaunchKernelGGL(k_round_end<false>, dim3(1), dim3(1), 0, s, w);
+        hipLaunchKernelGGL(k_round_end<false>, dim3(1), dim3(1), 0, s, w, (int)hashed);
     }
     return hipGetLastError();
 }

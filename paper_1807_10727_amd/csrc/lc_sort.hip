@@ -539,6 +539,164 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
 }
 
 // ---------------------------------------------------------------------------------------
+// duplicate drop by hashing (small rounds)
+// ---------------------------------------------------------------------------------------
+
+// Keys hold 2 ceil(log2 L) <= 62 bits, so no key has every bit set.
+constexpr uint64_t kEmptySlot = ~0ull;
+
+// The key set lives in the round's own edge buffer (E_r, consumed by the relabel) and the kept
+// keys go back into the relabel's buffer, so the round ends with the edges in the other buffer
+// than a sorted round of an even pass count would leave them (the host tells the round end).
+__device__ inline uint64_t *hash_table(const Work &w) { return w.keys[w.st->e_sel]; }
+
+// A key's home slot: a multiplicative hash, its high word scaled to [0, slots).
+__device__ inline uint64_t home_slot(uint64_t key, uint64_t slots) {
+    return __umul64hi(key * 0x9E3779B97F4A7C15ull, slots);
+}
+
+// Table size: 2 K + 1 slots (at most half full).  A round with more keys than the host's bound
+// allowed, or than its buffer holds, is flagged and keeps a table that fits the buffer: the
+// inserts then run out of probes and flag it again, and no access leaves the buffer.
+__global__ void k_hash_plan(Work w) {
+    RoundState *st = w.st;
+    const uint64_t K = st->s_keys;
+    uint64_t slots = 2 * K + 1;
+    if (K > (uint64_t)kHashMaxRecords || slots > (uint64_t)w.kcap) {
+        atomicOr(&st->err, 4u);
+        slots = (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
+    }
+    st->hash_slots = (int32_t)slots;
+    st->aux_n = (u64c)ceil_div((int64_t)slots, kSortTile);   // entries of the count scan
+}
+
+__global__ __launch_bounds__(kThreads) void k_hash_clear(Work w) {
+    const int64_t slots = w.st->hash_slots;
+    uint64_t *tab = hash_table(w);
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kThreads)
+        tab[i] = kEmptySlot;
+}
+
+// Every key the relabel wrote (in its slabs) joins the set: linear probing from its home slot,
+// an empty slot claimed with a compare-and-swap, a repeat stopping at its own key.  A slot
+// changes only once (from empty), so a plain read that finds a key reads it right.
+__global__ __launch_bounds__(kSortThreads) void k_hash_insert(Work w) {
+    RoundState *st = w.st;
+    const uint64_t slots = (uint64_t)st->hash_slots;
+    const Tiles tl = tiles_of(w, 0);
+    const uint64_t *in = w.keys[sort_src(st->round, st->e_sel)];
+    u64c *tab = (u64c *)hash_table(w);
+    bool lost = false;
+    for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
+        const int tv = tl.valid(tile);
+        for (int i = threadIdx.x; i < tv; i += kSortThreads) {
+            const uint64_t key = in[tile * kSortTile + i];
+            uint64_t h = home_slot(key, slots);
+            bool placed = false;
+            for (uint64_t probe = 0; probe < slots; ++probe) {
+                uint64_t cur = tab[h];
+                if (cur == kEmptySlot) cur = atomicCAS(&tab[h], (u64c)kEmptySlot, (u64c)key);
+                if (cur == kEmptySlot || cur == key) {
+                    placed = true;
+                    break;
+                }
+                h = h + 1 == slots ? 0 : h + 1;
+            }
+            lost |= !placed;
+        }
+    }
+    if (lost) atomicOr(&st->err, 4u);
+}
+
+// Kept keys per table tile (kSortTile slots, the last one ragged), and the next graph's nodes:
+// both endpoints of every kept edge.
+__global__ __launch_bounds__(kSortThreads) void k_hash_count(Work w) {
+    RoundState *st = w.st;
+    __shared__ uint32_t lds[kSortThreads / kWave + 1];
+    const int64_t slots = st->hash_slots;
+    const int64_t ntiles = ceil_div(slots, kSortTile);
+    const uint64_t *tab = hash_table(w);
+    const int kb = st->kb;
+    const int hbs = st->hb_shift;
+    const uint64_t n_lab = st->n_labels;
+    bool broken = false;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t kk[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
+            kk[j] = idx < slots ? tab[idx] : kEmptySlot;
+        }
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (kk[j] == kEmptySlot) continue;
+            ++cnt;
+            uint64_t lo, hi;
+            edge_key_split(kk[j], kb, hbs, lo, hi);
+            if (lo < n_lab && hi < n_lab) {
+                w.has_edge[lo] = 1;
+                w.has_edge[hi] = 1;
+            } else {
+                broken = true;
+            }
+        }
+        uint32_t total;
+        block_excl_scan<kSortThreads>(cnt, lds, &total);
+        if (threadIdx.x == 0) w.tile_cnt[tile] = total;
+    }
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+// The next graph's edge list: the kept keys, tile by tile at the scanned tile offsets, renamed
+// into the next round's indices (as the unique write renames the sorted heads).
+__global__ __launch_bounds__(kSortThreads) void k_hash_write(Work w) {
+    constexpr int kWaves = kSortThreads / kWave;
+    RoundState *st = w.st;
+    __shared__ uint32_t rowcnt[kSortItems * kWaves];
+    const int64_t slots = st->hash_slots;
+    const int64_t ntiles = ceil_div(slots, kSortTile);
+    const uint64_t *tab = hash_table(w);
+    uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
+    const int kb = st->kb;
+    const int hbs = st->hb_shift;
+    const uint64_t n_lab = st->n_labels;
+    const bool same = st->n_next == n_lab;   // every label keeps an edge: index = rank
+    const int wave = threadIdx.x / kWave;
+    const uint64_t lt = lanemask_lt();
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t k[kSortItems];
+        uint64_t bal[kSortItems];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
+            k[j] = idx < slots ? tab[idx] : kEmptySlot;
+            bal[j] = ballot(k[j] != kEmptySlot);
+            if (lane_id() == 0) rowcnt[j * kWaves + wave] = (uint32_t)__popcll(bal[j]);
+        }
+        __syncthreads();
+        static_assert(kSortItems * kWaves == kWave, "one (row, wave) count per lane of wave 0");
+        if (threadIdx.x < kWave) {   // exclusive prefix over (row, wave)
+            const uint32_t c = rowcnt[threadIdx.x];
+            rowcnt[threadIdx.x] = (uint32_t)w.tile_cnt[tile] + wave_incl_scan(c) - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (k[j] != kEmptySlot) {
+                const uint32_t off = rowcnt[j * kWaves + wave] + (uint32_t)__popcll(bal[j] & lt);
+                uint64_t lo, hi;
+                edge_key_split(k[j], kb, hbs, lo, hi);
+                const uint32_t a = lo < n_lab ? (same ? (uint32_t)lo : nmap_rank(w.nmap, lo)) : 0u;
+                const uint32_t b = hi < n_lab ? (same ? (uint32_t)hi : nmap_rank(w.nmap, hi)) : 0u;
+                out[off] = ((uint64_t)a << 32) | b;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 
@@ -588,6 +746,26 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
         hipLaunchKernelGGL(k_flags_down, dim3(grid), dim3(kThreads), 0, s, f, n, (const uint32_t *)w.partials, map);
     else   // all of it in one workgroup (small rounds)
         hipLaunchKernelGGL(k_flags_single, dim3(1), dim3(kThreads), 0, s, f, n, map, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage) {
+    switch (stage) {
+        case 0:
+            hipLaunchKernelGGL(k_hash_plan, dim3(1), dim3(1), 0, s, w);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_hash_clear, dim3(grid), dim3(kThreads), 0, s, w);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_hash_insert, dim3(grid), dim3(kSortThreads), 0, s, w);
+            break;
+        case 3:
+            hipLaunchKernelGGL(k_hash_count, dim3(grid), dim3(kSortThreads), 0, s, w);
+            break;
+        default:
+            hipLaunchKernelGGL(k_hash_write, dim3(grid), dim3(kSortThreads), 0, s, w);
+    }
     return hipGetLastError();
 }
 
