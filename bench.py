@@ -47,8 +47,8 @@ FAMILY_SYMBOL = {
 }
 
 
-# rounds >= 1 with at most this many records drop repeated edges by hashing (the library's
-# kHashMaxRecords)
+# rounds >= 1 with at most this many keys drop repeated edges by hashing (the library's
+# kHashMaxRecords; the bench graph's key buffers always hold the table)
 HASH_MAX_RECORDS = 1 << 22
 
 
@@ -70,8 +70,8 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
     K = keys the relabel wrote and the sort processed (S less the repeats the relabel
     workgroups dropped), M' = distinct edges out, P = radix passes over the keys: they carry
     2 ceil(log2 L) bits in digits of at most 8 bits, L = the round's labels = the next round's
-    nodes plus the labels the round finalised.  Rounds >= 1 of at most HASH_MAX_RECORDS
-    records drop repeats through a hashed key set instead of sorting.
+    nodes plus the labels the round finalised.  Rounds >= 1 with at most HASH_MAX_RECORDS
+    keys drop repeats through a hashed key set instead of sorting.
     Random-access amplification (cache-line reads for 4-byte gathers and atomics) is
     implementation overhead and deliberately not counted.  With the tiled round 0,
     T = 2 (M - loops) directed records are written once, re-read by the row pass and read
@@ -104,7 +104,7 @@ def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
             add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
             add("parent", 8 * N)                       # lv in, parent out
             add("relabel" + sfx, 8 * M + 4 * N + 8 * K)   # records in, parents in once, keys out
-        if r >= 1 and M <= HASH_MAX_RECORDS:
+        if r >= 1 and K <= HASH_MAX_RECORDS:
             # keys in, each distinct key stored in the key set and read back by the count and
             # the write, renamed unique keys out
             add("hash_dedup", 8 * K + 32 * m_out)

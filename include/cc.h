@@ -136,9 +136,11 @@ typedef struct {
     int64_t m_survive;    /* records whose two endpoints get different parents (repeats counted) */
     int64_t m_out;        /* distinct loop-free edges of the next graph, |E_{r+1}| */
     int64_t n_finalised;  /* distinct parents of this round that keep no edge */
-    int64_t m_sorted;     /* keys this round's sort processed: m_survive less the repeats each
-                             relabel workgroup recognised itself (launch-dependent, not a
-                             property of the method; m_survive in round 0) */
+    int64_t m_sorted;     /* keys this round's duplicate drop processed (a radix sort, or from
+                             round 1 on a hashed key set when at most 2^22 of them): m_survive
+                             less the repeats each relabel workgroup recognised itself
+                             (launch-dependent, not a property of the method; m_survive in
+                             round 0) */
 } cc_round_stats;
 
 typedef struct cc_ctx cc_ctx;

@@ -114,7 +114,8 @@ class Solver:
         return [cc_get_round_stats(self.ctx, r) for r in range(rounds)]
 
     def sorted_keys(self, rounds: int):
-        """For each round, the keys its sort processed (include/cc.h, cc_round_stats.m_sorted)."""
+        """For each round, the keys its duplicate drop processed (include/cc.h,
+        cc_round_stats.m_sorted)."""
         return [cc_get_round_sorted(self.ctx, r) for r in range(rounds)]
 
     def rounds_in_graph(self, rounds: int):

@@ -211,17 +211,18 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(first ? kRelabelIn : kRelabel, launch_relabel(w, src, gslab, stream));
     }
-    // rounds >= 1 small enough for the key set drop repeats by hashing, the rest by sorting
-    const bool hashed = LC_HASH_DEDUP && !first && M <= kHashMaxRecords && 2 * M + 1 <= w.kcap;
-    const int ghash = grid_tiles(2 * M + 1);
-    if (hashed) {
-        RUN(kHashDedup, launch_hash_dedup(w, 1, stream, 0));
-        RUN(kHashDedup, launch_hash_dedup(w, grid_for(2 * M + 1), stream, 1));
-        RUN(kHashDedup, launch_hash_dedup(w, gt, stream, 2));
-        RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 3));
-    }
-    for (int p = 0; p < (hashed ? 0 : passes); ++p) {
-        RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0));
+    // rounds >= 1 small enough for the key set drop repeats by hashing; larger ones choose on
+    // the device once their key count is known (both ways enqueued, the unused one returns at
+    // once); round 0 sorts
+    const int dedup = !LC_HASH_DEDUP || first                         ? kDedupSort
+                      : (M <= kHashMaxRecords && 2 * M + 1 <= w.kcap) ? kDedupHash
+                                                                      : kDedupDevice;
+    const bool gated = dedup == kDedupDevice;
+    const int64_t hmax = dedup == kDedupHash ? 2 * M + 1 : std::min<int64_t>(2 * kHashMaxRecords + 1, w.kcap);
+    const int ghash = grid_tiles(hmax);
+    if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, 1, stream, 0, gated));
+    for (int p = 0; p < (dedup == kDedupHash ? 0 : passes); ++p) {
+        RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0, gated));
         if (small_sort) {
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 5));
         } else {
@@ -229,10 +230,15 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
             RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
         }
-        RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4));
+        RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4, gated));
     }
-    if (!hashed) RUN(kUnique, launch_unique(w, gt, stream, 0));
-    RUN(hashed ? kHashDedup : kUnique, launch_unique(w, 1, stream, 1));   // tile counts scanned
+    if (dedup != kDedupSort) {   // after the gated sort, whose skipped count pass empties aux_n
+        RUN(kHashDedup, launch_hash_dedup(w, grid_for(hmax), stream, 1));
+        RUN(kHashDedup, launch_hash_dedup(w, gt, stream, 2));
+        RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 3));
+    }
+    if (dedup != kDedupHash) RUN(kUnique, launch_unique(w, gt, stream, 0, gated));
+    RUN(dedup == kDedupHash ? kHashDedup : kUnique, launch_unique(w, 1, stream, 1));   // tile counts scanned
     if (small_flags) {
         RUN(kNodeScan, launch_map_scan(w, false, 1, stream, 3));
     } else {
@@ -242,11 +248,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
-    if (hashed)
-        RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 4));
-    else
-        RUN(kUnique, launch_unique(w, gt, stream, 2));
-    RUN(kRoundEnd, launch_round_end(w, r, hashed, stream));
+    if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 4));
+    if (dedup != kDedupHash) RUN(kUnique, launch_unique(w, gt, stream, 2, gated));
+    RUN(kRoundEnd, launch_round_end(w, r, dedup, stream));
     return true;
 }
 

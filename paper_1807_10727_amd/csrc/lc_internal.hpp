@@ -140,6 +140,9 @@ constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one work
 #define LC_HASH_DEDUP 1
 #endif
 constexpr int64_t kHashMaxRecords = 1 << 22;   // as large as a captured tail's record bound
+// A round of more records hashes when its keys (known on the device after the relabel, often
+// far fewer than its records) do: the hashing kernels and the sort are both enqueued, gated.
+enum Dedup { kDedupSort = 0, kDedupHash = 1, kDedupDevice = 2 };
 #ifndef LC_SCATTER_WAVES
 #define LC_SCATTER_WAVES 3   // waves per SIMD the radix scatter is compiled for
 #endif
@@ -275,21 +278,24 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
 // parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
-hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage);
+// gated (this and the unique): skipped when the round's device-side choice was to hash
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated = false);
 // prefix counts of the label map (total -> n_labels) or of the next-graph node map over the
 // labels (total -> n_next)
 hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage);
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
                            hipStream_t s, int stage);
-hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage);
-// duplicate drop by hashing: stage 0 table size (one thread), 1 clear, 2 insert the relabel's
-// keys, 3 count the kept keys per table tile and mark the next graph's nodes, 4 write them
-// renamed into the relabel's buffer (after the tile counts and the node map are scanned)
-hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage);
+hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage, bool gated = false);
+// duplicate drop by hashing: stage 0 table size (one thread; decide: or the choice to sort),
+// 1 clear, 2 insert the relabel's keys, 3 count the kept keys per table tile and mark the next
+// graph's nodes, 4 write them renamed into the relabel's buffer (after the tile counts and the
+// node map are scanned)
+hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage, bool decide = false);
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);
-// hashed: the round dropped repeats by hashing (its edges are in the relabel's buffer)
-hipError_t launch_round_end(const Work &w, int round, bool hashed, hipStream_t s);
+// dedup: how the round dropped repeats: kDedupSort, kDedupHash (its edges are then in the
+// relabel's buffer) or kDedupDevice (the device chose; hash_slots nonzero: it hashed)
+hipError_t launch_round_end(const Work &w, int round, int dedup, hipStream_t s);
 // the current graph's edges by name (the graph round `next_round` reads)
 hipError_t launch_dump_edges(const Work &w, uint64_t *out, int next_round, int grid, hipStream_t s);
 hipError_t launch_compose(const Work &w, bool identity, int cur_round, void *labels, bool out64, bool batch,

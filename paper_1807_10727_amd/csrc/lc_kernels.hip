@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_
 }
 
 template <bool kFirst>
-__global__ void k_round_end(Work w, int hashed) {
+__global__ void k_round_end(Work w, int dedup) {
     RoundState *st = w.st;
     if (st->m_cur > 0) {
         const int r = st->round;
@@ -479,6 +479,7 @@ __global__ void k_round_end(Work w, int hashed) {
         st->map_off += st->n_cur;
     }
     // the unique write's output (the hashed drop writes into the relabel's buffer)
+    const bool hashed = dedup == kDedupHash || (dedup == kDedupDevice && st->hash_slots != 0);
     st->e_sel = hashed ? sort_src(st->round, st->e_sel) : 1 - sorted_sel(st->round, st->e_sel, st->nbits);
     st->n_cur = st->n_next;
     st->m_cur = st->m_next;
@@ -730,11 +731,11 @@ hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s) {
     LC_LAUNCH(k_map<false>, grid, w, (const uint32_t *)w.names[round & 1]);
 }
 
-hipError_t launch_round_end(const Work &w, int round, bool hashed, hipStream_t s) {
+hipError_t launch_round_end(const Work &w, int round, int dedup, hipStream_t s) {
     if (round == 0) {
-        hipLaunchKernelGGL(k_round_end<true>, dim3(1), dim3(1), 0, s, w, (int)hashed);
+        hipLaunchKernelGGL(k_round_end<true>, dim3(1), dim3(1), 0, s, w, dedup);
     } else {
-        hipLaunchKernelGGL(k_round_end<false>, dim3(1), dim3(1), 0, s, w, (int)hashed);
+        hipLaunchKernelGGL(k_round_end<false>, dim3(1), dim3(1), 0, s, w, dedup);
     }
     return hipGetLastError();
 }

@@ -161,10 +161,12 @@ typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
 
 __device__ inline bool is_leader(uint64_t peers) { return (int)(__ffsll((long long)peers) - 1) == lane_id(); }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
+// gated: the round chose its duplicate drop on the device, and a hashed choice (hash_slots
+// nonzero) skips the sort (an empty count table, so the scans that follow do nothing)
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass, int gated) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
-    if (pass >= passes) {
+    if (pass >= passes || (gated && st->hash_slots != 0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = 0;
         return;
     }
@@ -222,10 +224,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass) {
 // words for a third more waves in flight than the unconstrained register count allows
 // (measured faster).
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LC_SCATTER_WAVES)))
-void k_sort_scatter(Work w, int pass) {
+void k_sort_scatter(Work w, int pass, int gated) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
-    if (pass >= passes) return;
+    if (pass >= passes || (gated && st->hash_slots != 0)) return;
     int shift, width;
     pass_digit(st->nbits, pass, shift, width);
     const int nbins = 1 << width;
@@ -432,8 +434,9 @@ __global__ __launch_bounds__(kThreads) void k_flags_single(const uint8_t *f, con
 // Heads (first key of every run of equal sorted keys) per tile, and the next graph's node
 // marks: both endpoints of every kept edge (the endpoints of all survivors, the same set).
 // Keys with equal lo are adjacent, so lo is marked by the first key of its run only.
-__global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
+__global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w, int gated) {
     RoundState *st = w.st;
+    if (gated && st->hash_slots != 0) return;   // the round hashed
     __shared__ uint32_t lds[kSortThreads / kWave + 1];
     const int64_t S = (int64_t)st->s_keys;
     const int64_t ntiles = ceil_div(S, kSortTile);
@@ -482,9 +485,10 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_count(Work w) {
 // kSortThreads consecutive keys [j * kSortThreads, (j + 1) * kSortThreads): a wave ballot
 // per row and a prefix over (row, wave) give each head its place, so consecutive lanes read,
 // gather and write consecutive keys.
-__global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w) {
+__global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w, int gated) {
     constexpr int kWaves = kSortThreads / kWave;
     RoundState *st = w.st;
+    if (gated && st->hash_slots != 0) return;   // the round hashed
     __shared__ uint32_t rowcnt[kSortItems * kWaves];
     const int64_t S = (int64_t)st->s_keys;
     const int64_t ntiles = ceil_div(S, kSortTile);
@@ -555,19 +559,25 @@ __device__ inline uint64_t home_slot(uint64_t key, uint64_t slots) {
     return __umul64hi(key * 0x9E3779B97F4A7C15ull, slots);
 }
 
-// Table size: 2 K + 1 slots (at most half full).  A round with more keys than the host's bound
-// allowed, or than its buffer holds, is flagged and keeps a table that fits the buffer: the
-// inserts then run out of probes and flag it again, and no access leaves the buffer.
-__global__ void k_hash_plan(Work w) {
+// Table size: 2 K + 1 slots (at most half full).  decide: the host could not bound K (a round
+// of many records), and a round whose keys do not fit sorts instead (hash_slots 0: every
+// hashing kernel returns at once, the gated sort runs).  Otherwise a round with more keys
+// than the host's bound allowed, or than its buffer holds, is flagged and keeps a table that
+// fits the buffer: the inserts then run out of probes and flag it again, and no access leaves
+// the buffer.
+__global__ void k_hash_plan(Work w, int decide) {
     RoundState *st = w.st;
     const uint64_t K = st->s_keys;
     uint64_t slots = 2 * K + 1;
     if (K > (uint64_t)kHashMaxRecords || slots > (uint64_t)w.kcap) {
-        atomicOr(&st->err, 4u);
-        slots = (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
+        if (decide) {
+            slots = 0;
+        } else {
+            atomicOr(&st->err, 4u);
+            slots = (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
+        }
     }
     st->hash_slots = (int32_t)slots;
-    st->aux_n = (u64c)ceil_div((int64_t)slots, kSortTile);   // entries of the count scan
 }
 
 __global__ __launch_bounds__(kThreads) void k_hash_clear(Work w) {
@@ -583,6 +593,7 @@ __global__ __launch_bounds__(kThreads) void k_hash_clear(Work w) {
 __global__ __launch_bounds__(kSortThreads) void k_hash_insert(Work w) {
     RoundState *st = w.st;
     const uint64_t slots = (uint64_t)st->hash_slots;
+    if (slots == 0) return;   // the round sorts
     const Tiles tl = tiles_of(w, 0);
     const uint64_t *in = w.keys[sort_src(st->round, st->e_sel)];
     u64c *tab = (u64c *)hash_table(w);
@@ -614,7 +625,9 @@ __global__ __launch_bounds__(kSortThreads) void k_hash_count(Work w) {
     RoundState *st = w.st;
     __shared__ uint32_t lds[kSortThreads / kWave + 1];
     const int64_t slots = st->hash_slots;
+    if (slots == 0) return;   // the round sorts
     const int64_t ntiles = ceil_div(slots, kSortTile);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;   // entries of the count scan
     const uint64_t *tab = hash_table(w);
     const int kb = st->kb;
     const int hbs = st->hb_shift;
@@ -654,7 +667,7 @@ __global__ __launch_bounds__(kSortThreads) void k_hash_write(Work w) {
     constexpr int kWaves = kSortThreads / kWave;
     RoundState *st = w.st;
     __shared__ uint32_t rowcnt[kSortItems * kWaves];
-    const int64_t slots = st->hash_slots;
+    const int64_t slots = st->hash_slots;   // 0: the round sorts
     const int64_t ntiles = ceil_div(slots, kSortTile);
     const uint64_t *tab = hash_table(w);
     uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
@@ -713,21 +726,21 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
     return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage) {
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated) {
     switch (stage) {
         case 5:   // the count table scanned by one workgroup (small rounds)
             hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.counts, &w.st->aux_n, 0,
                                (u64c *)nullptr);
             return hipGetLastError();
         case 0:
-            hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
+            hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
             return hipGetLastError();
         case 1:
         case 2:
         case 3:
             return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 1);
         default:
-            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, s, w, pass);
+            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
             return hipGetLastError();
     }
 }
@@ -749,10 +762,10 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
     return hipGetLastError();
 }
 
-hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage) {
+hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage, bool decide) {
     switch (stage) {
         case 0:
-            hipLaunchKernelGGL(k_hash_plan, dim3(1), dim3(1), 0, s, w);
+            hipLaunchKernelGGL(k_hash_plan, dim3(1), dim3(1), 0, s, w, (int)decide);
             break;
         case 1:
             hipLaunchKernelGGL(k_hash_clear, dim3(grid), dim3(kThreads), 0, s, w);
@@ -769,14 +782,14 @@ hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage) 
     return hipGetLastError();
 }
 
-hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage) {
+hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage, bool gated) {
     if (stage == 0)
-        hipLaunchKernelGGL(k_unique_count, dim3(grid), dim3(kSortThreads), 0, s, w);
+        hipLaunchKernelGGL(k_unique_count, dim3(grid), dim3(kSortThreads), 0, s, w, (int)gated);
     else if (stage == 1)
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.tile_cnt, &w.st->aux_n, 0,
                            &w.st->m_next);
     else
-        hipLaunchKernelGGL(k_unique_write, dim3(grid), dim3(kSortThreads), 0, s, w);
+        hipLaunchKernelGGL(k_unique_write, dim3(grid), dim3(kSortThreads), 0, s, w, (int)gated);
     return hipGetLastError();
 }
 

@@ -22,12 +22,12 @@ DEVICE_PASSES = [6, 6, 5, 5, 4, 4, 4, 2]
 
 def test_radix_passes_follow_the_labels():
     fb = bench.family_bytes(STATS, 26777216, tiled=True, loops=0, sorted_keys=SORTED)
-    # rounds 0 and 1 sort; rounds 2.. (at most 2^22 records each) drop repeats by hashing
-    sorted_rounds = [i for i, st in enumerate(STATS) if st[0] == 0 or st[2] > bench.HASH_MAX_RECORDS]
-    assert sorted_rounds == [0, 1]
+    # round 0 sorts; rounds 1.. (at most 2^22 keys each, round 1 from 121 M records) hash
+    sorted_rounds = [i for i, st in enumerate(STATS) if st[0] == 0 or SORTED[i] > bench.HASH_MAX_RECORDS]
+    assert sorted_rounds == [0]
     assert fb["sort_scatter"] == sum(16 * SORTED[i] * DEVICE_PASSES[i] for i in sorted_rounds)
     assert fb["sort_hist"] == sum(8 * SORTED[i] * DEVICE_PASSES[i] for i in sorted_rounds)
-    assert fb["hash_dedup"] == sum(8 * SORTED[i] + 32 * STATS[i][4] for i in range(2, len(STATS)))
+    assert fb["hash_dedup"] == sum(8 * SORTED[i] + 32 * STATS[i][4] for i in range(1, len(STATS)))
 
 
 def test_round0_tiled_families():
@@ -35,4 +35,5 @@ def test_round0_tiled_families():
     T = 2 * STATS[0][2]
     assert fb["part_b_scatter"] == 16 * T
     assert fb["min2_tiled"] == 8 * T + 8 * 26777216
-    assert fb["unique"] == 16 * SORTED[0] + 8 * STATS[0][4] + 16 * SORTED[1] + 8 * STATS[1][4]
+    assert fb["unique"] == 16 * SORTED[0] + 8 * STATS[0][4]
+    assert fb["hash_dedup"] == 8 * SORTED[1] + 32 * STATS[1][4]

@@ -178,10 +178,20 @@ def test_er_paths_full_size_vs_oracle(lc, er_full, rule):
                    finish_edges=finish) as s:
         rounds = s.run()
         stats = s.stats(rounds)
+        keys = s.sorted_keys(rounds)
         finished = s.finished
         labels = s.labels().cpu().numpy()
     del src_t, dst_t
     torch.cuda.empty_cache()
+    # Round 1 reads more records than the host lets a round hash, so the device chooses once
+    # the relabel has counted its keys: LocalContraction's 121 M records leave ~1.5 M keys
+    # (hashed), the one-hop rule keeps 108 M distinct edges (sorted).  Both choices are then
+    # checked bit for bit below.
+    assert stats[1][2] > 1 << 22
+    if rule == "local":
+        assert keys[1] <= 1 << 22
+    if rule == "one_hop":
+        assert keys[1] > 1 << 22
     want = futs[rule].result()
     assert rounds == want.rounds
     assert finished == want.finished == (finish > 0)
