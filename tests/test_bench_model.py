@@ -37,3 +37,13 @@ def test_round0_tiled_families():
     assert fb["min2_tiled"] == 8 * T + 8 * 26777216
     assert fb["unique"] == 16 * SORTED[0] + 8 * STATS[0][4]
     assert fb["hash_dedup"] == 8 * SORTED[1] + 32 * STATS[1][4]
+
+
+def test_families_outside_captured_tails():
+    # a captured tail holds rounds >= 1 of at most 2^22 records: they hash, so the radix and
+    # unique families and round 0's never run there; the per-round families do
+    for fam in ("sort_scatter", "sort_hist", "sort_scan", "unique", "min2_tiled", "part_b_scatter",
+                "relabel_round0"):
+        assert bench.tail_free(fam)
+    for fam in ("min1", "min2", "relabel", "hash_dedup", "round_begin", "map", "nodes"):
+        assert not bench.tail_free(fam)
