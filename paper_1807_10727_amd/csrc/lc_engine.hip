@@ -220,7 +220,8 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const bool gated = dedup == kDedupDevice;
     const int64_t hmax = dedup == kDedupHash ? 2 * M + 1 : std::min<int64_t>(2 * kHashMaxRecords + 1, w.kcap);
     const int ghash = grid_tiles(hmax);
-    if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, 1, stream, 0, gated));
+    // the table sized and cleared first: when gated, that kernel also records the choice
+    if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, grid_for(hmax), stream, 1, gated));
     for (int p = 0; p < (dedup == kDedupHash ? 0 : passes); ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0, gated));
         if (small_sort) {
@@ -233,7 +234,6 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4, gated));
     }
     if (dedup != kDedupSort) {   // after the gated sort, whose skipped count pass empties aux_n
-        RUN(kHashDedup, launch_hash_dedup(w, grid_for(hmax), stream, 1));
         RUN(kHashDedup, launch_hash_dedup(w, gt, stream, 2));
         RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 3));
     }

@@ -286,10 +286,10 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
 hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u64c *total, int grid,
                            hipStream_t s, int stage);
 hipError_t launch_unique(const Work &w, int grid, hipStream_t s, int stage, bool gated = false);
-// duplicate drop by hashing: stage 0 table size (one thread; decide: or the choice to sort),
-// 1 clear, 2 insert the relabel's keys, 3 count the kept keys per table tile and mark the next
-// graph's nodes, 4 write them renamed into the relabel's buffer (after the tile counts and the
-// node map are scanned)
+// duplicate drop by hashing: stage 1 size and clear the table (decide: or choose to sort;
+// before a gated sort), 2 insert the relabel's keys, 3 count the kept keys per table tile and
+// mark the next graph's nodes, 4 write them renamed into the relabel's buffer (after the tile
+// counts and the node map are scanned)
 hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage, bool decide = false);
 hipError_t launch_nodes(const Work &w, bool batch, int round, int grid, hipStream_t s);
 hipError_t launch_map(const Work &w, int round, int grid, hipStream_t s);

@@ -559,31 +559,25 @@ __device__ inline uint64_t home_slot(uint64_t key, uint64_t slots) {
     return __umul64hi(key * 0x9E3779B97F4A7C15ull, slots);
 }
 
-// Table size: 2 K + 1 slots (at most half full).  decide: the host could not bound K (a round
-// of many records), and a round whose keys do not fit sorts instead (hash_slots 0: every
-// hashing kernel returns at once, the gated sort runs).  Otherwise a round with more keys
-// than the host's bound allowed, or than its buffer holds, is flagged and keeps a table that
-// fits the buffer: the inserts then run out of probes and flag it again, and no access leaves
-// the buffer.
-__global__ void k_hash_plan(Work w, int decide) {
+// The table: 2 K + 1 slots (at most half full), cleared to empty.  Every workgroup derives
+// the size from K; workgroup 0 records it for the kernels that follow.  decide: the host could
+// not bound K (a round of many records), and a round whose keys do not fit sorts instead
+// (hash_slots 0: every hashing kernel returns at once, the gated sort runs).  Otherwise a
+// round with more keys than the host's bound allowed, or than its buffer holds, is flagged
+// and keeps a table that fits the buffer: the inserts then run out of probes and flag it
+// again, and no access leaves the buffer.
+__global__ __launch_bounds__(kThreads) void k_hash_clear(Work w, int decide) {
     RoundState *st = w.st;
     const uint64_t K = st->s_keys;
     uint64_t slots = 2 * K + 1;
-    if (K > (uint64_t)kHashMaxRecords || slots > (uint64_t)w.kcap) {
-        if (decide) {
-            slots = 0;
-        } else {
-            atomicOr(&st->err, 4u);
-            slots = (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
-        }
+    const bool over = K > (uint64_t)kHashMaxRecords || slots > (uint64_t)w.kcap;
+    if (over) slots = decide ? 0 : (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->hash_slots = (int32_t)slots;
+        if (over && !decide) atomicOr(&st->err, 4u);
     }
-    st->hash_slots = (int32_t)slots;
-}
-
-__global__ __launch_bounds__(kThreads) void k_hash_clear(Work w) {
-    const int64_t slots = w.st->hash_slots;
     uint64_t *tab = hash_table(w);
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kThreads)
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < (int64_t)slots; i += (int64_t)gridDim.x * kThreads)
         tab[i] = kEmptySlot;
 }
 
@@ -764,11 +758,8 @@ hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, 
 
 hipError_t launch_hash_dedup(const Work &w, int grid, hipStream_t s, int stage, bool decide) {
     switch (stage) {
-        case 0:
-            hipLaunchKernelGGL(k_hash_plan, dim3(1), dim3(1), 0, s, w, (int)decide);
-            break;
         case 1:
-            hipLaunchKernelGGL(k_hash_clear, dim3(grid), dim3(kThreads), 0, s, w);
+            hipLaunchKernelGGL(k_hash_clear, dim3(grid), dim3(kThreads), 0, s, w, (int)decide);
             break;
         case 2:
             hipLaunchKernelGGL(k_hash_insert, dim3(grid), dim3(kSortThreads), 0, s, w);
