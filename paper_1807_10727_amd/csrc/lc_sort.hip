@@ -582,8 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_hash_clear(Work w, int decide) {
 }
 
 // Every key the relabel wrote (in its slabs) joins the set: linear probing from its home slot,
-// an empty slot claimed with a compare-and-swap, a repeat stopping at its own key.  A slot
-// changes only once (from empty), so a plain read that finds a key reads it right.
+// an empty slot claimed with a compare-and-swap, a repeat stopping at its own key.
 __global__ __launch_bounds__(kSortThreads) void k_hash_insert(Work w) {
     RoundState *st = w.st;
     const uint64_t slots = (uint64_t)st->hash_slots;
@@ -599,8 +598,8 @@ __global__ __launch_bounds__(kSortThreads) void k_hash_insert(Work w) {
             uint64_t h = home_slot(key, slots);
             bool placed = false;
             for (uint64_t probe = 0; probe < slots; ++probe) {
-                uint64_t cur = tab[h];
-                if (cur == kEmptySlot) cur = atomicCAS(&tab[h], (u64c)kEmptySlot, (u64c)key);
+                // the swap returns the slot's key whether or not it claims the slot
+                const uint64_t cur = atomicCAS(&tab[h], (u64c)kEmptySlot, (u64c)key);
                 if (cur == kEmptySlot || cur == key) {
                     placed = true;
                     break;
