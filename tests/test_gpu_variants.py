@@ -174,3 +174,29 @@ def test_finish_canonical_labels_unchanged(lc):
         with lc.Solver(g.n, s_t, d_t, seed=5, flags=lc.CC_CANONICAL, finish_edges=finish) as s:
             s.run()
             np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want)
+
+
+def test_hashed_rounds_launch_structure(lc):
+    """G(2^13, 2^17) plus 30 paths of 300 vertices (six rounds): every round after the first
+    holds at most half the input's records, so the host sends each to the hashed key set.  The radix kernels then run only in round 0
+    (one launch per 8-bit digit of its 2 ceil(log2 n)-bit keys), each later round launches the
+    five hashing kernels (clear, insert, count, the tile-count scan, write), and the result
+    equals the oracle's."""
+    g = graphgen.er_with_paths(15, 1 << 13, 1 << 17, 30, 300)
+    s_t, d_t = dev(g)
+    with lc.Solver(g.n, s_t, d_t, seed=5, flags=lc.CC_PROFILE | lc.CC_EAGER) as s:
+        r = s.run()
+        stats = s.stats(r)
+        times = s.kernel_times()
+        labels = s.labels().cpu().numpy().astype(np.uint32)
+    assert r >= 3
+    assert all(2 * st[2] + 1 <= g.m for st in stats[1:])
+    kb = int(np.ceil(np.log2(g.n)))
+    passes = (2 * kb + 7) // 8
+    assert times["sort_scatter"][1] == passes and times["sort_hist"][1] == passes
+    assert times["unique"][1] == 3                      # round 0's count, scan and write
+    assert times["hash_dedup"][1] == 5 * (r - 1)
+    want = oracle.run(g.n, g.src, g.dst, seed=5)
+    assert r == want.rounds
+    assert [tuple(x) for x in stats] == [tuple(x) for x in want.stats]
+    np.testing.assert_array_equal(labels, want.labels)
