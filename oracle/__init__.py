@@ -29,6 +29,11 @@ Parity status of its functions (what pins each one; the tests hold the pins):
   * ``run(finish_edges=T)`` -- union-find finish (Section 6): pinned by the per-round results
                         being those of the plain run up to the switch, and by labels equal to
                         the smallest name of each remaining component (recomputed with scipy).
+  * ``components_min_id`` -- textbook union-find (smallest id of each component): pinned to
+                        scipy's connected_components and to an independent Python union-find on
+                        random, power-law, path, edgeless and one-vertex graphs, with isolated
+                        ids at both ends, loops, repeats, and a merge order whose kept root is
+                        not the component's smallest id.
 """
 from __future__ import annotations
 

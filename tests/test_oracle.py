@@ -255,6 +255,58 @@ def test_partition_matches_union_find_and_scipy(kind):
     np.testing.assert_array_equal(want[res.labels.astype(np.int64)], want)
 
 
+@pytest.mark.parametrize("kind", ["gnm", "rmat", "paths", "sparse", "isolated_ends", "loops_repeats",
+                                  "no_edges", "one_vertex", "chain_merge"])
+def test_components_min_id_equals_library_components(kind):
+    """The oracle's union-find (`components_min_id`) against scipy's connected_components
+    (a library routine) and the textbook union-find of lcref: every vertex gets the
+    smallest id of its component.  Covers ids 0 and n-1 in singleton components, records
+    with loops and repeats, an edgeless graph, n = 1, and a merge order in which the root
+    union by size keeps is not the component's smallest id."""
+    if kind == "gnm":
+        g = graphgen.workload_small()
+    elif kind == "rmat":
+        g = graphgen.Graph(1 << 14, *graphgen.rmat(7, 14, 8 << 14))
+    elif kind == "paths":
+        g = graphgen.er_with_paths(11, 1 << 12, 1 << 12, 50, 200)
+    elif kind == "sparse":
+        g = graphgen.Graph(1 << 15, *graphgen.gnm(3, 1 << 15, 1 << 14))
+    elif kind == "isolated_ends":
+        # ids 0 and n-1 appear in no record; the rest form a few components
+        n = 1000
+        s, d = graphgen.gnm(5, n - 2, 600)
+        g = graphgen.Graph(n, s + np.uint32(1), d + np.uint32(1))
+    elif kind == "loops_repeats":
+        s, d = graphgen.gnm(9, 300, 500)
+        s = np.concatenate([s, s, np.arange(300, dtype=np.uint32)])
+        d = np.concatenate([d, d, np.arange(300, dtype=np.uint32)])
+        g = graphgen.Graph(300, s, d)
+    elif kind == "no_edges":
+        g = graphgen.Graph(17, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    elif kind == "one_vertex":
+        g = graphgen.Graph(1, np.zeros(1, np.uint32), np.zeros(1, np.uint32))
+    else:
+        # a large tree on high ids is built first, then a small one containing id 2 joins it:
+        # union by size keeps the large tree's root, which is not the component's minimum
+        hi = np.arange(50, 99, dtype=np.uint32)
+        s = np.concatenate([hi, np.array([2, 3], np.uint32)])
+        d = np.concatenate([hi + np.uint32(1), np.array([3, 60], np.uint32)])
+        g = graphgen.Graph(120, s, d)
+    got = oracle.components_min_id(g.n, g.src, g.dst).astype(np.int64)
+    want = canon(scipy_components(g.n, g.src, g.dst)) if g.n else np.zeros(0, np.int64)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(got, canon(union_find(g.n, g.src, g.dst)))
+    # every value is the smallest member of its class, and classes are closed under records
+    assert np.all(got <= np.arange(g.n))
+    assert np.all(got[got] == got)
+    np.testing.assert_array_equal(got[g.src.astype(np.int64)], got[g.dst.astype(np.int64)])
+
+
+def test_components_min_id_rejects_out_of_range_ids():
+    with pytest.raises(ValueError):
+        oracle.components_min_id(4, np.array([0, 4], np.uint32), np.array([1, 2], np.uint32))
+
+
 def test_per_phase_definition_and_invariants():
     """Replays the phases independently: each recorded parent must be the argmin of the
     priority over the closed two-hop ball (sparse (A+I)^2), rho(p(x)) <= rho(x) (proof of the
