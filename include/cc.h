@@ -96,7 +96,9 @@ enum {
     CC_ROUND0_TILED = 1u << 3,  /* round 0 over the tiled record layout */
     CC_EAGER = 1u << 4,         /* cc_run enqueues every round on its own (no captured tail) */
     CC_TREE = 1u << 5,          /* TreeContraction phases (see below) */
-    CC_ONE_HOP = 1u << 6        /* one-hop labels (see below) */
+    CC_ONE_HOP = 1u << 6,       /* one-hop labels (see below) */
+    CC_EXPLICIT_PRIO = 1u << 7, /* priorities from caller tables (cc_set_explicit_priorities) */
+    CC_RECORD_ROUNDS = 1u << 8  /* keep every round's parents (cc_round_parents of any round) */
 };
 
 /* Label rule of a phase.  Default: LocalContraction (Section 3), the vertex of smallest
@@ -123,7 +125,7 @@ typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
     int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
     uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED | CC_EAGER |
-                            CC_TREE | CC_ONE_HOP */
+                            CC_TREE | CC_ONE_HOP | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS */
     void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
 } cc_options;
 
@@ -192,12 +194,63 @@ cc_status cc_run(cc_ctx *ctx, int32_t *rounds);
 cc_status cc_labels(cc_ctx *ctx, void *d_labels);
 
 /*
- * Parents of the most recent round (test and inspection aid, not on the
- * measured path): d_parents (int32[n_vertices]) receives, for every name x
- * that was a node of that round, the name of its parent, and -1 for every
- * other name.  *n_nodes (nullable, host) receives the node count.  Synchronises.
+ * Parents of round r (Section 3: the vertex of smallest priority in N(N(x)) of every node x),
+ * a test and inspection aid, not on the measured path.  d_parents (int32[n_vertices])
+ * receives, for every name x that was a node of round r, the name of its parent, and -1 for
+ * every other name.  *n_nodes (nullable, host) receives the round's node count.
+ * Synchronises.  r < 0 means the most recent round, which is always available unless it ran
+ * inside a captured tail or the union-find finish ended the solve.  Earlier rounds need
+ * CC_RECORD_ROUNDS: the context then copies every round's parents into a record area of the
+ * workspace (4 bytes per vertex for round 0, 8 bytes per node for later rounds, at most 20
+ * bytes per vertex in all; cc_workspace_size grows by that much) and runs every round
+ * eagerly.  CC_E_STATE for a round that has not run, was not recorded (no CC_RECORD_ROUNDS,
+ * or the record area was full), or is unavailable as above; CC_E_ARG for a null pointer.
  */
-cc_status cc_round_parents(cc_ctx *ctx, int32_t *d_parents, int64_t *n_nodes);
+cc_status cc_round_parents(cc_ctx *ctx, int32_t r, int32_t *d_parents, int64_t *n_nodes);
+
+/*
+ * One-hop and two-hop minima of the most recent round (test and inspection aid, not on the
+ * measured path): for every name x that was a node of that round, d_m1[x] = the smallest
+ * priority in the closed neighbourhood N(x) and d_l[x] = the smallest priority in N(N(x))
+ * (Section 3: the parent is the vertex with that priority; Section 2: N(x) contains x), and
+ * 0xFFFFFFFF for every other name (both uint32[n_vertices], device).  After a round 0 that
+ * ran over the tiled layout the two-hop minimum is not kept, and d_l[x] is then the priority
+ * of x's parent, which equals it by definition.  LocalContraction only: CC_E_STATE with
+ * CC_TREE or CC_ONE_HOP, before the first round, after a round inside a captured tail, or
+ * after the union-find finish.  Synchronises.
+ */
+cc_status cc_debug_round_arrays(cc_ctx *ctx, uint32_t *d_m1, uint32_t *d_l);
+
+/*
+ * Explicit priorities (needs CC_EXPLICIT_PRIO at cc_create).  A test hook for the
+ * definition's "any ordering" (Section 3: rho is a random ordering of the nodes): from round
+ * r on, until a later round has a table of its own, the priority of node name x is d_prio[x]
+ * instead of the seeded hash; rounds before the first table use the hash.  d_prio is
+ * uint32[n_vertices], device memory borrowed until cc_destroy or a replacing call for the
+ * same r, and must be a permutation of 0 .. n_vertices-1 (an ordering of all names; the
+ * parent is found through its inverse, which the library builds in the workspace: 4 bytes
+ * per vertex more).  A table that is not a permutation makes the round that first uses it
+ * fail with CC_E_INPUT.  With CC_EXPLICIT_PRIO round 0 reads the records directly
+ * (CC_ROUND0_TILED is CC_E_ARG) and cc_run runs every round eagerly.  CC_E_STATE without
+ * CC_EXPLICIT_PRIO; CC_E_ARG for r < 0 or a null table.
+ */
+cc_status cc_set_explicit_priorities(cc_ctx *ctx, int32_t r, const uint32_t *d_prio);
+
+/*
+ * Round checkpoint in host memory.  Between rounds a solve is its current edge set, the
+ * names of its nodes and the per-round maps that compose the labels (Section 3: a phase reads
+ * only the graph the previous one left).  cc_save_state writes that state and the statistics
+ * so far into h_buf (host); with h_buf NULL it only sets *bytes to the size needed, and a
+ * *bytes smaller than that is CC_E_ARG.  cc_load_state restores it into a context created for
+ * the same graph (same n_vertices, n_edges, layout and label rule; CC_E_ARG otherwise, and for
+ * a buffer that is not a checkpoint) that has its workspace; cc_run or cc_contract_round then
+ * continue with the next round, and every later round, the statistics and the labels equal
+ * those of the uninterrupted solve.  Explicit priority tables and recorded parents are not
+ * part of a checkpoint (set the tables again after loading).  Both synchronise.  CC_E_NOMEM
+ * without a workspace; CC_E_STATE on a context whose solve has failed.
+ */
+cc_status cc_save_state(cc_ctx *ctx, void *h_buf, size_t *bytes);
+cc_status cc_load_state(cc_ctx *ctx, const void *h_buf, size_t bytes);
 
 /*
  * Edges of the graph the most recent round left (test and inspection aid, not on the

@@ -90,6 +90,8 @@ def _load():
         lib.lco_run_variant.restype = ctypes.c_int32
         lib.lco_run_variant.argtypes = lib.lco_run.argtypes + [ctypes.c_int32, ctypes.c_int64,
                                                                ctypes.POINTER(ctypes.c_int32)]
+        lib.lco_run_full.restype = ctypes.c_int32
+        lib.lco_run_full.argtypes = lib.lco_run_variant.argtypes + [u32p, u32p, ctypes.c_int32]
         lib.lco_run_batch.restype = ctypes.c_int32
         lib.lco_run_batch.argtypes = [ctypes.c_int64, i64p, i64p, u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p,
                                       ctypes.POINTER(ctypes.c_int32), u32p, ctypes.c_int32]
@@ -129,11 +131,13 @@ class Result:
     stats: list = field(default_factory=list)   # tuples (round, n_active, m_in, m_survive, m_out, n_finalised)
     parents: np.ndarray | None = None  # uint32 [min(rounds, cap), n0], NOT_A_NODE off V_r
     finished: bool = False             # the union-find finish ran
+    m1: np.ndarray | None = None       # uint32 [min(rounds, cap), n0] one-hop minima, 0xFFFFFFFF off V_r
+    l: np.ndarray | None = None        # uint32 [min(rounds, cap), n0] two-hop minima
 
 
 def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0,
         record_parents: bool = False, parents_cap: int = 64, stats_cap: int = 256, variant: str = "local",
-        finish_edges: int = 0) -> Result:
+        finish_edges: int = 0, record_minima: bool = False, minima_cap: int = 16) -> Result:
     """Run the oracle.  `explicit_prio` is an optional [rows, n] table of priorities (phase r
     uses row min(r, rows-1)).  `variant`: "local" (LocalContraction), "tree"
     (TreeContraction) or "one_hop"; `finish_edges` > 0 finishes with union-find once a phase
@@ -152,16 +156,22 @@ def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0
         assert ep.shape[1] == n
         rows = ep.shape[0]
     fin = ctypes.c_int32(0)
-    r = lib.lco_run_variant(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
-                            _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats,
-                            stats_cap, _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0,
-                            VARIANTS[variant], int(finish_edges), ctypes.byref(fin))
+    m1 = np.empty((minima_cap, max(n, 1)), dtype=np.uint32) if record_minima else None
+    l2 = np.empty((minima_cap, max(n, 1)), dtype=np.uint32) if record_minima else None
+    r = lib.lco_run_full(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
+                         _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats,
+                         stats_cap, _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0,
+                         VARIANTS[variant], int(finish_edges), ctypes.byref(fin), _ptr(m1, ctypes.c_uint32),
+                         _ptr(l2, ctypes.c_uint32), minima_cap if record_minima else 0)
     if r < 0:
         raise ValueError("oracle rejected the input (ids out of range or out of memory)")
     res = Result(labels[:n], int(r), [stats[i].as_tuple() for i in range(min(r, stats_cap))],
                  finished=bool(fin.value))
     if record_parents:
         res.parents = par[:min(r, parents_cap), :n]
+    if record_minima:
+        res.m1 = m1[:min(r, minima_cap), :n]
+        res.l = l2[:min(r, minima_cap), :n]
     return res
 
 

@@ -141,12 +141,17 @@ static void uf_union(uint32_t *up, uint32_t a, uint32_t b) {
  *   finish_edges   0, or: before every phase after the first, if at most this
  *                  many edges are left, finish with union-find instead.
  *   finished       out (may be NULL): 1 when the finish ran.
+ *   m1_rows, l_rows  out (may be NULL): [minima_cap][n0] one-hop and two-hop
+ *                  minimum priorities of every node of each phase (not for
+ *                  TreeContraction; the one-hop label's two-hop row repeats the
+ *                  one-hop row), 0xFFFFFFFF for names that are not nodes.
  * Returns the number of phases run, or -1 on bad input / out of memory.
  */
-int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
-                        const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
-                        uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
-                        int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished) {
+int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
+                     const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
+                     uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
+                     int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished,
+                     uint32_t *m1_rows, uint32_t *l_rows, int32_t minima_cap) {
     if (variant < LCO_LOCAL || variant > LCO_ONE_HOP) return -1;
     if (finished) *finished = 0;
     if (n0 < 0 || m0 < 0 || n0 > 0xFFFFFFFFLL) return -1;
@@ -266,6 +271,16 @@ int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint3
         }
         /* l_arg[x] is now the label vertex (parent) of node x */
 
+        /* optional: the one-hop and two-hop minimum priorities of every node (the values
+           whose argmin the labels are), 0xFFFFFFFF for names that are not nodes */
+        if (m1_rows && l_rows && variant != LCO_TREE && r < minima_cap) {
+            uint32_t *row1 = m1_rows + (int64_t)r * n0, *row2 = l_rows + (int64_t)r * n0;
+            for (int64_t x = 0; x < n0; ++x) {
+                row1[x] = in_v[x] ? m1_val[x] : 0xFFFFFFFFu;
+                row2[x] = in_v[x] ? l_val[x] : 0xFFFFFFFFu;
+            }
+        }
+
         if (parents && r < parents_cap) {
             uint32_t *row = parents + (int64_t)r * n0;
             for (int64_t x = 0; x < n0; ++x) row[x] = in_v[x] ? l_arg[x] : 0xFFFFFFFFu;
@@ -329,6 +344,14 @@ int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint3
     free(E); free(E2); free(in_v); free(is_label); free(in_next);
     free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg); free(up);
     return r;
+}
+
+int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,
+                        const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
+                        uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
+                        int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished) {
+    return lco_run_full(n0, m0, src, dst, seed, explicit_prio, prio_rows, max_rounds, labels, stats, stats_cap,
+                        parents, parents_cap, variant, finish_edges, finished, NULL, NULL, 0);
 }
 
 int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,

@@ -17,13 +17,16 @@ from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_bat
 from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
-                  CC_EAGER, CC_ONE_HOP, CC_PROFILE, CC_ROUND0_DIRECT, CC_ROUND0_TILED, CC_TREE, CCError,
+                  CC_EAGER, CC_EXPLICIT_PRIO, CC_ONE_HOP, CC_PROFILE, CC_RECORD_ROUNDS, CC_ROUND0_DIRECT,
+                  CC_ROUND0_TILED, CC_TREE, CCError, cc_debug_round_arrays, cc_load_state, cc_save_state,
+                  cc_set_explicit_priorities,
                   cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
                   cc_labels, cc_last_error, cc_reset, cc_round_edges, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
 
-__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_ONE_HOP", "CC_PROFILE",
-           "CC_ROUND0_DIRECT", "CC_ROUND0_TILED", "CC_TREE", "cc_version"]
+__all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_EXPLICIT_PRIO",
+           "CC_ONE_HOP", "CC_PROFILE", "CC_RECORD_ROUNDS", "CC_ROUND0_DIRECT", "CC_ROUND0_TILED", "CC_TREE",
+           "cc_version"]
 
 
 def _torch():
@@ -94,12 +97,37 @@ class Solver:
         cc_labels(self.ctx, out.data_ptr() if self.n else 1)
         return out
 
-    def parents(self):
-        """Parents of the last round, by name (-1 for names that were not nodes)."""
+    def parents(self, r: int = -1):
+        """Parents of round r (default: the most recent one), by name (-1 for names that were
+        not nodes), and the round's node count.  Earlier rounds need CC_RECORD_ROUNDS."""
         torch = _torch()
         out = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
-        k = cc_round_parents(self.ctx, out.data_ptr())
+        k = cc_round_parents(self.ctx, r, out.data_ptr())
         return out[:self.n], k
+
+    def minima(self):
+        """One-hop and two-hop minima of the most recent round by name (uint32 values in
+        int32 tensors; -1 = 0xFFFFFFFF for names that were not nodes)."""
+        torch = _torch()
+        m1 = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        l2 = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        cc_debug_round_arrays(self.ctx, m1.data_ptr(), l2.data_ptr())
+        return m1[:self.n], l2[:self.n]
+
+    def set_priorities(self, r: int, table) -> None:
+        """Explicit priorities from round r on (CC_EXPLICIT_PRIO): an int32 device tensor of
+        n values, a permutation of 0 .. n-1, kept referenced while the context lives."""
+        if not table.is_cuda or table.numel() < self.n or not table.is_contiguous():
+            raise ValueError("the table must be a contiguous device tensor of n entries")
+        self._tables = getattr(self, "_tables", {})
+        self._tables[int(r)] = table
+        cc_set_explicit_priorities(self.ctx, r, table.data_ptr())
+
+    def save_state(self) -> bytes:
+        return cc_save_state(self.ctx)
+
+    def load_state(self, data: bytes) -> None:
+        cc_load_state(self.ctx, data)
 
     def edges(self):
         """Edges of the graph the last round left, by name: an int64 tensor of
@@ -166,7 +194,7 @@ class Batch:
     [edge_off[g], edge_off[g+1]); seeds[g] is its priority seed.  Labels come back as one
     int32 tensor with graph g's labels at [vtx_off[g], vtx_off[g+1])."""
 
-    def __init__(self, vtx_off, edge_off, seeds, src, dst, stream=None, **config):
+    def __init__(self, vtx_off, edge_off, seeds, src, dst, stream=None, ws_fill=None, **config):
         torch = _torch()
         import numpy as np
         self.voff = np.ascontiguousarray(vtx_off, dtype=np.int64)
@@ -182,6 +210,8 @@ class Batch:
                                  stream=self.stream.cuda_stream)
         self.ws_bytes = cc_batch_workspace_size(self.b)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        if ws_fill is not None:   # a workspace that starts with these bytes (tests)
+            self.ws.fill_(int(ws_fill))
         cc_batch_set_workspace(self.b, self.ws.data_ptr(), self.ws_bytes)
         if config:
             cc_batch_set_config(self.b, **config)

@@ -30,6 +30,8 @@ CC_ROUND0_TILED = 1 << 3
 CC_EAGER = 1 << 4
 CC_TREE = 1 << 5
 CC_ONE_HOP = 1 << 6
+CC_EXPLICIT_PRIO = 1 << 7
+CC_RECORD_ROUNDS = 1 << 8
 
 
 class cc_graph_desc(ctypes.Structure):
@@ -93,7 +95,11 @@ _sig = {
     "cc_contract_round": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_round_stats)]),
     "cc_run": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32)]),
     "cc_labels": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p]),
-    "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "cc_debug_round_arrays": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cc_set_explicit_priorities": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cc_save_state": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cc_load_state": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_size_t]),
     "cc_round_edges": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     "cc_get_round_stats": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.POINTER(cc_round_stats)]),
     "cc_kernel_family_count": (ctypes.c_int32, []),
@@ -193,10 +199,36 @@ def cc_labels(ctx, ptr: int) -> None:
     _check(ctx, _lib.cc_labels(ctx, ptr))
 
 
-def cc_round_parents(ctx, ptr: int) -> int:
+def cc_round_parents(ctx, r: int, ptr: int) -> int:
+    """Parents of round r (r < 0: the most recent one) by name into the device buffer at ptr
+    (int32[n_vertices]); returns the round's node count."""
     n = ctypes.c_int64()
-    _check(ctx, _lib.cc_round_parents(ctx, ptr, ctypes.byref(n)))
+    _check(ctx, _lib.cc_round_parents(ctx, int(r), ptr, ctypes.byref(n)))
     return int(n.value)
+
+
+def cc_debug_round_arrays(ctx, m1_ptr: int, l_ptr: int) -> None:
+    """One-hop and two-hop minima of the most recent round by name (uint32[n_vertices] each)."""
+    _check(ctx, _lib.cc_debug_round_arrays(ctx, m1_ptr, l_ptr))
+
+
+def cc_set_explicit_priorities(ctx, r: int, ptr: int) -> None:
+    """Round r and later use the priority table at ptr (uint32[n_vertices], a permutation)."""
+    _check(ctx, _lib.cc_set_explicit_priorities(ctx, int(r), ptr))
+
+
+def cc_save_state(ctx) -> bytes:
+    """The context's round checkpoint as bytes (two calls: size, then the copy)."""
+    n = ctypes.c_size_t(0)
+    _check(ctx, _lib.cc_save_state(ctx, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(ctx, _lib.cc_save_state(ctx, buf, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def cc_load_state(ctx, data: bytes) -> None:
+    buf = ctypes.create_string_buffer(data, len(data))
+    _check(ctx, _lib.cc_load_state(ctx, buf, len(data)))
 
 
 def cc_round_edges(ctx, ptr: int, cap: int) -> int:

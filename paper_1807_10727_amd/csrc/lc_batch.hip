@@ -76,31 +76,20 @@ __global__ __launch_bounds__(kThreads) void k_globalize(const int32_t *src, cons
     if (bad) atomicOr(err, 1u);
 }
 
-__global__ void k_state_init(RoundState *st, int64_t n0, int64_t m0, int64_t map_cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+// The whole state is cleared first (the workspace arrives with arbitrary bytes, and every
+// field must start where the plain solve's zero-filled upload starts it), then the counts of
+// the union graph are set.  A kernel rather than a memset: it is captured into the batch's
+// graph, which records no memset nodes.
+__global__ __launch_bounds__(kThreads) void k_state_init(RoundState *st, int64_t n0, int64_t m0, int64_t map_cap) {
+    static_assert(sizeof(RoundState) % 8 == 0, "state cleared in 8-byte words");
+    uint64_t *words = (uint64_t *)st;
+    for (size_t i = threadIdx.x; i < sizeof(RoundState) / 8; i += kThreads) words[i] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
         st->n_cur = (u64c)n0;
         st->m_cur = (u64c)m0;
-        st->n_prev = 0;
-        st->aux_n = 0;
-        st->map_off = 0;
         st->map_cap = (u64c)map_cap;
-        st->n_slabs = 0;
-        st->round = 0;
-        st->nbits = 0;
-        st->kb = 0;
-        st->hb_shift = 0;
-        st->e_sel = 0;
-        st->hash_slots = 0;   // read by every round end
         st->done = m0 == 0 ? 1 : 0;
-        st->levels = 0;
-        st->n_active = 0;
-        st->s_count = 0;
-        st->s_keys = 0;
-        st->n_final = 0;
-        st->n_labels = 0;
-        st->err = 0;
-        st->m_next = 0;
-        st->n_next = 0;
     }
 }
 
@@ -280,7 +269,7 @@ cc_status plan(cc_batch *b) {
 bool enqueue_prologue(cc_batch *b, int32_t *labels) {
     hipStream_t s = b->stream;
     const int64_t n0 = b->w.n0;
-    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, b->w.st, n0, b->union_m, std::max<int64_t>(n0, 1));
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(kThreads), 0, s, b->w.st, n0, b->union_m, std::max<int64_t>(n0, 1));
     if (!batch_hip(b, hipGetLastError(), "state init")) return false;
     hipLaunchKernelGGL(k_fill_i32, dim3(b->grid_for(b->G)), dim3(kThreads), 0, s, b->d_rounds, 0, (int64_t)b->G);
     if (!batch_hip(b, hipGetLastError(), "round counters")) return false;

@@ -37,7 +37,7 @@ bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags) {
     return n0 >= kTiledMinVertices && m0 >= kTiledMinVertices;
 }
 
-size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w) {
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w, uint32_t extras) {
     const size_t n = (size_t)std::max<int64_t>(n0, 1);
     const size_t m = (size_t)std::max<int64_t>(m0, 2);
     // records a key buffer holds: the tiled round 0 keeps two directed records per input
@@ -85,6 +85,11 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     t.tile_cnt = (uint32_t *)take(4 * tiles + 64);
     t.slab_cnt = (uint32_t *)take(4 * slabs + 64);
     t.partials = (uint32_t *)take(4 * parts);
+    if (extras & kWsExplicit) t.pinv = (uint32_t *)take(4 * n);
+    if (extras & kWsRecord) {
+        t.rec_cap = kRecordPerVertex * (int64_t)n;
+        t.rec = (uint32_t *)take(4 * (size_t)t.rec_cap);
+    }
     t.n0 = n0;
     t.m0 = m0;
     if (w) *w = t;
@@ -173,7 +178,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const bool small_sort = scan_entries <= kSmallScanEntries;
     const bool small_flags = N <= kSmallFlagNodes;
 
-    RUN(kRoundBegin, launch_round_begin(w, !first && !batch && variant != kVarTree, r, gn, stream));
+    RUN(kRoundBegin, launch_round_begin(w, !first && !batch && variant != kVarTree, r, gn, stream, pc.tab));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
     if (first && tiled) {
         const int ga = (int)std::min<int64_t>(tp.tiles_a, grid_cap);
@@ -313,6 +318,10 @@ cc_status hip_status(cc_ctx *c) { return c->failed_status ? c->failed_status : C
 
 namespace {
 
+uint32_t ws_extras(uint32_t flags) {
+    return ((flags & CC_EXPLICIT_PRIO) ? (uint32_t)kWsExplicit : 0u) | ((flags & CC_RECORD_ROUNDS) ? (uint32_t)kWsRecord : 0u);
+}
+
 cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     c->o.seed = seed;
     c->stats.clear();
@@ -329,6 +338,9 @@ cc_status reset_solve(cc_ctx *c, uint64_t seed) {
     c->finished = false;
     c->failed_status = 0;
     c->err.clear();
+    c->recs.clear();
+    c->rec_used = 0;
+    c->inv_for = nullptr;
     for (int i = 0; i < kFamilies; ++i) {
         c->fam_ms[i] = 0.0;
         c->fam_launches[i] = 0;
@@ -340,6 +352,18 @@ cc_status reset_solve(cc_ctx *c, uint64_t seed) {
 }  // namespace
 
 namespace lc {
+
+// The explicit priority table of round r: the one set for the latest round <= r (null: hash).
+const uint32_t *table_for(const cc_ctx *c, int32_t r) {
+    const uint32_t *t = nullptr;
+    int32_t best = -1;
+    for (const auto &e : c->prio_tabs)
+        if (e.first <= r && e.first > best) {
+            best = e.first;
+            t = e.second;
+        }
+    return t;
+}
 
 // Enqueue round `next_round` and the asynchronous readback of the device state (no wait).
 // *launched is 0 when nothing was enqueued (solve finished, or an error was returned).
@@ -356,7 +380,29 @@ cc_status ctx_round_enqueue(cc_ctx *c, int *launched) {
     }
     PrioCtx pc{};
     pc.key = round_key(c->o.seed, r);
+    pc.tab = table_for(c, r);
+    if (pc.tab) {
+        pc.inv = c->w.pinv;
+        if (c->inv_for != pc.tab) {   // a new table: build (and check) its inverse first
+            if (!c->hip_ok(launch_prio_inverse(c->w, pc.tab, c->grid_for(c->g.n_vertices), c->stream),
+                           "priority inverse"))
+                return hip_status(c);
+            c->inv_for = pc.tab;
+        }
+    }
     if (!c->enqueue_round(r, N, M, pc)) return hip_status(c);
+    if (c->w.rec) {   // CC_RECORD_ROUNDS: copy the parents before the next round overwrites them
+        const int64_t count = r == 0 ? c->g.n_vertices : N;
+        const int64_t need = r == 0 ? count : 2 * count;
+        if ((int64_t)c->recs.size() <= r) c->recs.resize((size_t)r + 1, cc_ctx::Rec{-1, 0});
+        if (c->rec_used + need <= c->w.rec_cap) {
+            if (!c->hip_ok(launch_record_parents(c->w, r, c->w.rec + c->rec_used, c->grid_for(count), c->stream),
+                           "record parents"))
+                return hip_status(c);
+            c->recs[r] = cc_ctx::Rec{c->rec_used, count};
+            c->rec_used += need;
+        }
+    }
     if (!c->hip_ok(hipMemcpyAsync(c->h_st, c->w.st, sizeof(RoundState), hipMemcpyDeviceToHost, c->stream),
                    "state readback"))
         return hip_status(c);
@@ -373,6 +419,7 @@ cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out) {
     const int r = c->next_round;
     const int64_t N = c->pending_N, M = c->pending_M;
     if (st.err & 1u) return fail(c, CC_E_INPUT, "an edge record names a vertex outside [0, n_vertices)");
+    if (st.err & 8u) return fail(c, CC_E_INPUT, "an explicit priority table is not a permutation of [0, n_vertices)");
     if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
     if (r == 0) c->ran_first = true;
     if (r > 0) {
@@ -442,7 +489,8 @@ void drop_tails(cc_ctx *c) {
 // A capture costs far more than a few small rounds: a context captures only once it has
 // finished an earlier solve, i.e. when it is being reused.
 bool tail_wanted(const cc_ctx *c) {
-    return !(c->o.flags & CC_EAGER) && c->o.max_rounds == 0 && c->finish_edges == 0 && c->solves_done > 0 &&
+    return !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS)) && c->o.max_rounds == 0 &&
+           c->finish_edges == 0 && c->solves_done > 0 &&
            c->next_round >= 1 &&
            !c->done && c->m_cur > 0 && c->m_cur <= kTailMaxRecords;
 }
@@ -590,6 +638,7 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if ((opts->flags & CC_ROUND0_DIRECT) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     if ((opts->flags & CC_ROUND0_TILED) && g.n_vertices > 0 && !tiled_fits(g.n_vertices)) return CC_E_ARG;
     if ((opts->flags & CC_TREE) && (opts->flags & CC_ONE_HOP)) return CC_E_ARG;
+    if ((opts->flags & CC_EXPLICIT_PRIO) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
     cc_ctx *c = new (std::nothrow) cc_ctx();
     if (!c) return CC_E_NOMEM;
     c->g = g;
@@ -617,10 +666,10 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
             return CC_E_NOMEM;
         }
     }
-    c->tiled = choose_tiled(g.n_vertices, g.n_edges, opts->flags);
+    c->tiled = !(opts->flags & CC_EXPLICIT_PRIO) && choose_tiled(g.n_vertices, g.n_edges, opts->flags);
     c->variant = (opts->flags & CC_TREE) ? kVarTree : (opts->flags & CC_ONE_HOP) ? kVarOneHop : kVarLocal;
     c->tp = tiled_plan(g.n_vertices, g.n_edges);
-    c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, c->tiled, nullptr, nullptr);
+    c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, c->tiled, nullptr, nullptr, ws_extras(opts->flags));
     *out = c;
     return CC_OK;
 }
@@ -637,7 +686,7 @@ cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
     if ((uintptr_t)d_ws % 256 != 0) return reject(c, CC_E_ARG, "workspace must be 256-byte aligned");
     c->ws = d_ws;
     c->ws_bytes = bytes;
-    plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)d_ws, &c->w);
+    plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)d_ws, &c->w, ws_extras(c->o.flags));
     return reset_solve(c, c->o.seed);
 }
 
@@ -676,18 +725,60 @@ cc_status cc_labels(cc_ctx *c, void *d_labels) {
     return ctx_labels_enqueue(c, d_labels);
 }
 
-cc_status cc_round_parents(cc_ctx *c, int32_t *d_parents, int64_t *n_nodes) {
+cc_status cc_round_parents(cc_ctx *c, int32_t r, int32_t *d_parents, int64_t *n_nodes) {
     if (!c || !d_parents) return CC_E_ARG;
     if (c->failed_status) return c->failed_status;
+    if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
+    const int last = c->next_round - 1;
+    if (r < 0) r = last;
+    if (r > last) return reject(c, CC_E_STATE, "that round has not run");
+    const int grid = c->grid_for(c->g.n_vertices);
+    hipError_t e;
+    if (r < (int)c->recs.size() && c->recs[r].off >= 0) {   // recorded (CC_RECORD_ROUNDS)
+        e = launch_expand_record(c->w, r, c->w.rec + c->recs[r].off, c->recs[r].count, d_parents, grid, c->stream);
+    } else {
+        if (r != last) return reject(c, CC_E_STATE, "only the most recent round is kept (use CC_RECORD_ROUNDS)");
+        if (last == c->last_graph_round)
+            return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
+        if (c->finished) return reject(c, CC_E_STATE, "the solve ended with the union-find finish");
+        e = launch_dump_parents(c->w, d_parents, last, grid, c->stream);
+    }
+    if (!c->hip_ok(e, "dump parents")) return CC_E_HIP;
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
+    if (n_nodes) *n_nodes = r < (int)c->stats.size() ? c->stats[r].n_active : 0;
+    return CC_OK;
+}
+
+cc_status cc_debug_round_arrays(cc_ctx *c, uint32_t *d_m1, uint32_t *d_l) {
+    if (!c || !d_m1 || !d_l) return CC_E_ARG;
+    if (c->failed_status) return c->failed_status;
+    if (c->variant != kVarLocal) return reject(c, CC_E_STATE, "the minima are kept for LocalContraction only");
     if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
     const int last = c->next_round - 1;
     if (last == c->last_graph_round)
         return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
     if (c->finished) return reject(c, CC_E_STATE, "the solve ended with the union-find finish");
-    hipError_t e = launch_dump_parents(c->w, d_parents, last, c->grid_for(c->g.n_vertices), c->stream);
-    if (!c->hip_ok(e, "dump parents")) return CC_E_HIP;
+    PrioCtx pc{};
+    pc.tab = table_for(c, last);
+    pc.inv = c->w.pinv;
+    hipError_t e = launch_dump_minima(c->w, last, last == 0 && c->tiled, pc, d_m1, d_l, c->grid_for(c->g.n_vertices),
+                                      c->stream);
+    if (!c->hip_ok(e, "dump minima")) return CC_E_HIP;
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
-    if (n_nodes) *n_nodes = last < (int)c->stats.size() ? c->stats[last].n_active : 0;
+    return CC_OK;
+}
+
+cc_status cc_set_explicit_priorities(cc_ctx *c, int32_t r, const uint32_t *d_prio) {
+    if (!c || r < 0 || !d_prio) return CC_E_ARG;
+    if (!(c->o.flags & CC_EXPLICIT_PRIO)) return reject(c, CC_E_STATE, "the context was created without CC_EXPLICIT_PRIO");
+    bool replaced = false;
+    for (auto &e : c->prio_tabs)
+        if (e.first == r) {
+            e.second = d_prio;
+            replaced = true;
+        }
+    if (!replaced) c->prio_tabs.push_back({r, d_prio});
+    c->inv_for = nullptr;   // the next round rebuilds the inverse of its table
     return CC_OK;
 }
 
@@ -741,6 +832,187 @@ cc_status cc_kernel_times(const cc_ctx *c, double *ms, int64_t *launches, int32_
     for (int i = 0; i < kFamilies && i < cap; ++i) {
         if (ms) ms[i] = c->fam_ms[i];
         if (launches) launches[i] = c->fam_launches[i];
+    }
+    return CC_OK;
+}
+
+// ---- round checkpoints --------------------------------------------------------------------
+//
+// Layout: CkptHeader, then the statistics so far, the device round state, the current edge
+// records (8 bytes each, in the buffer the state names), the names of the current nodes, the
+// name -> index array, map0 and the used part of the map arena.  Between rounds nothing else
+// on the device is read by a later round.
+
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x31304B43504B434CULL;   // "LCKPCK01"
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version, rule;   // rule: CC_TREE | CC_ONE_HOP bits of the context
+    int64_t n0, m0;
+    int32_t layout, next_round, rounds, ran_first;
+    int32_t done, host_levels, finished, n_stats;
+    int64_t host_map_used, n_cur, m_cur, map_used;
+    uint64_t seed;
+    int32_t e_sel, state_bytes;
+    int64_t total_bytes;
+};
+
+struct CkptSizes {
+    size_t stats, state, edges, names, idx, map0, maps, total;
+};
+
+CkptSizes ckpt_sizes(int64_t n0, int n_stats, int64_t m_cur, int64_t n_cur, int64_t map_used) {
+    CkptSizes z{};
+    z.stats = sizeof(cc_round_stats) * (size_t)n_stats;
+    z.state = sizeof(RoundState);
+    z.edges = 8 * (size_t)m_cur;
+    z.names = 4 * (size_t)n_cur;
+    z.idx = 4 * (size_t)n0;
+    z.map0 = 4 * (size_t)n0;
+    z.maps = 4 * (size_t)map_used;
+    z.total = sizeof(CkptHeader) + z.stats + z.state + z.edges + z.names + z.idx + z.map0 + z.maps;
+    return z;
+}
+
+uint32_t rule_bits(uint32_t flags) { return flags & (CC_TREE | CC_ONE_HOP); }
+
+}  // namespace
+
+cc_status cc_save_state(cc_ctx *c, void *h_buf, size_t *bytes) {
+    if (!c || !bytes) return CC_E_ARG;
+    if (c->failed_status) return reject(c, CC_E_STATE, "the solve has failed");
+    if (!c->ws) return reject(c, CC_E_NOMEM, "no workspace: call cc_set_workspace first");
+    RoundState st;
+    if (!c->hip_ok(hipMemcpyAsync(&st, c->w.st, sizeof st, hipMemcpyDeviceToHost, c->stream), "state readback") ||
+        !c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize"))
+        return CC_E_HIP;
+    const int64_t n0 = c->g.n_vertices;
+    const int64_t m_cur = c->next_round == 0 ? 0 : (int64_t)st.m_cur;
+    const int64_t n_cur = c->next_round == 0 ? 0 : (int64_t)st.n_cur;
+    const int64_t map_used = (int64_t)st.map_off;
+    const CkptSizes z = ckpt_sizes(n0, (int)c->stats.size(), m_cur, n_cur, map_used);
+    if (!h_buf) {
+        *bytes = z.total;
+        return CC_OK;
+    }
+    if (*bytes < z.total) return reject(c, CC_E_ARG, "checkpoint buffer smaller than the size cc_save_state reports");
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.version = kCkptVersion;
+    h.rule = rule_bits(c->o.flags);
+    h.n0 = n0;
+    h.m0 = c->g.n_edges;
+    h.layout = c->g.layout;
+    h.next_round = c->next_round;
+    h.rounds = c->rounds;
+    h.ran_first = c->ran_first ? 1 : 0;
+    h.done = c->done ? 1 : 0;
+    h.host_levels = c->host_levels;
+    h.finished = c->finished ? 1 : 0;
+    h.n_stats = (int32_t)c->stats.size();
+    h.host_map_used = c->host_map_used;
+    h.n_cur = c->n_cur;
+    h.m_cur = c->m_cur;
+    h.map_used = map_used;
+    h.seed = c->o.seed;
+    h.e_sel = st.e_sel;
+    h.state_bytes = (int32_t)sizeof(RoundState);
+    h.total_bytes = (int64_t)z.total;
+    char *p = (char *)h_buf;
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    if (z.stats) memcpy(p, c->stats.data(), z.stats);
+    p += z.stats;
+    memcpy(p, &st, z.state);
+    p += z.state;
+    struct Piece {
+        const void *src;
+        size_t n;
+    } pieces[] = {{c->w.keys[st.e_sel & 1], z.edges},
+                  {c->w.names[c->next_round & 1], z.names},
+                  {c->w.idx_of, z.idx},
+                  {c->w.map0, z.map0},
+                  {c->w.maps, z.maps}};
+    for (const Piece &q : pieces) {
+        if (q.n && !c->hip_ok(hipMemcpyAsync(p, q.src, q.n, hipMemcpyDeviceToHost, c->stream), "checkpoint copy"))
+            return CC_E_HIP;
+        p += q.n;
+    }
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
+    *bytes = z.total;
+    return CC_OK;
+}
+
+cc_status cc_load_state(cc_ctx *c, const void *h_buf, size_t bytes) {
+    if (!c || !h_buf) return CC_E_ARG;
+    if (!c->ws) return reject(c, CC_E_NOMEM, "no workspace: call cc_set_workspace first");
+    CkptHeader h;
+    if (bytes < sizeof h) return reject(c, CC_E_ARG, "not a checkpoint");
+    memcpy(&h, h_buf, sizeof h);
+    if (h.magic != kCkptMagic || h.version != kCkptVersion || h.state_bytes != (int32_t)sizeof(RoundState))
+        return reject(c, CC_E_ARG, "not a checkpoint of this library version");
+    if (h.n0 != c->g.n_vertices || h.m0 != c->g.n_edges || h.layout != c->g.layout || h.rule != rule_bits(c->o.flags))
+        return reject(c, CC_E_ARG, "the checkpoint belongs to another graph or label rule");
+    const int64_t n0 = c->g.n_vertices;
+    const int64_t m_cur = h.next_round == 0 ? 0 : h.m_cur, n_cur = h.next_round == 0 ? 0 : h.n_cur;
+    if (h.n_stats < 0 || h.n_stats > kStatRounds || h.next_round < 0 || h.rounds < 0 || h.rounds > h.next_round ||
+        m_cur < 0 || m_cur > c->w.kcap || n_cur < 0 || n_cur > n0 || h.map_used < 0 || h.map_used > std::max<int64_t>(n0, 1) ||
+        h.e_sel < 0 || h.e_sel > 1 || h.host_levels < 0 || h.host_levels > kMaxLevels)
+        return reject(c, CC_E_ARG, "inconsistent checkpoint");
+    const CkptSizes z = ckpt_sizes(n0, h.n_stats, m_cur, n_cur, h.map_used);
+    if ((int64_t)z.total != h.total_bytes || bytes < z.total) return reject(c, CC_E_ARG, "truncated checkpoint");
+    const char *p = (const char *)h_buf + sizeof h;
+    std::vector<cc_round_stats> stats((size_t)h.n_stats);
+    if (z.stats) memcpy(stats.data(), p, z.stats);
+    p += z.stats;
+    RoundState st;
+    memcpy(&st, p, z.state);
+    p += z.state;
+    if ((int64_t)st.m_cur != m_cur && h.next_round > 0) return reject(c, CC_E_ARG, "inconsistent checkpoint");
+    // every copy below is ordered before the next round on the stream; the host buffer is
+    // read before this call returns (synchronised)
+    struct Piece {
+        void *dst;
+        const void *src;
+        size_t n;
+    } pieces[] = {{c->w.st, &st, z.state},
+                  {c->w.keys[h.e_sel], nullptr, z.edges},
+                  {c->w.names[h.next_round & 1], nullptr, z.names},
+                  {c->w.idx_of, nullptr, z.idx},
+                  {c->w.map0, nullptr, z.map0},
+                  {c->w.maps, nullptr, z.maps}};
+    for (Piece &q : pieces) {
+        const void *src = q.src ? q.src : (const void *)p;
+        if (q.n && !c->hip_ok(hipMemcpyAsync(q.dst, src, q.n, hipMemcpyHostToDevice, c->stream), "checkpoint copy"))
+            return fail(c, CC_E_HIP, "checkpoint copy failed");
+        if (!q.src) p += q.n;
+    }
+    if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return fail(c, CC_E_HIP, "checkpoint copy failed");
+    memcpy(c->h_st, &st, sizeof st);
+    c->o.seed = h.seed;
+    c->stats = std::move(stats);
+    c->rounds = h.rounds;
+    c->next_round = h.next_round;
+    c->ran_first = h.ran_first != 0;
+    c->done = h.done != 0;
+    c->labels_ready = c->done;
+    c->finished = h.finished != 0;
+    c->host_levels = h.host_levels;
+    c->host_map_used = h.host_map_used;
+    c->n_cur = h.n_cur;
+    c->m_cur = h.m_cur;
+    c->last_graph_round = -1;
+    c->failed_status = 0;
+    c->err.clear();
+    c->recs.clear();
+    c->rec_used = 0;
+    c->inv_for = nullptr;
+    for (int i = 0; i < kFamilies; ++i) {
+        c->fam_ms[i] = 0.0;
+        c->fam_launches[i] = 0;
     }
     return CC_OK;
 }

@@ -25,7 +25,11 @@ extern const char *const kFamilyNames[kFamilies];
 
 // Lays the workspace out from `base` (or only sizes it when base is null).  `tiled`: round 0
 // runs over the tiled record layout, whose two key buffers hold twice the input records.
-size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w);
+// `extras`: kWsExplicit adds the inverse of an explicit priority table, kWsRecord the round
+// record area (CC_EXPLICIT_PRIO, CC_RECORD_ROUNDS).
+enum { kWsExplicit = 1, kWsRecord = 2 };
+constexpr int64_t kRecordPerVertex = 5;   // 4-byte record entries per vertex (20 bytes)
+size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w, uint32_t extras = 0);
 // Whether a plain solve of this size with these cc_options flags runs round 0 tiled.
 bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags);
 int ceil_log2_host(int64_t n);
@@ -106,6 +110,17 @@ struct cc_ctx : public lc::Engine {
     hipStream_t cap_stream = nullptr;
     std::vector<Tail> tails;
     uint64_t tail_clock = 0;
+    // explicit priority tables (CC_EXPLICIT_PRIO): (first round, table), and the table whose
+    // inverse the workspace holds
+    std::vector<std::pair<int32_t, const uint32_t *>> prio_tabs;
+    const uint32_t *inv_for = nullptr;
+    // recorded parents (CC_RECORD_ROUNDS): per round, its first record entry (-1: not
+    // recorded) and its node count in the record
+    struct Rec {
+        int64_t off, count;
+    };
+    std::vector<Rec> recs;
+    int64_t rec_used = 0;
 };
 
 namespace lc {

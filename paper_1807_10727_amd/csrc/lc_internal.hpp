@@ -49,7 +49,8 @@ struct RoundState {
     alignas(128) uint32_t jflag[3];   // TreeContraction: pointer-jumping passes that changed a pointer
     uint32_t jdone;                   // TreeContraction: a pass found every pointer on its cycle
     alignas(128) uint32_t err;    // bit 0: input id out of range; bit 1: map arena overflow;
-                                  // bit 2: internal consistency (atomics)
+                                  // bit 2: internal consistency; bit 3: an explicit priority
+                                  // table that is not a permutation of [0, n0) (atomics)
     alignas(128) u64c m_next;     // distinct edges of the next graph (one workgroup)
     u64c n_next;                  // nodes of the next graph (one workgroup)
     alignas(128) u64c level_off[kMaxLevels];
@@ -73,11 +74,24 @@ struct EdgeIn {
 // Priority context.  Plain graph: one round key.  Batch of independent graphs packed in
 // one id space: graph g owns ids voff[g] .. voff[g+1]-1 and hashes its local ids with its
 // own per-round key keys[g].
+// An explicit ordering (cc_set_explicit_priorities) replaces the hash in a plain solve:
+// tab[name] is the node's priority, a permutation of [0, n0), and inv its inverse.
 struct PrioCtx {
     RoundKey key;
     const RoundKey *keys;   // [G] (batch)
     const uint32_t *voff;   // [G+1] (batch)
+    const uint32_t *tab;    // [n0] explicit priorities, or null (hashed)
+    const uint32_t *inv;    // [n0] inverse of tab
 };
+
+// Priority of a name in a plain solve, and the name that has a given priority.
+__device__ inline uint32_t rho_of(const PrioCtx &pc, uint32_t name) {
+    return pc.tab ? pc.tab[name] : prio(pc.key, name);
+}
+__device__ inline uint32_t rho_name(const PrioCtx &pc, uint32_t p, int64_t n0) {
+    if (pc.tab) return (int64_t)p < n0 ? pc.inv[p] : 0xFFFFFFFFu;
+    return prio_inv(pc.key, p);
+}
 
 // Workspace arrays of one solve (device pointers).
 struct Work {
@@ -104,6 +118,9 @@ struct Work {
     uint32_t *partials;  // scan partial sums
     int64_t kcap;        // records each key buffer holds
     uint32_t *tile_cnt;  // [sort tiles] unique: heads per tile
+    uint32_t *pinv;      // [n0] inverse of an explicit priority table (CC_EXPLICIT_PRIO), else null
+    uint32_t *rec;       // round record arena (CC_RECORD_ROUNDS), else null
+    int64_t rec_cap;     // 4-byte entries of the record arena
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
     int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
     int64_t n0, m0;
@@ -259,7 +276,21 @@ inline bool tiled_fits(int64_t n) { return n >= 1 && tiled_plan(n, 1).rows <= kT
 // rest); every kernel reads its true element count from RoundState.
 
 // seeded: plain solve, rounds >= 1 (node words start at the own priority)
-hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s);
+hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s,
+                              const uint32_t *tab = nullptr);
+// explicit priorities: inv[tab[x]] = x, and err bit 3 when tab is not a permutation of [0, n0)
+hipError_t launch_prio_inverse(const Work &w, const uint32_t *tab, int grid, hipStream_t s);
+// the parents of the round that just ended, recorded at rec: round 0 as one entry per id (the
+// parent's name or kNoParent), later rounds as (name, parent name) pairs of its nodes
+hipError_t launch_record_parents(const Work &w, int round, uint32_t *rec, int grid, hipStream_t s);
+// expand a record into out[name] = parent name, -1 for names that were not nodes
+hipError_t launch_expand_record(const Work &w, int round, const uint32_t *rec, int64_t count, int32_t *out,
+                                int grid, hipStream_t s);
+// one-hop and two-hop minima of the round that just ended, by name (kInf for other names);
+// dense_m1: the tiled round 0's row pass left m1 one value per id and no two-hop word, whose
+// value is then the priority of the node's parent (the definition of the parent)
+hipError_t launch_dump_minima(const Work &w, int last_round, bool dense_m1, const PrioCtx &p, uint32_t *m1,
+                              uint32_t *l2, int grid, hipStream_t s);
 hipError_t launch_min1(const Work &w, const EdgeIn *in, const PrioCtx &p, bool batch, int round, int grid,
                        hipStream_t s);
 hipError_t launch_min2(const Work &w, const EdgeIn *in, int grid, hipStream_t s);

@@ -34,7 +34,7 @@ template <bool kFirst, bool kBatch>
 __device__ inline uint32_t node_prio(const PrioCtx &pc, const Work &w, const uint32_t *names, const uint32_t *gids,
                                      uint32_t i) {
     const uint32_t name = kFirst ? i : names[i];
-    if (!kBatch) return prio(pc.key, name);
+    if (!kBatch) return rho_of(pc, name);
     const uint32_t g = kFirst ? w.gid0[i] : gids[i];
     return prio(pc.keys[g], name - pc.voff[g]);
 }
@@ -50,7 +50,7 @@ __device__ inline int ceil_log2(uint64_t n) { return n <= 1 ? 0 : 64 - __clzll((
 // load that fetches the current minimum brings along; the two-hop accumulator may start at
 // rho(x) because it ends at most at m1[x] <= rho(x).
 template <bool kSeeded>
-__global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t *names) {
+__global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t *names, const uint32_t *tab) {
     RoundState *st = w.st;
     const int64_t n = (int64_t)st->n_cur;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
         uint64_t v = ~0ull;
         if (kSeeded) {
-            const uint64_t p = prio(key, names[i]);
+            const uint64_t p = tab ? tab[names[i]] : prio(key, names[i]);
             v = (p << 32) | p;
         }
         ((uint64_t *)w.ml)[i] = v;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
         }
         uint32_t name;
         if (!kBatch) {
-            name = prio_inv(pc.key, l);
+            name = rho_name(pc, l, w.n0);
         } else {
             const uint32_t g = kFirst ? w.gid0[i] : gids[i];
             name = prio_inv(pc.keys[g], l) + pc.voff[g];
@@ -613,6 +613,88 @@ __global__ __launch_bounds__(kThreads) void k_fill_gid(uint32_t *gid0, const uin
 }
 
 // ---------------------------------------------------------------------------------------
+// explicit priorities, round records and inspection (off the measured path)
+// ---------------------------------------------------------------------------------------
+
+// inv[tab[x]] = x; a value outside [0, n0) sets err bit 3
+__global__ __launch_bounds__(kThreads) void k_prio_inverse(Work w, const uint32_t *tab) {
+    bool bad = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < w.n0; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t t = tab[x];
+        if ((int64_t)t < w.n0)
+            w.pinv[t] = (uint32_t)x;
+        else
+            bad = true;
+    }
+    if (bad) atomicOr(&w.st->err, 8u);
+}
+
+// A table whose values all lie in [0, n0) is a permutation iff no two names share a value,
+// i.e. iff every name reads itself back through the inverse.
+__global__ __launch_bounds__(kThreads) void k_prio_inverse_check(Work w, const uint32_t *tab) {
+    bool bad = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < w.n0; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t t = tab[x];
+        if ((int64_t)t < w.n0 && w.pinv[t] != (uint32_t)x) bad = true;
+    }
+    if (bad) atomicOr(&w.st->err, 8u);
+}
+
+// Parent of node i of the round that just ended, as a name (kNoParent: not a node).
+__device__ inline uint32_t parent_name(const Work &w, int first, const uint32_t *names_prev, int64_t i) {
+    const uint32_t q = w.par[i];
+    if (q == kNoParent) return kNoParent;
+    const uint32_t p = w.lab_at[q];
+    return first ? p : names_prev[p];
+}
+
+__global__ __launch_bounds__(kThreads) void k_record_parents(Work w, int first, const uint32_t *names_prev,
+                                                             uint32_t *rec) {
+    const int64_t n = (int64_t)w.st->n_prev;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t p = parent_name(w, first, names_prev, i);
+        if (first) {
+            rec[i] = p;
+        } else {
+            rec[2 * i] = names_prev[i];
+            rec[2 * i + 1] = p;
+        }
+    }
+}
+
+// out (filled with -1 before) receives the recorded parents by name
+__global__ __launch_bounds__(kThreads) void k_expand_record(Work w, int first, const uint32_t *rec, int64_t count,
+                                                            int32_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kThreads) {
+        if (first) {
+            out[i] = (int32_t)rec[i];
+        } else {
+            const uint32_t x = rec[2 * i];
+            if ((int64_t)x < w.n0) out[x] = (int32_t)rec[2 * i + 1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dump_minima(Work w, int first, int dense, PrioCtx pc,
+                                                          const uint32_t *names_prev, uint32_t *m1o, uint32_t *l2o) {
+    const RoundState *st = w.st;
+    if (!pc.tab) pc.key = st->key;   // the key of the round that just ended
+    const int64_t n = (int64_t)st->n_prev;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t p = parent_name(w, first, names_prev, i);
+        if (p == kNoParent) continue;
+        const uint32_t x = first ? (uint32_t)i : names_prev[i];
+        if (dense) {
+            m1o[x] = w.ml[i];
+            l2o[x] = rho_of(pc, p);
+        } else {
+            m1o[x] = w.ml[2 * i];
+            l2o[x] = w.ml[2 * i + 1];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 
@@ -622,10 +704,10 @@ __global__ __launch_bounds__(kThreads) void k_fill_gid(uint32_t *gid0, const uin
         return hipGetLastError();                                             \
     } while (0)
 
-hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s) {
+hipError_t launch_round_begin(const Work &w, bool seeded, int round, int grid, hipStream_t s, const uint32_t *tab) {
     const uint32_t *names = w.names[round & 1];
-    if (seeded) LC_LAUNCH(k_round_begin<true>, grid, w, names);
-    LC_LAUNCH(k_round_begin<false>, grid, w, names);
+    if (seeded) LC_LAUNCH(k_round_begin<true>, grid, w, names, tab);
+    LC_LAUNCH(k_round_begin<false>, grid, w, names, tab);
 }
 
 template <bool kBatch>
@@ -791,6 +873,35 @@ hipError_t launch_dump_parents(const Work &w, int32_t *out, int last_round, int 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     LC_LAUNCH(k_dump_parents, grid, w, last_round == 0 ? 1 : 0, (const uint32_t *)w.names[last_round & 1], out);
+}
+
+hipError_t launch_prio_inverse(const Work &w, const uint32_t *tab, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_prio_inverse, dim3(grid), dim3(kThreads), 0, s, w, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LC_LAUNCH(k_prio_inverse_check, grid, w, tab);
+}
+
+hipError_t launch_record_parents(const Work &w, int round, uint32_t *rec, int grid, hipStream_t s) {
+    LC_LAUNCH(k_record_parents, grid, w, round == 0 ? 1 : 0, (const uint32_t *)w.names[round & 1], rec);
+}
+
+hipError_t launch_expand_record(const Work &w, int round, const uint32_t *rec, int64_t count, int32_t *out,
+                                int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, (uint32_t *)out, 0xFFFFFFFFu, w.n0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LC_LAUNCH(k_expand_record, grid, w, round == 0 ? 1 : 0, rec, count, out);
+}
+
+hipError_t launch_dump_minima(const Work &w, int last_round, bool dense_m1, const PrioCtx &p, uint32_t *m1,
+                              uint32_t *l2, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, m1, kInf, w.n0);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(kThreads), 0, s, l2, kInf, w.n0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    LC_LAUNCH(k_dump_minima, grid, w, last_round == 0 ? 1 : 0, dense_m1 ? 1 : 0, p,
+              (const uint32_t *)w.names[last_round & 1], m1, l2);
 }
 
 hipError_t launch_dump_edges(const Work &w, uint64_t *out, int next_round, int grid, hipStream_t s) {

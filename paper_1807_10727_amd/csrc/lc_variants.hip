@@ -29,7 +29,7 @@ namespace lc {
 
 template <bool kFirst>
 __device__ inline uint32_t tree_prio(const PrioCtx &pc, const uint32_t *names, uint32_t i) {
-    return prio(pc.key, kFirst ? i : names[i]);
+    return rho_of(pc, kFirst ? i : names[i]);
 }
 
 // Open one-hop minimum: each loop-free record sends rho(b) to a and rho(a) to b (no self
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_tree_f(Work w, PrioCtx pc) {
         const uint32_t m = tree_m1<kDense>(w, i);
         uint32_t p = (uint32_t)i;
         if (m != kInf) {
-            const uint32_t name = prio_inv(pc.key, m);
+            const uint32_t name = rho_name(pc, m, w.n0);
             p = kFirst ? name : ((int64_t)name < w.n0 ? w.idx_of[name] : 0xFFFFFFFFu);
             if ((int64_t)p >= n) {   // cannot happen for a consistent state
                 broken = true;

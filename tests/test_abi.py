@@ -150,3 +150,64 @@ def test_kernel_families_listed():
     for want in ("min1", "min2", "parent", "relabel", "sort_scatter", "unique", "compose", "part_a_hist",
                  "part_b_scatter", "min1_tiled", "min2_tiled", "relabel_tiled"):
         assert want in names
+
+
+def test_inspection_and_checkpoint_entry_points_validate_without_a_gpu():
+    """The test and inspection half of the boundary: explicit priorities, per-round parents,
+    the round minima and checkpoints reject bad calls before touching the device."""
+    from paper_1807_10727_amd import _cc
+    for want in ("cc_set_explicit_priorities", "cc_debug_round_arrays", "cc_save_state", "cc_load_state"):
+        assert want in declared_functions()
+    n, m = 1000, 5000
+
+    def size(flags):
+        ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=flags)
+        try:
+            return _cc.cc_workspace_size(ctx)
+        finally:
+            _cc.cc_destroy(ctx)
+
+    base = size(_cc.CC_ROUND0_DIRECT)
+    # the inverse of an explicit table: 4 bytes per vertex; the round records: 20 bytes per vertex
+    assert 4 * n <= size(_cc.CC_ROUND0_DIRECT | _cc.CC_EXPLICIT_PRIO) - base <= 4 * n + 256
+    assert 20 * n <= size(_cc.CC_ROUND0_DIRECT | _cc.CC_RECORD_ROUNDS) - base <= 20 * n + 256
+    # explicit priorities run round 0 directly
+    assert size(_cc.CC_EXPLICIT_PRIO) == size(_cc.CC_ROUND0_DIRECT | _cc.CC_EXPLICIT_PRIO)
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_EXPLICIT_PRIO | _cc.CC_ROUND0_TILED)
+    assert e.value.status == _cc.CC_E_ARG
+
+    ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000)
+    with pytest.raises(_cc.CCError) as e:     # no CC_EXPLICIT_PRIO
+        _cc.cc_set_explicit_priorities(ctx, 0, 0x3000)
+    assert e.value.status == _cc.CC_E_STATE
+    for r in (0, -1):
+        with pytest.raises(_cc.CCError) as e:   # no round has run
+            _cc.cc_round_parents(ctx, r, 0x3000)
+        assert e.value.status == _cc.CC_E_STATE
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_debug_round_arrays(ctx, 0x3000, 0x4000)
+    assert e.value.status == _cc.CC_E_STATE
+    with pytest.raises(_cc.CCError) as e:      # no workspace yet
+        _cc.cc_save_state(ctx)
+    assert e.value.status == _cc.CC_E_NOMEM
+    with pytest.raises(_cc.CCError) as e:
+        _cc.cc_load_state(ctx, b"\0" * 64)
+    assert e.value.status == _cc.CC_E_NOMEM
+    _cc.cc_destroy(ctx)
+
+    ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_EXPLICIT_PRIO)
+    for r, ptr in ((-1, 0x3000), (0, 0)):
+        with pytest.raises(_cc.CCError) as e:
+            _cc.cc_set_explicit_priorities(ctx, r, ptr)
+        assert e.value.status == _cc.CC_E_ARG
+    _cc.cc_set_explicit_priorities(ctx, 0, 0x3000)   # only stored: read by the rounds that use it
+    _cc.cc_set_explicit_priorities(ctx, 2, 0x5000)
+    _cc.cc_set_explicit_priorities(ctx, 0, 0x7000)   # replaces round 0's table
+    _cc.cc_destroy(ctx)
+
+    ctx = _cc.cc_create(n, m, _cc.CC_EDGES_SOA_I32, 0x1000, 0x2000, flags=_cc.CC_TREE)
+    with pytest.raises(_cc.CCError) as e:      # the minima are LocalContraction's
+        _cc.cc_debug_round_arrays(ctx, 0x3000, 0x4000)
+    assert e.value.status == _cc.CC_E_STATE
+    _cc.cc_destroy(ctx)

@@ -1,0 +1,381 @@
+"""The HIP library's own sources, built for the host against an emulation of the HIP
+execution model (tests/hipemu), against the oracle -- no GPU needed.
+
+This checks the kernels' and the engine's logic bit for bit (indexing, bounds, LDS, wave
+ballots and shuffles, barriers, the host round engine, captured graphs, the batch and the
+server), including the boundary calls for explicit priorities, recorded rounds, round minima
+and checkpoints.  It does not replace the GPU parity tests (tests/test_gpu_*.py): the
+hardware's timing and memory model are not emulated."""
+from itertools import permutations
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from lcref import all_graph_adjacency, contract_edges, graph_records, split_keys
+
+hipemu = pytest.importorskip("hipemu")
+
+DIRECT, TILED = 1 << 2, 1 << 3
+RULES = {"local": 0, "tree": 1 << 5, "one_hop": 1 << 6}
+
+
+@pytest.fixture(scope="module")
+def cc():
+    try:
+        return hipemu.binding()
+    except Exception as e:   # no host compiler: nothing to emulate with
+        pytest.skip("emulated build unavailable: %r" % (e,))
+
+
+def dev(a, dt=np.int32):
+    return hipemu.device(a, dt)
+
+
+def inputs(g, layout):
+    if layout == "soa32":
+        return dev(g.src), dev(g.dst)
+    if layout == "soa64":
+        return dev(g.src, np.int64), dev(g.dst, np.int64)
+    return dev(graphgen.pack(g.src, g.dst), np.uint64), None
+
+
+def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=True):
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule, record_parents=True)
+    s_, d_ = inputs(g, layout)
+    with hipemu.Solver(g.n, s_, d_, seed=seed, flags=flags | RULES[rule] | cc.CC_EAGER) as s:
+        a, b = g.src, g.dst
+        r = 0
+        while per_round:
+            st, stats = s.contract_round()
+            if st == cc.CC_DONE:
+                break
+            assert stats == tuple(want.stats[r])
+            par, k = s.parents()
+            np.testing.assert_array_equal(par.view(np.uint32), want.parents[r], err_msg="round %d" % r)
+            e = np.sort(s.edges())
+            want_e = contract_edges(a, b, want.parents[r])
+            np.testing.assert_array_equal(e, want_e, err_msg="edges after round %d" % r)
+            a, b = split_keys(want_e)
+            r += 1
+        rounds = s.run()
+        assert rounds == want.rounds
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    return want
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("layout", ["soa32", "soa64", "packed"])
+def test_emulated_solve_matches_oracle(cc, mode, layout):
+    g = graphgen.Graph(6000, *graphgen.gnm(0x5151, 6000, 20011))
+    check_solve(cc, g, 3, flags={"direct": DIRECT, "tiled": TILED}[mode], layout=layout)
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("rule", ["tree", "one_hop"])
+def test_emulated_rules_match_oracle(cc, mode, rule):
+    g = graphgen.er_with_paths(0x77, 3000, 7000, 10, 50)
+    check_solve(cc, g, 4, flags={"direct": DIRECT, "tiled": TILED}[mode], rule=rule)
+
+
+def test_emulated_degenerate_inputs(cc):
+    """Loops and repeats only, an edgeless graph, out-of-range ids."""
+    g = graphgen.Graph(50, np.arange(50, dtype=np.uint32), np.arange(50, dtype=np.uint32))
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=1) as s:
+        assert s.run() == 0
+        np.testing.assert_array_equal(s.labels(), np.arange(50))
+    g = graphgen.Graph(40, np.array([3, 3, 3, 9], np.uint32), np.array([9, 9, 9, 3], np.uint32))
+    check_solve(cc, g, 2)
+    with hipemu.Solver(10, dev(np.array([1, 12])), dev(np.array([2, 3])), seed=1) as s:
+        with pytest.raises(cc.CCError) as e:
+            s.run()
+        assert e.value.status == cc.CC_E_INPUT
+
+
+def test_emulated_captured_tails(cc):
+    """A reused context replays captured tails for the small rounds (one readback each);
+    rounds, statistics and labels are unchanged."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=10)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=99) as s:
+        s.run()
+        s.reset(10)
+        rounds = s.run()
+        assert any(cc.cc_get_round_stats(s.ctx, r, True)[-1] for r in range(rounds))
+        assert rounds == want.rounds
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_union_find_finish_and_canonical(cc):
+    g = graphgen.er_with_paths(0xF1, 5000, 9000, 20, 100)
+    want = oracle.run(g.n, g.src, g.dst, seed=5, finish_edges=300)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=5, finish_edges=300) as s:
+        rounds = s.run()
+        assert rounds == want.rounds and want.finished
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    comp = oracle.components_min_id(g.n, g.src, g.dst)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=5, flags=cc.CC_CANONICAL) as s:
+        s.run()
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), comp)
+
+
+# ---- explicit priorities ---------------------------------------------------------------------
+
+def all_orderings_union(max_n):
+    """Every labelled graph on n <= max_n vertices under every ordering of its vertices, as
+    one disjoint union with a priority table that orders each copy by its own ordering."""
+    srcs, dsts, tabs = [], [], []
+    off = 0
+    for n in range(1, max_n + 1):
+        adj = all_graph_adjacency(n)
+        G = adj.shape[0]
+        src, dst, eoff = graph_records(adj)
+        gid = np.repeat(np.arange(G, dtype=np.uint32), np.diff(eoff).astype(np.int64))
+        perms = np.array(list(permutations(range(n))), dtype=np.uint32)
+        P = perms.shape[0]
+        base_rec = (np.arange(P, dtype=np.uint32)[:, None] * np.uint32(G) + gid[None, :]) * np.uint32(n) + np.uint32(off)
+        srcs.append((base_rec + src[None, :]).ravel())
+        dsts.append((base_rec + dst[None, :]).ravel())
+        base_v = (np.arange(P * G, dtype=np.uint32) * np.uint32(n) + np.uint32(off)).reshape(P, G, 1)
+        tabs.append((base_v + perms[:, None, :]).ravel())
+        off += P * G * n
+    return off, np.concatenate(srcs), np.concatenate(dsts), np.concatenate(tabs)
+
+
+def test_emulated_every_ordering_of_every_graph_up_to_5(cc):
+    n, src, dst, tab = all_orderings_union(5)
+    assert np.array_equal(np.sort(tab), np.arange(n, dtype=np.uint32))
+    want = oracle.run(n, src, dst, explicit_prio=tab, record_parents=True)
+    with hipemu.Solver(n, dev(src), dev(dst), flags=cc.CC_EXPLICIT_PRIO | cc.CC_RECORD_ROUNDS) as s:
+        s.set_priorities(0, tab)
+        rounds = s.run()
+        assert rounds == want.rounds
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        for r in range(rounds):
+            np.testing.assert_array_equal(s.parents(r)[0].view(np.uint32), want.parents[r], err_msg="round %d" % r)
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_identity_order_on_a_path(cc):
+    k = 61
+    src = np.arange(k - 1, dtype=np.uint32)
+    with hipemu.Solver(k, dev(src), dev(src + 1), flags=cc.CC_EXPLICIT_PRIO) as s:
+        s.set_priorities(0, np.arange(k))
+        assert s.run() == (k - 1 + 1) // 2
+        assert np.all(s.labels() == 0)
+
+
+def test_emulated_tables_per_round(cc):
+    g = graphgen.er_with_paths(0xE1, 3000, 5000, 30, 60)
+    rng = np.random.default_rng(11)
+    rows = np.stack([rng.permutation(g.n).astype(np.uint32) for _ in range(4)])
+    want = oracle.run(g.n, g.src, g.dst, explicit_prio=rows, record_parents=True)
+    assert want.rounds > 4
+    for rule_flags in (0, RULES["tree"], RULES["one_hop"]):
+        if rule_flags:
+            want = oracle.run(g.n, g.src, g.dst, explicit_prio=rows, record_parents=True,
+                              variant="tree" if rule_flags == RULES["tree"] else "one_hop")
+        with hipemu.Solver(g.n, dev(g.src), dev(g.dst),
+                           flags=cc.CC_EXPLICIT_PRIO | cc.CC_RECORD_ROUNDS | rule_flags) as s:
+            for r in (2, 0, 3, 1):
+                s.set_priorities(r, rows[r])
+            rounds = s.run()
+            assert rounds == want.rounds
+            assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+            for r in range(rounds):
+                np.testing.assert_array_equal(s.parents(r)[0].view(np.uint32), want.parents[r])
+            np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_table_must_be_a_permutation(cc):
+    g = graphgen.Graph(500, *graphgen.gnm(3, 500, 900))
+    bad = np.arange(500, dtype=np.uint32)
+    bad[7] = 3
+    big = np.arange(500, dtype=np.uint32)
+    big[0] = 500
+    for table in (bad, big):
+        with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_EXPLICIT_PRIO) as s:
+            s.set_priorities(0, table)
+            with pytest.raises(cc.CCError) as e:
+                s.run()
+            assert e.value.status == cc.CC_E_INPUT
+
+
+def test_emulated_hash_before_the_first_table(cc):
+    """Rounds before the first table use the seeded hash: a table from round 1 on leaves
+    round 0 as in a hashed solve."""
+    g = graphgen.er_with_paths(0xE2, 2000, 4000, 10, 80)
+    plain = oracle.run(g.n, g.src, g.dst, seed=8, record_parents=True)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=8, flags=cc.CC_EXPLICIT_PRIO) as s:
+        s.set_priorities(1, np.arange(g.n))
+        s.contract_round()
+        np.testing.assert_array_equal(s.parents()[0].view(np.uint32), plain.parents[0])
+
+
+# ---- recorded rounds, minima, checkpoints ------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("rule", ["local", "tree", "one_hop"])
+def test_emulated_recorded_parents(cc, mode, rule):
+    g = graphgen.er_with_paths(0xBEEF, 4000, 9001, 10, 120)
+    want = oracle.run(g.n, g.src, g.dst, seed=9, variant=rule, record_parents=True)
+    flags = {"direct": DIRECT, "tiled": TILED}[mode] | RULES[rule] | cc.CC_RECORD_ROUNDS
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=9, flags=flags) as s:
+        rounds = s.run()
+        assert rounds == want.rounds
+        stats = s.stats(rounds)
+        for r in range(rounds):
+            par, k = s.parents(r)
+            np.testing.assert_array_equal(par.view(np.uint32), want.parents[r], err_msg="round %d" % r)
+            assert k == stats[r][1]
+        with pytest.raises(cc.CCError):
+            s.parents(rounds + 1)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=9, flags=flags & ~cc.CC_RECORD_ROUNDS) as s:
+        s.contract_round()
+        s.contract_round()
+        np.testing.assert_array_equal(s.parents(1)[0].view(np.uint32), want.parents[1])
+        with pytest.raises(cc.CCError) as e:
+            s.parents(0)
+        assert e.value.status == cc.CC_E_STATE
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+def test_emulated_round_minima(cc, mode):
+    g = graphgen.er_with_paths(0xA11, 6000, 15000, 10, 200)
+    want = oracle.run(g.n, g.src, g.dst, seed=4, record_minima=True, minima_cap=64)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=4, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+        r = 0
+        while s.contract_round()[0] != cc.CC_DONE:
+            m1, l2 = s.minima()
+            np.testing.assert_array_equal(m1, want.m1[r], err_msg="m1 round %d" % r)
+            np.testing.assert_array_equal(l2, want.l[r], err_msg="l round %d" % r)
+            r += 1
+        assert r == want.rounds
+
+
+def test_emulated_explicit_minima(cc):
+    g = graphgen.Graph(2000, *graphgen.gnm(8, 2000, 3000))
+    tab = np.random.default_rng(8).permutation(g.n).astype(np.uint32)
+    want = oracle.run(g.n, g.src, g.dst, explicit_prio=tab, record_minima=True)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_EXPLICIT_PRIO) as s:
+        s.set_priorities(0, tab)
+        s.contract_round()
+        m1, l2 = s.minima()
+    np.testing.assert_array_equal(m1, want.m1[0])
+    np.testing.assert_array_equal(l2, want.l[0])
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 4, 99])
+def test_emulated_checkpoint_resume(cc, k):
+    g = graphgen.er_with_paths(0xC4, 6000, 14000, 20, 300)
+    want = oracle.run(g.n, g.src, g.dst, seed=21)
+    assert want.rounds > 4
+    s_, d_ = dev(g.src), dev(g.dst)
+    with hipemu.Solver(g.n, s_, d_, seed=21, flags=TILED, max_rounds=k) as a:
+        if k:
+            a.run()
+        blob = a.save_state()
+    with hipemu.Solver(g.n, s_, d_, seed=1234, flags=DIRECT) as b:
+        b.load_state(blob)
+        rounds = b.run()
+        assert rounds == want.rounds
+        assert [tuple(x) for x in b.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(b.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_checkpoint_after_a_forced_failure(cc):
+    g = graphgen.er_with_paths(0xF00, 5000, 10000, 20, 300)
+    tab = np.random.default_rng(3).permutation(g.n).astype(np.uint32)
+    want = oracle.run(g.n, g.src, g.dst, explicit_prio=tab)
+    assert want.rounds > 4
+    bad = tab.copy()
+    bad[:2] = bad[0]
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_EXPLICIT_PRIO) as s:
+        s.set_priorities(0, tab)
+        for _ in range(3):
+            s.contract_round()
+        blob = s.save_state()
+        s.set_priorities(3, bad)
+        with pytest.raises(cc.CCError) as e:
+            s.contract_round()
+        assert e.value.status == cc.CC_E_INPUT
+        with pytest.raises(cc.CCError):
+            s.run()
+        s.load_state(blob)
+        s.set_priorities(3, tab)
+        rounds = s.run()
+        assert rounds == want.rounds
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_checkpoint_rejects_another_graph(cc):
+    g = graphgen.Graph(3000, *graphgen.gnm(1, 3000, 6000))
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=2) as a:
+        a.contract_round()
+        blob = a.save_state()
+    with hipemu.Solver(g.n + 1, dev(g.src), dev(g.dst), seed=2) as b:
+        for data in (blob, b"not a checkpoint" * 8, blob[:100]):
+            with pytest.raises(cc.CCError) as e:
+                b.load_state(data)
+            assert e.value.status == cc.CC_E_ARG
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=2, flags=cc.CC_TREE) as c:
+        with pytest.raises(cc.CCError) as e:
+            c.load_state(blob)
+        assert e.value.status == cc.CC_E_ARG
+
+
+# ---- batch and serving -----------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [0, 1, 3])
+@pytest.mark.parametrize("fill", [0x00, 0xFF])
+def test_emulated_batch(cc, variant, fill):
+    """The batch (LDS solver and union path, captured and replayed) on a workspace that
+    starts with arbitrary bytes: each graph's labels and rounds are the oracle's."""
+    b = graphgen.batch_mix(seed=31, count=24, log2_min=4, log2_max=11)
+    want_lab, want_rounds, _ = oracle.run_batch(b.voff, b.eoff, b.src, b.dst, b.seeds)
+    with hipemu.Batch(b.voff, b.eoff, b.seeds, b.src, b.dst, ws_fill=fill, small_variant=variant) as bt:
+        n_small, _ = bt.split()
+        assert (n_small > 0) == (variant > 0)
+        for _ in range(2):
+            lab, rounds = bt.run()
+            np.testing.assert_array_equal(rounds, want_rounds)
+            np.testing.assert_array_equal(lab.astype(np.uint32), want_lab)
+
+
+def test_emulated_server(cc):
+    """Requests of both paths (fused LDS launch and per-slot rounds) in one server: every
+    result is the oracle's."""
+    import time
+    trace = graphgen.request_trace(0x5E7, 10, rate=1.0, log2_min=5, log2_max=13)
+    graphs = [r.graph() for r in trace]
+    arena = hipemu._aligned(1 << 28, None)
+    srv = cc.cc_server_create(arena.ctypes.data, arena.size, n_slots=3, small_variant=1,
+                              max_small_per_launch=4)
+    keep, out = {}, {}
+    try:
+        for i, (g, r) in enumerate(zip(graphs, trace)):
+            s_, d_ = dev(g.src), dev(g.dst)
+            lab = np.full(max(g.n, 1), -7, np.int32)
+            rid = cc.cc_server_submit(srv, g.n, g.m, cc.CC_EDGES_SOA_I32, s_.ctypes.data, d_.ctypes.data, r.seed,
+                                      lab.ctypes.data)
+            keep[rid] = (i, s_, d_, lab)
+        t_end = time.time() + 300
+        while len(out) < len(graphs) and time.time() < t_end:
+            for res in cc.cc_server_wait(srv, 0.5):
+                out[res["id"]] = res
+    finally:
+        cc.cc_server_destroy(srv)
+    assert len(out) == len(graphs)
+    small = 0
+    for rid, res in out.items():
+        i, _, _, lab = keep[rid]
+        g = graphs[i]
+        want = oracle.run(g.n, g.src, g.dst, seed=trace[i].seed)
+        assert res["status"] == 0 and res["rounds"] == want.rounds
+        np.testing.assert_array_equal(lab[:g.n].astype(np.uint32), want.labels, err_msg="request %d" % i)
+        small += res["small_path"]
+    assert 0 < small < len(graphs)

@@ -53,6 +53,19 @@ def test_batch_matches_oracle(lc, variant, use_graph):
         check_batch(lc, b, lab2, rounds2)
 
 
+@pytest.mark.parametrize("fill", [0x00, 0xA5, 0xFF])
+def test_batch_ignores_workspace_contents(lc, fill):
+    """The workspace arrives with arbitrary bytes (a torch.empty tensor): whatever it holds,
+    including a round state full of ones, every run of the batch (the captured graph and its
+    replays, union and LDS paths) gives the oracle's labels and round counts."""
+    b = make_batch(64, seed=23)
+    s, d = dev_arrays(b)
+    with lc.Batch(b.voff, b.eoff, b.seeds, s, d, ws_fill=fill, small_variant=1) as bt:
+        for _ in range(3):
+            lab, rounds = bt.run()
+            check_batch(lc, b, lab, rounds)
+
+
 def test_batch_more_rounds_than_captured(lc):
     b = make_batch(40, seed=5, log2_min=8, log2_max=12, deg_lo=1.5, deg_hi=2.0)
     s, d = dev_arrays(b)

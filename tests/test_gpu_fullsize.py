@@ -18,6 +18,9 @@ in threads (the oracle's calls release the interpreter lock) when the module's f
 starts, so they overlap the GPU work.
 The batched and serving workloads are checked graph by graph on a seeded sample against the
 oracle (labels and round counts, bit for bit)."""
+import hashlib
+import json
+import os
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -32,6 +35,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 DEV = "cuda:0"
 BENCH_SEED = graphgen.CONFIG_SEED_BASE + 1     # the seed of bench.py's first timed step
+RMAT26_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat26_seed_c0ffee01.json")
 
 
 @pytest.fixture(scope="module")
@@ -230,12 +234,65 @@ def test_er_paths_round0_edges(lc, er_full):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.fixture(scope="module")
+def rmat26():
+    return graphgen.workload_rmat()
+
+
 @pytest.mark.slow
 @pytest.mark.timeout(1200)
-def test_rmat26_full_size(lc):
-    """R-MAT scale 26, edge factor 16 (1,073,741,824 packed records, 2^26 ids)."""
-    g = graphgen.workload_rmat()
-    run_full_graph(lc, g, "packed", graphgen.CONFIG_SEED_BASE + 2, 500)
+def test_rmat26_full_size(lc, rmat26):
+    """R-MAT scale 26, edge factor 16 (1,073,741,824 packed records, 2^26 ids): the checks
+    that hold at any size (sampled round-0 parents from the definition, closed-form round-0
+    statistics, partition against union-find, tiled = direct)."""
+    run_full_graph(lc, rmat26, "packed", graphgen.CONFIG_SEED_BASE + 2, 500)
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_rmat26_bit_exact_vs_oracle(lc, rmat26):
+    """R-MAT scale 26 at the bench's first seed against the oracle's stored results
+    (tests/golden/rmat26_seed_c0ffee01.json, written by make_rmat26_golden.py from the oracle
+    alone): in the timed configuration (tiled round 0, CC_PROFILE, a context that has solved
+    before) the round count, every round's statistics and the SHA-256 of the raw labels; with
+    every round recorded, round 0 direct and tiled, the SHA-256 of every round's parents by
+    name; and the canonical labels."""
+    with open(RMAT26_GOLDEN) as f:
+        gold = json.load(f)
+    assert gold["seed"] == BENCH_SEED and gold["n_records"] == rmat26.m
+    keys = torch.from_numpy(graphgen.pack(rmat26.src, rmat26.dst).view(np.int64)).to(DEV)
+    n = rmat26.n
+    stream = torch.cuda.current_stream()
+    want_stats = [tuple(x) for x in gold["stats"]]
+    with lc.Solver(n, keys, None, seed=BENCH_SEED, flags=lc.CC_PROFILE, stream=stream) as s:
+        s.reset(BENCH_SEED + 1000)
+        s.run()
+        s.reset(BENCH_SEED)
+        rounds = s.run()
+        assert s.kernel_times()["min1_tiled"][1] == 1
+        assert rounds == gold["rounds"]
+        assert [tuple(x) for x in s.stats(rounds)] == want_stats
+        assert _sha(s.labels().cpu().numpy().view(np.uint32)) == gold["labels_sha256"]
+    torch.cuda.empty_cache()
+    for flags in (lc.CC_ROUND0_DIRECT, lc.CC_ROUND0_TILED | lc.CC_CANONICAL):
+        with lc.Solver(n, keys, None, seed=BENCH_SEED, flags=flags | lc.CC_RECORD_ROUNDS, stream=stream) as s:
+            rounds = s.run()
+            assert rounds == gold["rounds"]
+            assert [tuple(x) for x in s.stats(rounds)] == want_stats
+            for r in range(rounds):
+                par, k = s.parents(r)
+                assert _sha(par.cpu().numpy()) == gold["parents_sha256"][r], "round %d, flags %d" % (r, flags)
+                assert k == want_stats[r][1]
+            lab = s.labels().cpu().numpy().view(np.uint32)
+            key = "canonical_labels_sha256" if flags & lc.CC_CANONICAL else "labels_sha256"
+            assert _sha(lab) == gold[key]
+        torch.cuda.empty_cache()
+    del keys
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.timeout(900)
@@ -260,10 +317,16 @@ def test_batch_4096_sampled(lc):
 @pytest.mark.timeout(900)
 def test_serving_trace_sampled(lc):
     """The first 24 requests of the serving benchmark's trace (log-uniform sizes up to
-    2^24 vertices), submitted at once: each result equals its solo solve, and the oracle's
-    labels for requests of at most 2^20 vertices."""
+    2^24 vertices, 620 M records in all), submitted at once: each result equals its solo
+    solve and the oracle's labels and round count (the oracle runs in threads, started
+    first, so that it overlaps the GPU work)."""
     trace = graphgen.request_trace(graphgen.CONFIG_SEED_BASE + 4, 24, rate=1.0)
     graphs = [r.graph() for r in trace]
+    oracle.run(2, np.array([0], np.uint32), np.array([1], np.uint32))   # load the library once
+    pool = ThreadPoolExecutor(max_workers=8)
+    order = sorted(range(len(graphs)), key=lambda i: -graphs[i].m)      # largest first
+    futs = {i: pool.submit(oracle.run, graphs[i].n, graphs[i].src, graphs[i].dst, seed=trace[i].seed)
+            for i in order}
     dev = [(torch.from_numpy(g.src.view(np.int32)).to(DEV), torch.from_numpy(g.dst.view(np.int32)).to(DEV))
            for g in graphs]
     torch.cuda.synchronize()
@@ -282,7 +345,7 @@ def test_serving_trace_sampled(lc):
         solo, rounds, _ = lc.solve(g.n, dev[i][0], dev[i][1], seed=r.seed)
         np.testing.assert_array_equal(got, solo.cpu().numpy(), err_msg="request %d" % i)
         assert res["rounds"] == rounds
-        if g.n <= (1 << 20):
-            want = oracle.run(g.n, g.src, g.dst, seed=r.seed)
-            np.testing.assert_array_equal(got.astype(np.uint32), want.labels, err_msg="request %d" % i)
-            assert res["rounds"] == want.rounds
+        want = futs[i].result()
+        np.testing.assert_array_equal(got.astype(np.uint32), want.labels, err_msg="request %d" % i)
+        assert res["rounds"] == want.rounds
+    pool.shutdown(wait=True)

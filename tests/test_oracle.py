@@ -14,7 +14,7 @@ import pytest
 
 import graphgen
 import oracle
-from lcref import (all_graph_adjacency, brute_all, canon, graph_records, scipy_components, simple_edges,
+from lcref import (all_graph_adjacency, brute_all, canon, contract_edges, graph_records, scipy_components, simple_edges,
                    spec_priority, spec_priority_inverse, two_hop_parents, union_find)
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -300,6 +300,38 @@ def test_components_min_id_equals_library_components(kind):
     assert np.all(got <= np.arange(g.n))
     assert np.all(got[got] == got)
     np.testing.assert_array_equal(got[g.src.astype(np.int64)], got[g.dst.astype(np.int64)])
+
+
+@pytest.mark.parametrize("variant", ["local", "one_hop"])
+def test_recorded_minima_follow_the_definition(variant):
+    """The oracle's per-round minima (record_minima): m1[x] = min of rho over the closed
+    N(x), l[x] = min of rho over N(N(x)) (Section 3; N(x) contains x, Section 2), recomputed
+    here with numpy on each round's graph (the input's simple edges, then each previous
+    graph contracted through the oracle's own parents), and l[x] = rho(parent(x))."""
+    g = graphgen.er_with_paths(21, 3000, 6000, 20, 40)
+    seed = 77
+    res = oracle.run(g.n, g.src, g.dst, seed=seed, variant=variant, record_parents=True, record_minima=True)
+    assert res.rounds >= 3
+    lo, hi = simple_edges(g.src, g.dst)
+    a, b = lo.astype(np.int64), hi.astype(np.int64)
+    for r in range(res.rounds):
+        rho = spec_priority(seed, r, np.arange(g.n)).astype(np.int64)
+        nodes = np.unique(np.concatenate([a, b]))
+        m1 = np.full(g.n, 0xFFFFFFFF, np.int64)
+        m1[nodes] = rho[nodes]
+        np.minimum.at(m1, a, rho[b])
+        np.minimum.at(m1, b, rho[a])
+        l2 = m1.copy()
+        if variant == "local":
+            np.minimum.at(l2, a, m1[b])
+            np.minimum.at(l2, b, m1[a])
+        np.testing.assert_array_equal(res.m1[r].astype(np.int64), m1, err_msg="round %d" % r)
+        np.testing.assert_array_equal(res.l[r].astype(np.int64), l2, err_msg="round %d" % r)
+        par = res.parents[r].astype(np.int64)
+        np.testing.assert_array_equal(rho[par[nodes]], l2[nodes])
+        k = contract_edges(a, b, np.where(par >= 0xFFFFFFFF, np.arange(g.n), par))
+        a, b = (k >> np.uint64(32)).astype(np.int64), (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    assert a.size == 0
 
 
 def test_components_min_id_rejects_out_of_range_ids():
