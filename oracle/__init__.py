@@ -29,6 +29,12 @@ Parity status of its functions (what pins each one; the tests hold the pins):
   * ``run(finish_edges=T)`` -- union-find finish (Section 6): pinned by the per-round results
                         being those of the plain run up to the switch, and by labels equal to
                         the smallest name of each remaining component (recomputed with scipy).
+  * ``run(variant="merge_to_large")`` -- MergeToLarge (Section 5): pinned by an independent
+                        step-by-step Python restatement (sets and dictionaries) on every
+                        graph with up to 5 vertices and on random graphs, by the step's own
+                        invariants (each node within distance 2 of a large node joins the
+                        class of the best one; the others keep theirs), by the reduction to
+                        LocalContraction when no node can be large, and by partition.
   * ``components_min_id`` -- textbook union-find (smallest id of each component): pinned to
                         scipy's connected_components and to an independent Python union-find on
                         random, power-law, path, edgeless and one-vertex graphs, with isolated
@@ -91,7 +97,7 @@ def _load():
         lib.lco_run_variant.argtypes = lib.lco_run.argtypes + [ctypes.c_int32, ctypes.c_int64,
                                                                ctypes.POINTER(ctypes.c_int32)]
         lib.lco_run_full.restype = ctypes.c_int32
-        lib.lco_run_full.argtypes = lib.lco_run_variant.argtypes + [u32p, u32p, ctypes.c_int32]
+        lib.lco_run_full.argtypes = lib.lco_run_variant.argtypes + [u32p, u32p, ctypes.c_int32, i64p, ctypes.c_int32]
         lib.lco_run_batch.restype = ctypes.c_int32
         lib.lco_run_batch.argtypes = [ctypes.c_int64, i64p, i64p, u32p, u32p, ctypes.POINTER(ctypes.c_uint64), u32p,
                                       ctypes.POINTER(ctypes.c_int32), u32p, ctypes.c_int32]
@@ -121,7 +127,7 @@ def priority(seed: int, rnd: int, name: int) -> int:
     return int(_load().lco_priority(seed & 0xFFFFFFFFFFFFFFFF, rnd, name & 0xFFFFFFFF))
 
 
-VARIANTS = {"local": 0, "tree": 1, "one_hop": 2}
+VARIANTS = {"local": 0, "tree": 1, "one_hop": 2, "merge_to_large": 3}
 
 
 @dataclass
@@ -137,10 +143,12 @@ class Result:
 
 def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0,
         record_parents: bool = False, parents_cap: int = 64, stats_cap: int = 256, variant: str = "local",
-        finish_edges: int = 0, record_minima: bool = False, minima_cap: int = 16) -> Result:
+        finish_edges: int = 0, record_minima: bool = False, minima_cap: int = 16, alphas=None) -> Result:
     """Run the oracle.  `explicit_prio` is an optional [rows, n] table of priorities (phase r
     uses row min(r, rows-1)).  `variant`: "local" (LocalContraction), "tree"
-    (TreeContraction) or "one_hop"; `finish_edges` > 0 finishes with union-find once a phase
+    (TreeContraction), "one_hop" or "merge_to_large" (LocalContraction phases, each followed
+    by a MergeToLarge step with parameter alphas[min(i, len - 1)] in phase i; default: one
+    alpha, default_alpha(n)); `finish_edges` > 0 finishes with union-find once a phase
     leaves at most that many edges."""
     lib = _load()
     src = _u32(src)
@@ -158,11 +166,15 @@ def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0
     fin = ctypes.c_int32(0)
     m1 = np.empty((minima_cap, max(n, 1)), dtype=np.uint32) if record_minima else None
     l2 = np.empty((minima_cap, max(n, 1)), dtype=np.uint32) if record_minima else None
+    al = None
+    if variant == "merge_to_large":
+        al = np.ascontiguousarray([default_alpha(n)] if alphas is None else alphas, dtype=np.int64)
     r = lib.lco_run_full(n, m, _ptr(src, ctypes.c_uint32), _ptr(dst, ctypes.c_uint32), seed & 0xFFFFFFFFFFFFFFFF,
                          _ptr(ep, ctypes.c_uint32), rows, max_rounds, _ptr(labels, ctypes.c_uint32), stats,
                          stats_cap, _ptr(par, ctypes.c_uint32), parents_cap if record_parents else 0,
                          VARIANTS[variant], int(finish_edges), ctypes.byref(fin), _ptr(m1, ctypes.c_uint32),
-                         _ptr(l2, ctypes.c_uint32), minima_cap if record_minima else 0)
+                         _ptr(l2, ctypes.c_uint32), minima_cap if record_minima else 0, _ptr(al, ctypes.c_int64),
+                         0 if al is None else int(al.shape[0]))
     if r < 0:
         raise ValueError("oracle rejected the input (ids out of range or out of memory)")
     res = Result(labels[:n], int(r), [stats[i].as_tuple() for i in range(min(r, stats_cap))],
@@ -173,6 +185,12 @@ def run(n: int, src, dst, seed: int = 0, explicit_prio=None, max_rounds: int = 0
         res.m1 = m1[:min(r, minima_cap), :n]
         res.l = l2[:min(r, minima_cap), :n]
     return res
+
+
+def default_alpha(n: int) -> int:
+    """MergeToLarge parameter used when none is given: max(2, ceil(ln n))."""
+    import math
+    return max(2, int(math.ceil(math.log(max(n, 2)))))
 
 
 def run_batch(voff, eoff, src, dst, seeds, record_parents: bool = False, parents_cap: int = 8):

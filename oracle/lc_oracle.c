@@ -31,6 +31,16 @@
  *     (a reading: the paper names no representative);
  *   - the one-hop label (Section 6, the Cracker-equivalent rule without its
  *     edge rewiring): the vertex of smallest priority in the closed N(v).
+ *   - MergeToLarge (Section 5, paragraph "MergeToLarge step"): every
+ *     LocalContraction phase is followed by a step on the graph it left.  A node
+ *     of that graph is large when its class had at least alpha_i nodes (alpha_i
+ *     given per phase i); its priority is the alpha_i-th largest priority of its
+ *     members in that phase.  Each node takes as its label the large node of
+ *     largest priority within distance 2 (itself included), or keeps itself when
+ *     there is none, and nodes with equal labels merge.  In the statistics, phase
+ *     i is round 2i (LocalContraction, priorities of round 2i) and its step is
+ *     round 2i+1 (reading: merging means equal labels, as in LocalContraction; a
+ *     large node may itself move to another large node).
  * And an optional finish (Section 6): once a phase leaves at most
  * `finish_edges` edges, the components of what is left are found by
  * union-find, and each is named by its smallest name.
@@ -109,6 +119,7 @@ static int64_t sort_unique(uint64_t *k, int64_t n) {
 #define LCO_LOCAL 0     /* LocalContraction */
 #define LCO_TREE 1      /* TreeContraction */
 #define LCO_ONE_HOP 2   /* one-hop label */
+#define LCO_MTL 3       /* LocalContraction phases, each followed by a MergeToLarge step */
 
 /* union-find over names (path halving), for the TreeContraction components and the finish */
 static uint32_t uf_find(uint32_t *up, uint32_t x) {
@@ -137,7 +148,7 @@ static void uf_union(uint32_t *up, uint32_t a, uint32_t b) {
  *   parents        out [parents_cap][n0]: label vertex of every node of the
  *                  phase, 0xFFFFFFFF for names that are not nodes of it
  *                  (may be NULL).
- *   variant        LCO_LOCAL, LCO_TREE or LCO_ONE_HOP.
+ *   variant        LCO_LOCAL, LCO_TREE, LCO_ONE_HOP or LCO_MTL.
  *   finish_edges   0, or: before every phase after the first, if at most this
  *                  many edges are left, finish with union-find instead.
  *   finished       out (may be NULL): 1 when the finish ran.
@@ -151,8 +162,10 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
                      const uint32_t *explicit_prio, int32_t prio_rows, int32_t max_rounds,
                      uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
                      int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished,
-                     uint32_t *m1_rows, uint32_t *l_rows, int32_t minima_cap) {
-    if (variant < LCO_LOCAL || variant > LCO_ONE_HOP) return -1;
+                     uint32_t *m1_rows, uint32_t *l_rows, int32_t minima_cap, const int64_t *alphas,
+                     int32_t n_alphas) {
+    if (variant < LCO_LOCAL || variant > LCO_MTL) return -1;
+    if (variant == LCO_MTL && (!alphas || n_alphas < 1)) return -1;
     if (finished) *finished = 0;
     if (n0 < 0 || m0 < 0 || n0 > 0xFFFFFFFFLL) return -1;
     for (int64_t i = 0; i < m0; ++i)
@@ -170,9 +183,16 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
     uint32_t *l_val = (uint32_t *)malloc(sizeof(uint32_t) * nn);
     uint32_t *l_arg = (uint32_t *)malloc(sizeof(uint32_t) * nn);
     uint32_t *up = (uint32_t *)malloc(sizeof(uint32_t) * nn);
-    if (!E || !E2 || !in_v || !is_label || !in_next || !rho || !m1_val || !m1_arg || !l_val || !l_arg || !up) {
+    /* MergeToLarge: class size, priority and "large" of each name, and (class, priority) pairs */
+    const int mtl = variant == LCO_MTL;
+    uint32_t *mtl_prio = (uint32_t *)malloc(mtl ? sizeof(uint32_t) * nn : 1);
+    uint8_t *mtl_large = (uint8_t *)malloc(mtl ? nn : 1);
+    uint64_t *mtl_pairs = (uint64_t *)malloc(mtl ? sizeof(uint64_t) * nn : 1);
+    if (!E || !E2 || !in_v || !is_label || !in_next || !rho || !m1_val || !m1_arg || !l_val || !l_arg || !up ||
+        !mtl_prio || !mtl_large || !mtl_pairs) {
         free(E); free(E2); free(in_v); free(is_label); free(in_next);
         free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg); free(up);
+        free(mtl_prio); free(mtl_large); free(mtl_pairs);
         return -1;
     }
 
@@ -222,7 +242,46 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
             }
         }
 
-        if (variant == LCO_TREE) {
+        const int mtl_step = mtl && (r & 1);
+        if (mtl_step) {
+            /* MergeToLarge step (Section 5, run at the end of the previous LocalContraction
+               step on the graph it left): a node takes as its label the large node of largest
+               priority within distance 2, or keeps itself when there is none.  m1: best
+               candidate in the closed N(x) (in_next flags "has one"); l: best over N(N(x))
+               (is_label flags "has one"). */
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) {
+                    in_next[x] = mtl_large[x];
+                    m1_val[x] = mtl_prio[x];
+                    m1_arg[x] = (uint32_t)x;
+                }
+            for (int64_t i = 0; i < mE; ++i) {
+                uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
+                if (mtl_large[b] && (!in_next[a] || mtl_prio[b] > m1_val[a])) {
+                    in_next[a] = 1; m1_val[a] = mtl_prio[b]; m1_arg[a] = b;
+                }
+                if (mtl_large[a] && (!in_next[b] || mtl_prio[a] > m1_val[b])) {
+                    in_next[b] = 1; m1_val[b] = mtl_prio[a]; m1_arg[b] = a;
+                }
+            }
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) {
+                    is_label[x] = in_next[x];
+                    l_val[x] = m1_val[x];
+                    l_arg[x] = m1_arg[x];
+                }
+            for (int64_t i = 0; i < mE; ++i) {
+                uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
+                if (in_next[b] && (!is_label[a] || m1_val[b] > l_val[a])) {
+                    is_label[a] = 1; l_val[a] = m1_val[b]; l_arg[a] = m1_arg[b];
+                }
+                if (in_next[a] && (!is_label[b] || m1_val[a] > l_val[b])) {
+                    is_label[b] = 1; l_val[b] = m1_val[a]; l_arg[b] = m1_arg[a];
+                }
+            }
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x] && !is_label[x]) l_arg[x] = (uint32_t)x;
+        } else if (variant == LCO_TREE) {
             /* f(v): argmin of rho over the neighbours other than v (every node of
                the phase has one: the edges are loop-free) */
             for (int64_t x = 0; x < n0; ++x)
@@ -261,7 +320,7 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
                over N(N(v)); the one-hop label stops here */
             for (int64_t x = 0; x < n0; ++x)
                 if (in_v[x]) { l_val[x] = m1_val[x]; l_arg[x] = m1_arg[x]; }
-            if (variant == LCO_LOCAL) {
+            if (variant == LCO_LOCAL || variant == LCO_MTL) {
                 for (int64_t i = 0; i < mE; ++i) {
                     uint32_t a = (uint32_t)(E[i] >> 32), b = (uint32_t)E[i];
                     if (m1_val[b] < l_val[a]) { l_val[a] = m1_val[b]; l_arg[a] = m1_arg[b]; }
@@ -273,7 +332,7 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
 
         /* optional: the one-hop and two-hop minimum priorities of every node (the values
            whose argmin the labels are), 0xFFFFFFFF for names that are not nodes */
-        if (m1_rows && l_rows && variant != LCO_TREE && r < minima_cap) {
+        if (m1_rows && l_rows && variant != LCO_TREE && !mtl_step && r < minima_cap) {
             uint32_t *row1 = m1_rows + (int64_t)r * n0, *row2 = l_rows + (int64_t)r * n0;
             for (int64_t x = 0; x < n0; ++x) {
                 row1[x] = in_v[x] ? m1_val[x] : 0xFFFFFFFFu;
@@ -321,6 +380,30 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
             n_next += in_next[x];
         }
 
+        /* MergeToLarge, after a LocalContraction step: the nodes this step created are the
+           classes of equal labels; a class of at least alpha nodes is large, and its priority
+           is the alpha-th largest priority of its members in this step (Section 5).  The
+           pairs (label, complement of the priority) sort each class by falling priority. */
+        if (mtl && !mtl_step) {
+            const int32_t ph = r / 2;
+            const int64_t alpha = alphas[ph < n_alphas ? ph : n_alphas - 1];
+            int64_t np = 0;
+            for (int64_t x = 0; x < n0; ++x)
+                if (in_v[x]) mtl_pairs[np++] = ((uint64_t)l_arg[x] << 32) | (uint64_t)(uint32_t)~rho[x];
+            qsort(mtl_pairs, (size_t)np, sizeof(uint64_t), cmp_u64);
+            memset(mtl_large, 0, nn);
+            for (int64_t i = 0; i < np;) {
+                int64_t j = i;
+                while (j < np && (mtl_pairs[j] >> 32) == (mtl_pairs[i] >> 32)) ++j;
+                const uint32_t y = (uint32_t)(mtl_pairs[i] >> 32);
+                if (alpha >= 1 && j - i >= alpha) {
+                    mtl_large[y] = 1;
+                    mtl_prio[y] = ~(uint32_t)mtl_pairs[i + alpha - 1];
+                }
+                i = j;
+            }
+        }
+
         /* compose: a vertex whose node took part in this phase moves to its label */
         for (int64_t v = 0; v < n0; ++v)
             if (in_v[labels[v]]) labels[v] = l_arg[labels[v]];
@@ -343,6 +426,7 @@ int32_t lco_run_full(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t
 
     free(E); free(E2); free(in_v); free(is_label); free(in_next);
     free(rho); free(m1_val); free(m1_arg); free(l_val); free(l_arg); free(up);
+    free(mtl_prio); free(mtl_large); free(mtl_pairs);
     return r;
 }
 
@@ -351,7 +435,7 @@ int32_t lco_run_variant(int64_t n0, int64_t m0, const uint32_t *src, const uint3
                         uint32_t *labels, lco_round_stats *stats, int32_t stats_cap, uint32_t *parents,
                         int32_t parents_cap, int32_t variant, int64_t finish_edges, int32_t *finished) {
     return lco_run_full(n0, m0, src, dst, seed, explicit_prio, prio_rows, max_rounds, labels, stats, stats_cap,
-                        parents, parents_cap, variant, finish_edges, finished, NULL, NULL, 0);
+                        parents, parents_cap, variant, finish_edges, finished, NULL, NULL, 0, NULL, 0);
 }
 
 int32_t lco_run(int64_t n0, int64_t m0, const uint32_t *src, const uint32_t *dst, uint64_t seed,

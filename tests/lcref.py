@@ -318,3 +318,60 @@ def split_keys(k):
     """(a, b) name arrays of uint64 keys (a << 32) | b."""
     k = np.asarray(k, dtype=np.uint64)
     return (k >> np.uint64(32)).astype(np.uint32), (k & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# MergeToLarge, restated step by step with sets (small graphs only)
+# --------------------------------------------------------------------------------------
+
+def merge_to_large_reference(n: int, src, dst, prio_of, alphas, max_rounds: int = 64):
+    """LocalContraction phases each followed by the MergeToLarge step (Section 5), written
+    with Python sets and dictionaries, independent of the oracle's arrays.
+
+    prio_of(r, v) -> priority of name v in round r (only even rounds are LocalContraction
+    steps; their priorities are compared by the smallest).  Phase i is round 2i; its step,
+    round 2i + 1, works on the graph the phase left: a node is large when its class had at
+    least alpha_i nodes, its priority is the alpha_i-th largest member priority, and every
+    node takes the large node of largest priority within distance 2 (itself included) as its
+    label, or keeps itself.  Returns (labels, rounds, parents per round as dicts, stats per
+    round as tuples (round, n_active, m_in, m_survive, m_out, n_finalised))."""
+    src = [int(x) for x in np.asarray(src).tolist()]
+    dst = [int(x) for x in np.asarray(dst).tolist()]
+    records = [(a, b) for a, b in zip(src, dst) if a != b]
+    E = {(min(a, b), max(a, b)) for a, b in records}
+    label = list(range(n))
+    parents, stats = [], []
+    large, mprio = {}, {}
+    r = 0
+    while E and r < max_rounds:
+        V = sorted({x for e in E for x in e})
+        nb = {v: {v} for v in V}
+        for a, b in E:
+            nb[a].add(b)
+            nb[b].add(a)
+        two = {v: set().union(*(nb[u] for u in nb[v])) for v in V}
+        if r % 2 == 0:
+            rho = {v: prio_of(r, v) for v in V}
+            par = {v: min(two[v], key=lambda u: rho[u]) for v in V}
+            members = {}
+            for v in V:
+                members.setdefault(par[v], []).append(rho[v])
+            alpha = alphas[min(r // 2, len(alphas) - 1)]
+            large = {y: len(ms) >= alpha for y, ms in members.items()}
+            mprio = {y: sorted(ms, reverse=True)[alpha - 1] for y, ms in members.items() if len(ms) >= alpha}
+        else:
+            par = {}
+            for v in V:
+                cands = [u for u in two[v] if large.get(u, False)]
+                par[v] = max(cands, key=lambda u: mprio[u]) if cands else v
+        parents.append(par)
+        edges_in = records if r == 0 else sorted(E)
+        survive = sum(1 for a, b in edges_in if par[a] != par[b])
+        E2 = {(min(par[a], par[b]), max(par[a], par[b])) for a, b in E if par[a] != par[b]}
+        keep = {x for e in E2 for x in e}
+        fin = len(set(par.values()) - keep)
+        stats.append((r, len(V), len(src) if r == 0 else len(E), survive, len(E2), fin))
+        label = [par.get(l, l) for l in label]
+        E = E2
+        r += 1
+    return np.array(label, np.int64), r, parents, stats

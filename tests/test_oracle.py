@@ -14,7 +14,8 @@ import pytest
 
 import graphgen
 import oracle
-from lcref import (all_graph_adjacency, brute_all, canon, contract_edges, graph_records, scipy_components, simple_edges,
+from lcref import (all_graph_adjacency, brute_all, canon, contract_edges, graph_records, merge_to_large_reference,
+                   scipy_components, simple_edges,
                    spec_priority, spec_priority_inverse, two_hop_parents, union_find)
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -505,3 +506,90 @@ def test_edge_counts_follow_the_contraction(variant):
                 assert want.stats[r + 1][2] == e.size
             a, b = split_keys(e)
         assert a.size == 0
+
+
+# ---------------------------------------------------------------------------------------
+# MergeToLarge (Section 5)
+# ---------------------------------------------------------------------------------------
+
+def _mtl_check(n, src, dst, seed, alphas, table=None):
+    if table is None:
+        prio_of = lambda r, v: oracle.priority(seed, r, v)   # noqa: E731 (pinned separately above)
+    else:
+        prio_of = lambda r, v: int(table[v])                   # noqa: E731
+    lab, rounds, pars, stats = merge_to_large_reference(n, src, dst, prio_of, alphas)
+    res = oracle.run(n, src, dst, seed=seed, variant="merge_to_large", alphas=alphas, record_parents=True,
+                     explicit_prio=table)
+    assert res.rounds == rounds
+    assert [tuple(x) for x in res.stats] == stats
+    for r in range(rounds):
+        want = np.full(n, oracle.NOT_A_NODE, np.uint32)
+        for v, p in pars[r].items():
+            want[v] = p
+        np.testing.assert_array_equal(res.parents[r], want, err_msg="round %d" % r)
+    np.testing.assert_array_equal(res.labels.astype(np.int64), lab)
+    return res
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_merge_to_large_equals_restatement_all_graphs(n):
+    """Every labelled graph on n vertices, two seeds, alpha in {1, 2, 3}: the oracle's
+    MergeToLarge run equals the step-by-step restatement round by round."""
+    adj = all_graph_adjacency(n)
+    src, dst, eoff = graph_records(adj)
+    for g in range(adj.shape[0]):
+        a, b = eoff[g], eoff[g + 1]
+        for seed in (1, 2):
+            for alpha in (1, 2, 3):
+                _mtl_check(n, src[a:b], dst[a:b], seed, [alpha])
+
+
+@pytest.mark.parametrize("kind", ["gnm", "paths", "dense"])
+def test_merge_to_large_equals_restatement_random(kind):
+    if kind == "gnm":
+        g = graphgen.Graph(300, *graphgen.gnm(4, 300, 500))
+    elif kind == "paths":
+        g = graphgen.er_with_paths(6, 100, 150, 4, 40)
+    else:
+        g = graphgen.Graph(120, *graphgen.gnm(8, 120, 1500))
+    for alphas in ([2], [3, 6, 12], [1]):
+        res = _mtl_check(g.n, g.src, g.dst, 31, alphas)
+        np.testing.assert_array_equal(canon(res.labels), canon(scipy_components(g.n, g.src, g.dst)))
+    tab = np.random.default_rng(5).permutation(g.n).astype(np.uint32)
+    _mtl_check(g.n, g.src, g.dst, 0, [2], table=tab)
+
+
+def test_merge_to_large_without_large_nodes_is_local_contraction():
+    """With alpha larger than any class no node is large: every MergeToLarge step keeps each
+    node (no survivor lost, same edges), and under one explicit ordering the LocalContraction
+    steps are exactly the plain run's phases."""
+    g = graphgen.er_with_paths(12, 2000, 3000, 10, 200)
+    tab = np.random.default_rng(2).permutation(g.n).astype(np.uint32)
+    plain = oracle.run(g.n, g.src, g.dst, explicit_prio=tab, record_parents=True)
+    res = oracle.run(g.n, g.src, g.dst, explicit_prio=tab, variant="merge_to_large", alphas=[g.n + 1],
+                     record_parents=True)
+    assert res.rounds == 2 * plain.rounds - 1
+    np.testing.assert_array_equal(res.labels, plain.labels)
+    for i in range(plain.rounds):
+        np.testing.assert_array_equal(res.parents[2 * i], plain.parents[i])
+        assert res.stats[2 * i][1:] == plain.stats[i][1:]
+        if 2 * i + 1 < res.rounds:
+            st = res.stats[2 * i + 1]
+            assert st[2] == st[3] == st[4] and st[5] == 0
+            nodes = res.parents[2 * i + 1] != oracle.NOT_A_NODE
+            np.testing.assert_array_equal(res.parents[2 * i + 1][nodes], np.nonzero(nodes)[0])
+
+
+def test_merge_to_large_shrinks_dense_random_graphs():
+    """Section 5, lemma on G(n, alpha_n / n) with alpha_n >= 4 ln n: one phase of
+    LocalContraction with the MergeToLarge step (parameter alpha_n / 4) leaves at most
+    n / alpha_n nodes (with high probability; checked over several seeds)."""
+    n = 1 << 14
+    alpha_n = int(math.ceil(4 * math.log(n)))
+    m = n * alpha_n // 2
+    for seed in range(4):
+        g = graphgen.Graph(n, *graphgen.gnm(100 + seed, n, m))
+        res = oracle.run(n, g.src, g.dst, seed=seed, variant="merge_to_large", alphas=[alpha_n // 4], max_rounds=2)
+        st = res.stats[1]
+        nodes_after = len(np.unique(res.labels))
+        assert nodes_after <= n / alpha_n, (seed, nodes_after, st)
