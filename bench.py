@@ -158,7 +158,7 @@ def bench_variants(args, lc, n0, m0, src, dst, layout, stream, base_seed):
 
     want = canonical(0, 0)
     for name, flags, finish in (("tree", lc.CC_TREE, 0), ("one_hop", lc.CC_ONE_HOP, 0),
-                                ("uf_finish", 0, args.finish_edges)):
+                                ("uf_finish", 0, args.finish_edges), ("merge_to_large", lc.CC_MERGE_TO_LARGE, 0)):
         with lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout,
                        finish_edges=finish) as s:
             labels = torch.empty(n0, dtype=torch.int32, device=dev)

@@ -98,7 +98,8 @@ enum {
     CC_TREE = 1u << 5,          /* TreeContraction phases (see below) */
     CC_ONE_HOP = 1u << 6,       /* one-hop labels (see below) */
     CC_EXPLICIT_PRIO = 1u << 7, /* priorities from caller tables (cc_set_explicit_priorities) */
-    CC_RECORD_ROUNDS = 1u << 8  /* keep every round's parents (cc_round_parents of any round) */
+    CC_RECORD_ROUNDS = 1u << 8, /* keep every round's parents (cc_round_parents of any round) */
+    CC_MERGE_TO_LARGE = 1u << 9 /* each phase followed by a MergeToLarge step (see below) */
 };
 
 /* Label rule of a phase.  Default: LocalContraction (Section 3), the vertex of smallest
@@ -111,6 +112,18 @@ enum {
  * comparison, without its edge rewiring); more phases than LocalContraction.  Setting both
  * makes cc_create return CC_E_ARG.  Either runs round 0 directly or tiled like the default
  * rule.  Priorities, statistics, naming and the labels' meaning are as for LocalContraction. */
+
+/* MergeToLarge (Section 5, paragraph "MergeToLarge step"; the step behind the O(log log n)
+ * bound on random graphs): with CC_MERGE_TO_LARGE every LocalContraction phase is followed by a
+ * step on the graph the phase left.  A node of that graph is large when its class (the nodes
+ * of the phase whose parent it is) holds at least alpha_i nodes, alpha_i being the parameter of
+ * phase i (cc_set_merge_to_large); its priority is the alpha_i-th largest priority of its class
+ * in that phase.  Every node then takes as its parent the large node of largest priority within
+ * distance 2 (itself included), or keeps itself, and nodes with equal parents merge, as in a
+ * LocalContraction phase.  In the statistics and in cc_round_parents, phase i is round 2i (its
+ * priorities are those of round 2i) and its step is round 2i + 1.  LocalContraction rule only
+ * (with CC_TREE or CC_ONE_HOP cc_create returns CC_E_ARG); cc_run runs every round eagerly, and
+ * the workspace grows by 28 bytes per vertex. */
 
 /* cc_run and captured tails.  On a context that has already finished a solve, once the
  * remaining graph has at most 2^22 records, cc_run replays a hipGraph of up to 8 rounds
@@ -125,7 +138,7 @@ typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
     int32_t max_rounds;  /* 0: run until no edge is left; k > 0: cc_run stops after k rounds */
     uint32_t flags;      /* CC_CANONICAL | CC_PROFILE | CC_ROUND0_DIRECT | CC_ROUND0_TILED | CC_EAGER |
-                            CC_TREE | CC_ONE_HOP | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS */
+                            CC_TREE | CC_ONE_HOP | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE */
     void *stream;        /* hipStream_t for all work of this context; NULL = null stream */
 } cc_options;
 
@@ -220,6 +233,14 @@ cc_status cc_round_parents(cc_ctx *ctx, int32_t r, int32_t *d_parents, int64_t *
  * after the union-find finish.  Synchronises.
  */
 cc_status cc_debug_round_arrays(cc_ctx *ctx, uint32_t *d_m1, uint32_t *d_l);
+
+/*
+ * MergeToLarge parameters (needs CC_MERGE_TO_LARGE at cc_create): phase i uses
+ * h_alphas[min(i, count - 1)] (host array, copied).  Without a call every phase uses
+ * max(2, ceil(ln n_vertices)).  Applies from the next round enqueued.  CC_E_STATE without
+ * CC_MERGE_TO_LARGE; CC_E_ARG for a null array, count < 1 or an alpha outside [1, 2^32 - 1].
+ */
+cc_status cc_set_merge_to_large(cc_ctx *ctx, const int64_t *h_alphas, int32_t count);
 
 /*
  * Explicit priorities (needs CC_EXPLICIT_PRIO at cc_create).  A test hook for the

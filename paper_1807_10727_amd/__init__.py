@@ -17,14 +17,16 @@ from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_bat
 from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
-                  CC_EAGER, CC_EXPLICIT_PRIO, CC_ONE_HOP, CC_PROFILE, CC_RECORD_ROUNDS, CC_ROUND0_DIRECT,
+                  CC_EAGER, CC_EXPLICIT_PRIO, CC_MERGE_TO_LARGE, CC_ONE_HOP, CC_PROFILE, CC_RECORD_ROUNDS,
+                  CC_ROUND0_DIRECT,
                   CC_ROUND0_TILED, CC_TREE, CCError, cc_debug_round_arrays, cc_load_state, cc_save_state,
-                  cc_set_explicit_priorities,
+                  cc_set_explicit_priorities, cc_set_merge_to_large,
                   cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
                   cc_labels, cc_last_error, cc_reset, cc_round_edges, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
 
 __all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_EXPLICIT_PRIO",
+           "CC_MERGE_TO_LARGE",
            "CC_ONE_HOP", "CC_PROFILE", "CC_RECORD_ROUNDS", "CC_ROUND0_DIRECT", "CC_ROUND0_TILED", "CC_TREE",
            "cc_version"]
 
@@ -122,6 +124,10 @@ class Solver:
         self._tables = getattr(self, "_tables", {})
         self._tables[int(r)] = table
         cc_set_explicit_priorities(self.ctx, r, table.data_ptr())
+
+    def set_merge_to_large(self, alphas) -> None:
+        """MergeToLarge parameters of phases 0, 1, ... (CC_MERGE_TO_LARGE)."""
+        cc_set_merge_to_large(self.ctx, alphas)
 
     def save_state(self) -> bytes:
         return cc_save_state(self.ctx)

@@ -32,6 +32,7 @@ CC_TREE = 1 << 5
 CC_ONE_HOP = 1 << 6
 CC_EXPLICIT_PRIO = 1 << 7
 CC_RECORD_ROUNDS = 1 << 8
+CC_MERGE_TO_LARGE = 1 << 9
 
 
 class cc_graph_desc(ctypes.Structure):
@@ -98,6 +99,7 @@ _sig = {
     "cc_round_parents": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "cc_debug_round_arrays": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_void_p]),
     "cc_set_explicit_priorities": (ctypes.c_int32, [_ctx_p, ctypes.c_int32, ctypes.c_void_p]),
+    "cc_set_merge_to_large": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "cc_save_state": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "cc_load_state": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_size_t]),
     "cc_round_edges": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -215,6 +217,12 @@ def cc_debug_round_arrays(ctx, m1_ptr: int, l_ptr: int) -> None:
 def cc_set_explicit_priorities(ctx, r: int, ptr: int) -> None:
     """Round r and later use the priority table at ptr (uint32[n_vertices], a permutation)."""
     _check(ctx, _lib.cc_set_explicit_priorities(ctx, int(r), ptr))
+
+
+def cc_set_merge_to_large(ctx, alphas) -> None:
+    """MergeToLarge parameters of phases 0, 1, ... (the last one repeats)."""
+    a = (ctypes.c_int64 * len(alphas))(*[int(x) for x in alphas])
+    _check(ctx, _lib.cc_set_merge_to_large(ctx, a, len(alphas)))
 
 
 def cc_save_state(ctx) -> bytes:

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -26,7 +27,7 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup"};
+    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -89,6 +90,13 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     if (extras & kWsRecord) {
         t.rec_cap = kRecordPerVertex * (int64_t)n;
         t.rec = (uint32_t *)take(4 * (size_t)t.rec_cap);
+    }
+    if (extras & kWsMerge) {
+        t.mtl_size = (uint32_t *)take(4 * n);
+        t.mtl_v = (uint32_t *)take(4 * n);
+        t.mtl_cnt = (uint32_t *)take(4 * n);
+        t.mtl_acc[0] = (uint64_t *)take(8 * n);
+        t.mtl_acc[1] = (uint64_t *)take(8 * n);
     }
     t.n0 = n0;
     t.m0 = m0;
@@ -178,7 +186,8 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const bool small_sort = scan_entries <= kSmallScanEntries;
     const bool small_flags = N <= kSmallFlagNodes;
 
-    RUN(kRoundBegin, launch_round_begin(w, !first && !batch && variant != kVarTree, r, gn, stream, pc.tab));
+    RUN(kRoundBegin,
+        launch_round_begin(w, !first && !batch && variant != kVarTree && mtl_mode != 2, r, gn, stream, pc.tab));
     if (batch) RUN(kRoundBegin, launch_batch_keys(w, d_keys, d_seeds, n_graphs, stream));
     if (first && tiled) {
         const int ga = (int)std::min<int64_t>(tp.tiles_a, grid_cap);
@@ -204,6 +213,10 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
             RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, grid_cap / 8));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
         RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, grid_cap / 8));
+    } else if (mtl_mode == 2) {   // MergeToLarge step (rounds >= 1 only)
+        RUN(kMergeLarge, launch_mtl_labels(w, mtl_alpha, gn, gm, stream));
+        RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
+        RUN(kRelabel, launch_relabel(w, src, gslab, stream));
     } else if (variant == kVarTree) {
         RUN(first ? kMin1In : kMin1, launch_min1_open(w, src, pc, r, gm, stream));
         RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream));
@@ -253,6 +266,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     }
     RUN(kNodes, launch_nodes(w, batch, r, gn, stream));
     RUN(kMap, launch_map(w, r, gn, stream));
+    if (mtl_mode == 1) RUN(kMergeLarge, launch_mtl_prep(w, pc, r, mtl_alpha, gn, gn, stream));
     if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, ghash, stream, 4));
     if (dedup != kDedupHash) RUN(kUnique, launch_unique(w, gt, stream, 2, gated));
     RUN(kRoundEnd, launch_round_end(w, r, dedup, stream));
@@ -319,7 +333,8 @@ cc_status hip_status(cc_ctx *c) { return c->failed_status ? c->failed_status : C
 namespace {
 
 uint32_t ws_extras(uint32_t flags) {
-    return ((flags & CC_EXPLICIT_PRIO) ? (uint32_t)kWsExplicit : 0u) | ((flags & CC_RECORD_ROUNDS) ? (uint32_t)kWsRecord : 0u);
+    return ((flags & CC_EXPLICIT_PRIO) ? (uint32_t)kWsExplicit : 0u) | ((flags & CC_RECORD_ROUNDS) ? (uint32_t)kWsRecord : 0u) |
+           ((flags & CC_MERGE_TO_LARGE) ? (uint32_t)kWsMerge : 0u);
 }
 
 cc_status reset_solve(cc_ctx *c, uint64_t seed) {
@@ -375,8 +390,20 @@ cc_status ctx_round_enqueue(cc_ctx *c, int *launched) {
     const int r = c->next_round;
     const int64_t N = r == 0 ? c->g.n_vertices : c->n_cur;
     const int64_t M = r == 0 ? c->g.n_edges : c->m_cur;
-    if (r > 0 && (c->host_levels >= kMaxLevels || c->host_map_used + N > std::max<int64_t>(c->g.n_vertices, 1))) {
+    // MergeToLarge: even rounds are LocalContraction steps, odd rounds the step after each.
+    // An LC step keeps room for its own map level and the step's, because the step reads the
+    // sizes and priorities that the LC step left, and a fold between them must not intervene.
+    const bool mtl = (c->o.flags & CC_MERGE_TO_LARGE) != 0;
+    const int levels_needed = mtl ? 2 : 1;
+    if (r > 0 && !(mtl && (r & 1)) &&
+        (c->host_levels + levels_needed > kMaxLevels ||
+         c->host_map_used + levels_needed * N > std::max<int64_t>(c->g.n_vertices, 1))) {
         if (!c->flatten()) return hip_status(c);
+    }
+    c->mtl_mode = !mtl ? 0 : (r & 1) ? 2 : 1;
+    if (mtl) {
+        const size_t ph = (size_t)(r / 2);
+        c->mtl_alpha = (uint64_t)c->mtl_alphas[std::min(ph, c->mtl_alphas.size() - 1)];
     }
     PrioCtx pc{};
     pc.key = round_key(c->o.seed, r);
@@ -489,7 +516,7 @@ void drop_tails(cc_ctx *c) {
 // A capture costs far more than a few small rounds: a context captures only once it has
 // finished an earlier solve, i.e. when it is being reused.
 bool tail_wanted(const cc_ctx *c) {
-    return !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS)) && c->o.max_rounds == 0 &&
+    return !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE)) && c->o.max_rounds == 0 &&
            c->finish_edges == 0 && c->solves_done > 0 &&
            c->next_round >= 1 &&
            !c->done && c->m_cur > 0 && c->m_cur <= kTailMaxRecords;
@@ -639,6 +666,7 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if ((opts->flags & CC_ROUND0_TILED) && g.n_vertices > 0 && !tiled_fits(g.n_vertices)) return CC_E_ARG;
     if ((opts->flags & CC_TREE) && (opts->flags & CC_ONE_HOP)) return CC_E_ARG;
     if ((opts->flags & CC_EXPLICIT_PRIO) && (opts->flags & CC_ROUND0_TILED)) return CC_E_ARG;
+    if ((opts->flags & CC_MERGE_TO_LARGE) && (opts->flags & (CC_TREE | CC_ONE_HOP))) return CC_E_ARG;
     cc_ctx *c = new (std::nothrow) cc_ctx();
     if (!c) return CC_E_NOMEM;
     c->g = g;
@@ -670,6 +698,11 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     c->variant = (opts->flags & CC_TREE) ? kVarTree : (opts->flags & CC_ONE_HOP) ? kVarOneHop : kVarLocal;
     c->tp = tiled_plan(g.n_vertices, g.n_edges);
     c->ws_need = plan_workspace(g.n_vertices, g.n_edges, false, c->tiled, nullptr, nullptr, ws_extras(opts->flags));
+    {   // default MergeToLarge parameter: max(2, ceil(ln n))
+        int64_t a = 2;
+        while ((double)a < std::log((double)std::max<int64_t>(g.n_vertices, 2))) ++a;
+        c->mtl_alphas.assign(1, a);
+    }
     *out = c;
     return CC_OK;
 }
@@ -755,6 +788,8 @@ cc_status cc_debug_round_arrays(cc_ctx *c, uint32_t *d_m1, uint32_t *d_l) {
     if (c->variant != kVarLocal) return reject(c, CC_E_STATE, "the minima are kept for LocalContraction only");
     if (!c->ran_first || c->next_round == 0) return reject(c, CC_E_STATE, "no round has run");
     const int last = c->next_round - 1;
+    if ((c->o.flags & CC_MERGE_TO_LARGE) && (last & 1))
+        return reject(c, CC_E_STATE, "the last round was a MergeToLarge step (no minima)");
     if (last == c->last_graph_round)
         return reject(c, CC_E_STATE, "the last round ran inside a captured tail (use CC_EAGER)");
     if (c->finished) return reject(c, CC_E_STATE, "the solve ended with the union-find finish");
@@ -765,6 +800,15 @@ cc_status cc_debug_round_arrays(cc_ctx *c, uint32_t *d_m1, uint32_t *d_l) {
                                       c->stream);
     if (!c->hip_ok(e, "dump minima")) return CC_E_HIP;
     if (!c->hip_ok(hipStreamSynchronize(c->stream), "stream synchronize")) return CC_E_HIP;
+    return CC_OK;
+}
+
+cc_status cc_set_merge_to_large(cc_ctx *c, const int64_t *h_alphas, int32_t count) {
+    if (!c || !h_alphas || count < 1) return CC_E_ARG;
+    if (!(c->o.flags & CC_MERGE_TO_LARGE)) return reject(c, CC_E_STATE, "the context was created without CC_MERGE_TO_LARGE");
+    for (int32_t i = 0; i < count; ++i)
+        if (h_alphas[i] < 1 || h_alphas[i] > 0xFFFFFFFFLL) return reject(c, CC_E_ARG, "alpha must be in [1, 2^32 - 1]");
+    c->mtl_alphas.assign(h_alphas, h_alphas + count);
     return CC_OK;
 }
 
@@ -861,11 +905,12 @@ struct CkptHeader {
 };
 
 struct CkptSizes {
-    size_t stats, state, edges, names, idx, map0, maps, total;
+    size_t stats, state, edges, names, idx, map0, maps, mtl, total;
 };
 
-CkptSizes ckpt_sizes(int64_t n0, int n_stats, int64_t m_cur, int64_t n_cur, int64_t map_used) {
+CkptSizes ckpt_sizes(int64_t n0, int n_stats, int64_t m_cur, int64_t n_cur, int64_t map_used, bool mtl) {
     CkptSizes z{};
+    z.mtl = mtl ? 4 * (size_t)n_cur : 0;
     z.stats = sizeof(cc_round_stats) * (size_t)n_stats;
     z.state = sizeof(RoundState);
     z.edges = 8 * (size_t)m_cur;
@@ -873,11 +918,15 @@ CkptSizes ckpt_sizes(int64_t n0, int n_stats, int64_t m_cur, int64_t n_cur, int6
     z.idx = 4 * (size_t)n0;
     z.map0 = 4 * (size_t)n0;
     z.maps = 4 * (size_t)map_used;
-    z.total = sizeof(CkptHeader) + z.stats + z.state + z.edges + z.names + z.idx + z.map0 + z.maps;
+    z.total = sizeof(CkptHeader) + z.stats + z.state + z.edges + z.names + z.idx + z.map0 + z.maps + 2 * z.mtl;
     return z;
 }
 
-uint32_t rule_bits(uint32_t flags) { return flags & (CC_TREE | CC_ONE_HOP); }
+uint32_t rule_bits(uint32_t flags) { return flags & (CC_TREE | CC_ONE_HOP | CC_MERGE_TO_LARGE); }
+
+// After a LocalContraction step of a MergeToLarge solve, the sizes and priorities of the next
+// graph's classes are part of the state (the step reads them).
+bool ckpt_has_mtl(uint32_t flags, int32_t next_round) { return (flags & CC_MERGE_TO_LARGE) && (next_round & 1); }
 
 }  // namespace
 
@@ -893,7 +942,7 @@ cc_status cc_save_state(cc_ctx *c, void *h_buf, size_t *bytes) {
     const int64_t m_cur = c->next_round == 0 ? 0 : (int64_t)st.m_cur;
     const int64_t n_cur = c->next_round == 0 ? 0 : (int64_t)st.n_cur;
     const int64_t map_used = (int64_t)st.map_off;
-    const CkptSizes z = ckpt_sizes(n0, (int)c->stats.size(), m_cur, n_cur, map_used);
+    const CkptSizes z = ckpt_sizes(n0, (int)c->stats.size(), m_cur, n_cur, map_used, ckpt_has_mtl(c->o.flags, c->next_round));
     if (!h_buf) {
         *bytes = z.total;
         return CC_OK;
@@ -935,7 +984,9 @@ cc_status cc_save_state(cc_ctx *c, void *h_buf, size_t *bytes) {
                   {c->w.names[c->next_round & 1], z.names},
                   {c->w.idx_of, z.idx},
                   {c->w.map0, z.map0},
-                  {c->w.maps, z.maps}};
+                  {c->w.maps, z.maps},
+                  {c->w.mtl_size, z.mtl},
+                  {c->w.mtl_v, z.mtl}};
     for (const Piece &q : pieces) {
         if (q.n && !c->hip_ok(hipMemcpyAsync(p, q.src, q.n, hipMemcpyDeviceToHost, c->stream), "checkpoint copy"))
             return CC_E_HIP;
@@ -962,7 +1013,7 @@ cc_status cc_load_state(cc_ctx *c, const void *h_buf, size_t bytes) {
         m_cur < 0 || m_cur > c->w.kcap || n_cur < 0 || n_cur > n0 || h.map_used < 0 || h.map_used > std::max<int64_t>(n0, 1) ||
         h.e_sel < 0 || h.e_sel > 1 || h.host_levels < 0 || h.host_levels > kMaxLevels)
         return reject(c, CC_E_ARG, "inconsistent checkpoint");
-    const CkptSizes z = ckpt_sizes(n0, h.n_stats, m_cur, n_cur, h.map_used);
+    const CkptSizes z = ckpt_sizes(n0, h.n_stats, m_cur, n_cur, h.map_used, ckpt_has_mtl(h.rule, h.next_round));
     if ((int64_t)z.total != h.total_bytes || bytes < z.total) return reject(c, CC_E_ARG, "truncated checkpoint");
     const char *p = (const char *)h_buf + sizeof h;
     std::vector<cc_round_stats> stats((size_t)h.n_stats);
@@ -983,7 +1034,9 @@ cc_status cc_load_state(cc_ctx *c, const void *h_buf, size_t bytes) {
                   {c->w.names[h.next_round & 1], nullptr, z.names},
                   {c->w.idx_of, nullptr, z.idx},
                   {c->w.map0, nullptr, z.map0},
-                  {c->w.maps, nullptr, z.maps}};
+                  {c->w.maps, nullptr, z.maps},
+                  {c->w.mtl_size, nullptr, z.mtl},
+                  {c->w.mtl_v, nullptr, z.mtl}};
     for (Piece &q : pieces) {
         const void *src = q.src ? q.src : (const void *)p;
         if (q.n && !c->hip_ok(hipMemcpyAsync(q.dst, src, q.n, hipMemcpyHostToDevice, c->stream), "checkpoint copy"))

@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kUfFinish, kHashDedup, kFamilies
+    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kFamilies
 };
 
 // how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)
@@ -27,7 +27,7 @@ extern const char *const kFamilyNames[kFamilies];
 // runs over the tiled record layout, whose two key buffers hold twice the input records.
 // `extras`: kWsExplicit adds the inverse of an explicit priority table, kWsRecord the round
 // record area (CC_EXPLICIT_PRIO, CC_RECORD_ROUNDS).
-enum { kWsExplicit = 1, kWsRecord = 2 };
+enum { kWsExplicit = 1, kWsRecord = 2, kWsMerge = 4 };
 constexpr int64_t kRecordPerVertex = 5;   // 4-byte record entries per vertex (20 bytes)
 size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w, uint32_t extras = 0);
 // Whether a plain solve of this size with these cc_options flags runs round 0 tiled.
@@ -55,6 +55,10 @@ struct Engine {
     const uint64_t *d_seeds = nullptr;  // [G] per-graph seeds (device)
     const uint32_t *d_voff = nullptr;   // [G+1] first union id of each graph (device)
     int32_t n_graphs = 0;
+    // MergeToLarge: 0 off; 1 this round is a LocalContraction step whose next-round classes
+    // get their sizes and priorities; 2 this round is the MergeToLarge step
+    int mtl_mode = 0;
+    uint64_t mtl_alpha = 0;
     int host_levels = 0;          // per-round maps currently kept in the arena
     int64_t host_map_used = 0;
     std::string err;
@@ -121,6 +125,8 @@ struct cc_ctx : public lc::Engine {
     };
     std::vector<Rec> recs;
     int64_t rec_used = 0;
+    // MergeToLarge parameters of phases 0, 1, ... (the last one repeats)
+    std::vector<int64_t> mtl_alphas;
 };
 
 namespace lc {

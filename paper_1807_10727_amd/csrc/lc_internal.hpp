@@ -121,6 +121,10 @@ struct Work {
     uint32_t *pinv;      // [n0] inverse of an explicit priority table (CC_EXPLICIT_PRIO), else null
     uint32_t *rec;       // round record arena (CC_RECORD_ROUNDS), else null
     int64_t rec_cap;     // 4-byte entries of the record arena
+    // MergeToLarge (CC_MERGE_TO_LARGE), per node of the graph a LocalContraction step left:
+    // class size, the alpha-th largest member priority, a count; the two best-candidate passes
+    uint32_t *mtl_size, *mtl_v, *mtl_cnt;   // [n0] each
+    uint64_t *mtl_acc[2];                    // [n0] each
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
     int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
     int64_t n0, m0;
@@ -303,6 +307,12 @@ hipError_t launch_min1_open(const Work &w, const EdgeIn *in, const PrioCtx &p, i
 // dense: after the tiled round 0's row pass (m1 dense, f kept in lab_at)
 hipError_t launch_tree_labels(const Work &w, const PrioCtx &p, int round, int64_t n_bound, int grid, hipStream_t s,
                               bool dense = false);
+// MergeToLarge (lc_variants.hip): after the LocalContraction step of round `round` (its node
+// map built), the class size and priority of every next-round node; then, in the next round,
+// the parents of the step (the best large node within two hops)
+hipError_t launch_mtl_prep(const Work &w, const PrioCtx &p, int round, uint64_t alpha, int grid_cur, int grid_next,
+                           hipStream_t s);
+hipError_t launch_mtl_labels(const Work &w, uint64_t alpha, int grid_nodes, int grid_edges, hipStream_t s);
 // union-find finish of the graph of round `round` (lc_variants.hip)
 hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);

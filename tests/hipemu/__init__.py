@@ -167,6 +167,9 @@ class Solver:
         self._tables[int(r)] = t
         self.cc.cc_set_explicit_priorities(self.ctx, r, t.ctypes.data)
 
+    def set_merge_to_large(self, alphas):
+        self.cc.cc_set_merge_to_large(self.ctx, alphas)
+
     def stats(self, rounds):
         return [self.cc.cc_get_round_stats(self.ctx, r) for r in range(rounds)]
 

@@ -379,3 +379,84 @@ def test_emulated_server(cc):
         np.testing.assert_array_equal(lab[:g.n].astype(np.uint32), want.labels, err_msg="request %d" % i)
         small += res["small_path"]
     assert 0 < small < len(graphs)
+
+
+# ---- MergeToLarge ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("alphas", [[1], [2], [3, 5, 9], [10 ** 6]])
+def test_emulated_merge_to_large(cc, mode, alphas):
+    """Every round (LocalContraction steps and MergeToLarge steps) against the oracle: parents
+    by name, statistics, the edges each round leaves, labels."""
+    g = graphgen.er_with_paths(0x3E7, 5000, 16000, 20, 150)
+    want = oracle.run(g.n, g.src, g.dst, seed=12, variant="merge_to_large", alphas=alphas, record_parents=True,
+                      parents_cap=64)
+    flags = {"direct": DIRECT, "tiled": TILED}[mode] | cc.CC_MERGE_TO_LARGE | cc.CC_RECORD_ROUNDS
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=12, flags=flags) as s:
+        s.set_merge_to_large(alphas)
+        a, b = g.src, g.dst
+        r = 0
+        while s.contract_round()[0] != cc.CC_DONE:
+            e = np.sort(s.edges())
+            want_e = contract_edges(a, b, want.parents[r])
+            np.testing.assert_array_equal(e, want_e, err_msg="edges after round %d" % r)
+            a, b = split_keys(want_e)
+            r += 1
+        rounds = s.run()
+        assert rounds == want.rounds == r
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        for q in range(rounds):
+            np.testing.assert_array_equal(s.parents(q)[0].view(np.uint32), want.parents[q], err_msg="round %d" % q)
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_merge_to_large_default_alpha_and_explicit(cc):
+    g = graphgen.Graph(3000, *graphgen.gnm(0x3E8, 3000, 12000))
+    want = oracle.run(g.n, g.src, g.dst, seed=2, variant="merge_to_large")      # default alpha
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=2, flags=cc.CC_MERGE_TO_LARGE) as s:
+        assert s.run() == want.rounds
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    tab = np.random.default_rng(4).permutation(g.n).astype(np.uint32)
+    want = oracle.run(g.n, g.src, g.dst, explicit_prio=tab, variant="merge_to_large", alphas=[4])
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_MERGE_TO_LARGE | cc.CC_EXPLICIT_PRIO) as s:
+        s.set_merge_to_large([4])
+        s.set_priorities(0, tab)
+        assert s.run() == want.rounds
+        assert [tuple(x) for x in s.stats(want.rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_emulated_merge_to_large_checkpoint(cc, k):
+    """A checkpoint after a LocalContraction step carries the classes' sizes and priorities
+    that the following MergeToLarge step reads."""
+    g = graphgen.er_with_paths(0x3E9, 4000, 12000, 20, 150)
+    want = oracle.run(g.n, g.src, g.dst, seed=6, variant="merge_to_large", alphas=[3])
+    assert want.rounds > k
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=6, flags=cc.CC_MERGE_TO_LARGE, max_rounds=k) as a:
+        a.set_merge_to_large([3])
+        a.run()
+        blob = a.save_state()
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=6, flags=cc.CC_MERGE_TO_LARGE) as b:
+        b.set_merge_to_large([3])
+        b.load_state(blob)
+        assert b.run() == want.rounds
+        assert [tuple(x) for x in b.stats(want.rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(b.labels().astype(np.uint32), want.labels)
+
+
+def test_emulated_merge_to_large_arguments(cc):
+    g = graphgen.Graph(100, *graphgen.gnm(1, 100, 200))
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst)) as s:
+        with pytest.raises(cc.CCError) as e:
+            s.set_merge_to_large([3])
+        assert e.value.status == cc.CC_E_STATE
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_MERGE_TO_LARGE) as s:
+        for bad in ([0], [3, -1]):
+            with pytest.raises(cc.CCError) as e:
+                s.set_merge_to_large(bad)
+            assert e.value.status == cc.CC_E_ARG
+    for rule in (cc.CC_TREE, cc.CC_ONE_HOP):
+        with pytest.raises(cc.CCError) as e:
+            hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_MERGE_TO_LARGE | rule)
+        assert e.value.status == cc.CC_E_ARG

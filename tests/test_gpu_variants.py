@@ -200,3 +200,33 @@ def test_hashed_rounds_launch_structure(lc):
     assert r == want.rounds
     assert [tuple(x) for x in stats] == [tuple(x) for x in want.stats]
     np.testing.assert_array_equal(labels, want.labels)
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+@pytest.mark.parametrize("alphas", [[2], [3, 6, 12], [1 << 30]])
+@pytest.mark.parametrize("name", ["gnm_mid", "rmat", "paths", "workload_small"])
+def test_merge_to_large_parity(lc, name, alphas, mode):
+    """MergeToLarge (Section 5): every round -- the LocalContraction steps and the steps after
+    them -- against the oracle: parents by name, statistics, edges left, labels."""
+    g = GRAPHS[name]()
+    seed = 0x3E7 + len(name)
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant="merge_to_large", alphas=alphas, record_parents=True)
+    s_t, d_t = dev(g)
+    with lc.Solver(g.n, s_t, d_t, seed=seed, flags=lc.CC_MERGE_TO_LARGE | MODES[mode]) as s:
+        s.set_merge_to_large(alphas)
+        a, b = g.src, g.dst
+        r = 0
+        while True:
+            st, stats = s.contract_round()
+            if st == lc.CC_DONE:
+                break
+            assert tuple(stats) == tuple(want.stats[r])
+            par, _ = s.parents()
+            np.testing.assert_array_equal(par.cpu().numpy().view(np.uint32), want.parents[r], err_msg="round %d" % r)
+            got_e = np.sort(s.edges().cpu().numpy().view(np.uint64))
+            want_e = contract_edges(a, b, want.parents[r])
+            np.testing.assert_array_equal(got_e, want_e, err_msg="edges after round %d" % r)
+            a, b = split_keys(want_e)
+            r += 1
+        assert s.run() == want.rounds == r
+        np.testing.assert_array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels)
