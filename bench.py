@@ -2,16 +2,21 @@
 """Throughput of LocalContraction connected components on one MI355X.
 
 A step is one full solve -- every round until no edge is left, then the label of every
-vertex -- of the G(n, m) graph with n = 2^24, m = 2^27 (int32 ids, endpoints uniform,
-duplicates and self-loops kept) plus 10,000 disjoint random paths of 1,000 vertices,
-with the edge list already resident in HBM.  Each step draws fresh priorities (seed
-base + step index).  The value is input edges per second.
+vertex -- of the headline workload, with its edge list already resident in HBM.  Each step
+draws fresh priorities (seed base + step index).  The value is input edges per second.
 
-Printed (stdout, one JSON line): the metric, the roofline of the dominant kernel family
-(algorithmic bytes per launch over its HIP-event launch time, against 8 TB/s), the CPU
-oracle timed on a bounded sample of the same mix, the same workload under TreeContraction,
-the one-hop label and the union-find finish, the batched and the serving legs.
-Diagnostics go to stderr.
+Headline workload (default, --workload rmat26): R-MAT scale 26, edge factor 16 (2^26 ids,
+2^30 packed records), quadrants (0.57, 0.19, 0.19, 0.05) with +-10% noise per level, ids
+permuted -- the largest single-GPU configuration of the hot path.  The G(2^24, 2^27) graph
+plus 10,000 paths of 1,000 vertices and the small G(65,536, 262,144) graph are timed after it
+as secondary figures.
+
+Printed (stdout, one JSON line): the metric; the roofline of the dominant step of the hot
+path (its algorithmic bytes by the byte model below over the measured time of the kernels
+that carry it out, against 8 TB/s); the CPU oracle timed on a bounded sample of the same
+workload with a single-thread union-find beside it; the secondary workloads; the same
+workload under TreeContraction, the one-hop label, the union-find finish and MergeToLarge;
+the batched and the serving legs.  Diagnostics go to stderr.
 """
 import argparse
 import json
@@ -24,120 +29,84 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 COPY_REPS = 5             # timed repetitions of the 1 GiB calibration copy
-# kernel symbol (as rocprofv3 prints it) of each timed family of the int32 input path
-FAMILY_SYMBOL = {
-    "min1_round0": "lc::k_min1<lc::ReadSoa32<4>, true, false>",
-    "min2_round0": "lc::k_min2<lc::ReadSoa32<4> >",
-    "relabel_round0": "lc::k_relabel<lc::ReadSoa32<4> >",
-    "min1": "lc::k_min1_seeded",
-    "min2": "lc::k_min2<lc::ReadInternal>",
-    "relabel": "lc::k_relabel<lc::ReadInternal>",
-    "sort_hist": "lc::k_sort_hist",
-    "sort_scatter": "lc::k_sort_scatter",
-    "compose": "lc::k_compose<false, false>",
-    "part_a_hist": "lc::k_part_a_hist<lc::ReadSoa32<4> >",
-    "part_a_scatter": "lc::k_part_a_scatter<lc::ReadSoa32<4> >",
-    "part_b_hist": "lc::k_part_b_hist",
-    "part_b_scatter": "lc::k_part_b_scatter",
-    "min1_tiled": "lc::k_tiled_min<1>",
-    "min2_tiled": "lc::k_tiled_min<2>",
-    "relabel_tiled": "lc::k_tiled_relabel",
+
+# The steps of a round (rows a2-a7 of the hot path) and the kernel families that carry out
+# each.  The tiled round 0's partition belongs to the implementation (it moves no algorithmic
+# byte); rounds inside a captured tail are timed together ("tail").
+FAMILY_STEP = {
+    "round_begin": "a2_one_hop", "min1_round0": "a2_one_hop", "min1": "a2_one_hop", "min1_tiled": "a2_one_hop",
+    "min2_round0": "a3_two_hop", "min2": "a3_two_hop", "min2_tiled": "a3_two_hop", "parent": "a3_two_hop",
+    "label_ranks": "a4_relabel", "relabel_round0": "a4_relabel", "relabel": "a4_relabel",
+    "relabel_tiled": "a4_relabel",
+    "sort_hist": "a5_dedup", "sort_scan": "a5_dedup", "sort_scatter": "a5_dedup", "unique": "a5_dedup",
+    "hash_dedup": "a5_dedup",
+    "node_scan": "a6_nodes", "nodes": "a6_nodes", "map": "a6_nodes", "round_end": "a6_nodes",
+    "compose": "a7_labels", "flatten": "a7_labels",
+    "part_a_hist": "partition", "part_a_scatter": "partition", "part_b_hist": "partition",
+    "part_b_scatter": "partition", "part_scan": "partition",
+    "tail_graph": "tail", "uf_finish": "finish", "merge_large": "merge_large",
 }
-
-
-def tail_free(family):
-    """Whether a kernel family never runs inside a captured tail.  A tail holds rounds >= 1 of
-    at most 2^22 records, which drop repeats by hashing: no radix pass and no unique, and
-    round 0's families run once."""
-    return (family in ("sort_hist", "sort_scan", "sort_scatter", "unique") or family.endswith("_round0")
-            or family.startswith("part_") or family.endswith("_tiled"))
-
-
-# rounds >= 1 with at most this many keys drop repeated edges by hashing (the library's
-# kHashMaxRecords; the bench graph's key buffers always hold the table)
-HASH_MAX_RECORDS = 1 << 22
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def ceil_log2(n):
-    b = 0
-    while (1 << b) < n:
-        b += 1
-    return b
-
-
-def family_bytes(stats, n0, tiled=False, loops=0, sorted_keys=None):
-    """Algorithmic bytes each kernel family must move, summed over the rounds of a solve.
-
-    Per round r: N = nodes addressed (n0 in round 0), M = records read, S = survivors,
-    K = keys the relabel wrote and the sort processed (S less the repeats the relabel
-    workgroups dropped), M' = distinct edges out, P = radix passes over the keys: they carry
-    2 ceil(log2 L) bits in digits of at most 8 bits, L = the round's labels = the next round's
-    nodes plus the labels the round finalised.  Rounds >= 1 with at most HASH_MAX_RECORDS
-    keys drop repeats through a hashed key set instead of sorting.
-    Random-access amplification (cache-line reads for 4-byte gathers and atomics) is
-    implementation overhead and deliberately not counted.  With the tiled round 0,
-    T = 2 (M - loops) directed records are written once, re-read by the row pass and read
-    by each row kernel."""
-    fam = {}
+def step_bytes(stats, n0, in_graph=None):
+    """Algorithmic bytes of each step of the hot path over one solve (the byte model:
+    what the method must move once, int32 names and 8-byte records).  Per round r, with N the
+    nodes addressed (n0 in round 0), M the records read, S the survivors of the relabel
+    (repeats counted) and M' the distinct edges out:
+        a2 one-hop minimum   8 M + 4 N          records; m1 written
+        a3 two-hop minimum   8 M + 8 N          records; m1 read, l (the parent) written
+        a4 relabel           8 M + 4 N + 8 S    records; parents read; survivors written
+        a5 duplicate drop    8 S + 8 M'         survivors read once, distinct edges written,
+                                                however many passes the implementation makes
+        a6 next nodes, map   4 N                the round's map written
+        a7 labels            4 N (+ 4 n0)       the map read; the labels written once
+    Total 24 M + 16 S + 8 M' + 24 N per round, plus 4 n0.  Random-access amplification, extra
+    sort passes and the tiled round 0's partition are the implementation's overhead.  Rounds
+    that ran inside a captured tail (in_graph[i] true) count under "tail"."""
+    out = {}
 
     def add(k, v):
-        fam[k] = fam.get(k, 0) + v
+        out[k] = out.get(k, 0) + v
 
-    for i, (r, n_active, m_in, s, m_out, fin) in enumerate(stats):
+    for i, (r, n_active, m_in, s, m_out, _fin) in enumerate(stats):
         N = n0 if r == 0 else n_active
         M = m_in
-        K = sorted_keys[i]
-        L = fin + (stats[i + 1][1] if i + 1 < len(stats) else 0)
-        P = (2 * ceil_log2(max(L, 2)) + 7) // 8
-        sfx = "_round0" if r == 0 else ""
-        add("round_begin", 10 * N)                 # m1, lv (4 B) and two flag bytes per node
-        add("label_ranks", 8 * N + 3 * N // 8)     # parents in, their label ranks out, label map scanned
-        if r == 0 and tiled:
-            T = 2 * (M - loops)
-            add("part_a_hist", 8 * M)              # records in
-            add("part_a_scatter", 8 * M + 8 * T)   # records in, directed records out
-            add("part_b_hist", 8 * T)
-            add("part_b_scatter", 16 * T)
-            add("min1_tiled", 8 * T + 4 * N)       # directed records in, m1 out
-            add("min2_tiled", 8 * T + 8 * N)       # directed records in, m1 in once, parent out
-            add("relabel_tiled", 8 * T + 4 * N + 8 * K)   # directed records, parents once, keys out
-        else:
-            add("min1" + sfx, 8 * M + 4 * N)           # records in, m1 out once
-            add("min2" + sfx, 8 * M + 8 * N)           # records in, m1 in once, lv out once
-            add("parent", 8 * N)                       # lv in, parent out
-            add("relabel" + sfx, 8 * M + 4 * N + 8 * K)   # records in, parents in once, keys out
-        if r >= 1 and K <= HASH_MAX_RECORDS:
-            # keys in, each distinct key stored in the key set and read back by the count and
-            # the write, renamed unique keys out
-            add("hash_dedup", 8 * K + 32 * m_out)
-        else:
-            add("sort_hist", 8 * K * P)                # keys in per pass
-            add("sort_scatter", 16 * K * P)            # keys in and out per pass
-            add("unique", 16 * K + 8 * m_out)          # sorted keys read twice, renamed unique keys out
-        add("node_scan", 2 * N)                    # flags of the labels (at most N) in twice, node map out
-        add("nodes", 9 * N)
-        add("map", 9 * N)
-    fam["compose"] = fam.get("compose", 0) + 8 * n0
-    return fam
+        parts = {"a2_one_hop": 8 * M + 4 * N, "a3_two_hop": 8 * M + 8 * N, "a4_relabel": 8 * M + 4 * N + 8 * s,
+                 "a5_dedup": 8 * s + 8 * m_out, "a6_nodes": 4 * N, "a7_labels": 4 * N}
+        tail = bool(in_graph[i]) if in_graph is not None else False
+        for k, v in parts.items():
+            add("tail" if tail else k, v)
+    add("a7_labels", 4 * n0)
+    return out
 
 
 def job_alg_bytes(stats, n0):
-    """The job's algorithmic bytes: three streaming reads of the records, the survivors
-    written and read once, the unique edges written, 24 bytes of node state per node and
-    round, and the labels.  Survivors as the method defines them (m_survive), whatever
-    share of them the implementation drops before writing."""
-    b = 4 * n0
-    for (r, n_active, m_in, s, m_out, _fin) in stats:
-        N = n0 if r == 0 else n_active
-        b += 24 * m_in + 16 * s + 8 * m_out + 24 * N
-    return b
+    """The whole solve's algorithmic bytes: the sum of step_bytes."""
+    return sum(step_bytes(stats, n0).values())
 
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown CPU"
+
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 def bench_variants(args, lc, n0, m0, src, dst, layout, stream, base_seed):
     """The same workload, seeds and residency under the other label rules and with the
@@ -186,16 +155,35 @@ def bench_variants(args, lc, n0, m0, src, dst, layout, stream, base_seed):
     return out
 
 
-def cpu_baseline(shrink):
+def cpu_baseline(workload, rmat_scale, er_shrink):
+    """The oracle (single-threaded C, as it stands) on a bounded sample of the headline
+    workload -- the same generator recipe at a smaller size -- and a textbook single-thread
+    union-find (the partition only, the paper's choice for a graph that fits one machine,
+    Section 6) on the same sample."""
     import graphgen
     import oracle
-    g = graphgen.workload_er_paths(shrink=shrink)
+    if workload.startswith("rmat"):
+        g = graphgen.workload_rmat(scale=rmat_scale)
+        what = ("R-MAT scale %d, edge factor 16, same recipe as the headline graph (n=%d, m=%d records)"
+                % (rmat_scale, g.n, g.m))
+    elif workload == "small":
+        g = graphgen.workload_small()
+        what = "the same graph (n=%d, m=%d records)" % (g.n, g.m)
+    else:
+        g = graphgen.workload_er_paths(shrink=er_shrink)
+        what = ("the same G(n,m)+paths mix scaled by 1/%d (n=%d, m=%d records)" % (er_shrink, g.n, g.m))
     t0 = time.perf_counter()
-    res = oracle.run(g.n, g.src, g.dst, seed=graphgen.CONFIG_SEED_BASE)
+    res = oracle.run(g.n, g.src, g.dst, seed=graphgen.CONFIG_SEED_BASE + 1)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.components_min_id(g.n, g.src, g.dst)
+    dt_uf = time.perf_counter() - t0
+    host = "%s, 1 of %d cores" % (cpu_model(), host_cores())
     return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "same G(n,m)+paths mix scaled by 1/%d: n=%d, m=%d records, %d rounds, %.1f s single-threaded"
-                      % (shrink, g.n, g.m, res.rounds, dt)}
+            "sample": "%s: %d rounds in %.1f s on %s" % (what, res.rounds, dt, host),
+            "host": host, "seconds": round(dt, 2),
+            "union_find": {"value": g.m / dt_uf, "unit": "edges/s", "cores": 1, "seconds": round(dt_uf, 2),
+                           "kind": "textbook union-find, partition only"}}
 
 
 def bench_batch(args, log_prefix="batch"):
@@ -330,7 +318,7 @@ def bench_serve(args):
     base_arr = [r.arrival for (r, _, _, _) in reqs]
     loads = []
     identical = True
-    srv = lc.Server(args.serve_budget_gib << 30, n_slots=args.serve_slots, small_variant=1,
+    srv = lc.Server(args.serve_budget_gib << 30, n_slots=args.serve_slots, small_variant=args.serve_small_variant,
                     max_small_per_launch=256)
     try:
         for rho in args.serve_loads:
@@ -373,19 +361,94 @@ def bench_serve(args):
             "labels_identical_to_solo": identical, "peak_arena_gib": peak / 2**30}
 
 
+WORKLOADS = ("rmat26", "er_paths", "small", "rmat24")
+
+
+def make_workload(name):
+    """(graph, description) of a named workload (seeded generators, no method arithmetic)."""
+    import graphgen
+    if name == "er_paths":
+        return graphgen.workload_er_paths(), "G(n=2^24, m=2^27) + 10,000 paths x 1,000 vertices, int32 ids"
+    if name == "small":
+        return graphgen.workload_small(), "G(n=65,536, m=262,144), int32 ids"
+    scale = 26 if name == "rmat26" else 24
+    return (graphgen.workload_rmat(scale=scale),
+            "R-MAT scale %d, edge factor 16, (0.57,0.19,0.19,0.05) +-10%%, permuted ids, packed u64 records" % scale)
+
+
+def upload(name, g, dev):
+    import numpy as np
+    import torch
+    import paper_1807_10727_amd as lc
+    if name.startswith("rmat"):
+        keys = graphgen_pack(g)
+        return torch.from_numpy(keys).to(dev), None, lc.CC_EDGES_PACKED_U64
+    return (torch.from_numpy(g.src.view(np.int32)).to(dev), torch.from_numpy(g.dst.view(np.int32)).to(dev),
+            lc.CC_EDGES_SOA_I32)
+
+
+def graphgen_pack(g):
+    import numpy as np
+    import graphgen
+    return graphgen.pack(g.src, g.dst).view(np.int64)
+
+
+def bench_secondary(name, steps, warmup):
+    """A secondary workload: `steps` full solves (a reused context, as a user runs them),
+    input edges per second and the job's algorithmic bytes over the step time."""
+    import torch
+    import graphgen
+    import paper_1807_10727_amd as lc
+    dev = torch.device("cuda:0")
+    g, wname = make_workload(name)
+    src, dst, layout = upload(name, g, dev)
+    n0, m0 = g.n, int(src.shape[0])
+    del g
+    stream = torch.cuda.current_stream(dev)
+    base = graphgen.CONFIG_SEED_BASE + 1
+    labels = torch.empty(n0, dtype=torch.int32, device=dev)
+    with lc.Solver(n0, src, dst, seed=base, stream=stream, layout=layout) as s:
+        for i in range(warmup):
+            s.reset(base + 1000 + i)
+            s.run()
+            s.labels(labels)
+        torch.cuda.synchronize()
+        stats, rounds = [], []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            s.reset(base + i)
+            rounds.append(s.run())
+            s.labels(labels)
+            stats.append(s.stats(rounds[-1]))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    job = sum(job_alg_bytes(st, n0) for st in stats)
+    out = {"workload": wname, "n_vertices": n0, "n_records": m0, "steps": steps,
+           "ms_per_step": dt * 1e3 / steps, "value": m0 * steps / dt, "unit": "edges/s", "rounds": rounds[0],
+           "job_alg_frac": round(job / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    log("secondary %s: %.3f ms/step, %.3g edges/s, rounds %s" % (name, out["ms_per_step"], out["value"], rounds))
+    del src, dst, labels
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="er_paths", choices=["er_paths", "small", "rmat26", "rmat24"])
+    ap.add_argument("--workload", default="rmat26", choices=WORKLOADS)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--eager", action="store_true",
-                    help="run every round eagerly even without per-kernel timing (as the timed run does)")
+    ap.add_argument("--eager", action="store_true", help="run every round eagerly (no captured tails)")
     ap.add_argument("--round0", default="auto", choices=["auto", "direct", "tiled"],
                     help="how round 0 reads the input records (auto: the library's choice by size)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-shrink", type=int, default=8)
+    ap.add_argument("--cpu-rmat-scale", type=int, default=21,
+                    help="R-MAT scale of the oracle's sample of an R-MAT headline (same recipe)")
+    ap.add_argument("--cpu-shrink", type=int, default=8, help="divisor of the G(n,m)+paths sample")
+    ap.add_argument("--secondary", default="er_paths,small",
+                    help="comma-separated secondary workloads timed after the headline ('' for none)")
+    ap.add_argument("--secondary-steps", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-mode leg")
     ap.add_argument("--batch-only", action="store_true", help="run only the batched-mode leg")
     ap.add_argument("--batch-graphs", type=int, default=4096)
@@ -398,10 +461,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-log2-max", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-small-variant", type=int, default=3)
     ap.add_argument("--serve-budget-gib", type=int, default=128)
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.2])
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip TreeContraction, the one-hop label and the union-find finish")
+                    help="skip TreeContraction, the one-hop label, the union-find finish and MergeToLarge")
     ap.add_argument("--variant-steps", type=int, default=5)
     ap.add_argument("--finish-edges", type=int, default=1 << 22)
     args = ap.parse_args()
@@ -411,7 +475,6 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import graphgen
@@ -426,39 +489,19 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    if args.workload == "er_paths":
-        g = graphgen.workload_er_paths()
-        wname = "G(n=2^24, m=2^27) + 10,000 paths x 1,000 vertices, int32 ids"
-    elif args.workload == "small":
-        g = graphgen.workload_small()
-        wname = "G(n=65,536, m=262,144), int32 ids"
-    else:
-        scale = 26 if args.workload == "rmat26" else 24
-        g = graphgen.workload_rmat(scale=scale)
-        wname = "R-MAT scale %d, edge factor 16, (0.57,0.19,0.19,0.05) +-10%%, permuted ids" % scale
+    g, wname = make_workload(args.workload)
     log("generated %s: n=%d m=%d in %.1fs" % (wname, g.n, g.m, time.perf_counter() - t0))
-
-    if args.workload.startswith("rmat"):
-        keys = graphgen.pack(g.src, g.dst).view(np.int64)
-        src = torch.from_numpy(keys).to(dev)
-        dst = None
-        layout = lc.CC_EDGES_PACKED_U64
-    else:
-        src = torch.from_numpy(g.src.view(np.int32)).to(dev)
-        dst = torch.from_numpy(g.dst.view(np.int32)).to(dev)
-        layout = lc.CC_EDGES_SOA_I32
-    loops = int(np.count_nonzero(g.src == g.dst))
-    del g.src, g.dst
+    src, dst, layout = upload(args.workload, g, dev)
     n0, m0 = g.n, int(src.shape[0])
+    del g
     torch.cuda.synchronize()
 
-    # calibration copy for the HBM traffic counters: one plain 1 GiB device-to-device copy
+    # the streaming bandwidth this GPU reaches: a plain 1 GiB device copy timed with events
+    # (read + write), reported beside the 8 TB/s peak
     cal_a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     cal_b = torch.empty_like(cal_a)
     cal_b.copy_(cal_a)
     torch.cuda.synchronize()
-    # the same copy timed with events: the streaming bandwidth this GPU reaches (read + write),
-    # the second denominator beside the 8 TB/s peak
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
     for _ in range(COPY_REPS):
@@ -469,10 +512,6 @@ def main():
     log("plain 1 GiB device copy: %.1f GB/s (read + write)" % copy_gbs)
     del cal_a, cal_b
 
-    # Per-kernel events sit only on eagerly launched rounds (a captured tail carries none).
-    # Later rounds replay captured tails, unless the dominant family also runs in such rounds:
-    # then the solver is made again with every round eager (CC_EAGER), so that each of its
-    # launches carries its events on the stream.
     flags = 0 if args.no_profile else lc.CC_PROFILE
     if args.eager:
         flags |= lc.CC_EAGER
@@ -494,94 +533,85 @@ def main():
             acc_ms[k] = acc_ms.get(k, 0.0) + ms
             acc_n[k] = acc_n.get(k, 0) + n
 
-    def fam_bytes_of(stats_list, keys_list, launches):
+    def steps_of(acc, fams):
         out = {}
-        for st, ks in zip(stats_list, keys_list):
-            for k, v in family_bytes(st, n0, tiled=launches.get("min1_tiled", 0) > 0, loops=loops,
-                                     sorted_keys=ks).items():
-                out[k] = out.get(k, 0) + v
+        for k, v in acc.items():
+            st = FAMILY_STEP.get(k, k)
+            if fams is None or k in fams:
+                out[st] = out.get(st, 0) + v
         return out
 
-    def log_families(title, acc_ms, acc_n, acc_bytes, steps):
-        log("%s: kernel family       ms/step  launches/step  GB/s(alg)" % title)
-        for k in sorted(acc_ms, key=lambda x: -acc_ms[x]):
-            if acc_n[k] == 0:
-                continue
-            gbs = acc_bytes.get(k, 0) / (acc_ms[k] * 1e-3) / 1e9 if acc_ms[k] > 0 else 0.0
-            log("  %-16s %8.3f %10.1f %10.1f" % (k, acc_ms[k] / steps, acc_n[k] / steps, gbs))
-
-    # Warm-up steps time every kernel family; the dominant one (largest kernel time) is then
-    # the only family timed during the measured steps, so that the events of the others do
-    # not slow the stream down.  One more warm-up step runs with that setting (it captures
-    # the tails of rounds the measured steps replay).
-    warm_ms, warm_n, warm_stats, warm_keys = {}, {}, [], []
-    for i in range(max(args.warmup - 1, 0) if not args.no_profile else args.warmup):
+    # Warm-up: every kernel family is timed with events; the step of the hot path whose kernels
+    # take the most time is the dominant one.  The timed steps then put events around that
+    # step's families only (events around every launch slow the stream down), and the last
+    # warm-up step runs with that setting (it also captures the tails the timed steps replay).
+    # Events sit only on eagerly launched rounds, and the bytes of rounds inside captured
+    # tails are counted under "tail", so time and bytes cover the same launches.
+    warm_ms, warm_n, warm_bytes = {}, {}, {}
+    n_warm = max(args.warmup - 1, 0) if not args.no_profile else args.warmup
+    for i in range(n_warm):
         r = step(1000 + i)
-        warm_stats.append(solver.stats(r))
-        warm_keys.append(solver.sorted_keys(r))
+        for k, v in step_bytes(solver.stats(r), n0, solver.rounds_in_graph(r)).items():
+            warm_bytes[k] = warm_bytes.get(k, 0) + v
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
-    dom = None
+    dom_step, dom_fams = None, None
     if not args.no_profile and warm_ms:
-        warm_bytes = fam_bytes_of(warm_stats, warm_keys, warm_n)
-        steps_w = len(warm_stats)
-        log_families("warm-up", warm_ms, warm_n, warm_bytes, steps_w)
-        log("warm-up: sum of kernel time per step %.3f ms" % (sum(warm_ms.values()) / steps_w))
-        dom = max((k for k in warm_ms if k in warm_bytes and warm_n[k] > 0), key=lambda k: warm_ms[k])
-        if not tail_free(dom) and not flags & lc.CC_EAGER:
-            log("dominant family %s also runs in captured tails: every round eager" % dom)
-            flags |= lc.CC_EAGER
-            solver.close()
-            solver = lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout)
-        solver.profile_families([dom])
+        per_step = steps_of(warm_ms, None)
+        log("warm-up: step            ms/solve   GB/s (algorithmic)")
+        for k in sorted(per_step, key=lambda x: -per_step[x]):
+            gbs = warm_bytes.get(k, 0) / (per_step[k] * 1e-3) / 1e9 if per_step[k] > 0 else 0.0
+            log("  %-18s %8.3f %10.1f" % (k, per_step[k] / n_warm, gbs))
+        log("warm-up: kernel family       ms/solve  launches/solve")
+        for k in sorted(warm_ms, key=lambda x: -warm_ms[x]):
+            if warm_n[k]:
+                log("  %-18s %8.3f %10.1f" % (k, warm_ms[k] / n_warm, warm_n[k] / n_warm))
+        log("warm-up: sum of kernel time per solve %.3f ms" % (sum(warm_ms.values()) / n_warm))
+        timed = {k: v for k, v in per_step.items() if k in warm_bytes and k not in ("tail",)}
+        dom_step = max(timed, key=lambda k: timed[k])
+        dom_fams = sorted(k for k, v in warm_n.items() if v and FAMILY_STEP.get(k) == dom_step)
+        solver.profile_families(dom_fams)
         step(2000)
         torch.cuda.synchronize()
     solver.reset(base_seed)            # clears the per-kernel timers too
-    all_stats = []
-    all_keys = []
-    rounds = []
-    fam_ms = {}
-    fam_n = {}
+    all_stats, in_graph, rounds = [], [], []
+    fam_ms, fam_n = {}, {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = step(i)
         rounds.append(r)
         all_stats.append(solver.stats(r))
-        all_keys.append(solver.sorted_keys(r))
+        in_graph.append(solver.rounds_in_graph(r))
         collect(fam_ms, fam_n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
     value = m0 * args.steps / dt
     log("rounds per step: %s" % rounds)
-    for st, k in zip(all_stats[0], all_keys[0]):
-        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st + " sorted=%d" % k)
+    for st, ig in zip(all_stats[0], in_graph[0]):
+        log("  round %d: n_active=%d m_in=%d survive=%d m_out=%d finalised=%d" % st + (" (tail)" if ig else ""))
 
-    # algorithmic bytes per family over the timed steps
-    fam_bytes = fam_bytes_of(all_stats, all_keys, fam_n if dom is None else warm_n)
     job_bytes = sum(job_alg_bytes(st, n0) for st in all_stats)
-
     roofline = None
-    if not args.no_profile and fam_ms:
-        if dom is None:
-            log_families("timed", fam_ms, fam_n, fam_bytes, args.steps)
-            dom = max((k for k in fam_ms if k in fam_bytes and fam_n[k] > 0), key=lambda k: fam_ms[k])
-        avg_launch_s = fam_ms[dom] * 1e-3 / fam_n[dom]
-        bytes_per_launch = fam_bytes[dom] / fam_n[dom]
-        achieved = bytes_per_launch / avg_launch_s / 1e9
-        traffic = None
-        if dom in FAMILY_SYMBOL and args.workload == "er_paths":
-            from paper_1807_10727_amd import profiling
-            traffic = profiling.load_traffic(TRAFFIC_FILE, FAMILY_SYMBOL[dom])
-        roofline = {"bound": "hbm", "kernel": dom, "symbol": FAMILY_SYMBOL.get(dom), "achieved": round(achieved, 1),
+    if dom_step is not None:
+        b = {}
+        for st, ig in zip(all_stats, in_graph):
+            for k, v in step_bytes(st, n0, ig).items():
+                b[k] = b.get(k, 0) + v
+        ms = sum(fam_ms.get(k, 0.0) for k in dom_fams)
+        launches = sum(fam_n.get(k, 0) for k in dom_fams)
+        achieved = b[dom_step] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        top = max(dom_fams, key=lambda k: fam_ms.get(k, 0.0))
+        roofline = {"bound": "hbm", "kernel": dom_step, "families": dom_fams, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None if traffic is None else int(traffic),
-                    "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                    "traffic": None, "bytes_per_solve": int(b[dom_step] / args.steps),
+                    "ms_per_solve": round(ms / args.steps, 4), "launches_per_solve": launches / args.steps,
+                    "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+                    "largest_family": top, "largest_family_ms_per_solve": round(fam_ms.get(top, 0.0) / args.steps, 4),
                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
-        log("timed steps: %s %.3f ms/step over %d launches/step, %.1f GB/s algorithmic"
-            % (dom, fam_ms[dom] / args.steps, fam_n[dom] / args.steps, achieved))
-
+        log("timed steps: %s (%s) %.3f ms/solve over %.1f launches/solve, %.1f GB/s algorithmic"
+            % (dom_step, ",".join(dom_fams), ms / args.steps, launches / args.steps, achieved))
     job_gbs = job_bytes / dt / 1e9
     log("job algorithmic bytes per step %.2f GB -> %.1f GB/s (%.1f%% of 8 TB/s)"
         % (job_bytes / args.steps / 1e9, job_gbs, 100 * job_gbs / HBM_PEAK_GBS))
@@ -598,6 +628,16 @@ def main():
             variants = {"error": repr(e)}
     del src, dst
     torch.cuda.empty_cache()
+
+    secondary = {}
+    for name in [x for x in args.secondary.split(",") if x and x != args.workload]:
+        try:
+            secondary[name] = bench_secondary(name, args.secondary_steps if name != "small" else 5 * args.secondary_steps,
+                                              2)
+        except Exception as e:  # the main figure stands on its own
+            log("secondary %s failed: %r" % (name, e))
+            secondary[name] = {"error": repr(e)}
+
     batched = None
     if not args.no_batch:
         try:
@@ -617,7 +657,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         try:
-            cpu = cpu_baseline(args.cpu_shrink if args.workload == "er_paths" else 8)
+            cpu = cpu_baseline(args.workload, args.cpu_rmat_scale, args.cpu_shrink)
+            log("cpu baseline: %s" % cpu["sample"])
         except Exception as e:  # the GPU figure stands on its own
             log("cpu baseline failed: %r" % (e,))
 
@@ -640,6 +681,7 @@ def main():
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "job_alg_frac_of_copy": round(job_gbs / copy_gbs, 4),
         "cpu_baseline": cpu,
+        "secondary": secondary,
         "variants": variants,
         "batched": batched,
         "serving": serving,
