@@ -153,9 +153,9 @@ typedef struct {
     int64_t n_finalised;  /* distinct parents of this round that keep no edge */
     int64_t m_sorted;     /* keys this round's duplicate drop processed (a radix sort, or from
                              round 1 on a hashed key set when at most 2^22 of them): m_survive
-                             less the repeats each relabel workgroup recognised itself
-                             (launch-dependent, not a property of the method; m_survive in
-                             round 0) */
+                             less the repeats each relabel workgroup recognised itself (an LDS
+                             key set per workgroup, in every round but a round 0 that reads the
+                             input directly; launch-dependent, not a property of the method) */
 } cc_round_stats;
 
 typedef struct cc_ctx cc_ctx;

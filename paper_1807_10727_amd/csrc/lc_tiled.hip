@@ -375,6 +375,33 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, 
     if (broken) atomicOr(&st->err, 4u);
 }
 
+// Repeats in the relabel's output.  A workgroup keeps the keys it has written in an LDS set
+// (open addressing, kRowSetProbes linear probes, kept for the whole launch) and drops a key it
+// finds there: on power-law inputs most survivors of round 0 repeat a few parent pairs (hubs
+// and their neighbourhoods contract onto the same parents), and they need not reach the sort.
+// A key whose probes all meet other keys is written anyway; the sort drops every repeat left.
+// Where keys hardly repeat (uniform random graphs) the probes cost more than they save, so a
+// workgroup stops using the set once kRowSetTrial keys found fewer than 1/16 repeats.
+#ifndef LC_ROW_SET_LOG2
+#define LC_ROW_SET_LOG2 11
+#endif
+constexpr int kRowSetLog2 = LC_ROW_SET_LOG2;
+constexpr int kRowSetSlots = 1 << kRowSetLog2;
+constexpr int kRowSetProbes = 8;
+constexpr uint32_t kRowSetTrial = 8192;
+
+// false when `key` is in the set already
+__device__ inline bool row_set_insert(unsigned long long *set, uint64_t key) {
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kRowSetLog2));
+    for (int p = 0; p < kRowSetProbes; ++p) {
+        const unsigned long long old = atomicCAS(&set[h], ~0ull, (unsigned long long)key);
+        if (old == ~0ull) return true;
+        if (old == key) return false;
+        h = (h + 1) & (kRowSetSlots - 1);
+    }
+    return true;
+}
+
 // Relabel one direction of each record through the parents: (x, y) is taken when
 // (x < y) differs from the parity of x + y, which takes exactly one of (x, y) and (y, x) and
 // about half of every row's records, so all rows advance through the columns at the same
@@ -390,7 +417,16 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
     __shared__ uint32_t lpar[1 << kTxShiftMax];
     __shared__ uint32_t lds[kTRowThreads / kWave + 1];
     __shared__ u64c sbase;
+    __shared__ unsigned long long rset[kRowSetSlots];
+    __shared__ uint32_t set_tries, set_drops, set_on;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->keys_dense = 1;
+    for (int i = threadIdx.x; i < kRowSetSlots; i += kTRowThreads) rset[i] = ~0ull;   // no key has all bits set
+    if (threadIdx.x == 0) {
+        set_tries = 0;
+        set_drops = 0;
+        set_on = 1;
+    }
+    __syncthreads();
     const int64_t T = (int64_t)st->t_count;
     const int64_t nt = tiles_b_of(st);
     const int64_t n = (int64_t)st->n_cur;
@@ -398,7 +434,7 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
     uint64_t *out = w.keys[0];
     const int kb = st->kb;
     const int hbs = st->hb_shift;
-    uint32_t kept = 0;
+    uint32_t survived = 0;   // this thread's survivors (repeats counted)
     bool broken = false;
     // one workgroup per row of [row0, row0 + gridDim.x)
     const int row_end = min(tp.rows, row0 + (int)gridDim.x);
@@ -427,7 +463,8 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
                 pb[q] = v[q] ? w.par[y] : 0u;
             }
             uint64_t key[2 * kPairs];
-            uint32_t c = 0;
+            uint32_t c = 0, tries = 0, drops = 0;
+            const bool use_set = set_on != 0;   // read without a barrier: either value is valid
 #pragma unroll
             for (int q = 0; q < 2 * kPairs; ++q) {
                 const int64_t xi = (int64_t)(uint32_t)(r[q] >> 32) - base;
@@ -441,12 +478,26 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
                     }
                 }
                 v[q] = v[q] && pa != pb[q];
+                survived += v[q];
                 const uint32_t lo = min(pa, pb[q]), hi = max(pa, pb[q]);
                 key[q] = edge_key(lo, hi, kb, hbs);
+                if (use_set && v[q]) {
+                    ++tries;
+                    if (!row_set_insert(rset, key[q])) {
+                        v[q] = false;
+                        ++drops;
+                    }
+                }
                 c += v[q];
             }
+            if (tries) {
+                atomicAdd(&set_tries, tries);
+                if (drops) atomicAdd(&set_drops, drops);
+            }
             uint32_t total;
-            const uint32_t off = block_excl_scan<kTRowThreads>(c, lds, &total);
+            const uint32_t off = block_excl_scan<kTRowThreads>(c, lds, &total);   // (its barriers also
+                                                                                  // order the counts above)
+            if (threadIdx.x == 0 && set_on && set_tries >= kRowSetTrial && 16 * set_drops < set_tries) set_on = 0;
             if (total == 0) continue;
             if (threadIdx.x == 0) sbase = atomicAdd(&st->s_keys, (u64c)total);
             __syncthreads();
@@ -455,11 +506,11 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
             for (int q = 0; q < 2 * kPairs; ++q) {
                 if (v[q]) *dst++ = key[q];
             }
-            kept += total;
         }
         __syncthreads();   // lpar is rewritten for the next row
     }
-    if (threadIdx.x == 0 && kept) atomicAdd(&st->s_count, (u64c)kept);
+    survived = block_sum<kTRowThreads>(survived, lds);
+    if (threadIdx.x == 0 && survived) atomicAdd(&st->s_count, (u64c)survived);
     if (broken) atomicOr(&st->err, 4u);
 }
 
