@@ -244,7 +244,7 @@ cc_status cc_set_merge_to_large(cc_ctx *ctx, const int64_t *h_alphas, int32_t co
 
 /*
  * Explicit priorities (needs CC_EXPLICIT_PRIO at cc_create).  A test hook for the
- * definition's "any ordering" (Section 3: rho is a random ordering of the nodes): from round
+ * definition, under which the ordering may be any one-to-one map (Section 3): from round
  * r on, until a later round has a table of its own, the priority of node name x is d_prio[x]
  * instead of the seeded hash; rounds before the first table use the hash.  d_prio is
  * uint32[n_vertices], device memory borrowed until cc_destroy or a replacing call for the
