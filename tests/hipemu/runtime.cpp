@@ -7,6 +7,7 @@
 // deadlock and aborts the process with a message that names the kernel's state.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -237,19 +238,37 @@ void run_grid(const std::function<void()> &body, dim3 grid, dim3 block) {
     t_block_dim = block;
     t_grid_dim = grid;
     g_group = &g;
-    for (uint32_t bz = 0; bz < grid.z; ++bz)
-        for (uint32_t by = 0; by < grid.y; ++by)
-            for (uint32_t bx = 0; bx < grid.x; ++bx) {
-                t_block_idx = dim3(bx, by, bz);
-                for (size_t i = 0; i < nt; ++i) {
-                    Fiber &f = g.fibers[i];
-                    f.item = Item{};
-                    f.item.tid = dim3((uint32_t)(i % block.x), (uint32_t)((i / block.x) % block.y),
-                                      (uint32_t)(i / ((size_t)block.x * block.y)));
-                    init_fiber(f, g_stacks[i]);
-                }
-                run_group(g);
-            }
+    // Workgroups run one after another, in an order set by HIPEMU_BLOCK_ORDER: "forward"
+    // (default), "reverse", or a number seeding a shuffle.  Results that depend on the order
+    // in which workgroups run (which the GPU does not fix) show up as differences between
+    // orders.
+    const size_t nb = (size_t)grid.x * grid.y * grid.z;
+    std::vector<size_t> order(nb);
+    for (size_t b = 0; b < nb; ++b) order[b] = b;
+    const char *mode = getenv("HIPEMU_BLOCK_ORDER");
+    if (mode && strcmp(mode, "reverse") == 0) {
+        std::reverse(order.begin(), order.end());
+    } else if (mode && strcmp(mode, "forward") != 0 && *mode) {
+        uint64_t x = strtoull(mode, nullptr, 0) * 0x9E3779B97F4A7C15ull + 1;
+        for (size_t b = nb; b > 1; --b) {   // Fisher-Yates with an xorshift stream
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            std::swap(order[b - 1], order[(size_t)(x % b)]);
+        }
+    }
+    for (size_t b : order) {
+        t_block_idx = dim3((uint32_t)(b % grid.x), (uint32_t)((b / grid.x) % grid.y),
+                           (uint32_t)(b / ((size_t)grid.x * grid.y)));
+        for (size_t i = 0; i < nt; ++i) {
+            Fiber &f = g.fibers[i];
+            f.item = Item{};
+            f.item.tid = dim3((uint32_t)(i % block.x), (uint32_t)((i / block.x) % block.y),
+                              (uint32_t)(i / ((size_t)block.x * block.y)));
+            init_fiber(f, g_stacks[i]);
+        }
+        run_group(g);
+    }
     g_group = nullptr;
 }
 

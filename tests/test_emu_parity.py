@@ -460,3 +460,52 @@ def test_emulated_merge_to_large_arguments(cc):
         with pytest.raises(cc.CCError) as e:
             hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_MERGE_TO_LARGE | rule)
         assert e.value.status == cc.CC_E_ARG
+
+
+# ---- order independence ------------------------------------------------------------------------
+
+ORDER_CHECK = r"""
+import sys
+sys.path[:0] = [%r, %r]
+import numpy as np, graphgen, oracle, hipemu
+cc = hipemu.binding()
+fails = []
+cases = [("rmat", graphgen.Graph(1 << 14, *graphgen.rmat(3, 14, 16 << 14)), cc.CC_ROUND0_TILED, 0),
+         ("paths", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0),
+         ("mtl", graphgen.er_with_paths(10, 3000, 9000, 20, 100), cc.CC_ROUND0_TILED, cc.CC_MERGE_TO_LARGE)]
+for name, g, flags, extra in cases:
+    want = oracle.run(g.n, g.src, g.dst, seed=5, variant="merge_to_large" if extra else "local", alphas=[3] if extra else None)
+    with hipemu.Solver(g.n, hipemu.device(g.src, np.int32), hipemu.device(g.dst, np.int32), seed=5,
+                       flags=flags | extra) as s:
+        if extra:
+            s.set_merge_to_large([3])
+        r = s.run()
+        ok = r == want.rounds and [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats] and \
+            np.array_equal(s.labels().astype(np.uint32), want.labels)
+    if not ok:
+        fails.append(name)
+b = graphgen.batch_mix(seed=41, count=16, log2_min=4, log2_max=11)
+lab_w, rounds_w, _ = oracle.run_batch(b.voff, b.eoff, b.src, b.dst, b.seeds)
+with hipemu.Batch(b.voff, b.eoff, b.seeds, b.src, b.dst, small_variant=1) as bt:
+    lab, rounds = bt.run()
+    if not (np.array_equal(rounds, rounds_w) and np.array_equal(lab.astype(np.uint32), lab_w)):
+        fails.append("batch")
+print("FAILS", fails)
+"""
+
+
+@pytest.mark.parametrize("order", ["reverse", "12345", "777"])
+def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
+    """The same solves with the workgroups of every launch run in reverse or shuffled order:
+    atomics, cursors and the relabel's key sets then see other interleavings, and the results
+    must not change."""
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = ORDER_CHECK % (os.path.dirname(here), here)
+    env = dict(os.environ, HIPEMU_BLOCK_ORDER=order)
+    proc = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                          text=True, timeout=600)
+    assert proc.returncode == 0, proc.stderr[-2000:]
+    assert "FAILS []" in proc.stdout, proc.stdout
