@@ -154,8 +154,8 @@ typedef struct {
     int64_t m_sorted;     /* keys this round's duplicate drop processed (a radix sort, or from
                              round 1 on a hashed key set when at most 2^22 of them): m_survive
                              less the repeats each relabel workgroup recognised itself (an LDS
-                             key set per workgroup, in every round but a round 0 that reads the
-                             input directly; launch-dependent, not a property of the method) */
+                             key set per workgroup; launch-dependent, not a property of the
+                             method) */
 } cc_round_stats;
 
 typedef struct cc_ctx cc_ctx;

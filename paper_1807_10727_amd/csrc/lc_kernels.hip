@@ -271,17 +271,25 @@ constexpr unsigned long long kNoKey = ~0ull;   // no sort key has all 64 bits se
 
 // False when `key` is in the set already; true when it was added now, or when its probes
 // all met other keys (the key is then written again: later passes drop any repeat).
+template <int kLog2 = kDedupLog2>
 __device__ inline bool set_insert(unsigned long long *set, uint64_t key) {
     if (key == kNoKey) return true;
-    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kDedupLog2));
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kLog2));
     for (int p = 0; p < kDedupProbes; ++p) {
         const unsigned long long old = atomicCAS(&set[h], kNoKey, (unsigned long long)key);
         if (old == kNoKey) return true;
         if (old == key) return false;
-        h = (h + 1) & (kDedupSlots - 1);
+        h = (h + 1) & ((1 << kLog2) - 1);
     }
     return true;
 }
+
+// Round 0 read directly from the caller's records: the same per-workgroup set, smaller (the
+// unsorted records repeat only on power-law inputs), switched off by a workgroup once
+// kInputSetTrial of its keys found fewer than 1/16 repeats (uniform random inputs, where the
+// probes would cost more than they save).
+constexpr int kInputSetLog2 = 11;
+constexpr uint32_t kInputSetTrial = 4096;
 
 // Relabel every record through the parents and keep the loop-free ones as sort keys
 // (edge_key of (min, max) of the two parents).  Each workgroup owns a slab of kSlab
@@ -290,22 +298,29 @@ __device__ inline bool set_insert(unsigned long long *set, uint64_t key) {
 // slower: the first chunks of every workgroup all write and contend on it).  slab_cnt holds
 // the keys per slab; the first radix pass reads the slabs.
 //
-// On sorted records (rounds >= 1) a workgroup also drops every key it has written before:
-// a dense region that contracts onto a few parents maps many records onto the same parent
-// pairs, and a hash set in LDS (kept for the whole launch) removes most of those repeats
-// before they reach the sort.  s_count still counts every survivor; s_keys counts the keys.
+// A workgroup also drops every key it has written before: a dense region that contracts
+// onto a few parents maps many records onto the same parent pairs (rounds >= 1, and round 0
+// of power-law inputs), and a hash set in LDS (kept for the whole launch) removes most of
+// those repeats before they reach the sort.  s_count still counts every survivor; s_keys
+// counts the keys.
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     constexpr int V = R::kV;
-    constexpr bool kDedup = R::kSorted;
+    constexpr bool kDedup = true;
+    constexpr bool kAdaptive = !R::kSorted;
+    constexpr int kSetLog2 = R::kSorted ? kDedupLog2 : kInputSetLog2;
     constexpr int64_t kChunksPerSlab = kSlab / V;
     RoundState *st = w.st;
     __shared__ uint32_t lds[kThreads / kWave + 1];
-    __shared__ unsigned long long set[kDedup ? kDedupSlots : 1];
-    if (kDedup) {
-        for (int i = threadIdx.x; i < kDedupSlots; i += kThreads) set[i] = kNoKey;
-        __syncthreads();
+    __shared__ unsigned long long set[1 << kSetLog2];
+    __shared__ uint32_t set_tries, set_drops, set_on;
+    for (int i = threadIdx.x; i < (1 << kSetLog2); i += kThreads) set[i] = kNoKey;
+    if (threadIdx.x == 0) {
+        set_tries = 0;
+        set_drops = 0;
+        set_on = 1;
     }
+    __syncthreads();
     rd.init(st);
     const int64_t nch = rd.chunks();
     const int64_t nslabs = ceil_div(rd.records(), kSlab);
@@ -327,7 +342,8 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
             const int64_t c = cb + threadIdx.x;
             uint64_t key[V];
             bool keep[V];
-            uint32_t cnt = 0;
+            uint32_t cnt = 0, tries = 0, drops = 0;
+            const bool use_set = !kAdaptive || set_on != 0;   // read without a barrier: either value is valid
             if (c < c_end) {
                 uint32_t a[V], b[V], pa[V], pb[V];
                 rd.read(c, a, b, bad);
@@ -342,15 +358,26 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
                     survived += keep[j];
                     const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
                     key[j] = edge_key(lo, hi, kb, hbs);
-                    if (kDedup && keep[j]) keep[j] = set_insert(set, key[j]);
+                    if (kDedup && use_set && keep[j]) {
+                        ++tries;
+                        keep[j] = set_insert<kSetLog2>(set, key[j]);
+                        drops += !keep[j];
+                    }
                     cnt += keep[j];
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < V; ++j) keep[j] = false;
             }
+            if (kAdaptive && tries) {
+                atomicAdd(&set_tries, tries);
+                if (drops) atomicAdd(&set_drops, drops);
+            }
             uint32_t total;
-            uint32_t off = cursor + block_excl_scan<kThreads>(cnt, lds, &total);
+            uint32_t off = cursor + block_excl_scan<kThreads>(cnt, lds, &total);   // (its barriers also order
+                                                                                // the counts above)
+            if (kAdaptive && threadIdx.x == 0 && set_on && set_tries >= kInputSetTrial && 16 * set_drops < set_tries)
+                set_on = 0;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 if (keep[j]) dst[off++] = key[j];

@@ -509,3 +509,20 @@ def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
                           text=True, timeout=600)
     assert proc.returncode == 0, proc.stderr[-2000:]
     assert "FAILS []" in proc.stdout, proc.stdout
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled"])
+def test_emulated_round0_key_sets(cc, mode):
+    """Round 0 on a power-law graph: the relabel workgroups' key sets drop most repeated keys
+    before the sort (m_sorted well below m_survive), and everything the method defines is
+    unchanged; on a uniform random graph the sets switch themselves off early."""
+    g = graphgen.Graph(1 << 15, *graphgen.rmat(21, 15, 16 << 15))
+    want = check_solve(cc, g, 17, flags={"direct": DIRECT, "tiled": TILED}[mode], per_round=False)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=17, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+        s.contract_round()
+        assert cc.cc_get_round_sorted(s.ctx, 0) * 4 < want.stats[0][3]
+    u = graphgen.Graph(1 << 15, *graphgen.gnm(22, 1 << 15, 1 << 17))
+    want = oracle.run(u.n, u.src, u.dst, seed=17)
+    with hipemu.Solver(u.n, dev(u.src), dev(u.dst), seed=17, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+        s.contract_round()
+        assert cc.cc_get_round_sorted(s.ctx, 0) > 0.9 * want.stats[0][3]
