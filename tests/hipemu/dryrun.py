@@ -2,6 +2,7 @@
 
     python tests/hipemu/dryrun.py bench <bench.py arguments>
     python tests/hipemu/dryrun.py smoke
+    python tests/hipemu/dryrun.py pytest <pytest arguments>
 
 The process installs the numpy stand-in for torch (faketorch.py) and binds the package's
 ctypes module to the emulated library before anything imports them, so the benchmark's and the
@@ -33,6 +34,10 @@ def main():
     elif what == "smoke":
         import __graft_entry__
         __graft_entry__.smoke()
+    elif what == "pytest":
+        # GPU tests' own logic against the emulated library (toy sizes only: they are slow here)
+        import pytest
+        raise SystemExit(pytest.main(sys.argv[2:]))
     else:
         raise SystemExit("usage: dryrun.py bench|smoke [arguments]")
 

@@ -121,6 +121,17 @@ def from_numpy(a):
     return Tensor(a)
 
 
+def tensor(values, dtype=None, device=None):
+    a = _aligned_empty(len(values), dtype)
+    a[...] = np.asarray(values, dtype=a.dtype)
+    return Tensor(a, device)
+
+
+def arange(a, b=None, device=None, dtype=None):
+    lo, hi = (0, a) if b is None else (a, b)
+    return Tensor(np.arange(lo, hi, dtype=_np_dtype(dtype) if dtype is not None else np.int64), device)
+
+
 def equal(x, y):
     return bool(x.a.shape == y.a.shape and np.array_equal(x.a, y.a))
 

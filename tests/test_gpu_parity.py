@@ -304,9 +304,9 @@ def test_heavy_repeats_and_hub(lc, case, mode):
 def test_relabel_drops_workgroup_repeats(lc, mode, seed):
     """G(2^15, 2^18), seeds whose round 1 maps 3,100-4,600 survivors onto five or fewer
     parent pairs.  The relabel workgroups drop the repeats they recognise themselves before
-    the sort: the keys sorted lie between the distinct edges out and the survivors (all
-    survivors in round 0), far fewer than the survivors in round 1, and rounds, statistics
-    and labels stay bit-exact with the oracle."""
+    the sort: the keys sorted lie between the distinct edges out and the survivors, far fewer
+    than the survivors in round 1, and rounds, statistics and labels stay bit-exact with the
+    oracle."""
     g = graphgen.Graph(1 << 15, *graphgen.gnm(31, 1 << 15, 1 << 18))
     s_t, d_t, _ = to_device(g)
     with lc.Solver(g.n, s_t, d_t, seed=seed, flags=MODES[mode] | lc.CC_EAGER) as s:
@@ -317,7 +317,6 @@ def test_relabel_drops_workgroup_repeats(lc, mode, seed):
     want = oracle.run(g.n, g.src, g.dst, seed=seed)
     assert r == want.rounds and st == [tuple(x) for x in want.stats]
     np.testing.assert_array_equal(lab.astype(np.uint32), want.labels)
-    assert ks[0] == st[0][3]
     for x, k in zip(st, ks):
         assert x[4] <= k <= x[3]
     assert st[1][3] > 1000 and ks[1] * 10 < st[1][3]
