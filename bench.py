@@ -455,6 +455,7 @@ def main():
     ap.add_argument("--batch-log2-max", type=int, default=18)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: none, tune every run)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the solver's default knobs (no autotuning)")
     ap.add_argument("--verbose-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-only", action="store_true")
@@ -515,11 +516,31 @@ def main():
     flags = 0 if args.no_profile else lc.CC_PROFILE
     if args.eager:
         flags |= lc.CC_EAGER
-    flags |= {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED}[args.round0]
+    round0_flag = {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED}[args.round0]
+    flags |= round0_flag
     stream = torch.cuda.current_stream(dev)
     base_seed = graphgen.CONFIG_SEED_BASE + 1
+
+    # The solver's knobs (form of round 0, workgroups per CU, round 0's key sets) are tuned on
+    # this graph first, without per-kernel events; every candidate must give the same labels.
+    tuning = None
+    if not args.no_tune:
+        from paper_1807_10727_amd import autotune
+        space = dict(autotune.SOLVER_SPACE)
+        if args.round0 != "auto":
+            space.pop("round0")
+        t0 = time.perf_counter()
+        with lc.Solver(n0, src, dst, seed=base_seed, flags=round0_flag, stream=stream, layout=layout) as ts:
+            tuning, t_best, tried = autotune.tune_solver(ts, seed=base_seed + 500, repeats=1, cache=args.tune_cache,
+                                                         log=log if args.verbose_tune else None, space=space)
+        torch.cuda.empty_cache()
+        log("solver autotune picked %s (%d candidates timed, best %.3f ms, %.1fs)"
+            % (tuning, tried, t_best * 1e3, time.perf_counter() - t0))
+
     labels = torch.empty(n0, dtype=torch.int32, device=dev)
     solver = lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout)
+    if tuning:
+        solver.set_tuning(**tuning)
     log("workspace %.2f GiB" % (solver.ws_bytes / 2**30))
 
     def step(i):
@@ -676,7 +697,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": wname, "n_vertices": n0, "n_records": m0, "rounds": rounds[0],
-                   "round0": args.round0, "parallelism": "single GPU"},
+                   "round0": args.round0, "tuning": tuning, "parallelism": "single GPU"},
         "roofline": roofline,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "job_alg_frac_of_copy": round(job_gbs / copy_gbs, 4),

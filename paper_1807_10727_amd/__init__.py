@@ -20,7 +20,7 @@ from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, 
                   CC_EAGER, CC_EXPLICIT_PRIO, CC_MERGE_TO_LARGE, CC_ONE_HOP, CC_PROFILE, CC_RECORD_ROUNDS,
                   CC_ROUND0_DIRECT,
                   CC_ROUND0_TILED, CC_TREE, CCError, cc_debug_round_arrays, cc_load_state, cc_save_state,
-                  cc_set_explicit_priorities, cc_set_merge_to_large,
+                  cc_set_explicit_priorities, cc_set_merge_to_large, cc_get_tuning, cc_set_tuning,
                   cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
                   cc_labels, cc_last_error, cc_reset, cc_round_edges, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
                   cc_set_workspace, cc_version, cc_workspace_size)
@@ -71,6 +71,15 @@ class Solver:
         cc_set_workspace(self.ctx, self.ws.data_ptr(), self.ws_bytes)
         if finish_edges:
             cc_set_finish(self.ctx, finish_edges)
+
+    def set_tuning(self, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1) -> None:
+        """Tuning knobs (include/cc.h, cc_tuning); resets the solve.  A tiled round 0 needs a
+        workspace sized for it: the one this object allocated when the context chose it."""
+        cc_set_tuning(self.ctx, round0, blocks_per_cu, round0_key_sets)
+
+    @property
+    def tuning(self) -> dict:
+        return cc_get_tuning(self.ctx)
 
     def set_finish(self, max_edges: int) -> None:
         """Union-find finish once a round leaves at most max_edges edges (0: off)."""

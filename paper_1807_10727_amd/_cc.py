@@ -54,6 +54,14 @@ class cc_round_stats(ctypes.Structure):
         return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
 
 
+class cc_tuning(ctypes.Structure):
+    _fields_ = [("round0", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("round0_key_sets", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"round0": self.round0, "blocks_per_cu": self.blocks_per_cu, "round0_key_sets": self.round0_key_sets}
+
+
 class cc_batch_config(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("small_variant", ctypes.c_int32),
                 ("small_threads", ctypes.c_int32), ("small_blocks_per_cu", ctypes.c_int32),
@@ -93,6 +101,8 @@ _sig = {
     "cc_workspace_size": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_size_t)]),
     "cc_set_workspace": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p, ctypes.c_size_t]),
     "cc_reset": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
+    "cc_set_tuning": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_tuning)]),
+    "cc_get_tuning": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_tuning)]),
     "cc_contract_round": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_round_stats)]),
     "cc_run": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(ctypes.c_int32)]),
     "cc_labels": (ctypes.c_int32, [_ctx_p, ctypes.c_void_p]),
@@ -182,6 +192,17 @@ def cc_set_workspace(ctx, ptr: int, nbytes: int) -> None:
 
 def cc_reset(ctx, seed: int) -> None:
     _check(ctx, _lib.cc_reset(ctx, seed & 0xFFFFFFFFFFFFFFFF))
+
+
+def cc_set_tuning(ctx, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1) -> None:
+    t = cc_tuning(int(round0), int(blocks_per_cu), int(round0_key_sets), 0)
+    _check(ctx, _lib.cc_set_tuning(ctx, ctypes.byref(t)))
+
+
+def cc_get_tuning(ctx) -> dict:
+    t = cc_tuning()
+    _check(ctx, _lib.cc_get_tuning(ctx, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def cc_contract_round(ctx):

@@ -1,11 +1,11 @@
-"""Autotuner for the batched solve.
+"""Autotuners for the batched and the single-graph solves.
 
 The knobs of ``cc_batch_config`` (grid size of the streaming kernels, the LDS solver's
-size limits, workgroup size and persistence) change only speed: every candidate must give
-bit-identical labels, and the tuner checks that.  Candidates are timed on the batch
-itself (or on a caller-chosen sample of the same mix), coordinate by coordinate, and the
-winner is cached as JSON under a key made of the device (architecture, CU count) and the
-batch's size class (log2 of its graph and record counts).
+size limits, workgroup size and persistence) and of ``cc_tuning`` (the form of round 0,
+workgroups per compute unit, round 0's key sets) change only speed: every candidate must
+give bit-identical labels, and the tuner checks that.  Candidates are timed on the batch or
+the graph itself, coordinate by coordinate, and the winner is cached as JSON under a key made
+of the device (architecture, CU count) and the size class (log2 of the counts).
 """
 from __future__ import annotations
 
@@ -102,6 +102,78 @@ def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, s
             if t < best_t:
                 best_t, cfg = t, cand
         batch.configure(**cfg)
+    if cache:
+        data = _load(cache)
+        data[key] = {"config": cfg, "seconds": best_t}
+        _store(cache, data)
+    return cfg, best_t, tried
+
+
+# ---- single-graph solve ------------------------------------------------------------------
+
+SOLVER_SPACE = {
+    "round0": [1, 2],                  # direct, tiled (where the context can take it)
+    "blocks_per_cu": [4, 8, 16],
+    "round0_key_sets": [1, 0],
+}
+
+
+def solver_size_class(solver) -> str:
+    return "n2^%d:m2^%d" % (max(0, round(math.log2(max(solver.n, 1)))), max(0, round(math.log2(max(solver.m, 1)))))
+
+
+def _time_solver(solver, seed, repeats):
+    import torch
+    best = float("inf")
+    digest = None
+    for i in range(repeats + 1):       # the first run warms the candidate (and its kernels)
+        solver.reset(seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.run()
+        lab = solver.labels()
+        torch.cuda.synchronize()
+        if i:
+            best = min(best, time.perf_counter() - t0)
+        if digest is None:
+            digest = hashlib.sha1(lab.cpu().numpy().tobytes()).hexdigest()
+    return best, digest
+
+
+def tune_solver(solver, seed: int = 0, repeats: int = 1, cache: str | None = DEFAULT_CACHE, log=None, space=None):
+    """Pick the fastest ``cc_tuning`` for `solver` (a paper_1807_10727_amd.Solver whose
+    workspace was sized for its default form), apply it and return (tuning dict, seconds of
+    the best solve, number of candidates timed).  Each candidate solves the graph with `seed`
+    and must give the labels of the first one."""
+    key = "solver|%s|%s" % (device_key(), solver_size_class(solver))
+    if cache:
+        hit = _load(cache).get(key)
+        if hit:
+            solver.set_tuning(**hit["config"])
+            return hit["config"], hit["seconds"], 0
+    space = space or SOLVER_SPACE
+    cfg = dict(solver.tuning)
+    solver.set_tuning(**cfg)
+    best_t, ref = _time_solver(solver, seed, repeats)
+    tried = 1
+    for knob, values in space.items():
+        for v in values:
+            if v == cfg[knob]:
+                continue
+            cand = dict(cfg, **{knob: v})
+            try:
+                solver.set_tuning(**cand)
+            except Exception:          # e.g. a tiled round 0 the context cannot take
+                continue
+            t, digest = _time_solver(solver, seed, repeats)
+            tried += 1
+            if digest != ref:
+                raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+            if log:
+                log("  tune %-16s %s -> %.3f ms" % (knob, v, t * 1e3))
+            if t < best_t:
+                best_t, cfg = t, cand
+        solver.set_tuning(**cfg)
     if cache:
         data = _load(cache)
         data[key] = {"config": cfg, "seconds": best_t}

@@ -166,7 +166,6 @@ struct cc_batch : public lc::Engine {
     const int32_t *d_src = nullptr, *d_dst = nullptr;
     cc_options o{};
     cc_batch_config cfg{};
-    int cus = 256;
     size_t max_lds = 65536;
     // device arrays carved after the union workspace
     int64_t *d_voff64 = nullptr, *d_eoff64 = nullptr, *d_ubase = nullptr;

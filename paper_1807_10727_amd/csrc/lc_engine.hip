@@ -172,7 +172,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gt = grid_tiles(M);
     // the scatter keeps LC_SCATTER_WAVES waves per SIMD resident (four-wave workgroups): a grid
     // of exactly that many workgroups runs in one go instead of a resident share and a tail
-    const int gt_scatter = LC_SCATTER_GRID ? std::min(gt, std::max(1, grid_cap / 8 * LC_SCATTER_WAVES)) : gt;
+    const int gt_scatter = LC_SCATTER_GRID ? std::min(gt, std::max(1, cus * LC_SCATTER_WAVES)) : gt;
     const int gscan_l = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), 32 * kThreads), grid_cap);
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = 2 * kb;   // edge_key
@@ -210,9 +210,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         else if (variant == kVarOneHop)
             RUN(kParent, launch_tiled_parent1(w, pc, gn, stream));
         else
-            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, grid_cap / 8));
+            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, cus));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
-        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, grid_cap / 8));
+        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, cus));
     } else if (mtl_mode == 2) {   // MergeToLarge step (rounds >= 1 only)
         RUN(kMergeLarge, launch_mtl_labels(w, mtl_alpha, gn, gm, stream));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
@@ -683,7 +683,8 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     c->in.vec = aligned ? 1 : 0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    c->grid_cap = std::max(cus, 1) * 8;
+    c->cus = std::max(cus, 1);
+    c->grid_cap = c->cus * 8;
     if (hipHostMalloc((void **)&c->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
         // no usable device yet: a pageable mirror still works for every later copy
         (void)hipGetLastError();
@@ -720,7 +721,41 @@ cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
     c->ws = d_ws;
     c->ws_bytes = bytes;
     plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)d_ws, &c->w, ws_extras(c->o.flags));
+    c->w.round0_sets_off = c->round0_sets_off ? 1 : 0;
+    drop_tails(c);   // captured tails hold pointers into the previous workspace
     return reset_solve(c, c->o.seed);
+}
+
+cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
+    if (!c || !t) return CC_E_ARG;
+    if (t->round0 < 0 || t->round0 > 2 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
+        (t->round0_key_sets != 0 && t->round0_key_sets != 1) || t->reserved != 0)
+        return reject(c, CC_E_ARG, "tuning value out of range");
+    const bool tiled = t->round0 == 0 ? c->tiled : t->round0 == 2;
+    if (tiled && (!tiled_fits(c->g.n_vertices) || (c->o.flags & CC_EXPLICIT_PRIO)))
+        return reject(c, CC_E_ARG, "the tiled round 0 does not apply to this context");
+    const size_t need =
+        plan_workspace(c->g.n_vertices, c->g.n_edges, false, tiled, nullptr, nullptr, ws_extras(c->o.flags));
+    if (c->ws && c->ws_bytes < need) return reject(c, CC_E_NOMEM, "the workspace is too small for that round-0 form");
+    c->tiled = tiled;
+    c->ws_need = need;
+    c->blocks_per_cu = t->blocks_per_cu ? t->blocks_per_cu : 8;
+    c->grid_cap = c->cus * c->blocks_per_cu;
+    c->round0_sets_off = t->round0_key_sets == 0;
+    drop_tails(c);   // captured with the previous grid sizes and layout
+    if (!c->ws) return CC_OK;
+    plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)c->ws, &c->w, ws_extras(c->o.flags));
+    c->w.round0_sets_off = c->round0_sets_off ? 1 : 0;
+    return reset_solve(c, c->o.seed);
+}
+
+cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
+    if (!c || !t) return CC_E_ARG;
+    t->round0 = c->tiled ? 2 : 1;
+    t->blocks_per_cu = c->blocks_per_cu;
+    t->round0_key_sets = c->round0_sets_off ? 0 : 1;
+    t->reserved = 0;
+    return CC_OK;
 }
 
 cc_status cc_reset(cc_ctx *c, uint64_t seed) {

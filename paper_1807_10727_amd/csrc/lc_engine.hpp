@@ -45,7 +45,10 @@ struct Engine {
     bool profile = false;
     uint64_t prof_mask = ~0ull;   // families timed under CC_PROFILE (bit i: family i)
     bool done = false;
-    int grid_cap = 2048;
+    int grid_cap = 2048;          // workgroups of the grid-stride kernels (CUs x blocks per CU)
+    int cus = 256;                // compute units (row generations, resident scatter grid)
+    int blocks_per_cu = 8;        // tuning: grid_cap = cus * blocks_per_cu
+    bool round0_sets_off = false; // tuning: round 0's relabel without key sets
     void *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state

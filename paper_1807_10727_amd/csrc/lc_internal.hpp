@@ -128,6 +128,7 @@ struct Work {
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
     int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
     int64_t n0, m0;
+    int32_t round0_sets_off;   // 1: round 0's relabel workgroups keep no key set (tuning)
 };
 
 constexpr int kThreads = 256;                      // workgroup size of the streaming kernels

@@ -343,7 +343,8 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
             uint64_t key[V];
             bool keep[V];
             uint32_t cnt = 0, tries = 0, drops = 0;
-            const bool use_set = !kAdaptive || set_on != 0;   // read without a barrier: either value is valid
+            // read without a barrier: either value is valid
+            const bool use_set = !kAdaptive || (set_on != 0 && !w.round0_sets_off);
             if (c < c_end) {
                 uint32_t a[V], b[V], pa[V], pb[V];
                 rd.read(c, a, b, bad);

@@ -464,7 +464,8 @@ __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp
             }
             uint64_t key[2 * kPairs];
             uint32_t c = 0, tries = 0, drops = 0;
-            const bool use_set = set_on != 0;   // read without a barrier: either value is valid
+            const bool use_set = set_on != 0 && !w.round0_sets_off;   // read without a barrier: either
+                                                                        // value is valid
 #pragma unroll
             for (int q = 0; q < 2 * kPairs; ++q) {
                 const int64_t xi = (int64_t)(uint32_t)(r[q] >> 32) - base;

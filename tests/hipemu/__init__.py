@@ -167,6 +167,13 @@ class Solver:
         self._tables[int(r)] = t
         self.cc.cc_set_explicit_priorities(self.ctx, r, t.ctypes.data)
 
+    def set_tuning(self, **kw):
+        self.cc.cc_set_tuning(self.ctx, **kw)
+
+    @property
+    def tuning(self):
+        return self.cc.cc_get_tuning(self.ctx)
+
     def set_merge_to_large(self, alphas):
         self.cc.cc_set_merge_to_large(self.ctx, alphas)
 

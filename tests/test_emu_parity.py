@@ -526,3 +526,33 @@ def test_emulated_round0_key_sets(cc, mode):
     with hipemu.Solver(u.n, dev(u.src), dev(u.dst), seed=17, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
         s.contract_round()
         assert cc.cc_get_round_sorted(s.ctx, 0) > 0.9 * want.stats[0][3]
+
+
+# ---- tuning knobs ------------------------------------------------------------------------------
+
+def test_emulated_tuning_knobs_keep_results(cc):
+    """Every cc_tuning setting (round-0 form, workgroups per CU, round 0's key sets) gives the
+    oracle's results; impossible settings are refused."""
+    g = graphgen.Graph(1 << 15, *graphgen.rmat(4, 15, 8 << 15))
+    want = oracle.run(g.n, g.src, g.dst, seed=3)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=TILED) as s:
+        for r0 in (1, 2):
+            for bpc in (1, 4, 16):
+                for ks in (1, 0):
+                    s.set_tuning(round0=r0, blocks_per_cu=bpc, round0_key_sets=ks)
+                    assert s.tuning == {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
+                    r = s.run()
+                    assert r == want.rounds
+                    assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+                    np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+        with pytest.raises(cc.CCError) as e:
+            s.set_tuning(blocks_per_cu=65)
+        assert e.value.status == cc.CC_E_ARG
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=DIRECT) as s:   # workspace sized for direct
+        with pytest.raises(cc.CCError) as e:
+            s.set_tuning(round0=2)
+        assert e.value.status == cc.CC_E_NOMEM
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), flags=cc.CC_EXPLICIT_PRIO) as s:
+        with pytest.raises(cc.CCError) as e:
+            s.set_tuning(round0=2)
+        assert e.value.status == cc.CC_E_ARG
