@@ -44,7 +44,8 @@ FAMILY_STEP = {
     "node_scan": "a6_nodes", "nodes": "a6_nodes", "map": "a6_nodes", "round_end": "a6_nodes",
     "compose": "a7_labels", "flatten": "a7_labels",
     "part_a_hist": "partition", "part_a_scatter": "partition", "part_b_hist": "partition",
-    "part_b_scatter": "partition", "part_scan": "partition",
+    "part_b_scatter": "partition", "part_scan": "partition", "part_rows_hist": "partition",
+    "part_rows_scatter": "partition",
     "tail_graph": "tail", "uf_finish": "finish", "merge_large": "merge_large",
 }
 

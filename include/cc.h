@@ -191,7 +191,10 @@ cc_status cc_reset(cc_ctx *ctx, uint64_t seed);
 typedef struct {
     int32_t round0;           /* 0: keep the current form; 1: round 0 reads the records directly;
                                  2: round 0 over the tiled layout (needs n_vertices <= 2^26, no
-                                 CC_EXPLICIT_PRIO, and a workspace sized for it) */
+                                 CC_EXPLICIT_PRIO, and a workspace sized for it); 3: as 2, but the
+                                 records reach their rows in one partition pass, unordered inside
+                                 a row (two passes over the records fewer, less L2 locality in the
+                                 row kernels' gathers; same conditions) */
     int32_t blocks_per_cu;    /* workgroups per compute unit of the grid-stride kernels (1..64); 0: 8 */
     int32_t round0_key_sets;  /* 1 (default): round 0's relabel workgroups drop the repeated keys they
                                  see through an LDS set; 0: they write every survivor */
@@ -203,7 +206,7 @@ typedef struct {
  * current seed does, and drops captured tails.  CC_E_ARG for a value out of range or a tiled
  * round 0 the context cannot take; CC_E_NOMEM when a workspace is set and is smaller than the
  * new form needs (cc_workspace_size reports the size for the current form).  cc_get_tuning
- * reports the knobs in force (round0 1 or 2).
+ * reports the knobs in force (round0 1, 2 or 3).
  */
 cc_status cc_set_tuning(cc_ctx *ctx, const cc_tuning *t);
 cc_status cc_get_tuning(const cc_ctx *ctx, cc_tuning *t);

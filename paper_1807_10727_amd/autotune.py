@@ -112,7 +112,8 @@ def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, s
 # ---- single-graph solve ------------------------------------------------------------------
 
 SOLVER_SPACE = {
-    "round0": [1, 2],                  # direct, tiled (where the context can take it)
+    "round0": [1, 2, 3],               # direct, tiled, tiled with the one-pass row partition
+                                       # (the tiled forms where the context can take them)
     "blocks_per_cu": [4, 8, 16],
     "round0_key_sets": [1, 0],
 }

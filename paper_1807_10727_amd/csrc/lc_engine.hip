@@ -27,7 +27,7 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large"};
+    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -194,16 +194,26 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         const int gb = (int)std::min<int64_t>(tp.tiles_b, grid_cap);
         const int gsa = (int)std::min<int64_t>(ceil_div(256 * tp.tiles_a, kScanTile), grid_cap);
         const int gsb = (int)std::min<int64_t>(ceil_div((int64_t)tp.rows * tp.tiles_b, kScanTile), grid_cap);
-        RUN(kPartAHist, launch_tiled_partition(w, in, tp, ga, stream, 0));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 1));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 2));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 3));
-        RUN(kPartAScatter, launch_tiled_partition(w, in, tp, ga, stream, 4));
-        RUN(kPartBHist, launch_tiled_partition(w, in, tp, gb, stream, 5));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 6));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 7));
-        RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 8));
-        RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
+        if (tiled_rows) {
+            const int gr = (int)std::min<int64_t>(tp.tiles_r, grid_cap);
+            const int gsr = (int)std::min<int64_t>(ceil_div((int64_t)tp.rows * tp.tiles_r, kScanTile), grid_cap);
+            RUN(kPartRowsHist, launch_tiled_partition(w, in, tp, gr, stream, 10));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsr, stream, 11));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 12));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsr, stream, 13));
+            RUN(kPartRowsScatter, launch_tiled_partition(w, in, tp, gr, stream, 14));
+        } else {
+            RUN(kPartAHist, launch_tiled_partition(w, in, tp, ga, stream, 0));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 1));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 2));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsa, stream, 3));
+            RUN(kPartAScatter, launch_tiled_partition(w, in, tp, ga, stream, 4));
+            RUN(kPartBHist, launch_tiled_partition(w, in, tp, gb, stream, 5));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 6));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, 1, stream, 7));
+            RUN(kPartScan, launch_tiled_partition(w, in, tp, gsb, stream, 8));
+            RUN(kPartBScatter, launch_tiled_partition(w, in, tp, gb, stream, 9));
+        }
         RUN(kMin1Tiled, launch_tiled_min1(w, pc, tp, stream, variant == kVarTree));
         if (variant == kVarTree)
             RUN(kParent, launch_tree_labels(w, pc, r, N, gn, stream, true));
@@ -728,16 +738,18 @@ cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
 
 cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     if (!c || !t) return CC_E_ARG;
-    if (t->round0 < 0 || t->round0 > 2 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
+    if (t->round0 < 0 || t->round0 > 3 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
         (t->round0_key_sets != 0 && t->round0_key_sets != 1) || t->reserved != 0)
         return reject(c, CC_E_ARG, "tuning value out of range");
-    const bool tiled = t->round0 == 0 ? c->tiled : t->round0 == 2;
+    const bool tiled = t->round0 == 0 ? c->tiled : t->round0 >= 2;
+    const bool rows = t->round0 == 0 ? c->tiled_rows : t->round0 == 3;
     if (tiled && (!tiled_fits(c->g.n_vertices) || (c->o.flags & CC_EXPLICIT_PRIO)))
         return reject(c, CC_E_ARG, "the tiled round 0 does not apply to this context");
     const size_t need =
         plan_workspace(c->g.n_vertices, c->g.n_edges, false, tiled, nullptr, nullptr, ws_extras(c->o.flags));
     if (c->ws && c->ws_bytes < need) return reject(c, CC_E_NOMEM, "the workspace is too small for that round-0 form");
     c->tiled = tiled;
+    c->tiled_rows = tiled && rows;
     c->ws_need = need;
     c->blocks_per_cu = t->blocks_per_cu ? t->blocks_per_cu : 8;
     c->grid_cap = c->cus * c->blocks_per_cu;
@@ -751,7 +763,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
 
 cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
     if (!c || !t) return CC_E_ARG;
-    t->round0 = c->tiled ? 2 : 1;
+    t->round0 = c->tiled ? (c->tiled_rows ? 3 : 2) : 1;
     t->blocks_per_cu = c->blocks_per_cu;
     t->round0_key_sets = c->round0_sets_off ? 0 : 1;
     t->reserved = 0;

@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kFamilies
+    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kPartRowsHist, kPartRowsScatter, kFamilies
 };
 
 // how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)
@@ -40,6 +40,7 @@ struct Engine {
     EdgeIn in{};
     bool batch = false;
     bool tiled = false;           // round 0 over the tiled record layout
+    bool tiled_rows = false;      // ... partitioned by row in one pass (no column order in a row)
     int variant = kVarLocal;
     TPlan tp{};
     bool profile = false;

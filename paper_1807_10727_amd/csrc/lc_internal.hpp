@@ -36,6 +36,7 @@ struct RoundState {
     int32_t hb_shift;  // next-round block of an endpoint: index >> hb_shift (kb: one block)
     int32_t keys_dense;  // the relabel wrote its keys packed at [0, s_keys) (else: in slabs)
     u64c t_count;      // round 0, tiled layout: directed records (twice the loop-free inputs)
+    u64c t_tiles;      // round 0, tiled layout: tiles of the row partition (its count table's columns)
     uint64_t seed;     // priority seed of a plain solve
     RoundKey key;      // this round's priority key, round_key(seed, round) (plain solve)
     int32_t rounds_active;   // rounds so far that read at least one record
@@ -247,12 +248,14 @@ struct TPlan {
     int32_t rows, cols;  // row blocks (<= kTRowsMax), column blocks (<= 256)
     int64_t tiles_a;     // partition pass A: tiles of kTaIn input records
     int64_t tiles_b;     // partition pass B: upper bound of its kTbTile-record tiles
+    int64_t tiles_r;     // the one-pass row partition: tiles of kTrIn input records
 };
 constexpr int kTxShiftMax = 15;            // 2^15 four-byte node values: 128 KiB of LDS
 constexpr int kTRowsMax = 2048;            // row digit of at most 11 bits
 constexpr int kTaIn = 2048;                // input records per pass-A tile
 constexpr int kTbThreads = 512;
 constexpr int kTbTile = 16 * kTbThreads;   // directed records per pass-B tile
+constexpr int kTrIn = kTbTile / 2;         // input records per tile of the one-pass row partition
 constexpr int kTRowThreads = 1024;         // workgroup of the per-row kernels
 constexpr int64_t kTiledMinVertices = 1 << 20;   // default: tiled round 0 from 2^20 ids and records
 
@@ -271,6 +274,7 @@ inline TPlan tiled_plan(int64_t n, int64_t m) {
     p.cols = (int32_t)ceil_div(n < 1 ? 1 : n, (int64_t)1 << p.ys);
     p.tiles_a = ceil_div(m < 1 ? 1 : m, kTaIn);
     p.tiles_b = ceil_div(2 * (m < 1 ? 1 : m), kTbTile);
+    p.tiles_r = ceil_div(m < 1 ? 1 : m, kTrIn);
     return p;
 }
 
@@ -351,6 +355,8 @@ hipError_t launch_batch_keys(const Work &w, RoundKey *keys, const uint64_t *seed
 hipError_t launch_fill_gid(uint32_t *gid0, const uint32_t *voff, int32_t n_graphs, int grid, hipStream_t s);
 // Tiled round 0.  Partition stages: 0 = pass-A counts, 1..3 = their scan (total ->
 // t_count), 4 = pass-A scatter, 5 = pass-B counts, 6..8 = their scan, 9 = pass-B scatter.
+// The one-pass row form (no column order inside a row): 10 = counts by row of both directed
+// records of every input record, 11..13 = their scan (total -> t_count), 14 = scatter.
 hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &tp, int grid, hipStream_t s,
                                   int stage);
 // open: TreeContraction's one-hop minimum without the node's own priority

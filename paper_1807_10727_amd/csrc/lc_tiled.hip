@@ -144,7 +144,9 @@ __global__ __launch_bounds__(kThreads) void k_part_a_scatter(R rd, Work w, TPlan
 // partition pass B: directed records -> ordered by row block, column order kept per tile
 // ---------------------------------------------------------------------------------------
 
-__device__ inline int64_t tiles_b_of(const RoundState *st) { return ceil_div((int64_t)st->t_count, kTbTile); }
+// columns of the row partition's count table (pass B's tiles, or the one-pass form's), set by
+// the partition's count pass
+__device__ inline int64_t tiles_b_of(const RoundState *st) { return (int64_t)st->t_tiles; }
 
 // Load the two records at even position p of a key array that holds an even number of
 // records (so p + 1 is in range whenever p is).
@@ -180,11 +182,12 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_hist(Work w, TPlan tp) {
     RoundState *st = w.st;
     __shared__ uint32_t hist[kTRowsMax];
     const int64_t T = (int64_t)st->t_count;
-    const int64_t nt = tiles_b_of(st);
+    const int64_t nt = ceil_div(T, kTbTile);
     const int64_t nslabs = ceil_div(T, kSlab);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->aux_n = (u64c)tp.rows * (u64c)nt;
         st->n_slabs = (u64c)nslabs;
+        st->t_tiles = (u64c)nt;
     }
     const uint64_t *in = w.keys[0];
     const int xs = tp.xs;
@@ -272,6 +275,143 @@ __global__ __launch_bounds__(kTbThreads) void k_part_b_scatter(Work w, TPlan tp)
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------------------
+// the one-pass row partition: input records -> directed records ordered by row block only
+// ---------------------------------------------------------------------------------------
+//
+// Both directed records of every loop-free input record go straight to their rows, in one
+// counting pass over the input (pass A and its column order skipped): the row kernels only
+// need a row's records together, and the column order inside a row serves the L2 locality
+// of their gathers, which this form gives up for two passes fewer over the records.
+
+template <class R>
+__global__ __launch_bounds__(kTbThreads) void k_part_r_hist(R rd, Work w, TPlan tp) {
+    constexpr int V = R::kV;
+    constexpr int kChunks = kTrIn / V;   // reader chunks per tile
+    static_assert(kChunks * V == kTrIn, "tile of whole reader chunks");
+    RoundState *st = w.st;
+    __shared__ uint32_t hist[kTRowsMax];
+    rd.init(st);
+    const int64_t M = rd.records();
+    const int64_t nch = rd.chunks();
+    const int64_t nt = ceil_div(M, kTrIn);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->aux_n = (u64c)tp.rows * (u64c)nt;
+        st->n_slabs = (u64c)ceil_div(2 * M, kSlab);
+        st->t_tiles = (u64c)nt;
+    }
+    const int xs = tp.xs;
+    bool bad = false;
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < tp.rows; i += kTbThreads) hist[i] = 0;
+        __syncthreads();
+        for (int it = threadIdx.x; it < kChunks; it += kTbThreads) {
+            const int64_t c = tile * kChunks + it;
+            if (c < nch) {
+                uint32_t a[V], b[V];
+                rd.read(c, a, b, bad);
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    if (a[j] != b[j]) {
+                        atomicAdd(&hist[a[j] >> xs], 1u);
+                        atomicAdd(&hist[b[j] >> xs], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < tp.rows; i += kTbThreads) w.counts[(int64_t)i * nt + tile] = hist[i];
+        __syncthreads();
+    }
+    if (bad) atomicOr(&st->err, 1u);
+}
+
+// LDS as pass B's scatter (80 KiB): the tile's row counts, scanned in place into tile starts,
+// the global offsets, and the staged directed records.
+template <class R>
+__global__ __launch_bounds__(kTbThreads) void k_part_r_scatter(R rd, Work w, TPlan tp) {
+    constexpr int V = R::kV;
+    constexpr int kChunks = kTrIn / V;
+    constexpr int kPer = kChunks / kTbThreads;   // reader chunks per thread and tile
+    static_assert(kPer * kTbThreads == kChunks, "whole reader chunks per thread");
+    constexpr int kItems = 2 * V * kPer;        // directed records per thread and tile
+    constexpr int kPerThread = kTRowsMax / kTbThreads;
+    static_assert(kPerThread * kTbThreads == kTRowsMax, "row digits per thread");
+    RoundState *st = w.st;
+    __shared__ uint32_t dstart[kTRowsMax];
+    __shared__ uint32_t gofs[kTRowsMax];
+    __shared__ uint64_t skeys[kTbTile];
+    uint32_t *lds = (uint32_t *)skeys;
+    rd.init(st);
+    const int64_t nch = rd.chunks();
+    const int64_t nt = tiles_b_of(st);
+    uint64_t *out = w.keys[1];
+    const int xs = tp.xs;
+    const int rows = tp.rows;
+    bool bad = false;
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < nt; tile += gridDim.x) {
+        for (int i = threadIdx.x; i < rows; i += kTbThreads) dstart[i] = 0;
+        __syncthreads();
+        uint64_t k[kItems];
+        uint32_t rk[kItems];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t c = tile * kChunks + (int64_t)u * kTbThreads + threadIdx.x;
+            uint32_t a[V], b[V];
+            if (c < nch) {
+                rd.read(c, a, b, bad);
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const int q = 2 * (u * V + j);
+                const bool valid = a[j] != b[j];
+                k[q] = ((uint64_t)a[j] << 32) | b[j];
+                k[q + 1] = ((uint64_t)b[j] << 32) | a[j];
+                rk[q] = valid ? atomicAdd(&dstart[a[j] >> xs], 1u) : ~0u;
+                rk[q + 1] = valid ? atomicAdd(&dstart[b[j] >> xs], 1u) : ~0u;
+            }
+        }
+        __syncthreads();
+        uint32_t total;
+        {
+            uint32_t c[kPerThread];
+            uint32_t sum = 0;
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int i = kPerThread * threadIdx.x + q;
+                c[q] = i < rows ? dstart[i] : 0u;
+                sum += c[q];
+            }
+            uint32_t run = block_excl_scan<kTbThreads>(sum, lds, &total);
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                const int i = kPerThread * threadIdx.x + q;
+                if (i < rows) {
+                    dstart[i] = run;
+                    gofs[i] = w.counts[(int64_t)i * nt + tile];
+                }
+                run += c[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kItems; ++q) {
+            if (rk[q] != ~0u) skeys[dstart[(uint32_t)(k[q] >> 32) >> xs] + rk[q]] = k[q];
+        }
+        __syncthreads();
+        for (uint32_t pos = threadIdx.x; pos < total; pos += kTbThreads) {
+            const uint64_t kk = skeys[pos];
+            const uint32_t d = (uint32_t)(kk >> 32) >> xs;
+            out[gofs[d] + pos - dstart[d]] = kk;
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(&st->err, 1u);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -528,6 +668,30 @@ static hipError_t part_a(const R &rd, const Work &w, const TPlan &tp, int grid, 
     return hipGetLastError();
 }
 
+template <class R>
+static hipError_t part_r(const R &rd, const Work &w, const TPlan &tp, int grid, hipStream_t s, bool scatter) {
+    if (scatter)
+        hipLaunchKernelGGL(k_part_r_scatter<R>, dim3(grid), dim3(kTbThreads), 0, s, rd, w, tp);
+    else
+        hipLaunchKernelGGL(k_part_r_hist<R>, dim3(grid), dim3(kTbThreads), 0, s, rd, w, tp);
+    return hipGetLastError();
+}
+
+static hipError_t part_r_layout(const EdgeIn &e, const Work &w, const TPlan &tp, int grid, hipStream_t s,
+                                bool scatter) {
+    switch (e.layout) {
+        case kSoa32:
+            if (e.vec) return part_r(ReadSoa32<4>(e), w, tp, grid, s, scatter);
+            return part_r(ReadSoa32<1>(e), w, tp, grid, s, scatter);
+        case kSoa64:
+            if (e.vec) return part_r(ReadSoa64<2>(e), w, tp, grid, s, scatter);
+            return part_r(ReadSoa64<1>(e), w, tp, grid, s, scatter);
+        default:
+            if (e.vec) return part_r(ReadPacked<2>(e), w, tp, grid, s, scatter);
+            return part_r(ReadPacked<1>(e), w, tp, grid, s, scatter);
+    }
+}
+
 static hipError_t part_a_layout(const EdgeIn &e, const Work &w, const TPlan &tp, int grid, hipStream_t s,
                                 bool scatter) {
     switch (e.layout) {
@@ -564,6 +728,14 @@ hipError_t launch_tiled_partition(const Work &w, const EdgeIn &in, const TPlan &
         case 9:
             hipLaunchKernelGGL(k_part_b_scatter, dim3(grid), dim3(kTbThreads), 0, s, w, tp);
             return hipGetLastError();
+        case 10:
+            return part_r_layout(in, w, tp, grid, s, false);
+        case 11:
+        case 12:
+        case 13:
+            return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, &w.st->t_count, grid, s, stage - 11);
+        case 14:
+            return part_r_layout(in, w, tp, grid, s, true);
         default:
             return hipErrorInvalidValue;
     }

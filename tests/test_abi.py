@@ -148,7 +148,8 @@ def test_kernel_families_listed():
     from paper_1807_10727_amd import _cc
     names = _cc.cc_kernel_family_names()
     for want in ("min1", "min2", "parent", "relabel", "sort_scatter", "unique", "compose", "part_a_hist",
-                 "part_b_scatter", "min1_tiled", "min2_tiled", "relabel_tiled"):
+                 "part_b_scatter", "part_rows_hist", "part_rows_scatter", "min1_tiled", "min2_tiled",
+                 "relabel_tiled"):
         assert want in names
 
 

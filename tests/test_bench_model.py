@@ -43,6 +43,8 @@ def test_round0_dedup_of_the_full_size_graphs():
 
 
 def test_partition_and_tails_are_not_steps_of_the_method():
-    assert bench.FAMILY_STEP["part_b_scatter"] == "partition"
+    assert bench.FAMILY_STEP["part_b_scatter"] == bench.FAMILY_STEP["part_rows_scatter"] == "partition"
+    from paper_1807_10727_amd import _cc
+    assert set(_cc.cc_kernel_family_names()) <= set(bench.FAMILY_STEP)   # every kernel is placed
     assert bench.FAMILY_STEP["sort_scatter"] == bench.FAMILY_STEP["hash_dedup"] == "a5_dedup"
     assert "partition" not in bench.step_bytes(TOY, 8)

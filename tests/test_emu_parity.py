@@ -41,10 +41,12 @@ def inputs(g, layout):
     return dev(graphgen.pack(g.src, g.dst), np.uint64), None
 
 
-def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=True):
+def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=True, round0=0):
     want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule, record_parents=True)
     s_, d_ = inputs(g, layout)
     with hipemu.Solver(g.n, s_, d_, seed=seed, flags=flags | RULES[rule] | cc.CC_EAGER) as s:
+        if round0:
+            s.set_tuning(round0=round0)
         a, b = g.src, g.dst
         r = 0
         while per_round:
@@ -66,11 +68,14 @@ def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=Tr
     return want
 
 
-@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 @pytest.mark.parametrize("layout", ["soa32", "soa64", "packed"])
 def test_emulated_solve_matches_oracle(cc, mode, layout):
+    """Round by round (parents, edges, counts) and the final labels; "rows" is the tiled round
+    0 fed by the one-pass row partition."""
     g = graphgen.Graph(6000, *graphgen.gnm(0x5151, 6000, 20011))
-    check_solve(cc, g, 3, flags={"direct": DIRECT, "tiled": TILED}[mode], layout=layout)
+    check_solve(cc, g, 3, flags={"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode], layout=layout,
+                round0=3 if mode == "rows" else 0)
 
 
 @pytest.mark.parametrize("mode", ["direct", "tiled"])
@@ -511,19 +516,32 @@ def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
     assert "FAILS []" in proc.stdout, proc.stdout
 
 
-@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 def test_emulated_round0_key_sets(cc, mode):
     """Round 0 on a power-law graph: the relabel workgroups' key sets drop most repeated keys
     before the sort (m_sorted well below m_survive), and everything the method defines is
-    unchanged; on a uniform random graph the sets switch themselves off early."""
+    unchanged; on a uniform random graph the sets switch themselves off early.  "rows": the
+    tiled round 0 with the one-pass row partition."""
+    flags = {"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode]
+
+    def solver(h, seed):
+        s = hipemu.Solver(h.n, dev(h.src), dev(h.dst), seed=seed, flags=flags)
+        if mode == "rows":
+            s.set_tuning(round0=3)
+        return s
+
     g = graphgen.Graph(1 << 15, *graphgen.rmat(21, 15, 16 << 15))
-    want = check_solve(cc, g, 17, flags={"direct": DIRECT, "tiled": TILED}[mode], per_round=False)
-    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=17, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+    want = oracle.run(g.n, g.src, g.dst, seed=17)
+    with solver(g, 17) as s:
+        assert s.run() == want.rounds
+        assert [tuple(x) for x in s.stats(want.rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    with solver(g, 17) as s:
         s.contract_round()
         assert cc.cc_get_round_sorted(s.ctx, 0) * 4 < want.stats[0][3]
     u = graphgen.Graph(1 << 15, *graphgen.gnm(22, 1 << 15, 1 << 17))
     want = oracle.run(u.n, u.src, u.dst, seed=17)
-    with hipemu.Solver(u.n, dev(u.src), dev(u.dst), seed=17, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+    with solver(u, 17) as s:
         s.contract_round()
         assert cc.cc_get_round_sorted(s.ctx, 0) > 0.9 * want.stats[0][3]
 
@@ -536,7 +554,7 @@ def test_emulated_tuning_knobs_keep_results(cc):
     g = graphgen.Graph(1 << 15, *graphgen.rmat(4, 15, 8 << 15))
     want = oracle.run(g.n, g.src, g.dst, seed=3)
     with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=TILED) as s:
-        for r0 in (1, 2):
+        for r0 in (1, 2, 3):
             for bpc in (1, 4, 16):
                 for ks in (1, 0):
                     s.set_tuning(round0=r0, blocks_per_cu=bpc, round0_key_sets=ks)

@@ -258,6 +258,31 @@ def test_profile_times_kernels(lc):
     assert all(n == 0 for k, (_, n) in t.items() if k != "sort_scatter")
 
 
+def test_tuning_knobs_keep_results(lc):
+    """Every cc_tuning setting gives the oracle's rounds, counts and labels: the three round-0
+    forms (direct, tiled with the two-pass partition, tiled with the one-pass row partition),
+    grid sizes and round 0's key sets, on a power-law graph of many partition tiles with a
+    ragged last tile."""
+    g = graphgen.Graph(1 << 16, *graphgen.rmat(0x7077, 16, (12 << 16) + 4093))
+    want = oracle.run(g.n, g.src, g.dst, seed=11)
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=11, flags=MODES["tiled"] | lc.CC_PROFILE) as s:
+        for r0 in (1, 2, 3):
+            for bpc in (1, 8, 16):
+                for ks in (1, 0):
+                    s.set_tuning(round0=r0, blocks_per_cu=bpc, round0_key_sets=ks)
+                    assert s.tuning == {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
+                    r = s.run()
+                    assert r == want.rounds, (r0, bpc, ks)
+                    assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats], (r0, bpc, ks)
+                    assert np.array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels), (r0, bpc, ks)
+                    t = s.kernel_times()   # this solve's launches (a reset clears them)
+                    ran = {f for f in ("min1_round0", "part_a_hist", "part_b_scatter", "part_rows_hist",
+                                       "part_rows_scatter") if t[f][1]}
+                    assert ran == [set(), {"min1_round0"}, {"part_a_hist", "part_b_scatter"},
+                                   {"part_rows_hist", "part_rows_scatter"}][r0], (r0, ran)
+
+
 # --- heavy repeats and a hub ------------------------------------------------------------
 
 def dup_path(nv, reps, seed):
