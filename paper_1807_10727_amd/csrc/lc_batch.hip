@@ -195,12 +195,15 @@ namespace {
 
 size_t batch_extra_bytes(int32_t G) {
     const size_t g = (size_t)G + 1;
-    return 256 * 12 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 2 + sizeof(SmallDesc) * g + g + 64;
+    return (256 + LC_WS_GUARD) * 12 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 2 +
+           sizeof(SmallDesc) * g + g + 64;
 }
 
 char *carve(char *&p, size_t bytes) {
     char *r = p;
-    p += (bytes + 255) / 256 * 256;
+    const size_t step = (bytes + 255) / 256 * 256 + LC_WS_GUARD;
+    ws_mark(r, bytes, step - bytes);
+    p += step;
     return r;
 }
 

@@ -18,6 +18,13 @@
 #include "cc.h"
 #include "lc_engine.hpp"
 
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer) && LC_WS_GUARD > 0
+#define LC_WS_POISON 1
+#include <sanitizer/asan_interface.h>
+#endif
+#endif
+
 namespace lc {
 
 // Kernel families timed with CC_PROFILE.  The round-0 passes over the input records
@@ -30,6 +37,15 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+#ifdef LC_WS_POISON
+void ws_mark(char *p, size_t bytes, size_t gap) {
+    ASAN_UNPOISON_MEMORY_REGION(p, bytes);
+    ASAN_POISON_MEMORY_REGION(p + bytes, gap);
+}
+#else
+void ws_mark(char *, size_t, size_t) {}
+#endif
 
 bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags) {
     if (flags & CC_ROUND0_DIRECT) return false;
@@ -56,7 +72,9 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *p = base ? base + off : nullptr;
-        off = align_up(off + bytes, 256);
+        const size_t next = align_up(off + bytes, 256) + LC_WS_GUARD;
+        if (p) ws_mark(p, bytes, next - off - bytes);
+        off = next;
         return p;
     };
     Work t{};

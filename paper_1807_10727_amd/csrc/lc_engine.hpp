@@ -30,6 +30,18 @@ extern const char *const kFamilyNames[kFamilies];
 enum { kWsExplicit = 1, kWsRecord = 2, kWsMerge = 4 };
 constexpr int64_t kRecordPerVertex = 5;   // 4-byte record entries per vertex (20 bytes)
 size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base, Work *w, uint32_t extras = 0);
+// Guard gaps for bounds-checking builds.  A host build of the library under AddressSanitizer
+// (device memory is then host memory) sets LC_WS_GUARD to a multiple of 256: every buffer
+// carved from a workspace is followed by that many bytes, marked as not addressable together
+// with the buffer's alignment slack, so that an access past a buffer's declared size is
+// reported where it happens instead of landing in the next buffer.  GPU builds keep 0.
+#ifndef LC_WS_GUARD
+#define LC_WS_GUARD 0
+#endif
+static_assert(LC_WS_GUARD % 256 == 0, "guard gaps keep the 256-byte alignment of workspace buffers");
+// Marks [p, p + bytes) addressable and the `gap` bytes after it not (bounds-checking builds
+// only; otherwise nothing).
+void ws_mark(char *p, size_t bytes, size_t gap);
 // Whether a plain solve of this size with these cc_options flags runs round 0 tiled.
 bool choose_tiled(int64_t n0, int64_t m0, uint32_t flags);
 int ceil_log2_host(int64_t n);

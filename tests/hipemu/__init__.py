@@ -24,7 +24,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
-BUILD = os.path.join(HERE, "_build")
+# HIPEMU_ASAN=1: the bounds-checking build -- AddressSanitizer, with a guard gap after every
+# workspace buffer (LC_WS_GUARD), so that any access outside an allocation or past a carved
+# buffer's end stops the process with a report.  The process must preload asan_runtime().
+ASAN = os.environ.get("HIPEMU_ASAN") == "1"
+BUILD = os.path.join(HERE, "_build_asan" if ASAN else "_build")
 CSRC = os.path.join(ROOT, "paper_1807_10727_amd", "csrc")
 LIB = os.path.join(BUILD, "libcc.so")
 CXX = os.environ.get("HIPEMU_CXX", "/opt/rocm/llvm/bin/clang++")
@@ -58,6 +62,10 @@ def build(force: bool = False) -> str:
             return LIB
     flags = ["-std=c++17", "-O2", "-fPIC", "-pthread", "-Wno-unknown-attributes", "-Wno-ignored-attributes",
              "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    link = []
+    if ASAN:
+        flags += ["-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-DLC_WS_GUARD=256"]
+        link = ["-fsanitize=address", "-shared-libasan"]
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
@@ -69,10 +77,29 @@ def build(force: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(compile_one, _sources()))
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.run([CXX, "-shared", "-pthread", "-o", tmp] + objs, check=True)
+    subprocess.run([CXX, "-shared", "-pthread"] + link + ["-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
     shutil.copyfile(os.path.join(ROOT, "paper_1807_10727_amd", "_cc.py"), os.path.join(BUILD, "_cc.py"))
     return LIB
+
+
+def asan_runtime() -> str:
+    """The AddressSanitizer runtime that a process loading the HIPEMU_ASAN build preloads."""
+    out = subprocess.run([CXX, "-print-file-name=libclang_rt.asan-x86_64.so"], stdout=subprocess.PIPE, text=True,
+                         check=True).stdout.strip()
+    if not os.path.isabs(out) or not os.path.exists(out):
+        raise RuntimeError("no AddressSanitizer runtime next to " + CXX)
+    return out
+
+
+def asan_env(env=None) -> dict:
+    """Environment of a child process that runs the bounds-checking build."""
+    env = dict(os.environ if env is None else env)
+    env["HIPEMU_ASAN"] = "1"
+    env["LD_PRELOAD"] = asan_runtime()
+    # fibers switch stacks by hand: no fake stacks; leaks are not what is checked
+    env["ASAN_OPTIONS"] = "detect_leaks=0:detect_stack_use_after_return=0:halt_on_error=1"
+    return env
 
 
 def binding():
