@@ -78,11 +78,12 @@ def test_emulated_solve_matches_oracle(cc, mode, layout):
                 round0=3 if mode == "rows" else 0)
 
 
-@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 @pytest.mark.parametrize("rule", ["tree", "one_hop"])
 def test_emulated_rules_match_oracle(cc, mode, rule):
     g = graphgen.er_with_paths(0x77, 3000, 7000, 10, 50)
-    check_solve(cc, g, 4, flags={"direct": DIRECT, "tiled": TILED}[mode], rule=rule)
+    check_solve(cc, g, 4, flags={"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode], rule=rule,
+                round0=3 if mode == "rows" else 0)
 
 
 def test_emulated_degenerate_inputs(cc):
@@ -388,7 +389,7 @@ def test_emulated_server(cc):
 
 # ---- MergeToLarge ----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 @pytest.mark.parametrize("alphas", [[1], [2], [3, 5, 9], [10 ** 6]])
 def test_emulated_merge_to_large(cc, mode, alphas):
     """Every round (LocalContraction steps and MergeToLarge steps) against the oracle: parents
@@ -396,8 +397,10 @@ def test_emulated_merge_to_large(cc, mode, alphas):
     g = graphgen.er_with_paths(0x3E7, 5000, 16000, 20, 150)
     want = oracle.run(g.n, g.src, g.dst, seed=12, variant="merge_to_large", alphas=alphas, record_parents=True,
                       parents_cap=64)
-    flags = {"direct": DIRECT, "tiled": TILED}[mode] | cc.CC_MERGE_TO_LARGE | cc.CC_RECORD_ROUNDS
+    flags = {"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode] | cc.CC_MERGE_TO_LARGE | cc.CC_RECORD_ROUNDS
     with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=12, flags=flags) as s:
+        if mode == "rows":
+            s.set_tuning(round0=3)
         s.set_merge_to_large(alphas)
         a, b = g.src, g.dst
         r = 0
