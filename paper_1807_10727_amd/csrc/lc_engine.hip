@@ -679,9 +679,9 @@ cc_status run_finish(cc_ctx *c) {
 
 }  // namespace
 
-extern "C" {
+namespace lc {
 
-cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx **out) {
+cc_status ctx_create(const cc_graph_desc *graph, const cc_options *opts, RoundState *mirror, cc_ctx **out) {
     if (!out) return CC_E_ARG;
     *out = nullptr;
     if (!graph || !opts) return CC_E_ARG;
@@ -713,7 +713,10 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     c->cus = std::max(cus, 1);
     c->grid_cap = c->cus * 8;
-    if (hipHostMalloc((void **)&c->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+    if (mirror) {
+        c->h_st = mirror;
+        c->h_st_borrowed = true;
+    } else if (hipHostMalloc((void **)&c->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
         // no usable device yet: a pageable mirror still works for every later copy
         (void)hipGetLastError();
         c->h_st = (RoundState *)calloc(1, sizeof(RoundState));
@@ -734,6 +737,14 @@ cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx *
     }
     *out = c;
     return CC_OK;
+}
+
+}  // namespace lc
+
+extern "C" {
+
+cc_status cc_create(const cc_graph_desc *graph, const cc_options *opts, cc_ctx **out) {
+    return lc::ctx_create(graph, opts, nullptr, out);
 }
 
 cc_status cc_workspace_size(const cc_ctx *c, size_t *bytes) {
@@ -1141,7 +1152,7 @@ cc_status cc_destroy(cc_ctx *c) {
     for (auto e : c->events) (void)hipEventDestroy(e);
     drop_tails(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->h_st) {
+    if (c->h_st && !c->h_st_borrowed) {
         if (c->h_st_pageable)
             free(c->h_st);
         else

@@ -66,6 +66,7 @@ struct Engine {
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state
     bool h_st_pageable = false;
+    bool h_st_borrowed = false;   // the mirror belongs to the caller (a server slot)
     // batch of independent graphs (union path)
     RoundKey *d_keys = nullptr;         // [G] per-graph round keys (device)
     const uint64_t *d_seeds = nullptr;  // [G] per-graph seeds (device)
@@ -149,6 +150,11 @@ namespace lc {
 cc_status fail(cc_ctx *c, cc_status s, const char *msg);
 cc_status reject(cc_ctx *c, cc_status s, const char *msg);
 cc_status hip_status(cc_ctx *c);
+// cc_create with the host mirror of the round state supplied by the caller (non-null: kept
+// until cc_destroy, never freed by it).  The serving scheduler gives each slot one for good:
+// freeing pinned host memory synchronises the whole device, which would stall every other
+// request in flight each time one completes.
+cc_status ctx_create(const cc_graph_desc *graph, const cc_options *opts, RoundState *mirror, cc_ctx **out);
 // asynchronous round interface (used by the serving scheduler)
 cc_status ctx_round_enqueue(cc_ctx *c, int *launched);
 cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out);

@@ -5,8 +5,10 @@
 //   - small requests (int32 records within the LDS limits of the configured variant) that
 //     are waiting are fused into one launch of the persistent LDS solver, which solves
 //     each of them in one workgroup;
-//   - every other request gets a slot stream and a workspace carved from the caller's
-//     arena, and advances one round per step: the scheduler enqueues a round and an
+//   - every other request gets a slot stream, the slot's host mirror of the round state
+//     (allocated once: freeing pinned memory would synchronise the whole device each time a
+//     request completes) and a workspace carved from the caller's arena, and advances one
+//     round per step: the scheduler enqueues a round and an
 //     asynchronous readback of its state, and picks the request up again when the event
 //     behind that readback has completed, so rounds of different requests run
 //     concurrently on their streams.
@@ -19,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -122,6 +125,8 @@ struct cc_server {
     std::vector<hipStream_t> streams;       // one per slot
     std::vector<hipEvent_t> events;         // one per slot
     std::vector<Request *> slot_req;
+    RoundState *mirrors = nullptr;          // pinned host mirrors of the round state, one per slot
+    bool mirrors_pageable = false;
     hipStream_t small_stream = nullptr;
     std::vector<SmallLaunch> small;         // small launches (in flight or free)
     std::mutex mu;
@@ -180,7 +185,7 @@ bool admit_large(cc_server *s, Request *r, int k) {
     cc_options o{};
     o.seed = r->seed;
     o.stream = s->streams[k];
-    cc_status st = cc_create(&r->g, &o, &r->ctx);
+    cc_status st = ctx_create(&r->g, &o, s->mirrors + k, &r->ctx);
     if (st == CC_OK) st = cc_set_workspace(r->ctx, s->arena + off, r->footprint);
     int launched = 0;
     if (st == CC_OK) st = ctx_round_enqueue(r->ctx, &launched);
@@ -312,6 +317,24 @@ void complete_small(cc_server *s, SmallLaunch &L) {
     L.busy = false;
 }
 
+// the server's streams, events and host buffers (its scheduler has stopped)
+void free_server(cc_server *s) {
+    for (auto st : s->streams) (void)hipStreamDestroy(st);
+    for (auto ev : s->events) (void)hipEventDestroy(ev);
+    if (s->small_stream) (void)hipStreamDestroy(s->small_stream);
+    for (auto &L : s->small) {
+        if (L.h) (void)hipHostFree(L.h);
+        if (L.ev) (void)hipEventDestroy(L.ev);
+    }
+    if (s->mirrors) {
+        if (s->mirrors_pageable)
+            free(s->mirrors);
+        else
+            (void)hipHostFree(s->mirrors);
+    }
+    delete s;
+}
+
 void worker_loop(cc_server *s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -437,6 +460,13 @@ cc_status cc_server_create(void *d_arena, size_t budget_bytes, const cc_server_c
         s->events.push_back(ev);
     }
     s->slot_req.assign(s->streams.size(), nullptr);
+    if (ok && hipHostMalloc((void **)&s->mirrors, sizeof(RoundState) * (size_t)cfg->n_slots, hipHostMallocDefault) !=
+                  hipSuccess) {
+        (void)hipGetLastError();   // a pageable mirror still works, only slower to copy
+        s->mirrors = (RoundState *)calloc((size_t)cfg->n_slots, sizeof(RoundState));
+        s->mirrors_pageable = true;
+        ok = s->mirrors != nullptr;
+    }
     if (ok) ok = hipStreamCreateWithFlags(&s->small_stream, hipStreamNonBlocking) == hipSuccess;
     s->small.resize(cfg->small_launches);
     for (auto &L : s->small) {
@@ -452,14 +482,7 @@ cc_status cc_server_create(void *d_arena, size_t budget_bytes, const cc_server_c
     }
     if (!ok) {
         (void)hipGetLastError();
-        for (auto st : s->streams) (void)hipStreamDestroy(st);
-        for (auto ev : s->events) (void)hipEventDestroy(ev);
-        if (s->small_stream) (void)hipStreamDestroy(s->small_stream);
-        for (auto &L : s->small) {
-            if (L.h) (void)hipHostFree(L.h);
-            if (L.ev) (void)hipEventDestroy(L.ev);
-        }
-        delete s;
+        free_server(s);
         return CC_E_HIP;
     }
     s->worker = std::thread(worker_loop, s);
@@ -572,14 +595,7 @@ cc_status cc_server_destroy(cc_server *s) {
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
     for (auto *r : s->done) delete r;
-    for (auto st : s->streams) (void)hipStreamDestroy(st);
-    for (auto ev : s->events) (void)hipEventDestroy(ev);
-    if (s->small_stream) (void)hipStreamDestroy(s->small_stream);
-    for (auto &L : s->small) {
-        if (L.h) (void)hipHostFree(L.h);
-        if (L.ev) (void)hipEventDestroy(L.ev);
-    }
-    delete s;
+    free_server(s);
     return CC_OK;
 }
 

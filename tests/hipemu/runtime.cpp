@@ -5,6 +5,7 @@
 // operation per wave (for the lanes of that wave waiting at the same call site), or, when
 // every live work-item waits at __syncthreads, releases the barrier.  Anything else is a
 // deadlock and aborts the process with a message that names the kernel's state.
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -331,7 +332,11 @@ hipError_t hipMemsetAsync(void *dst, int v, size_t n, hipStream_t s) {
     return hipSuccess;
 }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
-hipError_t hipDeviceSynchronize() { return hipSuccess; }
+static std::atomic<long long> g_device_syncs{0};
+hipError_t hipDeviceSynchronize() {
+    ++g_device_syncs;
+    return hipSuccess;
+}
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) {
     *s = new ihipStream_t();
     return hipSuccess;
@@ -392,11 +397,16 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
     *ms = std::chrono::duration<float, std::milli>(b->t - a->t).count();
     return hipSuccess;
 }
+// Calls that on the GPU wait for all work on the device (HIP frees synchronise the device
+// before they release memory): counted, so that tests can check that a path makes none.
+extern "C" long long hipemu_device_syncs(void) { return g_device_syncs.load(); }
+
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) {
     *p = calloc(1, n ? n : 1);
     return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 hipError_t hipHostFree(void *p) {
+    ++g_device_syncs;
     free(p);
     return hipSuccess;
 }

@@ -8,6 +8,8 @@ and checkpoints.  It does not replace the GPU parity tests (tests/test_gpu_*.py)
 hardware's timing and memory model are not emulated."""
 from itertools import permutations
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -354,14 +356,19 @@ def test_emulated_batch(cc, variant, fill):
 
 def test_emulated_server(cc):
     """Requests of both paths (fused LDS launch and per-slot rounds) in one server: every
-    result is the oracle's."""
+    result is the oracle's.  While it serves, the server makes no call that synchronises the
+    whole device (such as freeing pinned host memory when a request completes), which would
+    stall every other request in flight."""
     import time
+    syncs = cc._lib.hipemu_device_syncs
+    syncs.restype = ctypes.c_longlong
     trace = graphgen.request_trace(0x5E7, 10, rate=1.0, log2_min=5, log2_max=13)
     graphs = [r.graph() for r in trace]
     arena = hipemu._aligned(1 << 28, None)
     srv = cc.cc_server_create(arena.ctypes.data, arena.size, n_slots=3, small_variant=1,
                               max_small_per_launch=4)
     keep, out = {}, {}
+    syncs0 = syncs()
     try:
         for i, (g, r) in enumerate(zip(graphs, trace)):
             s_, d_ = dev(g.src), dev(g.dst)
@@ -373,9 +380,11 @@ def test_emulated_server(cc):
         while len(out) < len(graphs) and time.time() < t_end:
             for res in cc.cc_server_wait(srv, 0.5):
                 out[res["id"]] = res
+        served_syncs = syncs() - syncs0
     finally:
         cc.cc_server_destroy(srv)
     assert len(out) == len(graphs)
+    assert served_syncs == 0
     small = 0
     for rid, res in out.items():
         i, _, _, lab = keep[rid]
