@@ -441,8 +441,9 @@ def main():
     ap.add_argument("--workload", default="rmat26", choices=WORKLOADS)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--eager", action="store_true", help="run every round eagerly (no captured tails)")
-    ap.add_argument("--round0", default="auto", choices=["auto", "direct", "tiled"],
-                    help="how round 0 reads the input records (auto: the library's choice by size)")
+    ap.add_argument("--round0", default="auto", choices=["auto", "direct", "tiled", "rows"],
+                    help="how round 0 reads the input records (auto: the library's choice by size, then the "
+                         "tuner's; rows: tiled, with the one-pass row partition)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rmat-scale", type=int, default=21,
                     help="R-MAT scale of the oracle's sample of an R-MAT headline (same recipe)")
@@ -517,7 +518,8 @@ def main():
     flags = 0 if args.no_profile else lc.CC_PROFILE
     if args.eager:
         flags |= lc.CC_EAGER
-    round0_flag = {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED}[args.round0]
+    round0_flag = {"auto": 0, "direct": lc.CC_ROUND0_DIRECT, "tiled": lc.CC_ROUND0_TILED,
+                   "rows": lc.CC_ROUND0_TILED}[args.round0]
     flags |= round0_flag
     stream = torch.cuda.current_stream(dev)
     base_seed = graphgen.CONFIG_SEED_BASE + 1
@@ -529,9 +531,11 @@ def main():
         from paper_1807_10727_amd import autotune
         space = dict(autotune.SOLVER_SPACE)
         if args.round0 != "auto":
-            space.pop("round0")
+            space.pop("round0")     # the form asked for stays
         t0 = time.perf_counter()
         with lc.Solver(n0, src, dst, seed=base_seed, flags=round0_flag, stream=stream, layout=layout) as ts:
+            if args.round0 == "rows":
+                ts.set_tuning(round0=3)
             tuning, t_best, tried = autotune.tune_solver(ts, seed=base_seed + 500, repeats=1, cache=args.tune_cache,
                                                          log=log if args.verbose_tune else None, space=space)
         torch.cuda.empty_cache()
@@ -542,6 +546,8 @@ def main():
     solver = lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout)
     if tuning:
         solver.set_tuning(**tuning)
+    elif args.round0 == "rows":
+        solver.set_tuning(round0=3)
     log("workspace %.2f GiB" % (solver.ws_bytes / 2**30))
 
     def step(i):
