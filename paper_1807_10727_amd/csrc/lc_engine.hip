@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -677,6 +678,35 @@ cc_status run_finish(cc_ctx *c) {
     return CC_DONE;
 }
 
+// Pinned host mirrors of the round state, kept for reuse by later contexts.  Freeing pinned
+// memory synchronises the whole device (hipHostFree waits for all work on it), so a context
+// that ends while others still run must not free its mirror; it returns it here instead.  The
+// pool holds at most as many mirrors (a few KB each) as contexts ever existed at once.
+std::mutex g_mirror_mu;
+std::vector<RoundState *> g_mirrors;
+
+RoundState *mirror_take() {
+    {
+        std::lock_guard<std::mutex> lk(g_mirror_mu);
+        if (!g_mirrors.empty()) {
+            RoundState *m = g_mirrors.back();
+            g_mirrors.pop_back();
+            return m;
+        }
+    }
+    RoundState *m = nullptr;
+    if (hipHostMalloc((void **)&m, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return m;
+}
+
+void mirror_give(RoundState *m) {
+    std::lock_guard<std::mutex> lk(g_mirror_mu);
+    g_mirrors.push_back(m);
+}
+
 }  // namespace
 
 namespace lc {
@@ -716,9 +746,10 @@ cc_status ctx_create(const cc_graph_desc *graph, const cc_options *opts, RoundSt
     if (mirror) {
         c->h_st = mirror;
         c->h_st_borrowed = true;
-    } else if (hipHostMalloc((void **)&c->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+    } else if ((c->h_st = mirror_take()) != nullptr) {
+        c->h_st_pooled = true;
+    } else {
         // no usable device yet: a pageable mirror still works for every later copy
-        (void)hipGetLastError();
         c->h_st = (RoundState *)calloc(1, sizeof(RoundState));
         c->h_st_pageable = true;
         if (!c->h_st) {
@@ -1152,12 +1183,10 @@ cc_status cc_destroy(cc_ctx *c) {
     for (auto e : c->events) (void)hipEventDestroy(e);
     drop_tails(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->h_st && !c->h_st_borrowed) {
-        if (c->h_st_pageable)
-            free(c->h_st);
-        else
-            (void)hipHostFree(c->h_st);
-    }
+    if (c->h_st_pooled)
+        mirror_give(c->h_st);   // the stream is idle: no copy to or from it is pending
+    else if (c->h_st_pageable)
+        free(c->h_st);
     delete c;
     return CC_OK;
 }

@@ -67,6 +67,7 @@ struct Engine {
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state
     bool h_st_pageable = false;
     bool h_st_borrowed = false;   // the mirror belongs to the caller (a server slot)
+    bool h_st_pooled = false;     // the mirror returns to the library's pool on destroy
     // batch of independent graphs (union path)
     RoundKey *d_keys = nullptr;         // [G] per-graph round keys (device)
     const uint64_t *d_seeds = nullptr;  // [G] per-graph seeds (device)

@@ -354,6 +354,21 @@ def test_emulated_batch(cc, variant, fill):
             np.testing.assert_array_equal(lab.astype(np.uint32), want_lab)
 
 
+def test_emulated_contexts_end_without_a_device_wide_wait(cc):
+    """Destroying a context while others run must not wait for the whole device: its pinned
+    host mirror of the round state goes back to a pool instead of being freed."""
+    syncs = cc._lib.hipemu_device_syncs
+    syncs.restype = ctypes.c_longlong
+    g = graphgen.Graph(500, *graphgen.gnm(0x51, 500, 1500))
+    want = oracle.run(g.n, g.src, g.dst, seed=5)
+    before = syncs()
+    for _ in range(6):
+        with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=5) as s:
+            assert s.run() == want.rounds
+            np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    assert syncs() == before
+
+
 def test_emulated_server(cc):
     """Requests of both paths (fused LDS launch and per-slot rounds) in one server: every
     result is the oracle's.  While it serves, the server makes no call that synchronises the
