@@ -198,6 +198,13 @@ typedef struct {
     int32_t blocks_per_cu;    /* workgroups per compute unit of the grid-stride kernels (1..64); 0: 8 */
     int32_t round0_key_sets;  /* 1 (default): round 0's relabel workgroups drop the repeated keys they
                                  see through an LDS set; 0: they write every survivor */
+    int32_t scatter_waves;    /* waves per SIMD the radix scatter is built for: 2, 3 or 4; 0: 3 */
+    int32_t row_pairs;        /* tiled round 0, two-hop row pass: record pairs in flight per thread
+                                 (2, 4 or 8); 0: 4 */
+    int32_t relabel_pairs;    /* tiled round 0, relabel row pass: the same (1, 2 or 4); 0: 2 */
+    int32_t row_generation;   /* tiled round 0: rows of the two gathering row passes launched
+                                 together, per compute unit (1..8); 0: 1; -1: every row in one
+                                 launch */
     int32_t reserved;         /* must be 0 */
 } cc_tuning;
 
@@ -206,7 +213,7 @@ typedef struct {
  * current seed does, and drops captured tails.  CC_E_ARG for a value out of range or a tiled
  * round 0 the context cannot take; CC_E_NOMEM when a workspace is set and is smaller than the
  * new form needs (cc_workspace_size reports the size for the current form).  cc_get_tuning
- * reports the knobs in force (round0 1, 2 or 3).
+ * reports the knobs in force (round0 1, 2 or 3; every 0 "default" resolved to its value).
  */
 cc_status cc_set_tuning(cc_ctx *ctx, const cc_tuning *t);
 cc_status cc_get_tuning(const cc_ctx *ctx, cc_tuning *t);

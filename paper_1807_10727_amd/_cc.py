@@ -54,12 +54,15 @@ class cc_round_stats(ctypes.Structure):
         return (self.round, self.n_active, self.m_in, self.m_survive, self.m_out, self.n_finalised)
 
 
+TUNING_KNOBS = ("round0", "blocks_per_cu", "round0_key_sets", "scatter_waves", "row_pairs", "relabel_pairs",
+                "row_generation")
+
+
 class cc_tuning(ctypes.Structure):
-    _fields_ = [("round0", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32), ("round0_key_sets", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+    _fields_ = [(k, ctypes.c_int32) for k in TUNING_KNOBS] + [("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"round0": self.round0, "blocks_per_cu": self.blocks_per_cu, "round0_key_sets": self.round0_key_sets}
+        return {k: getattr(self, k) for k in TUNING_KNOBS}
 
 
 class cc_batch_config(ctypes.Structure):
@@ -194,8 +197,11 @@ def cc_reset(ctx, seed: int) -> None:
     _check(ctx, _lib.cc_reset(ctx, seed & 0xFFFFFFFFFFFFFFFF))
 
 
-def cc_set_tuning(ctx, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1) -> None:
-    t = cc_tuning(int(round0), int(blocks_per_cu), int(round0_key_sets), 0)
+def cc_set_tuning(ctx, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1, scatter_waves: int = 0,
+                  row_pairs: int = 0, relabel_pairs: int = 0, row_generation: int = 0) -> None:
+    """Knobs of include/cc.h's cc_tuning; 0 keeps a knob's default (round0: the current form)."""
+    t = cc_tuning(int(round0), int(blocks_per_cu), int(round0_key_sets), int(scatter_waves), int(row_pairs),
+                  int(relabel_pairs), int(row_generation), 0)
     _check(ctx, _lib.cc_set_tuning(ctx, ctypes.byref(t)))
 
 

@@ -85,6 +85,8 @@ def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, s
     best_t, ref = _time_run(batch, repeats)
     tried = 1
     for knob, values in space.items():
+        if knob in ROW_KNOBS and cfg["round0"] == 1:
+            continue                   # a direct round 0 has no row passes
         for v in values:
             if v == cfg[knob]:
                 continue
@@ -116,7 +118,14 @@ SOLVER_SPACE = {
                                        # (the tiled forms where the context can take them)
     "blocks_per_cu": [4, 8, 16],
     "round0_key_sets": [1, 0],
+    "scatter_waves": [3, 2, 4],
+    "row_pairs": [4, 2, 8],            # the tiled forms only (no effect on a direct round 0)
+    "relabel_pairs": [2, 1, 4],
+    "row_generation": [1, 2, -1],
 }
+
+
+ROW_KNOBS = ("row_pairs", "relabel_pairs", "row_generation")
 
 
 def solver_size_class(solver) -> str:
@@ -158,6 +167,8 @@ def tune_solver(solver, seed: int = 0, repeats: int = 1, cache: str | None = DEF
     best_t, ref = _time_solver(solver, seed, repeats)
     tried = 1
     for knob, values in space.items():
+        if knob in ROW_KNOBS and cfg["round0"] == 1:
+            continue                   # a direct round 0 has no row passes
         for v in values:
             if v == cfg[knob]:
                 continue

@@ -189,9 +189,11 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int gn = grid_for(N);
     const int gm = grid_for(ceil_div(M, first ? 4 : 2));
     const int gt = grid_tiles(M);
-    // the scatter keeps LC_SCATTER_WAVES waves per SIMD resident (four-wave workgroups): a grid
+    // the scatter keeps scatter_waves waves per SIMD resident (four-wave workgroups): a grid
     // of exactly that many workgroups runs in one go instead of a resident share and a tail
-    const int gt_scatter = LC_SCATTER_GRID ? std::min(gt, std::max(1, cus * LC_SCATTER_WAVES)) : gt;
+    const int gt_scatter = LC_SCATTER_GRID ? std::min(gt, std::max(1, cus * scatter_waves)) : gt;
+    // rows of the gathering row passes launched together (0: all of them)
+    const int row_gen = row_generation < 0 ? 0 : cus * row_generation;
     const int gscan_l = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(N, 1), 32 * kThreads), grid_cap);
     const int kb = ceil_log2_host(std::max<int64_t>(N, 2));
     const int nbits = 2 * kb;   // edge_key
@@ -239,9 +241,9 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         else if (variant == kVarOneHop)
             RUN(kParent, launch_tiled_parent1(w, pc, gn, stream));
         else
-            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, cus));
+            RUN(kMin2Tiled, launch_tiled_min2(w, pc, tp, stream, row_gen, row_pairs));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
-        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, cus));
+        RUN(kRelabelTiled, launch_tiled_relabel(w, tp, stream, row_gen, relabel_pairs));
     } else if (mtl_mode == 2) {   // MergeToLarge step (rounds >= 1 only)
         RUN(kMergeLarge, launch_mtl_labels(w, mtl_alpha, gn, gm, stream));
         RUN(kLabelRanks, launch_rank_parents(w, gn, small_flags ? 0 : gscan_l, stream));
@@ -278,7 +280,7 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 2));
             RUN(kSortScan, launch_sort_pass(w, p, gscan_c, stream, 3));
         }
-        RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4, gated));
+        RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 4, gated, scatter_waves));
     }
     if (dedup != kDedupSort) {   // after the gated sort, whose skipped count pass empties aux_n
         RUN(kHashDedup, launch_hash_dedup(w, gt, stream, 2));
@@ -798,8 +800,11 @@ cc_status cc_set_workspace(cc_ctx *c, void *d_ws, size_t bytes) {
 
 cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     if (!c || !t) return CC_E_ARG;
+    auto one_of = [](int v, int a, int b, int d) { return v == 0 || v == a || v == b || v == d; };
     if (t->round0 < 0 || t->round0 > 3 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
-        (t->round0_key_sets != 0 && t->round0_key_sets != 1) || t->reserved != 0)
+        (t->round0_key_sets != 0 && t->round0_key_sets != 1) || !one_of(t->scatter_waves, 2, 3, 4) ||
+        !one_of(t->row_pairs, 2, 4, 8) || !one_of(t->relabel_pairs, 1, 2, 4) || t->row_generation < -1 ||
+        t->row_generation > 8 || t->reserved != 0)
         return reject(c, CC_E_ARG, "tuning value out of range");
     const bool tiled = t->round0 == 0 ? c->tiled : t->round0 >= 2;
     const bool rows = t->round0 == 0 ? c->tiled_rows : t->round0 == 3;
@@ -814,6 +819,10 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     c->blocks_per_cu = t->blocks_per_cu ? t->blocks_per_cu : 8;
     c->grid_cap = c->cus * c->blocks_per_cu;
     c->round0_sets_off = t->round0_key_sets == 0;
+    c->scatter_waves = t->scatter_waves ? t->scatter_waves : LC_SCATTER_WAVES;
+    c->row_pairs = t->row_pairs ? t->row_pairs : LC_TMIN2_PAIRS;
+    c->relabel_pairs = t->relabel_pairs ? t->relabel_pairs : LC_TRELABEL_PAIRS;
+    c->row_generation = t->row_generation ? t->row_generation : 1;
     drop_tails(c);   // captured with the previous grid sizes and layout
     if (!c->ws) return CC_OK;
     plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)c->ws, &c->w, ws_extras(c->o.flags));
@@ -826,6 +835,10 @@ cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
     t->round0 = c->tiled ? (c->tiled_rows ? 3 : 2) : 1;
     t->blocks_per_cu = c->blocks_per_cu;
     t->round0_key_sets = c->round0_sets_off ? 0 : 1;
+    t->scatter_waves = c->scatter_waves;
+    t->row_pairs = c->row_pairs;
+    t->relabel_pairs = c->relabel_pairs;
+    t->row_generation = c->row_generation;
     t->reserved = 0;
     return CC_OK;
 }

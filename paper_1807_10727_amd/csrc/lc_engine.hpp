@@ -62,6 +62,10 @@ struct Engine {
     int cus = 256;                // compute units (row generations, resident scatter grid)
     int blocks_per_cu = 8;        // tuning: grid_cap = cus * blocks_per_cu
     bool round0_sets_off = false; // tuning: round 0's relabel without key sets
+    int scatter_waves = LC_SCATTER_WAVES;  // tuning: radix scatter build (waves per SIMD)
+    int row_pairs = LC_TMIN2_PAIRS;        // tuning: tiled two-hop pass, record pairs per thread
+    int relabel_pairs = LC_TRELABEL_PAIRS; // tuning: tiled relabel, record pairs per thread
+    int row_generation = 1;                // tuning: gathering row passes, rows per CU a launch (-1 all)
     void *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state

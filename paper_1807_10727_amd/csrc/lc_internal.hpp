@@ -167,7 +167,18 @@ constexpr int64_t kHashMaxRecords = 1 << 22;   // as large as a captured tail's 
 // far fewer than its records) do: the hashing kernels and the sort are both enqueued, gated.
 enum Dedup { kDedupSort = 0, kDedupHash = 1, kDedupDevice = 2 };
 #ifndef LC_SCATTER_WAVES
-#define LC_SCATTER_WAVES 3   // waves per SIMD the radix scatter is compiled for
+#define LC_SCATTER_WAVES 3   // default waves per SIMD of the radix scatter (2, 3 or 4 are built)
+#endif
+static_assert(LC_SCATTER_WAVES >= 2 && LC_SCATTER_WAVES <= 4, "the radix scatter is built for 2, 3 or 4 waves");
+// Record pairs each thread keeps in flight in the gathering row kernels of the tiled round 0
+// (defaults; the tuner may pick others).  A row sweeps the whole column id space once, so
+// the ids its workgroup gathers in one step span (pairs * 2 * 1024 / row records) of that
+// space: few enough pairs keep the span of the rows running together on an XCD inside its L2.
+#ifndef LC_TMIN2_PAIRS
+#define LC_TMIN2_PAIRS 4
+#endif
+#ifndef LC_TRELABEL_PAIRS
+#define LC_TRELABEL_PAIRS 2
 #endif
 #ifndef LC_SCATTER_GRID
 #define LC_SCATTER_GRID 1
@@ -325,7 +336,9 @@ hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
 // gated (this and the unique): skipped when the round's device-side choice was to hash
-hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated = false);
+// scatter_waves: the radix scatter build to launch (2, 3 or 4 waves per SIMD)
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated = false,
+                            int scatter_waves = LC_SCATTER_WAVES);
 // prefix counts of the label map (total -> n_labels) or of the next-graph node map over the
 // labels (total -> n_next)
 hipError_t launch_map_scan(const Work &w, bool labels, int grid, hipStream_t s, int stage);
@@ -364,8 +377,10 @@ hipError_t launch_tiled_min1(const Work &w, const PrioCtx &p, const TPlan &tp, h
 // the one-hop label's parents from the row pass's one-hop minima
 hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipStream_t s);
 // gen: rows per launch (the CU count: one 1024-thread, 128 KiB-LDS workgroup each)
-hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen);
-hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen);
+// gen: rows launched together (<= 0: all rows in one launch); pairs: record pairs in flight
+// per thread (two-hop pass 2, 4 or 8; relabel 1, 2 or 4; other values take the default)
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen, int pairs);
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen, int pairs);
 
 // Scan stages: 0 = block sums, 1 = scan of the sums (one workgroup), 2 = block downsweep.
 // Sort stages: 0 = digit counts, 1..3 = scan of the counts (or 5: the whole scan in one

@@ -220,10 +220,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass, in
     }
 }
 
-// Waves per SIMD the scatter is compiled for (LC_SCATTER_WAVES): 3 trades a few spilled
-// words for a third more waves in flight than the unconstrained register count allows
-// (measured faster).
-__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(LC_SCATTER_WAVES)))
+// Waves per SIMD the scatter is compiled for: 3 (the default, LC_SCATTER_WAVES) trades a few
+// spilled words for a third more waves in flight than the unconstrained register count
+// allows (measured faster on the bench graph).  Builds for 2 and 4 waves exist for the tuner.
+template <int kWavesPerSimd>
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd)))
 void k_sort_scatter(Work w, int pass, int gated) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
@@ -719,7 +720,8 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
     return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated) {
+hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated,
+                            int scatter_waves) {
     switch (stage) {
         case 5:   // the count table scanned by one workgroup (small rounds)
             hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kThreads), 0, s, w.counts, &w.st->aux_n, 0,
@@ -733,7 +735,12 @@ hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, in
         case 3:
             return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 1);
         default:
-            hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
+            if (scatter_waves == 2)
+                hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
+            else if (scatter_waves == 4)
+                hipLaunchKernelGGL(k_sort_scatter<4>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
+            else
+                hipLaunchKernelGGL(k_sort_scatter<3>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
             return hipGetLastError();
     }
 }

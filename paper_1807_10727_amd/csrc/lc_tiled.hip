@@ -5,7 +5,8 @@
 // cache line.  This file first partitions the input, once, into directed records
 // (x << 32 | y), two per loop-free input record, grouped by the row block x >> xs and,
 // inside a row, by the column block y >> ys (two counting passes: pass A by column into
-// one key buffer, pass B by row into the other; the order inside a tile is free).  Then:
+// one key buffer, pass B by row into the other; the order inside a tile is free), or by
+// row only in one counting pass (no column order).  Then:
 //
 //   min1     one workgroup per row: LDS minimum of rho(y) over the row's records, folded
 //            with rho(x); no global atomics (Section 2: x is in its own neighbourhood)
@@ -19,17 +20,6 @@
 
 #include "lc_internal.hpp"
 #include "lc_readers.hpp"
-
-// Record pairs each thread keeps in flight in the gathering row kernels.  A row sweeps
-// the whole column id space once, so the ids its workgroup gathers in one step span
-// (pairs * 2 * 1024 / row records) of that space: few enough pairs keep the span of the
-// rows running together on an XCD inside its L2.
-#ifndef LC_TMIN2_PAIRS
-#define LC_TMIN2_PAIRS 4
-#endif
-#ifndef LC_TRELABEL_PAIRS
-#define LC_TRELABEL_PAIRS 2
-#endif
 
 namespace lc {
 
@@ -434,9 +424,9 @@ __device__ inline void row_range(const Work &w, const TPlan &tp, int X, int64_t 
 // id without a loop-free record; kOpen leaves rho(x) out (TreeContraction's open
 // neighbourhood).  kStep 2: two-hop minimum min(m1[x], min m1[y]) and the parent it names
 // (the inverse of the priority bijection); an id without records is its own parent.
-template <int kStep, bool kOpen = false>
+template <int kStep, bool kOpen = false, int kPairs2 = LC_TMIN2_PAIRS>
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_min(Work w, PrioCtx pc, TPlan tp, int row0) {
-    constexpr int kUnroll = kStep == 1 ? 4 : LC_TMIN2_PAIRS;   // record pairs in flight per thread
+    constexpr int kUnroll = kStep == 1 ? 4 : kPairs2;   // record pairs in flight per thread
     __shared__ uint32_t acc[1 << kTxShiftMax];
     RoundState *st = w.st;
     pc.key = st->key;
@@ -550,8 +540,8 @@ __device__ inline bool row_set_insert(unsigned long long *set, uint64_t key) {
 // records; each chunk reserves its survivors' space at the end of the packed key array with
 // one atomic, so the first radix pass reads full tiles (only about half of the directed
 // records are taken, which would leave slabs aligned to the records half empty).
+template <int kPairs>   // record pairs per thread and chunk (LC_TRELABEL_PAIRS by default)
 __global__ __launch_bounds__(kTRowThreads) void k_tiled_relabel(Work w, TPlan tp, int row0) {
-    constexpr int kPairs = LC_TRELABEL_PAIRS;   // record pairs per thread and chunk
     constexpr int kChunk = 2 * kPairs * kTRowThreads;
     RoundState *st = w.st;
     __shared__ uint32_t lpar[1 << kTxShiftMax];
@@ -791,16 +781,26 @@ hipError_t launch_tiled_parent1(const Work &w, const PrioCtx &p, int grid, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen) {
+hipError_t launch_tiled_min2(const Work &w, const PrioCtx &p, const TPlan &tp, hipStream_t s, int gen, int pairs) {
     return by_generations(tp, gen, [&](int r0, int g) {
-        hipLaunchKernelGGL(k_tiled_min<2>, dim3(g), dim3(kTRowThreads), 0, s, w, p, tp, r0);
+        if (pairs == 2)
+            hipLaunchKernelGGL((k_tiled_min<2, false, 2>), dim3(g), dim3(kTRowThreads), 0, s, w, p, tp, r0);
+        else if (pairs == 8)
+            hipLaunchKernelGGL((k_tiled_min<2, false, 8>), dim3(g), dim3(kTRowThreads), 0, s, w, p, tp, r0);
+        else
+            hipLaunchKernelGGL((k_tiled_min<2, false, 4>), dim3(g), dim3(kTRowThreads), 0, s, w, p, tp, r0);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen) {
+hipError_t launch_tiled_relabel(const Work &w, const TPlan &tp, hipStream_t s, int gen, int pairs) {
     return by_generations(tp, gen, [&](int r0, int g) {
-        hipLaunchKernelGGL(k_tiled_relabel, dim3(g), dim3(kTRowThreads), 0, s, w, tp, r0);
+        if (pairs == 1)
+            hipLaunchKernelGGL(k_tiled_relabel<1>, dim3(g), dim3(kTRowThreads), 0, s, w, tp, r0);
+        else if (pairs == 4)
+            hipLaunchKernelGGL(k_tiled_relabel<4>, dim3(g), dim3(kTRowThreads), 0, s, w, tp, r0);
+        else
+            hipLaunchKernelGGL(k_tiled_relabel<2>, dim3(g), dim3(kTRowThreads), 0, s, w, tp, r0);
         return hipGetLastError();
     });
 }

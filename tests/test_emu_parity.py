@@ -43,12 +43,12 @@ def inputs(g, layout):
     return dev(graphgen.pack(g.src, g.dst), np.uint64), None
 
 
-def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=True, round0=0):
+def check_solve(cc, g, seed, flags=0, layout="soa32", rule="local", per_round=True, round0=0, tuning=None):
     want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule, record_parents=True)
     s_, d_ = inputs(g, layout)
     with hipemu.Solver(g.n, s_, d_, seed=seed, flags=flags | RULES[rule] | cc.CC_EAGER) as s:
-        if round0:
-            s.set_tuning(round0=round0)
+        if round0 or tuning:
+            s.set_tuning(round0=round0, **(tuning or {}))
         a, b = g.src, g.dst
         r = 0
         while per_round:
@@ -585,7 +585,8 @@ def test_emulated_tuning_knobs_keep_results(cc):
             for bpc in (1, 4, 16):
                 for ks in (1, 0):
                     s.set_tuning(round0=r0, blocks_per_cu=bpc, round0_key_sets=ks)
-                    assert s.tuning == {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
+                    assert {k: s.tuning[k] for k in ("round0", "blocks_per_cu", "round0_key_sets")} == \
+                        {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
                     r = s.run()
                     assert r == want.rounds
                     assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
@@ -601,3 +602,28 @@ def test_emulated_tuning_knobs_keep_results(cc):
         with pytest.raises(cc.CCError) as e:
             s.set_tuning(round0=2)
         assert e.value.status == cc.CC_E_ARG
+
+
+KERNEL_KNOBS = [("scatter_waves", (2, 4)), ("row_pairs", (2, 8)), ("relabel_pairs", (1, 4)),
+                ("row_generation", (2, 8, -1))]
+
+
+@pytest.mark.parametrize("r0", [2, 3])
+def test_emulated_kernel_knobs_keep_results(cc, r0):
+    """The kernel builds and launch shapes the tuner may pick (radix scatter waves, record
+    pairs in flight in the tiled row passes, rows launched together) give the oracle's rounds,
+    statistics and labels, round by round; 0 means the default and is reported resolved; values
+    outside the built set are refused."""
+    g = graphgen.Graph(1 << 15, *graphgen.rmat(9, 15, (8 << 15) + 777))
+    for knob, values in KERNEL_KNOBS:
+        for v in values:
+            check_solve(cc, g, 6, flags=TILED, round0=r0, per_round=(knob == "row_pairs"), tuning={knob: v})
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=TILED) as s:
+        s.set_tuning()
+        t = s.tuning
+        assert (t["scatter_waves"], t["row_pairs"], t["relabel_pairs"], t["row_generation"]) == (3, 4, 2, 1)
+        for knob, bad in (("scatter_waves", 5), ("row_pairs", 3), ("relabel_pairs", 8), ("row_generation", 9),
+                          ("row_generation", -2)):
+            with pytest.raises(cc.CCError) as e:
+                s.set_tuning(**{knob: bad})
+            assert e.value.status == cc.CC_E_ARG

@@ -271,7 +271,8 @@ def test_tuning_knobs_keep_results(lc):
             for bpc in (1, 8, 16):
                 for ks in (1, 0):
                     s.set_tuning(round0=r0, blocks_per_cu=bpc, round0_key_sets=ks)
-                    assert s.tuning == {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
+                    assert {k: s.tuning[k] for k in ("round0", "blocks_per_cu", "round0_key_sets")} == \
+                        {"round0": r0, "blocks_per_cu": bpc, "round0_key_sets": ks}
                     r = s.run()
                     assert r == want.rounds, (r0, bpc, ks)
                     assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats], (r0, bpc, ks)
@@ -281,6 +282,26 @@ def test_tuning_knobs_keep_results(lc):
                                        "part_rows_scatter") if t[f][1]}
                     assert ran == [set(), {"min1_round0"}, {"part_a_hist", "part_b_scatter"},
                                    {"part_rows_hist", "part_rows_scatter"}][r0], (r0, ran)
+
+
+@pytest.mark.parametrize("r0", [2, 3])
+def test_kernel_knobs_keep_results(lc, r0):
+    """The kernel builds and launch shapes the tuner may pick (radix scatter waves, record
+    pairs in flight in the tiled row passes, rows launched together) give the oracle's rounds,
+    statistics and labels, on a power-law graph of many rows and partition tiles."""
+    g = graphgen.Graph(1 << 17, *graphgen.rmat(0x7078, 17, (12 << 17) + 1021))
+    want = oracle.run(g.n, g.src, g.dst, seed=13)
+    s_t, d_t, _ = to_device(g)
+    with lc.Solver(g.n, s_t, d_t, seed=13, flags=MODES["tiled"]) as s:
+        for knob, values in (("scatter_waves", (2, 3, 4)), ("row_pairs", (2, 4, 8)), ("relabel_pairs", (1, 2, 4)),
+                             ("row_generation", (1, 2, 8, -1))):
+            for v in values:
+                s.set_tuning(round0=r0, **{knob: v})
+                assert s.tuning[knob] == v and s.tuning["round0"] == r0
+                r = s.run()
+                assert r == want.rounds, (knob, v)
+                assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats], (knob, v)
+                assert np.array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels), (knob, v)
 
 
 # --- heavy repeats and a hub ------------------------------------------------------------
