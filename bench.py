@@ -40,7 +40,7 @@ FAMILY_STEP = {
     "label_ranks": "a4_relabel", "relabel_round0": "a4_relabel", "relabel": "a4_relabel",
     "relabel_tiled": "a4_relabel",
     "sort_hist": "a5_dedup", "sort_scan": "a5_dedup", "sort_scatter": "a5_dedup", "unique": "a5_dedup",
-    "hash_dedup": "a5_dedup",
+    "hash_dedup": "a5_dedup", "bucket_sort": "a5_dedup",
     "node_scan": "a6_nodes", "nodes": "a6_nodes", "map": "a6_nodes", "round_end": "a6_nodes",
     "compose": "a7_labels", "flatten": "a7_labels",
     "part_a_hist": "partition", "part_a_scatter": "partition", "part_b_hist": "partition",

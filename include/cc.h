@@ -205,6 +205,9 @@ typedef struct {
     int32_t row_generation;   /* tiled round 0: rows of the two gathering row passes launched
                                  together, per compute unit (1..8); 0: 1; -1: every row in one
                                  launch */
+    int32_t round0_sort;      /* how round 0 orders its keys for the duplicate drop: 1 (0: default)
+                                 LSD radix passes; 2 two levels of buckets cut at splitters drawn
+                                 from the keys, then each bucket sorted in LDS */
     int32_t reserved;         /* must be 0 */
 } cc_tuning;
 

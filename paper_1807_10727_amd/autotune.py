@@ -122,6 +122,7 @@ SOLVER_SPACE = {
     "row_pairs": [4, 2, 8],            # the tiled forms only (no effect on a direct round 0)
     "relabel_pairs": [2, 1, 4],
     "row_generation": [1, 2, -1],
+    "round0_sort": [1, 2],             # LSD radix passes, sampled buckets
 }
 
 

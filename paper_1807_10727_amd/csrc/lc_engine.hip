@@ -35,7 +35,7 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter"};
+    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter", "bucket_sort"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -68,6 +68,8 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
         count_entries = std::max(count_entries, (size_t)256 * (size_t)tp.tiles_a);
         count_entries = std::max(count_entries, (size_t)tp.rows * (size_t)tp.tiles_b);
     }
+    // the sampled buckets' second level: tiles never cross a first-level bucket
+    if (!batch) count_entries = std::max(count_entries, (size_t)256 * (tiles + kBucketLevel2Tiles));
     const size_t parts = std::max<size_t>((size_t)ceil_div((int64_t)n, kScanTile),
                                           (size_t)ceil_div((int64_t)count_entries, kScanTile)) + 16;
     size_t off = 0;
@@ -109,6 +111,11 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
     if (extras & kWsRecord) {
         t.rec_cap = kRecordPerVertex * (int64_t)n;
         t.rec = (uint32_t *)take(4 * (size_t)t.rec_cap);
+    }
+    if (!batch) {
+        t.btab = (BucketTab *)take(sizeof(BucketTab) * 257);
+        t.bseg = (uint64_t *)take(8 * 257);
+        t.btile = (uint32_t *)take(4 * 257);
     }
     if (extras & kWsMerge) {
         t.mtl_size = (uint32_t *)take(4 * n);
@@ -271,7 +278,26 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
     const int ghash = grid_tiles(hmax);
     // the table sized and cleared first: when gated, that kernel also records the choice
     if (dedup != kDedupSort) RUN(kHashDedup, launch_hash_dedup(w, grid_for(hmax), stream, 1, gated));
-    for (int p = 0; p < (dedup == kDedupHash ? 0 : passes); ++p) {
+    const bool buckets = first && !batch && round0_sort == 2;
+    if (buckets) {   // round 0's keys into sampled buckets, each sorted in LDS (lc_bucket.hip)
+        const int64_t entries =
+            (int64_t)256 * (ceil_div(std::max<int64_t>(tiled ? 2 * M : M, 1), kSortTile) + 2 + kBucketLevel2Tiles);
+        const int gsb = (int)std::min<int64_t>(ceil_div(entries, kScanTile), grid_cap);
+        RUN(kBucketSort, launch_bucket(w, 0, 1, stream));
+        for (int level = 0; level < 2; ++level) {
+            if (level == 1) {
+                RUN(kBucketSort, launch_bucket(w, 3, 1, stream));
+                RUN(kBucketSort, launch_bucket(w, 4, 256, stream));
+            }
+            RUN(kBucketSort, launch_bucket(w, level ? 5 : 1, gt, stream));
+            RUN(kSortScan, launch_sort_pass(w, 0, gsb, stream, 1));
+            RUN(kSortScan, launch_sort_pass(w, 0, 1, stream, 2));
+            RUN(kSortScan, launch_sort_pass(w, 0, gsb, stream, 3));
+            RUN(kBucketSort, launch_bucket(w, level ? 6 : 2, gt, stream));
+        }
+        RUN(kBucketSort, launch_bucket(w, 7, grid_cap, stream));
+    }
+    for (int p = 0; p < (dedup == kDedupHash || buckets ? 0 : passes); ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0, gated));
         if (small_sort) {
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 5));
@@ -804,7 +830,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     if (t->round0 < 0 || t->round0 > 3 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
         (t->round0_key_sets != 0 && t->round0_key_sets != 1) || !one_of(t->scatter_waves, 2, 3, 4) ||
         !one_of(t->row_pairs, 2, 4, 8) || !one_of(t->relabel_pairs, 1, 2, 4) || t->row_generation < -1 ||
-        t->row_generation > 8 || t->reserved != 0)
+        t->row_generation > 8 || t->round0_sort < 0 || t->round0_sort > 2 || t->reserved != 0)
         return reject(c, CC_E_ARG, "tuning value out of range");
     const bool tiled = t->round0 == 0 ? c->tiled : t->round0 >= 2;
     const bool rows = t->round0 == 0 ? c->tiled_rows : t->round0 == 3;
@@ -823,6 +849,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     c->row_pairs = t->row_pairs ? t->row_pairs : LC_TMIN2_PAIRS;
     c->relabel_pairs = t->relabel_pairs ? t->relabel_pairs : LC_TRELABEL_PAIRS;
     c->row_generation = t->row_generation ? t->row_generation : 1;
+    c->round0_sort = t->round0_sort ? t->round0_sort : 1;
     drop_tails(c);   // captured with the previous grid sizes and layout
     if (!c->ws) return CC_OK;
     plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)c->ws, &c->w, ws_extras(c->o.flags));
@@ -839,6 +866,7 @@ cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
     t->row_pairs = c->row_pairs;
     t->relabel_pairs = c->relabel_pairs;
     t->row_generation = c->row_generation;
+    t->round0_sort = c->round0_sort;
     t->reserved = 0;
     return CC_OK;
 }

@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kPartRowsHist, kPartRowsScatter, kFamilies
+    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kPartRowsHist, kPartRowsScatter, kBucketSort, kFamilies
 };
 
 // how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)
@@ -66,6 +66,7 @@ struct Engine {
     int row_pairs = LC_TMIN2_PAIRS;        // tuning: tiled two-hop pass, record pairs per thread
     int relabel_pairs = LC_TRELABEL_PAIRS; // tuning: tiled relabel, record pairs per thread
     int row_generation = 1;                // tuning: gathering row passes, rows per CU a launch (-1 all)
+    int round0_sort = 1;                   // tuning: round 0's duplicate drop, 1 radix passes, 2 sampled buckets
     void *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state

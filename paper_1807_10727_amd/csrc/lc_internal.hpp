@@ -41,6 +41,8 @@ struct RoundState {
     RoundKey key;      // this round's priority key, round_key(seed, round) (plain solve)
     int32_t rounds_active;   // rounds so far that read at least one record
     int32_t hash_slots;      // slots of the hashed duplicate drop (rounds that use it)
+    u64c b_tiles1;           // sampled buckets: tiles of the first level
+    u64c b_tiles2;           // sampled buckets: tiles of the second level (within first-level buckets)
     alignas(128) u64c n_active;   // nodes with a loop-free edge (atomics)
     alignas(128) u64c s_count;    // records surviving relabelling, repeats counted (atomics)
     alignas(128) u64c s_keys;     // sort keys written by the relabel: the survivors less the
@@ -94,6 +96,22 @@ __device__ inline uint32_t rho_name(const PrioCtx &pc, uint32_t p, int64_t n0) {
     return prio_inv(pc.key, p);
 }
 
+// Splitters of one level of the sampled-bucket duplicate drop (lc_bucket.hip): up to 255
+// distinct sample values u[0] < u[1] < ... cut the keys into at most 256 buckets in key order.
+// A value that several splitter ranks of the sample fell on ("heavy") gets a bucket of its
+// own, holding only keys equal to it; the open bucket open_id[i] holds the keys above u[i-1]
+// and up to u[i] (below u[i] when u[i] is heavy), open_id[m] those above u[m-1].
+struct alignas(16) BucketTab {
+    uint64_t u[255];
+    uint8_t heavy[255];
+    uint8_t eq_id[255];     // bucket of the keys equal to a heavy u[i]
+    uint8_t open_id[256];
+    uint8_t eqb[256];       // bucket b holds a single key value
+    int32_t m;              // distinct splitters
+    int32_t nb;             // buckets (<= 256)
+};
+static_assert(sizeof(BucketTab) % 16 == 0, "bucket tables are copied in 16-byte words");
+
 // Workspace arrays of one solve (device pointers).
 struct Work {
     RoundState *st;
@@ -127,6 +145,12 @@ struct Work {
     uint32_t *mtl_size, *mtl_v, *mtl_cnt;   // [n0] each
     uint64_t *mtl_acc[2];                    // [n0] each
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
+    // sampled-bucket duplicate drop (single solves): the first level's table and one table per
+    // first-level bucket; first-level bucket starts ([257], the last = keys) and first tiles of
+    // the second level ([257], the last = its tile count)
+    BucketTab *btab;     // [257]
+    uint64_t *bseg;      // [257]
+    uint32_t *btile;     // [257]
     int32_t *g_rounds;   // batch: [G] rounds in which each graph still had an edge
     int64_t n0, m0;
     int32_t round0_sets_off;   // 1: round 0's relabel workgroups keep no key set (tuning)
@@ -332,6 +356,41 @@ hipError_t launch_mtl_labels(const Work &w, uint64_t alpha, int grid_nodes, int 
 // union-find finish of the graph of round `round` (lc_variants.hip)
 hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_edges, hipStream_t s);
 hipError_t launch_relabel(const Work &w, const EdgeIn *in, int grid, hipStream_t s);
+// Tiles of one pass.  Pass 0 reads the relabel output in place: either packed (the tiled
+// round 0), or in slabs, where tile t is the (t % 2)-th half of slab t / 2,
+// filled from its start with that slab's survivors.  Later passes read a compact array of S
+// keys.  In every case the keys of tile t are the first valid(t) positions of
+// [t * kSortTile, (t + 1) * kSortTile).
+struct Tiles {
+    int64_t ntiles;
+    int64_t S;
+    const uint32_t *slab_cnt;
+    bool slab;
+    __device__ int valid(int64_t t) const {
+        constexpr int kPer = kSlab / kSortTile;
+        const int64_t c = slab ? (int64_t)slab_cnt[t / kPer] - (t % kPer) * kSortTile : S - t * kSortTile;
+        return c <= 0 ? 0 : (c >= kSortTile ? kSortTile : (int)c);
+    }
+};
+
+__device__ inline Tiles tiles_of(const Work &w, int pass) {
+    const RoundState *st = w.st;
+    Tiles t;
+    t.S = (int64_t)st->s_keys;
+    t.slab = pass == 0 && !st->keys_dense;
+    t.slab_cnt = w.slab_cnt;
+    t.ntiles = t.slab ? (int64_t)st->n_slabs * (kSlab / kSortTile) : ceil_div(t.S, kSortTile);
+    return t;
+}
+
+// Sampled-bucket duplicate drop of round 0 (lc_bucket.hip), in place of the radix passes:
+// stage 0 first-level splitters (one workgroup), 1 first-level counts, 2 first-level scatter,
+// 3 first-level bucket starts and second-level tiles (one workgroup), 4 second-level
+// splitters, 5 second-level counts, 6 second-level scatter, 7 sort of each final bucket into
+// the buffer the radix passes would have left the keys in.  The count tables are scanned
+// between stages 1 and 2 and between 5 and 6 (launch_sort_pass stages 1-3).
+constexpr int kBucketLevel2Tiles = 256;   // extra count-table tiles of the second level
+hipError_t launch_bucket(const Work &w, int stage, int grid, hipStream_t s);
 // parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);

@@ -125,33 +125,6 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const T *in, uint32_t *o
 // radix sort passes
 // ---------------------------------------------------------------------------------------
 
-// Tiles of one pass.  Pass 0 reads the relabel output in place: either packed (the tiled
-// round 0), or in slabs, where tile t is the (t % 2)-th half of slab t / 2,
-// filled from its start with that slab's survivors.  Later passes read a compact array of S
-// keys.  In every case the keys of tile t are the first valid(t) positions of
-// [t * kSortTile, (t + 1) * kSortTile).
-struct Tiles {
-    int64_t ntiles;
-    int64_t S;
-    const uint32_t *slab_cnt;
-    bool slab;
-    __device__ int valid(int64_t t) const {
-        constexpr int kPer = kSlab / kSortTile;
-        const int64_t c = slab ? (int64_t)slab_cnt[t / kPer] - (t % kPer) * kSortTile : S - t * kSortTile;
-        return c <= 0 ? 0 : (c >= kSortTile ? kSortTile : (int)c);
-    }
-};
-
-__device__ inline Tiles tiles_of(const Work &w, int pass) {
-    const RoundState *st = w.st;
-    Tiles t;
-    t.S = (int64_t)st->s_keys;
-    t.slab = pass == 0 && !st->keys_dense;
-    t.slab_cnt = w.slab_cnt;
-    t.ntiles = t.slab ? (int64_t)st->n_slabs * (kSlab / kSortTile) : ceil_div(t.S, kSortTile);
-    return t;
-}
-
 // Keys stream through each radix pass once: non-temporal loads leave L2 to the per-tile
 // tables and the output runs (measured: count pass ~11 % faster, scatter ~2 %).
 #ifndef LC_NT_KEYS

@@ -26,7 +26,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 # HIPEMU_ASAN=1: the bounds-checking build -- AddressSanitizer, with a guard gap after every
 # workspace buffer (LC_WS_GUARD), so that any access outside an allocation or past a carved
-# buffer's end stops the process with a report.  The process must preload asan_runtime().
+# buffer's end stops the process with a report, and a tiny sample and LDS capacity for the
+# sampled-bucket sort's second level and final buckets (its global-memory path then runs too).  The process must preload
+# asan_runtime().
 ASAN = os.environ.get("HIPEMU_ASAN") == "1"
 BUILD = os.path.join(HERE, "_build_asan" if ASAN else "_build")
 CSRC = os.path.join(ROOT, "paper_1807_10727_amd", "csrc")
@@ -64,7 +66,11 @@ def build(force: bool = False) -> str:
              "-I", os.path.join(HERE, "include"), "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     link = []
     if ASAN:
-        flags += ["-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-DLC_WS_GUARD=256"]
+        # the sampled-bucket sort cuts its second level from 4 sampled keys and holds at most
+        # 16 keys of a final bucket in LDS here, so that its in-place global sort of larger
+        # buckets runs in every test that uses that sort
+        flags += ["-O1", "-g", "-fsanitize=address", "-fno-omit-frame-pointer", "-DLC_WS_GUARD=256",
+                  "-DLC_BUCKET_CAP=16", "-DLC_BUCKET_SAMPLE2=4"]
         link = ["-fsanitize=address", "-shared-libasan"]
 
     def compile_one(src):

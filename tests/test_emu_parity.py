@@ -604,6 +604,28 @@ def test_emulated_tuning_knobs_keep_results(cc):
         assert e.value.status == cc.CC_E_ARG
 
 
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
+@pytest.mark.parametrize("layout", ["soa32", "packed"])
+def test_emulated_bucket_sort_matches_oracle(cc, mode, layout):
+    """Round 0's keys ordered by the sampled buckets instead of the radix passes: parents,
+    edges, statistics and labels of every round equal the oracle's."""
+    g = graphgen.Graph(6000, *graphgen.gnm(0x5152, 6000, 24011))
+    check_solve(cc, g, 3, flags={"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode], layout=layout,
+                round0=3 if mode == "rows" else 0, tuning={"round0_sort": 2})
+
+
+@pytest.mark.parametrize("key_sets", [1, 0])
+def test_emulated_bucket_sort_heavy_keys(cc, key_sets):
+    """A power-law graph whose round-0 keys repeat many times (most of all with the relabel's
+    key sets off): heavy keys get buckets of their own; the results stay the oracle's."""
+    g = graphgen.Graph(1 << 14, *graphgen.rmat(31, 14, 20 << 14))
+    for flags in (TILED, DIRECT):
+        check_solve(cc, g, 8, flags=flags, per_round=False,
+                    tuning={"round0_sort": 2, "round0_key_sets": key_sets})
+    star = graphgen.Graph(3000, np.zeros(40000, np.uint32), (np.arange(40000) % 2999 + 1).astype(np.uint32))
+    check_solve(cc, star, 2, flags=TILED, tuning={"round0_sort": 2, "round0_key_sets": key_sets})
+
+
 KERNEL_KNOBS = [("scatter_waves", (2, 4)), ("row_pairs", (2, 8)), ("relabel_pairs", (1, 4)),
                 ("row_generation", (2, 8, -1))]
 
@@ -621,9 +643,10 @@ def test_emulated_kernel_knobs_keep_results(cc, r0):
     with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=TILED) as s:
         s.set_tuning()
         t = s.tuning
-        assert (t["scatter_waves"], t["row_pairs"], t["relabel_pairs"], t["row_generation"]) == (3, 4, 2, 1)
+        assert (t["scatter_waves"], t["row_pairs"], t["relabel_pairs"], t["row_generation"], t["round0_sort"]) == \
+            (3, 4, 2, 1, 1)
         for knob, bad in (("scatter_waves", 5), ("row_pairs", 3), ("relabel_pairs", 8), ("row_generation", 9),
-                          ("row_generation", -2)):
+                          ("row_generation", -2), ("round0_sort", 3)):
             with pytest.raises(cc.CCError) as e:
                 s.set_tuning(**{knob: bad})
             assert e.value.status == cc.CC_E_ARG

@@ -237,6 +237,31 @@ def test_er_paths_round0_edges(lc, er_full):
     np.testing.assert_array_equal(got, want)
 
 
+TUNED = [{"round0_sort": 2}, {"round0": 3}, {"round0": 3, "round0_sort": 2, "round0_key_sets": 0},
+         {"round0": 1, "round0_sort": 2}, {"row_pairs": 8, "relabel_pairs": 4, "row_generation": -1, "scatter_waves": 4}]
+
+
+@pytest.mark.timeout(900)
+def test_er_paths_tuned_vs_oracle(lc, er_full):
+    """The bench graph under the knobs the tuner may pick (the sampled-bucket sort of round 0's
+    129 M keys, the one-pass row partition, the direct round 0, other row-pass and scatter
+    builds): rounds, statistics and labels bit for bit against the oracle."""
+    g, futs = er_full
+    src_t = torch.from_numpy(g.src.view(np.int32)).to(DEV)
+    dst_t = torch.from_numpy(g.dst.view(np.int32)).to(DEV)
+    want = futs["local"].result()
+    with lc.Solver(g.n, src_t, dst_t, seed=BENCH_SEED, stream=torch.cuda.current_stream()) as s:
+        for knobs in TUNED:
+            print("knobs", knobs, flush=True)
+            s.set_tuning(**knobs)
+            rounds = s.run()
+            assert rounds == want.rounds, knobs
+            assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats], knobs
+            np.testing.assert_array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels, err_msg=str(knobs))
+    del src_t, dst_t
+    torch.cuda.empty_cache()
+
+
 @pytest.fixture(scope="module")
 def rmat26():
     return graphgen.workload_rmat()
@@ -261,7 +286,8 @@ def test_rmat26_bit_exact_vs_oracle(lc, rmat26):
     """R-MAT scale 26 at the bench's first seed against the oracle's stored results
     (tests/golden/rmat26_seed_c0ffee01.json, written by make_rmat26_golden.py from the oracle
     alone): in the timed configuration (tiled round 0, CC_PROFILE, a context that has solved
-    before) the round count, every round's statistics and the SHA-256 of the raw labels; with
+    before) the round count, every round's statistics and the SHA-256 of the raw labels; the
+    same under the knobs the tuner may pick; with
     every round recorded, round 0 direct and tiled, the SHA-256 of every round's parents by
     name; and the canonical labels."""
     with open(RMAT26_GOLDEN) as f:
@@ -280,6 +306,15 @@ def test_rmat26_bit_exact_vs_oracle(lc, rmat26):
         assert rounds == gold["rounds"]
         assert [tuple(x) for x in s.stats(rounds)] == want_stats
         assert _sha(s.labels().cpu().numpy().view(np.uint32)) == gold["labels_sha256"]
+    torch.cuda.empty_cache()
+    with lc.Solver(n, keys, None, seed=BENCH_SEED, stream=stream) as s:   # the knobs the tuner may pick
+        for knobs in TUNED:
+            print("knobs", knobs, flush=True)
+            s.set_tuning(**knobs)
+            rounds = s.run()
+            assert rounds == gold["rounds"], knobs
+            assert [tuple(x) for x in s.stats(rounds)] == want_stats, knobs
+            assert _sha(s.labels().cpu().numpy().view(np.uint32)) == gold["labels_sha256"], knobs
     torch.cuda.empty_cache()
     for flags in (lc.CC_ROUND0_DIRECT, lc.CC_ROUND0_TILED | lc.CC_CANONICAL):
         with lc.Solver(n, keys, None, seed=BENCH_SEED, flags=flags | lc.CC_RECORD_ROUNDS, stream=stream) as s:

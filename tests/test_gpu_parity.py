@@ -44,10 +44,12 @@ def to_device(g, layout="soa32", offset=0):
     return k[offset:], None, 2
 
 
-def gpu_solve(lc, g, seed, layout="soa32", per_round=True, flags=0, max_rounds=0, offset=0):
+def gpu_solve(lc, g, seed, layout="soa32", per_round=True, flags=0, max_rounds=0, offset=0, tuning=None):
     s_t, d_t, lay = to_device(g, layout, offset)
     out = {"parents": [], "stats": []}
     with lc.Solver(g.n, s_t, d_t, seed=seed, flags=flags, max_rounds=max_rounds, layout=lay) as s:
+        if tuning:
+            s.set_tuning(**tuning)
         if per_round:
             while max_rounds == 0 or len(out["stats"]) < max_rounds:
                 st, stats = s.contract_round()
@@ -100,6 +102,17 @@ def check(lc, g, seed, **kw):
 def test_gnm_parity(lc, n, m, seed, mode):
     g = graphgen.Graph(n, *graphgen.gnm(seed * 7919, n, m))
     check(lc, g, seed, flags=MODES[mode])
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
+@pytest.mark.parametrize("n,m,seed", [(5000, 20001, 3), ((1 << 20) + 3, (1 << 22) + 1, 6)])
+def test_bucket_sort_parity(lc, n, m, seed, mode):
+    """Round 0's keys ordered by the sampled buckets (two levels of splitters, each final
+    bucket sorted in LDS) instead of the radix passes, round by round against the oracle; the
+    larger graph fills the 65,536 final buckets with ~60 keys each."""
+    g = graphgen.Graph(n, *graphgen.gnm(seed * 7919, n, m))
+    tuning = {"round0_sort": 2, "round0": 3 if mode == "rows" else 0}
+    check(lc, g, seed, flags=MODES["direct" if mode == "direct" else "tiled"], tuning=tuning)
 
 
 @pytest.mark.parametrize("n,m,seed", [((1 << 20) + 3, (1 << 22) + 1, 6), ((1 << 22) + 7777, 1 << 23, 7)])
@@ -287,14 +300,15 @@ def test_tuning_knobs_keep_results(lc):
 @pytest.mark.parametrize("r0", [2, 3])
 def test_kernel_knobs_keep_results(lc, r0):
     """The kernel builds and launch shapes the tuner may pick (radix scatter waves, record
-    pairs in flight in the tiled row passes, rows launched together) give the oracle's rounds,
-    statistics and labels, on a power-law graph of many rows and partition tiles."""
+    pairs in flight in the tiled row passes, rows launched together, round 0's sampled-bucket
+    sort) give the oracle's rounds, statistics and labels, on a power-law graph of many rows
+    and partition tiles."""
     g = graphgen.Graph(1 << 17, *graphgen.rmat(0x7078, 17, (12 << 17) + 1021))
     want = oracle.run(g.n, g.src, g.dst, seed=13)
     s_t, d_t, _ = to_device(g)
     with lc.Solver(g.n, s_t, d_t, seed=13, flags=MODES["tiled"]) as s:
         for knob, values in (("scatter_waves", (2, 3, 4)), ("row_pairs", (2, 4, 8)), ("relabel_pairs", (1, 2, 4)),
-                             ("row_generation", (1, 2, 8, -1))):
+                             ("row_generation", (1, 2, 8, -1)), ("round0_sort", (1, 2))):
             for v in values:
                 s.set_tuning(round0=r0, **{knob: v})
                 assert s.tuning[knob] == v and s.tuning["round0"] == r0
