@@ -59,7 +59,15 @@ def test_guard_gaps_are_in_place():
 
 @pytest.mark.slow
 def test_emulated_parity_suite_under_bounds_checking():
-    out = run(["-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", os.path.join(HERE, "test_emu_parity.py")], 1200)
+    """The whole emulated parity suite, in four worker processes (the first test of this file
+    has built the library, so the workers do not race to build it)."""
+    try:
+        import xdist  # noqa: F401
+        workers = ["-n", "4"]
+    except ImportError:
+        workers = []
+    out = run(["-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] + workers +
+              [os.path.join(HERE, "test_emu_parity.py")], 1200)
     assert " passed" in out and "failed" not in out
 
 
