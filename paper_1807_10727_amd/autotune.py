@@ -2,7 +2,9 @@
 
 The knobs of ``cc_batch_config`` (grid size of the streaming kernels, the LDS solver's
 size limits, workgroup size and persistence) and of ``cc_tuning`` (the form of round 0,
-workgroups per compute unit, round 0's key sets) change only speed: every candidate must
+workgroups per compute unit, round 0's key sets, the radix scatter build, the record pairs
+and launch generations of the tiled row passes, how round 0 sorts its keys) change only
+speed: every candidate must
 give bit-identical labels, and the tuner checks that.  Candidates are timed on the batch or
 the graph itself, coordinate by coordinate, and the winner is cached as JSON under a key made
 of the device (architecture, CU count) and the size class (log2 of the counts).
