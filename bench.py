@@ -269,10 +269,15 @@ def _pct(xs, q):
 
 
 def bench_serve(args):
-    """Poisson arrivals of requests with vertex counts log-uniform in [2^10, 2^24] (half
-    G(n,m) with average degree U[4,16], half R-MAT with edge factor 16), inputs resident in
-    HBM, served by the continuous-batching server under an HBM budget, against the same
-    trace served FIFO by sequential plain solves (their measured service times)."""
+    """Continuous batching under load.  A pool of graphs (vertex counts log-uniform in
+    [2^10, 2^24], half G(n,m) with average degree U[4,16], half R-MAT with edge factor 16) is
+    made resident in HBM; the trace is serve_warmup + serve_requests requests with Poisson
+    arrivals, each a pool graph drawn at random with a priority seed of its own, so that a
+    trace of thousands of requests needs only the pool's memory.  The server (HBM budget,
+    slots) replays it at several loads; the same trace served FIFO by sequential plain solves
+    (each request's measured service time) is the baseline.  Latency percentiles and graphs/s
+    cover the requests after the warm-up ones; every request's labels must equal its solo
+    solve."""
     import numpy as np
     import torch
 
@@ -281,42 +286,47 @@ def bench_serve(args):
 
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    trace = graphgen.request_trace(graphgen.CONFIG_SEED_BASE + 4, args.serve_requests, rate=1.0,
-                                   log2_min=10, log2_max=args.serve_log2_max)
-    reqs = []
-    for r in trace:
+    pool_spec = graphgen.request_trace(graphgen.CONFIG_SEED_BASE + 4, args.serve_pool, rate=1.0,
+                                       log2_min=10, log2_max=args.serve_log2_max)
+    pool = []
+    for r in pool_spec:
         g = r.graph()
-        reqs.append((r, g.n, torch.from_numpy(g.src.view(np.int32)).to(dev),
-                     torch.from_numpy(g.dst.view(np.int32)).to(dev)))
+        pool.append((g.n, torch.from_numpy(g.src.view(np.int32)).to(dev), torch.from_numpy(g.dst.view(np.int32)).to(dev)))
         del g
-    total_m = sum(int(x[2].shape[0]) for x in reqs)
+    total = args.serve_warmup + args.serve_requests
+    base_arr, which, seeds = graphgen.request_mix(graphgen.CONFIG_SEED_BASE + 5, total, len(pool))
+    reqs = [pool[k] + (seeds[i],) for i, k in enumerate(which)]
+    pool_m = sum(int(x[1].shape[0]) for x in pool)
+    total_m = sum(int(pool[k][1].shape[0]) for k in which)
     torch.cuda.synchronize()
-    log("serve: %d requests, %d records, generated and uploaded in %.1fs" % (len(reqs), total_m, time.perf_counter() - t0))
+    log("serve: pool of %d graphs (%d records) generated and uploaded in %.1fs; trace of %d + %d requests"
+        % (len(pool), pool_m, time.perf_counter() - t0, args.serve_warmup, args.serve_requests))
 
-    # sequential plain solves, back to back: service times and reference labels
+    # sequential plain solves in trace order, back to back: service times and reference labels
     ref = []
     service = []
-    for (r, n, s, d) in reqs[:min(4, len(reqs))]:          # warm the kernels
-        lc.solve(n, s, d, seed=r.seed)
-    for (r, n, s, d) in reqs:
+    for (n, s, d, sd) in reqs[:min(4, len(reqs))]:          # warm the kernels
+        lc.solve(n, s, d, seed=sd)
+    for (n, s, d, sd) in reqs:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        lab, _, _ = lc.solve(n, s, d, seed=r.seed)
+        lab, _, _ = lc.solve(n, s, d, seed=sd)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t1)
         ref.append(lab)
     cap = len(reqs) / sum(service)
     log("serve: sequential capacity %.1f requests/s (service p50 %.2f ms, max %.2f ms)"
         % (cap, 1e3 * _pct(service, 50), 1e3 * max(service)))
+    W = args.serve_warmup
 
     def fifo(arrivals):
-        fin, lat = 0.0, []
+        fin, lat, done = 0.0, [], []
         for a, sv in zip(arrivals, service):
             fin = max(fin, a) + sv
             lat.append(fin - a)
-        return lat, fin - arrivals[0]
+            done.append(fin)
+        return lat[W:], done[-1] - arrivals[W] if len(arrivals) > W else 0.0
 
-    base_arr = [r.arrival for (r, _, _, _) in reqs]
     loads = []
     identical = True
     srv = lc.Server(args.serve_budget_gib << 30, n_slots=args.serve_slots, small_variant=args.serve_small_variant,
@@ -328,36 +338,39 @@ def bench_serve(args):
             seq_lat, seq_span = fifo(arr)
             labs = {}
             t_start = srv.info()["now"]
-            for i, (r, n, s, d) in enumerate(reqs):
+            for i, (n, s, d, sd) in enumerate(reqs):
                 while srv.info()["now"] - t_start < arr[i] - arr[0]:
                     time.sleep(0.0002)
-                rid, lab = srv.submit(n, s, d, r.seed)
+                rid, lab = srv.submit(n, s, d, sd)
                 labs[rid] = (i, lab)
             res = srv.drain()
             if len(res) != len(reqs) or any(x["status"] != 0 for x in res):
                 raise RuntimeError("serving run lost or failed requests")
-            lat = [x["t_done"] - x["t_submit"] for x in res]
-            span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+            timed = [x for x in res if labs[x["id"]][0] >= W]
+            lat = [x["t_done"] - x["t_submit"] for x in timed]
+            span = max(x["t_done"] for x in timed) - min(x["t_submit"] for x in timed) if timed else 0.0
             for x in res:
                 i, lab = labs[x["id"]]
                 identical &= bool(torch.equal(lab, ref[i]))
+            del labs
             loads.append({"load": rho, "lambda_req_per_s": lam,
                           "p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99),
-                          "graphs_per_s": len(res) / span,
+                          "graphs_per_s": len(timed) / span if span > 0 else None,
                           "sequential_p50_ms": 1e3 * _pct(seq_lat, 50), "sequential_p99_ms": 1e3 * _pct(seq_lat, 99),
-                          "sequential_graphs_per_s": len(res) / seq_span,
-                          "small_path": sum(1 for x in res if x["small_path"])})
-            log("serve: load %.1f  p50 %.2f ms  p99 %.2f ms  %.1f graphs/s | sequential p50 %.2f ms  p99 %.2f ms  %.1f graphs/s"
+                          "sequential_graphs_per_s": len(seq_lat) / seq_span if seq_span > 0 else None,
+                          "small_path": sum(1 for x in timed if x["small_path"])})
+            log("serve: load %.1f  p50 %.2f ms  p99 %.2f ms  %s graphs/s | sequential p50 %.2f ms  p99 %.2f ms  %s graphs/s"
                 % (rho, loads[-1]["p50_ms"], loads[-1]["p99_ms"], loads[-1]["graphs_per_s"],
                    loads[-1]["sequential_p50_ms"], loads[-1]["sequential_p99_ms"], loads[-1]["sequential_graphs_per_s"]))
         peak = srv.info()["peak_bytes"]
     finally:
         srv.close()
-    del reqs, ref
+    del reqs, ref, pool
     torch.cuda.empty_cache()
     if not identical:
         raise RuntimeError("served labels differ from the solo solves")
-    return {"requests": len(base_arr), "records": total_m, "budget_gib": args.serve_budget_gib,
+    return {"requests": args.serve_requests, "warmup_requests": W, "pool_graphs": args.serve_pool,
+            "pool_records": pool_m, "trace_records": total_m, "budget_gib": args.serve_budget_gib,
             "slots": args.serve_slots, "sequential_capacity_req_per_s": cap, "loads": loads,
             "labels_identical_to_solo": identical, "peak_arena_gib": peak / 2**30}
 
@@ -461,7 +474,9 @@ def main():
     ap.add_argument("--verbose-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-only", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="timed requests of the serving trace")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="untimed requests before them")
+    ap.add_argument("--serve-pool", type=int, default=128, help="distinct graphs the trace draws from")
     ap.add_argument("--serve-log2-max", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-small-variant", type=int, default=3)

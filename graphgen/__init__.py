@@ -34,6 +34,7 @@ CONFIG_SEED_BASE = 0xC0FFEE00
 
 ST_BATCH = 10
 ST_TRACE = 11
+ST_MIX = 12
 
 
 def build(force: bool = True) -> str:
@@ -269,3 +270,17 @@ def request_trace(seed: int, count: int, rate: float, log2_min: int = 10, log2_m
             scale = max(1, int(math.ceil(math.log2(n))))
             out.append(Request(t, "rmat", 1 << scale, rmat_ef << scale, gseed))
     return out
+
+
+def request_mix(seed: int, count: int, pool: int, rate: float = 1.0):
+    """A long request trace over a pool of `pool` graphs: Poisson arrivals at `rate` per
+    second, each request a uniformly drawn pool graph with a priority seed of its own.
+    Returns (arrivals, pool indices, priority seeds) as lists."""
+    u = _unit(draws(seed, ST_MIX, 2 * count))
+    t, arr, idx, seeds = 0.0, [], [], []
+    for j in range(count):
+        t += -math.log(1.0 - float(u[2 * j])) / rate
+        arr.append(t)
+        idx.append(min(pool - 1, int(float(u[2 * j + 1]) * pool)))
+        seeds.append(sm64(seed ^ (j + 0x7A11)))
+    return arr, idx, seeds

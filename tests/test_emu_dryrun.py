@@ -31,7 +31,8 @@ def test_smoke_runs():
 def test_bench_json_contract():
     proc = run(["bench", "--workload", "small", "--steps", "2", "--warmup", "2", "--secondary", "",
                 "--variant-steps", "1", "--batch-graphs", "12", "--batch-log2-max", "9", "--batch-steps", "1",
-                "--serve-requests", "6", "--serve-log2-max", "12", "--serve-loads", "1.0", "--serve-budget-gib", "1"],
+                "--serve-requests", "6", "--serve-warmup", "2", "--serve-pool", "3", "--serve-log2-max", "12",
+                "--serve-loads", "1.0", "--serve-budget-gib", "1"],
                900)
     lines = [x for x in proc.stdout.splitlines() if x.strip()]
     assert len(lines) == 1
@@ -49,6 +50,7 @@ def test_bench_json_contract():
     assert set(d["variants"]) == {"tree", "one_hop", "uf_finish", "merge_to_large"}
     assert d["batched"]["labels_identical_to_sequential"]
     assert d["serving"]["labels_identical_to_solo"]
+    assert d["serving"]["requests"] == 6 and d["serving"]["warmup_requests"] == 2 and d["serving"]["pool_graphs"] == 3
     # more than one GPU is refused with a message
     proc = subprocess.run([sys.executable, DRY, "bench", "--gpus", "2"], cwd=ROOT, stdout=subprocess.PIPE,
                           stderr=subprocess.PIPE, text=True, timeout=120)
