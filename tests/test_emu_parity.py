@@ -250,11 +250,14 @@ def test_emulated_recorded_parents(cc, mode, rule):
         assert e.value.status == cc.CC_E_STATE
 
 
-@pytest.mark.parametrize("mode", ["direct", "tiled"])
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 def test_emulated_round_minima(cc, mode):
     g = graphgen.er_with_paths(0xA11, 6000, 15000, 10, 200)
     want = oracle.run(g.n, g.src, g.dst, seed=4, record_minima=True, minima_cap=64)
-    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=4, flags={"direct": DIRECT, "tiled": TILED}[mode]) as s:
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=4, flags={"direct": DIRECT, "tiled": TILED,
+                                                                    "rows": TILED}[mode]) as s:
+        if mode == "rows":
+            s.set_tuning(round0=3, round0_sort=2)
         r = 0
         while s.contract_round()[0] != cc.CC_DONE:
             m1, l2 = s.minima()
