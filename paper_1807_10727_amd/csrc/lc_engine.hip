@@ -1170,7 +1170,13 @@ cc_status cc_load_state(cc_ctx *c, const void *h_buf, size_t bytes) {
     RoundState st;
     memcpy(&st, p, z.state);
     p += z.state;
-    if ((int64_t)st.m_cur != m_cur && h.next_round > 0) return reject(c, CC_E_ARG, "inconsistent checkpoint");
+    // The device state must agree with the header and keep later rounds inside the workspace:
+    // they index the edge buffers, the names and the map arena with these fields.
+    bool consistent = st.e_sel == h.e_sel && (int64_t)st.map_off == h.map_used && st.levels >= 0 &&
+                      st.levels <= kMaxLevels && (int64_t)st.map_cap == std::max<int64_t>(n0, 1);
+    if (h.next_round > 0) consistent = consistent && (int64_t)st.m_cur == m_cur && (int64_t)st.n_cur == n_cur;
+    for (int l = 0; consistent && l < st.levels; ++l) consistent = (int64_t)st.level_off[l] <= h.map_used;
+    if (!consistent) return reject(c, CC_E_ARG, "inconsistent checkpoint");
     // every copy below is ordered before the next round on the stream; the host buffer is
     // read before this call returns (synchronised)
     struct Piece {

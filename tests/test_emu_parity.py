@@ -337,6 +337,21 @@ def test_emulated_checkpoint_rejects_another_graph(cc):
         with pytest.raises(cc.CCError) as e:
             c.load_state(blob)
         assert e.value.status == cc.CC_E_ARG
+    # a device state that disagrees with the header, or would index past the map arena, is
+    # refused before anything reaches the device (header: 120 bytes, n_stats at byte 60, n_cur
+    # at byte 72; state fields n_cur at byte 0, map_off at byte 32, e_sel at byte 64)
+    n_stats = int(np.frombuffer(blob, np.int32, 1, 60)[0])
+    st0 = 120 + n_stats * ctypes.sizeof(cc.cc_round_stats)
+    assert n_stats == 1
+    assert int(np.frombuffer(blob, np.uint64, 1, st0)[0]) == int(np.frombuffer(blob, np.int64, 1, 72)[0]) > 0
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=2) as d:
+        d.load_state(blob)                       # the blob as written loads
+        for at, value in ((st0 + 32, 1 << 40), (st0 + 64, 7)):
+            bad = bytearray(blob)
+            bad[at:at + 8] = int(value).to_bytes(8, "little")
+            with pytest.raises(cc.CCError) as e:
+                d.load_state(bytes(bad))
+            assert e.value.status == cc.CC_E_ARG
 
 
 # ---- batch and serving -----------------------------------------------------------------------
