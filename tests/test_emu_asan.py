@@ -68,7 +68,7 @@ def test_emulated_parity_suite_under_bounds_checking():
         workers = []
     out = run(["-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] + workers +
               [os.path.join(HERE, "test_emu_parity.py")], 1200)
-    assert " passed" in out and "failed" not in out
+    assert " passed" in out and "failed" not in out and "skipped" not in out
 
 
 def test_smoke_under_bounds_checking():
