@@ -520,13 +520,17 @@ sys.path[:0] = [%r, %r]
 import numpy as np, graphgen, oracle, hipemu
 cc = hipemu.binding()
 fails = []
-cases = [("rmat", graphgen.Graph(1 << 14, *graphgen.rmat(3, 14, 16 << 14)), cc.CC_ROUND0_TILED, 0),
-         ("paths", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0),
-         ("mtl", graphgen.er_with_paths(10, 3000, 9000, 20, 100), cc.CC_ROUND0_TILED, cc.CC_MERGE_TO_LARGE)]
-for name, g, flags, extra in cases:
+rmat = graphgen.Graph(1 << 14, *graphgen.rmat(3, 14, 16 << 14))
+cases = [("rmat", rmat, cc.CC_ROUND0_TILED, 0, {}),
+         ("rmat rows buckets", rmat, cc.CC_ROUND0_TILED, 0, {"round0": 3, "round0_sort": 2}),
+         ("paths", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0, {}),
+         ("mtl", graphgen.er_with_paths(10, 3000, 9000, 20, 100), cc.CC_ROUND0_TILED, cc.CC_MERGE_TO_LARGE, {})]
+for name, g, flags, extra, knobs in cases:
     want = oracle.run(g.n, g.src, g.dst, seed=5, variant="merge_to_large" if extra else "local", alphas=[3] if extra else None)
     with hipemu.Solver(g.n, hipemu.device(g.src, np.int32), hipemu.device(g.dst, np.int32), seed=5,
                        flags=flags | extra) as s:
+        if knobs:
+            s.set_tuning(**knobs)
         if extra:
             s.set_merge_to_large([3])
         r = s.run()
