@@ -268,7 +268,7 @@ cc_status plan(cc_batch *b) {
 }
 
 // Everything before the union rounds: state reset, union input, per-graph round marks.
-bool enqueue_prologue(cc_batch *b, int32_t *labels) {
+bool enqueue_prologue(cc_batch *b) {
     hipStream_t s = b->stream;
     const int64_t n0 = b->w.n0;
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(kThreads), 0, s, b->w.st, n0, b->union_m, std::max<int64_t>(n0, 1));
@@ -346,7 +346,7 @@ cc_status capture(cc_batch *b, int32_t *labels) {
     b->stream = b->cap_stream;
     bool ok = batch_hip(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
     const int rounds = std::max(1, b->cfg.rounds_per_graph);
-    if (ok) ok = enqueue_prologue(b, labels);
+    if (ok) ok = enqueue_prologue(b);
     if (ok && b->union_m > 0) {
         for (int r = 0; ok && r < rounds; ++r) ok = enqueue_union_round(b, r);
     }
@@ -555,7 +555,7 @@ cc_status cc_batch_run(cc_batch *b, int32_t *d_labels, int32_t *h_rounds) {
             if (!b->read_state()) return CC_E_HIP;
         }
     } else {
-        if (!enqueue_prologue(b, d_labels)) return CC_E_HIP;
+        if (!enqueue_prologue(b)) return CC_E_HIP;
         if (!b->read_state()) return CC_E_HIP;
         int r = 0;
         while (b->union_m > 0 && !b->h_st->done) {

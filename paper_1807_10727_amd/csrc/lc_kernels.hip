@@ -264,8 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const u
 }
 
 // Workgroup-local set of sort keys already written (sorted records, i.e. rounds >= 1).
-constexpr int kDedupLog2 = LC_DEDUP_LOG2;
-constexpr int kDedupSlots = 1 << kDedupLog2;
+constexpr int kDedupLog2 = LC_DEDUP_LOG2;   // slots: 1 << kDedupLog2
 constexpr int kDedupProbes = 8;
 constexpr unsigned long long kNoKey = ~0ull;   // no sort key has all 64 bits set (lo < hi)
 
