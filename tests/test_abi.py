@@ -212,3 +212,55 @@ def test_inspection_and_checkpoint_entry_points_validate_without_a_gpu():
         _cc.cc_debug_round_arrays(ctx, 0x3000, 0x4000)
     assert e.value.status == _cc.CC_E_STATE
     _cc.cc_destroy(ctx)
+
+
+STRUCTS = ("cc_tuning", "cc_round_stats", "cc_batch_config", "cc_server_config", "cc_request_result",
+           "cc_server_info_t", "cc_graph_desc", "cc_options")
+
+
+def header_struct_fields(name):
+    """Field names of a `typedef struct {...} name;` in include/cc.h, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", text, flags=re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        # "const void *src, *dst" -> src, dst; "int32_t round0" -> round0
+        first, *rest = decl.split(",")
+        out.append(re.findall(r"([A-Za-z_][A-Za-z0-9_]*)\s*$", first)[0])
+        out += [re.sub(r"[\s*]", "", r) for r in rest]
+    return out
+
+
+def test_marshalled_structs_match_the_header():
+    """The ctypes mirrors of the structs the boundary passes by pointer have the header's
+    fields in the header's order, and (compiled with the host C compiler) the same size and
+    field offsets."""
+    from paper_1807_10727_amd import _cc
+    for name in STRUCTS:
+        mirror = getattr(_cc, name)
+        assert [f[0] for f in mirror._fields_] == header_struct_fields(name), name
+    import shutil
+    import tempfile
+    if not shutil.which("gcc"):
+        pytest.skip("no host C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", "#include \"cc.h\"", "int main(void) {"]
+    for name in STRUCTS:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f in header_struct_fields(name):
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines += ["return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        with open(src, "w") as f:
+            f.write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.dirname(HEADER), src, "-o", exe], check=True)
+        got = dict(l.split() for l in subprocess.run([exe], stdout=subprocess.PIPE, text=True, check=True)
+                   .stdout.splitlines())
+    for name in STRUCTS:
+        mirror = getattr(_cc, name)
+        assert int(got[name]) == ctypes.sizeof(mirror), name
+        for f in header_struct_fields(name):
+            assert int(got["%s.%s" % (name, f)]) == getattr(mirror, f).offset, (name, f)
