@@ -599,12 +599,19 @@ def main():
         collect(warm_ms, warm_n)
     torch.cuda.synchronize()
     dom_step, dom_fams = None, None
+    step_rooflines = None
     if not args.no_profile and warm_ms:
         per_step = steps_of(warm_ms, None)
+        step_rooflines = {}
         log("warm-up: step            ms/solve   GB/s (algorithmic)")
         for k in sorted(per_step, key=lambda x: -per_step[x]):
             gbs = warm_bytes.get(k, 0) / (per_step[k] * 1e-3) / 1e9 if per_step[k] > 0 else 0.0
             log("  %-18s %8.3f %10.1f" % (k, per_step[k] / n_warm, gbs))
+            # every step of the hot path, timed with events around all of its kernels
+            step_rooflines[k] = {"ms_per_solve": round(per_step[k] / n_warm, 4),
+                                 "bytes_per_solve": int(warm_bytes[k] / n_warm) if k in warm_bytes else None,
+                                 "achieved_gbs": round(gbs, 1) if k in warm_bytes else None,
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4) if k in warm_bytes else None}
         log("warm-up: kernel family       ms/solve  launches/solve")
         for k in sorted(warm_ms, key=lambda x: -warm_ms[x]):
             if warm_n[k]:
@@ -721,6 +728,7 @@ def main():
         "config": {"workload": wname, "n_vertices": n0, "n_records": m0, "rounds": rounds[0],
                    "round0": args.round0, "tuning": tuning, "parallelism": "single GPU"},
         "roofline": roofline,
+        "step_rooflines": step_rooflines,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),
         "job_alg_frac_of_copy": round(job_gbs / copy_gbs, 4),
         "cpu_baseline": cpu,

@@ -44,6 +44,9 @@ def test_bench_json_contract():
     r = d["roofline"]
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
     assert r["kernel"].startswith("a") and r["frac"] == round(r["achieved"] / 8000.0, 4)
+    sr = d["step_rooflines"]
+    assert r["kernel"] in sr and {"a2_one_hop", "a4_relabel", "a5_dedup"} <= set(sr)
+    assert all(v["ms_per_solve"] >= 0 for v in sr.values())
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] == 1 and "of" in c["host"] and "union_find" in c
     assert all(v["canonical_labels_identical"] for v in d["variants"].values())
