@@ -1,0 +1,75 @@
+"""Randomised parity of the emulated device code with the oracle (CPU only).
+
+Hypothesis draws the graph (size, density, a power-law or uniform mix, repeated records,
+loops, isolated ids), the seed, the input layout, the label rule and the solver's knobs (round-0
+form, key sets, the order of round 0's keys, kernel builds, grid size); every draw must give
+the oracle's round count, statistics and labels.  The draws are derandomised, so a failure
+is reproducible, and sized so that the whole test takes about a minute.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+hypothesis = pytest.importorskip("hypothesis")
+hipemu = pytest.importorskip("hipemu")
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+from test_emu_parity import DIRECT, RULES, TILED, inputs  # noqa: E402
+
+
+@st.composite
+def graphs(draw):
+    n = draw(st.integers(1, 3000))
+    m = draw(st.integers(0, 4 * n + 50))
+    seed = draw(st.integers(0, 2 ** 32 - 1))
+    kind = draw(st.sampled_from(["gnm", "rmat", "paths"]))
+    if m == 0:
+        src = dst = np.zeros(0, np.uint32)
+    elif kind == "gnm":
+        src, dst = graphgen.gnm(seed, n, m)
+    elif kind == "rmat":
+        scale = max(1, int(np.ceil(np.log2(n))))
+        src, dst = graphgen.rmat(seed, scale, m)
+        src, dst = src % np.uint32(n), dst % np.uint32(n)
+    else:
+        g = graphgen.er_with_paths(seed, n, m // 2, max(1, n // 50), min(50, n))
+        return g
+    # repeats and loops on top
+    extra = draw(st.integers(0, 20))
+    if extra and src.size:
+        pick = np.arange(extra) % src.size
+        src = np.concatenate([src, src[pick], dst[pick[:extra // 2]]]).astype(np.uint32)
+        dst = np.concatenate([dst, dst[pick], dst[pick[:extra // 2]]]).astype(np.uint32)
+    return graphgen.Graph(n, src, dst)
+
+
+KNOBS = st.fixed_dictionaries({
+    "round0": st.sampled_from([1, 2, 3]),
+    "round0_key_sets": st.sampled_from([0, 1]),
+    "round0_sort": st.sampled_from([1, 2]),
+    "scatter_waves": st.sampled_from([2, 3, 4]),
+    "row_pairs": st.sampled_from([2, 4, 8]),
+    "relabel_pairs": st.sampled_from([1, 2, 4]),
+    "row_generation": st.sampled_from([-1, 1, 2]),
+    "blocks_per_cu": st.sampled_from([1, 8]),
+})
+
+
+@settings(max_examples=150, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(g=graphs(), seed=st.integers(0, 2 ** 64 - 1), layout=st.sampled_from(["soa32", "soa64", "packed"]),
+       rule=st.sampled_from(["local", "local", "tree", "one_hop"]), knobs=KNOBS)
+def test_random_solves_match_the_oracle(g, seed, layout, rule, knobs):
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
+    s_, d_ = inputs(g, layout)
+    # every knob setting needs the tiled workspace; the context sizes for it with CC_ROUND0_TILED
+    flags = (TILED if g.n > 0 else DIRECT) | RULES[rule]
+    with hipemu.Solver(g.n, s_, d_, seed=seed, flags=flags) as s:
+        if g.n > 0:
+            s.set_tuning(**knobs)
+        r = s.run()
+        assert r == want.rounds
+        assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
