@@ -1,7 +1,8 @@
 """Randomised parity of the emulated device code with the oracle (CPU only).
 
 Hypothesis draws the graph (size, density, a power-law or uniform mix, repeated records,
-loops, isolated ids), the seed, the input layout, the label rule and the solver's knobs (round-0
+loops, isolated ids), the seed, the input layout, the label rule (with MergeToLarge's
+parameters) and the solver's knobs (round-0
 form, key sets, the order of round 0's keys, kernel builds, grid size); every draw must give
 the oracle's round count, statistics and labels.  The draws are derandomised, so a failure
 is reproducible, and sized so that the whole test takes about a minute.
@@ -17,6 +18,8 @@ hipemu = pytest.importorskip("hipemu")
 from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
 
 from test_emu_parity import DIRECT, RULES, TILED, inputs  # noqa: E402
+
+MTL = 1 << 9   # CC_MERGE_TO_LARGE (include/cc.h)
 
 
 @st.composite
@@ -60,15 +63,19 @@ KNOBS = st.fixed_dictionaries({
 @settings(max_examples=150, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(g=graphs(), seed=st.integers(0, 2 ** 64 - 1), layout=st.sampled_from(["soa32", "soa64", "packed"]),
-       rule=st.sampled_from(["local", "local", "tree", "one_hop"]), knobs=KNOBS)
-def test_random_solves_match_the_oracle(g, seed, layout, rule, knobs):
-    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
+       rule=st.sampled_from(["local", "local", "tree", "one_hop", "merge_to_large"]), knobs=KNOBS,
+       alphas=st.lists(st.integers(1, 6), min_size=1, max_size=3))
+def test_random_solves_match_the_oracle(g, seed, layout, rule, knobs, alphas):
+    mtl = rule == "merge_to_large"
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule, alphas=alphas if mtl else None)
     s_, d_ = inputs(g, layout)
     # every knob setting needs the tiled workspace; the context sizes for it with CC_ROUND0_TILED
-    flags = (TILED if g.n > 0 else DIRECT) | RULES[rule]
+    flags = (TILED if g.n > 0 else DIRECT) | (MTL if mtl else RULES[rule])
     with hipemu.Solver(g.n, s_, d_, seed=seed, flags=flags) as s:
         if g.n > 0:
             s.set_tuning(**knobs)
+        if mtl:
+            s.set_merge_to_large(alphas)
         r = s.run()
         assert r == want.rounds
         assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
