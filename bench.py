@@ -330,7 +330,8 @@ def bench_serve(args):
     loads = []
     identical = True
     srv = lc.Server(args.serve_budget_gib << 30, n_slots=args.serve_slots, small_variant=args.serve_small_variant,
-                    max_small_per_launch=256)
+                    max_small_per_launch=256, cohort_max=args.serve_cohort_max,
+                    cohort_max_vertices=1 << args.serve_cohort_log2_vertices)
     try:
         for rho in args.serve_loads:
             lam = rho * cap
@@ -358,7 +359,8 @@ def bench_serve(args):
                           "graphs_per_s": len(timed) / span if span > 0 else None,
                           "sequential_p50_ms": 1e3 * _pct(seq_lat, 50), "sequential_p99_ms": 1e3 * _pct(seq_lat, 99),
                           "sequential_graphs_per_s": len(seq_lat) / seq_span if seq_span > 0 else None,
-                          "small_path": sum(1 for x in timed if x["small_path"])})
+                          "small_path": sum(1 for x in timed if x["small_path"]),
+                          "in_cohorts": sum(1 for x in timed if x["cohort"] > 1)})
             log("serve: load %.1f  p50 %.2f ms  p99 %.2f ms  %s graphs/s | sequential p50 %.2f ms  p99 %.2f ms  %s graphs/s"
                 % (rho, loads[-1]["p50_ms"], loads[-1]["p99_ms"], loads[-1]["graphs_per_s"],
                    loads[-1]["sequential_p50_ms"], loads[-1]["sequential_p99_ms"], loads[-1]["sequential_graphs_per_s"]))
@@ -370,6 +372,7 @@ def bench_serve(args):
     if not identical:
         raise RuntimeError("served labels differ from the solo solves")
     return {"requests": args.serve_requests, "warmup_requests": W, "pool_graphs": args.serve_pool,
+            "cohort_max": args.serve_cohort_max, "cohort_max_vertices": 1 << args.serve_cohort_log2_vertices,
             "pool_records": pool_m, "trace_records": total_m, "budget_gib": args.serve_budget_gib,
             "slots": args.serve_slots, "sequential_capacity_req_per_s": cap, "loads": loads,
             "labels_identical_to_solo": identical, "peak_arena_gib": peak / 2**30}
@@ -477,6 +480,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="timed requests of the serving trace")
     ap.add_argument("--serve-warmup", type=int, default=200, help="untimed requests before them")
     ap.add_argument("--serve-pool", type=int, default=128, help="distinct graphs the trace draws from")
+    ap.add_argument("--serve-cohort-max", type=int, default=16,
+                    help="large requests the server may start together as one union (0: none)")
+    ap.add_argument("--serve-cohort-log2-vertices", type=int, default=20,
+                    help="largest request (log2 vertices) that may join a cohort")
     ap.add_argument("--serve-log2-max", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-small-variant", type=int, default=3)

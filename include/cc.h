@@ -406,8 +406,13 @@ const char *cc_batch_last_error(const cc_batch *batch);
  * slots and memory free up, and their work overlaps on the device.  Waiting small
  * requests (CC_EDGES_SOA_I32 within the LDS limits of small_variant) are fused into one
  * launch of the LDS solver; every other request gets a slot stream and a workspace from
- * the arena and advances one round (Section 3, one phase) per scheduler step.  A request's
- * labels equal its solo solve with the same seed, whatever else is in flight.
+ * the arena and advances one round (Section 3, one phase) per scheduler step.  With
+ * cohort_max > 1, waiting large requests of at most cohort_max_vertices vertices (int32 SoA)
+ * share a slot as one cohort: their graphs form one disjoint union, and each scheduler step
+ * runs one round of all of them as one launch sequence (each graph keeps its own priorities
+ * and round count, so its labels are its solo solve's); a request of a cohort whose records
+ * name a vertex out of range fails alone (CC_E_INPUT).
+ * A request's labels equal its solo solve with the same seed, whatever else is in flight.
  *
  * The arena is caller-owned device memory of budget_bytes (256-byte aligned); request
  * workspaces are carved from it and returned when the request completes, so the budget
@@ -425,6 +430,11 @@ typedef struct {
     int32_t small_blocks_per_cu;   /* 1..16 */
     int32_t max_small_per_launch;  /* small requests fused into one launch (1..65536) */
     int32_t small_launches;        /* small launches in flight at once (1..8) */
+    int32_t cohort_max;            /* up to this many waiting large requests (int32 SoA, at most
+                                      cohort_max_vertices vertices each) start together as one
+                                      cohort: one disjoint union whose every round is one launch
+                                      sequence for all of them (0 or 1: none; at most 64) */
+    int32_t cohort_max_vertices;   /* 0: 2^20 */
 } cc_server_config;
 
 typedef struct {
@@ -432,7 +442,7 @@ typedef struct {
     cc_status status;      /* CC_OK; CC_E_INPUT for an id out of range; CC_E_STATE if cancelled */
     int32_t rounds;
     int32_t small_path;    /* 1 if solved by the fused LDS launch */
-    int32_t reserved;
+    int32_t cohort;        /* requests of the cohort it was solved in (0: solved on its own) */
     double t_submit;       /* seconds on the server clock (cc_server_info().now) */
     double t_admit;
     double t_done;         /* labels written */
@@ -458,6 +468,9 @@ cc_status cc_server_poll(cc_server *server, cc_request_result *out, int32_t cap,
 cc_status cc_server_wait(cc_server *server, cc_request_result *out, int32_t cap, int32_t *n, double timeout_s);
 /* Cancel a request that has not completed (it completes with CC_E_STATE). */
 cc_status cc_server_cancel(cc_server *server, uint64_t req_id);
+/* paused != 0: admit no new request until called again with 0 (requests in flight continue,
+ * submissions wait), for instance to release a burst of requests together. */
+cc_status cc_server_pause(cc_server *server, int32_t paused);
 cc_status cc_server_info(cc_server *server, cc_server_info_t *info);
 /* Finishes every admitted request, cancels the waiting ones, stops the scheduler. */
 cc_status cc_server_destroy(cc_server *server);

@@ -14,7 +14,7 @@ from __future__ import annotations
 from . import _cc
 from ._cc import (cc_batch_create, cc_batch_destroy, cc_batch_get_config, cc_batch_run, cc_batch_set_config,
                   cc_batch_set_workspace, cc_batch_split, cc_batch_workspace_size)
-from ._cc import (cc_server_cancel, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
+from ._cc import (cc_server_cancel, cc_server_pause, cc_server_create, cc_server_destroy, cc_server_info, cc_server_poll,
                   cc_server_submit, cc_server_wait)
 from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, CC_EDGES_SOA_I64, CC_OK,
                   CC_EAGER, CC_EXPLICIT_PRIO, CC_MERGE_TO_LARGE, CC_ONE_HOP, CC_PROFILE, CC_RECORD_ROUNDS,
@@ -313,6 +313,10 @@ class Server:
         while self._held and time.time() < t_end:
             out += self.wait(0.5)
         return out
+
+    def pause(self, paused: bool = True) -> None:
+        """Admit no new request while paused (requests in flight continue)."""
+        cc_server_pause(self.srv, paused)
 
     def cancel(self, rid: int):
         cc_server_cancel(self.srv, rid)

@@ -77,12 +77,13 @@ class cc_batch_config(ctypes.Structure):
 class cc_server_config(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("small_variant", ctypes.c_int32), ("small_threads", ctypes.c_int32),
                 ("small_blocks_per_cu", ctypes.c_int32), ("max_small_per_launch", ctypes.c_int32),
-                ("small_launches", ctypes.c_int32)]
+                ("small_launches", ctypes.c_int32), ("cohort_max", ctypes.c_int32),
+                ("cohort_max_vertices", ctypes.c_int32)]
 
 
 class cc_request_result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("small_path", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("small_path", ctypes.c_int32), ("cohort", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
     def as_dict(self):
@@ -146,6 +147,7 @@ _sig = {
                                         ctypes.POINTER(ctypes.c_int32)]),
     "cc_server_wait": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_request_result), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_double]),
+    "cc_server_pause": (ctypes.c_int32, [_ctx_p, ctypes.c_int32]),
     "cc_server_cancel": (ctypes.c_int32, [_ctx_p, ctypes.c_uint64]),
     "cc_server_info": (ctypes.c_int32, [_ctx_p, ctypes.POINTER(cc_server_info_t)]),
     "cc_server_destroy": (ctypes.c_int32, [_ctx_p]),
@@ -414,9 +416,10 @@ def _scheck(srv, status: int) -> int:
 
 
 def cc_server_create(arena_ptr: int, budget: int, n_slots: int = 4, small_variant: int = 1, small_threads: int = 256,
-                     small_blocks_per_cu: int = 2, max_small_per_launch: int = 1024, small_launches: int = 2):
+                     small_blocks_per_cu: int = 2, max_small_per_launch: int = 1024, small_launches: int = 2,
+                     cohort_max: int = 0, cohort_max_vertices: int = 0):
     c = cc_server_config(n_slots, small_variant, small_threads, small_blocks_per_cu, max_small_per_launch,
-                         small_launches)
+                         small_launches, cohort_max, cohort_max_vertices)
     srv = _ctx_p()
     _scheck(None, _lib.cc_server_create(arena_ptr, budget, ctypes.byref(c), ctypes.byref(srv)))
     return srv
@@ -447,6 +450,10 @@ def cc_server_wait(srv, timeout_s: float = 1.0, cap: int = 256):
 
 def cc_server_cancel(srv, rid: int) -> None:
     _scheck(srv, _lib.cc_server_cancel(srv, rid))
+
+
+def cc_server_pause(srv, paused: bool) -> None:
+    _scheck(srv, _lib.cc_server_pause(srv, 1 if paused else 0))
 
 
 def cc_server_info(srv) -> dict:

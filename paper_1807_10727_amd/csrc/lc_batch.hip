@@ -33,10 +33,14 @@ namespace lc {
 
 // Union records of the large graphs as packed global ids; graph big[j] owns union records
 // [ubase[j], ubase[j+1]).  Out-of-range local ids become loops and set the error bit.
-__global__ __launch_bounds__(kThreads) void k_globalize(const int32_t *src, const int32_t *dst, const int64_t *voff,
-                                                        const int64_t *eoff, const int32_t *big,
+// srcp/dstp non-null (cohorts of the serving scheduler): graph g's records are srcp[g][i],
+// dstp[g][i] instead of src/dst at eoff[g] + i.
+// bad_g[g] (all graphs) is set for a graph with a record out of range.
+__global__ __launch_bounds__(kThreads) void k_globalize(const int32_t *src, const int32_t *dst,
+                                                        const int32_t *const *srcp, const int32_t *const *dstp,
+                                                        const int64_t *voff, const int64_t *eoff, const int32_t *big,
                                                         const int64_t *ubase, int32_t nbig, uint64_t *out,
-                                                        uint32_t *err) {
+                                                        uint32_t *err, int32_t *bad_g) {
     constexpr int64_t kChunk = 16384;
     const int64_t total = nbig ? ubase[nbig] : 0;
     const int64_t nchunks = ceil_div(total, kChunk);
@@ -60,13 +64,15 @@ __global__ __launch_bounds__(kThreads) void k_globalize(const int32_t *src, cons
             const int32_t g = big[j];
             const int64_t base = voff[g];
             const int64_t n = voff[g + 1] - base;
-            const int64_t i = eoff[g] + (u - ubase[j]);
-            const int32_t x = src[i], y = dst[i];
+            const int64_t li = u - ubase[j];
+            const int32_t x = srcp ? srcp[g][li] : src[eoff[g] + li];
+            const int32_t y = srcp ? dstp[g][li] : dst[eoff[g] + li];
             uint64_t rec;
             if ((uint32_t)x < (uint64_t)n && (uint32_t)y < (uint64_t)n) {
                 rec = ((uint64_t)(base + x) << 32) | (uint64_t)(base + y);
             } else {
                 bad = true;
+                bad_g[g] = 1;
                 rec = 0ull;   // a loop: skipped by every kernel
             }
             out[u] = rec;
@@ -97,9 +103,17 @@ __global__ __launch_bounds__(kThreads) void k_fill_i32(int32_t *p, int32_t v, in
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) p[i] = v;
 }
 
-// labels of the union part (graphs not flagged `skip`), as local ids
+// a graph with a record out of range reports -1 rounds (cohorts: its request alone fails)
+__global__ __launch_bounds__(kThreads) void k_mark_bad(int32_t *rounds, const int32_t *bad_g, int32_t G) {
+    for (int32_t g = blockIdx.x * kThreads + threadIdx.x; g < G; g += gridDim.x * kThreads)
+        if (bad_g[g]) rounds[g] = -1;
+}
+
+// labels of the union part (graphs not flagged `skip`), as local ids: at labels[v], or at
+// labp[g][v - voff[g]] when labp is non-null (cohorts of the serving scheduler)
 __global__ __launch_bounds__(kThreads) void k_compose_batch(Work w, const uint32_t *names_cur, int32_t *labels,
-                                                            const uint32_t *voff, const uint8_t *skip) {
+                                                            int32_t *const *labp, const uint32_t *voff,
+                                                            const uint8_t *skip) {
     const RoundState *st = w.st;
     const int levels = st->levels;
     for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < w.n0; v += (int64_t)gridDim.x * kThreads) {
@@ -108,7 +122,10 @@ __global__ __launch_bounds__(kThreads) void k_compose_batch(Work w, const uint32
         uint32_t x = w.map0[v];
         for (int l = 0; l < levels && !(x & kFinal); ++l) x = w.maps[st->level_off[l] + x];
         const uint32_t name = (x & kFinal) ? (x & ~kFinal) : (names_cur ? names_cur[x] : x);
-        labels[v] = (int32_t)(name - voff[g]);
+        if (labp)
+            labp[g][v - voff[g]] = (int32_t)(name - voff[g]);
+        else
+            labels[v] = (int32_t)(name - voff[g]);
     }
 }
 
@@ -171,7 +188,7 @@ struct cc_batch : public lc::Engine {
     int64_t *d_voff64 = nullptr, *d_eoff64 = nullptr, *d_ubase = nullptr;
     uint32_t *d_voff32 = nullptr, *d_queue = nullptr;
     uint64_t *d_seeds_w = nullptr;
-    int32_t *d_big = nullptr, *d_rounds = nullptr;
+    int32_t *d_big = nullptr, *d_rounds = nullptr, *d_bad = nullptr;
     SmallDesc *d_desc = nullptr;
     std::vector<SmallDesc> h_desc;
     int32_t *desc_labels = nullptr;   // labels pointer the uploaded descriptors point into
@@ -189,14 +206,23 @@ struct cc_batch : public lc::Engine {
     int captured_rounds = 0;
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     std::vector<int32_t> last_rounds;
+    // a cohort of the serving scheduler: every graph's records and labels at pointers of its
+    // own (int32 local ids), rounds driven one at a time by the scheduler (cohort_begin /
+    // cohort_advance)
+    bool ptr_mode = false;
+    std::vector<const int32_t *> h_srcp, h_dstp;
+    std::vector<int32_t *> h_labp;
+    const int32_t **d_srcp = nullptr, **d_dstp = nullptr;
+    int32_t **d_labp = nullptr;
+    int async_round = 0, async_phase = 0;
 };
 
 namespace {
 
 size_t batch_extra_bytes(int32_t G) {
     const size_t g = (size_t)G + 1;
-    return (256 + LC_WS_GUARD) * 12 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 2 +
-           sizeof(SmallDesc) * g + g + 64;
+    return (256 + LC_WS_GUARD) * 16 + 8 * g * 3 + 4 * g + 8 * g + sizeof(RoundKey) * g + 4 * g * 2 +
+           sizeof(SmallDesc) * g + g + 64 + 3 * 8 * g + 4 * g;
 }
 
 char *carve(char *&p, size_t bytes) {
@@ -275,11 +301,16 @@ bool enqueue_prologue(cc_batch *b) {
     if (!batch_hip(b, hipGetLastError(), "state init")) return false;
     hipLaunchKernelGGL(k_fill_i32, dim3(b->grid_for(b->G)), dim3(kThreads), 0, s, b->d_rounds, 0, (int64_t)b->G);
     if (!batch_hip(b, hipGetLastError(), "round counters")) return false;
+    hipLaunchKernelGGL(k_fill_i32, dim3(b->grid_for(b->G)), dim3(kThreads), 0, s, b->d_bad, 0, (int64_t)b->G);
+    if (!batch_hip(b, hipGetLastError(), "input flags")) return false;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kThreads), 0, s, (int32_t *)b->d_queue, 0, (int64_t)1);
     if (!batch_hip(b, hipGetLastError(), "queue reset")) return false;
     const int gch = (int)std::min<int64_t>(ceil_div(std::max<int64_t>(b->union_m, 1), 16384), b->grid_cap);
-    hipLaunchKernelGGL(k_globalize, dim3(gch), dim3(kThreads), 0, s, b->d_src, b->d_dst, b->d_voff64, b->d_eoff64,
-                       b->d_big, b->d_ubase, (int32_t)b->big_list.size(), b->w.keys[1], &b->w.st->err);
+    const int32_t *const *srcp = b->ptr_mode ? b->d_srcp : nullptr;
+    const int32_t *const *dstp = b->ptr_mode ? b->d_dstp : nullptr;
+    hipLaunchKernelGGL(k_globalize, dim3(gch), dim3(kThreads), 0, s, b->d_src, b->d_dst, srcp, dstp, b->d_voff64,
+                       b->d_eoff64, b->d_big, b->d_ubase, (int32_t)b->big_list.size(), b->w.keys[1], &b->w.st->err,
+                       b->d_bad);
     return batch_hip(b, hipGetLastError(), "union input");
 }
 
@@ -287,8 +318,9 @@ bool enqueue_epilogue(cc_batch *b, int32_t *labels, int cur_round) {
     hipStream_t s = b->stream;
     if (b->w.n0 > 0) {
         const uint32_t *names_cur = cur_round == 0 ? nullptr : b->w.names[cur_round & 1];
+        int32_t *const *labp = b->ptr_mode ? b->d_labp : nullptr;
         hipLaunchKernelGGL(k_compose_batch, dim3(b->grid_for(b->w.n0)), dim3(kThreads), 0, s, b->w, names_cur, labels,
-                           (const uint32_t *)b->d_voff32, (const uint8_t *)b->d_skip);
+                           labp, (const uint32_t *)b->d_voff32, (const uint8_t *)b->d_skip);
         if (!batch_hip(b, hipGetLastError(), "compose")) return false;
     }
     return true;
@@ -377,13 +409,12 @@ cc_status finish_checks(cc_batch *b) {
     return CC_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
-                          const uint64_t *h_seeds, const void *d_src, const void *d_dst, const cc_options *opts,
-                          cc_batch **out) {
+// A batch over graphs packed in d_src/d_dst (cc_batch_create), or over graphs whose records
+// and labels sit at per-graph pointers (psrc non-null: a cohort of the serving scheduler, which
+// also lends its host mirror of the round state).
+cc_status create_batch(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off, const uint64_t *h_seeds,
+                       const void *d_src, const void *d_dst, const cc_options *opts, RoundState *mirror,
+                       const int32_t *const *psrc, const int32_t *const *pdst, int32_t *const *plab, cc_batch **out) {
     if (!out) return CC_E_ARG;
     *out = nullptr;
     if (n_graphs < 0 || !opts || (n_graphs > 0 && (!h_vtx_off || !h_edge_off || !h_seeds))) return CC_E_ARG;
@@ -393,7 +424,7 @@ cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int6
     const int64_t n0 = n_graphs ? h_vtx_off[n_graphs] : 0;
     const int64_t m0 = n_graphs ? h_edge_off[n_graphs] : 0;
     if (n0 > 0x7FFFFFFFLL || m0 > 0xFFFFFFFELL) return CC_E_ARG;
-    if (m0 > 0 && (!d_src || !d_dst)) return CC_E_ARG;
+    if (m0 > 0 && !psrc && (!d_src || !d_dst)) return CC_E_ARG;
     cc_batch *b = new (std::nothrow) cc_batch();
     if (!b) return CC_E_NOMEM;
     b->G = n_graphs;
@@ -428,7 +459,18 @@ cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int6
     b->cfg.rounds_per_graph = 24;
     b->cfg.use_graph = 1;
     if (small_bytes(b->cfg.small_variant, b->cfg.small_threads) > b->max_lds) b->cfg.small_variant = 1;
-    if (hipHostMalloc((void **)&b->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+    if (psrc) {   // a cohort: the records and labels of graph g at per-graph pointers
+        b->ptr_mode = true;
+        b->h_srcp.assign(psrc, psrc + n_graphs);
+        b->h_dstp.assign(pdst, pdst + n_graphs);
+        b->h_labp.assign(plab, plab + n_graphs);
+        b->cfg.small_variant = 0;   // every graph takes the union path
+        b->cfg.use_graph = 0;       // its rounds are driven one at a time
+    }
+    if (mirror) {
+        b->h_st = mirror;
+        b->h_st_borrowed = true;
+    } else if (hipHostMalloc((void **)&b->h_st, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         b->h_st = (RoundState *)calloc(1, sizeof(RoundState));
         b->h_st_pageable = true;
@@ -440,6 +482,17 @@ cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int6
     b->ws_need = plan_workspace(n0, m0, true, false, nullptr, nullptr) + batch_extra_bytes(n_graphs);
     *out = b;
     return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,
+                          const uint64_t *h_seeds, const void *d_src, const void *d_dst, const cc_options *opts,
+                          cc_batch **out) {
+    return create_batch(n_graphs, h_vtx_off, h_edge_off, h_seeds, d_src, d_dst, opts, nullptr, nullptr, nullptr,
+                        nullptr, out);
 }
 
 cc_status cc_batch_workspace_size(const cc_batch *b, size_t *bytes) {
@@ -468,6 +521,10 @@ cc_status cc_batch_set_workspace(cc_batch *b, void *d_ws, size_t bytes) {
     b->d_rounds = (int32_t *)carve(p, 4 * g);
     b->d_skip = (uint8_t *)carve(p, g);
     b->d_queue = (uint32_t *)carve(p, 64);
+    b->d_srcp = (const int32_t **)carve(p, 8 * g);
+    b->d_dstp = (const int32_t **)carve(p, 8 * g);
+    b->d_labp = (int32_t **)carve(p, 8 * g);
+    b->d_bad = (int32_t *)carve(p, 4 * g);
     b->w.g_rounds = b->d_rounds;
     b->d_seeds = b->d_seeds_w;
     b->d_voff = b->d_voff32;
@@ -481,6 +538,13 @@ cc_status cc_batch_set_workspace(cc_batch *b, void *d_ws, size_t bytes) {
               batch_hip(b, hipMemcpyAsync(b->d_voff32, v32.data(), 4 * g, hipMemcpyHostToDevice, s), "upload") &&
               (b->G == 0 || batch_hip(b, hipMemcpyAsync(b->d_seeds_w, b->h_seeds.data(), 8 * (size_t)b->G,
                                                         hipMemcpyHostToDevice, s), "upload"));
+    if (ok && b->ptr_mode && b->G > 0)
+        ok = batch_hip(b, hipMemcpyAsync(b->d_srcp, b->h_srcp.data(), 8 * (size_t)b->G, hipMemcpyHostToDevice, s),
+                       "upload") &&
+             batch_hip(b, hipMemcpyAsync(b->d_dstp, b->h_dstp.data(), 8 * (size_t)b->G, hipMemcpyHostToDevice, s),
+                       "upload") &&
+             batch_hip(b, hipMemcpyAsync(b->d_labp, b->h_labp.data(), 8 * (size_t)b->G, hipMemcpyHostToDevice, s),
+                       "upload");
     if (!ok) return CC_E_HIP;
     if (n0 > 0) {
         const int ggrid = std::max(1, std::min(b->G, b->grid_cap));
@@ -594,7 +658,7 @@ cc_status cc_batch_destroy(cc_batch *b) {
     drop_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     for (auto e : b->events) (void)hipEventDestroy(e);
-    if (b->h_st) {
+    if (b->h_st && !b->h_st_borrowed) {
         if (b->h_st_pageable)
             free(b->h_st);
         else
@@ -607,3 +671,83 @@ cc_status cc_batch_destroy(cc_batch *b) {
 const char *cc_batch_last_error(const cc_batch *b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"
+
+
+// ---- cohorts of the serving scheduler --------------------------------------------------------
+//
+// A cohort is a batch in pointer mode whose rounds the scheduler drives one at a time on its
+// slot stream: cohort_begin enqueues the union input and round 0, cohort_advance (once the
+// state readback it enqueued has completed) the next round or the labels.  Each call ends with
+// a state readback into the borrowed mirror; the caller records its event after it.
+
+namespace lc {
+
+cc_status cohort_create(int32_t G, const int64_t *h_voff, const int64_t *h_eoff, const uint64_t *h_seeds,
+                        const int32_t *const *h_src, const int32_t *const *h_dst, int32_t *const *h_labels,
+                        hipStream_t stream, RoundState *mirror, cc_batch **out) {
+    if (!h_src || !h_dst || !h_labels || !mirror || G < 1) return CC_E_ARG;
+    cc_options o{};
+    o.stream = stream;
+    return create_batch(G, h_voff, h_eoff, h_seeds, nullptr, nullptr, &o, mirror, h_src, h_dst, h_labels, out);
+}
+
+static bool cohort_readback(cc_batch *b) {
+    return batch_hip(b, hipMemcpyAsync(b->h_st, b->w.st, sizeof(RoundState), hipMemcpyDeviceToHost, b->stream),
+                     "state readback");
+}
+
+// the labels of every graph, then its round count into h_rounds (pinned, G entries; -1 for a
+// graph with a record out of range)
+static cc_status cohort_finish(cc_batch *b, int32_t *h_rounds) {
+    if (!enqueue_epilogue(b, nullptr, b->async_round)) return CC_E_HIP;
+    hipLaunchKernelGGL(k_mark_bad, dim3(b->grid_for(b->G)), dim3(kThreads), 0, b->stream, b->d_rounds,
+                       (const int32_t *)b->d_bad, b->G);
+    if (!batch_hip(b, hipGetLastError(), "input flags")) return CC_E_HIP;
+    if (!batch_hip(b, hipMemcpyAsync(h_rounds, b->d_rounds, 4 * (size_t)b->G, hipMemcpyDeviceToHost, b->stream),
+                   "rounds readback") ||
+        !cohort_readback(b))
+        return CC_E_HIP;
+    b->async_phase = 2;
+    return CC_OK;
+}
+
+cc_status cohort_begin(cc_batch *b, int32_t *h_rounds) {
+    if (!b || !b->ptr_mode || !b->ws) return CC_E_ARG;
+    if (!b->planned) {
+        const cc_status st = plan(b);
+        if (st != CC_OK) return st;
+    }
+    b->failed_status = 0;
+    if (!enqueue_prologue(b)) return CC_E_HIP;
+    b->async_round = 0;
+    if (b->union_m == 0) return cohort_finish(b, h_rounds);
+    if (!enqueue_union_round(b, 0) || !cohort_readback(b)) return CC_E_HIP;
+    b->async_round = 1;
+    b->async_phase = 1;
+    return CC_OK;
+}
+
+cc_status cohort_advance(cc_batch *b, int32_t *h_rounds, bool *finished) {
+    *finished = false;
+    const RoundState &st = *b->h_st;
+    // a record out of range (error bit 0) became a loop: its graph alone is reported (by its
+    // round count), the others are solved as usual; any other error ends the cohort
+    if (st.err & ~1u) {
+        *finished = true;
+        return bfail(b, CC_E_STATE, "internal consistency check failed on the device");
+    }
+    if (b->async_phase == 2) {
+        *finished = true;
+        return CC_OK;
+    }
+    if (st.done) return cohort_finish(b, h_rounds);
+    if (st.levels >= kMaxLevels) {
+        *finished = true;
+        return bfail(b, CC_E_STATE, "too many rounds for the map arena");
+    }
+    if (!enqueue_union_round(b, b->async_round) || !cohort_readback(b)) return CC_E_HIP;
+    ++b->async_round;
+    return CC_OK;
+}
+
+}  // namespace lc

@@ -161,6 +161,18 @@ cc_status hip_status(cc_ctx *c);
 // freeing pinned host memory synchronises the whole device, which would stall every other
 // request in flight each time one completes.
 cc_status ctx_create(const cc_graph_desc *graph, const cc_options *opts, RoundState *mirror, cc_ctx **out);
+// Cohorts of the serving scheduler (lc_batch.hip): G graphs of int32 local ids whose records
+// and labels stay at per-graph device pointers, solved as one disjoint union (the batch's union
+// path), every round of all of them one launch sequence on `stream`.  cohort_begin enqueues the
+// union input and round 0, cohort_advance (after the previous call's state readback into
+// `mirror` has completed) the next round or the labels, and sets *finished once the labels
+// and the rounds (h_rounds: G entries, pinned) are written.  Workspace as for a batch
+// (cc_batch_workspace_size / cc_batch_set_workspace); cc_batch_destroy ends it.
+cc_status cohort_create(int32_t G, const int64_t *h_voff, const int64_t *h_eoff, const uint64_t *h_seeds,
+                        const int32_t *const *h_src, const int32_t *const *h_dst, int32_t *const *h_labels,
+                        hipStream_t stream, RoundState *mirror, cc_batch **out);
+cc_status cohort_begin(cc_batch *b, int32_t *h_rounds);
+cc_status cohort_advance(cc_batch *b, int32_t *h_rounds, bool *finished);
 // asynchronous round interface (used by the serving scheduler)
 cc_status ctx_round_enqueue(cc_ctx *c, int *launched);
 cc_status ctx_round_complete(cc_ctx *c, cc_round_stats *out);

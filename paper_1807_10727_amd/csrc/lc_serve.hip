@@ -102,6 +102,14 @@ struct Request {
     size_t off = 0;
     int slot = -1;
     int phase = 0;   // 1: a round in flight, 2: labels in flight
+    int32_t cohort = 0;       // requests of the cohort it was solved in
+};
+
+// Large requests solved together as one disjoint union on one slot (cohort_*).
+struct Cohort {
+    std::vector<Request *> reqs;
+    cc_batch *b = nullptr;
+    size_t off = 0, footprint = 0;
 };
 
 struct SmallLaunch {
@@ -125,8 +133,11 @@ struct cc_server {
     std::vector<hipStream_t> streams;       // one per slot
     std::vector<hipEvent_t> events;         // one per slot
     std::vector<Request *> slot_req;
+    std::vector<Cohort *> slot_cohort;      // a slot holds a request or a cohort
     RoundState *mirrors = nullptr;          // pinned host mirrors of the round state, one per slot
     bool mirrors_pageable = false;
+    int32_t *rounds_pinned = nullptr;       // per slot: the round counts of a cohort's requests
+    int64_t n_cohorts = 0;
     hipStream_t small_stream = nullptr;
     std::vector<SmallLaunch> small;         // small launches (in flight or free)
     std::mutex mu;
@@ -136,6 +147,7 @@ struct cc_server {
     std::unordered_map<uint64_t, Request *> live;
     uint64_t next_id = 1;
     bool stop = false;
+    bool paused = false;                    // admit nothing new (cc_server_pause)
     std::thread worker;
     std::chrono::steady_clock::time_point t0;
     std::string err;
@@ -238,6 +250,96 @@ void advance_large(cc_server *s, int k) {
     release_large(s, r);
     s->live.erase(r->id);
     finish_locked(s, r, st);
+}
+
+constexpr int kCohortMax = 64;
+
+bool cohort_ok(const cc_server *s, const Request *r) {
+    const int64_t nmax = s->cfg.cohort_max_vertices > 0 ? s->cfg.cohort_max_vertices : (int64_t)1 << 20;
+    return s->cfg.cohort_max > 1 && !r->small && !r->cancelled && r->g.layout == CC_EDGES_SOA_I32 &&
+           r->g.n_vertices > 0 && r->g.n_vertices <= nmax;
+}
+
+void release_cohort(cc_server *s, int k) {
+    Cohort *c = s->slot_cohort[k];
+    if (c->b) cc_batch_destroy(c->b);   // the slot's mirror is borrowed: nothing to free on the host
+    if (c->footprint) s->alloc.release(c->off, c->footprint);
+    s->slot_cohort[k] = nullptr;
+    delete c;
+}
+
+// start the requests `reqs` as one cohort on slot k (lock held); false when it cannot start
+// (memory short, or a HIP failure, after which the requests stay pending)
+bool admit_cohort(cc_server *s, const std::vector<Request *> &reqs, int k) {
+    const int32_t G = (int32_t)reqs.size();
+    std::vector<int64_t> voff(G + 1, 0), eoff(G + 1, 0);
+    std::vector<uint64_t> seeds(G);
+    std::vector<const int32_t *> src(G), dst(G);
+    std::vector<int32_t *> lab(G);
+    for (int32_t i = 0; i < G; ++i) {
+        const Request *r = reqs[i];
+        voff[i + 1] = voff[i] + r->g.n_vertices;
+        eoff[i + 1] = eoff[i] + r->g.n_edges;
+        seeds[i] = r->seed;
+        src[i] = (const int32_t *)r->g.src;
+        dst[i] = (const int32_t *)r->g.dst;
+        lab[i] = (int32_t *)r->labels;
+    }
+    if (voff[G] > 0x7FFFFFFFLL || eoff[G] > 0xFFFFFFFELL) return false;
+    Cohort *c = new (std::nothrow) Cohort();
+    if (!c) return false;
+    if (cohort_create(G, voff.data(), eoff.data(), seeds.data(), src.data(), dst.data(), lab.data(), s->streams[k],
+                      s->mirrors + k, &c->b) != CC_OK) {
+        delete c;
+        return false;
+    }
+    size_t need = 0;
+    (void)cc_batch_workspace_size(c->b, &need);
+    if (!s->alloc.alloc(need, &c->off)) {
+        cc_batch_destroy(c->b);
+        delete c;
+        return false;
+    }
+    c->footprint = need;
+    s->peak_used = std::max(s->peak_used, s->alloc.used);
+    s->slot_cohort[k] = c;
+    int32_t *h_rounds = s->rounds_pinned + (size_t)k * kCohortMax;
+    if (cc_batch_set_workspace(c->b, s->arena + c->off, need) != CC_OK || cohort_begin(c->b, h_rounds) != CC_OK ||
+        hipEventRecord(s->events[k], s->streams[k]) != hipSuccess) {
+        (void)hipStreamSynchronize(s->streams[k]);
+        release_cohort(s, k);
+        return false;
+    }
+    const double t = s->now();
+    for (Request *r : reqs) {
+        r->t_admit = t;
+        r->cohort = G;
+    }
+    c->reqs = reqs;
+    s->n_cohorts += 1;
+    return true;
+}
+
+// a cohort slot's event has completed: its next round, its labels, or its end (lock held)
+void advance_cohort(cc_server *s, int k) {
+    Cohort *c = s->slot_cohort[k];
+    int32_t *h_rounds = s->rounds_pinned + (size_t)k * kCohortMax;
+    bool finished = false;
+    const cc_status st = cohort_advance(c->b, h_rounds, &finished);
+    if (st == CC_OK && !finished) {
+        if (hipEventRecord(s->events[k], s->streams[k]) == hipSuccess) return;
+    }
+    (void)hipStreamSynchronize(s->streams[k]);
+    std::vector<Request *> reqs = c->reqs;
+    release_cohort(s, k);
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        Request *r = reqs[i];
+        cc_status rs = st;
+        if (rs == CC_OK) rs = h_rounds[i] < 0 ? CC_E_INPUT : (r->cancelled ? CC_E_STATE : CC_OK);   // -1: bad input
+        r->rounds = rs == CC_OK ? h_rounds[i] : 0;
+        s->live.erase(r->id);
+        finish_locked(s, r, rs);
+    }
 }
 
 // fuse waiting small requests into one LDS-solver launch (lock held)
@@ -344,9 +446,12 @@ void worker_loop(cc_server *s) {
         bool progress = false;
         // completions
         for (size_t k = 0; k < s->slot_req.size(); ++k) {
-            if (!s->slot_req[k]) continue;
+            if (!s->slot_req[k] && !s->slot_cohort[k]) continue;
             if (hipEventQuery(s->events[k]) == hipSuccess) {
-                advance_large(s, (int)k);
+                if (s->slot_req[k])
+                    advance_large(s, (int)k);
+                else
+                    advance_cohort(s, (int)k);
                 progress = true;
             }
         }
@@ -359,7 +464,8 @@ void worker_loop(cc_server *s) {
         // admission, in arrival order; a large request waiting for memory keeps later large
         // requests waiting too (no starvation), small ones may pass it
         bool large_blocked = false;
-        for (auto it = s->pending.begin(); it != s->pending.end();) {
+        const bool admitting = !s->paused || s->stop;
+        for (auto it = s->pending.begin(); admitting && it != s->pending.end();) {
             Request *r = *it;
             if (r->cancelled) {
                 s->live.erase(r->id);
@@ -383,10 +489,22 @@ void worker_loop(cc_server *s) {
             }
             int free_slot = -1;
             for (size_t k = 0; k < s->slot_req.size(); ++k)
-                if (!s->slot_req[k]) {
+                if (!s->slot_req[k] && !s->slot_cohort[k]) {
                     free_slot = (int)k;
                     break;
                 }
+            if (free_slot >= 0 && cohort_ok(s, r)) {
+                // this request and the waiting ones after it that can join, up to cohort_max
+                std::vector<Request *> co{r};
+                const int cmax = std::min(s->cfg.cohort_max, kCohortMax);
+                for (auto jt = std::next(it); jt != s->pending.end() && (int)co.size() < cmax; ++jt)
+                    if (cohort_ok(s, *jt)) co.push_back(*jt);
+                if (co.size() > 1 && admit_cohort(s, co, free_slot)) {
+                    for (Request *q : co) s->pending.erase(std::find(s->pending.begin(), s->pending.end(), q));
+                    progress = true;
+                    break;   // the pending list changed: scan it again on the next pass
+                }
+            }
             if (free_slot < 0 || !admit_large(s, r, free_slot)) {
                 large_blocked = true;
                 ++it;
@@ -407,10 +525,11 @@ void worker_loop(cc_server *s) {
                 (void)before;
             }
         }
-        bool active = !s->pending.empty();
+        bool active = !s->pending.empty() && admitting;
         for (auto *r : s->slot_req) active |= r != nullptr;
+        for (auto *c : s->slot_cohort) active |= c != nullptr;
         for (auto &L : s->small) active |= L.busy;
-        if (s->stop && !active) break;
+        if (s->stop && !active && s->pending.empty()) break;
         if (!progress) {
             // device work in flight: poll again shortly; otherwise sleep until a submit
             if (active)
@@ -432,7 +551,7 @@ cc_status cc_server_create(void *d_arena, size_t budget_bytes, const cc_server_c
     if (cfg->n_slots < 1 || cfg->n_slots > 64 || cfg->small_variant < 0 || cfg->small_variant >= kNumSmallVariants ||
         (cfg->small_threads != 256 && cfg->small_threads != 512) || cfg->small_blocks_per_cu < 1 ||
         cfg->max_small_per_launch < 1 || cfg->max_small_per_launch > 65536 || cfg->small_launches < 1 ||
-        cfg->small_launches > 8)
+        cfg->small_launches > 8 || cfg->cohort_max < 0 || cfg->cohort_max > kCohortMax || cfg->cohort_max_vertices < 0)
         return CC_E_ARG;
     cc_server *s = new (std::nothrow) cc_server();
     if (!s) return CC_E_NOMEM;
@@ -460,13 +579,17 @@ cc_status cc_server_create(void *d_arena, size_t budget_bytes, const cc_server_c
         s->events.push_back(ev);
     }
     s->slot_req.assign(s->streams.size(), nullptr);
-    if (ok && hipHostMalloc((void **)&s->mirrors, sizeof(RoundState) * (size_t)cfg->n_slots, hipHostMallocDefault) !=
-                  hipSuccess) {
-        (void)hipGetLastError();   // a pageable mirror still works, only slower to copy
-        s->mirrors = (RoundState *)calloc((size_t)cfg->n_slots, sizeof(RoundState));
+    s->slot_cohort.assign(s->streams.size(), nullptr);
+    // pinned host memory for every slot, allocated once: a mirror of the round state and a
+    // cohort's round counts (freeing pinned memory later would synchronise the whole device)
+    const size_t host_bytes = (sizeof(RoundState) + 4 * (size_t)kCohortMax) * (size_t)cfg->n_slots;
+    if (ok && hipHostMalloc((void **)&s->mirrors, host_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();   // pageable host memory still works, only slower to copy
+        s->mirrors = (RoundState *)calloc(1, host_bytes);
         s->mirrors_pageable = true;
         ok = s->mirrors != nullptr;
     }
+    if (ok) s->rounds_pinned = (int32_t *)(s->mirrors + cfg->n_slots);
     if (ok) ok = hipStreamCreateWithFlags(&s->small_stream, hipStreamNonBlocking) == hipSuccess;
     s->small.resize(cfg->small_launches);
     for (auto &L : s->small) {
@@ -534,7 +657,7 @@ static int32_t take_done(cc_server *s, cc_request_result *out, int32_t cap) {
         o.status = r->status;
         o.rounds = r->rounds;
         o.small_path = r->small ? 1 : 0;
-        o.reserved = 0;
+        o.cohort = r->cohort;
         o.t_submit = r->t_submit;
         o.t_admit = r->t_admit;
         o.t_done = r->t_done;
@@ -570,6 +693,16 @@ cc_status cc_server_cancel(cc_server *s, uint64_t req_id) {
     return CC_OK;
 }
 
+cc_status cc_server_pause(cc_server *s, int32_t paused) {
+    if (!s) return CC_E_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->paused = paused != 0;
+    }
+    s->cv.notify_all();
+    return CC_OK;
+}
+
 cc_status cc_server_info(cc_server *s, cc_server_info_t *info) {
     if (!s || !info) return CC_E_ARG;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -577,6 +710,7 @@ cc_status cc_server_info(cc_server *s, cc_server_info_t *info) {
     info->pending = (int64_t)s->pending.size();
     int64_t active = 0;
     for (auto *r : s->slot_req) active += r != nullptr;
+    for (auto *c : s->slot_cohort) active += c ? (int64_t)c->reqs.size() : 0;
     for (auto &L : s->small) active += L.busy ? (int64_t)L.reqs.size() : 0;
     info->active = active;
     info->bytes_in_use = (int64_t)s->alloc.used;

@@ -429,6 +429,60 @@ def test_emulated_server(cc):
     assert 0 < small < len(graphs)
 
 
+def test_emulated_server_cohorts(cc):
+    """Large requests started together as cohorts (one disjoint union, one launch sequence a
+    round for all of them): every request's labels and round count are the oracle's; a
+    request with an id out of range fails alone, its cohort's others are unaffected; no
+    device-wide wait while serving."""
+    import time
+    syncs = cc._lib.hipemu_device_syncs
+    syncs.restype = ctypes.c_longlong
+    rng = np.random.default_rng(5)
+    graphs = []
+    for i in range(11):
+        n = int(rng.integers(600, 4000))
+        g = graphgen.Graph(n, *graphgen.gnm(700 + i, n, int(rng.integers(n // 2, 3 * n))))
+        graphs.append(g)
+    bad = 6   # this request names a vertex out of range
+    graphs[bad] = graphgen.Graph(graphs[bad].n, graphs[bad].src.copy(), graphs[bad].dst.copy())
+    graphs[bad].dst[3] = graphs[bad].n + 5
+    arena = hipemu._aligned(1 << 28, None)
+    srv = cc.cc_server_create(arena.ctypes.data, arena.size, n_slots=2, small_variant=1, max_small_per_launch=4,
+                              cohort_max=4, cohort_max_vertices=1 << 12)
+    keep, out = {}, {}
+    syncs0 = syncs()
+    try:
+        cc.cc_server_pause(srv, True)   # the whole burst waits, then starts as cohorts
+        for i, g in enumerate(graphs):
+            s_, d_ = dev(g.src), dev(g.dst)
+            lab = np.full(g.n, -7, np.int32)
+            rid = cc.cc_server_submit(srv, g.n, g.m, cc.CC_EDGES_SOA_I32, s_.ctypes.data, d_.ctypes.data, 40 + i,
+                                      lab.ctypes.data)
+            keep[rid] = (i, s_, d_, lab)
+        cc.cc_server_pause(srv, False)
+        t_end = time.time() + 300
+        while len(out) < len(graphs) and time.time() < t_end:
+            for res in cc.cc_server_wait(srv, 0.5):
+                out[res["id"]] = res
+        served_syncs = syncs() - syncs0
+    finally:
+        cc.cc_server_destroy(srv)
+    assert len(out) == len(graphs)
+    assert served_syncs == 0
+    cohorts = 0
+    for rid, res in out.items():
+        i, _, _, lab = keep[rid]
+        if i == bad:
+            assert res["status"] == cc.CC_E_INPUT and res["cohort"] == 4
+            continue
+        g = graphs[i]
+        want = oracle.run(g.n, g.src, g.dst, seed=40 + i)
+        assert res["status"] == 0 and res["rounds"] == want.rounds, (i, res)
+        np.testing.assert_array_equal(lab.astype(np.uint32), want.labels, err_msg="request %d" % i)
+        cohorts += res["cohort"] > 1
+    assert cohorts == 10   # every request ran fused: 4 + 4 (with the bad one) + 3
+
+
 # ---- MergeToLarge ----------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])

@@ -164,3 +164,48 @@ def test_degenerate_requests(lc):
         want = expect(g, 5)
         np.testing.assert_array_equal(lab.cpu().numpy().astype(np.uint32), want.labels)
         assert r["rounds"] == want.rounds
+
+
+@pytest.mark.parametrize("cohort_max", [4, 64])
+def test_cohorts_equal_oracle(lc, cohort_max):
+    """Large requests fused into cohorts (one disjoint union, one launch sequence a round for
+    all of them): every request's labels and rounds are the oracle's, a request with an id
+    out of range fails alone, and a cancelled one ends cancelled."""
+    reqs = request_graphs(48, seed=7, log2_min=9, log2_max=16)
+    bad_g = graphgen.Graph(3000, *graphgen.gnm(77, 3000, 9000))
+    bad_dst = bad_g.dst.astype(np.int64)
+    bad_dst[11] = 3000 + 9
+    bad = (bad_g, 123, torch.from_numpy(bad_g.src.view(np.int32)).to(DEV),
+           torch.from_numpy(bad_dst.astype(np.int32)).to(DEV))
+    reqs.insert(20, bad)
+    torch.cuda.synchronize()
+    with lc.Server(2 << 30, n_slots=2, small_variant=1, max_small_per_launch=16, cohort_max=cohort_max,
+                   cohort_max_vertices=1 << 16) as srv:
+        srv.pause()   # the whole burst waits, then starts as cohorts
+        labs = {}
+        for i, (g, sd, s, d) in enumerate(reqs):
+            rid, lab = srv.submit(g.n, s, d, sd)
+            labs[rid] = (i, lab)
+        cancel_id = max(labs)
+        try:
+            srv.cancel(cancel_id)
+        except lc.CCError:
+            pass   # already completed
+        srv.pause(False)
+        res = srv.drain()
+    assert len(res) == len(reqs)
+    fused = 0
+    for x in res:
+        i, lab = labs[x["id"]]
+        if i == 20:
+            assert x["status"] == -2   # CC_E_INPUT
+            continue
+        if x["id"] == cancel_id and x["status"] != 0:
+            assert x["status"] == -5   # CC_E_STATE
+            continue
+        g, sd = reqs[i][0], reqs[i][1]
+        want = expect(g, sd)
+        assert x["status"] == 0 and x["rounds"] == want.rounds, (i, x)
+        np.testing.assert_array_equal(lab.cpu().numpy().view(np.uint32), want.labels)
+        fused += x["cohort"] > 1
+    assert fused > 0
