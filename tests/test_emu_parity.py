@@ -483,6 +483,28 @@ def test_emulated_server_cohorts(cc):
     assert cohorts == 10   # every request ran fused: 4 + 4 (with the bad one) + 3
 
 
+def test_emulated_server_pause(cc):
+    """While paused the server admits nothing (submissions wait, info reports them pending);
+    destroying a paused server with waiting requests ends them and returns."""
+    import time
+    g = graphgen.Graph(3000, *graphgen.gnm(9, 3000, 9000))
+    s_, d_ = dev(g.src), dev(g.dst)
+    labs = [np.full(g.n, -7, np.int32) for _ in range(3)]
+    arena = hipemu._aligned(1 << 26, None)
+    srv = cc.cc_server_create(arena.ctypes.data, arena.size, n_slots=2, small_variant=1, cohort_max=4)
+    try:
+        cc.cc_server_pause(srv, True)
+        for i, lab in enumerate(labs):
+            cc.cc_server_submit(srv, g.n, g.m, cc.CC_EDGES_SOA_I32, s_.ctypes.data, d_.ctypes.data, 3, lab.ctypes.data)
+        time.sleep(0.2)
+        info = cc.cc_server_info(srv)
+        assert info["pending"] == 3 and info["active"] == 0
+        assert cc.cc_server_poll(srv) == []
+        assert all((lab == -7).all() for lab in labs)
+    finally:
+        cc.cc_server_destroy(srv)   # paused, with waiting requests: must return
+
+
 # ---- MergeToLarge ----------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
