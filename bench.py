@@ -474,6 +474,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: none, tune every run)")
     ap.add_argument("--no-tune", action="store_true", help="keep the solver's default knobs (no autotuning)")
+    ap.add_argument("--tune-knobs", default="", help="comma-separated knobs to tune (default: all of them)")
     ap.add_argument("--verbose-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-only", action="store_true")
@@ -552,8 +553,14 @@ def main():
     if not args.no_tune:
         from paper_1807_10727_amd import autotune
         space = dict(autotune.SOLVER_SPACE)
+        if args.tune_knobs:
+            keep = args.tune_knobs.split(",")
+            unknown = [k for k in keep if k not in space]
+            if unknown:
+                raise SystemExit("unknown tuning knobs: %s" % ",".join(unknown))
+            space = {k: v for k, v in space.items() if k in keep}
         if args.round0 != "auto":
-            space.pop("round0")     # the form asked for stays
+            space.pop("round0", None)     # the form asked for stays
         t0 = time.perf_counter()
         with lc.Solver(n0, src, dst, seed=base_seed, flags=round0_flag, stream=stream, layout=layout) as ts:
             if args.round0 == "rows":

@@ -30,6 +30,7 @@ def test_smoke_runs():
 @pytest.mark.slow
 def test_bench_json_contract():
     proc = run(["bench", "--workload", "small", "--steps", "2", "--warmup", "2", "--secondary", "",
+                "--tune-knobs", "round0,round0_sort,row_pairs",
                 "--variant-steps", "1", "--batch-graphs", "12", "--batch-log2-max", "9", "--batch-steps", "1",
                 "--serve-requests", "6", "--serve-warmup", "2", "--serve-pool", "3", "--serve-log2-max", "12",
                 "--serve-loads", "1.0", "--serve-budget-gib", "1"],

@@ -60,7 +60,7 @@ KNOBS = st.fixed_dictionaries({
 })
 
 
-@settings(max_examples=150, deadline=None, derandomize=True,
+@settings(max_examples=100, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(g=graphs(), seed=st.integers(0, 2 ** 64 - 1), layout=st.sampled_from(["soa32", "soa64", "packed"]),
        rule=st.sampled_from(["local", "local", "tree", "one_hop", "merge_to_large"]), knobs=KNOBS,
@@ -82,7 +82,7 @@ def test_random_solves_match_the_oracle(g, seed, layout, rule, knobs, alphas):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
-@settings(max_examples=60, deadline=None, derandomize=True,
+@settings(max_examples=40, deadline=None, derandomize=True,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(seed=st.integers(0, 2 ** 32 - 1), count=st.integers(1, 24), log2_max=st.integers(2, 12),
        small_variant=st.sampled_from([0, 1, 2, 3]), small_threads=st.sampled_from([256, 512]),
