@@ -12,9 +12,10 @@
 //             tiles of a pass never crossing a first-level bucket;
 //   final     one workgroup per final bucket (up to 65,536 of them, ~K / 65,536 keys each)
 //             sorts the bucket in LDS and writes it where the radix passes would have left
-//             the keys.  A bucket larger than LDS holds is sorted in place in global memory
-//             by the same network: slow, and rare (buckets average a third of the capacity
-//             at 2^28 keys, and a heavy key gets a bucket of its own, which needs no sort).
+//             the keys.  A bucket larger than LDS holds is sorted in place by the same
+//             network, its chunk-local stages in LDS and only the others in global memory
+//             (rare: buckets average half the capacity at 2^28 keys, and a heavy key gets a
+//             bucket of its own, which needs no sort).
 //
 // Splitters only decide where the buckets are cut, never what the result is: every key lands
 // in the one bucket whose range holds it, buckets follow in key order, and every bucket ends
@@ -41,29 +42,69 @@ static_assert(kSortThreads == 256, "the bucket passes give each thread one of th
 // all-ascending form (the first comparator of each merge mirrors the block), whose
 // comparators always put the smaller key at the lower index.  Positions from n up are
 // treated as +infinity: every comparator that reaches one keeps its keys where they are, so
-// they are never read or written.  `a` is LDS or global memory; the workgroup's barriers order
-// the stages.
+// they are never read or written.  One stage: merge size k, comparator distance j, over
+// `half` comparator slots (half the network's size); the caller orders stages with barriers.
+template <typename Idx>
+__device__ inline void network_stage(uint64_t *a, Idx n, Idx half, Idx k, Idx j) {
+    const bool mirror = j == (k >> 1);
+    const int sh = __builtin_ctzll((unsigned long long)j);
+    for (Idx t = threadIdx.x; t < half; t += blockDim.x) {
+        const Idx i = ((t >> sh) << (sh + 1)) | (t & (j - 1));   // bit sh of i is 0
+        const Idx l = mirror ? (i ^ (k - 1)) : (i | j);        // l > i
+        if (l < n) {
+            const uint64_t x = a[i], y = a[l];
+            if (y < x) {
+                a[i] = y;
+                a[l] = x;
+            }
+        }
+    }
+}
+
 template <typename Idx>
 __device__ void sort_network(uint64_t *a, Idx n) {
     Idx N = 1;
     while (N < n) N <<= 1;
     for (Idx k = 2; k <= N; k <<= 1) {
         for (Idx j = k >> 1; j > 0; j >>= 1) {
-            const bool mirror = j == (k >> 1);
-            const int sh = __builtin_ctzll((unsigned long long)j);
-            for (Idx t = threadIdx.x; t < (N >> 1); t += blockDim.x) {
-                const Idx i = ((t >> sh) << (sh + 1)) | (t & (j - 1));   // bit sh of i is 0
-                const Idx l = mirror ? (i ^ (k - 1)) : (i | j);        // l > i
-                if (l < n) {
-                    const uint64_t x = a[i], y = a[l];
-                    if (y < x) {
-                        a[i] = y;
-                        a[l] = x;
-                    }
-                }
-            }
+            network_stage<Idx>(a, n, N >> 1, k, j);
             __syncthreads();
         }
+    }
+}
+
+// The same network for a bucket larger than LDS holds, g[0, n) in global memory, with the
+// stages that stay inside one LDS-sized chunk run in LDS (`lds`: kBkCap keys): first every
+// chunk is sorted there (the stages of merge size up to kBkCap), then, for each larger merge
+// size, the stages whose comparators cross chunks run in global memory and the rest chunk by
+// chunk in LDS.  Only log2(n / kBkCap) (log2(n / kBkCap) + 1) / 2 stages touch global memory.
+__device__ void sort_large(uint64_t *g, int64_t n, uint64_t *lds) {
+    int64_t N = 1;
+    while (N < n) N <<= 1;
+    auto chunk_pass = [&](bool full) {
+        for (int64_t c0 = 0; c0 < n; c0 += kBkCap) {
+            const int len = (int)(n - c0 < kBkCap ? n - c0 : kBkCap);
+            for (int i = threadIdx.x; i < len; i += blockDim.x) lds[i] = g[c0 + i];
+            __syncthreads();
+            if (full) {
+                sort_network<int>(lds, len);
+            } else {   // half-cleaners only (a merge size above kBkCap never mirrors here)
+                for (int j = kBkCap >> 1; j > 0; j >>= 1) {
+                    network_stage<int>(lds, len, kBkCap >> 1, 2 * kBkCap, j);
+                    __syncthreads();
+                }
+            }
+            for (int i = threadIdx.x; i < len; i += blockDim.x) g[c0 + i] = lds[i];
+            __syncthreads();
+        }
+    };
+    chunk_pass(true);
+    for (int64_t k = 2 * (int64_t)kBkCap; k <= N; k <<= 1) {
+        for (int64_t j = k >> 1; j >= kBkCap; j >>= 1) {
+            network_stage<int64_t>(g, n, N >> 1, k, j);
+            __syncthreads();
+        }
+        chunk_pass(false);
     }
 }
 
@@ -426,8 +467,8 @@ __global__ __launch_bounds__(kSortThreads) void k_bk_final(Work w) {
             __syncthreads();
             sort_network<int>(a, (int)n);
             for (int i = threadIdx.x; i < (int)n; i += kSortThreads) out[start + i] = a[i];
-        } else {   // larger than LDS: the same network in place in global memory
-            sort_network<int64_t>(in + start, n);
+        } else {   // larger than LDS: the same network, in place, its chunk-local stages in LDS
+            sort_large(in + start, n, a);
             if (dst != src)
                 for (int64_t i = threadIdx.x; i < n; i += kSortThreads) out[start + i] = in[start + i];
         }
