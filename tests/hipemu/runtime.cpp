@@ -167,13 +167,26 @@ bool resolve_wave(Group &g, int w) {
     return true;
 }
 
+// HIPEMU_ITEM_ORDER=reverse runs the work-items of a workgroup last to first between their
+// synchronisation points: a kernel that lets waves touch the same LDS or global words without
+// a barrier between them then sees the other order.
+bool items_reversed() {
+    static const bool rev = [] {
+        const char *m = getenv("HIPEMU_ITEM_ORDER");
+        return m && strcmp(m, "reverse") == 0;
+    }();
+    return rev;
+}
+
 void run_group(Group &g) {
     const int n = (int)g.fibers.size();
     const int waves = (n + kWave - 1) / kWave;
+    const bool rev = items_reversed();
     int done = 0;
     for (;;) {
         bool ran = false;
-        for (int i = 0; i < n; ++i) {
+        for (int ii = 0; ii < n; ++ii) {
+            const int i = rev ? n - 1 - ii : ii;
             Fiber &f = g.fibers[(size_t)i];
             if (f.item.state != 0) continue;
             g.cur = i;

@@ -624,17 +624,21 @@ print("FAILS", fails)
 """
 
 
-@pytest.mark.parametrize("order", ["reverse", "12345", "777"])
+@pytest.mark.parametrize("order", ["reverse", "12345", "777", "forward/items reversed"])
 def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
     """The same solves with the workgroups of every launch run in reverse or shuffled order:
     atomics, cursors and the relabel's key sets then see other interleavings, and the results
-    must not change."""
+    must not change.  The last case keeps the workgroups in order but runs the work-items of
+    each one last to first between synchronisation points, which would expose waves sharing
+    LDS or global words without a barrier between them."""
     import os
     import subprocess
     import sys
     here = os.path.dirname(os.path.abspath(__file__))
     code = ORDER_CHECK % (os.path.dirname(here), here)
-    env = dict(os.environ, HIPEMU_BLOCK_ORDER=order)
+    env = dict(os.environ, HIPEMU_BLOCK_ORDER=order.split("/")[0])
+    if order.endswith("items reversed"):
+        env["HIPEMU_ITEM_ORDER"] = "reverse"
     proc = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                           text=True, timeout=600)
     assert proc.returncode == 0, proc.stderr[-2000:]
