@@ -21,8 +21,7 @@
 // current value and only issues the atomic when it can lower it: values only decrease, so
 // a stale read can only cause a redundant atomic, never a missed one.
 
-#include "lc_internal.hpp"
-#include "lc_readers.hpp"
+#include "lc_steps.hpp"
 
 namespace lc {
 
@@ -39,89 +38,15 @@ __device__ inline uint32_t node_prio(const PrioCtx &pc, const Work &w, const uin
     return prio(pc.keys[g], name - pc.voff[g]);
 }
 
-__device__ inline int ceil_log2(uint64_t n) { return n <= 1 ? 0 : 64 - __clzll((long long)(n - 1)); }
-
-
 // ---------------------------------------------------------------------------------------
 
-// kSeeded (plain solve, rounds >= 1, where every node has a loop-free record): both halves of
-// the node word start at the node's own priority rather than +inf.  The one-hop minimum over
-// the closed neighbourhood then only needs the far endpoint's priority, which the same 8-byte
-// load that fetches the current minimum brings along; the two-hop accumulator may start at
-// rho(x) because it ends at most at m1[x] <= rho(x).
 template <bool kSeeded>
 __global__ __launch_bounds__(kThreads) void k_round_begin(Work w, const uint32_t *names, const uint32_t *tab) {
-    RoundState *st = w.st;
-    const int64_t n = (int64_t)st->n_cur;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->n_active = 0;
-        st->s_count = 0;
-        st->s_keys = 0;
-        st->n_slabs = 0;
-        st->m_next = 0;
-        st->n_next = 0;
-        st->n_final = 0;
-        st->n_labels = 0;
-        st->kb = ceil_log2(n < 2 ? 2 : (uint64_t)n);
-        st->hb_shift = st->kb;
-        st->nbits = 2 * st->kb;
-        st->key = round_key(st->seed, st->round);
-    }
-    RoundKey key{};
-    if (kSeeded) key = round_key(st->seed, st->round);
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        uint64_t v = ~0ull;
-        if (kSeeded) {
-            const uint64_t p = tab ? tab[names[i]] : prio(key, names[i]);
-            v = (p << 32) | p;
-        }
-        ((uint64_t *)w.ml)[i] = v;
-        w.is_label[i] = 0;
-        w.has_edge[i] = 0;
-    }
+    step_round_begin<kSeeded>(w, names, tab);
 }
 
-// One-hop minimum, plain solve, rounds >= 1 (node words seeded with the own priority): each
-// record sends rho(b) to a and rho(a) to b, read from the high halves of the two words.
 __global__ __launch_bounds__(kThreads) void k_min1_seeded(ReadInternal rd, Work w) {
-    constexpr int V = ReadInternal::kV;
-    rd.init(w.st);
-    const int64_t nch = rd.chunks();
-    const uint64_t *word = (const uint64_t *)w.ml;
-    uint32_t *m1 = w.ml;
-    bool bad = false;
-    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
-        const int64_t c = cb + threadIdx.x;
-        uint32_t a[V], b[V];
-        uint64_t wa[V], wb[V];
-        bool ok[V];
-        if (c < nch) {
-            rd.read(c, a, b, bad);
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            ok[j] = a[j] != b[j];
-            wa[j] = wb[j] = ~0ull;
-            if (ok[j]) {
-                wa[j] = word[a[j]];
-                wb[j] = word[b[j]];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const uint32_t pa = (uint32_t)(wa[j] >> 32), pb = (uint32_t)(wb[j] >> 32);
-            bool la;
-            const uint32_t va = run_min(ok[j] ? a[j] : 0xFFFFFFFFu, pb, la);
-            if (ok[j]) {
-                if (la && (uint32_t)wa[j] > va) atomicMin(&m1[2 * (size_t)a[j]], va);
-                if ((uint32_t)wb[j] > pa) atomicMin(&m1[2 * (size_t)b[j]], pa);
-            }
-        }
-    }
-    if (bad) atomicOr(&w.st->err, 1u);
+    step_min1_seeded(rd, w);
 }
 
 template <class R, bool kFirst, bool kBatch>
@@ -183,335 +108,41 @@ __global__ __launch_bounds__(kThreads) void k_min1(R rd, Work w, PrioCtx pc, con
 
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_min2(R rd, Work w) {
-    constexpr int V = R::kV;
-    rd.init(w.st);
-    const int64_t nch = rd.chunks();
-    const uint64_t *word = (const uint64_t *)w.ml;   // low half: one-hop min, high half: two-hop min
-    uint32_t *ml = w.ml;
-    bool bad = false;
-    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
-        const int64_t c = cb + threadIdx.x;
-        uint32_t a[V], b[V];
-        uint64_t wa[V], wb[V];
-        bool ok[V];
-        if (c < nch) {
-            rd.read(c, a, b, bad);
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            ok[j] = a[j] != b[j];
-            if (ok[j]) {
-                wa[j] = word[a[j]];
-                wb[j] = word[b[j]];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            const uint32_t v = ok[j] ? min((uint32_t)wa[j], (uint32_t)wb[j]) : kInf;
-            bool la = true;
-            const uint32_t va = R::kSorted ? run_min(ok[j] ? a[j] : 0xFFFFFFFFu, v, la) : v;
-            if (ok[j]) {
-                if (la && (uint32_t)(wa[j] >> 32) > va) atomicMin(&ml[2 * (size_t)a[j] + 1], va);
-                if ((uint32_t)(wb[j] >> 32) > v) atomicMin(&ml[2 * (size_t)b[j] + 1], v);
-            }
-        }
-    }
+    step_min2<R>(rd, w);
 }
 
-// word 1: the two-hop minimum (LocalContraction); word 0: the one-hop minimum (one-hop label)
 template <bool kFirst, bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_parent(Work w, PrioCtx pc, const uint32_t *gids, int word) {
-    RoundState *st = w.st;
-    if (!kBatch) pc.key = st->key;
-    const int64_t n = (int64_t)st->n_cur;
-    uint32_t active = 0;
-    bool broken = false;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t l = w.ml[2 * i + word];
-        if (l == kInf) {  // no loop-free record touches this id (round 0 only)
-            w.par[i] = (uint32_t)i;
-            continue;
-        }
-        uint32_t name;
-        if (!kBatch) {
-            name = rho_name(pc, l, w.n0);
-        } else {
-            const uint32_t g = kFirst ? w.gid0[i] : gids[i];
-            name = prio_inv(pc.keys[g], l) + pc.voff[g];
-        }
-        uint32_t p;
-        if (kFirst) {
-            p = name;
-        } else {
-            p = (int64_t)name < w.n0 ? w.idx_of[name] : 0xFFFFFFFFu;
-        }
-        if ((int64_t)p >= n) {  // cannot happen for a consistent state; never index out of range
-            broken = true;
-            p = (uint32_t)i;
-        }
-        w.par[i] = p;
-        w.is_label[p] = 1;
-        if (kBatch) w.g_rounds[kFirst ? w.gid0[i] : gids[i]] = st->round + 1;
-        ++active;
-    }
-    __shared__ uint32_t red[kThreads / kWave];
-    active = block_sum<kThreads>(active, red);   // one atomic per workgroup
-    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
-    if (broken) atomicOr(&st->err, 4u);
+    step_parent<kFirst, kBatch>(w, pc, gids, word);
 }
 
-// Workgroup-local set of sort keys already written (sorted records, i.e. rounds >= 1).
-constexpr int kDedupLog2 = LC_DEDUP_LOG2;   // slots: 1 << kDedupLog2
-constexpr int kDedupProbes = 8;
-constexpr unsigned long long kNoKey = ~0ull;   // no sort key has all 64 bits set (lo < hi)
-
-// False when `key` is in the set already; true when it was added now, or when its probes
-// all met other keys (the key is then written again: later passes drop any repeat).
-template <int kLog2 = kDedupLog2>
-__device__ inline bool set_insert(unsigned long long *set, uint64_t key) {
-    if (key == kNoKey) return true;
-    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kLog2));
-    for (int p = 0; p < kDedupProbes; ++p) {
-        const unsigned long long old = atomicCAS(&set[h], kNoKey, (unsigned long long)key);
-        if (old == kNoKey) return true;
-        if (old == key) return false;
-        h = (h + 1) & ((1 << kLog2) - 1);
-    }
-    return true;
-}
-
-// Round 0 read directly from the caller's records: the same per-workgroup set, smaller (the
-// unsorted records repeat only on power-law inputs), switched off by a workgroup once
-// kInputSetTrial of its keys found fewer than 1/16 repeats (uniform random inputs, where the
-// probes would cost more than they save).
-constexpr int kInputSetLog2 = 11;
-constexpr uint32_t kInputSetTrial = 4096;
-
-// Relabel every record through the parents and keep the loop-free ones as sort keys
-// (edge_key of (min, max) of the two parents).  Each workgroup owns a slab of kSlab
-// consecutive records and writes its survivors, in order, to the start of the same slab of
-// the output: no global counter is involved (one shared cursor, taken per chunk, measured
-// slower: the first chunks of every workgroup all write and contend on it).  slab_cnt holds
-// the keys per slab; the first radix pass reads the slabs.
-//
-// A workgroup also drops every key it has written before: a dense region that contracts
-// onto a few parents maps many records onto the same parent pairs (rounds >= 1, and round 0
-// of power-law inputs), and a hash set in LDS (kept for the whole launch) removes most of
-// those repeats before they reach the sort.  s_count still counts every survivor; s_keys
-// counts the keys.
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
-    constexpr int V = R::kV;
-    constexpr bool kDedup = true;
-    constexpr bool kAdaptive = !R::kSorted;
-    constexpr int kSetLog2 = R::kSorted ? kDedupLog2 : kInputSetLog2;
-    constexpr int64_t kChunksPerSlab = kSlab / V;
-    RoundState *st = w.st;
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    __shared__ unsigned long long set[1 << kSetLog2];
-    __shared__ uint32_t set_tries, set_drops, set_on;
-    for (int i = threadIdx.x; i < (1 << kSetLog2); i += kThreads) set[i] = kNoKey;
-    if (threadIdx.x == 0) {
-        set_tries = 0;
-        set_drops = 0;
-        set_on = 1;
-    }
-    __syncthreads();
-    rd.init(st);
-    const int64_t nch = rd.chunks();
-    const int64_t nslabs = ceil_div(rd.records(), kSlab);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->n_slabs = (u64c)nslabs;
-        st->keys_dense = 0;
-    }
-    uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
-    const int kb = st->kb;
-    const int hbs = st->hb_shift;
-    bool bad = false;
-    uint32_t survived = 0;   // this thread's loop-free records
-    uint64_t written = 0;    // this workgroup's keys (thread 0)
-    for (int64_t slab = blockIdx.x; slab < nslabs; slab += gridDim.x) {
-        const int64_t c_end = min(nch, (slab + 1) * kChunksPerSlab);
-        uint64_t *dst = out + slab * kSlab;
-        uint32_t cursor = 0;
-        for (int64_t cb = slab * kChunksPerSlab; cb < c_end; cb += kThreads) {
-            const int64_t c = cb + threadIdx.x;
-            uint64_t key[V];
-            bool keep[V];
-            uint32_t cnt = 0, tries = 0, drops = 0;
-            // read without a barrier: either value is valid
-            const bool use_set = !kAdaptive || (set_on != 0 && !w.round0_sets_off);
-            if (c < c_end) {
-                uint32_t a[V], b[V], pa[V], pb[V];
-                rd.read(c, a, b, bad);
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    pa[j] = a[j] != b[j] ? w.par[a[j]] : 0u;
-                    pb[j] = a[j] != b[j] ? w.par[b[j]] : 0u;
-                }
-#pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    keep[j] = pa[j] != pb[j];
-                    survived += keep[j];
-                    const uint32_t lo = min(pa[j], pb[j]), hi = max(pa[j], pb[j]);
-                    key[j] = edge_key(lo, hi, kb, hbs);
-                    if (kDedup && use_set && keep[j]) {
-                        ++tries;
-                        keep[j] = set_insert<kSetLog2>(set, key[j]);
-                        drops += !keep[j];
-                    }
-                    cnt += keep[j];
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < V; ++j) keep[j] = false;
-            }
-            if (kAdaptive && tries) {
-                atomicAdd(&set_tries, tries);
-                if (drops) atomicAdd(&set_drops, drops);
-            }
-            uint32_t total;
-            uint32_t off = cursor + block_excl_scan<kThreads>(cnt, lds, &total);   // (its barriers also order
-                                                                                // the counts above)
-            if (kAdaptive && threadIdx.x == 0 && set_on && set_tries >= kInputSetTrial && 16 * set_drops < set_tries)
-                set_on = 0;
-#pragma unroll
-            for (int j = 0; j < V; ++j) {
-                if (keep[j]) dst[off++] = key[j];
-            }
-            cursor += total;
-        }
-        if (threadIdx.x == 0) w.slab_cnt[slab] = cursor;
-        written += cursor;
-    }
-    survived = block_sum<kThreads>(survived, lds);
-    if (threadIdx.x == 0) {
-        if (survived) atomicAdd(&st->s_count, (u64c)survived);
-        if (written) atomicAdd(&st->s_keys, (u64c)written);
-    }
+    step_relabel<R>(rd, w);
 }
 
-// Parents become ranks among the labels (the distinct parents, marked in lmap, whose scan
-// has just run): the relabelled edges then name their endpoints with ceil(log2 L) bits
-// instead of ceil(log2 N), and everything after the relabel works over the L labels.
-// lab_at inverts the ranking.
 __global__ __launch_bounds__(kThreads) void k_rank_parents(Work w) {
-    const int64_t n = (int64_t)w.st->n_cur;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t p = w.par[i];
-        w.par[i] = nmap_has(w.lmap, p) ? nmap_rank(w.lmap, p) : kNoParent;
-        if (nmap_has(w.lmap, i)) w.lab_at[nmap_rank(w.lmap, i)] = (uint32_t)i;
-    }
+    step_rank_parents(w);
 }
 
-// Key width of the round's sort (2 ceil(log2 L) bits) and the block width of the next
-// round's edge order: kBlockNodes labels, which become about as many next-round nodes.
 __global__ void k_plan_blocks(Work w) {
-    RoundState *st = w.st;
-    const uint64_t L = st->n_labels;
-    const int kb = ceil_log2(L < 2 ? 2 : L);
-    st->kb = kb;
-    st->hb_shift = kb < LC_BLOCK_NODES_LOG2 ? kb : LC_BLOCK_NODES_LOG2;
-    st->nbits = 2 * kb;
+    step_plan_blocks(w);
 }
 
-// The next graph's nodes: the labels that keep an edge, named and indexed; the others are
-// final (counted).
 template <bool kFirst, bool kBatch>
 __global__ __launch_bounds__(kThreads) void k_nodes(Work w, const uint32_t *names_cur, uint32_t *names_next,
                                                     const uint32_t *gids_cur, uint32_t *gids_next) {
-    RoundState *st = w.st;
-    const int64_t L = (int64_t)st->n_labels;
-    uint32_t fin = 0;
-    for (int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x; j < L; j += (int64_t)gridDim.x * kThreads) {
-        if (nmap_has(w.nmap, j)) {
-            const uint32_t k = nmap_rank(w.nmap, j);
-            const uint32_t x = w.lab_at[j];
-            const uint32_t nm = kFirst ? x : names_cur[x];
-            names_next[k] = nm;
-            w.idx_of[nm] = k;
-            if (kBatch) gids_next[k] = kFirst ? w.gid0[x] : gids_cur[x];
-        } else {
-            ++fin;
-        }
-    }
-    __shared__ uint32_t red[kThreads / kWave];
-    fin = block_sum<kThreads>(fin, red);
-    if (threadIdx.x == 0 && fin) atomicAdd(&st->n_final, (u64c)fin);
+    step_nodes<kFirst, kBatch>(w, names_cur, names_next, gids_cur, gids_next);
 }
 
 template <bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_map(Work w, const uint32_t *names_cur) {
-    RoundState *st = w.st;
-    const int64_t n = (int64_t)st->n_cur;
-    uint32_t *out;
-    if (kFirst) {
-        out = w.map0;
-    } else {
-        if (n == 0) return;
-        if (st->map_off + (u64c)n > st->map_cap || st->levels >= kMaxLevels) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 2u);
-            return;
-        }
-        out = w.maps + st->map_off;
-    }
-    // the parent's bit and its index in the next graph come from one 8-byte word of the map;
-    // a final parent is named through the label of its rank.  When every label keeps an edge,
-    // a parent's index in the next graph is its rank.
-    const bool same = st->n_next == st->n_labels;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const uint32_t q = w.par[i];
-        if (q == kNoParent) {   // round 0: an id without a loop-free record is final on its own
-            out[i] = kFinal | (uint32_t)i;
-            continue;
-        }
-        if (same) {
-            out[i] = q;
-            continue;
-        }
-        const uint2 e = *(const uint2 *)(w.nmap + 2 * (q >> 5));
-        if ((e.x >> (q & 31)) & 1u) {
-            out[i] = e.y + (uint32_t)__popc(e.x & ((1u << (q & 31)) - 1u));
-        } else {
-            const uint32_t x = w.lab_at[q];
-            out[i] = kFinal | (kFirst ? x : names_cur[x]);
-        }
-    }
+    step_map<kFirst>(w, names_cur);
 }
 
 template <bool kFirst>
 __global__ void k_round_end(Work w, int dedup) {
-    RoundState *st = w.st;
-    if (st->m_cur > 0) {
-        const int r = st->round;
-        if (r < kStatRounds) {
-            u64c *s = st->rstats[r];
-            s[0] = (u64c)r;
-            s[1] = st->n_active;
-            s[2] = st->m_cur;
-            s[3] = st->s_count;
-            s[4] = st->m_next;
-            s[5] = st->n_final;
-            s[6] = st->s_keys;
-        }
-        st->rounds_active = r + 1;
-    }
-    st->n_prev = st->n_cur;
-    if (!kFirst && st->n_cur > 0 && !(st->err & 2u)) {
-        st->level_off[st->levels] = st->map_off;
-        st->levels += 1;
-        st->map_off += st->n_cur;
-    }
-    // the unique write's output (the hashed drop writes into the relabel's buffer)
-    const bool hashed = dedup == kDedupHash || (dedup == kDedupDevice && st->hash_slots != 0);
-    st->e_sel = hashed ? sort_src(st->round, st->e_sel) : 1 - sorted_sel(st->round, st->e_sel, st->nbits);
-    st->n_cur = st->n_next;
-    st->m_cur = st->m_next;
-    st->round += 1;
-    st->done = st->m_next == 0 ? 1 : 0;
+    step_round_end<kFirst>(w, dedup);
 }
 
 // label of every original vertex: chase its map0 entry through the kept levels

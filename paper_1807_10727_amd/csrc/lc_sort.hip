@@ -13,37 +13,13 @@
 // every kept edge as nodes of the next graph), one-workgroup scan; after the next graph's
 // index is known, an ordered write of the heads renamed into it.
 
-#include "lc_internal.hpp"
+#include "lc_steps.hpp"
 
 namespace lc {
 
 // ---------------------------------------------------------------------------------------
 // generic exclusive scan of uint8 or uint32 values into uint32 (count on the device)
 // ---------------------------------------------------------------------------------------
-
-template <typename T>
-__device__ inline void load16(const T *in, int64_t base, int64_t n, uint32_t (&v)[16]) {
-    if (base + 16 <= n) {
-        if (sizeof(T) == 1) {
-            uint4 x = *(const uint4 *)(in + base);
-            uint32_t wds[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-            for (int j = 0; j < 16; ++j) v[j] = (wds[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint4 x = *(const uint4 *)(in + base + 4 * q);
-                v[4 * q + 0] = x.x;
-                v[4 * q + 1] = x.y;
-                v[4 * q + 2] = x.z;
-                v[4 * q + 3] = x.w;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = base + j < n ? (uint32_t)in[base + j] : 0u;
-    }
-}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_scan_reduce(const T *in, const u64c *n_ptr, uint32_t *partials) {
@@ -62,30 +38,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const T *in, const u64
     }
 }
 
-// One workgroup scans `cnt` values in place (cnt = *n_ptr, or ceil(*n_ptr / per_entry)).
 __global__ __launch_bounds__(kThreads) void k_scan_single(uint32_t *data, const u64c *n_ptr, int per_entry,
                                                           u64c *total_out) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t n = (int64_t)*n_ptr;
-    const int64_t cnt = per_entry ? ceil_div(n, per_entry) : n;
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < cnt; base += kScanTile) {
-        uint32_t v[16];
-        const int64_t my = base + threadIdx.x * 16;
-        load16(data, my, cnt, v);
-        uint32_t sum = 0;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) sum += v[j];
-        uint32_t total;
-        uint32_t run = carry + block_excl_scan<kThreads>(sum, lds, &total);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (my + j < cnt) data[my + j] = run;
-            run += v[j];
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
+    step_scan_single(data, n_ptr, per_entry, total_out);
 }
 
 template <typename T>
@@ -322,83 +277,18 @@ void k_sort_scatter(Work w, int pass, int gated) {
 // next-graph node map: prefix counts over the bit words
 // ---------------------------------------------------------------------------------------
 
-// Bit map from byte flags (label map, node map): thread t of a block turns the 32 flags of
-// word blk * kThreads + t into bits; the blocks' counts are scanned like any other.
-__device__ inline uint32_t label_bits(const uint8_t *f, int64_t w, int64_t n) {
-    const int64_t base = w * 32;
-    uint32_t bits = 0;
-    if (base + 32 <= n) {
-        const uint4 a = *(const uint4 *)(f + base), b = *(const uint4 *)(f + base + 16);
-        const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) bits |= (((v[q] >> (8 * k)) & 0xFFu) != 0u ? 1u : 0u) << (4 * q + k);
-    } else {
-        for (int k = 0; k < 32; ++k)
-            if (base + k < n && f[base + k]) bits |= 1u << k;
-    }
-    return bits;
-}
-
 __global__ __launch_bounds__(kThreads) void k_flags_reduce(const uint8_t *f, const u64c *n_ptr, uint32_t *partials) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t n = (int64_t)*n_ptr;
-    const int64_t nw = ceil_div(n, 32);
-    const int64_t nblk = ceil_div(nw, kThreads);
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int64_t wd = blk * kThreads + threadIdx.x;
-        const uint32_t c = wd < nw ? (uint32_t)__popc(label_bits(f, wd, n)) : 0u;
-        uint32_t total;
-        block_excl_scan<kThreads>(c, lds, &total);
-        if (threadIdx.x == 0) partials[blk] = total;
-    }
+    step_flags_reduce(f, n_ptr, partials);
 }
 
 __global__ __launch_bounds__(kThreads) void k_flags_down(const uint8_t *f, const u64c *n_ptr,
                                                          const uint32_t *partials, uint32_t *lmap) {
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t n = (int64_t)*n_ptr;
-    const int64_t nw = ceil_div(n, 32);
-    const int64_t nblk = ceil_div(nw, kThreads);
-    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int64_t wd = blk * kThreads + threadIdx.x;
-        const uint32_t bits = wd < nw ? label_bits(f, wd, n) : 0u;
-        uint32_t total;
-        const uint32_t before = partials[blk] + block_excl_scan<kThreads>((uint32_t)__popc(bits), lds, &total);
-        if (wd < nw) *(uint2 *)(lmap + 2 * wd) = make_uint2(bits, before);
-    }
+    step_flags_down(f, n_ptr, partials, lmap);
 }
 
-// The same in one workgroup, for small rounds: every stage in a single launch (four words a
-// thread per step, a running carry across steps).
 __global__ __launch_bounds__(kThreads) void k_flags_single(const uint8_t *f, const u64c *n_ptr, uint32_t *map,
                                                            u64c *total_out) {
-    constexpr int kW = 4;
-    __shared__ uint32_t lds[kThreads / kWave + 1];
-    const int64_t n = (int64_t)*n_ptr;
-    const int64_t nw = ceil_div(n, 32);
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < nw; base += (int64_t)kThreads * kW) {
-        uint32_t bits[kW], c[kW], sum = 0;
-#pragma unroll
-        for (int q = 0; q < kW; ++q) {
-            const int64_t wd = base + (int64_t)threadIdx.x * kW + q;
-            bits[q] = wd < nw ? label_bits(f, wd, n) : 0u;
-            c[q] = (uint32_t)__popc(bits[q]);
-            sum += c[q];
-        }
-        uint32_t total;
-        uint32_t run = carry + block_excl_scan<kThreads>(sum, lds, &total);
-#pragma unroll
-        for (int q = 0; q < kW; ++q) {
-            const int64_t wd = base + (int64_t)threadIdx.x * kW + q;
-            if (wd < nw) *(uint2 *)(map + 2 * wd) = make_uint2(bits[q], run);
-            run += c[q];
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0) *total_out = carry;
+    step_flags_single(f, n_ptr, map, total_out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -520,160 +410,20 @@ __global__ __launch_bounds__(kSortThreads) void k_unique_write(Work w, int gated
 // duplicate drop by hashing (small rounds)
 // ---------------------------------------------------------------------------------------
 
-// Keys hold 2 ceil(log2 L) <= 62 bits, so no key has every bit set.
-constexpr uint64_t kEmptySlot = ~0ull;
-
-// The key set lives in the round's own edge buffer (E_r, consumed by the relabel) and the kept
-// keys go back into the relabel's buffer, so the round ends with the edges in the other buffer
-// than a sorted round of an even pass count would leave them (the host tells the round end).
-__device__ inline uint64_t *hash_table(const Work &w) { return w.keys[w.st->e_sel]; }
-
-// A key's home slot: a multiplicative hash, its high word scaled to [0, slots).
-__device__ inline uint64_t home_slot(uint64_t key, uint64_t slots) {
-    return __umul64hi(key * 0x9E3779B97F4A7C15ull, slots);
-}
-
-// The table: 2 K + 1 slots (at most half full), cleared to empty.  Every workgroup derives
-// the size from K; workgroup 0 records it for the kernels that follow.  decide: the host could
-// not bound K (a round of many records), and a round whose keys do not fit sorts instead
-// (hash_slots 0: every hashing kernel returns at once, the gated sort runs).  Otherwise a
-// round with more keys than the host's bound allowed, or than its buffer holds, is flagged
-// and keeps a table that fits the buffer: the inserts then run out of probes and flag it
-// again, and no access leaves the buffer.
 __global__ __launch_bounds__(kThreads) void k_hash_clear(Work w, int decide) {
-    RoundState *st = w.st;
-    const uint64_t K = st->s_keys;
-    uint64_t slots = 2 * K + 1;
-    const bool over = K > (uint64_t)kHashMaxRecords || slots > (uint64_t)w.kcap;
-    if (over) slots = decide ? 0 : (uint64_t)min((int64_t)2 * kHashMaxRecords + 1, w.kcap);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->hash_slots = (int32_t)slots;
-        if (over && !decide) atomicOr(&st->err, 4u);
-    }
-    uint64_t *tab = hash_table(w);
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < (int64_t)slots; i += (int64_t)gridDim.x * kThreads)
-        tab[i] = kEmptySlot;
+    step_hash_clear(w, decide);
 }
 
-// Every key the relabel wrote (in its slabs) joins the set: linear probing from its home slot,
-// an empty slot claimed with a compare-and-swap, a repeat stopping at its own key.
 __global__ __launch_bounds__(kSortThreads) void k_hash_insert(Work w) {
-    RoundState *st = w.st;
-    const uint64_t slots = (uint64_t)st->hash_slots;
-    if (slots == 0) return;   // the round sorts
-    const Tiles tl = tiles_of(w, 0);
-    const uint64_t *in = w.keys[sort_src(st->round, st->e_sel)];
-    u64c *tab = (u64c *)hash_table(w);
-    bool lost = false;
-    for (int64_t tile = blockIdx.x; tile < tl.ntiles; tile += gridDim.x) {
-        const int tv = tl.valid(tile);
-        for (int i = threadIdx.x; i < tv; i += kSortThreads) {
-            const uint64_t key = in[tile * kSortTile + i];
-            uint64_t h = home_slot(key, slots);
-            bool placed = false;
-            for (uint64_t probe = 0; probe < slots; ++probe) {
-                // the swap returns the slot's key whether or not it claims the slot
-                const uint64_t cur = atomicCAS(&tab[h], (u64c)kEmptySlot, (u64c)key);
-                if (cur == kEmptySlot || cur == key) {
-                    placed = true;
-                    break;
-                }
-                h = h + 1 == slots ? 0 : h + 1;
-            }
-            lost |= !placed;
-        }
-    }
-    if (lost) atomicOr(&st->err, 4u);
+    step_hash_insert(w);
 }
 
-// Kept keys per table tile (kSortTile slots, the last one ragged), and the next graph's nodes:
-// both endpoints of every kept edge.
 __global__ __launch_bounds__(kSortThreads) void k_hash_count(Work w) {
-    RoundState *st = w.st;
-    __shared__ uint32_t lds[kSortThreads / kWave + 1];
-    const int64_t slots = st->hash_slots;
-    if (slots == 0) return;   // the round sorts
-    const int64_t ntiles = ceil_div(slots, kSortTile);
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->aux_n = (u64c)ntiles;   // entries of the count scan
-    const uint64_t *tab = hash_table(w);
-    const int kb = st->kb;
-    const int hbs = st->hb_shift;
-    const uint64_t n_lab = st->n_labels;
-    bool broken = false;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        uint64_t kk[kSortItems];
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
-            kk[j] = idx < slots ? tab[idx] : kEmptySlot;
-        }
-        uint32_t cnt = 0;
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            if (kk[j] == kEmptySlot) continue;
-            ++cnt;
-            uint64_t lo, hi;
-            edge_key_split(kk[j], kb, hbs, lo, hi);
-            if (lo < n_lab && hi < n_lab) {
-                w.has_edge[lo] = 1;
-                w.has_edge[hi] = 1;
-            } else {
-                broken = true;
-            }
-        }
-        uint32_t total;
-        block_excl_scan<kSortThreads>(cnt, lds, &total);
-        if (threadIdx.x == 0) w.tile_cnt[tile] = total;
-    }
-    if (broken) atomicOr(&st->err, 4u);
+    step_hash_count(w);
 }
 
-// The next graph's edge list: the kept keys, tile by tile at the scanned tile offsets, renamed
-// into the next round's indices (as the unique write renames the sorted heads).
 __global__ __launch_bounds__(kSortThreads) void k_hash_write(Work w) {
-    constexpr int kWaves = kSortThreads / kWave;
-    RoundState *st = w.st;
-    __shared__ uint32_t rowcnt[kSortItems * kWaves];
-    const int64_t slots = st->hash_slots;   // 0: the round sorts
-    const int64_t ntiles = ceil_div(slots, kSortTile);
-    const uint64_t *tab = hash_table(w);
-    uint64_t *out = w.keys[sort_src(st->round, st->e_sel)];
-    const int kb = st->kb;
-    const int hbs = st->hb_shift;
-    const uint64_t n_lab = st->n_labels;
-    const bool same = st->n_next == n_lab;   // every label keeps an edge: index = rank
-    const int wave = threadIdx.x / kWave;
-    const uint64_t lt = lanemask_lt();
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        uint64_t k[kSortItems];
-        uint64_t bal[kSortItems];
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t idx = tile * kSortTile + j * kSortThreads + threadIdx.x;
-            k[j] = idx < slots ? tab[idx] : kEmptySlot;
-            bal[j] = ballot(k[j] != kEmptySlot);
-            if (lane_id() == 0) rowcnt[j * kWaves + wave] = (uint32_t)__popcll(bal[j]);
-        }
-        __syncthreads();
-        static_assert(kSortItems * kWaves == kWave, "one (row, wave) count per lane of wave 0");
-        if (threadIdx.x < kWave) {   // exclusive prefix over (row, wave)
-            const uint32_t c = rowcnt[threadIdx.x];
-            rowcnt[threadIdx.x] = (uint32_t)w.tile_cnt[tile] + wave_incl_scan(c) - c;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            if (k[j] != kEmptySlot) {
-                const uint32_t off = rowcnt[j * kWaves + wave] + (uint32_t)__popcll(bal[j] & lt);
-                uint64_t lo, hi;
-                edge_key_split(k[j], kb, hbs, lo, hi);
-                const uint32_t a = lo < n_lab ? (same ? (uint32_t)lo : nmap_rank(w.nmap, lo)) : 0u;
-                const uint32_t b = hi < n_lab ? (same ? (uint32_t)hi : nmap_rank(w.nmap, hi)) : 0u;
-                out[off] = ((uint64_t)a << 32) | b;
-            }
-        }
-        __syncthreads();
-    }
+    step_hash_write(w);
 }
 
 // ---------------------------------------------------------------------------------------
