@@ -33,7 +33,7 @@ COPY_REPS = 5             # timed repetitions of the 1 GiB calibration copy
 
 # The steps of a round (rows a2-a7 of the hot path) and the kernel families that carry out
 # each.  The tiled round 0's partition belongs to the implementation (it moves no algorithmic
-# byte); rounds inside a captured tail are timed together ("tail").
+# byte); rounds inside a captured tail or the persistent launch are timed together ("tail").
 FAMILY_STEP = {
     "round_begin": "a2_one_hop", "min1_round0": "a2_one_hop", "min1": "a2_one_hop", "min1_tiled": "a2_one_hop",
     "min2_round0": "a3_two_hop", "min2": "a3_two_hop", "min2_tiled": "a3_two_hop", "parent": "a3_two_hop",
@@ -46,7 +46,7 @@ FAMILY_STEP = {
     "part_a_hist": "partition", "part_a_scatter": "partition", "part_b_hist": "partition",
     "part_b_scatter": "partition", "part_scan": "partition", "part_rows_hist": "partition",
     "part_rows_scatter": "partition",
-    "tail_graph": "tail", "uf_finish": "finish", "merge_large": "merge_large",
+    "tail_graph": "tail", "fused_rounds": "tail", "uf_finish": "finish", "merge_large": "merge_large",
 }
 
 
@@ -68,7 +68,8 @@ def step_bytes(stats, n0, in_graph=None):
         a7 labels            4 N (+ 4 n0)       the map read; the labels written once
     Total 24 M + 16 S + 8 M' + 24 N per round, plus 4 n0.  Random-access amplification, extra
     sort passes and the tiled round 0's partition are the implementation's overhead.  Rounds
-    that ran inside a captured tail (in_graph[i] true) count under "tail"."""
+    that ran inside a captured tail or the persistent launch (in_graph[i] nonzero) count under
+    "tail"."""
     out = {}
 
     def add(k, v):

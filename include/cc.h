@@ -132,7 +132,10 @@ enum {
  * bound by launch overhead.  Results are
  * identical; rounds run this way have in_graph = 1 in their statistics, their kernels are
  * timed together as the family "tail_graph", and cc_round_parents is not available for
- * them.  CC_EAGER turns this off (cc_contract_round never uses it). */
+ * them.  CC_EAGER turns this off (cc_contract_round never uses it).  With cc_tuning.tail >= 2
+ * the rounds that fit the hashed duplicate drop run instead in one persistent cooperative
+ * launch (fresh contexts too), timed as "fused_rounds", with in_graph = 2 and the same
+ * conditions. */
 
 typedef struct {
     uint64_t seed;       /* priority seed (round keys derive from it as specified above) */
@@ -145,7 +148,8 @@ typedef struct {
 /* Statistics of one round (all counts exact). */
 typedef struct {
     int32_t round;        /* r, from 0 */
-    int32_t in_graph;     /* 1 when the round ran inside a captured tail (see cc_run) */
+    int32_t in_graph;     /* 1 when the round ran inside a captured tail (see cc_run), 2 inside the
+                             persistent launch (cc_tuning.tail) */
     int64_t n_active;     /* nodes with at least one loop-free edge in this round */
     int64_t m_in;         /* records read: the raw input count in round 0, |E_r| after */
     int64_t m_survive;    /* records whose two endpoints get different parents (repeats counted) */
@@ -208,7 +212,15 @@ typedef struct {
     int32_t round0_sort;      /* how round 0 orders its keys for the duplicate drop: 1 (0: default)
                                  LSD radix passes; 2 two levels of buckets cut at splitters drawn
                                  from the keys, then each bucket sorted in LDS */
-    int32_t reserved;         /* must be 0 */
+    int32_t tail;             /* cc_run's rounds >= 1 once at most 2^22 records remain: 1 (0: default)
+                                 a launch sequence per round (replayed from a captured graph on a
+                                 reused context); 2, 3, 4: all of them in one persistent cooperative
+                                 launch of 1, 2 or 4 workgroups per compute unit (at most what
+                                 stays resident), the steps of a round separated by grid-wide
+                                 barriers, one readback in all; its rounds report in_graph = 2.
+                                 LocalContraction and one-hop rules without CC_EAGER,
+                                 CC_EXPLICIT_PRIO, CC_RECORD_ROUNDS or CC_MERGE_TO_LARGE (otherwise
+                                 the default applies) */
 } cc_tuning;
 
 /*

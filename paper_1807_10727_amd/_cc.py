@@ -55,11 +55,11 @@ class cc_round_stats(ctypes.Structure):
 
 
 TUNING_KNOBS = ("round0", "blocks_per_cu", "round0_key_sets", "scatter_waves", "row_pairs", "relabel_pairs",
-                "row_generation", "round0_sort")
+                "row_generation", "round0_sort", "tail")
 
 
 class cc_tuning(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_int32) for k in TUNING_KNOBS] + [("reserved", ctypes.c_int32)]
+    _fields_ = [(k, ctypes.c_int32) for k in TUNING_KNOBS]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in TUNING_KNOBS}
@@ -200,10 +200,11 @@ def cc_reset(ctx, seed: int) -> None:
 
 
 def cc_set_tuning(ctx, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1, scatter_waves: int = 0,
-                  row_pairs: int = 0, relabel_pairs: int = 0, row_generation: int = 0, round0_sort: int = 0) -> None:
+                  row_pairs: int = 0, relabel_pairs: int = 0, row_generation: int = 0, round0_sort: int = 0,
+                  tail: int = 0) -> None:
     """Knobs of include/cc.h's cc_tuning; 0 keeps a knob's default (round0: the current form)."""
     t = cc_tuning(int(round0), int(blocks_per_cu), int(round0_key_sets), int(scatter_waves), int(row_pairs),
-                  int(relabel_pairs), int(row_generation), int(round0_sort), 0)
+                  int(relabel_pairs), int(row_generation), int(round0_sort), int(tail))
     _check(ctx, _lib.cc_set_tuning(ctx, ctypes.byref(t)))
 
 

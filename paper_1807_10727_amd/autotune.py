@@ -125,6 +125,8 @@ SOLVER_SPACE = {
     "relabel_pairs": [2, 1, 4],
     "row_generation": [1, 2, -1],
     "round0_sort": [1, 2],             # LSD radix passes, sampled buckets
+    "tail": [1, 2, 3],                 # small rounds: launch sequences, one persistent launch
+                                       # (1 or 2 workgroups per compute unit)
 }
 
 

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcc.so")
-SOURCES = ["lc_kernels.hip", "lc_sort.hip", "lc_bucket.hip", "lc_tiled.hip", "lc_variants.hip", "lc_engine.hip",
-           "lc_batch.hip", "lc_serve.hip"]
+SOURCES = ["lc_kernels.hip", "lc_sort.hip", "lc_bucket.hip", "lc_fused.hip", "lc_tiled.hip", "lc_variants.hip",
+           "lc_engine.hip", "lc_batch.hip", "lc_serve.hip"]
 ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950")
 
 

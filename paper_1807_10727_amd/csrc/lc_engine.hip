@@ -35,7 +35,8 @@ const char *const kFamilyNames[kFamilies] = {
     "relabel_round0", "relabel",  "sort_hist", "sort_scan",   "sort_scatter", "unique", "node_scan",
     "nodes",       "map",         "round_end",   "compose",   "flatten",
     "part_a_hist", "part_a_scatter", "part_b_hist", "part_b_scatter", "part_scan", "min1_tiled", "min2_tiled",
-    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter", "bucket_sort"};
+    "relabel_tiled", "tail_graph", "uf_finish", "hash_dedup", "merge_large", "part_rows_hist", "part_rows_scatter", "bucket_sort",
+    "fused_rounds"};
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -553,6 +554,7 @@ cc_status ctx_labels_enqueue(cc_ctx *c, void *d_labels) {
 namespace {
 
 cc_status round_once(cc_ctx *c, cc_round_stats *out);
+cc_status adopt_device_rounds(cc_ctx *c, int in_graph);
 
 constexpr int kTailRounds = 8;                 // rounds per captured tail
 constexpr int64_t kTailMaxRecords = 1 << 22;   // remaining graph small enough for a tail
@@ -642,6 +644,13 @@ cc_status run_tail(cc_ctx *c) {
     c->ev_end(ev);
     if (!c->hip_ok(e, "graph launch")) return hip_status(c);
     if (!c->read_state()) return hip_status(c);
+    return adopt_device_rounds(c, 1);
+}
+
+// Statistics of the rounds [c->next_round, st.rounds_active) that ran on the device without
+// a readback of their own (a captured tail or the persistent launch), and the host's view of
+// the state after them.
+cc_status adopt_device_rounds(cc_ctx *c, int in_graph) {
     const RoundState &st = *c->h_st;
     if (st.err & 1u) return fail(c, CC_E_INPUT, "an edge record names a vertex outside [0, n_vertices)");
     if (st.err & ~1u) return fail(c, CC_E_STATE, "internal consistency check failed on the device");
@@ -649,7 +658,7 @@ cc_status run_tail(cc_ctx *c) {
     for (int r = c->next_round; r < end; ++r) {
         cc_round_stats s{};
         s.round = r;
-        s.in_graph = 1;
+        s.in_graph = in_graph;
         s.n_active = (int64_t)st.rstats[r][1];
         s.m_in = (int64_t)st.rstats[r][2];
         s.m_survive = (int64_t)st.rstats[r][3];
@@ -667,6 +676,37 @@ cc_status run_tail(cc_ctx *c) {
     c->m_cur = (int64_t)st.m_cur;
     c->done = st.m_cur == 0;
     return c->done ? CC_DONE : CC_OK;
+}
+
+bool fused_wanted(const cc_ctx *c) {
+    return c->tail >= 2 && !c->fused_unavailable && c->variant != kVarTree &&
+           !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE)) &&
+           c->o.max_rounds == 0 && c->finish_edges == 0 && c->next_round >= 1 && c->next_round < kStatRounds &&
+           !c->done && c->m_cur > 0 && c->m_cur <= kHashMaxRecords && 2 * c->m_cur + 1 <= c->w.kcap;
+}
+
+// The remaining small rounds in one persistent launch and one readback.  Its rounds end when
+// the graph is empty or the next round does not fit the launch (then the loop of cc_run goes
+// on with the other paths); a device that cannot keep the grid resident turns the launch off
+// for this context.
+cc_status run_fused(cc_ctx *c) {
+    const int64_t cap = std::max<int64_t>(c->g.n_vertices, 1);
+    if ((c->host_levels >= kMaxLevels || c->host_map_used + c->n_cur > cap) && !c->flatten()) return hip_status(c);
+    const int before = c->next_round;
+    const bool ev = c->ev_begin(kFusedRounds);
+    const hipError_t e =
+        launch_fused_rounds(c->w, c->variant == kVarOneHop, 1 << (c->tail - 2), c->cus, c->stream);
+    c->ev_end(ev);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        c->fused_unavailable = true;
+        return round_once(c, nullptr);
+    }
+    if (!c->hip_ok(e, "persistent rounds")) return hip_status(c);
+    if (!c->read_state()) return hip_status(c);
+    const cc_status s = adopt_device_rounds(c, 2);
+    if (s == CC_OK && c->next_round == before) return round_once(c, nullptr);   // nothing fitted
+    return s;
 }
 
 // one round, synchronously; returns CC_OK, CC_DONE or an error
@@ -830,7 +870,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     if (t->round0 < 0 || t->round0 > 3 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
         (t->round0_key_sets != 0 && t->round0_key_sets != 1) || !one_of(t->scatter_waves, 2, 3, 4) ||
         !one_of(t->row_pairs, 2, 4, 8) || !one_of(t->relabel_pairs, 1, 2, 4) || t->row_generation < -1 ||
-        t->row_generation > 8 || t->round0_sort < 0 || t->round0_sort > 2 || t->reserved != 0)
+        t->row_generation > 8 || t->round0_sort < 0 || t->round0_sort > 2 || t->tail < 0 || t->tail > 4)
         return reject(c, CC_E_ARG, "tuning value out of range");
     const bool tiled = t->round0 == 0 ? c->tiled : t->round0 >= 2;
     const bool rows = t->round0 == 0 ? c->tiled_rows : t->round0 == 3;
@@ -850,6 +890,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     c->relabel_pairs = t->relabel_pairs ? t->relabel_pairs : LC_TRELABEL_PAIRS;
     c->row_generation = t->row_generation ? t->row_generation : 1;
     c->round0_sort = t->round0_sort ? t->round0_sort : 1;
+    c->tail = t->tail ? t->tail : 1;
     drop_tails(c);   // captured with the previous grid sizes and layout
     if (!c->ws) return CC_OK;
     plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)c->ws, &c->w, ws_extras(c->o.flags));
@@ -867,7 +908,7 @@ cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
     t->relabel_pairs = c->relabel_pairs;
     t->row_generation = c->row_generation;
     t->round0_sort = c->round0_sort;
-    t->reserved = 0;
+    t->tail = c->tail;
     return CC_OK;
 }
 
@@ -888,7 +929,10 @@ cc_status cc_run(cc_ctx *c, int32_t *rounds) {
     if (!c) return CC_E_ARG;
     for (;;) {
         if (c->o.max_rounds > 0 && c->next_round >= c->o.max_rounds) break;
-        cc_status s = finish_wanted(c) ? run_finish(c) : tail_wanted(c) ? run_tail(c) : round_once(c, nullptr);
+        cc_status s = finish_wanted(c)  ? run_finish(c)
+                      : fused_wanted(c) ? run_fused(c)
+                      : tail_wanted(c)  ? run_tail(c)
+                                        : round_once(c, nullptr);
         if (s == CC_DONE) break;
         if (s != CC_OK) return s;
     }

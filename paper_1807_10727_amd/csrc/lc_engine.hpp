@@ -16,7 +16,7 @@ enum Family {
     kRoundBegin = 0, kMin1In, kMin1, kMin2In, kMin2, kParent, kLabelRanks, kRelabelIn, kRelabel, kSortHist,
     kSortScan, kSortScatter, kUnique, kNodeScan, kNodes, kMap, kRoundEnd, kCompose, kFlatten,
     kPartAHist, kPartAScatter, kPartBHist, kPartBScatter, kPartScan, kMin1Tiled, kMin2Tiled, kRelabelTiled,
-    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kPartRowsHist, kPartRowsScatter, kBucketSort, kFamilies
+    kTailGraph, kUfFinish, kHashDedup, kMergeLarge, kPartRowsHist, kPartRowsScatter, kBucketSort, kFusedRounds, kFamilies
 };
 
 // how a round chooses its labels (cc_options.flags CC_TREE, CC_ONE_HOP)
@@ -67,6 +67,8 @@ struct Engine {
     int relabel_pairs = LC_TRELABEL_PAIRS; // tuning: tiled relabel, record pairs per thread
     int row_generation = 1;                // tuning: gathering row passes, rows per CU a launch (-1 all)
     int round0_sort = 1;                   // tuning: round 0's duplicate drop, 1 radix passes, 2 sampled buckets
+    int tail = 1;                          // tuning: small rounds, 1 a launch sequence each, 2..4 one
+                                           // persistent launch of 1 << (tail - 2) workgroups per CU
     void *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state
@@ -125,6 +127,7 @@ struct cc_ctx : public lc::Engine {
     int32_t last_graph_round = -1;          // last round run inside a captured tail
     int64_t solves_done = 0;                // solves that cc_run finished on this context
     int64_t finish_edges = 0;               // union-find finish threshold (0: off)
+    bool fused_unavailable = false;         // the device cannot keep the persistent grid resident
     bool finished = false;                  // this solve ended with the union-find finish
     // captured tails of rounds (cc_run), replayed while the rounded-up sizes match
     struct Tail {

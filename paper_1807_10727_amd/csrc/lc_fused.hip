@@ -1,0 +1,119 @@
+// Whole small rounds in one persistent launch.
+//
+// Once the remaining graph is small (rounds >= 1 with at most kHashMaxRecords records), a
+// round costs far more in launches than in work: it is about seventeen dependent kernels of a
+// few microseconds each (Section 3's phase: one-hop minimum, two-hop minimum, parents, label
+// map, relabel, duplicate drop, next node set and map), and each waits for the one before.
+// Here a single cooperative launch (every workgroup resident at once) runs round after round.
+// Each step is the same device body that its own kernel runs (lc_steps.hpp); where a kernel
+// boundary used to order two steps, a grid-wide barrier does: a step that reads what other
+// workgroups wrote in the step before (m1 before the two-hop pass, the parents before the
+// label map, and so on) starts only after every workgroup has finished that step.  Steps that
+// touch disjoint data share a phase (the label ranks and the key width; the next node set,
+// the per-round map and the write of the kept edges).
+//
+// Every workgroup reads the round state at the top of the loop, after the barrier that ended
+// the previous round, so all of them take the same decision.  The launch ends when no edge is
+// left, or when the next round does not fit it (more records than the hashed drop takes, no
+// room for another per-round map, the statistics table full, an error flagged); the host then
+// reads the state once and goes on with separate launches if edges remain.  The loop runs at
+// most kStatRounds rounds in all, so every workgroup leaves it.
+
+#include <hip/hip_cooperative_groups.h>
+
+#include "lc_steps.hpp"
+
+namespace lc {
+
+namespace {
+
+// Whether the next round runs inside this launch (the host's conditions for a hashed round,
+// evaluated on the device state).
+__device__ inline bool next_round_fits(const Work &w, const RoundState *st) {
+    const uint64_t m = st->m_cur, n = st->n_cur;
+    return st->err == 0 && st->round >= 1 && st->round < kStatRounds && m > 0 && m <= (uint64_t)kHashMaxRecords &&
+           2 * m + 1 <= (uint64_t)w.kcap && st->levels < kMaxLevels && st->map_off + n <= st->map_cap;
+}
+
+// Bit map with prefix counts of byte flags (label map or node map), as launch_map_scan builds
+// it: one workgroup for small counts, else count, scan and write phases.  `extra` runs on
+// workgroup 0 in the first phase (work of the same phase that touches other data).
+template <class Extra>
+__device__ inline void flag_map(cooperative_groups::grid_group &grid, bool single, const uint8_t *f, const u64c *n,
+                                uint32_t *map, u64c *total, uint32_t *partials, Extra extra) {
+    if (single) {
+        // the one-workgroup scan on the last workgroup, so that `extra` runs beside it
+        if (blockIdx.x == 0) extra();
+        if (blockIdx.x == gridDim.x - 1) step_flags_single(f, n, map, total);
+        return;
+    }
+    step_flags_reduce(f, n, partials);
+    if (blockIdx.x == 0) extra();
+    grid.sync();
+    if (blockIdx.x == 0) step_scan_single(partials, n, 32 * kThreads, total);
+    grid.sync();
+    step_flags_down(f, n, partials, map);
+}
+
+template <bool kOneHop>
+__global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work w, PrioCtx pc) {
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    RoundState *st = w.st;
+    auto none = [] {};
+    while (next_round_fits(w, st)) {
+        const int r = st->round;
+        const bool single = st->n_cur <= (u64c)kSmallFlagNodes;
+        const uint32_t *names = w.names[r & 1];
+        step_round_begin<true>(w, names, nullptr);
+        grid.sync();
+        step_min1_seeded(rd, w);
+        grid.sync();
+        if (!kOneHop) {
+            step_min2(rd, w);
+            grid.sync();
+        }
+        step_parent<false, false>(w, pc, nullptr, kOneHop ? 0 : 1);
+        grid.sync();
+        flag_map(grid, single, w.is_label, &st->n_cur, w.lmap, &st->n_labels, w.partials, none);
+        grid.sync();
+        step_rank_parents(w);
+        if (blockIdx.x == 0 && threadIdx.x == 0) step_plan_blocks(w);
+        grid.sync();
+        step_relabel(rd, w);
+        grid.sync();
+        step_hash_clear(w, 0);
+        grid.sync();
+        step_hash_insert(w);
+        grid.sync();
+        step_hash_count(w);
+        grid.sync();
+        // the kept keys' tile offsets (and the next round's record count) beside the node map
+        flag_map(grid, single, w.has_edge, &st->n_labels, w.nmap, &st->n_next, w.partials,
+                 [&] { step_scan_single(w.tile_cnt, &st->aux_n, 0, &st->m_next); });
+        grid.sync();
+        step_nodes<false, false>(w, names, w.names[(r + 1) & 1], nullptr, nullptr);
+        step_map<false>(w, names);
+        step_hash_write(w);
+        grid.sync();
+        if (blockIdx.x == 0 && threadIdx.x == 0) step_round_end<false>(w, kDedupHash);
+        grid.sync();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fused_rounds(const Work &w, bool one_hop, int per_cu, int cus, hipStream_t s) {
+    void (*kern)(ReadInternal, Work, PrioCtx) = one_hop ? k_fused_rounds<true> : k_fused_rounds<false>;
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0);
+    if (e != hipSuccess) return e;
+    if (occ < 1) return hipErrorCooperativeLaunchTooLarge;
+    const int grid = cus * (per_cu < occ ? per_cu : occ);
+    ReadInternal rd(w);
+    Work wk = w;
+    PrioCtx pc{};
+    void *args[] = {&rd, &wk, &pc};
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kThreads), args, 0, s);
+}
+
+}  // namespace lc

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <functional>
+#include <tuple>
 #include <type_traits>
 #include <utility>
 
@@ -80,6 +81,10 @@ extern thread_local dim3 t_block_idx, t_block_dim, t_grid_dim;
 uint64_t wave_op(int op, uint64_t val, int arg, int width, const char *file, int line);
 void sync_threads();
 void run_grid(const std::function<void()> &item, dim3 grid, dim3 block);
+// A cooperative launch: every workgroup runs at once, each on a host thread of its own, so
+// that grid-wide barriers (cooperative_groups, hip_cooperative_groups.h) can complete.
+void run_grid_cooperative(const std::function<void()> &item, dim3 grid, dim3 block);
+void grid_sync();
 
 }  // namespace hipemu
 
@@ -202,6 +207,7 @@ typedef enum hipError_t {
     hipErrorInvalidValue = 1,
     hipErrorOutOfMemory = 2,
     hipErrorNotReady = 600,
+    hipErrorCooperativeLaunchTooLarge = 720,
     hipErrorUnknown = 999
 } hipError_t;
 
@@ -292,3 +298,37 @@ inline void hipemu_launch(F kern, dim3 grid, dim3 block, size_t shmem, hipStream
 }
 #define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
     hipemu_launch((kern), dim3(grid), dim3(block), (size_t)(shmem), (stream), ##__VA_ARGS__)
+
+// Workgroups of a kernel resident on one compute unit at once: the emulated device (4 compute
+// units) takes resident_per_cu() of any kernel, 4 unless HIPEMU_RESIDENT_PER_CU says otherwise
+// (0 models a kernel too large to keep even one workgroup resident), so a cooperative grid
+// larger than 4 times that fails as on the GPU.
+namespace hipemu {
+constexpr int kCus = 4;
+int resident_per_cu();
+}  // namespace hipemu
+template <typename F>
+inline hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *n, F, int block, size_t shmem) {
+    if (block <= 0 || block > 1024 || shmem > 160 * 1024) return hipErrorInvalidValue;
+    *n = hipemu::resident_per_cu();
+    return hipSuccess;
+}
+template <typename... A, size_t... I>
+inline std::tuple<typename std::decay<A>::type...> hipemu_unpack(void **args, std::index_sequence<I...>) {
+    return std::tuple<typename std::decay<A>::type...>(*(typename std::decay<A>::type *)args[I]...);
+}
+// hipLaunchCooperativeKernel(kernel, grid, block, argument pointers, dynamic LDS, stream): the
+// arguments are copied when the call is made, as a launch copies them.
+template <typename... A>
+inline hipError_t hipLaunchCooperativeKernel(void (*kern)(A...), dim3 grid, dim3 block, void **args, unsigned shmem,
+                                             hipStream_t s) {
+    (void)shmem;
+    if (grid.x == 0 || block.x == 0 || block.x > 1024) return hipErrorInvalidValue;
+    if ((size_t)grid.x * grid.y * grid.z > (size_t)hipemu::kCus * hipemu::resident_per_cu())
+        return hipErrorCooperativeLaunchTooLarge;
+    auto vals = hipemu_unpack<A...>(args, std::index_sequence_for<A...>{});
+    hipemu::submit(s, [=]() {
+        hipemu::run_grid_cooperative([=]() { std::apply(kern, vals); }, grid, block);
+    });
+    return hipSuccess;
+}

@@ -10,9 +10,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 extern "C" void hipemu_switch(void **save_sp, void *new_sp);
@@ -286,6 +288,88 @@ void run_grid(const std::function<void()> &body, dim3 grid, dim3 block) {
     g_group = nullptr;
 }
 
+namespace {
+
+// The barrier of one cooperative launch, shared by its workgroups' threads.
+struct GridBarrier {
+    std::mutex mu;
+    std::condition_variable cv;
+    size_t n = 0, arrived = 0;
+    uint64_t gen = 0;
+};
+thread_local GridBarrier *t_grid_barrier = nullptr;
+
+}  // namespace
+
+void run_grid_cooperative(const std::function<void()> &body, dim3 grid, dim3 block) {
+    if (g_group) die("a kernel launched from inside a kernel");
+    const size_t nb = (size_t)grid.x * grid.y * grid.z;
+    const size_t nt = (size_t)block.x * block.y * block.z;
+    GridBarrier bar;
+    bar.n = nb;
+    std::vector<std::thread> threads;
+    threads.reserve(nb);
+    for (size_t b = 0; b < nb; ++b) {
+        threads.emplace_back([&, b]() {
+            std::vector<char *> stacks(nt);
+            for (auto &p : stacks)
+                if (!(p = (char *)malloc(kStack))) die("out of memory for work-item stacks");
+            Group g;
+            g.body = &body;
+            g.fibers.resize(nt);
+            t_block_dim = block;
+            t_grid_dim = grid;
+            t_block_idx = dim3((uint32_t)(b % grid.x), (uint32_t)((b / grid.x) % grid.y),
+                               (uint32_t)(b / ((size_t)grid.x * grid.y)));
+            t_grid_barrier = &bar;
+            for (size_t i = 0; i < nt; ++i) {
+                Fiber &f = g.fibers[i];
+                f.item = Item{};
+                f.item.tid = dim3((uint32_t)(i % block.x), (uint32_t)((i / block.x) % block.y),
+                                  (uint32_t)(i / ((size_t)block.x * block.y)));
+                init_fiber(f, stacks[i]);
+            }
+            g_group = &g;
+            run_group(g);
+            g_group = nullptr;
+            t_grid_barrier = nullptr;
+            for (char *p : stacks) free(p);
+        });
+    }
+    for (auto &t : threads) t.join();
+}
+
+// Every work-item of the workgroup meets at a workgroup barrier; its first work-item then
+// waits for the other workgroups' first work-items, and a second workgroup barrier lets the
+// rest go on.  A workgroup that never arrives (it left the kernel, or waits at another
+// barrier) is reported instead of hanging the test.
+void grid_sync() {
+    GridBarrier *b = t_grid_barrier;
+    if (!b) die("a grid barrier outside a cooperative launch");
+    sync_threads();
+    const Item *it = current();
+    if (it->tid.x == 0 && it->tid.y == 0 && it->tid.z == 0) {
+        std::unique_lock<std::mutex> lk(b->mu);
+        const uint64_t gen = b->gen;
+        if (++b->arrived == b->n) {
+            b->arrived = 0;
+            ++b->gen;
+            b->cv.notify_all();
+        } else if (!b->cv.wait_for(lk, std::chrono::seconds(120), [&] { return b->gen != gen; })) {
+            die("grid barrier: not every workgroup arrived within 120 s");
+        }
+    }
+    sync_threads();
+}
+
+int resident_per_cu() {
+    static const int n = [] {
+        const char *v = getenv("HIPEMU_RESIDENT_PER_CU");
+        return v && *v ? atoi(v) : 4;
+    }();
+    return n;
+}
+
 void set_error(hipError_t e) { g_last_error = e; }
 
 }  // namespace hipemu
@@ -329,7 +413,7 @@ hipError_t hipGetDevice(int *d) {
 }
 hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t a, int) {
     // a small device keeps the emulated grids small: 4 compute units
-    *v = a == hipDeviceAttributeMultiprocessorCount ? 4 : 160 * 1024;
+    *v = a == hipDeviceAttributeMultiprocessorCount ? hipemu::kCus : 160 * 1024;
     return hipSuccess;
 }
 hipError_t hipFuncSetAttribute(const void *, hipFuncAttribute, int v) {

@@ -117,6 +117,100 @@ def test_emulated_captured_tails(cc):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
+def in_graph(cc, s, rounds):
+    return [cc.cc_get_round_stats(s.ctx, r, True)[-1] for r in range(rounds)]
+
+
+@pytest.mark.parametrize("tail", [2, 3, 4])
+@pytest.mark.parametrize("rule", ["local", "one_hop"])
+def test_emulated_persistent_rounds(cc, tail, rule):
+    """cc_tuning.tail >= 2: the rounds after round 0 small enough for the hashed duplicate drop
+    run inside one cooperative launch, whose
+    workgroups the emulation runs on host threads of their own, meeting at real grid-wide
+    barriers.  Rounds, statistics and labels are the oracle's on a fresh and on a reused
+    context; those rounds report in_graph = 2, and their parents are not available."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=10, variant=rule)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=10, flags=RULES[rule]) as s:
+        s.set_tuning(tail=tail)
+        assert s.tuning["tail"] == tail
+        for _ in range(2):
+            rounds = s.run()
+            assert rounds == want.rounds
+            # round 0, and a round too large for the hashed duplicate drop, run on their own
+            ig = in_graph(cc, s, rounds)
+            first = ig.index(2)
+            assert first >= 1 and ig == [0] * first + [2] * (rounds - first)
+            assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+            np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+            with pytest.raises(cc.CCError) as e:
+                s.parents()
+            assert e.value.status == cc.CC_E_STATE
+            s.reset(10)
+        # back to the default: launch sequences per round (captured tails on this reused context)
+        s.set_tuning(tail=1)
+        rounds = s.run()
+        assert 2 not in in_graph(cc, s, rounds)
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=10, flags=RULES[rule] | cc.CC_EAGER) as s:
+        s.set_tuning(tail=tail)
+        rounds = s.run()
+        assert in_graph(cc, s, rounds) == [0] * rounds
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+@pytest.mark.parametrize("rule,seed,launches", [("local", 3, 1), ("one_hop", 22, 2)])
+def test_emulated_persistent_rounds_large(cc, rule, seed, launches):
+    """About a million path vertices.  LocalContraction: round 1 has more than 2^18 nodes, so
+    the label and node maps take the count, scan and write phases with grid-wide barriers
+    between them instead of one workgroup.  One-hop rule at this seed: the rounds' nodes add up
+    to more than the per-round map arena holds, so the launch stops before the round that
+    would overflow it, the host folds the maps, and a second launch finishes the solve."""
+    g = graphgen.er_with_paths(0xB16, 1 << 12, 1 << 13, 1000, 1000)
+    want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
+    assert want.stats[1][1] > 1 << 18
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=seed, flags=RULES[rule] | cc.CC_PROFILE) as s:
+        s.set_tuning(tail=2)
+        rounds = s.run()
+        assert rounds == want.rounds
+        ig = in_graph(cc, s, rounds)
+        assert ig[0] == 0 and ig[-1] == 2 and (rule != "local" or ig[1:] == [2] * (rounds - 1))
+        assert cc.cc_kernel_times(s.ctx)["fused_rounds"][1] == launches
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
+FALLBACK_CHECK = r"""
+import sys
+sys.path[:0] = [%r, %r]
+import numpy as np, graphgen, oracle, hipemu
+cc = hipemu.binding()
+g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+want = oracle.run(g.n, g.src, g.dst, seed=10)
+with hipemu.Solver(g.n, hipemu.device(g.src, np.int32), hipemu.device(g.dst, np.int32), seed=10) as s:
+    s.set_tuning(tail=4)
+    r = s.run()
+    ok = r == want.rounds and [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats] and \
+        np.array_equal(s.labels().astype(np.uint32), want.labels)
+    print("OK", ok, [cc.cc_get_round_stats(s.ctx, k, True)[-1] for k in range(r)])
+"""
+
+
+def test_emulated_persistent_rounds_fall_back(cc):
+    """A device that cannot keep even one workgroup of the persistent kernel resident per
+    compute unit refuses the cooperative launch; the context then runs the rounds one launch
+    sequence each, with the same results."""
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, HIPEMU_RESIDENT_PER_CU="0")
+    proc = subprocess.run([sys.executable, "-c", FALLBACK_CHECK % (os.path.dirname(here), here)], env=env,
+                          stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=600)
+    assert proc.returncode == 0, proc.stderr[-2000:]
+    assert "OK True [0, 0, 0" in proc.stdout and "2" not in proc.stdout.split("OK True")[1], proc.stdout
+
+
 def test_emulated_union_find_finish_and_canonical(cc):
     g = graphgen.er_with_paths(0xF1, 5000, 9000, 20, 100)
     want = oracle.run(g.n, g.src, g.dst, seed=5, finish_edges=300)
@@ -600,6 +694,7 @@ rmat = graphgen.Graph(1 << 14, *graphgen.rmat(3, 14, 16 << 14))
 cases = [("rmat", rmat, cc.CC_ROUND0_TILED, 0, {}),
          ("rmat rows buckets", rmat, cc.CC_ROUND0_TILED, 0, {"round0": 3, "round0_sort": 2}),
          ("paths", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0, {}),
+         ("paths persistent", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0, {"tail": 3}),
          ("mtl", graphgen.er_with_paths(10, 3000, 9000, 20, 100), cc.CC_ROUND0_TILED, cc.CC_MERGE_TO_LARGE, {})]
 for name, g, flags, extra, knobs in cases:
     want = oracle.run(g.n, g.src, g.dst, seed=5, variant="merge_to_large" if extra else "local", alphas=[3] if extra else None)

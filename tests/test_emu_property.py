@@ -3,7 +3,8 @@
 Hypothesis draws the graph (size, density, a power-law or uniform mix, repeated records,
 loops, isolated ids), the seed, the input layout, the label rule (with MergeToLarge's
 parameters) and the solver's knobs (round-0
-form, key sets, the order of round 0's keys, kernel builds, grid size); every draw must give
+form, key sets, the order of round 0's keys, kernel builds, grid size, the persistent launch of
+the small rounds); every draw must give
 the oracle's round count, statistics and labels.  The draws are derandomised, so a failure
 is reproducible, and sized so that the whole test takes about a minute.
 """
@@ -57,6 +58,7 @@ KNOBS = st.fixed_dictionaries({
     "relabel_pairs": st.sampled_from([1, 2, 4]),
     "row_generation": st.sampled_from([-1, 1, 2]),
     "blocks_per_cu": st.sampled_from([1, 8]),
+    "tail": st.sampled_from([1, 2, 4]),
 })
 
 

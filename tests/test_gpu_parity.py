@@ -418,6 +418,40 @@ def test_captured_tail_matches_eager_and_oracle(lc):
         assert eager.edges().numel() == 0   # an eager solve that ran to the end left no edge
 
 
+@pytest.mark.parametrize("tail", [2, 3, 4])
+@pytest.mark.parametrize("rule", ["local", "one_hop"])
+def test_persistent_rounds_match_oracle(lc, tail, rule):
+    """cc_tuning.tail >= 2: the rounds after round 0 run in one cooperative launch with
+    grid-wide barriers between their steps.  The oracle's rounds, statistics and labels, on a
+    fresh and a reused context with several seeds, on a graph whose round 1 has more than 2^18
+    nodes (the label and node maps' multi-phase form) and whose later rounds have fewer (the
+    one-workgroup form); those rounds report in_graph = 2 and are timed as "fused_rounds"."""
+    g = graphgen.er_with_paths(0xB16, 1 << 12, 1 << 13, 1000, 1000)
+    s_t, d_t, _ = to_device(g)
+    flags = {"local": 0, "one_hop": lc.CC_ONE_HOP}[rule]
+    with lc.Solver(g.n, s_t, d_t, seed=1, flags=flags | lc.CC_PROFILE) as s:
+        s.set_tuning(tail=tail)
+        assert s.tuning["tail"] == tail
+        for seed in (21, 22, 21):
+            s.reset(seed)
+            r = s.run()
+            want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
+            assert want.stats[1][1] > 1 << 18
+            assert r == want.rounds
+            assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+            ig = [lc.cc_get_round_stats(s.ctx, k, True)[-1] for k in range(r)]
+            first = ig.index(2)   # before it: round 0, and rounds too large for the hashed drop
+            assert ig == [0] * first + [2] * (r - first), ig
+            if rule == "local":
+                assert first == 1   # round 1, of more than 2^18 nodes, inside the launch
+            # one launch, or more where the per-round maps fill their arena (the launch stops,
+            # the host folds the maps and launches again: one-hop, seed 22)
+            assert s.kernel_times()["fused_rounds"][1] >= 1
+            lab = s.labels()
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(lab.cpu().numpy().view(np.uint32), want.labels)
+
+
 # --- the largest vertex ids ---------------------------------------------------------------
 
 @pytest.mark.parametrize("variant", ["local", "tree", "one_hop"])
