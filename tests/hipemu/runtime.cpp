@@ -240,25 +240,12 @@ void sync_threads() {
     yield();
 }
 
-void run_grid(const std::function<void()> &body, dim3 grid, dim3 block) {
-    if (g_group) die("a kernel launched from inside a kernel");
-    const size_t nt = (size_t)block.x * block.y * block.z;
-    Group g;
-    g.body = &body;
-    g.fibers.resize(nt);
-    while (g_stacks.size() < nt) {
-        char *s = (char *)malloc(kStack);
-        if (!s) die("out of memory for work-item stacks");
-        g_stacks.push_back(s);
-    }
-    t_block_dim = block;
-    t_grid_dim = grid;
-    g_group = &g;
-    // Workgroups run one after another, in an order set by HIPEMU_BLOCK_ORDER: "forward"
-    // (default), "reverse", or a number seeding a shuffle.  Results that depend on the order
-    // in which workgroups run (which the GPU does not fix) show up as differences between
-    // orders.
-    const size_t nb = (size_t)grid.x * grid.y * grid.z;
+namespace {
+
+// Workgroups run in an order set by HIPEMU_BLOCK_ORDER: "forward" (default), "reverse", or a
+// number seeding a shuffle.  Results that depend on the order in which workgroups run (which
+// the GPU does not fix) show up as differences between orders.
+std::vector<size_t> block_order(size_t nb) {
     std::vector<size_t> order(nb);
     for (size_t b = 0; b < nb; ++b) order[b] = b;
     const char *mode = getenv("HIPEMU_BLOCK_ORDER");
@@ -273,19 +260,125 @@ void run_grid(const std::function<void()> &body, dim3 grid, dim3 block) {
             std::swap(order[b - 1], order[(size_t)(x % b)]);
         }
     }
-    for (size_t b : order) {
-        t_block_idx = dim3((uint32_t)(b % grid.x), (uint32_t)((b / grid.x) % grid.y),
-                           (uint32_t)(b / ((size_t)grid.x * grid.y)));
-        for (size_t i = 0; i < nt; ++i) {
-            Fiber &f = g.fibers[i];
-            f.item = Item{};
-            f.item.tid = dim3((uint32_t)(i % block.x), (uint32_t)((i / block.x) % block.y),
-                              (uint32_t)(i / ((size_t)block.x * block.y)));
-            init_fiber(f, g_stacks[i]);
-        }
-        run_group(g);
+    return order;
+}
+
+// Workgroup b of a launch, all its work-items on this thread (g holds the fibers).
+void run_block(Group &g, size_t b, dim3 grid, dim3 block) {
+    const size_t nt = (size_t)block.x * block.y * block.z;
+    while (g_stacks.size() < nt) {
+        char *st = (char *)malloc(kStack);
+        if (!st) die("out of memory for work-item stacks");
+        g_stacks.push_back(st);
     }
+    t_block_idx = dim3((uint32_t)(b % grid.x), (uint32_t)((b / grid.x) % grid.y),
+                       (uint32_t)(b / ((size_t)grid.x * grid.y)));
+    for (size_t i = 0; i < nt; ++i) {
+        Fiber &f = g.fibers[i];
+        f.item = Item{};
+        f.item.tid = dim3((uint32_t)(i % block.x), (uint32_t)((i / block.x) % block.y),
+                          (uint32_t)(i / ((size_t)block.x * block.y)));
+        init_fiber(f, g_stacks[i]);
+    }
+    run_group(g);
+}
+
+// One launch's workgroups, taken in `order` by whichever thread is free.
+struct Job {
+    const std::function<void()> *body;
+    dim3 grid, block;
+    const std::vector<size_t> *order;
+    std::atomic<size_t> next{0};
+};
+
+void work_on(Job &job) {
+    const size_t nt = (size_t)job.block.x * job.block.y * job.block.z;
+    Group g;
+    g.body = job.body;
+    g.fibers.resize(nt);
+    t_block_dim = job.block;
+    t_grid_dim = job.grid;
+    g_group = &g;
+    for (size_t i; (i = job.next.fetch_add(1)) < job.order->size();) run_block(g, (*job.order)[i], job.grid, job.block);
     g_group = nullptr;
+}
+
+// HIPEMU_THREADS=n (n > 1) runs the workgroups of every launch on n host threads at once (the
+// caller and n - 1 workers), so that workgroups that race on global memory without the
+// atomics or the ordering the code relies on can give other results than one after another.
+// Each thread has its own LDS and work-item stacks.
+class Pool {
+  public:
+    explicit Pool(int n) {
+        for (int i = 0; i + 1 < n; ++i) std::thread([this] { loop(); }).detach();
+        workers_ = n - 1;
+    }
+    void run(Job &job) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &job;
+            active_ = workers_;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work_on(job);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return active_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            Job *job;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                job = job_;
+            }
+            work_on(*job);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--active_ == 0) done_.notify_all();
+        }
+    }
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    Job *job_ = nullptr;
+    int workers_ = 0, active_ = 0;
+    uint64_t gen_ = 0;
+};
+
+int pool_threads() {
+    static const int n = [] {
+        const char *v = getenv("HIPEMU_THREADS");
+        return v && *v ? std::max(1, atoi(v)) : 1;
+    }();
+    return n;
+}
+
+std::mutex g_pool_mu;   // launches from several host threads (the server's) take turns
+
+}  // namespace
+
+void run_grid(const std::function<void()> &body, dim3 grid, dim3 block) {
+    if (g_group) die("a kernel launched from inside a kernel");
+    const size_t nb = (size_t)grid.x * grid.y * grid.z;
+    const std::vector<size_t> order = block_order(nb);
+    Job job;
+    job.body = &body;
+    job.grid = grid;
+    job.block = block;
+    job.order = &order;
+    const int nthreads = pool_threads();
+    if (nthreads <= 1 || nb <= 1) {
+        work_on(job);
+        return;
+    }
+    static Pool *pool = new Pool(nthreads);   // kept for the process
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    pool->run(job);
 }
 
 namespace {

@@ -719,13 +719,15 @@ print("FAILS", fails)
 """
 
 
-@pytest.mark.parametrize("order", ["reverse", "12345", "777", "forward/items reversed"])
+@pytest.mark.parametrize("order", ["reverse", "12345", "777", "forward/items reversed", "4242/threads"])
 def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
     """The same solves with the workgroups of every launch run in reverse or shuffled order:
     atomics, cursors and the relabel's key sets then see other interleavings, and the results
-    must not change.  The last case keeps the workgroups in order but runs the work-items of
+    must not change.  "items reversed" keeps the workgroups in order but runs the work-items of
     each one last to first between synchronisation points, which would expose waves sharing
-    LDS or global words without a barrier between them."""
+    LDS or global words without a barrier between them.  "threads" runs the workgroups of
+    every launch on four host threads at once, so that workgroups really race on global
+    memory."""
     import os
     import subprocess
     import sys
@@ -734,6 +736,8 @@ def test_emulated_results_do_not_depend_on_workgroup_order(cc, order):
     env = dict(os.environ, HIPEMU_BLOCK_ORDER=order.split("/")[0])
     if order.endswith("items reversed"):
         env["HIPEMU_ITEM_ORDER"] = "reverse"
+    if order.endswith("threads"):
+        env["HIPEMU_THREADS"] = "4"
     proc = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                           text=True, timeout=600)
     assert proc.returncode == 0, proc.stderr[-2000:]
