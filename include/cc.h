@@ -221,6 +221,11 @@ typedef struct {
                                  LocalContraction and one-hop rules without CC_EAGER,
                                  CC_EXPLICIT_PRIO, CC_RECORD_ROUNDS or CC_MERGE_TO_LARGE (otherwise
                                  the default applies) */
+    int32_t radix_form;       /* the duplicate drop's LSD radix sorts: 1 (0: default) per digit a count
+                                 pass, a scan of the count table and a scatter; 2 one sweep: one
+                                 count pass for every digit at once, then per digit only the
+                                 scatter, each tile finding how many keys of each digit precede
+                                 it by decoupled look-back over the tiles before it */
 } cc_tuning;
 
 /*

@@ -74,11 +74,11 @@ class Solver:
 
     def set_tuning(self, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1, scatter_waves: int = 0,
                    row_pairs: int = 0, relabel_pairs: int = 0, row_generation: int = 0, round0_sort: int = 0,
-                   tail: int = 0) -> None:
+                   tail: int = 0, radix_form: int = 0) -> None:
         """Tuning knobs (include/cc.h, cc_tuning); resets the solve.  A tiled round 0 needs a
         workspace sized for it: the one this object allocated when the context chose it."""
         cc_set_tuning(self.ctx, round0, blocks_per_cu, round0_key_sets, scatter_waves, row_pairs, relabel_pairs,
-                      row_generation, round0_sort, tail)
+                      row_generation, round0_sort, tail, radix_form)
 
     @property
     def tuning(self) -> dict:

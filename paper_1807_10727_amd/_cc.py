@@ -55,7 +55,7 @@ class cc_round_stats(ctypes.Structure):
 
 
 TUNING_KNOBS = ("round0", "blocks_per_cu", "round0_key_sets", "scatter_waves", "row_pairs", "relabel_pairs",
-                "row_generation", "round0_sort", "tail")
+                "row_generation", "round0_sort", "tail", "radix_form")
 
 
 class cc_tuning(ctypes.Structure):
@@ -201,10 +201,10 @@ def cc_reset(ctx, seed: int) -> None:
 
 def cc_set_tuning(ctx, round0: int = 0, blocks_per_cu: int = 0, round0_key_sets: int = 1, scatter_waves: int = 0,
                   row_pairs: int = 0, relabel_pairs: int = 0, row_generation: int = 0, round0_sort: int = 0,
-                  tail: int = 0) -> None:
+                  tail: int = 0, radix_form: int = 0) -> None:
     """Knobs of include/cc.h's cc_tuning; 0 keeps a knob's default (round0: the current form)."""
     t = cc_tuning(int(round0), int(blocks_per_cu), int(round0_key_sets), int(scatter_waves), int(row_pairs),
-                  int(relabel_pairs), int(row_generation), int(round0_sort), int(tail))
+                  int(relabel_pairs), int(row_generation), int(round0_sort), int(tail), int(radix_form))
     _check(ctx, _lib.cc_set_tuning(ctx, ctypes.byref(t)))
 
 

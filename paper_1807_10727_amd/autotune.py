@@ -127,6 +127,7 @@ SOLVER_SPACE = {
     "round0_sort": [1, 2],             # LSD radix passes, sampled buckets
     "tail": [1, 2, 3],                 # small rounds: launch sequences, one persistent launch
                                        # (1 or 2 workgroups per compute unit)
+    "radix_form": [1, 2],              # radix passes: count, scan and scatter a digit; one sweep
 }
 
 

@@ -158,6 +158,16 @@ __device__ inline T block_excl_scan(T x, T *lds, T *total) {
 // tiles then read and write the same lines of per-tile tables (digit counts, offsets) from
 // one L2 instead of eight.
 constexpr int kXcds = 8;
+
+// Words that workgroups running at the same time hand to each other (the one-sweep radix
+// passes' look-back): atomic at device scope, so that a store on one XCD is seen by a load
+// on another without waiting for the kernel to end.
+__device__ inline uint32_t load_agent(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_agent(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ inline int64_t xcd_rank(int64_t b, int64_t g) {
     return g % kXcds ? b : (b % kXcds) * (g / kXcds) + b / kXcds;
 }

@@ -114,6 +114,8 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
         t.rec = (uint32_t *)take(4 * (size_t)t.rec_cap);
     }
     if (!batch) {
+        t.sweep = (uint32_t *)take(4 * (size_t)kSweepWords);
+        t.sweep_desc = (uint32_t *)take(4 * (size_t)kRadixMax * tiles);
         t.btab = (BucketTab *)take(sizeof(BucketTab) * 257);
         t.bseg = (uint64_t *)take(8 * 257);
         t.btile = (uint32_t *)take(4 * 257);
@@ -298,7 +300,15 @@ bool Engine::enqueue_round(int r, int64_t N, int64_t M, const PrioCtx &pc, int p
         }
         RUN(kBucketSort, launch_bucket(w, 7, grid_cap, stream));
     }
-    for (int p = 0; p < (dedup == kDedupHash || buckets ? 0 : passes); ++p) {
+    const bool sweep = radix_form == 2 && w.sweep && dedup != kDedupHash && !buckets && passes > 0 &&
+                       (uint64_t)M < kSweepMaxKeys;   // a round's keys never outnumber its records
+    if (sweep) {   // one count pass for every digit, then one scatter a digit (offsets by look-back)
+        RUN(kSortHist, launch_sort_pass(w, 0, 1, stream, 6, gated));
+        RUN(kSortHist, launch_sort_pass(w, 0, gt, stream, 7, gated));
+        for (int p = 0; p < passes; ++p)
+            RUN(kSortScatter, launch_sort_pass(w, p, gt_scatter, stream, 8, gated, scatter_waves));
+    }
+    for (int p = 0; p < (dedup == kDedupHash || buckets || sweep ? 0 : passes); ++p) {
         RUN(kSortHist, launch_sort_pass(w, p, gt, stream, 0, gated));
         if (small_sort) {
             RUN(kSortScan, launch_sort_pass(w, p, 1, stream, 5));
@@ -870,7 +880,8 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     if (t->round0 < 0 || t->round0 > 3 || t->blocks_per_cu < 0 || t->blocks_per_cu > 64 ||
         (t->round0_key_sets != 0 && t->round0_key_sets != 1) || !one_of(t->scatter_waves, 2, 3, 4) ||
         !one_of(t->row_pairs, 2, 4, 8) || !one_of(t->relabel_pairs, 1, 2, 4) || t->row_generation < -1 ||
-        t->row_generation > 8 || t->round0_sort < 0 || t->round0_sort > 2 || t->tail < 0 || t->tail > 4)
+        t->row_generation > 8 || t->round0_sort < 0 || t->round0_sort > 2 || t->tail < 0 || t->tail > 4 ||
+        t->radix_form < 0 || t->radix_form > 2)
         return reject(c, CC_E_ARG, "tuning value out of range");
     const bool tiled = t->round0 == 0 ? c->tiled : t->round0 >= 2;
     const bool rows = t->round0 == 0 ? c->tiled_rows : t->round0 == 3;
@@ -891,6 +902,7 @@ cc_status cc_set_tuning(cc_ctx *c, const cc_tuning *t) {
     c->row_generation = t->row_generation ? t->row_generation : 1;
     c->round0_sort = t->round0_sort ? t->round0_sort : 1;
     c->tail = t->tail ? t->tail : 1;
+    c->radix_form = t->radix_form ? t->radix_form : 1;
     drop_tails(c);   // captured with the previous grid sizes and layout
     if (!c->ws) return CC_OK;
     plan_workspace(c->g.n_vertices, c->g.n_edges, false, c->tiled, (char *)c->ws, &c->w, ws_extras(c->o.flags));
@@ -909,6 +921,7 @@ cc_status cc_get_tuning(const cc_ctx *c, cc_tuning *t) {
     t->row_generation = c->row_generation;
     t->round0_sort = c->round0_sort;
     t->tail = c->tail;
+    t->radix_form = c->radix_form;
     return CC_OK;
 }
 

@@ -69,6 +69,7 @@ struct Engine {
     int round0_sort = 1;                   // tuning: round 0's duplicate drop, 1 radix passes, 2 sampled buckets
     int tail = 1;                          // tuning: small rounds, 1 a launch sequence each, 2..4 one
                                            // persistent launch of 1 << (tail - 2) workgroups per CU
+    int radix_form = 1;                    // tuning: radix passes, 1 count/scan/scatter a digit, 2 one sweep
     void *ws = nullptr;
     size_t ws_bytes = 0, ws_need = 0;
     RoundState *h_st = nullptr;   // pinned host mirror of the device round state

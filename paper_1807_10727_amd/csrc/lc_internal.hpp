@@ -145,6 +145,11 @@ struct Work {
     uint32_t *mtl_size, *mtl_v, *mtl_cnt;   // [n0] each
     uint64_t *mtl_acc[2];                    // [n0] each
     uint32_t *slab_cnt;  // [slabs] relabel survivors per output slab
+    // one-sweep radix passes (single solves): digit totals of every pass, then a tile counter
+    // per pass ([kSweepWords]); the odd passes' look-back words ([kRadixMax * sort tiles]; the
+    // even passes use counts)
+    uint32_t *sweep;
+    uint32_t *sweep_desc;
     // sampled-bucket duplicate drop (single solves): the first level's table and one table per
     // first-level bucket; first-level bucket starts ([257], the last = keys) and first tiles of
     // the second level ([257], the last = its tile count)
@@ -176,6 +181,14 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kRadixMaxBits = LC_SORT_MAX_BITS;
 constexpr int kRadixMax = 1 << kRadixMaxBits;
 constexpr int kMaxPasses = 8;                      // 64-bit keys
+// One-sweep radix passes: a look-back word is empty, a tile's own count of a digit (below
+// 2^31), or kSweepPrefix with the count of that digit in the tile and all before it.
+constexpr uint32_t kSweepEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kSweepPrefix = 0x80000000u;
+constexpr int kSweepWords = kMaxPasses * kRadixMax + kMaxPasses;
+// A one-sweep sort of this many keys or more is flagged instead of run (its prefix words
+// could not hold the counts); the host gives such rounds (more records than that) the other form.
+constexpr uint64_t kSweepMaxKeys = 0x7FFFFFFFu;
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 constexpr int64_t kSmallScanEntries = 1 << 15;    // count tables scanned by one workgroup
 constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one workgroup
@@ -397,6 +410,9 @@ hipError_t launch_fused_rounds(const Work &w, bool one_hop, int per_cu, int cus,
 // parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);
+// stage 0 count pass, 1-3 scan of the count table (5: in one workgroup), 4 scatter; the
+// one-sweep form: 6 totals and tile counters zeroed (one workgroup), 7 the digit totals of
+// every pass, 8 the scatter of pass `pass` with its offsets found by look-back.
 // gated (this and the unique): skipped when the round's device-side choice was to hash
 // scatter_waves: the radix scatter build to launch (2, 3 or 4 waves per SIMD)
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated = false,

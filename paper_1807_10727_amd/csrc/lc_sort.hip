@@ -151,12 +151,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Work w, int pass, in
 // Waves per SIMD the scatter is compiled for: 3 (the default, LC_SCATTER_WAVES) trades a few
 // spilled words for a third more waves in flight than the unconstrained register count
 // allows (measured faster on the bench graph).  Builds for 2 and 4 waves exist for the tuner.
-template <int kWavesPerSimd>
+//
+// kSweep: the one-sweep form (cc_tuning.radix_form = 2).  No count pass or scan precedes the
+// scatter: every digit's start in the output is known from k_sweep_count, and a tile finds
+// how many keys of each digit the tiles before it hold by decoupled look-back.  Tiles are
+// numbered in the order workgroups take them (a counter per pass), so a tile only ever waits
+// for tiles that running workgroups already hold, whatever the grid.  Each tile publishes, per
+// digit, first its own count (an aggregate) and then, once its look-back is done, the count
+// of that digit in itself and every tile before it (an inclusive prefix, kSweepPrefix set).
+// The look-back of digit d walks back over the previous tiles' words, adding aggregates,
+// until it meets a prefix; a word still empty is polled again.  The words of a pass live in
+// one of two tables, and every tile of pass p empties its own words in the other table for
+// pass p + 1 (the count pass empties the first one).
+template <int kWavesPerSimd, bool kSweep>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd)))
 void k_sort_scatter(Work w, int pass, int gated) {
     RoundState *st = w.st;
     const int passes = npasses(st->nbits);
     if (pass >= passes || (gated && st->hash_slots != 0)) return;
+    if (kSweep && st->s_keys >= (u64c)kSweepMaxKeys) return;   // flagged by k_sweep_count
     int shift, width;
     pass_digit(st->nbits, pass, shift, width);
     const int nbins = 1 << width;
@@ -166,6 +179,8 @@ void k_sort_scatter(Work w, int pass, int gated) {
     const int src = sort_src(st->round, st->e_sel) ^ (pass & 1);
     const uint64_t *in = w.keys[src];
     uint64_t *out = w.keys[src ^ 1];
+    uint32_t *desc = (pass & 1) ? w.sweep_desc : w.counts;        // this pass's look-back words
+    uint32_t *desc_next = (pass & 1) ? w.counts : w.sweep_desc;   // the next pass's
 
     constexpr int kWaves = kSortThreads / kWave;
     constexpr int kPer = (kRadixMax + kSortThreads - 1) / kSortThreads;   // digits per thread at most
@@ -174,6 +189,8 @@ void k_sort_scatter(Work w, int pass, int gated) {
     __shared__ uint32_t dstart[kRadixMax];
     __shared__ uint32_t gofs[kRadixMax];
     __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t base[kSweep ? kRadixMax : 1];   // one sweep: each digit's start in the output
+    __shared__ int64_t s_tile;
 
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -181,15 +198,43 @@ void k_sort_scatter(Work w, int pass, int gated) {
     // thread t owns digits [t * per, (t + 1) * per) of this pass
     const int per = nbins > kSortThreads ? nbins / kSortThreads : 1;
 
-    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+    if (kSweep) {   // digit starts: exclusive prefix of the pass's digit totals
+        uint32_t c[kPer];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int d = threadIdx.x * per + q;
+            c[q] = (q < per && d < nbins) ? w.sweep[pass * kRadixMax + d] : 0u;
+            sum += c[q];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_scan<kSortThreads>(sum, lds, &total);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int d = threadIdx.x * per + q;
+            if (q < per && d < nbins) base[d] = run;
+            run += c[q];
+        }
+    }
+
+    int64_t tile = xcd_rank(blockIdx.x, gridDim.x);
+    for (;;) {
+        if (kSweep) {   // the next tile in the order workgroups ask for one
+            if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(&w.sweep[kMaxPasses * kRadixMax + pass], 1u);
+            __syncthreads();
+            tile = s_tile;
+        }
+        if (tile >= ntiles) break;
         const int tv = tl.valid(tile);
         // this tile's global digit offsets: loaded now, used after the ranking
         uint32_t my_gofs[kPer];
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
             const int d = threadIdx.x * per + q;
-            my_gofs[q] = (q < per && d < nbins) ? w.counts[(int64_t)d * ntiles + tile] : 0u;
+            my_gofs[q] = (!kSweep && q < per && d < nbins) ? w.counts[(int64_t)d * ntiles + tile] : 0u;
         }
+        if (kSweep)
+            for (int i = threadIdx.x; i < kRadixMax; i += kSortThreads) desc_next[tile * kRadixMax + i] = kSweepEmpty;
         for (int i = threadIdx.x; i < kWaves * kRadixMax; i += kSortThreads) (&wcnt[0][0])[i] = 0;
         __syncthreads();
 
@@ -237,6 +282,36 @@ void k_sort_scatter(Work w, int pass, int gated) {
                 tot[q] = run;
                 sum += run;
             }
+            if (kSweep) {
+                // publish this tile's own counts, then look back for the keys before it
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    const int d = threadIdx.x * per + q;
+                    if (q < per && d < nbins)
+                        store_agent(&desc[tile * kRadixMax + d], tile == 0 ? (kSweepPrefix | tot[q]) : tot[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    const int d = threadIdx.x * per + q;
+                    if (q < per && d < nbins && tile > 0) {
+                        uint32_t before = 0;
+                        for (int64_t j = tile - 1; j >= 0;) {
+                            const uint32_t v = load_agent(&desc[j * kRadixMax + d]);
+                            if (v == kSweepEmpty) {   // not published yet: poll again
+                                __builtin_amdgcn_s_sleep(1);
+                                continue;
+                            }
+                            before += v & ~kSweepPrefix;
+                            if (v & kSweepPrefix) break;
+                            --j;
+                        }
+                        store_agent(&desc[tile * kRadixMax + d], kSweepPrefix | (before + tot[q]));
+                        my_gofs[q] = base[d] + before;
+                    } else if (q < per && d < nbins) {
+                        my_gofs[q] = base[d];
+                    }
+                }
+            }
             uint32_t total;
             uint32_t ds = block_excl_scan<kSortThreads>(sum, lds, &total);
 #pragma unroll
@@ -270,7 +345,62 @@ void k_sort_scatter(Work w, int pass, int gated) {
             }
         }
         __syncthreads();
+        if (!kSweep) tile += gridDim.x;
     }
+}
+
+// One sweep, before the scatters: the digit totals of every pass from one read of the keys
+// (wave-aggregated LDS counts, one global add per digit and workgroup), and the first pass's
+// look-back words emptied.  k_sweep_reset zeroes the totals and the tile counters before it.
+__global__ __launch_bounds__(kSortThreads) void k_sweep_count(Work w, int gated) {
+    RoundState *st = w.st;
+    if (gated && st->hash_slots != 0) return;   // the round hashed
+    if (st->s_keys >= (u64c)kSweepMaxKeys) {      // a prefix word could not hold the counts
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 4u);
+        return;
+    }
+    const int nbits = st->nbits;
+    const int passes = npasses(nbits);
+    const Tiles tl = tiles_of(w, 0);
+    const uint64_t *in = w.keys[sort_src(st->round, st->e_sel)];
+    __shared__ uint32_t hist[kMaxPasses * kRadixMax];
+    for (int i = threadIdx.x; i < kMaxPasses * kRadixMax; i += kSortThreads) hist[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < tl.ntiles * kRadixMax;
+         i += (int64_t)gridDim.x * kSortThreads)
+        w.counts[i] = kSweepEmpty;
+    __syncthreads();
+    for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < tl.ntiles; tile += gridDim.x) {
+        const int tv = tl.valid(tile);
+        if (tv == 0) continue;   // uniform over the workgroup
+#pragma unroll 4
+        for (int j = 0; j < kSortItems; ++j) {
+            const int it = j * kSortThreads + threadIdx.x;
+            const bool valid = it < tv;
+            const uint64_t k = valid ? in[tile * kSortTile + it] : 0ull;
+            const uint64_t act = ballot(valid);
+            if (!act) continue;   // uniform over the wave
+            const int first = __ffsll((long long)act) - 1;
+            for (int p = 0; p < passes; ++p) {
+                int shift, width;
+                pass_digit(nbits, p, shift, width);
+                const uint32_t d = (uint32_t)(k >> shift) & ((1u << width) - 1u);
+                const uint32_t d0 = __shfl(d, first, kWave);
+                if (ballot(valid && d == d0) == act) {   // the whole wave in one digit: one add
+                    if (lane_id() == first) atomicAdd(&hist[p * kRadixMax + d0], (uint32_t)__popcll(act));
+                } else if (valid) {
+                    atomicAdd(&hist[p * kRadixMax + d], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < passes * kRadixMax; i += kSortThreads)
+        if (hist[i]) atomicAdd(&w.sweep[i], hist[i]);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sweep_reset(Work w, int gated) {
+    if (gated && w.st->hash_slots != 0) return;
+    for (int i = threadIdx.x; i < kSweepWords; i += kSortThreads) w.sweep[i] = 0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -443,6 +573,18 @@ hipError_t launch_scan_u32(uint32_t *data, uint32_t *partials, const u64c *n, u6
     return hipGetLastError();
 }
 
+template <bool kSweep>
+static hipError_t launch_scatter(const Work &w, int pass, int grid, hipStream_t s, bool gated, int scatter_waves) {
+    const dim3 g(grid), b(kSortThreads);
+    if (scatter_waves == 2)
+        hipLaunchKernelGGL((k_sort_scatter<2, kSweep>), g, b, 0, s, w, pass, (int)gated);
+    else if (scatter_waves == 4)
+        hipLaunchKernelGGL((k_sort_scatter<4, kSweep>), g, b, 0, s, w, pass, (int)gated);
+    else
+        hipLaunchKernelGGL((k_sort_scatter<3, kSweep>), g, b, 0, s, w, pass, (int)gated);
+    return hipGetLastError();
+}
+
 hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, int stage, bool gated,
                             int scatter_waves) {
     switch (stage) {
@@ -457,14 +599,16 @@ hipError_t launch_sort_pass(const Work &w, int pass, int grid, hipStream_t s, in
         case 2:
         case 3:
             return launch_scan_u32(w.counts, w.partials, &w.st->aux_n, nullptr, grid, s, stage - 1);
-        default:
-            if (scatter_waves == 2)
-                hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
-            else if (scatter_waves == 4)
-                hipLaunchKernelGGL(k_sort_scatter<4>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
-            else
-                hipLaunchKernelGGL(k_sort_scatter<3>, dim3(grid), dim3(kSortThreads), 0, s, w, pass, (int)gated);
+        case 6:   // one sweep: totals and tile counters zeroed
+            hipLaunchKernelGGL(k_sweep_reset, dim3(1), dim3(kSortThreads), 0, s, w, (int)gated);
             return hipGetLastError();
+        case 7:   // one sweep: the digit totals of every pass
+            hipLaunchKernelGGL(k_sweep_count, dim3(grid), dim3(kSortThreads), 0, s, w, (int)gated);
+            return hipGetLastError();
+        case 8:   // one sweep: the scatter of pass `pass`, its offsets by look-back
+            return launch_scatter<true>(w, pass, grid, s, gated, scatter_waves);
+        default:
+            return launch_scatter<false>(w, pass, grid, s, gated, scatter_waves);
     }
 }
 

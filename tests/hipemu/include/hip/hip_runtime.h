@@ -201,6 +201,17 @@ inline T atomicCAS(T *p, T cmp, T v) {
 template <typename T>
 inline T atomicExch(T *p, T v) { return __atomic_exchange_n(p, v, __ATOMIC_RELAXED); }
 
+// scoped atomics of HIP's clang: host atomics (every scope is the process here)
+#define __HIP_MEMORY_SCOPE_WORKGROUP 3
+#define __HIP_MEMORY_SCOPE_AGENT 4
+#define __HIP_MEMORY_SCOPE_SYSTEM 5
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), (order))
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), (order))
+namespace hipemu {
+void pause();   // a polling work-item lets the host thread breathe
+}  // namespace hipemu
+#define __builtin_amdgcn_s_sleep(n) ::hipemu::pause()
+
 // ---- runtime ------------------------------------------------------------------------------
 typedef enum hipError_t {
     hipSuccess = 0,

@@ -455,6 +455,12 @@ void grid_sync() {
     sync_threads();
 }
 
+std::atomic<long long> g_pauses{0};
+void pause() {
+    ++g_pauses;
+    std::this_thread::yield();
+}
+
 int resident_per_cu() {
     static const int n = [] {
         const char *v = getenv("HIPEMU_RESIDENT_PER_CU");
@@ -590,6 +596,8 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
 // Calls that on the GPU wait for all work on the device (HIP frees synchronise the device
 // before they release memory): counted, so that tests can check that a path makes none.
 extern "C" long long hipemu_device_syncs(void) { return g_device_syncs.load(); }
+// Polls of work-items waiting for another workgroup's word (__builtin_amdgcn_s_sleep).
+extern "C" long long hipemu_pauses(void) { return hipemu::g_pauses.load(); }
 
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) {
     *p = calloc(1, n ? n : 1);

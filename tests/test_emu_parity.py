@@ -81,6 +81,18 @@ def test_emulated_solve_matches_oracle(cc, mode, layout):
 
 
 @pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
+@pytest.mark.parametrize("rule", ["local", "one_hop"])
+def test_emulated_one_sweep_radix(cc, mode, rule):
+    """cc_tuning.radix_form = 2: one count pass for every digit, then per digit a scatter whose
+    tile offsets come from decoupled look-back.  Round by round (parents, edges, counts) and
+    the labels, on a graph whose rounds 0 and 1 sort (round 1 with the sort and the hashed
+    drop both enqueued, the device choosing)."""
+    g = graphgen.Graph(60000, *graphgen.gnm(0x5EE9, 60000, 200000))
+    check_solve(cc, g, 7, flags={"direct": DIRECT, "tiled": TILED, "rows": TILED}[mode], rule=rule,
+                round0=3 if mode == "rows" else 0, tuning={"radix_form": 2})
+
+
+@pytest.mark.parametrize("mode", ["direct", "tiled", "rows"])
 @pytest.mark.parametrize("rule", ["tree", "one_hop"])
 def test_emulated_rules_match_oracle(cc, mode, rule):
     g = graphgen.er_with_paths(0x77, 3000, 7000, 10, 50)
@@ -695,6 +707,9 @@ cases = [("rmat", rmat, cc.CC_ROUND0_TILED, 0, {}),
          ("rmat rows buckets", rmat, cc.CC_ROUND0_TILED, 0, {"round0": 3, "round0_sort": 2}),
          ("paths", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0, {}),
          ("paths persistent", graphgen.er_with_paths(9, 3000, 6000, 20, 200), cc.CC_ROUND0_DIRECT, 0, {"tail": 3}),
+         ("rmat one sweep", rmat, cc.CC_ROUND0_TILED, 0, {"radix_form": 2}),
+         ("gnm one sweep", graphgen.Graph(30000, *graphgen.gnm(8, 30000, 100000)), cc.CC_ROUND0_DIRECT, 0,
+          {"radix_form": 2}),
          ("mtl", graphgen.er_with_paths(10, 3000, 9000, 20, 100), cc.CC_ROUND0_TILED, cc.CC_MERGE_TO_LARGE, {})]
 for name, g, flags, extra, knobs in cases:
     want = oracle.run(g.n, g.src, g.dst, seed=5, variant="merge_to_large" if extra else "local", alphas=[3] if extra else None)

@@ -4,7 +4,7 @@ Hypothesis draws the graph (size, density, a power-law or uniform mix, repeated 
 loops, isolated ids), the seed, the input layout, the label rule (with MergeToLarge's
 parameters) and the solver's knobs (round-0
 form, key sets, the order of round 0's keys, kernel builds, grid size, the persistent launch of
-the small rounds); every draw must give
+the small rounds, the one-sweep radix passes); every draw must give
 the oracle's round count, statistics and labels.  The draws are derandomised, so a failure
 is reproducible, and sized so that the whole test takes about a minute.
 """
@@ -59,6 +59,7 @@ KNOBS = st.fixed_dictionaries({
     "row_generation": st.sampled_from([-1, 1, 2]),
     "blocks_per_cu": st.sampled_from([1, 8]),
     "tail": st.sampled_from([1, 2, 4]),
+    "radix_form": st.sampled_from([1, 2]),
 })
 
 

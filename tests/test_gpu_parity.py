@@ -308,7 +308,7 @@ def test_kernel_knobs_keep_results(lc, r0):
     s_t, d_t, _ = to_device(g)
     with lc.Solver(g.n, s_t, d_t, seed=13, flags=MODES["tiled"]) as s:
         for knob, values in (("scatter_waves", (2, 3, 4)), ("row_pairs", (2, 4, 8)), ("relabel_pairs", (1, 2, 4)),
-                             ("row_generation", (1, 2, 8, -1)), ("round0_sort", (1, 2))):
+                             ("row_generation", (1, 2, 8, -1)), ("round0_sort", (1, 2)), ("radix_form", (1, 2))):
             for v in values:
                 s.set_tuning(round0=r0, **{knob: v})
                 assert s.tuning[knob] == v and s.tuning["round0"] == r0
@@ -416,6 +416,17 @@ def test_captured_tail_matches_eager_and_oracle(lc):
             tail.edges()
         assert e.value.status == -5
         assert eager.edges().numel() == 0   # an eager solve that ran to the end left no edge
+
+
+@pytest.mark.parametrize("mode", sorted(MODES))
+def test_one_sweep_radix_parity(lc, mode):
+    """cc_tuning.radix_form = 2 (one count pass for every digit, then per digit a scatter whose
+    tile offsets come from decoupled look-back across the workgroups running at once): round
+    by round and the labels, on a uniform graph of 2^20 ids whose rounds 0 and 1 sort (round 1
+    also with the hashed drop enqueued, the device choosing), and on an R-MAT graph."""
+    for g, seed in ((graphgen.Graph(1 << 20, *graphgen.gnm(0x5EE9, 1 << 20, 3 << 20)), 7),
+                    (graphgen.Graph(1 << 18, *graphgen.rmat(0x5EEA, 18, 16 << 18)), 8)):
+        check(lc, g, seed, flags=MODES[mode], tuning={"radix_form": 2})
 
 
 @pytest.mark.parametrize("tail", [2, 3, 4])
