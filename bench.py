@@ -476,6 +476,8 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotune cache file (default: none, tune every run)")
     ap.add_argument("--no-tune", action="store_true", help="keep the solver's default knobs (no autotuning)")
     ap.add_argument("--tune-knobs", default="", help="comma-separated knobs to tune (default: all of them)")
+    ap.add_argument("--set", default="", metavar="KNOB=V,...",
+                    help="solver knobs (include/cc.h, cc_tuning) set as given; the tuner leaves them alone")
     ap.add_argument("--verbose-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-only", action="store_true")
@@ -550,6 +552,12 @@ def main():
 
     # The solver's knobs (form of round 0, workgroups per CU, round 0's key sets) are tuned on
     # this graph first, without per-kernel events; every candidate must give the same labels.
+    fixed = {}
+    for item in filter(None, args.set.split(",")):
+        k, _, v = item.partition("=")
+        if k not in lc.TUNING_KNOBS or not v.lstrip("-").isdigit():
+            raise SystemExit("--set takes knob=integer pairs of %s" % ",".join(lc.TUNING_KNOBS))
+        fixed[k] = int(v)
     tuning = None
     if not args.no_tune:
         from paper_1807_10727_amd import autotune
@@ -560,12 +568,13 @@ def main():
             if unknown:
                 raise SystemExit("unknown tuning knobs: %s" % ",".join(unknown))
             space = {k: v for k, v in space.items() if k in keep}
+        space = {k: v for k, v in space.items() if k not in fixed}   # knobs set as given stay
         if args.round0 != "auto":
             space.pop("round0", None)     # the form asked for stays
         t0 = time.perf_counter()
         with lc.Solver(n0, src, dst, seed=base_seed, flags=round0_flag, stream=stream, layout=layout) as ts:
-            if args.round0 == "rows":
-                ts.set_tuning(round0=3)
+            if args.round0 == "rows" or fixed:
+                ts.set_tuning(**dict({"round0": 3} if args.round0 == "rows" else {}, **fixed))
             tuning, t_best, tried = autotune.tune_solver(ts, seed=base_seed + 500, repeats=1, cache=args.tune_cache,
                                                          log=log if args.verbose_tune else None, space=space)
         torch.cuda.empty_cache()
@@ -576,8 +585,9 @@ def main():
     solver = lc.Solver(n0, src, dst, seed=base_seed, flags=flags, stream=stream, layout=layout)
     if tuning:
         solver.set_tuning(**tuning)
-    elif args.round0 == "rows":
-        solver.set_tuning(round0=3)
+    elif args.round0 == "rows" or fixed:
+        tuning = dict({"round0": 3} if args.round0 == "rows" else {}, **fixed)
+        solver.set_tuning(**tuning)
     log("workspace %.2f GiB" % (solver.ws_bytes / 2**30))
 
     def step(i):

@@ -23,7 +23,7 @@ from ._cc import (CC_CANONICAL, CC_DONE, CC_EDGES_PACKED_U64, CC_EDGES_SOA_I32, 
                   cc_set_explicit_priorities, cc_set_merge_to_large, cc_get_tuning, cc_set_tuning,
                   cc_contract_round, cc_create, cc_destroy, cc_get_finished, cc_get_round_sorted, cc_get_round_stats, cc_kernel_family_names, cc_kernel_times,
                   cc_labels, cc_last_error, cc_reset, cc_round_edges, cc_round_parents, cc_run, cc_set_finish, cc_set_profile_mask,
-                  cc_set_workspace, cc_version, cc_workspace_size)
+                  cc_set_workspace, cc_version, cc_workspace_size, TUNING_KNOBS)
 
 __all__ = ["Solver", "Batch", "Server", "solve", "CCError", "CC_CANONICAL", "CC_EAGER", "CC_EXPLICIT_PRIO",
            "CC_MERGE_TO_LARGE",

@@ -30,7 +30,7 @@ def test_smoke_runs():
 @pytest.mark.slow
 def test_bench_json_contract():
     proc = run(["bench", "--workload", "small", "--steps", "2", "--warmup", "2", "--secondary", "",
-                "--tune-knobs", "round0,round0_sort,row_pairs",
+                "--tune-knobs", "round0,round0_sort,row_pairs,tail", "--set", "tail=2,radix_form=2",
                 "--variant-steps", "1", "--batch-graphs", "12", "--batch-log2-max", "9", "--batch-steps", "1",
                 "--serve-requests", "6", "--serve-warmup", "2", "--serve-pool", "3", "--serve-log2-max", "12",
                 "--serve-loads", "1.0", "--serve-budget-gib", "1"],
@@ -42,6 +42,7 @@ def test_bench_json_contract():
               "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 2 and d["config"]["workload"].startswith("G(n=65,536")
+    assert d["config"]["tuning"]["tail"] == 2 and d["config"]["tuning"]["radix_form"] == 2   # --set, untuned
     r = d["roofline"]
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
     assert r["kernel"].startswith("a") and r["frac"] == round(r["achieved"] / 8000.0, 4)
