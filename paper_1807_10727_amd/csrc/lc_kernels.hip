@@ -121,12 +121,11 @@ __global__ __launch_bounds__(kThreads) void k_relabel(R rd, Work w) {
     step_relabel<R>(rd, w);
 }
 
+// The label ranks, and (one thread) the key width of the round's sort, which needs only the
+// label count that the label map's scan has already written.
 __global__ __launch_bounds__(kThreads) void k_rank_parents(Work w) {
     step_rank_parents(w);
-}
-
-__global__ void k_plan_blocks(Work w) {
-    step_plan_blocks(w);
+    if (blockIdx.x == 0 && threadIdx.x == 0) step_plan_blocks(w);
 }
 
 template <bool kFirst, bool kBatch>
@@ -447,9 +446,6 @@ hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rank_parents, dim3(grid), dim3(kThreads), 0, s, w);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_plan_blocks, dim3(1), dim3(1), 0, s, w);
     return hipGetLastError();
 }
 

@@ -85,6 +85,7 @@ void run_grid(const std::function<void()> &item, dim3 grid, dim3 block);
 // that grid-wide barriers (cooperative_groups, hip_cooperative_groups.h) can complete.
 void run_grid_cooperative(const std::function<void()> &item, dim3 grid, dim3 block);
 void grid_sync();
+void count_launch();   // kernels executed so far (hipemu_launches), graph replays included
 
 }  // namespace hipemu
 
@@ -305,7 +306,10 @@ inline void hipemu_launch(F kern, dim3 grid, dim3 block, size_t shmem, hipStream
         hipemu::set_error(hipErrorInvalidValue);
         return;
     }
-    hipemu::submit(s, [=]() { hipemu::run_grid([=]() { kern(args...); }, grid, block); });
+    hipemu::submit(s, [=]() {
+        hipemu::count_launch();
+        hipemu::run_grid([=]() { kern(args...); }, grid, block);
+    });
 }
 #define hipLaunchKernelGGL(kern, grid, block, shmem, stream, ...) \
     hipemu_launch((kern), dim3(grid), dim3(block), (size_t)(shmem), (stream), ##__VA_ARGS__)
@@ -339,6 +343,7 @@ inline hipError_t hipLaunchCooperativeKernel(void (*kern)(A...), dim3 grid, dim3
         return hipErrorCooperativeLaunchTooLarge;
     auto vals = hipemu_unpack<A...>(args, std::index_sequence_for<A...>{});
     hipemu::submit(s, [=]() {
+        hipemu::count_launch();
         hipemu::run_grid_cooperative([=]() { std::apply(kern, vals); }, grid, block);
     });
     return hipSuccess;

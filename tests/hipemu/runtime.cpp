@@ -456,6 +456,8 @@ void grid_sync() {
 }
 
 std::atomic<long long> g_pauses{0};
+std::atomic<long long> g_launches{0};
+void count_launch() { ++g_launches; }
 void pause() {
     ++g_pauses;
     std::this_thread::yield();
@@ -598,6 +600,8 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
 extern "C" long long hipemu_device_syncs(void) { return g_device_syncs.load(); }
 // Polls of work-items waiting for another workgroup's word (__builtin_amdgcn_s_sleep).
 extern "C" long long hipemu_pauses(void) { return hipemu::g_pauses.load(); }
+// Kernels executed (a replayed graph counts each kernel it holds).
+extern "C" long long hipemu_launches(void) { return hipemu::g_launches.load(); }
 
 hipError_t hipHostMalloc(void **p, size_t n, unsigned) {
     *p = calloc(1, n ? n : 1);

@@ -192,6 +192,30 @@ def test_emulated_persistent_rounds_large(cc, rule, seed, launches):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
+def test_emulated_kernel_counts(cc):
+    """Kernels executed per solve (run and labels) on a graph of many rounds: the persistent
+    launch of the small rounds and the one-sweep radix passes each execute fewer kernels than
+    the default launch sequences, and both together fewer than half as many, with the same
+    labels."""
+    lib = ctypes.CDLL(cc.LIB_PATH)
+    lib.hipemu_launches.restype = ctypes.c_longlong
+    g = graphgen.er_with_paths(0xD15, 1 << 14, 1 << 17, 40, 500)
+    want = oracle.run(g.n, g.src, g.dst, seed=3)
+    assert want.rounds >= 6
+    counts = {}
+    for name, kn in (("default", {}), ("tail", {"tail": 2}), ("sweep", {"radix_form": 2}),
+                     ("both", {"tail": 2, "radix_form": 2})):
+        with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=3, flags=DIRECT) as s:
+            s.set_tuning(**kn)
+            k0 = lib.hipemu_launches()
+            assert s.run() == want.rounds
+            lab = s.labels()
+            counts[name] = lib.hipemu_launches() - k0
+            np.testing.assert_array_equal(lab.astype(np.uint32), want.labels)
+    assert counts["tail"] < counts["default"] and counts["sweep"] < counts["default"]
+    assert 2 * counts["both"] < counts["default"], counts
+
+
 FALLBACK_CHECK = r"""
 import sys
 sys.path[:0] = [%r, %r]
