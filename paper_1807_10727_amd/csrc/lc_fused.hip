@@ -1,7 +1,7 @@
 // Whole small rounds in one persistent launch.
 //
 // Once the remaining graph is small (rounds >= 1 with at most kHashMaxRecords records), a
-// round costs far more in launches than in work: it is about seventeen dependent kernels of a
+// round costs far more in launches than in work: it is about sixteen dependent kernels of a
 // few microseconds each (Section 3's phase: one-hop minimum, two-hop minimum, parents, label
 // map, relabel, duplicate drop, next node set and map), and each waits for the one before.
 // Here a single cooperative launch (every workgroup resident at once) runs round after round.
