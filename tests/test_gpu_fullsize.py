@@ -238,14 +238,16 @@ def test_er_paths_round0_edges(lc, er_full):
 
 
 TUNED = [{"round0_sort": 2}, {"round0": 3}, {"round0": 3, "round0_sort": 2, "round0_key_sets": 0},
-         {"round0": 1, "round0_sort": 2}, {"row_pairs": 8, "relabel_pairs": 4, "row_generation": -1, "scatter_waves": 4}]
+         {"round0": 1, "round0_sort": 2}, {"row_pairs": 8, "relabel_pairs": 4, "row_generation": -1, "scatter_waves": 4},
+         {"radix_form": 2, "tail": 3}, {"round0": 1, "radix_form": 2, "tail": 2}]
 
 
 @pytest.mark.timeout(900)
 def test_er_paths_tuned_vs_oracle(lc, er_full):
     """The bench graph under the knobs the tuner may pick (the sampled-bucket sort of round 0's
     129 M keys, the one-pass row partition, the direct round 0, other row-pass and scatter
-    builds): rounds, statistics and labels bit for bit against the oracle."""
+    builds, the one-sweep radix passes, the small rounds in one persistent launch): rounds,
+    statistics and labels bit for bit against the oracle."""
     g, futs = er_full
     src_t = torch.from_numpy(g.src.view(np.int32)).to(DEV)
     dst_t = torch.from_numpy(g.dst.view(np.int32)).to(DEV)
