@@ -702,12 +702,17 @@ bool fused_wanted(const cc_ctx *c) {
 cc_status run_fused(cc_ctx *c) {
     const int64_t cap = std::max<int64_t>(c->g.n_vertices, 1);
     if ((c->host_levels >= kMaxLevels || c->host_map_used + c->n_cur > cap) && !c->flatten()) return hip_status(c);
+    const bool one_hop = c->variant == kVarOneHop;
+    const int grid = fused_rounds_grid(one_hop, 1 << (c->tail - 2), c->cus);
+    if (grid <= 0) {
+        c->fused_unavailable = true;
+        return round_once(c, nullptr);
+    }
     const int before = c->next_round;
     const bool ev = c->ev_begin(kFusedRounds);
-    const hipError_t e =
-        launch_fused_rounds(c->w, c->variant == kVarOneHop, 1 << (c->tail - 2), c->cus, c->stream);
+    const hipError_t e = launch_fused_rounds(c->w, one_hop, grid, c->stream);
     c->ev_end(ev);
-    if (e == hipErrorCooperativeLaunchTooLarge) {
+    if (e == hipErrorCooperativeLaunchTooLarge) {   // the runtime disagrees with the occupancy query
         (void)hipGetLastError();
         c->fused_unavailable = true;
         return round_once(c, nullptr);

@@ -100,20 +100,27 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
     }
 }
 
+typedef void (*FusedKernel)(ReadInternal, Work, PrioCtx);
+
+FusedKernel fused_kernel(bool one_hop) { return one_hop ? k_fused_rounds<true> : k_fused_rounds<false>; }
+
 }  // namespace
 
-hipError_t launch_fused_rounds(const Work &w, bool one_hop, int per_cu, int cus, hipStream_t s) {
-    void (*kern)(ReadInternal, Work, PrioCtx) = one_hop ? k_fused_rounds<true> : k_fused_rounds<false>;
+int fused_rounds_grid(bool one_hop, int per_cu, int cus) {
     int occ = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, 0);
-    if (e != hipSuccess) return e;
-    if (occ < 1) return hipErrorCooperativeLaunchTooLarge;
-    const int grid = cus * (per_cu < occ ? per_cu : occ);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fused_kernel(one_hop), kThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return occ < 1 ? 0 : cus * (per_cu < occ ? per_cu : occ);
+}
+
+hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, hipStream_t s) {
     ReadInternal rd(w);
     Work wk = w;
     PrioCtx pc{};
     void *args[] = {&rd, &wk, &pc};
-    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kThreads), args, 0, s);
+    return hipLaunchCooperativeKernel(fused_kernel(one_hop), dim3(grid), dim3(kThreads), args, 0, s);
 }
 
 }  // namespace lc

@@ -223,12 +223,14 @@ import numpy as np, graphgen, oracle, hipemu
 cc = hipemu.binding()
 g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
 want = oracle.run(g.n, g.src, g.dst, seed=10)
-with hipemu.Solver(g.n, hipemu.device(g.src, np.int32), hipemu.device(g.dst, np.int32), seed=10) as s:
+with hipemu.Solver(g.n, hipemu.device(g.src, np.int32), hipemu.device(g.dst, np.int32), seed=10,
+                   flags=cc.CC_PROFILE) as s:
     s.set_tuning(tail=4)
     r = s.run()
     ok = r == want.rounds and [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats] and \
         np.array_equal(s.labels().astype(np.uint32), want.labels)
-    print("OK", ok, [cc.cc_get_round_stats(s.ctx, k, True)[-1] for k in range(r)])
+    launches = cc.cc_kernel_times(s.ctx)["fused_rounds"][1]
+    print("OK", ok, launches, [cc.cc_get_round_stats(s.ctx, k, True)[-1] for k in range(r)])
 """
 
 
@@ -244,7 +246,7 @@ def test_emulated_persistent_rounds_fall_back(cc):
     proc = subprocess.run([sys.executable, "-c", FALLBACK_CHECK % (os.path.dirname(here), here)], env=env,
                           stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=600)
     assert proc.returncode == 0, proc.stderr[-2000:]
-    assert "OK True [0, 0, 0" in proc.stdout and "2" not in proc.stdout.split("OK True")[1], proc.stdout
+    assert "OK True 0 [0, 0, 0" in proc.stdout and "2" not in proc.stdout.split("OK True 0")[1], proc.stdout
 
 
 def test_emulated_union_find_finish_and_canonical(cc):
