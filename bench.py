@@ -553,6 +553,7 @@ def main():
     # The solver's knobs (form of round 0, workgroups per CU, round 0's key sets) are tuned on
     # this graph first, without per-kernel events; every candidate must give the same labels.
     fixed = {}
+    tuner_rejected = []   # candidates the tuner could not use (a failed solve, other labels)
     for item in filter(None, args.set.split(",")):
         k, _, v = item.partition("=")
         if k not in lc.TUNING_KNOBS or not v.lstrip("-").isdigit():
@@ -576,6 +577,7 @@ def main():
             if args.round0 == "rows" or fixed:
                 ts.set_tuning(**dict({"round0": 3} if args.round0 == "rows" else {}, **fixed))
             tuning, t_best, tried = autotune.tune_solver(ts, seed=base_seed + 500, repeats=1, cache=args.tune_cache,
+                                                         rejected=tuner_rejected,
                                                          log=log if args.verbose_tune else None, space=space)
         torch.cuda.empty_cache()
         log("solver autotune picked %s (%d candidates timed, best %.3f ms, %.1fs)"
@@ -752,6 +754,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "n_vertices": n0, "n_records": m0, "rounds": rounds[0],
                    "round0": args.round0, "tuning": tuning, "parallelism": "single GPU"},
+        "tuner_rejected": [{"knob": k, "value": v, "reason": why} for k, v, why in tuner_rejected],
         "roofline": roofline,
         "step_rooflines": step_rooflines,
         "job_alg_frac": round(job_gbs / HBM_PEAK_GBS, 4),

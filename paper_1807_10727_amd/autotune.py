@@ -156,11 +156,14 @@ def _time_solver(solver, seed, repeats):
     return best, digest
 
 
-def tune_solver(solver, seed: int = 0, repeats: int = 1, cache: str | None = DEFAULT_CACHE, log=None, space=None):
+def tune_solver(solver, seed: int = 0, repeats: int = 1, cache: str | None = DEFAULT_CACHE, log=None, space=None,
+                rejected=None):
     """Pick the fastest ``cc_tuning`` for `solver` (a paper_1807_10727_amd.Solver whose
     workspace was sized for its default form), apply it and return (tuning dict, seconds of
     the best solve, number of candidates timed).  Each candidate solves the graph with `seed`
-    and must give the labels of the first one."""
+    and must give the labels of the first one.  A candidate whose solve fails or gives other
+    labels is never picked: with a list passed as `rejected` it is recorded there (knob,
+    value, reason) and the walk goes on; without one its labels raise RuntimeError."""
     key = "solver|%s|%s" % (device_key(), solver_size_class(solver))
     if cache:
         hit = _load(cache).get(key)
@@ -183,10 +186,19 @@ def tune_solver(solver, seed: int = 0, repeats: int = 1, cache: str | None = DEF
                 solver.set_tuning(**cand)
             except Exception:          # e.g. a tiled round 0 the context cannot take
                 continue
-            t, digest = _time_solver(solver, seed, repeats)
+            try:
+                t, digest = _time_solver(solver, seed, repeats)
+            except Exception as e:     # e.g. CCError from the library
+                if rejected is None:
+                    raise
+                rejected.append((knob, v, "solve failed: %s" % (e,)))
+                continue
             tried += 1
             if digest != ref:
-                raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+                if rejected is None:
+                    raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+                rejected.append((knob, v, "labels differ from the first candidate's"))
+                continue
             if log:
                 log("  tune %-16s %s -> %.3f ms" % (knob, v, t * 1e3))
             if t < best_t:

@@ -43,6 +43,7 @@ def test_bench_json_contract():
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 2 and d["config"]["workload"].startswith("G(n=65,536")
     assert d["config"]["tuning"]["tail"] == 2 and d["config"]["tuning"]["radix_form"] == 2   # --set, untuned
+    assert d["tuner_rejected"] == []
     r = d["roofline"]
     assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["unit"] == "GB/s"
     assert r["kernel"].startswith("a") and r["frac"] == round(r["achieved"] / 8000.0, 4)
