@@ -214,9 +214,9 @@ constexpr uint32_t kInputSetTrial = 4096;
 //
 // A workgroup also drops every key it has written before: a dense region that contracts
 // onto a few parents maps many records onto the same parent pairs (rounds >= 1, and round 0
-// of power-law inputs), and a hash set in LDS (kept for the whole launch) removes most of
-// those repeats before they reach the sort.  s_count still counts every survivor; s_keys
-// counts the keys.
+// of power-law inputs), and a hash set in LDS (kept for the whole pass over the records)
+// removes most of those repeats before they reach the sort.  s_count still counts every
+// survivor; s_keys counts the keys.
 template <class R>
 __device__ inline void step_relabel(R rd, Work w) {
     constexpr int V = R::kV;
