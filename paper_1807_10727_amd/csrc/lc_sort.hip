@@ -368,6 +368,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sweep_count(Work w, int gated)
     for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < tl.ntiles * kRadixMax;
          i += (int64_t)gridDim.x * kSortThreads)
         w.counts[i] = kSweepEmpty;
+    // every pass's digit position, worked out once
+    int shifts[kMaxPasses];
+    uint32_t masks[kMaxPasses];
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; ++p) {
+        int width = 0;
+        shifts[p] = 0;
+        if (p < passes) pass_digit(nbits, p, shifts[p], width);
+        masks[p] = (1u << width) - 1u;
+    }
     __syncthreads();
     for (int64_t tile = xcd_rank(blockIdx.x, gridDim.x); tile < tl.ntiles; tile += gridDim.x) {
         const int tv = tl.valid(tile);
@@ -380,10 +390,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sweep_count(Work w, int gated)
             const uint64_t act = ballot(valid);
             if (!act) continue;   // uniform over the wave
             const int first = __ffsll((long long)act) - 1;
-            for (int p = 0; p < passes; ++p) {
-                int shift, width;
-                pass_digit(nbits, p, shift, width);
-                const uint32_t d = (uint32_t)(k >> shift) & ((1u << width) - 1u);
+#pragma unroll
+            for (int p = 0; p < kMaxPasses; ++p) {
+                if (p >= passes) break;   // uniform
+                const uint32_t d = (uint32_t)(k >> shifts[p]) & masks[p];
                 const uint32_t d0 = __shfl(d, first, kWave);
                 if (ballot(valid && d == d0) == act) {   // the whole wave in one digit: one add
                     if (lane_id() == first) atomicAdd(&hist[p * kRadixMax + d0], (uint32_t)__popcll(act));
