@@ -171,6 +171,21 @@ def test_emulated_persistent_rounds(cc, tail, rule):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
+@pytest.mark.parametrize("max_rounds", [3, 5])
+def test_emulated_persistent_rounds_stop_at_max_rounds(cc, max_rounds):
+    """cc_options.max_rounds inside the persistent launch: the solve stops after exactly that
+    many rounds, with the oracle's statistics and partial labels."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=10, max_rounds=max_rounds)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=10, max_rounds=max_rounds) as s:
+        s.set_tuning(tail=2)
+        rounds = s.run()
+        assert rounds == want.rounds == max_rounds
+        assert in_graph(cc, s, rounds)[-1] == 2
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
 @pytest.mark.parametrize("rule,seed,launches", [("local", 3, 1), ("one_hop", 22, 2)])
 def test_emulated_persistent_rounds_large(cc, rule, seed, launches):
     """About a million path vertices.  LocalContraction: round 1 has more than 2^18 nodes, so
