@@ -197,6 +197,8 @@ def test_max_rounds_partial_labels(lc, mode):
     g = graphgen.er_with_paths(5, 0, 0, 20, 400)
     for k in (1, 2, 3):
         check(lc, g, seed=8, max_rounds=k, flags=MODES[mode])
+        # cc_run alone, the rounds after round 0 in the persistent launch, stopping at k
+        check(lc, g, seed=8, max_rounds=k, flags=MODES[mode], per_round=False, tuning={"tail": 2})
 
 
 def test_canonical_labels(lc):
