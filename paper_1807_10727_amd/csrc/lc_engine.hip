@@ -691,7 +691,7 @@ cc_status adopt_device_rounds(cc_ctx *c, int in_graph) {
 bool fused_wanted(const cc_ctx *c) {
     return c->tail >= 2 && !c->fused_unavailable && c->variant != kVarTree &&
            !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE)) &&
-           (c->o.max_rounds == 0 || c->next_round < c->o.max_rounds) && c->finish_edges == 0 &&
+           (c->o.max_rounds == 0 || c->next_round < c->o.max_rounds) && c->m_cur > c->finish_edges &&
            c->next_round >= 1 && c->next_round < kStatRounds &&
            !c->done && c->m_cur > 0 && c->m_cur <= kHashMaxRecords && 2 * c->m_cur + 1 <= c->w.kcap;
 }
@@ -711,8 +711,8 @@ cc_status run_fused(cc_ctx *c) {
     }
     const int before = c->next_round;
     const bool ev = c->ev_begin(kFusedRounds);
-    const int limit = c->o.max_rounds > 0 ? c->o.max_rounds : kStatRounds;
-    const hipError_t e = launch_fused_rounds(c->w, one_hop, grid, limit, c->stream);
+    const FusedLimits lim{c->o.max_rounds > 0 ? c->o.max_rounds : kStatRounds, c->finish_edges};
+    const hipError_t e = launch_fused_rounds(c->w, one_hop, grid, lim, c->stream);
     c->ev_end(ev);
     if (e == hipErrorCooperativeLaunchTooLarge) {   // the runtime disagrees with the occupancy query
         (void)hipGetLastError();

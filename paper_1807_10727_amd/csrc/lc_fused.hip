@@ -16,8 +16,8 @@
 // the previous round, so all of them take the same decision.  The launch ends when no edge is
 // left, or when the next round does not fit it (more records than the hashed drop takes, no
 // room for another per-round map, the statistics table full, the caller's round limit reached,
-// an error flagged); the host then reads the state once and goes on with separate launches if
-// edges remain.  The loop runs at most kStatRounds rounds in all, so every workgroup leaves it.
+// few enough records left for the union-find finish, an error flagged); the host then reads the
+// state once and goes on with separate launches (or the finish) if edges remain.  The loop runs at most kStatRounds rounds in all, so every workgroup leaves it.
 
 #include <hip/hip_cooperative_groups.h>
 
@@ -28,11 +28,13 @@ namespace lc {
 namespace {
 
 // Whether the next round runs inside this launch (the host's conditions for a hashed round,
-// evaluated on the device state; rounds from round_limit on are left to the host).
-__device__ inline bool next_round_fits(const Work &w, const RoundState *st, int round_limit) {
+// evaluated on the device state).  Rounds from a.round_limit on, and a graph of at most
+// a.finish_edges records (which the union-find finish takes over), are left to the host.
+__device__ inline bool next_round_fits(const Work &w, const RoundState *st, const FusedLimits &a) {
     const uint64_t m = st->m_cur, n = st->n_cur;
-    return st->err == 0 && st->round >= 1 && st->round < round_limit && m > 0 && m <= (uint64_t)kHashMaxRecords &&
-           2 * m + 1 <= (uint64_t)w.kcap && st->levels < kMaxLevels && st->map_off + n <= st->map_cap;
+    return st->err == 0 && st->round >= 1 && st->round < a.round_limit && m > (uint64_t)a.finish_edges &&
+           m > 0 && m <= (uint64_t)kHashMaxRecords && 2 * m + 1 <= (uint64_t)w.kcap && st->levels < kMaxLevels &&
+           st->map_off + n <= st->map_cap;
 }
 
 // Bit map with prefix counts of byte flags (label map or node map), as launch_map_scan builds
@@ -56,11 +58,11 @@ __device__ inline void flag_map(cooperative_groups::grid_group &grid, bool singl
 }
 
 template <bool kOneHop>
-__global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work w, PrioCtx pc, int round_limit) {
+__global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work w, PrioCtx pc, FusedLimits lim) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     RoundState *st = w.st;
     auto none = [] {};
-    while (next_round_fits(w, st, round_limit)) {
+    while (next_round_fits(w, st, lim)) {
         const int r = st->round;
         const bool single = st->n_cur <= (u64c)kSmallFlagNodes;
         const uint32_t *names = w.names[r & 1];
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
     }
 }
 
-typedef void (*FusedKernel)(ReadInternal, Work, PrioCtx, int);
+typedef void (*FusedKernel)(ReadInternal, Work, PrioCtx, FusedLimits);
 
 FusedKernel fused_kernel(bool one_hop) { return one_hop ? k_fused_rounds<true> : k_fused_rounds<false>; }
 
@@ -115,12 +117,12 @@ int fused_rounds_grid(bool one_hop, int per_cu, int cus) {
     return occ < 1 ? 0 : cus * (per_cu < occ ? per_cu : occ);
 }
 
-hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, int round_limit, hipStream_t s) {
+hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, FusedLimits lim, hipStream_t s) {
     ReadInternal rd(w);
     Work wk = w;
     PrioCtx pc{};
-    int limit = round_limit < kStatRounds ? round_limit : kStatRounds;
-    void *args[] = {&rd, &wk, &pc, &limit};
+    if (lim.round_limit > kStatRounds) lim.round_limit = kStatRounds;
+    void *args[] = {&rd, &wk, &pc, &lim};
     return hipLaunchCooperativeKernel(fused_kernel(one_hop), dim3(grid), dim3(kThreads), args, 0, s);
 }
 

@@ -405,10 +405,14 @@ __device__ inline Tiles tiles_of(const Work &w, int pass) {
 constexpr int kBucketLevel2Tiles = 256;   // extra count-table tiles of the second level
 hipError_t launch_bucket(const Work &w, int stage, int grid, hipStream_t s);
 // Rounds >= 1 that fit the hashed duplicate drop, one after another in one cooperative launch
-// (lc_fused.hip), up to round round_limit (exclusive).  fused_rounds_grid: cus * min(per_cu,
-// workgroups of the kernel that stay resident on a CU), or 0 when not even one does.
+// (lc_fused.hip).  fused_rounds_grid: cus * min(per_cu, workgroups of the kernel that stay
+// resident on a CU), or 0 when not even one does.
 int fused_rounds_grid(bool one_hop, int per_cu, int cus);
-hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, int round_limit, hipStream_t s);
+struct FusedLimits {
+    int32_t round_limit;    // rounds from this one on are left to the host
+    int64_t finish_edges;   // a graph of at most this many records is left to the union-find finish
+};
+hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, FusedLimits lim, hipStream_t s);
 // parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:
 // the label scan in one workgroup)
 hipError_t launch_rank_parents(const Work &w, int grid, int grid_scan, hipStream_t s);

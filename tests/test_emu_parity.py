@@ -186,6 +186,20 @@ def test_emulated_persistent_rounds_stop_at_max_rounds(cc, max_rounds):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
+@pytest.mark.parametrize("finish", [300, 1000])
+def test_emulated_persistent_rounds_then_union_find(cc, finish):
+    """The union-find finish after rounds in the persistent launch: the launch stops once the
+    graph has at most `finish` records, and the finish ends the solve as the oracle's does."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=10, finish_edges=finish)
+    assert want.finished
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=10, finish_edges=finish) as s:
+        s.set_tuning(tail=3)
+        rounds = s.run()
+        assert rounds == want.rounds and 2 in in_graph(cc, s, rounds)
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
 @pytest.mark.parametrize("rule,seed,launches", [("local", 3, 1), ("one_hop", 22, 2)])
 def test_emulated_persistent_rounds_large(cc, rule, seed, launches):
     """About a million path vertices.  LocalContraction: round 1 has more than 2^18 nodes, so

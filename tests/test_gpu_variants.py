@@ -165,6 +165,22 @@ def test_finish_parity(lc, name, finish, variant):
         np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), plain.labels)
 
 
+@pytest.mark.parametrize("finish", [1, 300, 3000])
+def test_finish_after_persistent_rounds(lc, finish):
+    """The union-find finish after rounds run in the persistent launch (cc_tuning.tail): the
+    launch stops once the graph has at most `finish` records, and the finish ends the solve
+    with the oracle's rounds, statistics and labels."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=10, finish_edges=finish)
+    s_t, d_t = dev(g)
+    with lc.Solver(g.n, s_t, d_t, seed=10, finish_edges=finish) as s:
+        s.set_tuning(tail=3)
+        r = s.run()
+        assert r == want.rounds and s.finished == want.finished
+        assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().cpu().numpy().astype(np.uint32), want.labels)
+
+
 def test_finish_canonical_labels_unchanged(lc):
     """With CC_CANONICAL the finish changes nothing: the smallest id of every component."""
     g = graphgen.er_with_paths(19, 1 << 12, 1 << 13, 40, 500)
