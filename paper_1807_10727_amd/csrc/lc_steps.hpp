@@ -714,4 +714,149 @@ __device__ inline void step_hash_write(Work w) {
     }
 }
 
+// ---- TreeContraction (Section 4) ----
+
+template <bool kFirst>
+__device__ inline uint32_t tree_prio(const PrioCtx &pc, const uint32_t *names, uint32_t i) {
+    return rho_of(pc, kFirst ? i : names[i]);
+}
+
+// Open one-hop minimum: each loop-free record sends rho(b) to a and rho(a) to b (no self
+// term), into the low half of the node word, which round_begin filled with +inf.
+template <class R, bool kFirst>
+__device__ inline void step_min1_open(R rd, Work w, PrioCtx pc, const uint32_t *names) {
+    constexpr int V = R::kV;
+    rd.init(w.st);
+    pc.key = w.st->key;
+    const int64_t nch = rd.chunks();
+    uint32_t *m1 = w.ml;
+    bool bad = false;
+    for (int64_t cb = (int64_t)blockIdx.x * kThreads; cb < nch; cb += (int64_t)gridDim.x * kThreads) {
+        const int64_t c = cb + threadIdx.x;
+        uint32_t a[V], b[V];
+        if (c < nch) {
+            rd.read(c, a, b, bad);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) a[j] = b[j] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const bool ok = a[j] != b[j];
+            const uint32_t pa = ok ? tree_prio<kFirst>(pc, names, a[j]) : kInf;
+            const uint32_t pb = ok ? tree_prio<kFirst>(pc, names, b[j]) : kInf;
+            bool la = true;
+            const uint32_t va = R::kSorted ? run_min(ok ? a[j] : 0xFFFFFFFFu, pb, la) : pb;
+            if (ok) {
+                if (la && m1[2 * (size_t)a[j]] > va) atomicMin(&m1[2 * (size_t)a[j]], va);
+                if (m1[2 * (size_t)b[j]] > pa) atomicMin(&m1[2 * (size_t)b[j]], pa);
+            }
+        }
+    }
+    if (bad) atomicOr(&w.st->err, 1u);
+}
+
+// Where the open one-hop minimum and f live: the node word (low half m1, high half f), or
+// after the tiled round 0's row pass, a dense m1 array with f kept in lab_at (free until the
+// labels are ranked).
+template <bool kDense>
+__device__ inline uint32_t tree_m1(const Work &w, int64_t i) { return kDense ? w.ml[i] : w.ml[2 * i]; }
+template <bool kDense>
+__device__ inline uint32_t *tree_f_ptr(const Work &w, int64_t i) { return kDense ? w.lab_at + i : w.ml + 2 * i + 1; }
+
+// f(v) (see tree_f_ptr) and the starting jump pointer (par); a node without a loop-free
+// record (round 0 only) points to itself.  Resets the jump flags.
+template <bool kFirst, bool kDense>
+__device__ inline void step_tree_f(Work w, PrioCtx pc) {
+    RoundState *st = w.st;
+    pc.key = st->key;
+    const int64_t n = (int64_t)st->n_cur;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->jflag[0] = 0u;
+        st->jdone = 0u;
+    }
+    uint32_t active = 0;
+    bool broken = false;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t m = tree_m1<kDense>(w, i);
+        uint32_t p = (uint32_t)i;
+        if (m != kInf) {
+            const uint32_t name = rho_name(pc, m, w.n0);
+            p = kFirst ? name : ((int64_t)name < w.n0 ? w.idx_of[name] : 0xFFFFFFFFu);
+            if ((int64_t)p >= n) {   // cannot happen for a consistent state
+                broken = true;
+                p = (uint32_t)i;
+            }
+            ++active;
+        }
+        *tree_f_ptr<kDense>(w, i) = p;
+        w.par[i] = p;
+    }
+    __shared__ uint32_t red[kThreads / kWave];
+    active = block_sum<kThreads>(active, red);
+    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
+    if (broken) atomicOr(&st->err, 4u);
+}
+
+// A pointer found on its 2-cycle is final: the top bit of par marks it (node indices are
+// below 2^31), so later passes stream over it without gathering.
+constexpr uint32_t kOnCycle = 0x80000000u;
+
+// One pointer-jumping pass: a pointer not yet on a 2-cycle takes its target's pointer; one
+// found on its cycle is marked final.  Pass `it` reads whether pass it-1 moved a pointer
+// (flag slot (it + 2) % 3), records its own moves in slot it % 3 and clears slot
+// (it + 1) % 3 for the next pass; once a pass moves nothing, every pointer is on its cycle,
+// the next pass sets jdone and every later pass returns at once.  Passes never read a slot
+// that the same pass writes, so every workgroup decides alike.  Pointers read while another
+// thread updates them are valid either way (the old or the new position on the same path).
+template <bool kDense>
+__device__ inline void step_tree_jump(Work w, int it) {
+    RoundState *st = w.st;
+    if (st->jdone) return;
+    if (it > 0 && st->jflag[(it + 2) % 3] == 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->jdone = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->jflag[(it + 1) % 3] = 0u;
+    const int64_t n = (int64_t)st->n_cur;
+    bool changed = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        const uint32_t pj = w.par[x];
+        if (pj & kOnCycle) continue;
+        const uint32_t fj = *tree_f_ptr<kDense>(w, pj);
+        if (*tree_f_ptr<kDense>(w, fj) != pj) {
+            w.par[x] = w.par[pj] & ~kOnCycle;
+            changed = true;
+        } else {
+            w.par[x] = pj | kOnCycle;
+        }
+    }
+    if (__any(changed) && lane_id() == 0) st->jflag[it % 3] = 1u;
+}
+
+// The label of each node: the member of smaller priority of the 2-cycle its pointer reached.
+template <bool kFirst, bool kDense>
+__device__ inline void step_tree_label(Work w, PrioCtx pc, const uint32_t *names) {
+    RoundState *st = w.st;
+    pc.key = st->key;
+    const int64_t n = (int64_t)st->n_cur;
+    bool broken = false;
+    for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+        if (*tree_f_ptr<kDense>(w, x) == (uint32_t)x) {   // no neighbour: its own parent, nobody's label
+            w.par[x] = (uint32_t)x;
+            continue;
+        }
+        const uint32_t pj = w.par[x];
+        const uint32_t j = pj & ~kOnCycle;
+        const uint32_t fj = *tree_f_ptr<kDense>(w, j);
+        // a pointer without the mark was never found on its cycle: check it (the passes
+        // should have converged)
+        if (!(pj & kOnCycle) && *tree_f_ptr<kDense>(w, fj) != j) broken = true;
+        const uint32_t lab = tree_prio<kFirst>(pc, names, j) < tree_prio<kFirst>(pc, names, fj) ? j : fj;
+        w.par[x] = lab;
+        w.is_label[lab] = 1;
+    }
+    if (broken) atomicOr(&st->err, 4u);
+}
+
 }  // namespace lc
