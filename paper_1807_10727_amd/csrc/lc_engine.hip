@@ -689,7 +689,7 @@ cc_status adopt_device_rounds(cc_ctx *c, int in_graph) {
 }
 
 bool fused_wanted(const cc_ctx *c) {
-    return c->tail >= 2 && !c->fused_unavailable && c->variant != kVarTree &&
+    return c->tail >= 2 && !c->fused_unavailable &&
            !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE)) &&
            (c->o.max_rounds == 0 || c->next_round < c->o.max_rounds) && c->m_cur > c->finish_edges &&
            c->next_round >= 1 && c->next_round < kStatRounds &&
@@ -703,8 +703,8 @@ bool fused_wanted(const cc_ctx *c) {
 cc_status run_fused(cc_ctx *c) {
     const int64_t cap = std::max<int64_t>(c->g.n_vertices, 1);
     if ((c->host_levels >= kMaxLevels || c->host_map_used + c->n_cur > cap) && !c->flatten()) return hip_status(c);
-    const bool one_hop = c->variant == kVarOneHop;
-    const int grid = fused_rounds_grid(one_hop, 1 << (c->tail - 2), c->cus);
+    const int rule = c->variant == kVarTree ? kFusedTree : c->variant == kVarOneHop ? kFusedOneHop : kFusedLocal;
+    const int grid = fused_rounds_grid(rule, 1 << (c->tail - 2), c->cus);
     if (grid <= 0) {
         c->fused_unavailable = true;
         return round_once(c, nullptr);
@@ -712,7 +712,7 @@ cc_status run_fused(cc_ctx *c) {
     const int before = c->next_round;
     const bool ev = c->ev_begin(kFusedRounds);
     const FusedLimits lim{c->o.max_rounds > 0 ? c->o.max_rounds : kStatRounds, c->finish_edges};
-    const hipError_t e = launch_fused_rounds(c->w, one_hop, grid, lim, c->stream);
+    const hipError_t e = launch_fused_rounds(c->w, rule, grid, lim, c->stream);
     c->ev_end(ev);
     if (e == hipErrorCooperativeLaunchTooLarge) {   // the runtime disagrees with the occupancy query
         (void)hipGetLastError();

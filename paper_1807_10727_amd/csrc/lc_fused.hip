@@ -57,7 +57,9 @@ __device__ inline void flag_map(cooperative_groups::grid_group &grid, bool singl
     step_flags_down(f, n, partials, map);
 }
 
-template <bool kOneHop>
+// kRule: the label rule of the round (FusedRule): LocalContraction's two-hop minimum, the
+// one-hop label, or TreeContraction's pointer jumping to the 2-cycle of f (Section 4).
+template <int kRule>
 __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work w, PrioCtx pc, FusedLimits lim) {
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     RoundState *st = w.st;
@@ -66,16 +68,35 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
         const int r = st->round;
         const bool single = st->n_cur <= (u64c)kSmallFlagNodes;
         const uint32_t *names = w.names[r & 1];
-        step_round_begin<true>(w, names, nullptr);
-        grid.sync();
-        step_min1_seeded(rd, w);
-        grid.sync();
-        if (!kOneHop) {
-            step_min2(rd, w);
+        if (kRule == kFusedTree) {
+            step_round_begin<false>(w, names, nullptr);
+            grid.sync();
+            step_min1_open<ReadInternal, false>(rd, w, pc, names);
+            grid.sync();
+            step_tree_f<false, false>(w, pc);
+            grid.sync();
+            // as many jumping passes as a launch sequence enqueues for this round's nodes; the
+            // passes after convergence return at once
+            const int64_t n = (int64_t)st->n_cur;
+            const int passes = ceil_log2_i64(n < 2 ? 2 : n) + 2;
+            for (int it = 0; it < passes; ++it) {
+                step_tree_jump<false>(w, it);
+                grid.sync();
+            }
+            step_tree_label<false, false>(w, pc, names);
+            grid.sync();
+        } else {
+            step_round_begin<true>(w, names, nullptr);
+            grid.sync();
+            step_min1_seeded(rd, w);
+            grid.sync();
+            if (kRule == kFusedLocal) {
+                step_min2(rd, w);
+                grid.sync();
+            }
+            step_parent<false, false>(w, pc, nullptr, kRule == kFusedOneHop ? 0 : 1);
             grid.sync();
         }
-        step_parent<false, false>(w, pc, nullptr, kOneHop ? 0 : 1);
-        grid.sync();
         flag_map(grid, single, w.is_label, &st->n_cur, w.lmap, &st->n_labels, w.partials, none);
         grid.sync();
         step_rank_parents(w);
@@ -104,26 +125,29 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
 
 typedef void (*FusedKernel)(ReadInternal, Work, PrioCtx, FusedLimits);
 
-FusedKernel fused_kernel(bool one_hop) { return one_hop ? k_fused_rounds<true> : k_fused_rounds<false>; }
+FusedKernel fused_kernel(int rule) {
+    return rule == kFusedTree ? k_fused_rounds<kFusedTree>
+                              : rule == kFusedOneHop ? k_fused_rounds<kFusedOneHop> : k_fused_rounds<kFusedLocal>;
+}
 
 }  // namespace
 
-int fused_rounds_grid(bool one_hop, int per_cu, int cus) {
+int fused_rounds_grid(int rule, int per_cu, int cus) {
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fused_kernel(one_hop), kThreads, 0) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fused_kernel(rule), kThreads, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     return occ < 1 ? 0 : cus * (per_cu < occ ? per_cu : occ);
 }
 
-hipError_t launch_fused_rounds(const Work &w, bool one_hop, int grid, FusedLimits lim, hipStream_t s) {
+hipError_t launch_fused_rounds(const Work &w, int rule, int grid, FusedLimits lim, hipStream_t s) {
     ReadInternal rd(w);
     Work wk = w;
     PrioCtx pc{};
     if (lim.round_limit > kStatRounds) lim.round_limit = kStatRounds;
     void *args[] = {&rd, &wk, &pc, &lim};
-    return hipLaunchCooperativeKernel(fused_kernel(one_hop), dim3(grid), dim3(kThreads), args, 0, s);
+    return hipLaunchCooperativeKernel(fused_kernel(rule), dim3(grid), dim3(kThreads), args, 0, s);
 }
 
 }  // namespace lc

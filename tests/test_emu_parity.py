@@ -134,7 +134,7 @@ def in_graph(cc, s, rounds):
 
 
 @pytest.mark.parametrize("tail", [2, 3, 4])
-@pytest.mark.parametrize("rule", ["local", "one_hop"])
+@pytest.mark.parametrize("rule", ["local", "one_hop", "tree"])
 def test_emulated_persistent_rounds(cc, tail, rule):
     """cc_tuning.tail >= 2: the rounds after round 0 small enough for the hashed duplicate drop
     run inside one cooperative launch, whose
@@ -200,16 +200,17 @@ def test_emulated_persistent_rounds_then_union_find(cc, finish):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
-@pytest.mark.parametrize("rule,seed,launches", [("local", 3, 1), ("one_hop", 22, 2)])
+@pytest.mark.parametrize("rule,seed,launches", [("local", 3, 1), ("one_hop", 22, 2), ("tree", 3, 1)])
 def test_emulated_persistent_rounds_large(cc, rule, seed, launches):
     """About a million path vertices.  LocalContraction: round 1 has more than 2^18 nodes, so
     the label and node maps take the count, scan and write phases with grid-wide barriers
     between them instead of one workgroup.  One-hop rule at this seed: the rounds' nodes add up
     to more than the per-round map arena holds, so the launch stops before the round that
-    would overflow it, the host folds the maps, and a second launch finishes the solve."""
+    would overflow it, the host folds the maps, and a second launch finishes the solve.
+    TreeContraction: its pointer-jumping passes inside the launch, over 250,000 nodes."""
     g = graphgen.er_with_paths(0xB16, 1 << 12, 1 << 13, 1000, 1000)
     want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
-    assert want.stats[1][1] > 1 << 18
+    assert rule == "tree" or want.stats[1][1] > 1 << 18
     with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=seed, flags=RULES[rule] | cc.CC_PROFILE) as s:
         s.set_tuning(tail=2)
         rounds = s.run()

@@ -432,7 +432,7 @@ def test_one_sweep_radix_parity(lc, mode):
 
 
 @pytest.mark.parametrize("tail", [2, 3, 4])
-@pytest.mark.parametrize("rule", ["local", "one_hop"])
+@pytest.mark.parametrize("rule", ["local", "one_hop", "tree"])
 def test_persistent_rounds_match_oracle(lc, tail, rule):
     """cc_tuning.tail >= 2: the rounds after round 0 run in one cooperative launch with
     grid-wide barriers between their steps.  The oracle's rounds, statistics and labels, on a
@@ -441,7 +441,7 @@ def test_persistent_rounds_match_oracle(lc, tail, rule):
     one-workgroup form); those rounds report in_graph = 2 and are timed as "fused_rounds"."""
     g = graphgen.er_with_paths(0xB16, 1 << 12, 1 << 13, 1000, 1000)
     s_t, d_t, _ = to_device(g)
-    flags = {"local": 0, "one_hop": lc.CC_ONE_HOP}[rule]
+    flags = {"local": 0, "one_hop": lc.CC_ONE_HOP, "tree": lc.CC_TREE}[rule]
     with lc.Solver(g.n, s_t, d_t, seed=1, flags=flags | lc.CC_PROFILE) as s:
         s.set_tuning(tail=tail)
         assert s.tuning["tail"] == tail
@@ -449,7 +449,7 @@ def test_persistent_rounds_match_oracle(lc, tail, rule):
             s.reset(seed)
             r = s.run()
             want = oracle.run(g.n, g.src, g.dst, seed=seed, variant=rule)
-            assert want.stats[1][1] > 1 << 18
+            assert rule == "tree" or want.stats[1][1] > 1 << 18
             assert r == want.rounds
             assert [tuple(x) for x in s.stats(r)] == [tuple(x) for x in want.stats]
             ig = [lc.cc_get_round_stats(s.ctx, k, True)[-1] for k in range(r)]
