@@ -10,14 +10,16 @@
 // workgroups wrote in the step before (m1 before the two-hop pass, the parents before the
 // label map, and so on) starts only after every workgroup has finished that step.  Steps that
 // touch disjoint data share a phase (the label ranks and the key width; the next node set,
-// the per-round map and the write of the kept edges).
+// the per-round map and the write of the kept edges).  TreeContraction's rounds (Section 4)
+// run their open one-hop minimum, f and pointer-jumping passes the same way.
 //
 // Every workgroup reads the round state at the top of the loop, after the barrier that ended
 // the previous round, so all of them take the same decision.  The launch ends when no edge is
 // left, or when the next round does not fit it (more records than the hashed drop takes, no
 // room for another per-round map, the statistics table full, the caller's round limit reached,
-// few enough records left for the union-find finish, an error flagged); the host then reads the
-// state once and goes on with separate launches (or the finish) if edges remain.  The loop runs at most kStatRounds rounds in all, so every workgroup leaves it.
+// few enough records left for the union-find finish, an error flagged); the host then reads
+// the state once and goes on with separate launches (or the finish) if edges remain.  The
+// loop runs at most kStatRounds rounds in all, so every workgroup leaves it.
 
 #include <hip/hip_cooperative_groups.h>
 
