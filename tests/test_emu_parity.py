@@ -451,12 +451,15 @@ def test_emulated_checkpoint_resume(cc, k):
         if k:
             a.run()
         blob = a.save_state()
-    with hipemu.Solver(g.n, s_, d_, seed=1234, flags=DIRECT) as b:
-        b.load_state(blob)
-        rounds = b.run()
-        assert rounds == want.rounds
-        assert [tuple(x) for x in b.stats(rounds)] == [tuple(x) for x in want.stats]
-        np.testing.assert_array_equal(b.labels().astype(np.uint32), want.labels)
+    for tail in (1, 3):   # the resumed solve in launch sequences, or in the persistent launch
+        with hipemu.Solver(g.n, s_, d_, seed=1234, flags=DIRECT) as b:
+            b.set_tuning(tail=tail)
+            b.load_state(blob)
+            rounds = b.run()
+            assert rounds == want.rounds
+            assert [tuple(x) for x in b.stats(rounds)] == [tuple(x) for x in want.stats]
+            np.testing.assert_array_equal(b.labels().astype(np.uint32), want.labels)
+            assert (2 in in_graph(cc, b, rounds)) == (tail == 3 and rounds > max(k, 1))
 
 
 def test_emulated_checkpoint_after_a_forced_failure(cc):
