@@ -398,6 +398,8 @@ typedef struct {
     int32_t small_blocks_per_cu;  /* persistent LDS workgroups per CU (1..16) */
     int32_t rounds_per_graph;     /* union rounds captured in the graph (1..64); more run eagerly */
     int32_t use_graph;            /* 1: capture once and replay; 0: eager launches */
+    int32_t radix_form;           /* the union's radix sorts: 1 (0: default) count, scan and scatter
+                                     per digit; 2 one sweep, as cc_tuning.radix_form */
 } cc_batch_config;
 
 cc_status cc_batch_create(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t *h_edge_off,

@@ -68,7 +68,7 @@ class cc_tuning(ctypes.Structure):
 class cc_batch_config(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("small_variant", ctypes.c_int32),
                 ("small_threads", ctypes.c_int32), ("small_blocks_per_cu", ctypes.c_int32),
-                ("rounds_per_graph", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("rounds_per_graph", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("radix_form", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

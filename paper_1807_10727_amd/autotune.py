@@ -25,6 +25,7 @@ SEARCH_SPACE = {
     "small_threads": [256, 512],
     "small_blocks_per_cu": [1, 2, 4],
     "blocks_per_cu": [4, 8, 16],
+    "radix_form": [1, 2],              # the union's radix passes: count, scan and scatter a digit; one sweep
 }
 
 

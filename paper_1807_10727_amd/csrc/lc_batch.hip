@@ -458,6 +458,7 @@ cc_status create_batch(int32_t n_graphs, const int64_t *h_vtx_off, const int64_t
     b->cfg.small_blocks_per_cu = 2;
     b->cfg.rounds_per_graph = 24;
     b->cfg.use_graph = 1;
+    b->cfg.radix_form = 1;
     if (small_bytes(b->cfg.small_variant, b->cfg.small_threads) > b->max_lds) b->cfg.small_variant = 1;
     if (psrc) {   // a cohort: the records and labels of graph g at per-graph pointers
         b->ptr_mode = true;
@@ -561,11 +562,13 @@ cc_status cc_batch_set_config(cc_batch *b, const cc_batch_config *c) {
     if (c->blocks_per_cu < 1 || c->blocks_per_cu > 64 || c->small_variant < 0 ||
         c->small_variant >= kNumSmallVariants || (c->small_threads != 256 && c->small_threads != 512) ||
         c->small_blocks_per_cu < 1 || c->small_blocks_per_cu > 16 || c->rounds_per_graph < 1 ||
-        c->rounds_per_graph > 64)
+        c->rounds_per_graph > 64 || c->radix_form < 0 || c->radix_form > 2)
         return bfail(b, CC_E_ARG, "configuration out of range");
     if (c->small_variant > 0 && small_bytes(c->small_variant, c->small_threads) > b->max_lds)
         return bfail(b, CC_E_ARG, "small-graph variant needs more LDS than the device allows");
     b->cfg = *c;
+    if (b->cfg.radix_form == 0) b->cfg.radix_form = 1;
+    b->radix_form = b->cfg.radix_form;
     b->grid_cap = b->cus * c->blocks_per_cu;
     if (b->ws) return plan(b);
     return CC_OK;

@@ -113,9 +113,9 @@ size_t plan_workspace(int64_t n0, int64_t m0, bool batch, bool tiled, char *base
         t.rec_cap = kRecordPerVertex * (int64_t)n;
         t.rec = (uint32_t *)take(4 * (size_t)t.rec_cap);
     }
+    t.sweep = (uint32_t *)take(4 * (size_t)kSweepWords);
+    t.sweep_desc = (uint32_t *)take(4 * (size_t)kRadixMax * tiles);
     if (!batch) {
-        t.sweep = (uint32_t *)take(4 * (size_t)kSweepWords);
-        t.sweep_desc = (uint32_t *)take(4 * (size_t)kRadixMax * tiles);
         t.btab = (BucketTab *)take(sizeof(BucketTab) * 257);
         t.bseg = (uint64_t *)take(8 * 257);
         t.btile = (uint32_t *)take(4 * 257);

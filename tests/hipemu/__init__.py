@@ -258,6 +258,10 @@ class Batch:
     def split(self):
         return self.cc.cc_batch_split(self.b)
 
+    @property
+    def config(self):
+        return self.cc.cc_batch_get_config(self.b)
+
     def close(self):
         if self.b:
             self.cc.cc_batch_destroy(self.b)

@@ -523,12 +523,16 @@ def test_emulated_checkpoint_rejects_another_graph(cc):
 
 @pytest.mark.parametrize("variant", [0, 1, 3])
 @pytest.mark.parametrize("fill", [0x00, 0xFF])
-def test_emulated_batch(cc, variant, fill):
-    """The batch (LDS solver and union path, captured and replayed) on a workspace that
-    starts with arbitrary bytes: each graph's labels and rounds are the oracle's."""
+@pytest.mark.parametrize("radix_form", [1, 2])
+def test_emulated_batch(cc, variant, fill, radix_form):
+    """The batch (LDS solver and union path, captured and replayed; the union's radix passes in
+    either form) on a workspace that starts with arbitrary bytes: each graph's labels and
+    rounds are the oracle's."""
     b = graphgen.batch_mix(seed=31, count=24, log2_min=4, log2_max=11)
     want_lab, want_rounds, _ = oracle.run_batch(b.voff, b.eoff, b.src, b.dst, b.seeds)
-    with hipemu.Batch(b.voff, b.eoff, b.seeds, b.src, b.dst, ws_fill=fill, small_variant=variant) as bt:
+    with hipemu.Batch(b.voff, b.eoff, b.seeds, b.src, b.dst, ws_fill=fill, small_variant=variant,
+                      radix_form=radix_form) as bt:
+        assert bt.config["radix_form"] == radix_form
         n_small, _ = bt.split()
         assert (n_small > 0) == (variant > 0)
         for _ in range(2):

@@ -89,16 +89,18 @@ def test_random_solves_match_the_oracle(g, seed, layout, rule, knobs, alphas):
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(seed=st.integers(0, 2 ** 32 - 1), count=st.integers(1, 24), log2_max=st.integers(2, 12),
        small_variant=st.sampled_from([0, 1, 2, 3]), small_threads=st.sampled_from([256, 512]),
-       use_graph=st.sampled_from([0, 1]), blocks_per_cu=st.sampled_from([1, 8]), fill=st.sampled_from([0x00, 0xA5]))
+       use_graph=st.sampled_from([0, 1]), blocks_per_cu=st.sampled_from([1, 8]), fill=st.sampled_from([0x00, 0xA5]),
+       radix_form=st.sampled_from([1, 2]))
 def test_random_batches_match_the_oracle(seed, count, log2_max, small_variant, small_threads, use_graph,
-                                         blocks_per_cu, fill):
+                                         blocks_per_cu, fill, radix_form):
     """Random batches (sizes, the LDS solver's limits and workgroup size, captured or eager
-    rounds, grid size, workspace contents): every graph's labels and rounds are the oracle's,
-    run twice on the same batch."""
+    rounds, grid size, workspace contents, the form of the union's radix passes): every graph's
+    labels and rounds are the oracle's, run twice on the same batch."""
     b = graphgen.batch_mix(seed=seed, count=count, log2_min=1, log2_max=log2_max)
     want_lab, want_rounds, _ = oracle.run_batch(b.voff, b.eoff, b.src, b.dst, b.seeds)
     with hipemu.Batch(b.voff, b.eoff, b.seeds, b.src, b.dst, ws_fill=fill, small_variant=small_variant,
-                      small_threads=small_threads, use_graph=use_graph, blocks_per_cu=blocks_per_cu) as bt:
+                      small_threads=small_threads, use_graph=use_graph, blocks_per_cu=blocks_per_cu,
+                      radix_form=radix_form) as bt:
         for _ in range(2):
             lab, rounds = bt.run()
             np.testing.assert_array_equal(rounds, want_rounds)

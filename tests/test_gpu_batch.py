@@ -38,10 +38,12 @@ def dev_arrays(b):
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("use_graph", [1, 0])
-def test_batch_matches_oracle(lc, variant, use_graph):
+@pytest.mark.parametrize("radix_form", [1, 2])
+def test_batch_matches_oracle(lc, variant, use_graph, radix_form):
     b = make_batch(96, seed=11)
     s, d = dev_arrays(b)
-    with lc.Batch(b.voff, b.eoff, b.seeds, s, d, small_variant=variant, use_graph=use_graph) as bt:
+    with lc.Batch(b.voff, b.eoff, b.seeds, s, d, small_variant=variant, use_graph=use_graph,
+                  radix_form=radix_form) as bt:
         n_small, um = bt.split()
         if variant == 0:
             assert n_small == 0 and um == b.eoff[-1]
