@@ -208,7 +208,9 @@ def bench_batch(args, log_prefix="batch"):
     dst = torch.from_numpy(b.dst.view(np.int32)).to(dev)
     bt = lc.Batch(b.voff, b.eoff, b.seeds, src, dst)
     t0 = time.perf_counter()
-    cfg, _, tried = autotune.tune(bt, repeats=1, cache=args.tune_cache, log=log if args.verbose_tune else None)
+    rejected = []
+    cfg, _, tried = autotune.tune(bt, repeats=1, cache=args.tune_cache, log=log if args.verbose_tune else None,
+                                  rejected=rejected)
     log("%s: autotune picked %s (%d candidates timed, %.1fs)" % (log_prefix, cfg, tried, time.perf_counter() - t0))
     n_small, union_m = bt.split()
     lab, rounds = bt.run()                      # warm (captures the graph if needed)
@@ -258,7 +260,8 @@ def bench_batch(args, log_prefix="batch"):
             "sequential_graphs_per_s": b.count / t_seq, "sequential_ms": t_seq * 1e3,
             "speedup_vs_sequential": t_seq / t_batch, "labels_identical_to_sequential": same,
             "lds_path_graphs": n_small, "union_records": union_m, "max_rounds": int(rounds.max()),
-            "config": cfg}
+            "config": cfg,
+            "tuner_rejected": [{"knob": k, "value": v, "reason": why} for k, v, why in rejected]}
 
 
 def _pct(xs, q):

@@ -72,9 +72,11 @@ def _time_run(batch, repeats):
     return best, digest
 
 
-def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, space=None):
+def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, space=None, rejected=None):
     """Pick the fastest configuration for `batch` (a paper_1807_10727_amd.Batch), apply it
-    and return (config dict, seconds of the best run, number of candidates timed)."""
+    and return (config dict, seconds of the best run, number of candidates timed).  Every
+    candidate must give the labels of the first one; a candidate that fails or does not is
+    treated as in tune_solver (recorded in `rejected` when given, raised otherwise)."""
     key = "%s|%s" % (device_key(), size_class(batch))
     if cache:
         hit = _load(cache).get(key)
@@ -88,8 +90,6 @@ def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, s
     best_t, ref = _time_run(batch, repeats)
     tried = 1
     for knob, values in space.items():
-        if knob in ROW_KNOBS and cfg["round0"] == 1:
-            continue                   # a direct round 0 has no row passes
         for v in values:
             if v == cfg[knob]:
                 continue
@@ -98,10 +98,19 @@ def tune(batch, repeats: int = 2, cache: str | None = DEFAULT_CACHE, log=None, s
                 batch.configure(**cand)
             except Exception:          # e.g. an LDS variant larger than the device allows
                 continue
-            t, digest = _time_run(batch, repeats)
+            try:
+                t, digest = _time_run(batch, repeats)
+            except Exception as e:     # e.g. CCError from the library
+                if rejected is None:
+                    raise
+                rejected.append((knob, v, "run failed: %s" % (e,)))
+                continue
             tried += 1
             if digest != ref:
-                raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+                if rejected is None:
+                    raise RuntimeError("autotune candidate %r changed the labels" % (cand,))
+                rejected.append((knob, v, "labels differ from the first candidate's"))
+                continue
             if log:
                 log("  tune %-22s %s -> %.2f ms" % (knob, v, t * 1e3))
             if t < best_t:

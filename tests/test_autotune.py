@@ -1,6 +1,6 @@
-"""The single-graph autotuner's walk (host logic, no GPU): coordinate descent over the knobs,
-the row-pass knobs skipped for a direct round 0, and candidates that fail or change the labels
-never picked -- recorded when the caller asks, raised otherwise."""
+"""The autotuners' walks (host logic, no GPU): coordinate descent over the knobs, the row-pass
+knobs skipped for a direct round 0, and candidates that fail or change the labels never
+picked -- recorded when the caller asks, raised otherwise; for single solves and batches."""
 import sys
 import types
 
@@ -85,3 +85,40 @@ def test_failed_and_wrong_candidates_are_never_picked(clocked):
     clocked["solver"] = s2
     with pytest.raises(RuntimeError):
         autotune.tune_solver(s2, cache=None, space={"radix_form": [1, 2]})
+
+
+class FakeBatch:
+    """Stands in for paper_1807_10727_amd.Batch: run() advances the clock by the cost of the
+    configuration; one setting fails, another gives other labels."""
+
+    def __init__(self, cost, fail=(), wrong=()):
+        self.c = {"small_variant": 2, "blocks_per_cu": 8, "radix_form": 1, "use_graph": 1}
+        self.cost, self.fail, self.wrong = cost, fail, wrong
+        self.clock = 0.0
+        self.n_total = 4
+
+    @property
+    def config(self):
+        return dict(self.c)
+
+    def configure(self, **kw):
+        self.c.update(kw)
+
+    def run(self, with_rounds=True):
+        if any(self.c.get(k) == v for k, v in self.fail):
+            raise RuntimeError("the device refused it")
+        self.clock += self.cost(self.c)
+        bad = any(self.c.get(k) == v for k, v in self.wrong)
+        return types.SimpleNamespace(cpu=lambda: types.SimpleNamespace(numpy=lambda: np.array([9 if bad else 5]))), None
+
+
+def test_batch_walk_skips_failed_and_wrong_candidates(clocked, monkeypatch):
+    monkeypatch.setattr(autotune, "size_class", lambda b: "fake")
+    bt = FakeBatch(lambda c: 10.0 - 5 * (c["small_variant"] == 3) - 3 * (c["radix_form"] == 2) - (c["blocks_per_cu"] == 16),
+                   fail=[("small_variant", 3)], wrong=[("radix_form", 2)])
+    clocked["solver"] = bt
+    rejected = []
+    cfg, best, _ = autotune.tune(bt, repeats=1, cache=None, rejected=rejected,
+                                 space={"small_variant": [2, 3], "blocks_per_cu": [8, 16], "radix_form": [1, 2]})
+    assert cfg["small_variant"] == 2 and cfg["blocks_per_cu"] == 16 and cfg["radix_form"] == 1 and best == 9.0
+    assert [(k, v) for k, v, _ in rejected] == [("small_variant", 3), ("radix_form", 2)]

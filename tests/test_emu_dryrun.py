@@ -54,7 +54,7 @@ def test_bench_json_contract():
     assert c["kind"] == "oracle" and c["cores"] == 1 and "of" in c["host"] and "union_find" in c
     assert all(v["canonical_labels_identical"] for v in d["variants"].values())
     assert set(d["variants"]) == {"tree", "one_hop", "uf_finish", "merge_to_large"}
-    assert d["batched"]["labels_identical_to_sequential"]
+    assert d["batched"]["labels_identical_to_sequential"] and d["batched"]["tuner_rejected"] == []
     assert d["serving"]["labels_identical_to_solo"]
     assert d["serving"]["requests"] == 6 and d["serving"]["warmup_requests"] == 2 and d["serving"]["pool_graphs"] == 3
     # more than one GPU is refused with a message
