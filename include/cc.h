@@ -218,10 +218,11 @@ typedef struct {
                                  launch of 1, 2 or 4 workgroups per compute unit (at most what
                                  stays resident), the steps of a round separated by grid-wide
                                  barriers, one readback in all; its rounds report in_graph = 2.
-                                 Every label rule (TreeContraction's pointer jumping inside the
-                                 launch too), without CC_EAGER, CC_EXPLICIT_PRIO, CC_RECORD_ROUNDS
-                                 or CC_MERGE_TO_LARGE (otherwise the default applies); it stops at
-                                 opts.max_rounds and where the union-find finish takes over */
+                                 Every label rule and MergeToLarge (TreeContraction's pointer
+                                 jumping and MergeToLarge's class priorities inside the launch
+                                 too), without CC_EAGER, CC_EXPLICIT_PRIO or CC_RECORD_ROUNDS
+                                 (otherwise the default applies); it stops at opts.max_rounds and
+                                 where the union-find finish takes over */
     int32_t radix_form;       /* the duplicate drop's LSD radix sorts: 1 (0: default) per digit a count
                                  pass, a scan of the count table and a scatter; 2 one sweep: one
                                  count pass for every digit at once, then per digit only the

@@ -690,7 +690,7 @@ cc_status adopt_device_rounds(cc_ctx *c, int in_graph) {
 
 bool fused_wanted(const cc_ctx *c) {
     return c->tail >= 2 && !c->fused_unavailable &&
-           !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS | CC_MERGE_TO_LARGE)) &&
+           !(c->o.flags & (CC_EAGER | CC_EXPLICIT_PRIO | CC_RECORD_ROUNDS)) &&
            (c->o.max_rounds == 0 || c->next_round < c->o.max_rounds) && c->m_cur > c->finish_edges &&
            c->next_round >= 1 && c->next_round < kStatRounds &&
            !c->done && c->m_cur > 0 && c->m_cur <= kHashMaxRecords && 2 * c->m_cur + 1 <= c->w.kcap;
@@ -702,8 +702,17 @@ bool fused_wanted(const cc_ctx *c) {
 // for this context.
 cc_status run_fused(cc_ctx *c) {
     const int64_t cap = std::max<int64_t>(c->g.n_vertices, 1);
-    if ((c->host_levels >= kMaxLevels || c->host_map_used + c->n_cur > cap) && !c->flatten()) return hip_status(c);
-    const int rule = c->variant == kVarTree ? kFusedTree : c->variant == kVarOneHop ? kFusedOneHop : kFusedLocal;
+    // room for the next round's map (with MergeToLarge, a LocalContraction step's and its
+    // step's; no fold between the two, so none before a step)
+    const bool mtl = (c->o.flags & CC_MERGE_TO_LARGE) != 0;
+    const int levels = mtl ? ((c->next_round & 1) ? 0 : 2) : 1;
+    if (levels && (c->host_levels + levels > kMaxLevels || c->host_map_used + levels * c->n_cur > cap) &&
+        !c->flatten())
+        return hip_status(c);
+    const int rule = mtl                       ? kFusedMerge
+                     : c->variant == kVarTree   ? kFusedTree
+                     : c->variant == kVarOneHop ? kFusedOneHop
+                                                : kFusedLocal;
     const int grid = fused_rounds_grid(rule, 1 << (c->tail - 2), c->cus);
     if (grid <= 0) {
         c->fused_unavailable = true;
@@ -711,7 +720,15 @@ cc_status run_fused(cc_ctx *c) {
     }
     const int before = c->next_round;
     const bool ev = c->ev_begin(kFusedRounds);
-    const FusedLimits lim{c->o.max_rounds > 0 ? c->o.max_rounds : kStatRounds, c->finish_edges};
+    FusedLimits lim{};
+    lim.round_limit = c->o.max_rounds > 0 ? c->o.max_rounds : kStatRounds;
+    lim.finish_edges = c->finish_edges;
+    if (mtl) {   // the phases' alphas; phases past what the launch carries are left to the host
+        const size_t na = c->mtl_alphas.size();
+        lim.n_alphas = (int32_t)std::min<size_t>(na, kFusedAlphas);
+        for (int i = 0; i < lim.n_alphas; ++i) lim.alphas[i] = (uint64_t)c->mtl_alphas[(size_t)i];
+        if (na > (size_t)kFusedAlphas) lim.round_limit = std::min(lim.round_limit, 2 * kFusedAlphas);
+    }
     const hipError_t e = launch_fused_rounds(c->w, rule, grid, lim, c->stream);
     c->ev_end(ev);
     if (e == hipErrorCooperativeLaunchTooLarge) {   // the runtime disagrees with the occupancy query

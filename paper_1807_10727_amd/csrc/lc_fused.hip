@@ -11,7 +11,9 @@
 // label map, and so on) starts only after every workgroup has finished that step.  Steps that
 // touch disjoint data share a phase (the label ranks and the key width; the next node set,
 // the per-round map and the write of the kept edges).  TreeContraction's rounds (Section 4)
-// run their open one-hop minimum, f and pointer-jumping passes the same way.
+// run their open one-hop minimum, f and pointer-jumping passes the same way, and MergeToLarge's
+// (Section 5) the class sizes and priorities after a LocalContraction step and the two
+// candidate passes of its own step.
 //
 // Every workgroup reads the round state at the top of the loop, after the barrier that ended
 // the previous round, so all of them take the same decision.  The launch ends when no edge is
@@ -32,11 +34,15 @@ namespace {
 // Whether the next round runs inside this launch (the host's conditions for a hashed round,
 // evaluated on the device state).  Rounds from a.round_limit on, and a graph of at most
 // a.finish_edges records (which the union-find finish takes over), are left to the host.
+// With MergeToLarge (kMerge), a LocalContraction step (an even round) also needs room for the
+// map of the MergeToLarge step that follows it: no fold may come between the two.
+template <bool kMerge>
 __device__ inline bool next_round_fits(const Work &w, const RoundState *st, const FusedLimits &a) {
     const uint64_t m = st->m_cur, n = st->n_cur;
+    const int levels = kMerge && !(st->round & 1) ? 2 : 1;
     return st->err == 0 && st->round >= 1 && st->round < a.round_limit && m > (uint64_t)a.finish_edges &&
-           m > 0 && m <= (uint64_t)kHashMaxRecords && 2 * m + 1 <= (uint64_t)w.kcap && st->levels < kMaxLevels &&
-           st->map_off + n <= st->map_cap;
+           m > 0 && m <= (uint64_t)kHashMaxRecords && 2 * m + 1 <= (uint64_t)w.kcap &&
+           st->levels + levels <= kMaxLevels && st->map_off + levels * n <= st->map_cap;
 }
 
 // Bit map with prefix counts of byte flags (label map or node map), as launch_map_scan builds
@@ -60,17 +66,33 @@ __device__ inline void flag_map(cooperative_groups::grid_group &grid, bool singl
 }
 
 // kRule: the label rule of the round (FusedRule): LocalContraction's two-hop minimum, the
-// one-hop label, or TreeContraction's pointer jumping to the 2-cycle of f (Section 4).
+// one-hop label, TreeContraction's pointer jumping to the 2-cycle of f (Section 4), or
+// LocalContraction steps alternating with MergeToLarge steps (Section 5).
 template <int kRule>
 __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work w, PrioCtx pc, FusedLimits lim) {
+    constexpr bool kMerge = kRule == kFusedMerge;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     RoundState *st = w.st;
     auto none = [] {};
-    while (next_round_fits(w, st, lim)) {
+    while (next_round_fits<kMerge>(w, st, lim)) {
         const int r = st->round;
         const bool single = st->n_cur <= (u64c)kSmallFlagNodes;
         const uint32_t *names = w.names[r & 1];
-        if (kRule == kFusedTree) {
+        // MergeToLarge: odd rounds are its steps; phase r / 2 takes alpha (the last repeating)
+        const bool merge_step = kMerge && (r & 1);
+        const uint64_t alpha = kMerge ? lim.alphas[min(r / 2, lim.n_alphas - 1)] : 0;
+        if (merge_step) {
+            step_round_begin<false>(w, names, nullptr);
+            grid.sync();
+            for (int pass = 0; pass < 2; ++pass) {
+                step_mtl_seed(w, alpha, pass);
+                grid.sync();
+                step_mtl_max(rd, w, alpha, pass);
+                grid.sync();
+            }
+            step_mtl_parent(w);
+            grid.sync();
+        } else if (kRule == kFusedTree) {
             step_round_begin<false>(w, names, nullptr);
             grid.sync();
             step_min1_open<ReadInternal, false>(rd, w, pc, names);
@@ -92,7 +114,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
             grid.sync();
             step_min1_seeded(rd, w);
             grid.sync();
-            if (kRule == kFusedLocal) {
+            if (kRule != kFusedOneHop) {   // the two-hop minimum (LocalContraction, its steps under MergeToLarge)
                 step_min2(rd, w);
                 grid.sync();
             }
@@ -120,6 +142,18 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
         step_map<false>(w, names);
         step_hash_write(w);
         grid.sync();
+        if (kMerge && !merge_step) {   // the classes' sizes and alpha-th priorities for the next step
+            step_mtl_clear(w);
+            grid.sync();
+            step_mtl_size(w);
+            grid.sync();
+            for (int bit = 31; bit >= 0; --bit) {
+                step_mtl_count<false>(w, pc, names, bit, alpha);
+                grid.sync();
+                step_mtl_keep(w, bit, alpha);
+                grid.sync();
+            }
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0) step_round_end<false>(w, kDedupHash);
         grid.sync();
     }
@@ -128,8 +162,12 @@ __global__ __launch_bounds__(kThreads) void k_fused_rounds(ReadInternal rd, Work
 typedef void (*FusedKernel)(ReadInternal, Work, PrioCtx, FusedLimits);
 
 FusedKernel fused_kernel(int rule) {
-    return rule == kFusedTree ? k_fused_rounds<kFusedTree>
-                              : rule == kFusedOneHop ? k_fused_rounds<kFusedOneHop> : k_fused_rounds<kFusedLocal>;
+    switch (rule) {
+        case kFusedTree: return k_fused_rounds<kFusedTree>;
+        case kFusedOneHop: return k_fused_rounds<kFusedOneHop>;
+        case kFusedMerge: return k_fused_rounds<kFusedMerge>;
+        default: return k_fused_rounds<kFusedLocal>;
+    }
 }
 
 }  // namespace

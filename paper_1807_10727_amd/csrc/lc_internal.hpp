@@ -407,11 +407,14 @@ hipError_t launch_bucket(const Work &w, int stage, int grid, hipStream_t s);
 // Rounds >= 1 that fit the hashed duplicate drop, one after another in one cooperative launch
 // (lc_fused.hip).  fused_rounds_grid: cus * min(per_cu, workgroups of the kernel that stay
 // resident on a CU), or 0 when not even one does.
-enum FusedRule { kFusedLocal = 0, kFusedOneHop = 1, kFusedTree = 2 };
+enum FusedRule { kFusedLocal = 0, kFusedOneHop = 1, kFusedTree = 2, kFusedMerge = 3 };
 int fused_rounds_grid(int rule, int per_cu, int cus);
+constexpr int kFusedAlphas = 16;   // MergeToLarge phases whose alpha the persistent launch carries
 struct FusedLimits {
     int32_t round_limit;    // rounds from this one on are left to the host
+    int32_t n_alphas;       // MergeToLarge: alphas[i] is phase i's, the last repeating
     int64_t finish_edges;   // a graph of at most this many records is left to the union-find finish
+    uint64_t alphas[kFusedAlphas];
 };
 hipError_t launch_fused_rounds(const Work &w, int rule, int grid, FusedLimits lim, hipStream_t s);
 // parents -> label ranks, the label of each rank, and the key width of the sort (grid_scan 0:

@@ -204,110 +204,35 @@ hipError_t launch_uf_finish(const Work &w, int round, int grid_nodes, int grid_e
 // Priorities of different large nodes are priorities of different vertices, so they never tie.
 // ---------------------------------------------------------------------------------------
 
-// index in the next graph of the class of node i of this round, or -1 (final or not a node)
-__device__ inline int64_t mtl_next_class(const Work &w, int64_t i) {
-    const uint32_t q = w.par[i];
-    if (q == kNoParent || !nmap_has(w.nmap, q)) return -1;
-    return (int64_t)nmap_rank(w.nmap, q);
-}
-
 __global__ __launch_bounds__(kThreads) void k_mtl_clear(Work w) {
-    const int64_t n = (int64_t)w.st->n_next;
-    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
-        w.mtl_size[k] = 0;
-        w.mtl_v[k] = 0;
-        w.mtl_cnt[k] = 0;
-    }
+    step_mtl_clear(w);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mtl_size(Work w) {
-    const int64_t n = (int64_t)w.st->n_cur;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const int64_t k = mtl_next_class(w, i);
-        if (k >= 0) atomicAdd(&w.mtl_size[k], 1u);
-    }
+    step_mtl_size(w);
 }
 
-// The alpha-th largest member priority v of a large class, one bit at a time from the top:
-// with the bits above b settled, bit b is set when at least alpha members have a priority of
-// at least v | 2^b.  Count pass, then keep pass, for b = 31 .. 0.
 template <bool kFirst>
 __global__ __launch_bounds__(kThreads) void k_mtl_count(Work w, PrioCtx pc, const uint32_t *names, int bit,
                                                         uint64_t alpha) {
-    const RoundState *st = w.st;
-    if (!pc.tab) pc.key = st->key;
-    const int64_t n = (int64_t)st->n_cur;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
-        const int64_t k = mtl_next_class(w, i);
-        if (k < 0 || w.mtl_size[k] < alpha) continue;
-        const uint32_t cand = w.mtl_v[k] | (1u << bit);
-        if (rho_of(pc, kFirst ? (uint32_t)i : names[i]) >= cand) atomicAdd(&w.mtl_cnt[k], 1u);
-    }
+    step_mtl_count<kFirst>(w, pc, names, bit, alpha);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mtl_keep(Work w, int bit, uint64_t alpha) {
-    const int64_t n = (int64_t)w.st->n_next;
-    for (int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x; k < n; k += (int64_t)gridDim.x * kThreads) {
-        if (w.mtl_size[k] >= alpha && w.mtl_cnt[k] >= alpha) w.mtl_v[k] |= 1u << bit;
-        w.mtl_cnt[k] = 0;
-    }
-}
-
-// Candidate of node u in the step: (priority, u) of a large node, 0 otherwise (bit 31 of the
-// low word marks a candidate, so that a priority of 0 still beats "none").
-__device__ inline uint64_t mtl_cand(const Work &w, uint32_t u, uint64_t alpha) {
-    return w.mtl_size[u] >= alpha ? ((uint64_t)w.mtl_v[u] << 32) | 0x80000000ull | u : 0ull;
+    step_mtl_keep(w, bit, alpha);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mtl_seed(Work w, uint64_t alpha, int pass) {
-    const int64_t n = (int64_t)w.st->n_cur;
-    for (int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x; u < n; u += (int64_t)gridDim.x * kThreads)
-        w.mtl_acc[pass][u] = pass == 0 ? mtl_cand(w, (uint32_t)u, alpha) : w.mtl_acc[0][u];
+    step_mtl_seed(w, alpha, pass);
 }
 
-// pass 0: best candidate over the closed one-hop neighbourhood; pass 1: over two hops
 template <class R>
 __global__ __launch_bounds__(kThreads) void k_mtl_max(R rd, Work w, uint64_t alpha, int pass) {
-    constexpr int V = R::kV;
-    rd.init(w.st);
-    const int64_t nch = rd.chunks();
-    u64c *acc = (u64c *)w.mtl_acc[pass];
-    const uint64_t *prev = w.mtl_acc[0];
-    bool bad = false;
-    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nch; c += (int64_t)gridDim.x * kThreads) {
-        uint32_t a[V], b[V];
-        rd.read(c, a, b, bad);
-#pragma unroll
-        for (int j = 0; j < V; ++j) {
-            if (a[j] == b[j]) continue;
-            const uint64_t va = pass == 0 ? mtl_cand(w, a[j], alpha) : prev[a[j]];
-            const uint64_t vb = pass == 0 ? mtl_cand(w, b[j], alpha) : prev[b[j]];
-            if (vb > acc[a[j]]) atomicMax(&acc[a[j]], (u64c)vb);
-            if (va > acc[b[j]]) atomicMax(&acc[b[j]], (u64c)va);
-        }
-    }
+    step_mtl_max<R>(rd, w, alpha, pass);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mtl_parent(Work w) {
-    RoundState *st = w.st;
-    const int64_t n = (int64_t)st->n_cur;
-    uint32_t active = 0;
-    bool broken = false;
-    for (int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x; u < n; u += (int64_t)gridDim.x * kThreads) {
-        const uint64_t x = w.mtl_acc[1][u];
-        uint32_t p = x ? (uint32_t)(x & 0x7FFFFFFFull) : (uint32_t)u;
-        if ((int64_t)p >= n) {   // cannot happen for a consistent state
-            broken = true;
-            p = (uint32_t)u;
-        }
-        w.par[u] = p;
-        w.is_label[p] = 1;
-        ++active;
-    }
-    __shared__ uint32_t red[kThreads / kWave];
-    active = block_sum<kThreads>(active, red);
-    if (threadIdx.x == 0 && active) atomicAdd(&st->n_active, (u64c)active);
-    if (broken) atomicOr(&st->err, 4u);
+    step_mtl_parent(w);
 }
 
 hipError_t launch_mtl_prep(const Work &w, const PrioCtx &p, int round, uint64_t alpha, int grid_cur, int grid_next,

@@ -171,6 +171,24 @@ def test_emulated_persistent_rounds(cc, tail, rule):
         np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
 
 
+@pytest.mark.parametrize("alphas", [[3], [2, 5, 4]])
+@pytest.mark.parametrize("tail", [2, 3])
+def test_emulated_persistent_merge_to_large(cc, alphas, tail):
+    """MergeToLarge inside the persistent launch: LocalContraction steps (with the class sizes
+    and alpha-th priorities after each) alternating with MergeToLarge steps (two candidate
+    passes), each phase with its own alpha: rounds, statistics and labels are the oracle's."""
+    g = graphgen.er_with_paths(0x7A11, 20000, 50000, 40, 400)
+    want = oracle.run(g.n, g.src, g.dst, seed=5, variant="merge_to_large", alphas=alphas)
+    with hipemu.Solver(g.n, dev(g.src), dev(g.dst), seed=5, flags=(1 << 9) | cc.CC_PROFILE) as s:
+        s.set_tuning(tail=tail)
+        s.set_merge_to_large(alphas)
+        rounds = s.run()
+        assert rounds == want.rounds
+        assert 2 in in_graph(cc, s, rounds) and cc.cc_kernel_times(s.ctx)["fused_rounds"][1] >= 1
+        assert [tuple(x) for x in s.stats(rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().astype(np.uint32), want.labels)
+
+
 @pytest.mark.parametrize("max_rounds", [3, 5])
 def test_emulated_persistent_rounds_stop_at_max_rounds(cc, max_rounds):
     """cc_options.max_rounds inside the persistent launch: the solve stops after exactly that

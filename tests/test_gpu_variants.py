@@ -246,3 +246,9 @@ def test_merge_to_large_parity(lc, name, alphas, mode):
             r += 1
         assert s.run() == want.rounds == r
         np.testing.assert_array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels)
+        # cc_run alone, the rounds after round 0 in the persistent launch
+        s.set_tuning(tail=2)
+        s.set_merge_to_large(alphas)
+        assert s.run() == want.rounds
+        assert [tuple(x) for x in s.stats(want.rounds)] == [tuple(x) for x in want.stats]
+        np.testing.assert_array_equal(s.labels().cpu().numpy().view(np.uint32), want.labels)
