@@ -189,6 +189,11 @@ constexpr int kSweepWords = kMaxPasses * kRadixMax + kMaxPasses;
 // A one-sweep sort of this many keys or more is flagged instead of run (its prefix words
 // could not hold the counts); the host gives such rounds (more records than that) the other form.
 constexpr uint64_t kSweepMaxKeys = 0x7FFFFFFFu;
+// Polls of one look-back word before a tile gives up on it (seconds, where a tile takes
+// microseconds): a word that is never published, which a correct run cannot produce, then
+// fails the solve as an internal error instead of holding the GPU.  The offsets the tile
+// uses stay below the true ones, so its writes stay inside the key buffer.
+constexpr uint32_t kSweepMaxPolls = 1u << 22;
 constexpr int kSlab = 2 * kSortTile;               // records per relabel workgroup slab
 constexpr int64_t kSmallScanEntries = 1 << 15;    // count tables scanned by one workgroup
 constexpr int64_t kSmallFlagNodes = 1 << 18;      // flag maps built by one workgroup

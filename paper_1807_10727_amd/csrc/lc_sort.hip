@@ -294,10 +294,14 @@ void k_sort_scatter(Work w, int pass, int gated) {
                 for (int q = 0; q < kPer; ++q) {
                     const int d = threadIdx.x * per + q;
                     if (q < per && d < nbins && tile > 0) {
-                        uint32_t before = 0;
+                        uint32_t before = 0, polls = 0;
                         for (int64_t j = tile - 1; j >= 0;) {
                             const uint32_t v = load_agent(&desc[j * kRadixMax + d]);
                             if (v == kSweepEmpty) {   // not published yet: poll again
+                                if (++polls > kSweepMaxPolls) {   // never published: flagged, not waited for
+                                    atomicOr(&st->err, 4u);
+                                    break;
+                                }
                                 __builtin_amdgcn_s_sleep(1);
                                 continue;
                             }
